@@ -1,0 +1,226 @@
+#!/usr/bin/env python3
+"""Throughput of the sparse tensor contraction hot path on one MI355X.
+
+A step is one pass of the whole path over one synthetic input already resident
+in HBM: plan (group Y by contracting key, probe X, count products, size the
+output hash) then execute (expand and accumulate products, compact to COO).
+Prints ONE JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME] [--also a,b]
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "products/s + output nnz/s vs HBM roofline; batched/served p50/p99 vs per-call"
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+DESCRIPTIONS = {
+    "plain": "plain order-3 SpTC: 64^3 x 64^3, 2,621 nnz each (1%), X mode 2 with Y mode 0",
+    "block-sparse": "block-sparse order-4 x order-4: 48^4, 8^4 blocks p=0.1, 50% fill, values N(0,1)exp(-|i-j|/8), "
+                    "X modes (2,3) with Y modes (0,1)",
+    "block-sparse-1.5M": "block-sparse order-4 x order-4: 48^4, 8^4 blocks p=0.565 (~1.5M nnz), 50% fill, "
+                         "X modes (2,3) with Y modes (0,1)",
+    "imbalanced": "imbalanced order-3 SpTC: X 1e7 nnz on 2^17x2^14x2^15 (contracting mode Zipf 1.2), "
+                  "Y 1e6 nnz on 2^15x2^12x2^10, X mode 2 with Y mode 0",
+}
+
+
+def algorithmic_bytes(stage, p, products, nnz_z):
+    """Bytes a stage must move through HBM at minimum (each datum once; the
+    output hash read-modify-written once per product), per launch."""
+    nx, ny = p.X.nnz, p.Y.nnz
+    ox, oy = p.X.order, p.Y.order
+    nz_order = ox + oy - 2 * len(p.cx)
+    nc = len(p.cx)
+    if stage == "expand":
+        # per product: output-hash key read 8 B + value read 8 B + value write 8 B;
+        # X records (poff 8 B, group start 4 B, packed free key + value 16 B) and
+        # grouped Y entries (16 B) read once.
+        return 24 * products + 28 * nx + 16 * ny
+    if stage == "compact":
+        # occupied slot read once (16 B), COO written once (4 B per mode + 8 B value)
+        return nnz_z * (16 + 4 * nz_order + 8)
+    if stage == "x_probe":
+        return nx * (4 * ox + 8) + nx * (16 + 4 + 4)
+    if stage == "y_count":
+        return ny * 4 * nc
+    if stage == "y_scatter":
+        return ny * (4 * oy + 8) + 16 * ny
+    if stage == "p_scan":
+        return 4 * nx + 8 * (nx + 1)
+    return 0
+
+
+def time_oracle(p, products_total, max_seconds=25.0):
+    """The CPU oracle on a bounded sample: a prefix of X against all of Y,
+    sized so one run takes about max_seconds at most.  Returns the record."""
+    import numpy as np
+
+    import oracle
+    from paper_2410_10094_amd.workloads import Coo
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    nx = p.X.nnz
+    frac = 1.0
+    # a small calibration run sets the sample size
+    probe_n = max(1, min(nx, 20_000))
+    Xs = Coo(p.X.dims, p.X.idx[:, :probe_n], p.X.val[:probe_n])
+    _, pairs = oracle.match_counts(Xs, p.Y, p.cx, p.cy)
+    t0 = time.perf_counter()
+    oracle.contract(Xs, p.Y, p.cx, p.cy, nthreads=threads)
+    dt = max(time.perf_counter() - t0, 1e-6)
+    per_product = dt / max(pairs, 1)
+    budget_products = max_seconds / per_product
+    if products_total > budget_products:
+        frac = budget_products / products_total
+    n = max(1, min(nx, int(nx * frac)))
+    Xs = Coo(p.X.dims, p.X.idx[:, :n], p.X.val[:n])
+    _, pairs = oracle.match_counts(Xs, p.Y, p.cx, p.cy)
+    t0 = time.perf_counter()
+    r = oracle.contract(Xs, p.Y, p.cx, p.cy, nthreads=threads)
+    dt = time.perf_counter() - t0
+    sample = "full workload" if n == nx else f"first {n} of {nx} X nonzeros against all of Y"
+    return {"value": pairs / dt, "unit": "products/s", "cores": threads, "kind": "oracle",
+            "sample": f"{sample}: {pairs} products, {r.nnz} outputs, {dt:.2f} s, std::map join, "
+                      f"{threads} threads partitioned by leading output coordinate",
+            "output_nnz_per_s": r.nnz / dt}
+
+
+def run_workload(name, steps, warmup, with_events=True):
+    import torch
+
+    import paper_2410_10094_amd as sptc
+    from paper_2410_10094_amd import binding as B
+    from paper_2410_10094_amd import workloads as W
+
+    p = W.WORKLOADS[name]()
+    X = sptc.DeviceCoo.from_host(p.X)
+    Y = sptc.DeviceCoo.from_host(p.Y)
+    stream = torch.cuda.current_stream()
+
+    # Output buffers are sized once (the bound is the same every step).
+    with sptc.plan(X, Y, p.cx, p.cy) as pl0:
+        out_idx, out_val, out_nnz, cap = pl0.allocate_outputs()
+        products = pl0.products
+        out_slots = pl0.out_table_slots
+        info = dict(y_groups=pl0.y_groups, y_table_slots=pl0.y_table_slots, out_table_slots=out_slots,
+                    workspace_bytes=pl0.workspace_bytes, key_bits=pl0.key_bits)
+
+    nst = len(B.STAGES)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2 * nst)] for _ in range(steps)]
+    ev_arrays = [(ctypes.c_void_p * (2 * nst))(*[e.cuda_event for e in row]) for row in evs]
+    for row in evs:
+        for e in row:
+            e.record(stream)  # materialise the underlying hipEvent_t
+
+    def step(k=None):
+        opt = sptc.default_options()
+        if k is not None and with_events:
+            opt.stage_events = ctypes.cast(ev_arrays[k], ctypes.POINTER(ctypes.c_void_p))
+        pl = sptc.plan(X, Y, p.cx, p.cy, options=opt)
+        pl.execute_into(out_idx, out_val, cap, out_nnz)
+        pl.close()
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(k)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    nnz_z = int(out_nnz.item())
+    if nnz_z < 0:
+        raise RuntimeError(f"device reported status {-nnz_z}")
+    sec = (t1 - t0) / steps
+    stage_ms = {}
+    for s, sname in enumerate(B.STAGES):
+        stage_ms[sname] = sum(evs[k][2 * s].elapsed_time(evs[k][2 * s + 1]) for k in range(steps)) / steps
+    return dict(problem=p, products=products, nnz_z=nnz_z, sec=sec, stage_ms=stage_ms, info=info)
+
+
+def roofline_of(r):
+    p = r["problem"]
+    stage = max(r["stage_ms"], key=lambda s: r["stage_ms"][s])
+    ms = r["stage_ms"][stage]
+    bytes_alg = algorithmic_bytes(stage, p, r["products"], r["nnz_z"])
+    achieved = bytes_alg / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    return {"kernel": stage, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "ms_per_launch": round(ms, 4),
+            "algorithmic_bytes_per_launch": bytes_alg}
+
+
+def summary(name, r):
+    return {"workload": name, "products": r["products"], "out_nnz": r["nnz_z"],
+            "ms_per_step": round(r["sec"] * 1e3, 4), "products_per_s": r["products"] / r["sec"],
+            "output_nnz_per_s": r["nnz_z"] / r["sec"],
+            "stage_ms": {k: round(v, 4) for k, v in r["stage_ms"].items()}, "roofline": roofline_of(r)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="block-sparse", choices=sorted(DESCRIPTIONS))
+    ap.add_argument("--also", default="plain,imbalanced,block-sparse-1.5M",
+                    help="comma-separated extra workloads reported under 'also' ('' for none)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(the contraction would shard X by free key; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+    if args.steps < 1:
+        sys.exit("--steps must be >= 1")
+
+    import torch
+    torch.cuda.set_device(0)
+
+    r = run_workload(args.workload, args.steps, args.warmup)
+    p = r["problem"]
+    also = []
+    for name in [a for a in args.also.split(",") if a and a != args.workload]:
+        also.append(summary(name, run_workload(name, max(3, args.steps // 2), max(1, args.warmup))))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = time_oracle(p, r["products"])
+
+    line = {
+        "metric": METRIC,
+        "value": r["products"] / r["sec"],
+        "unit": "products/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["sec"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": DESCRIPTIONS[args.workload], "nnz_x": p.X.nnz, "nnz_y": p.Y.nnz,
+                   "products": r["products"], "out_nnz": r["nnz_z"], "step": "plan + execute",
+                   "parallelism": "single GPU"},
+        "output_nnz_per_s": r["nnz_z"] / r["sec"],
+        "roofline": roofline_of(r),
+        "cpu_baseline": cpu,
+        "stage_ms": {k: round(v, 4) for k, v in r["stage_ms"].items()},
+        "plan": r["info"],
+        "also": also,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,208 @@
+/*
+ * sptc.h -- sparse-sparse tensor contraction on AMD Instinct MI355X (gfx950).
+ *
+ * Computes, for COO tensors X and Y and paired contracted modes
+ * cx[t] <-> cy[t] (t = 0..ncontract-1),
+ *
+ *     Z[fX, fY] = sum over c of X[fX, c] * Y[c, fY]
+ *
+ * the general contraction of the paper's section 2.2 (Eq. 1, Eq. 2).  The
+ * contract lists pair up by position and paired modes must have equal length
+ * (section 2.2).  The output coordinate is X's free coordinates (ascending X
+ * mode order) followed by Y's free coordinates (ascending Y mode order), as
+ * in Eq. 4 and the matrix product of Fig. 2.  Output entries with equal
+ * coordinates are summed (section 2.4, accumulation); every coordinate reached
+ * by at least one matching pair is emitted, even if its sum is exactly zero.
+ * The output is COO (section 2.1, Fig. 1) in no particular order: the method
+ * never sorts (section 4.1.3), and a sorted output is optional (section 1).
+ *
+ * Method (sections 4.1-4.3 and the footnote to section 4.4): Y's nonzeros are
+ * grouped by their contracting-mode key in a device open-addressing hash with
+ * linear probing (section 2.3.1; the probing table for Y of section 4.2),
+ * counted, prefix-summed and scattered into a grouped array (the counting
+ * sort of section 4.1.1 and the array form of Y of section 4.2).  Every X
+ * nonzero probes that table for its group; the exact number of products P
+ * (the upper bound of section 4.3, taken over all of X) sizes an output hash
+ * keyed by the packed free coordinates.  Products are accumulated there with
+ * FP64 atomics and the table is compacted to COO by count, prefix sum and fill
+ * (writeback, section 2.5).
+ *
+ * Conventions
+ *  - Modes and coordinates are 0-based; 0 <= i_k < I_k (section 2.1.1).
+ *  - Tensor order 0..16 each; mode lengths 1..2^31; nnz < 2^32 - 1.
+ *  - Index arrays are int32, mode-major: idx[m * nnz + e] is coordinate m of
+ *    nonzero e.  Values are IEEE double.  Repeated coordinates are allowed and
+ *    act as separate terms.
+ *  - Coordinates are packed into 64-bit keys with ceil(log2 I_k) bits per
+ *    mode.  The packed X-free plus Y-free width must be at most 63 bits
+ *    (else SPTC_ERR_KEY_OVERFLOW); so must the contracting key.
+ *  - "device" pointers are HIP device memory (or memory the GPU can address,
+ *    e.g. pinned host memory where stated); "host" pointers are read by the
+ *    calling thread only during the call.
+ *  - Streams are hipStream_t passed as void*; NULL is the default stream.
+ *
+ * Errors: every entry point returns an sptc_status; no C++ exception crosses
+ * this interface.  sptc_last_error() gives a thread-local detail string for
+ * the last failure on the calling thread.  Errors found by kernels (probe
+ * length exhausted, coordinate out of range with validation on) are recorded
+ * in the plan: sptc_plan() reports them itself; after sptc_execute() they
+ * make *out_nnz negative (the negated status) and sptc_plan_status() returns
+ * them.
+ */
+#ifndef SPTC_H_
+#define SPTC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__) || defined(__clang__)
+#define SPTC_API __attribute__((visibility("default")))
+#else
+#define SPTC_API
+#endif
+
+#define SPTC_MAX_ORDER 16
+#define SPTC_MAX_OUT_ORDER 32
+
+typedef enum sptc_status {
+  SPTC_OK = 0,
+  SPTC_ERR_INVALID_ARG = 1,   /* null pointer, bad order/mode list, nnz, coordinate out of range */
+  SPTC_ERR_DIM_MISMATCH = 2,  /* paired modes of different length (section 2.2) */
+  SPTC_ERR_KEY_OVERFLOW = 3,  /* packed key wider than 63 bits */
+  SPTC_ERR_OUT_OF_MEMORY = 4, /* allocator returned NULL */
+  SPTC_ERR_CAPACITY = 5,      /* hash probe limit reached, or output larger than out_cap */
+  SPTC_ERR_HIP = 6,           /* a HIP runtime call failed */
+  SPTC_ERR_INTERNAL = 7
+} sptc_status;
+
+/* Optional device-memory allocator.  alloc returns device memory of `bytes`
+ * usable in stream order on `stream` (NULL on failure); release frees it in
+ * stream order.  When no allocator is given the library uses the device's
+ * stream-ordered memory pool (hipMallocAsync / hipFreeAsync). */
+typedef struct sptc_allocator {
+  void* (*alloc)(size_t bytes, void* stream, void* ctx);
+  void (*release)(void* ptr, size_t bytes, void* stream, void* ctx);
+  void* ctx;
+} sptc_allocator;
+
+/* A COO tensor (section 2.1, Fig. 1).  dims: host [order].  idx: device
+ * int32 [order][nnz] mode-major.  val: device double [nnz].  Both device
+ * arrays are borrowed: they must stay valid and unchanged while any plan
+ * built from them is executed (the plan reads X and Y when built). */
+typedef struct sptc_coo {
+  int32_t order;
+  const int64_t* dims;
+  int64_t nnz;
+  const int32_t* idx;
+  const double* val;
+} sptc_coo;
+
+/* Pipeline stages, for optional per-stage timing with HIP events. */
+typedef enum sptc_stage {
+  SPTC_STAGE_Y_COUNT = 0,    /* Y key table: clear, then count entries per contracting key */
+  SPTC_STAGE_Y_SCAN = 1,     /* prefix sum of the counts: group boundaries */
+  SPTC_STAGE_Y_SCATTER = 2,  /* grouped Y array */
+  SPTC_STAGE_X_PROBE = 3,    /* per X nonzero: its Y group */
+  SPTC_STAGE_P_SCAN = 4,     /* prefix sum of products per X nonzero; P */
+  SPTC_STAGE_OUT_CLEAR = 5,  /* output hash: mark every slot empty */
+  SPTC_STAGE_EXPAND = 6,     /* expand products, accumulate in the output hash */
+  SPTC_STAGE_COMPACT = 7,    /* output hash -> COO: count, prefix sum, fill */
+  SPTC_NUM_STAGES = 8
+} sptc_stage;
+
+typedef struct sptc_options {
+  double load_factor;        /* hash fill target in (0, 0.95]; default 1/1.3 (section 2.3.1) */
+  int32_t validate;          /* nonzero: check every coordinate is within its mode length */
+  int32_t max_probe;         /* probe-length guard per insert; 0 = table capacity */
+  uint64_t hash_seed;        /* xored into keys before hashing */
+  int64_t out_table_slots;   /* 0 = sized from the product count; else a power of two (testing) */
+  void** stage_events;       /* NULL, or 2*SPTC_NUM_STAGES hipEvent_t: entry 2s is recorded on the
+                                stream before stage s and entry 2s+1 after it (NULL entries skipped);
+                                the caller owns the events and keeps the array alive */
+} sptc_options;
+
+/* Sizes fixed by sptc_plan. */
+typedef struct sptc_info {
+  int32_t out_order;                       /* (order_X - ncontract) + (order_Y - ncontract) */
+  int64_t out_dims[SPTC_MAX_OUT_ORDER];    /* X free dims ascending, then Y free dims ascending */
+  int64_t products;                        /* P: number of matching (x, y) pairs */
+  int64_t out_nnz_bound;                   /* min(P, product of out_dims): enough out_cap */
+  int64_t y_groups;                        /* distinct contracting keys among Y's nonzeros */
+  int64_t y_table_slots;                   /* capacity of the Y key table */
+  int64_t out_table_slots;                 /* capacity of the output hash */
+  int64_t workspace_bytes;                 /* device memory the plan holds */
+  int32_t key_bits_contract, key_bits_x_free, key_bits_y_free;
+} sptc_info;
+
+typedef struct sptc_plan_s* sptc_plan_t;
+
+/* Fill *opt with the defaults. */
+SPTC_API void sptc_default_options(sptc_options* opt);
+
+/* Build a plan: group Y by contracting key, probe every X nonzero, count the
+ * products and size the output hash.  Enqueues work on `stream` and
+ * synchronises it once, to read the product count.  opt and alloc may be
+ * NULL.  On success *plan owns all workspace (released by sptc_free).  On
+ * failure *plan is NULL and nothing stays allocated. */
+SPTC_API sptc_status sptc_plan(sptc_plan_t* plan, const sptc_coo* X, const sptc_coo* Y, int32_t ncontract,
+                      const int32_t* cx, const int32_t* cy, const sptc_options* opt,
+                      const sptc_allocator* alloc, void* stream);
+
+/* Copy the plan's sizes into *info (host).  Does not synchronise. */
+SPTC_API sptc_status sptc_plan_info(sptc_plan_t plan, sptc_info* info);
+
+/* Expand all products, accumulate them in the output hash and write Z as
+ * COO: out_idx device int32 [out_order][out_cap] (mode-major with row stride
+ * out_cap; may be NULL when out_order is 0), out_val device double [out_cap],
+ * out_nnz a device or pinned-host int64 that receives nnz(Z), or the negated
+ * status when a kernel recorded an error (including nnz(Z) > out_cap, in
+ * which case only the first out_cap entries are written).  Never
+ * synchronises, allocates or copies to the host, so it can be captured into a
+ * HIP graph; the plan may be executed any number of times.  Executions of one
+ * plan must not overlap. */
+SPTC_API sptc_status sptc_execute(sptc_plan_t plan, int32_t* out_idx, double* out_val, int64_t out_cap,
+                         int64_t* out_nnz, void* stream);
+
+/* Replace the stage events used by later sptc_execute calls (same layout as
+ * sptc_options.stage_events; NULL turns timing off). */
+SPTC_API sptc_status sptc_plan_set_stage_events(sptc_plan_t plan, void** events);
+
+/* Synchronise `stream` and return the first error a kernel recorded for this
+ * plan (SPTC_OK if none). */
+SPTC_API sptc_status sptc_plan_status(sptc_plan_t plan, void* stream);
+
+/* Release the plan's workspace in stream order on the plan's stream. */
+SPTC_API void sptc_free(sptc_plan_t plan);
+
+SPTC_API const char* sptc_status_string(sptc_status status);
+SPTC_API const char* sptc_last_error(void);
+
+/* ---- Inspection of the plan's intermediate structures (stage checks) ---- */
+
+/* The Y groups (sections 4.1.1 and 4.2): for each distinct contracting key,
+ * its coordinates (device int32 [ncontract][cap], mode-major, in cy order),
+ * its number of entries and the start of its run in the grouped Y array
+ * (device int64 [cap] each).  *ngroups (host) receives the group count; when
+ * it exceeds cap nothing is written and SPTC_ERR_CAPACITY is returned.
+ * Groups come in table order.  Synchronises `stream`. */
+SPTC_API sptc_status sptc_plan_y_groups(sptc_plan_t plan, int32_t* key_coords, int64_t* counts, int64_t* starts,
+                               int64_t cap, int64_t* ngroups, void* stream);
+
+/* The grouped Y array (section 4.2): entry k's Y free coordinates (device
+ * int32 [order_Y - ncontract][nnz_Y], mode-major, ascending Y mode order) and
+ * value (device double [nnz_Y]).  Enqueued on `stream`. */
+SPTC_API sptc_status sptc_plan_y_grouped(sptc_plan_t plan, int32_t* free_coords, double* vals, void* stream);
+
+/* Per X nonzero, the number of Y nonzeros sharing its contracting key
+ * (device int64 [nnz_X]).  Enqueued on `stream`. */
+SPTC_API sptc_status sptc_plan_x_counts(sptc_plan_t plan, int64_t* counts, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPTC_H_ */

@@ -1,0 +1,555 @@
+// Host runtime of the C ABI in include/sptc.h: argument validation, key
+// layout, table sizing, workspace management and kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/sptc.h"
+#include "sptc_internal.hpp"
+
+using namespace sptc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+sptc_status fail(sptc_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+sptc_status hip_fail(hipError_t e, const char* what) {
+  return fail(SPTC_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                             \
+  do {                                            \
+    hipError_t e_ = (expr);                       \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr); \
+  } while (0)
+
+int32_t bits_for(int64_t d) {
+  if (d <= 1) return 0;
+  return 64 - __builtin_clzll((unsigned long long)(d - 1));
+}
+
+// Saturating product of mode lengths.
+int64_t sat_prod(const int64_t* d, const std::vector<int32_t>& modes) {
+  const int64_t cap = (int64_t)1 << 62;
+  int64_t p = 1;
+  for (int32_t m : modes) {
+    if (p > cap / std::max<int64_t>(d[m], 1)) return cap;
+    p *= d[m];
+  }
+  return p;
+}
+
+int64_t pow2_at_least(double x) {
+  int64_t c = 2;
+  while ((double)c < x && c < ((int64_t)1 << 46)) c <<= 1;
+  return c;
+}
+
+struct DeviceInfo {
+  int num_cus = 0;
+  bool pool_configured = false;
+};
+
+std::mutex g_dev_mu;
+DeviceInfo g_dev[64];
+
+sptc_status device_info(int dev, DeviceInfo** out) {
+  if (dev < 0 || dev >= 64) return fail(SPTC_ERR_HIP, "device ordinal %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_dev_mu);
+  DeviceInfo& d = g_dev[dev];
+  if (d.num_cus == 0) {
+    int cus = 0;
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    d.num_cus = std::max(cus, 1);
+  }
+  *out = &d;
+  return SPTC_OK;
+}
+
+sptc_status configure_pool(int dev, DeviceInfo* d) {
+  std::lock_guard<std::mutex> lock(g_dev_mu);
+  if (d->pool_configured) return SPTC_OK;
+  hipMemPool_t pool;
+  HIP_TRY(hipDeviceGetDefaultMemPool(&pool, dev));
+  uint64_t threshold = ~0ull;  // keep freed blocks cached in the pool
+  HIP_TRY(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &threshold));
+  d->pool_configured = true;
+  return SPTC_OK;
+}
+
+}  // namespace
+
+struct sptc_plan_s {
+  struct Buf {
+    void* p;
+    size_t bytes;
+  };
+
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool has_alloc = false;
+  sptc_allocator alloc{};
+  sptc_options opt{};
+  int num_cus = 1;
+
+  int32_t ox = 0, oy = 0, nc = 0;
+  int64_t nx = 0, ny = 0;
+  int32_t out_order = 0;
+  int64_t out_dims[SPTC_MAX_OUT_ORDER] = {};
+  int32_t bits_c = 0, bits_fx = 0, bits_fy = 0;
+  int32_t nfy = 0;
+
+  KeyPack x_c{}, x_f{}, y_c{}, y_f{};
+  Bounds xb{}, yb{};
+  KeyUnpack out_unpack{}, ykey_unpack{}, yfree_unpack{};
+
+  std::vector<Buf> bufs;
+  YSlot* ytab = nullptr;
+  int64_t ytab_slots = 0;
+  YEntry* yg = nullptr;
+  XEntry* xrec = nullptr;
+  uint32_t* xg = nullptr;
+  uint32_t* xcnt = nullptr;
+  unsigned long long* poff = nullptr;
+  unsigned long long* tile_sums = nullptr;
+  DevStatus* st = nullptr;
+  int64_t* scratch = nullptr;
+  ZSlot* ztab = nullptr;
+  int64_t ztab_slots = 0;
+  unsigned long long* ztile_sums = nullptr;
+
+  int64_t products = 0, y_groups = 0, out_bound = 0;
+  int64_t workspace = 0;
+  int32_t max_probe_y = 0, max_probe_z = 0;
+
+  sptc_status allocate(size_t bytes, void** out) {
+    bytes = std::max<size_t>(bytes, 16);
+    bytes = (bytes + 255) & ~(size_t)255;
+    void* p = nullptr;
+    if (has_alloc) {
+      p = alloc.alloc(bytes, stream, alloc.ctx);
+      if (!p) return fail(SPTC_ERR_OUT_OF_MEMORY, "allocator returned NULL for %zu bytes", bytes);
+    } else {
+      hipError_t e = hipMallocAsync(&p, bytes, stream);
+      if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return fail(SPTC_ERR_OUT_OF_MEMORY, "hipMallocAsync(%zu bytes): %s", bytes, hipGetErrorString(e));
+      }
+    }
+    bufs.push_back({p, bytes});
+    workspace += (int64_t)bytes;
+    *out = p;
+    return SPTC_OK;
+  }
+
+  template <class T>
+  sptc_status allocate_n(int64_t n, T** out) {
+    void* p = nullptr;
+    sptc_status s = allocate(sizeof(T) * (size_t)std::max<int64_t>(n, 1), &p);
+    *out = static_cast<T*>(p);
+    return s;
+  }
+
+  void release_all() {
+    for (auto it = bufs.rbegin(); it != bufs.rend(); ++it) {
+      if (has_alloc) {
+        if (alloc.release) alloc.release(it->p, it->bytes, stream, alloc.ctx);
+      } else {
+        (void)hipFreeAsync(it->p, stream);
+      }
+    }
+    bufs.clear();
+    workspace = 0;
+  }
+};
+
+namespace {
+
+sptc_status check_coo(const sptc_coo* T, const char* name) {
+  if (!T) return fail(SPTC_ERR_INVALID_ARG, "%s is NULL", name);
+  if (T->order < 0 || T->order > SPTC_MAX_ORDER)
+    return fail(SPTC_ERR_INVALID_ARG, "%s: order %d outside 0..%d", name, T->order, SPTC_MAX_ORDER);
+  if (T->order > 0 && !T->dims) return fail(SPTC_ERR_INVALID_ARG, "%s: dims is NULL", name);
+  for (int32_t m = 0; m < T->order; ++m)
+    if (T->dims[m] < 1 || T->dims[m] > ((int64_t)1 << 31))
+      return fail(SPTC_ERR_INVALID_ARG, "%s: mode %d length %lld outside 1..2^31", name, m, (long long)T->dims[m]);
+  if (T->nnz < 0 || T->nnz > (int64_t)0xfffffffeLL)
+    return fail(SPTC_ERR_INVALID_ARG, "%s: nnz %lld outside 0..2^32-2", name, (long long)T->nnz);
+  if (T->nnz > 0 && !T->val) return fail(SPTC_ERR_INVALID_ARG, "%s: val is NULL", name);
+  if (T->nnz > 0 && T->order > 0 && !T->idx) return fail(SPTC_ERR_INVALID_ARG, "%s: idx is NULL", name);
+  return SPTC_OK;
+}
+
+sptc_status check_options(const sptc_options& o) {
+  if (!(o.load_factor > 0.0 && o.load_factor <= 0.95))
+    return fail(SPTC_ERR_INVALID_ARG, "load_factor %g outside (0, 0.95]", o.load_factor);
+  if (o.max_probe < 0) return fail(SPTC_ERR_INVALID_ARG, "max_probe %d < 0", o.max_probe);
+  if (o.out_table_slots != 0 && (o.out_table_slots < 2 || (o.out_table_slots & (o.out_table_slots - 1))))
+    return fail(SPTC_ERR_INVALID_ARG, "out_table_slots %lld is not a power of two >= 2",
+                (long long)o.out_table_slots);
+  return SPTC_OK;
+}
+
+// Lays out `modes` of a tensor in a key, first listed mode most significant.
+KeyPack make_pack(const int64_t* dims, const std::vector<int32_t>& modes, int32_t* total_bits) {
+  KeyPack kp{};
+  kp.n = (int32_t)modes.size();
+  int32_t shift = 0;
+  for (int32_t k = kp.n - 1; k >= 0; --k) {
+    const int32_t b = bits_for(dims[modes[k]]);
+    kp.mode[k] = modes[k];
+    kp.shift[k] = shift;
+    kp.mask[k] = b == 0 ? 0u : (uint32_t)((1ull << b) - 1ull);
+    shift += b;
+  }
+  *total_bits = shift;
+  return kp;
+}
+
+void add_unpack(KeyUnpack& ku, const KeyPack& kp, int32_t extra_shift) {
+  for (int32_t k = 0; k < kp.n; ++k) {
+    ku.shift[ku.n] = kp.shift[k] + extra_shift;
+    ku.mask[ku.n] = kp.mask[k];
+    ku.n++;
+  }
+}
+
+Bounds make_bounds(const sptc_coo* T, int32_t check) {
+  Bounds b{};
+  b.order = T->order;
+  for (int32_t m = 0; m < T->order; ++m) b.dim[m] = (uint32_t)T->dims[m];
+  b.check = check;
+  return b;
+}
+
+// Records the stage's begin (0) or end (1) event when the caller asked for it.
+hipError_t mark(const sptc_plan_s* P, hipStream_t s, int stage, int end) {
+  if (!P->opt.stage_events) return hipSuccess;
+  void* ev = P->opt.stage_events[2 * stage + end];
+  return ev ? hipEventRecord(static_cast<hipEvent_t>(ev), s) : hipSuccess;
+}
+
+sptc_status status_from_bits(uint32_t err) {
+  if (err & kErrCoord) return fail(SPTC_ERR_INVALID_ARG, "a coordinate is outside its mode length");
+  if (err & kErrCapacity) return fail(SPTC_ERR_CAPACITY, "hash probe limit reached or output larger than out_cap");
+  if (err) return fail(SPTC_ERR_INTERNAL, "internal consistency check failed on the device (bits 0x%x)", err);
+  return SPTC_OK;
+}
+
+sptc_status plan_body(sptc_plan_s* P, const sptc_coo* X, const sptc_coo* Y, const int32_t* cx, const int32_t* cy) {
+  const hipStream_t s = P->stream;
+  // Y table sized from the number of distinct keys it can hold.
+  std::vector<int32_t> cyv(cy, cy + P->nc), cxv(cx, cx + P->nc);
+  const int64_t key_space = sat_prod(Y->dims, cyv);
+  const int64_t y_bound = std::min<int64_t>(P->ny, key_space);
+  P->ytab_slots = pow2_at_least((double)y_bound / P->opt.load_factor);
+  P->max_probe_y = P->opt.max_probe > 0 ? P->opt.max_probe : (int32_t)std::min<int64_t>(P->ytab_slots, 1 << 30);
+
+  sptc_status st;
+  if ((st = P->allocate_n(P->ytab_slots, &P->ytab))) return st;
+  if ((st = P->allocate_n(P->ny, &P->yg))) return st;
+  if ((st = P->allocate_n(P->nx, &P->xrec))) return st;
+  if ((st = P->allocate_n(P->nx, &P->xg))) return st;
+  if ((st = P->allocate_n(P->nx, &P->xcnt))) return st;
+  if ((st = P->allocate_n(P->nx + 1, &P->poff))) return st;
+  const int64_t tiles = std::max<int64_t>(scan_tiles(P->ytab_slots), scan_tiles(P->nx));
+  if ((st = P->allocate_n(tiles + 1, &P->tile_sums))) return st;
+  if ((st = P->allocate_n(1, &P->st))) return st;
+  if ((st = P->allocate_n(2, &P->scratch))) return st;
+
+  const uint64_t ymask = (uint64_t)P->ytab_slots - 1;
+  const uint64_t seed = P->opt.hash_seed;
+  HIP_TRY(hipMemsetAsync(P->st, 0, sizeof(DevStatus), s));
+  HIP_TRY(mark(P, s, SPTC_STAGE_Y_COUNT, 0));
+  HIP_TRY(launch_fill_empty(P->ytab, P->ytab_slots, nullptr, s));
+  HIP_TRY(launch_y_count(Y->idx, P->ny, P->y_c, P->ytab, ymask, seed, P->max_probe_y, P->st, P->num_cus, s));
+  HIP_TRY(mark(P, s, SPTC_STAGE_Y_COUNT, 1));
+  HIP_TRY(mark(P, s, SPTC_STAGE_Y_SCAN, 0));
+  HIP_TRY(launch_scan_y_table(P->ytab, P->ytab_slots, P->tile_sums, s));
+  HIP_TRY(mark(P, s, SPTC_STAGE_Y_SCAN, 1));
+  HIP_TRY(mark(P, s, SPTC_STAGE_Y_SCATTER, 0));
+  HIP_TRY(launch_y_scatter(Y->idx, Y->val, P->ny, P->y_c, P->y_f, P->yb, P->ytab, ymask, seed, P->max_probe_y,
+                           P->yg, P->st, P->num_cus, s));
+  HIP_TRY(mark(P, s, SPTC_STAGE_Y_SCATTER, 1));
+  HIP_TRY(mark(P, s, SPTC_STAGE_X_PROBE, 0));
+  HIP_TRY(launch_x_probe(X->idx, X->val, P->nx, P->x_c, P->x_f, P->xb, P->ytab, ymask, seed, P->max_probe_y,
+                         P->xrec, P->xg, P->xcnt, P->st, P->num_cus, s));
+  HIP_TRY(mark(P, s, SPTC_STAGE_X_PROBE, 1));
+  HIP_TRY(mark(P, s, SPTC_STAGE_P_SCAN, 0));
+  HIP_TRY(launch_scan_products(P->xcnt, P->nx, P->poff, P->tile_sums, P->st, s));
+  HIP_TRY(mark(P, s, SPTC_STAGE_P_SCAN, 1));
+
+  DevStatus host{};
+  HIP_TRY(hipMemcpyAsync(&host, P->st, sizeof host, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if ((st = status_from_bits(host.err))) return st;
+  P->products = (int64_t)host.products;
+  P->y_groups = (int64_t)host.groups;
+
+  // Output hash sized from the exact product count (section 4.3's bound,
+  // over all of X), capped by the number of output cells.
+  std::vector<int32_t> none;
+  int64_t cells = 1;
+  for (int32_t m = 0; m < P->out_order; ++m) {
+    if (cells > ((int64_t)1 << 62) / P->out_dims[m]) {
+      cells = (int64_t)1 << 62;
+      break;
+    }
+    cells *= P->out_dims[m];
+  }
+  P->out_bound = std::min<int64_t>(P->products, cells);
+  if (P->opt.out_table_slots > 0)
+    P->ztab_slots = P->opt.out_table_slots;
+  else
+    P->ztab_slots = pow2_at_least((double)P->out_bound / P->opt.load_factor);
+  P->max_probe_z = P->opt.max_probe > 0 ? P->opt.max_probe : (int32_t)std::min<int64_t>(P->ztab_slots, 1 << 30);
+  if ((st = P->allocate_n(P->ztab_slots, &P->ztab))) return st;
+  if ((st = P->allocate_n(scan_tiles(P->ztab_slots) + 1, &P->ztile_sums))) return st;
+  return SPTC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void sptc_default_options(sptc_options* opt) {
+  if (!opt) return;
+  opt->load_factor = 1.0 / 1.3;
+  opt->validate = 1;
+  opt->max_probe = 0;
+  opt->hash_seed = 0x9e3779b97f4a7c15ull;
+  opt->out_table_slots = 0;
+  opt->stage_events = nullptr;
+}
+
+sptc_status sptc_plan(sptc_plan_t* plan, const sptc_coo* X, const sptc_coo* Y, int32_t ncontract, const int32_t* cx,
+                      const int32_t* cy, const sptc_options* opt, const sptc_allocator* alloc, void* stream) {
+  if (!plan) return fail(SPTC_ERR_INVALID_ARG, "plan is NULL");
+  *plan = nullptr;
+  sptc_status st;
+  if ((st = check_coo(X, "X"))) return st;
+  if ((st = check_coo(Y, "Y"))) return st;
+  if (ncontract < 0 || ncontract > X->order || ncontract > Y->order)
+    return fail(SPTC_ERR_INVALID_ARG, "ncontract %d outside 0..min(order_X, order_Y)", ncontract);
+  if (ncontract > 0 && (!cx || !cy)) return fail(SPTC_ERR_INVALID_ARG, "cx or cy is NULL");
+  for (int32_t t = 0; t < ncontract; ++t) {
+    if (cx[t] < 0 || cx[t] >= X->order) return fail(SPTC_ERR_INVALID_ARG, "cx[%d] = %d out of range", t, cx[t]);
+    if (cy[t] < 0 || cy[t] >= Y->order) return fail(SPTC_ERR_INVALID_ARG, "cy[%d] = %d out of range", t, cy[t]);
+    for (int32_t u = 0; u < t; ++u)
+      if (cx[u] == cx[t] || cy[u] == cy[t]) return fail(SPTC_ERR_INVALID_ARG, "a mode is contracted twice");
+  }
+  for (int32_t t = 0; t < ncontract; ++t)
+    if (X->dims[cx[t]] != Y->dims[cy[t]])
+      return fail(SPTC_ERR_DIM_MISMATCH, "X mode %d has length %lld but Y mode %d has length %lld", cx[t],
+                  (long long)X->dims[cx[t]], cy[t], (long long)Y->dims[cy[t]]);
+  sptc_options o;
+  sptc_default_options(&o);
+  if (opt) o = *opt;
+  if ((st = check_options(o))) return st;
+  if (alloc && (!alloc->alloc || !alloc->release))
+    return fail(SPTC_ERR_INVALID_ARG, "allocator must provide alloc and release");
+
+  // Key layout: contracting key in cx/cy order, free keys in ascending mode
+  // order, output key = (X free << Y free bits) | Y free.
+  std::vector<int32_t> cxv(cx, cx + ncontract), cyv(cy, cy + ncontract), fx, fy;
+  for (int32_t m = 0; m < X->order; ++m)
+    if (std::find(cxv.begin(), cxv.end(), m) == cxv.end()) fx.push_back(m);
+  for (int32_t m = 0; m < Y->order; ++m)
+    if (std::find(cyv.begin(), cyv.end(), m) == cyv.end()) fy.push_back(m);
+
+  sptc_plan_s* P = new (std::nothrow) sptc_plan_s();
+  if (!P) return fail(SPTC_ERR_OUT_OF_MEMORY, "host allocation failed");
+  P->opt = o;
+  P->stream = static_cast<hipStream_t>(stream);
+  if (alloc) {
+    P->has_alloc = true;
+    P->alloc = *alloc;
+  }
+  P->ox = X->order;
+  P->oy = Y->order;
+  P->nc = ncontract;
+  P->nx = X->nnz;
+  P->ny = Y->nnz;
+  int32_t bits_cx = 0, bits_cy = 0;
+  P->x_c = make_pack(X->dims, cxv, &bits_cx);
+  P->y_c = make_pack(Y->dims, cyv, &bits_cy);
+  P->x_f = make_pack(X->dims, fx, &P->bits_fx);
+  P->y_f = make_pack(Y->dims, fy, &P->bits_fy);
+  P->bits_c = bits_cx;
+  P->nfy = (int32_t)fy.size();
+  P->out_order = (int32_t)(fx.size() + fy.size());
+  {
+    int32_t k = 0;
+    for (int32_t m : fx) P->out_dims[k++] = X->dims[m];
+    for (int32_t m : fy) P->out_dims[k++] = Y->dims[m];
+  }
+  add_unpack(P->out_unpack, P->x_f, P->bits_fy);
+  add_unpack(P->out_unpack, P->y_f, 0);
+  add_unpack(P->ykey_unpack, P->y_c, 0);
+  add_unpack(P->yfree_unpack, P->y_f, 0);
+  P->xb = make_bounds(X, o.validate);
+  P->yb = make_bounds(Y, o.validate);
+  if (P->bits_c > 63) {
+    delete P;
+    return fail(SPTC_ERR_KEY_OVERFLOW, "contracting key needs %d bits (> 63)", bits_cx);
+  }
+  if (P->bits_fx + P->bits_fy > 63) {
+    int32_t b = P->bits_fx + P->bits_fy;
+    delete P;
+    return fail(SPTC_ERR_KEY_OVERFLOW, "output key needs %d bits (> 63)", b);
+  }
+
+  DeviceInfo* di = nullptr;
+  hipError_t e = hipGetDevice(&P->device);
+  if (e != hipSuccess) {
+    delete P;
+    return hip_fail(e, "hipGetDevice");
+  }
+  if ((st = device_info(P->device, &di)) || (!P->has_alloc && (st = configure_pool(P->device, di)))) {
+    delete P;
+    return st;
+  }
+  P->num_cus = di->num_cus;
+
+  st = plan_body(P, X, Y, cx, cy);
+  if (st != SPTC_OK) {
+    std::string msg = g_last_error;
+    (void)hipStreamSynchronize(P->stream);
+    P->release_all();
+    delete P;
+    g_last_error = msg;
+    return st;
+  }
+  *plan = P;
+  return SPTC_OK;
+}
+
+sptc_status sptc_plan_info(sptc_plan_t P, sptc_info* info) {
+  if (!P || !info) return fail(SPTC_ERR_INVALID_ARG, "plan or info is NULL");
+  std::memset(info, 0, sizeof *info);
+  info->out_order = P->out_order;
+  for (int32_t m = 0; m < P->out_order; ++m) info->out_dims[m] = P->out_dims[m];
+  info->products = P->products;
+  info->out_nnz_bound = P->out_bound;
+  info->y_groups = P->y_groups;
+  info->y_table_slots = P->ytab_slots;
+  info->out_table_slots = P->ztab_slots;
+  info->workspace_bytes = P->workspace;
+  info->key_bits_contract = P->bits_c;
+  info->key_bits_x_free = P->bits_fx;
+  info->key_bits_y_free = P->bits_fy;
+  return SPTC_OK;
+}
+
+sptc_status sptc_execute(sptc_plan_t P, int32_t* out_idx, double* out_val, int64_t out_cap, int64_t* out_nnz,
+                         void* stream) {
+  if (!P) return fail(SPTC_ERR_INVALID_ARG, "plan is NULL");
+  if (!out_nnz) return fail(SPTC_ERR_INVALID_ARG, "out_nnz is NULL");
+  if (out_cap < 0) return fail(SPTC_ERR_INVALID_ARG, "out_cap < 0");
+  if (out_cap > 0 && !out_val) return fail(SPTC_ERR_INVALID_ARG, "out_val is NULL");
+  if (out_cap > 0 && P->out_order > 0 && !out_idx) return fail(SPTC_ERR_INVALID_ARG, "out_idx is NULL");
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  const uint64_t zmask = (uint64_t)P->ztab_slots - 1;
+  HIP_TRY(mark(P, s, SPTC_STAGE_OUT_CLEAR, 0));
+  HIP_TRY(launch_fill_empty(P->ztab, P->ztab_slots, P->st, s));
+  HIP_TRY(mark(P, s, SPTC_STAGE_OUT_CLEAR, 1));
+  HIP_TRY(mark(P, s, SPTC_STAGE_EXPAND, 0));
+  HIP_TRY(launch_expand_acc(P->poff, P->nx, P->xrec, P->xg, P->yg, P->ny, P->bits_fy, P->ztab, zmask,
+                            P->opt.hash_seed, P->max_probe_z, (uint64_t)P->products, P->st, P->num_cus, s));
+  HIP_TRY(mark(P, s, SPTC_STAGE_EXPAND, 1));
+  HIP_TRY(mark(P, s, SPTC_STAGE_COMPACT, 0));
+  HIP_TRY(launch_compact(P->ztab, P->ztab_slots, P->out_unpack, out_idx, out_val, out_cap, out_nnz, P->ztile_sums,
+                         P->st, s));
+  HIP_TRY(mark(P, s, SPTC_STAGE_COMPACT, 1));
+  return SPTC_OK;
+}
+
+sptc_status sptc_plan_set_stage_events(sptc_plan_t P, void** events) {
+  if (!P) return fail(SPTC_ERR_INVALID_ARG, "plan is NULL");
+  P->opt.stage_events = events;
+  return SPTC_OK;
+}
+
+sptc_status sptc_plan_status(sptc_plan_t P, void* stream) {
+  if (!P) return fail(SPTC_ERR_INVALID_ARG, "plan is NULL");
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  DevStatus host{};
+  HIP_TRY(hipMemcpyAsync(&host, P->st, sizeof host, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return status_from_bits(host.err);
+}
+
+void sptc_free(sptc_plan_t P) {
+  if (!P) return;
+  P->release_all();
+  delete P;
+}
+
+const char* sptc_status_string(sptc_status s) {
+  switch (s) {
+    case SPTC_OK: return "success";
+    case SPTC_ERR_INVALID_ARG: return "invalid argument";
+    case SPTC_ERR_DIM_MISMATCH: return "contracted modes have different lengths";
+    case SPTC_ERR_KEY_OVERFLOW: return "packed key wider than 63 bits";
+    case SPTC_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case SPTC_ERR_CAPACITY: return "hash table or output capacity exceeded";
+    case SPTC_ERR_HIP: return "HIP runtime error";
+    case SPTC_ERR_INTERNAL: return "internal error";
+  }
+  return "unknown status";
+}
+
+const char* sptc_last_error(void) { return g_last_error.c_str(); }
+
+sptc_status sptc_plan_y_groups(sptc_plan_t P, int32_t* key_coords, int64_t* counts, int64_t* starts, int64_t cap,
+                               int64_t* ngroups, void* stream) {
+  if (!P || !ngroups) return fail(SPTC_ERR_INVALID_ARG, "plan or ngroups is NULL");
+  *ngroups = P->y_groups;
+  if (P->y_groups > cap) return fail(SPTC_ERR_CAPACITY, "%lld groups exceed cap %lld", (long long)P->y_groups,
+                                     (long long)cap);
+  if (cap > 0 && (!counts || !starts || (P->nc > 0 && !key_coords)))
+    return fail(SPTC_ERR_INVALID_ARG, "output pointer is NULL");
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(launch_y_groups(P->ytab, P->ytab_slots, P->ykey_unpack, key_coords, counts, starts, cap, P->scratch,
+                          P->tile_sums, P->st, s));
+  int64_t n = 0;
+  HIP_TRY(hipMemcpyAsync(&n, P->scratch, sizeof n, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (n != P->y_groups) return fail(SPTC_ERR_INTERNAL, "group count %lld != %lld", (long long)n,
+                                    (long long)P->y_groups);
+  return SPTC_OK;
+}
+
+sptc_status sptc_plan_y_grouped(sptc_plan_t P, int32_t* free_coords, double* vals, void* stream) {
+  if (!P) return fail(SPTC_ERR_INVALID_ARG, "plan is NULL");
+  if (P->ny > 0 && (!vals || (P->nfy > 0 && !free_coords))) return fail(SPTC_ERR_INVALID_ARG, "output is NULL");
+  HIP_TRY(launch_y_grouped(P->yg, P->ny, P->yfree_unpack, free_coords, vals, static_cast<hipStream_t>(stream)));
+  return SPTC_OK;
+}
+
+sptc_status sptc_plan_x_counts(sptc_plan_t P, int64_t* counts, void* stream) {
+  if (!P) return fail(SPTC_ERR_INVALID_ARG, "plan is NULL");
+  if (P->nx > 0 && !counts) return fail(SPTC_ERR_INVALID_ARG, "counts is NULL");
+  HIP_TRY(launch_x_counts(P->poff, P->nx, counts, static_cast<hipStream_t>(stream)));
+  return SPTC_OK;
+}
+
+}  // extern "C"

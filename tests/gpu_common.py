@@ -1,0 +1,43 @@
+"""Helpers for the GPU tests: run the HIP path through the C ABI and compare
+with the oracle."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+
+import oracle
+from tests import helpers as H
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def to_device(p):
+    import paper_2410_10094_amd as sptc
+    return sptc.DeviceCoo.from_host(p.X), sptc.DeviceCoo.from_host(p.Y)
+
+
+def run_gpu(p, options=None, allocator="pool"):
+    """Plan + execute on cuda:0; returns (plan info dict, idx numpy, val numpy)."""
+    import paper_2410_10094_amd as sptc
+    X, Y = to_device(p)
+    with sptc.plan(X, Y, p.cx, p.cy, options=options, allocator=allocator) as pl:
+        idx, val = pl.execute()
+        info = dict(products=pl.products, out_nnz_bound=pl.out_nnz_bound, y_groups=pl.y_groups,
+                    out_order=pl.out_order, out_dims=pl.out_dims, out_table_slots=pl.out_table_slots)
+        return info, idx.cpu().numpy(), val.cpu().numpy()
+
+
+def assert_parity(p, gidx, gval, ref=None, nthreads=8):
+    """Coordinates and nnz bit-exact after sorting; values within the
+    tolerance of helpers.value_tolerance."""
+    if ref is None:
+        ref = oracle.contract(p.X, p.Y, p.cx, p.cy, nthreads=nthreads)
+    assert gval.shape[0] == ref.nnz, f"nnz {gval.shape[0]} != oracle {ref.nnz}"
+    gi, gv = H.sort_coo(gidx, gval)
+    np.testing.assert_array_equal(gi, ref.idx)
+    H.assert_values_close(gv, ref.val, ref.absval, ref.terms)
+    return ref

@@ -1,0 +1,128 @@
+"""The C-ABI library loads and exports every declared symbol, and argument
+validation (which runs before any HIP call) reports the right status.  CPU
+only: no call here reaches the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2410_10094_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    with open(os.path.join(ROOT, "include", "sptc.h")) as f:
+        text = f.read()
+    return re.findall(r"SPTC_API\s+[\w\s\*]+?\b(sptc_\w+)\s*\(", text)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = B.load()
+    names = declared_functions()
+    assert len(names) >= 11
+    assert set(names) == set(B.EXPORTS)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_status_strings():
+    for s in range(8):
+        assert B.status_string(s)
+    assert B.status_string(0) == "success"
+
+
+def test_default_options():
+    o = B.default_options()
+    assert abs(o.load_factor - 1 / 1.3) < 1e-15
+    assert o.validate == 1 and o.max_probe == 0 and o.out_table_slots == 0
+
+
+def _plan(X, Y, cx, cy, opt=None):
+    lib = B.load()
+    h = ctypes.c_void_p(12345)
+    acx, acy = B.int_array(cx), B.int_array(cy)
+    st = lib.sptc_plan(ctypes.byref(h), ctypes.byref(X) if X is not None else None,
+                       ctypes.byref(Y) if Y is not None else None, len(cx), acx, acy,
+                       ctypes.byref(opt) if opt is not None else None, None, None)
+    return st, h.value
+
+
+# Non-null fake device pointers: validation never dereferences them.
+FAKE = 0x1000
+
+
+def coo(dims, nnz=4, idx=FAKE, val=FAKE):
+    c, keep = B.make_coo(len(dims), dims, nnz, idx, val)
+    coo.keep.append(keep)
+    return c
+
+
+coo.keep = []
+
+
+@pytest.mark.parametrize("case,status", [
+    ("dim_mismatch", B.ERR_DIM_MISMATCH),
+    ("repeated_mode", B.ERR_INVALID_ARG),
+    ("mode_out_of_range", B.ERR_INVALID_ARG),
+    ("order_too_big", B.ERR_INVALID_ARG),
+    ("zero_dim", B.ERR_INVALID_ARG),
+    ("negative_nnz", B.ERR_INVALID_ARG),
+    ("null_idx", B.ERR_INVALID_ARG),
+    ("null_tensor", B.ERR_INVALID_ARG),
+    ("too_many_pairs", B.ERR_INVALID_ARG),
+    ("output_key_overflow", B.ERR_KEY_OVERFLOW),
+    ("bad_load_factor", B.ERR_INVALID_ARG),
+    ("bad_table_slots", B.ERR_INVALID_ARG),
+])
+def test_plan_validation(case, status):
+    X, Y, cx, cy, opt = coo((8, 9, 10)), coo((10, 9, 7)), [2], [0], None
+    if case == "dim_mismatch":
+        cx, cy = [1], [0]
+    elif case == "repeated_mode":
+        cx, cy = [2, 2], [0, 1]
+    elif case == "mode_out_of_range":
+        cx, cy = [3], [0]
+    elif case == "order_too_big":
+        X = coo((2,) * 17)
+        cx, cy = [0], [1]
+        Y = coo((10, 2, 7))
+    elif case == "zero_dim":
+        X = coo((8, 0, 10))
+    elif case == "negative_nnz":
+        X = coo((8, 9, 10), nnz=-1)
+    elif case == "null_idx":
+        X = coo((8, 9, 10), idx=None)
+    elif case == "null_tensor":
+        X = None
+    elif case == "too_many_pairs":
+        cx, cy = [0, 1, 2, 0], [0, 1, 2, 1]
+    elif case == "output_key_overflow":
+        X = coo((1 << 30, 1 << 30, 10))
+        Y = coo((10, 1 << 20, 7))
+    elif case == "bad_load_factor":
+        opt = B.default_options()
+        opt.load_factor = 1.5
+    elif case == "bad_table_slots":
+        opt = B.default_options()
+        opt.out_table_slots = 100
+    st, h = _plan(X, Y, cx, cy, opt)
+    assert st == status, (st, B.last_error())
+    assert h is None  # *plan is reset to NULL on failure
+    assert B.last_error()
+
+
+def test_execute_and_free_reject_null_plan():
+    lib = B.load()
+    assert lib.sptc_execute(None, None, None, 0, None, None) == B.ERR_INVALID_ARG
+    lib.sptc_free(None)  # no-op
+    info = B.Info()
+    assert lib.sptc_plan_info(None, ctypes.byref(info)) == B.ERR_INVALID_ARG
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(B, "_lib", None)
+    monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        B.load()

@@ -1,0 +1,212 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Coordinates and nnz must match the oracle bit for bit after sorting; values
+must agree within helpers.value_tolerance (1e-12 relative, or the
+summation-reordering bound for sums that cancel; bit-exact for single-term
+outputs)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2410_10094_amd import workloads as W
+from paper_2410_10094_amd.workloads import Coo, Problem
+from tests import helpers as H
+from tests.gpu_common import assert_parity, log, run_gpu, to_device
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _problems():
+    ps = [
+        W.plain(),  # the plain order-3 workload at full size
+        W.plain(seed=11, n=32, nnz=3000),
+        W.block_sparse(n=24, block=4),
+        W.block_sparse(seed=5, n=16, block=4, p_block=0.5, p_fill=0.7),
+        W.imbalanced(nnz_x=200_000, nnz_y=20_000, xdims=(1 << 13, 1 << 10, 1 << 11),
+                     ydims=(1 << 11, 1 << 8, 1 << 6)),
+        W.paper_set(21, 12, 3000),
+        W.paper_set(22, 10, 2000, order_x=4, order_y=4),
+    ]
+    rng = np.random.default_rng(42)
+    for s in range(14):
+        ox, oy = int(rng.integers(1, 6)), int(rng.integers(1, 6))
+        nc = int(rng.integers(0, min(ox, oy, 3) + 1))
+        dup = s % 4 == 3
+        nx, ny = int(rng.integers(1, 6000)), int(rng.integers(1, 6000))
+        lo, hi = (2, 9) if nc == 0 else (3, 40)
+        ps.append(W.random_problem(7000 + s, ox, oy, nc, lo, hi, nx, ny, duplicates=dup))
+    return ps
+
+
+PROBLEMS = _problems()
+
+
+@pytest.mark.parametrize("p", PROBLEMS, ids=lambda p: p.name)
+def test_parity_against_oracle(p):
+    log(f"[parity] {p.name} nnz {p.X.nnz}x{p.Y.nnz} cx={p.cx} cy={p.cy}")
+    info, gidx, gval = run_gpu(p)
+    per_x, total = oracle.match_counts(p.X, p.Y, p.cx, p.cy)
+    assert info["products"] == total
+    ref = assert_parity(p, gidx, gval)
+    assert ref.nnz <= info["out_nnz_bound"]
+
+
+def test_stage_y_groups_and_grouped_array():
+    """Y grouping (counting sort by contracting key): group counts equal the
+    oracle's per-tuple counts; each group's run in the grouped array is a
+    permutation of Y's entries with that key."""
+    import paper_2410_10094_amd as sptc
+    for p in [W.block_sparse(n=24, block=4), W.random_problem(91, 4, 3, 2, 2, 9, 4000, 3000, duplicates=True),
+              W.plain()]:
+        log(f"[stage-A] {p.name}")
+        X, Y = to_device(p)
+        with sptc.plan(X, Y, p.cx, p.cy) as pl:
+            kc, counts, starts = (t.cpu().numpy() for t in pl.y_groups_table())
+            free, vals = (t.cpu().numpy() for t in pl.y_grouped())
+        tuples, ocounts = oracle.group_counts(p.Y, p.cy)
+        assert pl.y_groups == ocounts.shape[0]
+        gi, gc, gs = H.sort_coo(kc, counts, starts)
+        np.testing.assert_array_equal(gi, tuples)
+        np.testing.assert_array_equal(gc, ocounts)
+        # runs tile the grouped array exactly
+        order = np.argsort(gs)
+        assert gs[order][0] == 0 and np.all(gs[order][1:] == (gs[order] + gc[order])[:-1])
+        assert (gs + gc).max() == p.Y.nnz
+        fy = [m for m in range(p.Y.order) if m not in p.cy]
+        for g in range(0, gi.shape[1], max(1, gi.shape[1] // 50)):
+            sel = np.all(p.Y.idx[list(p.cy)] == gi[:, g:g + 1], axis=0)
+            want = sorted(zip(*[p.Y.idx[m, sel].tolist() for m in fy], p.Y.val[sel].tolist()))
+            run = slice(gs[g], gs[g] + gc[g])
+            got = sorted(zip(*[free[k, run].tolist() for k in range(len(fy))], vals[run].tolist()))
+            assert got == want
+
+
+def test_stage_x_probe_counts():
+    """Pass 1: per-X product counts equal the oracle's match counts exactly,
+    and P is their sum."""
+    import paper_2410_10094_amd as sptc
+    for p in [W.plain(), W.imbalanced(nnz_x=100_000, nnz_y=10_000, xdims=(1 << 12, 1 << 10, 1 << 10),
+                                      ydims=(1 << 10, 1 << 8, 1 << 6))]:
+        log(f"[stage-B] {p.name}")
+        X, Y = to_device(p)
+        with sptc.plan(X, Y, p.cx, p.cy) as pl:
+            counts = pl.x_counts().cpu().numpy()
+            P = pl.products
+        per_x, total = oracle.match_counts(p.X, p.Y, p.cx, p.cy)
+        np.testing.assert_array_equal(counts, per_x)
+        assert P == total
+
+
+def _edge_problems():
+    out = []
+    e = np.zeros((3, 0), np.int32)
+    some = W.random_problem(1, 3, 3, 1, 4, 4, 50, 50)
+    out.append(Problem("empty-x", Coo((4, 4, 4), e, np.zeros(0)), some.Y, (2,), (0,)))
+    out.append(Problem("empty-y", some.X, Coo((4, 4, 4), e, np.zeros(0)), (2,), (0,)))
+    out.append(Problem("empty-both", Coo((4, 4, 4), e, np.zeros(0)), Coo((4, 4, 4), e, np.zeros(0)), (2,), (0,)))
+    out.append(W.random_problem(2, 2, 3, 0, 2, 6, 40, 30))  # outer product
+    out.append(W.random_problem(3, 2, 2, 2, 3, 5, 20, 20))  # full contraction: order-0 output
+    out.append(W.random_problem(4, 1, 1, 1, 7, 7, 5, 6))    # order-1 dot product
+    out.append(W.random_problem(5, 3, 3, 1, 1, 1, 1, 1))    # all dims 1
+    # explicit zeros and exact cancellation still give structural entries
+    out.append(Problem("zeros", Coo((2, 3), np.array([[0, 0], [1, 2]], np.int32), np.array([0.0, 1.0])),
+                       Coo((3, 2), np.array([[1, 2], [1, 1]], np.int32), np.array([5.0, -5.0])), (1,), (0,)))
+    out.append(Problem("cancel", Coo((1, 2), np.array([[0, 0], [0, 1]], np.int32), np.array([1.0, 1.0])),
+                       Coo((2, 1), np.array([[0, 1], [0, 0]], np.int32), np.array([2.5, -2.5])), (1,), (0,)))
+    # a 63-bit output key (40 + 23 bits)
+    rng = np.random.default_rng(9)
+    X = Coo((1 << 20, 1 << 20, 8), np.stack([rng.integers(0, 1 << 20, 500), rng.integers(0, 1 << 20, 500),
+                                             rng.integers(0, 8, 500)]).astype(np.int32), W.nonzero_uniform(rng, 500))
+    Y = Coo((8, 1 << 23), np.stack([rng.integers(0, 8, 400), rng.integers(0, 1 << 23, 400)]).astype(np.int32),
+            W.nonzero_uniform(rng, 400))
+    out.append(Problem("key-63-bits", X, Y, (2,), (0,)))
+    # huge groups: every X entry expands thousands of products
+    out.append(W.random_problem(6, 3, 3, 1, 2, 2, 300, 20000))
+    # most X entries match nothing: one tile spans many X entries
+    rng = np.random.default_rng(10)
+    X = Coo((200, 5000), np.stack([rng.integers(0, 200, 120_000), rng.integers(0, 5000, 120_000)]).astype(np.int32),
+            W.nonzero_uniform(rng, 120_000))
+    Y = Coo((5000, 30), np.array([[7, 7, 4000], [1, 2, 3]], np.int32), np.array([1.0, -2.0, 0.5]))
+    out.append(Problem("sparse-matches", X, Y, (1,), (0,)))
+    # many duplicates of the same coordinates
+    out.append(Problem("duplicates", Coo((3, 3), np.array([[1] * 50 + [2] * 50, [0] * 100], np.int32),
+                                         W.nonzero_uniform(np.random.default_rng(1), 100)),
+                       Coo((3, 2), np.array([[0] * 30, [1] * 30], np.int32),
+                           W.nonzero_uniform(np.random.default_rng(2), 30)), (1,), (0,)))
+    return out
+
+
+@pytest.mark.parametrize("p", _edge_problems(), ids=lambda p: p.name)
+def test_edge_cases(p):
+    log(f"[edge] {p.name}")
+    info, gidx, gval = run_gpu(p)
+    assert_parity(p, gidx, gval)
+
+
+def test_operand_swap():
+    p = W.random_problem(123, 3, 4, 2, 3, 12, 5000, 4000)
+    log("[swap]")
+    _, ai, av = run_gpu(p)
+    q = Problem("swapped", p.Y, p.X, p.cy, p.cx)
+    _, bi, bv = run_gpu(q)
+    ref = oracle.contract(p.X, p.Y, p.cx, p.cy)
+    nfx, nfy = p.X.order - 2, p.Y.order - 2
+    perm = list(range(nfy, nfy + nfx)) + list(range(nfy))
+    assert_parity(p, ai, av, ref)
+    assert_parity(p, bi[perm], bv, ref)
+
+
+def test_repeated_execute_and_determinism():
+    import paper_2410_10094_amd as sptc
+    p = W.block_sparse(n=24, block=4)
+    log("[repeat]")
+    X, Y = to_device(p)
+    ref = oracle.contract(p.X, p.Y, p.cx, p.cy, nthreads=8)
+    with sptc.plan(X, Y, p.cx, p.cy) as pl:
+        for _ in range(4):
+            idx, val = pl.execute()
+            assert_parity(p, idx.cpu().numpy(), val.cpu().numpy(), ref)
+
+
+def test_torch_allocator_matches_pool():
+    p = W.plain(seed=77, n=40, nnz=4000)
+    log("[torch-allocator]")
+    _, ai, av = run_gpu(p, allocator="torch")
+    assert_parity(p, ai, av)
+
+
+def test_small_out_cap_reports_capacity_and_plan_recovers():
+    import paper_2410_10094_amd as sptc
+    p = W.plain(seed=5, n=16, nnz=400)
+    log("[out-cap]")
+    X, Y = to_device(p)
+    with sptc.plan(X, Y, p.cx, p.cy) as pl:
+        with pytest.raises(sptc.SptcError) as e:
+            pl.execute(out_cap=10)
+        assert e.value.status == 5
+        idx, val = pl.execute()
+        assert_parity(p, idx.cpu().numpy(), val.cpu().numpy())
+
+
+def test_undersized_output_table_reports_capacity():
+    import paper_2410_10094_amd as sptc
+    p = W.plain(seed=6, n=16, nnz=400)
+    log("[tiny-table]")
+    X, Y = to_device(p)
+    opt = sptc.default_options(out_table_slots=64)
+    with sptc.plan(X, Y, p.cx, p.cy, options=opt) as pl:
+        with pytest.raises(sptc.SptcError) as e:
+            pl.execute()
+        assert e.value.status == 5
+
+
+def test_out_of_range_coordinate_is_rejected():
+    import paper_2410_10094_amd as sptc
+    p = W.plain(seed=7, n=16, nnz=100)
+    p.X.idx[0, 17] = 16  # one past the end of mode 0
+    log("[validate]")
+    X, Y = to_device(p)
+    with pytest.raises(sptc.SptcError) as e:
+        sptc.plan(X, Y, p.cx, p.cy)
+    assert e.value.status == 1
