@@ -117,10 +117,11 @@ def run_workload(name, steps, warmup, with_events=True):
 
     nst = len(B.STAGES)
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2 * nst)] for _ in range(steps)]
-    ev_arrays = [(ctypes.c_void_p * (2 * nst))(*[e.cuda_event for e in row]) for row in evs]
     for row in evs:
         for e in row:
-            e.record(stream)  # materialise the underlying hipEvent_t
+            e.record(stream)  # torch creates the hipEvent_t lazily, at the first record
+    ev_arrays = [(ctypes.c_void_p * (2 * nst))(*[e.cuda_event for e in row]) for row in evs]
+    assert all(e.cuda_event for row in evs for e in row)
 
     def step(k=None):
         opt = sptc.default_options()
