@@ -35,13 +35,33 @@ DESCRIPTIONS = {
 }
 
 
-def algorithmic_bytes(stage, p, products, nnz_z):
-    """Bytes a stage must move through HBM at minimum (each datum once; the
-    output hash read-modify-written once per product), per launch."""
+def algorithmic_bytes(stage, p, products, nnz_z, x_groups=0, mode="grouped", info=None):
+    """Bytes a stage must move through HBM at minimum (each datum once; on the
+    global-hash path the output hash is read-modify-written once per
+    product), per launch."""
     nx, ny = p.X.nnz, p.Y.nnz
     ox, oy = p.X.order, p.Y.order
     nz_order = ox + oy - 2 * len(p.cx)
     nc = len(p.cx)
+    info = info or {}
+    if stage == "direct":
+        # per direct group: group record 16 B, its X record 16 B, list id 4 B and
+        # offset 8 B; grouped-Y entries read once; one COO entry per product
+        nd, pd = info.get("direct_groups", 0), info.get("direct_products", 0)
+        return nd * (16 + 16 + 4 + 8) + 16 * ny + pd * (4 * nz_order + 8)
+    if stage == "block":
+        # grouped X records and grouped-Y entries read once, COO written once
+        return 16 * nx + 16 * ny + nnz_z * (4 * nz_order + 8)
+    if stage == "group_count":
+        # grouped X records (16 B) and the needed grouped-Y entries (16 B) read once;
+        # group records (16 B) and product offsets (2 x 8 B) read, one count (4 B) written per group
+        return 16 * nx + 16 * ny + x_groups * (16 + 16 + 4)
+    if stage == "group_fill":
+        # as the count pass, plus the output offsets (8 B per group) and the COO written once
+        return 16 * nx + 16 * ny + x_groups * (16 + 16 + 8 + 4) + nnz_z * (4 * nz_order + 8)
+    if stage == "x_probe" and mode == "grouped":
+        # X COO read once, grouped X records (16 B) written once
+        return nx * (4 * ox + 8) + 16 * nx
     if stage == "expand":
         # per product: output-hash key read 8 B + value read 8 B + value write 8 B;
         # X records (poff 8 B, group start 4 B, packed free key + value 16 B) and
@@ -95,7 +115,7 @@ def time_oracle(p, products_total, max_seconds=25.0):
             "output_nnz_per_s": r.nnz / dt}
 
 
-def run_workload(name, steps, warmup, with_events=True):
+def run_workload(name, steps, warmup, with_events=True, mode="grouped"):
     import torch
 
     import paper_2410_10094_amd as sptc
@@ -107,13 +127,16 @@ def run_workload(name, steps, warmup, with_events=True):
     Y = sptc.DeviceCoo.from_host(p.Y)
     stream = torch.cuda.current_stream()
 
+    mode_id = {"grouped": B.MODE_GROUPED, "global": B.MODE_GLOBAL}[mode]
     # Output buffers are sized once (the bound is the same every step).
-    with sptc.plan(X, Y, p.cx, p.cy) as pl0:
+    with sptc.plan(X, Y, p.cx, p.cy, options=sptc.default_options(mode=mode_id)) as pl0:
         out_idx, out_val, out_nnz, cap = pl0.allocate_outputs()
         products = pl0.products
         out_slots = pl0.out_table_slots
-        info = dict(y_groups=pl0.y_groups, y_table_slots=pl0.y_table_slots, out_table_slots=out_slots,
-                    workspace_bytes=pl0.workspace_bytes, key_bits=pl0.key_bits)
+        info = dict(mode=mode, y_groups=pl0.y_groups, y_table_slots=pl0.y_table_slots, out_table_slots=out_slots,
+                    workspace_bytes=pl0.workspace_bytes, key_bits=pl0.key_bits, x_groups=pl0.x_groups,
+                    group_classes=pl0.group_classes, direct_groups=pl0.group_classes["direct"],
+                    direct_products=pl0.direct_products)
 
     nst = len(B.STAGES)
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2 * nst)] for _ in range(steps)]
@@ -124,7 +147,7 @@ def run_workload(name, steps, warmup, with_events=True):
     assert all(e.cuda_event for row in evs for e in row)
 
     def step(k=None):
-        opt = sptc.default_options()
+        opt = sptc.default_options(mode=mode_id)
         if k is not None and with_events:
             opt.stage_events = ctypes.cast(ev_arrays[k], ctypes.POINTER(ctypes.c_void_p))
         pl = sptc.plan(X, Y, p.cx, p.cy, options=opt)
@@ -146,14 +169,14 @@ def run_workload(name, steps, warmup, with_events=True):
     stage_ms = {}
     for s, sname in enumerate(B.STAGES):
         stage_ms[sname] = sum(evs[k][2 * s].elapsed_time(evs[k][2 * s + 1]) for k in range(steps)) / steps
-    return dict(problem=p, products=products, nnz_z=nnz_z, sec=sec, stage_ms=stage_ms, info=info)
+    return dict(problem=p, products=products, nnz_z=nnz_z, sec=sec, stage_ms=stage_ms, info=info, mode=mode)
 
 
 def roofline_of(r):
     p = r["problem"]
     stage = max(r["stage_ms"], key=lambda s: r["stage_ms"][s])
     ms = r["stage_ms"][stage]
-    bytes_alg = algorithmic_bytes(stage, p, r["products"], r["nnz_z"])
+    bytes_alg = algorithmic_bytes(stage, p, r["products"], r["nnz_z"], r["info"]["x_groups"], r["mode"], r["info"])
     achieved = bytes_alg / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
     return {"kernel": stage, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "ms_per_launch": round(ms, 4),
@@ -176,6 +199,8 @@ def main():
     ap.add_argument("--also", default="plain,imbalanced,block-sparse-1.5M",
                     help="comma-separated extra workloads reported under 'also' ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", default="grouped", choices=["grouped", "global"],
+                    help="accumulation strategy: per-X-group LDS tables (default) or one global hash")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -187,11 +212,11 @@ def main():
     import torch
     torch.cuda.set_device(0)
 
-    r = run_workload(args.workload, args.steps, args.warmup)
+    r = run_workload(args.workload, args.steps, args.warmup, mode=args.mode)
     p = r["problem"]
     also = []
     for name in [a for a in args.also.split(",") if a and a != args.workload]:
-        also.append(summary(name, run_workload(name, max(3, args.steps // 2), max(1, args.warmup))))
+        also.append(summary(name, run_workload(name, max(3, args.steps // 2), max(1, args.warmup), mode=args.mode)))
 
     cpu = None
     if not args.no_cpu_baseline:

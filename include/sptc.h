@@ -111,8 +111,22 @@ typedef enum sptc_stage {
   SPTC_STAGE_OUT_CLEAR = 5,  /* output hash: mark every slot empty */
   SPTC_STAGE_EXPAND = 6,     /* expand products, accumulate in the output hash */
   SPTC_STAGE_COMPACT = 7,    /* output hash -> COO: count, prefix sum, fill */
-  SPTC_NUM_STAGES = 8
+  SPTC_STAGE_GROUP_COUNT = 8, /* grouped path, small groups: accumulate in LDS, count outputs */
+  SPTC_STAGE_GROUP_FILL = 9,  /* grouped path, small groups: prefix sum of the counts, accumulate again, write */
+  SPTC_STAGE_DIRECT = 10,     /* grouped path, single-entry groups: write every product as an output */
+  SPTC_STAGE_BLOCK = 11,      /* grouped path, large groups: accumulate in LDS, reserve and write */
+  SPTC_NUM_STAGES = 12
 } sptc_stage;
+
+/* Accumulation strategy.
+ * GROUPED (default): X is grouped by its free key too (section 4.1) and each
+ *   group's products are accumulated in an LDS table of its own sized from
+ *   the group's bound (section 4.3); only groups too large for LDS use the
+ *   output hash in device memory.  Plan stage X_PROBE then covers grouping X,
+ *   P_SCAN the product prefix sum and the classing of groups by size.
+ * GLOBAL: X stays ungrouped and every product goes to one output hash in
+ *   device memory (the footnote to section 4.4). */
+typedef enum sptc_mode { SPTC_MODE_GROUPED = 0, SPTC_MODE_GLOBAL = 1 } sptc_mode;
 
 typedef struct sptc_options {
   double load_factor;        /* hash fill target in (0, 0.95]; default 1/1.3 (section 2.3.1) */
@@ -123,6 +137,7 @@ typedef struct sptc_options {
   void** stage_events;       /* NULL, or 2*SPTC_NUM_STAGES hipEvent_t: entry 2s is recorded on the
                                 stream before stage s and entry 2s+1 after it (NULL entries skipped);
                                 the caller owns the events and keeps the array alive */
+  int32_t mode;              /* sptc_mode; default SPTC_MODE_GROUPED */
 } sptc_options;
 
 /* Sizes fixed by sptc_plan. */
@@ -136,6 +151,11 @@ typedef struct sptc_info {
   int64_t out_table_slots;                 /* capacity of the output hash */
   int64_t workspace_bytes;                 /* device memory the plan holds */
   int32_t key_bits_contract, key_bits_x_free, key_bits_y_free;
+  int32_t mode;                            /* sptc_mode the plan runs */
+  int64_t x_groups;                        /* grouped mode: distinct X free keys */
+  int64_t wave_groups, block_groups, global_groups;  /* grouped mode: groups per accumulation class */
+  int64_t direct_groups;                   /* grouped mode: single-entry groups written directly */
+  int64_t direct_products;                 /* their products (= their outputs) */
 } sptc_info;
 
 typedef struct sptc_plan_s* sptc_plan_t;
@@ -197,9 +217,18 @@ SPTC_API sptc_status sptc_plan_y_groups(sptc_plan_t plan, int32_t* key_coords, i
  * value (device double [nnz_Y]).  Enqueued on `stream`. */
 SPTC_API sptc_status sptc_plan_y_grouped(sptc_plan_t plan, int32_t* free_coords, double* vals, void* stream);
 
-/* Per X nonzero, the number of Y nonzeros sharing its contracting key
- * (device int64 [nnz_X]).  Enqueued on `stream`. */
+/* Global mode only: per X nonzero, the number of Y nonzeros sharing its
+ * contracting key (device int64 [nnz_X]).  Enqueued on `stream`. */
 SPTC_API sptc_status sptc_plan_x_counts(sptc_plan_t plan, int64_t* counts, void* stream);
+
+/* Grouped mode only: the X groups (section 4.1): per group its X free
+ * coordinates (device int32 [order_X - ncontract][cap], ascending X mode
+ * order), its number of X entries and its number of products, the group's
+ * bound of section 4.3 (device int64 [cap] each).  *ngroups (host) receives
+ * the group count; when it exceeds cap nothing is written and
+ * SPTC_ERR_CAPACITY is returned.  Enqueued on `stream`. */
+SPTC_API sptc_status sptc_plan_x_groups(sptc_plan_t plan, int32_t* free_coords, int64_t* counts, int64_t* products,
+                                        int64_t cap, int64_t* ngroups, void* stream);
 
 #ifdef __cplusplus
 }

@@ -142,6 +142,11 @@ class Plan:
         self.out_table_slots = info.out_table_slots
         self.workspace_bytes = info.workspace_bytes
         self.key_bits = (info.key_bits_contract, info.key_bits_x_free, info.key_bits_y_free)
+        self.mode = info.mode
+        self.x_groups = info.x_groups
+        self.group_classes = dict(direct=info.direct_groups, wave=info.wave_groups, block=info.block_groups,
+                                  global_=info.global_groups)
+        self.direct_products = info.direct_products
 
     def close(self):
         if getattr(self, "_h", None):
@@ -214,6 +219,21 @@ class Plan:
         _b.check(_b.load().sptc_plan_y_grouped(self._h, coords.data_ptr() if nfy else None, vals.data_ptr(),
                                                _stream_handle(None)))
         return coords[:, : self.Y.nnz], vals[: self.Y.nnz]
+
+    def x_groups_table(self):
+        """Grouped mode: (X free coordinates int32 [nfree_X, g], entry counts
+        int64 [g], product counts int64 [g]) of X's free-key groups."""
+        torch = _torch()
+        dev = self.X.val.device
+        g = self.x_groups
+        nfx = self.X.order - len(self.cx)
+        coords = torch.empty((nfx, max(g, 1)), dtype=torch.int32, device=dev)
+        counts = torch.empty(max(g, 1), dtype=torch.int64, device=dev)
+        prods = torch.empty(max(g, 1), dtype=torch.int64, device=dev)
+        ng = ctypes.c_int64()
+        _b.check(_b.load().sptc_plan_x_groups(self._h, coords.data_ptr() if nfx else None, counts.data_ptr(),
+                                              prods.data_ptr(), max(g, 1), ctypes.byref(ng), _stream_handle(None)))
+        return coords[:, :g], counts[:g], prods[:g]
 
     def x_counts(self):
         torch = _torch()

@@ -20,10 +20,13 @@ OK, ERR_INVALID_ARG, ERR_DIM_MISMATCH, ERR_KEY_OVERFLOW, ERR_OUT_OF_MEMORY, ERR_
 EXPORTS = (
     "sptc_default_options", "sptc_plan", "sptc_plan_info", "sptc_execute", "sptc_plan_status", "sptc_free",
     "sptc_status_string", "sptc_last_error", "sptc_plan_y_groups", "sptc_plan_y_grouped", "sptc_plan_x_counts",
-    "sptc_plan_set_stage_events",
+    "sptc_plan_set_stage_events", "sptc_plan_x_groups",
 )
 
-STAGES = ("y_count", "y_scan", "y_scatter", "x_probe", "p_scan", "out_clear", "expand", "compact")
+MODE_GROUPED, MODE_GLOBAL = 0, 1
+
+STAGES = ("y_count", "y_scan", "y_scatter", "x_probe", "p_scan", "out_clear", "expand", "compact", "group_count",
+          "group_fill", "direct", "block")
 
 
 class Coo(ctypes.Structure):
@@ -34,7 +37,7 @@ class Coo(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("load_factor", ctypes.c_double), ("validate", ctypes.c_int32), ("max_probe", ctypes.c_int32),
                 ("hash_seed", ctypes.c_uint64), ("out_table_slots", ctypes.c_int64),
-                ("stage_events", ctypes.POINTER(ctypes.c_void_p))]
+                ("stage_events", ctypes.POINTER(ctypes.c_void_p)), ("mode", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -42,7 +45,10 @@ class Info(ctypes.Structure):
                 ("products", ctypes.c_int64), ("out_nnz_bound", ctypes.c_int64), ("y_groups", ctypes.c_int64),
                 ("y_table_slots", ctypes.c_int64), ("out_table_slots", ctypes.c_int64),
                 ("workspace_bytes", ctypes.c_int64), ("key_bits_contract", ctypes.c_int32),
-                ("key_bits_x_free", ctypes.c_int32), ("key_bits_y_free", ctypes.c_int32)]
+                ("key_bits_x_free", ctypes.c_int32), ("key_bits_y_free", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("x_groups", ctypes.c_int64), ("wave_groups", ctypes.c_int64), ("block_groups", ctypes.c_int64),
+                ("global_groups", ctypes.c_int64), ("direct_groups", ctypes.c_int64),
+                ("direct_products", ctypes.c_int64)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
@@ -97,6 +103,8 @@ def load():
     lib.sptc_plan_x_counts.restype = st
     lib.sptc_plan_set_stage_events.argtypes = [P, ctypes.POINTER(ctypes.c_void_p)]
     lib.sptc_plan_set_stage_events.restype = st
+    lib.sptc_plan_x_groups.argtypes = [P, P, P, P, i64, ctypes.POINTER(i64), P]
+    lib.sptc_plan_x_groups.restype = st
     _lib = lib
     return lib
 

@@ -1,0 +1,718 @@
+// X-grouped path: X is grouped by its free key (paper section 4.1: hash each
+// free key to a small id, then counting sort), and each group's products are
+// accumulated in a table of its own, sized from the group's bound (section
+// 4.3: the sum of the Y counts over the group's X entries).  Groups never
+// share an output coordinate (the output key embeds the X free key), so no
+// accumulation crosses groups.
+//
+// Groups are sorted into four classes; d = min(products, Y free cells) is the
+// most distinct outputs a group can have:
+//   direct  one X entry and no repeated coordinate in Y: every product is its
+//           own output, written straight from a product-space gather;
+//   wave    d <= kWaveCap and few products: one wave, a private LDS hash;
+//           outputs found by a count pass, a prefix sum and a fill pass;
+//   block   dense Y free key (<= kDenseBits bits) or d <= kBlockCap: one
+//           1024-thread workgroup, a dense LDS accumulator or an LDS hash; a
+//           single pass that reserves the group's outputs with one atomic;
+//   global  everything else: the products go to the device-memory hash.
+#include <hip/hip_runtime.h>
+
+#include "../../include/sptc.h"
+#include "prim.hpp"
+#include "sptc_internal.hpp"
+
+namespace sptc {
+namespace {
+
+constexpr int kGBlock = 256;
+constexpr int kGWaves = kGBlock / 64;
+constexpr int kBBlock = 1024;                           // block-class workgroup
+constexpr int kBChunk = 1024;                           // X entries staged per chunk (product-parallel walk)
+constexpr unsigned long long kWaveMaxProducts = 16384;  // beyond this a group goes to a workgroup
+
+// ---------------------------------------------------------------------------
+// Plan: group X by free key
+// ---------------------------------------------------------------------------
+
+// X table -> dense group records, in table order (so group runs are in
+// increasing storage order).  Scans count << 32 | occupied in one pass.
+struct XTableScanOp {
+  YSlot* tab;
+  GroupRec* groups;
+  __device__ unsigned long long get(int64_t i) const {
+    const YSlot s = tab[i];
+    return s.key != kEmpty ? (((unsigned long long)s.count << 32) | 1ull) : 0ull;
+  }
+  __device__ void put(int64_t i, unsigned long long excl, unsigned long long v) const {
+    if (!v) return;
+    const unsigned count = (unsigned)(v >> 32);
+    GroupRec g;
+    g.phi = tab[i].key;
+    g.start = (unsigned)(excl >> 32);
+    g.count = count;
+    groups[(unsigned)(excl & 0xffffffffull)] = g;
+    tab[i].start = g.start + count;  // end of the run: the scatter takes and decrements
+  }
+};
+
+struct FinXGroups {
+  DevStatus* st;
+  __device__ void operator()(unsigned long long total) const { st->xgroups = total & 0xffffffffull; }
+};
+
+// Places every X entry in its group's run and records its Y group.
+__global__ __launch_bounds__(256) void k_x_scatter(const int32_t* __restrict__ xidx, const double* __restrict__ xval,
+                                                   int64_t nnz, KeyPack kf, KeyPack kc, Bounds b,
+                                                   YSlot* __restrict__ xtab, uint64_t xmask, int32_t max_probe_x,
+                                                   const YSlot* __restrict__ ytab, uint64_t ymask,
+                                                   int32_t max_probe_y, uint64_t seed, XRec* __restrict__ xr,
+                                                   DevStatus* st) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
+    if (b.check && !coords_ok(xidx, nnz, e, b)) record_error(st, kErrCoord);
+    const uint64_t fkey = pack_key(xidx, nnz, e, kf);
+    const int64_t s = find_slot(xtab, fkey, xmask, seed, max_probe_x);
+    if (s < 0) {
+      record_error(st, kErrInternal);
+      continue;
+    }
+    const unsigned pos = atomicSub(&xtab[s].start, 1u) - 1u;
+    if ((int64_t)pos >= nnz) {
+      record_error(st, kErrInternal);
+      continue;
+    }
+    const uint64_t ckey = pack_key(xidx, nnz, e, kc);
+    uint64_t ys = fmix64(ckey ^ seed) & ymask;
+    unsigned start = 0, count = 0;
+    for (int32_t probe = 0; probe < max_probe_y; ++probe) {
+      const YSlot slot = ytab[ys];
+      if (slot.key == ckey) {
+        start = slot.start;
+        count = slot.count;
+        break;
+      }
+      if (slot.key == kEmpty) break;
+      ys = (ys + 1) & ymask;
+    }
+    XRec r;
+    r.ystart = start;
+    r.ycnt = count;
+    r.v = xval[e];
+    xr[pos] = r;
+  }
+}
+
+struct EntryScanOp {
+  const XRec* xr;
+  unsigned long long* eoff;
+  __device__ unsigned long long get(int64_t i) const { return xr[i].ycnt; }
+  __device__ void put(int64_t i, unsigned long long excl, unsigned long long) const { eoff[i] = excl; }
+};
+
+struct FinEntries {
+  unsigned long long* eoff_end;
+  DevStatus* st;
+  __device__ void operator()(unsigned long long total) const {
+    *eoff_end = total;
+    st->products = total;
+  }
+};
+
+// Class codes (U128): direct {1, 0}, wave {1 << 32, 0}, block {0, 1},
+// global {0, 0}.
+struct ClassifyOp {
+  const GroupRec* groups;
+  const unsigned long long* eoff;
+  const DevStatus* st;
+  uint64_t ycells;
+  int32_t dense;
+  uint32_t* dlist;
+  uint32_t* wlist;
+  uint32_t* blist;
+  uint32_t* glist;
+  __device__ U128 code(int64_t g) const {
+    const GroupRec G = groups[g];
+    const unsigned long long b = eoff[G.start + G.count] - eoff[G.start];
+    const unsigned long long d = b < ycells ? b : ycells;
+    if (G.count == 1 && !st->ydup) return U128{1ull, 0ull};
+    if (d <= (unsigned long long)kWaveCap && b <= kWaveMaxProducts) return U128{1ull << 32, 0ull};
+    if (dense || d <= (unsigned long long)kBlockCap) return U128{0ull, 1ull};
+    return U128{0ull, 0ull};
+  }
+  __device__ U128 get(int64_t g) const { return (unsigned long long)g < st->xgroups ? code(g) : U128{0ull, 0ull}; }
+  __device__ void put(int64_t g, U128 excl, U128 v) const {
+    if ((unsigned long long)g >= st->xgroups) return;
+    const unsigned long long nd = excl.lo & 0xffffffffull, nw = excl.lo >> 32, nb = excl.hi;
+    if (v.lo == 1ull)
+      dlist[nd] = (uint32_t)g;
+    else if (v.lo)
+      wlist[nw] = (uint32_t)g;
+    else if (v.hi)
+      blist[nb] = (uint32_t)g;
+    else
+      glist[(unsigned long long)g - nd - nw - nb] = (uint32_t)g;
+  }
+};
+
+struct FinClassify {
+  DevStatus* st;
+  __device__ void operator()(U128 total) const {
+    st->class_lo = total.lo;
+    st->class_hi = total.hi;
+  }
+};
+
+struct DirectScanOp {
+  const GroupRec* groups;
+  const uint32_t* dlist;
+  const unsigned long long* eoff;
+  unsigned long long* dpos;
+  const DevStatus* st;
+  __device__ bool valid(int64_t i) const { return (unsigned long long)i < (st->class_lo & 0xffffffffull); }
+  __device__ unsigned long long get(int64_t i) const {
+    if (!valid(i)) return 0ull;
+    const GroupRec G = groups[dlist[i]];
+    return eoff[G.start + G.count] - eoff[G.start];
+  }
+  __device__ void put(int64_t i, unsigned long long excl, unsigned long long) const {
+    if (valid(i)) dpos[i] = excl;
+  }
+};
+
+struct FinDirect {
+  unsigned long long* dpos;
+  DevStatus* st;
+  __device__ void operator()(unsigned long long total) const {
+    dpos[st->class_lo & 0xffffffffull] = total;
+    st->direct_products = total;
+  }
+};
+
+struct GlobalEntryScanOp {
+  const GroupRec* groups;
+  const uint32_t* glist;
+  unsigned long long* gl_eoff;
+  __device__ unsigned long long get(int64_t i) const { return groups[glist[i]].count; }
+  __device__ void put(int64_t i, unsigned long long excl, unsigned long long) const { gl_eoff[i] = excl; }
+};
+
+struct FinGlobalEntries {
+  DevStatus* st;
+  __device__ void operator()(unsigned long long total) const { st->global_entries = total; }
+};
+
+__global__ __launch_bounds__(256) void k_gather_global(const GroupRec* __restrict__ groups,
+                                                       const uint32_t* __restrict__ glist, int64_t ngl,
+                                                       const unsigned long long* __restrict__ gl_eoff,
+                                                       const XRec* __restrict__ xr, XEntry* __restrict__ xrec,
+                                                       uint32_t* __restrict__ xg, uint32_t* __restrict__ xcnt) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < ngl; i += nwaves) {
+    const GroupRec G = groups[glist[i]];
+    const unsigned long long base = gl_eoff[i];
+    for (unsigned e = lane; e < G.count; e += 64) {
+      const XRec r = xr[G.start + e];
+      XEntry x;
+      x.phi = G.phi;
+      x.v = r.v;
+      xrec[base + e] = x;
+      xg[base + e] = r.ystart;
+      xcnt[base + e] = r.ycnt;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Execute: per-group accumulation in LDS
+// ---------------------------------------------------------------------------
+
+// Power-of-two table size holding d keys at load <= 0.7; at least 64 slots.
+__device__ __forceinline__ unsigned table_size_for(unsigned long long d, unsigned max_slots) {
+  const unsigned long long need = (d * 10 + 6) / 7;
+  unsigned t = 64;
+  while (t < need && t < max_slots) t <<= 1;
+  return t;
+}
+
+// Adds v at key in an LDS hash table (linear probing, 64-bit CAS).
+__device__ __forceinline__ bool lds_accumulate(ZSlot* tab, unsigned tmask, unsigned long long key, double v,
+                                               uint64_t seed) {
+  unsigned s = (unsigned)fmix64(key ^ seed) & tmask;
+  for (unsigned probe = 0; probe <= tmask; ++probe) {
+    const unsigned long long prev = atomicCAS(&tab[s].key, (unsigned long long)kEmpty, key);
+    if (prev == kEmpty || prev == key) {
+      atomicAdd(&tab[s].val, v);
+      return true;
+    }
+    s = (s + 1) & tmask;
+  }
+  return false;
+}
+
+__device__ __forceinline__ void write_output(const GroupArgs& a, unsigned long long pos, unsigned long long phix,
+                                             unsigned long long phiy, double v) {
+#pragma unroll
+  for (int m = 0; m < kMaxOrder; ++m)
+    if (m < a.ux.n) a.out_idx[(int64_t)m * a.out_cap + (int64_t)pos] = (int32_t)((phix >> a.ux.shift[m]) & a.ux.mask[m]);
+#pragma unroll
+  for (int m = 0; m < kMaxOrder; ++m)
+    if (m < a.uy.n)
+      a.out_idx[(int64_t)(a.ux.n + m) * a.out_cap + (int64_t)pos] = (int32_t)((phiy >> a.uy.shift[m]) & a.uy.mask[m]);
+  a.out_val[pos] = v;
+}
+
+struct WaveScratch {
+  unsigned long long off[64];
+  unsigned ys[64];
+  double v[64];
+};
+
+// One wave per group; each wave owns kWaveSlots LDS slots.
+template <bool FILL>
+__global__ __launch_bounds__(kGBlock) void k_group_wave(GroupArgs a, const uint32_t* __restrict__ wlist, int64_t nw) {
+  __shared__ ZSlot s_tab[kGWaves][kWaveSlots];
+  __shared__ WaveScratch s_sc[kGWaves];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  ZSlot* tab = s_tab[w];
+  WaveScratch& sc = s_sc[w];
+  for (int64_t i = (int64_t)blockIdx.x * kGWaves + w; i < nw; i += (int64_t)gridDim.x * kGWaves) {
+    const uint32_t g = wlist[i];
+    const GroupRec G = a.groups[g];
+    const unsigned long long p0 = a.eoff[G.start];
+    const unsigned long long b = a.eoff[G.start + G.count] - p0;
+    const unsigned long long d = b < a.ycells ? b : a.ycells;
+    const unsigned tsize = table_size_for(d, kWaveSlots);
+    const unsigned tmask = tsize - 1;
+    for (unsigned s = lane; s < tsize; s += 64) {
+      tab[s].key = kEmpty;
+      tab[s].val = 0.0;
+    }
+    wave_lds_fence();
+    for (unsigned base = 0; base < G.count; base += 64) {
+      const unsigned e = base + lane;
+      unsigned long long c = 0;
+      unsigned ys = 0;
+      double v = 0.0;
+      if (e < G.count) {
+        const XRec r = a.xr[G.start + e];
+        c = r.ycnt;
+        ys = r.ystart;
+        v = r.v;
+      }
+      const unsigned long long incl = wave_incl_scan(c);
+      const unsigned long long tot = __shfl(incl, 63, 64);
+      sc.off[lane] = incl - c;
+      sc.ys[lane] = ys;
+      sc.v[lane] = v;
+      wave_lds_fence();
+      for (unsigned long long q = lane; q < tot; q += 64) {
+        int lo = 0, hi = 63;  // the last entry whose run starts at or before q
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (sc.off[mid] <= q)
+            lo = mid;
+          else
+            hi = mid - 1;
+        }
+        const unsigned long long y = (unsigned long long)sc.ys[lo] + (q - sc.off[lo]);
+        if (y >= (unsigned long long)a.ny) {
+          record_error(a.st, kErrInternal);
+          continue;
+        }
+        const YEntry ye = a.yg[y];
+        if (!lds_accumulate(tab, tmask, ye.phi, __dmul_rn(sc.v[lo], ye.v), a.seed)) record_error(a.st, kErrCapacity);
+      }
+      wave_lds_fence();
+    }
+    if (!FILL) {
+      unsigned n = 0;
+      for (unsigned s = lane; s < tsize; s += 64) n += tab[s].key != kEmpty ? 1u : 0u;
+      n = (unsigned)wave_sum((unsigned long long)n);
+      if (lane == 0) a.gn[g] = n;
+    } else {
+      const unsigned long long base = a.goff[g];
+      unsigned long long run = 0;
+      for (unsigned s0 = 0; s0 < tsize; s0 += 64) {
+        const ZSlot z = tab[s0 + lane];
+        const bool occ = z.key != kEmpty;
+        const unsigned long long m = __ballot(occ);
+        if (occ) {
+          const unsigned long long pos = base + run + (unsigned long long)__popcll(m & lanemask_lt());
+          if ((int64_t)pos < a.out_cap) write_output(a, pos, G.phi, z.key, z.val);
+        }
+        run += (unsigned long long)__popcll(m);
+      }
+    }
+    wave_lds_fence();
+  }
+}
+
+// Block class: one 1024-thread workgroup per group, accumulating in a dense
+// LDS array indexed by the Y free key (with a presence flag per cell) or in an
+// LDS hash of up to kBlockSlots slots.  When the group's X entries average
+// many products, each wave walks whole Y runs (coalesced, no search);
+// otherwise the products are spread over all threads by a search over the
+// staged entry offsets.  Then the group's outputs are counted, reserved with
+// one atomic on the output cursor, and written.
+template <bool DENSE>
+__global__ __launch_bounds__(kBBlock) void k_group_block(GroupArgs a, const uint32_t* __restrict__ blist, int64_t nb,
+                                                         unsigned dense_cells) {
+  extern __shared__ __align__(16) unsigned char s_dyn[];
+  __shared__ unsigned long long s_off[kBChunk];
+  __shared__ unsigned s_ys[kBChunk];
+  __shared__ double s_v[kBChunk];
+  __shared__ unsigned long long s_wave[kBBlock / 64 + 1];
+  __shared__ unsigned long long s_base;
+  double* acc = reinterpret_cast<double*>(s_dyn);
+  unsigned char* flag = s_dyn + (size_t)dense_cells * 8;
+  ZSlot* tab = reinterpret_cast<ZSlot*>(s_dyn);
+  const unsigned tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr unsigned kWaves = kBBlock / 64;
+
+  for (int64_t i = blockIdx.x; i < nb; i += gridDim.x) {
+    const uint32_t g = blist[i];
+    const GroupRec G = a.groups[g];
+    const unsigned long long b = a.eoff[G.start + G.count] - a.eoff[G.start];
+    const unsigned long long d = b < a.ycells ? b : a.ycells;
+    const unsigned tsize = DENSE ? dense_cells : (table_size_for(d, kBlockSlots) < (unsigned)kBBlock
+                                                      ? (unsigned)kBBlock
+                                                      : table_size_for(d, kBlockSlots));
+    const unsigned tmask = tsize - 1;
+    for (unsigned s = tid; s < tsize; s += kBBlock) {
+      if (DENSE) {
+        acc[s] = 0.0;
+        flag[s] = 0;
+      } else {
+        tab[s].key = kEmpty;
+        tab[s].val = 0.0;
+      }
+    }
+    __syncthreads();
+
+    auto accumulate = [&](unsigned long long key, double pv) {
+      if (DENSE) {
+        const unsigned cell = (unsigned)key & tmask;
+        atomicAdd(&acc[cell], pv);
+        flag[cell] = 1;
+      } else if (!lds_accumulate(tab, tmask, key, pv, a.seed)) {
+        record_error(a.st, kErrCapacity);
+      }
+    };
+
+    if (b >= 32ull * G.count) {
+      // entry-parallel: a wave per X entry, lanes over its Y run
+      for (unsigned e = wave; e < G.count; e += kWaves) {
+        const XRec r = a.xr[G.start + e];
+        if ((unsigned long long)r.ystart + r.ycnt > (unsigned long long)a.ny) {
+          record_error(a.st, kErrInternal);
+          continue;
+        }
+        for (unsigned j = lane; j < r.ycnt; j += 64) {
+          const YEntry ye = a.yg[r.ystart + j];
+          accumulate(ye.phi, __dmul_rn(r.v, ye.v));
+        }
+      }
+    } else {
+      // product-parallel over chunks of kBChunk entries
+      for (unsigned base = 0; base < G.count; base += kBChunk) {
+        const unsigned e = base + tid;
+        unsigned long long c = 0;
+        unsigned ys = 0;
+        double v = 0.0;
+        if (e < G.count) {
+          const XRec r = a.xr[G.start + e];
+          c = r.ycnt;
+          ys = r.ystart;
+          v = r.v;
+        }
+        unsigned long long tot;
+        const unsigned long long excl = block_excl_scan<kBBlock>(c, s_wave, &tot);
+        s_off[tid] = excl;
+        s_ys[tid] = ys;
+        s_v[tid] = v;
+        __syncthreads();
+        for (unsigned long long q = tid; q < tot; q += kBBlock) {
+          int lo = 0, hi = kBChunk - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_off[mid] <= q)
+              lo = mid;
+            else
+              hi = mid - 1;
+          }
+          const unsigned long long y = (unsigned long long)s_ys[lo] + (q - s_off[lo]);
+          if (y >= (unsigned long long)a.ny) {
+            record_error(a.st, kErrInternal);
+            continue;
+          }
+          const YEntry ye = a.yg[y];
+          accumulate(ye.phi, __dmul_rn(s_v[lo], ye.v));
+        }
+        __syncthreads();
+      }
+    }
+    __syncthreads();
+
+    // count, reserve, write
+    unsigned long long n = 0;
+    for (unsigned s = tid; s < tsize; s += kBBlock) n += DENSE ? (flag[s] ? 1u : 0u) : (tab[s].key != kEmpty ? 1u : 0u);
+    n = block_sum<kBBlock>(n, s_wave);
+    if (tid == 0) s_base = atomicAdd(&a.st->out_base, n);
+    __syncthreads();
+    const unsigned long long obase = s_base;
+    unsigned long long run = 0;
+    for (unsigned s0 = 0; s0 < tsize; s0 += kBBlock) {
+      const unsigned s = s0 + tid;
+      bool occ;
+      unsigned long long key;
+      double val;
+      if (DENSE) {
+        occ = flag[s] != 0;
+        key = s;
+        val = acc[s];
+      } else {
+        const ZSlot z = tab[s];
+        occ = z.key != kEmpty;
+        key = z.key;
+        val = z.val;
+      }
+      unsigned long long tot;
+      const unsigned long long r = block_excl_scan<kBBlock>(occ ? 1ull : 0ull, s_wave, &tot);
+      if (occ) {
+        const unsigned long long pos = obase + run + r;
+        if ((int64_t)pos < a.out_cap) write_output(a, pos, G.phi, key, val);
+      }
+      run += tot;
+    }
+    __syncthreads();
+  }
+}
+
+// Direct class: output q is product q of the direct list.  Product-space
+// tiles stage the slice of dpos they overlap in LDS; each lane finds its
+// group by binary search there.  Lanes take consecutive products, so the Y
+// loads and the COO stores coalesce.
+constexpr int kDBlock = 256;
+constexpr int kDItems = 8;
+constexpr int kDTile = kDBlock * kDItems;
+
+__global__ __launch_bounds__(kDBlock) void k_group_direct(GroupArgs a, const uint32_t* __restrict__ dlist,
+                                                          const unsigned long long* __restrict__ dpos, int64_t nd,
+                                                          uint64_t nprod) {
+  __shared__ unsigned long long s_pos[kDTile + 1];
+  __shared__ int64_t s_range[2];
+  const uint64_t ntiles = (nprod + kDTile - 1) / kDTile;
+  for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const uint64_t p0 = t * kDTile;
+    const uint64_t p1 = (p0 + kDTile < nprod) ? p0 + kDTile : nprod;
+    if (threadIdx.x == 0) s_range[0] = upper_bound_idx(dpos, 0, nd + 1, p0) - 1;
+    if (threadIdx.x == 64) s_range[1] = upper_bound_idx(dpos, 0, nd + 1, p1 - 1) - 1;
+    __syncthreads();
+    const int64_t ilo = s_range[0], ihi = s_range[1];
+    const int64_t nloc = ihi - ilo + 1;
+    const bool staged = nloc <= kDTile;
+    if (staged)
+      for (int64_t k = threadIdx.x; k <= nloc; k += kDBlock) s_pos[k] = dpos[ilo + k];
+    __syncthreads();
+    for (int it = 0; it < kDItems; ++it) {
+      const uint64_t q = p0 + (uint64_t)it * kDBlock + threadIdx.x;
+      if (q >= p1) break;
+      int64_t li;
+      unsigned long long qs;
+      if (staged) {
+        int lo = 0, hi = (int)nloc - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (s_pos[mid] <= q)
+            lo = mid;
+          else
+            hi = mid - 1;
+        }
+        li = ilo + lo;
+        qs = s_pos[lo];
+      } else {
+        li = upper_bound_idx(dpos, ilo, ihi + 1, q) - 1;
+        qs = dpos[li];
+      }
+      const GroupRec G = a.groups[dlist[li]];
+      const XRec r = a.xr[G.start];
+      const unsigned long long y = (unsigned long long)r.ystart + (q - qs);
+      if (y >= (unsigned long long)a.ny) {
+        record_error(a.st, kErrInternal);
+        continue;
+      }
+      const YEntry ye = a.yg[y];
+      if ((int64_t)q < a.out_cap) write_output(a, q, G.phi, ye.phi, __dmul_rn(r.v, ye.v));
+    }
+    __syncthreads();
+  }
+}
+
+struct ListScanOp {
+  const uint32_t* gn;
+  const uint32_t* wlist;
+  unsigned long long* goff;
+  uint64_t base;
+  __device__ unsigned long long get(int64_t i) const { return gn[wlist[i]]; }
+  __device__ void put(int64_t i, unsigned long long excl, unsigned long long) const { goff[wlist[i]] = base + excl; }
+};
+
+struct FinOutBase {
+  DevStatus* st;
+  uint64_t base;
+  __device__ void operator()(unsigned long long total) const { st->out_base = base + total; }
+};
+
+__global__ void k_finalize(int64_t* out_nnz, int64_t out_cap, DevStatus* st) {
+  const unsigned long long total = st->out_base;
+  uint32_t err = st->err;
+  if ((int64_t)total > out_cap) {
+    err |= kErrCapacity;
+    atomicOr(&st->err, kErrCapacity);
+  }
+  *out_nnz = err ? -(int64_t)status_of(err) : (int64_t)total;
+}
+
+__global__ void k_reset_status(DevStatus* st) {
+  st->err = 0u;
+  st->out_base = 0ull;
+}
+
+// Inspection: X groups -> (free coordinates, entry count, product count).
+__global__ void k_x_groups(const GroupRec* __restrict__ groups, int64_t ng, const unsigned long long* __restrict__ eoff,
+                           KeyUnpack ku, int32_t* __restrict__ coords, int64_t* __restrict__ counts,
+                           int64_t* __restrict__ products, int64_t cap) {
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ng && g < cap;
+       g += (int64_t)gridDim.x * blockDim.x) {
+    const GroupRec G = groups[g];
+#pragma unroll
+    for (int m = 0; m < kMaxOrder; ++m)
+      if (m < ku.n) coords[(int64_t)m * cap + g] = (int32_t)((G.phi >> ku.shift[m]) & ku.mask[m]);
+    counts[g] = G.count;
+    products[g] = (int64_t)(eoff[G.start + G.count] - eoff[G.start]);
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+hipError_t launch_scan_x_table(YSlot* tab, int64_t nslots, GroupRec* groups, void* tile_sums, DevStatus* st,
+                               hipStream_t stream) {
+  return device_scan(XTableScanOp{tab, groups}, nslots, tile_sums, FinXGroups{st}, stream);
+}
+
+hipError_t launch_x_scatter(const int32_t* xidx, const double* xval, int64_t nnz, KeyPack kf, KeyPack kc, Bounds b,
+                            YSlot* xtab, uint64_t xmask, int32_t max_probe_x, const YSlot* ytab, uint64_t ymask,
+                            int32_t max_probe_y, uint64_t seed, XRec* xr, DevStatus* st, int num_cus,
+                            hipStream_t stream) {
+  if (nnz <= 0) return hipSuccess;
+  k_x_scatter<<<grid_for(nnz, 256, num_cus), 256, 0, stream>>>(xidx, xval, nnz, kf, kc, b, xtab, xmask, max_probe_x,
+                                                                ytab, ymask, max_probe_y, seed, xr, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_entries(const XRec* xr, int64_t n, unsigned long long* eoff, void* tile_sums, DevStatus* st,
+                               hipStream_t stream) {
+  return device_scan(EntryScanOp{xr, eoff}, n, tile_sums, FinEntries{eoff + n, st}, stream);
+}
+
+hipError_t launch_classify(const GroupRec* groups, int64_t max_groups, const unsigned long long* eoff,
+                           uint64_t ycells, int32_t dense, uint32_t* dlist, uint32_t* wlist, uint32_t* blist,
+                           uint32_t* glist, void* tile_sums, DevStatus* st, hipStream_t stream) {
+  return device_scan(ClassifyOp{groups, eoff, st, ycells, dense, dlist, wlist, blist, glist}, max_groups, tile_sums,
+                     FinClassify{st}, stream);
+}
+
+hipError_t launch_scan_direct(const GroupRec* groups, const uint32_t* dlist, int64_t max_groups,
+                              const unsigned long long* eoff, unsigned long long* dpos, void* tile_sums,
+                              DevStatus* st, hipStream_t stream) {
+  return device_scan(DirectScanOp{groups, dlist, eoff, dpos, st}, max_groups, tile_sums, FinDirect{dpos, st},
+                     stream);
+}
+
+hipError_t launch_scan_global_entries(const GroupRec* groups, const uint32_t* glist, int64_t ngl,
+                                      unsigned long long* gl_eoff, void* tile_sums, DevStatus* st,
+                                      hipStream_t stream) {
+  return device_scan(GlobalEntryScanOp{groups, glist, gl_eoff}, ngl, tile_sums, FinGlobalEntries{st}, stream);
+}
+
+hipError_t launch_gather_global(const GroupRec* groups, const uint32_t* glist, int64_t ngl,
+                                const unsigned long long* gl_eoff, const XRec* xr, XEntry* xrec, uint32_t* xg,
+                                uint32_t* xcnt, int num_cus, hipStream_t stream) {
+  if (ngl <= 0) return hipSuccess;
+  k_gather_global<<<grid_for(ngl * 64, 256, num_cus), 256, 0, stream>>>(groups, glist, ngl, gl_eoff, xr, xrec, xg,
+                                                                         xcnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_group_wave(const GroupArgs& a, const uint32_t* wlist, int64_t nw, int fill, int num_cus,
+                             hipStream_t stream) {
+  if (nw <= 0) return hipSuccess;
+  const unsigned grid = grid_for(nw * 64, kGBlock, num_cus, 8);
+  if (fill)
+    k_group_wave<true><<<grid, kGBlock, 0, stream>>>(a, wlist, nw);
+  else
+    k_group_wave<false><<<grid, kGBlock, 0, stream>>>(a, wlist, nw);
+  return hipGetLastError();
+}
+
+hipError_t launch_group_block(const GroupArgs& a, const uint32_t* blist, int64_t nb, int dense, int num_cus,
+                              hipStream_t stream) {
+  if (nb <= 0) return hipSuccess;
+  const unsigned grid = grid_for(nb * kBBlock, kBBlock, num_cus, 2);
+  if (dense) {
+    unsigned cells = 1u << a.bits_y;
+    if (cells < (unsigned)kBBlock) cells = kBBlock;
+    const size_t lds = (size_t)cells * 9;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_group_block<true>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    k_group_block<true><<<grid, kBBlock, lds, stream>>>(a, blist, nb, cells);
+  } else {
+    const size_t lds = (size_t)kBlockSlots * 16;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_group_block<false>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    k_group_block<false><<<grid, kBBlock, lds, stream>>>(a, blist, nb, 0u);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_group_direct(const GroupArgs& a, const uint32_t* dlist, const unsigned long long* dpos, int64_t nd,
+                               uint64_t nprod, int num_cus, hipStream_t stream) {
+  if (nd <= 0 || nprod == 0) return hipSuccess;
+  const uint64_t tiles = (nprod + kDTile - 1) / kDTile;
+  uint64_t g = (uint64_t)num_cus * 8;
+  if (g > tiles) g = tiles;
+  k_group_direct<<<dim3((unsigned)g), kDBlock, 0, stream>>>(a, dlist, dpos, nd, nprod);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_group_counts(const uint32_t* gn, const uint32_t* wlist, int64_t nw, uint64_t base,
+                                    unsigned long long* goff, void* tile_sums, DevStatus* st, hipStream_t stream) {
+  return device_scan(ListScanOp{gn, wlist, goff, base}, nw, tile_sums, FinOutBase{st, base}, stream);
+}
+
+hipError_t launch_finalize(int64_t* out_nnz, int64_t out_cap, DevStatus* st, hipStream_t stream) {
+  k_finalize<<<1, 1, 0, stream>>>(out_nnz, out_cap, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_status(DevStatus* st, hipStream_t stream) {
+  k_reset_status<<<1, 1, 0, stream>>>(st);
+  return hipGetLastError();
+}
+
+hipError_t launch_x_groups(const GroupRec* groups, int64_t ng, const unsigned long long* eoff, KeyUnpack ku,
+                           int32_t* coords, int64_t* counts, int64_t* products, int64_t cap, hipStream_t stream) {
+  if (ng <= 0) return hipSuccess;
+  int64_t g = (ng + 255) / 256;
+  if (g > 65536) g = 65536;
+  k_x_groups<<<dim3((unsigned)g), 256, 0, stream>>>(groups, ng, eoff, ku, coords, counts, products, cap);
+  return hipGetLastError();
+}
+
+}  // namespace sptc

@@ -1,7 +1,8 @@
 // HIP kernels for sparse-sparse tensor contraction on gfx950 (CDNA4).
 //
-// Pipeline (see sptc.h for the method and its citations):
-//   plan:    fill Y table -> y_count -> scan counts -> y_scatter -> x_probe -> scan products
+// Pipeline of the global-hash path (see sptc.h for the method and its
+// citations; grouped.hip holds the X-grouped path):
+//   plan:    fill Y table -> key_count -> scan counts -> y_scatter -> x_probe -> scan products
 //   execute: fill output hash -> expand_acc -> compact (count, scan, fill)
 //
 // Everything is wave64-native: reductions and scans use 64-lane shuffles and
@@ -10,206 +11,12 @@
 #include <hip/hip_runtime.h>
 
 #include "../../include/sptc.h"
+#include "prim.hpp"
 #include "sptc_internal.hpp"
 
 namespace sptc {
 namespace {
 
-// MurmurHash3 64-bit finalizer (Appleby, public domain): a bijective mixer
-// so that consecutive packed keys spread over the table.
-__device__ __forceinline__ uint64_t fmix64(uint64_t k) {
-  k ^= k >> 33;
-  k *= 0xff51afd7ed558ccdull;
-  k ^= k >> 33;
-  k *= 0xc4ceb9fe1a85ec53ull;
-  k ^= k >> 33;
-  return k;
-}
-
-__device__ __forceinline__ uint64_t pack_key(const int32_t* __restrict__ idx, int64_t nnz, int64_t e,
-                                             const KeyPack& kp) {
-  uint64_t k = 0;
-#pragma unroll
-  for (int t = 0; t < kMaxOrder; ++t) {
-    if (t < kp.n) {
-      const uint32_t c = (uint32_t)idx[(int64_t)kp.mode[t] * nnz + e];
-      k |= (uint64_t)(c & kp.mask[t]) << kp.shift[t];
-    }
-  }
-  return k;
-}
-
-// Checks every coordinate of entry e against its mode length.
-__device__ __forceinline__ bool coords_ok(const int32_t* __restrict__ idx, int64_t nnz, int64_t e, const Bounds& b) {
-  bool ok = true;
-#pragma unroll
-  for (int m = 0; m < kMaxOrder; ++m)
-    if (m < b.order) ok &= (uint32_t)idx[(int64_t)m * nnz + e] < (uint32_t)b.dim[m];
-  return ok;
-}
-
-__device__ __forceinline__ void record_error(DevStatus* st, uint32_t bits) { atomicOr(&st->err, bits); }
-
-__device__ __forceinline__ int status_of(uint32_t err) {
-  if (err & kErrCoord) return SPTC_ERR_INVALID_ARG;
-  if (err & kErrCapacity) return SPTC_ERR_CAPACITY;
-  if (err) return SPTC_ERR_INTERNAL;
-  return SPTC_OK;
-}
-
-// ---------------------------------------------------------------------------
-// wave64 / block primitives
-// ---------------------------------------------------------------------------
-
-__device__ __forceinline__ unsigned long long wave_incl_scan(unsigned long long v) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const unsigned long long t = __shfl_up(v, d, 64);
-    if (lane >= d) v += t;
-  }
-  return v;
-}
-
-__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-  return v;
-}
-
-// Exclusive scan over the block; *total receives the block sum.  s_wave
-// holds BLOCK/64 + 1 entries.  Ends with a barrier so s_wave can be reused.
-template <int BLOCK>
-__device__ __forceinline__ unsigned long long block_excl_scan(unsigned long long v, unsigned long long* s_wave,
-                                                             unsigned long long* total) {
-  constexpr int W = BLOCK / 64;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const unsigned long long incl = wave_incl_scan(v);
-  if (lane == 63) s_wave[wave] = incl;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned long long run = 0;
-#pragma unroll
-    for (int w = 0; w < W; ++w) {
-      const unsigned long long t = s_wave[w];
-      s_wave[w] = run;
-      run += t;
-    }
-    s_wave[W] = run;
-  }
-  __syncthreads();
-  const unsigned long long excl = s_wave[wave] + incl - v;
-  *total = s_wave[W];
-  __syncthreads();
-  return excl;
-}
-
-template <int BLOCK>
-__device__ __forceinline__ unsigned long long block_sum(unsigned long long v, unsigned long long* s_wave) {
-  constexpr int W = BLOCK / 64;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  v = wave_sum(v);
-  if (lane == 0) s_wave[wave] = v;
-  __syncthreads();
-  unsigned long long t = 0;
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int w = 0; w < W; ++w) t += s_wave[w];
-  }
-  __syncthreads();
-  return t;  // valid in thread 0
-}
-
-// ---------------------------------------------------------------------------
-// Device-wide exclusive scan: reduce tiles, scan tile sums, rescan tiles.
-// An Op supplies get(i) -> u64 and put(i, exclusive_prefix, value).
-// ---------------------------------------------------------------------------
-
-template <class Op>
-__global__ __launch_bounds__(kScanBlock) void k_tile_reduce(Op op, int64_t n, unsigned long long* tile_sums) {
-  __shared__ unsigned long long s_wave[kScanBlock / 64 + 1];
-  const int64_t base = (int64_t)blockIdx.x * kScanTile;
-  unsigned long long s = 0;
-#pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    const int64_t i = base + (int64_t)k * kScanBlock + threadIdx.x;
-    if (i < n) s += op.get(i);
-  }
-  s = block_sum<kScanBlock>(s, s_wave);
-  if (threadIdx.x == 0) tile_sums[blockIdx.x] = s;
-}
-
-constexpr int kTopBlock = 1024;
-constexpr int kTopItems = 8;
-
-// Single block: exclusive scan of tile sums in place; fin(total) runs on
-// thread 0 at the end.
-template <class Fin>
-__global__ __launch_bounds__(kTopBlock) void k_scan_tile_sums(unsigned long long* sums, int64_t ntiles, Fin fin) {
-  __shared__ unsigned long long s_wave[kTopBlock / 64 + 1];
-  unsigned long long carry = 0;
-  for (int64_t base = 0; base < ntiles; base += (int64_t)kTopBlock * kTopItems) {
-    unsigned long long v[kTopItems];
-    unsigned long long local = 0;
-    const int64_t first = base + (int64_t)threadIdx.x * kTopItems;
-#pragma unroll
-    for (int k = 0; k < kTopItems; ++k) {
-      v[k] = (first + k < ntiles) ? sums[first + k] : 0ull;
-      local += v[k];
-    }
-    unsigned long long total;
-    unsigned long long run = carry + block_excl_scan<kTopBlock>(local, s_wave, &total);
-#pragma unroll
-    for (int k = 0; k < kTopItems; ++k) {
-      if (first + k < ntiles) sums[first + k] = run;
-      run += v[k];
-    }
-    carry += total;
-  }
-  if (threadIdx.x == 0) fin(carry);
-}
-
-template <class Op>
-__global__ __launch_bounds__(kScanBlock) void k_tile_scan(Op op, int64_t n, const unsigned long long* tile_offsets) {
-  __shared__ unsigned long long s_wave[kScanBlock / 64 + 1];
-  const int64_t base = (int64_t)blockIdx.x * kScanTile;
-  unsigned long long carry = tile_offsets[blockIdx.x];
-  for (int k = 0; k < kScanItems; ++k) {
-    const int64_t chunk = base + (int64_t)k * kScanBlock;
-    if (chunk >= n) break;  // uniform across the block
-    const int64_t i = chunk + threadIdx.x;
-    const unsigned long long v = i < n ? op.get(i) : 0ull;
-    unsigned long long total;
-    const unsigned long long excl = block_excl_scan<kScanBlock>(v, s_wave, &total);
-    if (i < n) op.put(i, carry + excl, v);
-    carry += total;
-  }
-}
-
-struct FinNone {
-  __device__ void operator()(unsigned long long) const {}
-};
-
-template <class Op, class Fin>
-hipError_t device_scan(Op op, int64_t n, unsigned long long* tile_sums, Fin fin, hipStream_t stream) {
-  const int64_t tiles = scan_tiles(n);
-  if (tiles > 0) {
-    k_tile_reduce<Op><<<dim3((unsigned)tiles), dim3(kScanBlock), 0, stream>>>(op, n, tile_sums);
-  }
-  k_scan_tile_sums<Fin><<<1, kTopBlock, 0, stream>>>(tile_sums, tiles, fin);
-  if (tiles > 0) {
-    k_tile_scan<Op><<<dim3((unsigned)tiles), dim3(kScanBlock), 0, stream>>>(op, n, tile_sums);
-  }
-  return hipGetLastError();
-}
-
-inline unsigned grid_for(int64_t n, int block, int num_cus, int per_cu = 16) {
-  int64_t g = (n + block - 1) / block;
-  const int64_t cap = (int64_t)num_cus * per_cu;
-  if (g > cap) g = cap;
-  if (g < 1) g = 1;
-  return (unsigned)g;
-}
 
 // ---------------------------------------------------------------------------
 // Kernels
@@ -222,19 +29,21 @@ __global__ void k_fill_empty(uint4* __restrict__ slots, int64_t n, DevStatus* st
     slots[i] = e;
 }
 
-// A1: count Y entries per contracting key in the Y table.
-__global__ __launch_bounds__(256) void k_y_count(const int32_t* __restrict__ yidx, int64_t nnz, KeyPack kc,
-                                                 YSlot* __restrict__ tab, uint64_t mask, uint64_t seed,
-                                                 int32_t max_probe, DevStatus* st) {
+// A1: count entries per packed key (Y by contracting key; X by free key on
+// the grouped path) in an open-addressing table with linear probing.
+__global__ __launch_bounds__(256) void k_key_count(const int32_t* __restrict__ idx, int64_t nnz, KeyPack kc,
+                                                   YSlot* __restrict__ tab, uint64_t mask, uint64_t seed,
+                                                   int32_t max_probe, DevStatus* st,
+                                                   unsigned long long* distinct) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
-    const uint64_t key = pack_key(yidx, nnz, e, kc);
+    const uint64_t key = pack_key(idx, nnz, e, kc);
     uint64_t s = fmix64(key ^ seed) & mask;
     int32_t probe = 0;
     for (;;) {
       const unsigned long long prev = atomicCAS(&tab[s].key, (unsigned long long)kEmpty, (unsigned long long)key);
       if (prev == kEmpty || prev == key) {
         atomicAdd(&tab[s].count, 1u);
-        if (prev == kEmpty) atomicAdd(&st->groups, 1ull);
+        if (prev == kEmpty && distinct) atomicAdd(distinct, 1ull);
         break;
       }
       if (++probe >= max_probe) {
@@ -255,25 +64,14 @@ struct YTableScanOp {
   }
 };
 
-// Finds `key`, which must be present; returns the slot or -1.
-__device__ __forceinline__ int64_t find_slot(const YSlot* __restrict__ tab, uint64_t key, uint64_t mask,
-                                             uint64_t seed, int32_t max_probe) {
-  uint64_t s = fmix64(key ^ seed) & mask;
-  for (int32_t probe = 0; probe < max_probe; ++probe) {
-    const unsigned long long k = tab[s].key;
-    if (k == key) return (int64_t)s;
-    if (k == kEmpty) return -1;
-    s = (s + 1) & mask;
-  }
-  return -1;
-}
-
 // A3: scatter Y into its groups (counting-sort placement: take the end of
 // the group's run and decrement).
 __global__ __launch_bounds__(256) void k_y_scatter(const int32_t* __restrict__ yidx, const double* __restrict__ yval,
                                                    int64_t nnz, KeyPack kc, KeyPack kf, Bounds b,
                                                    YSlot* __restrict__ tab, uint64_t mask, uint64_t seed,
-                                                   int32_t max_probe, YEntry* __restrict__ yg, DevStatus* st) {
+                                                   int32_t max_probe, YEntry* __restrict__ yg,
+                                                   unsigned long long* __restrict__ yset, uint64_t yset_mask,
+                                                   int32_t bits_y, DevStatus* st) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
     if (b.check && !coords_ok(yidx, nnz, e, b)) record_error(st, kErrCoord);
     const uint64_t key = pack_key(yidx, nnz, e, kc);
@@ -291,7 +89,25 @@ __global__ __launch_bounds__(256) void k_y_scatter(const int32_t* __restrict__ y
     ent.phi = pack_key(yidx, nnz, e, kf);
     ent.v = yval[e];
     yg[pos] = ent;
+    if (yset) {  // a repeated full coordinate marks Y as having duplicates
+      const unsigned long long full = (key << bits_y) | ent.phi;
+      uint64_t h = fmix64(full ^ seed) & yset_mask;
+      for (uint64_t probe = 0; probe <= yset_mask; ++probe) {
+        const unsigned long long prev = atomicCAS(&yset[h], (unsigned long long)kEmpty, full);
+        if (prev == kEmpty) break;
+        if (prev == full) {
+          st->ydup = 1u;
+          break;
+        }
+        h = (h + 1) & yset_mask;
+      }
+    }
   }
+}
+
+__global__ void k_fill_keys(unsigned long long* __restrict__ keys, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    keys[i] = kEmpty;
 }
 
 // B1: each X entry finds its Y group: start and count (0 on a miss).
@@ -334,10 +150,10 @@ struct ProductScanOp {
 
 struct FinProducts {
   unsigned long long* poff_end;
-  DevStatus* st;
+  unsigned long long* total_out;
   __device__ void operator()(unsigned long long total) const {
     *poff_end = total;
-    st->products = total;
+    *total_out = total;
   }
 };
 
@@ -351,19 +167,6 @@ struct FinProducts {
 constexpr int kExpBlock = 256;
 constexpr int kExpItems = 8;
 constexpr int kExpTile = kExpBlock * kExpItems;
-
-__device__ __forceinline__ int64_t upper_bound_u64(const unsigned long long* __restrict__ a, int64_t lo, int64_t hi,
-                                                   unsigned long long v) {
-  // first index in [lo, hi) with a[i] > v (hi if none)
-  while (lo < hi) {
-    const int64_t mid = lo + ((hi - lo) >> 1);
-    if (a[mid] <= v)
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  return lo;
-}
 
 __device__ __forceinline__ void hash_accumulate(ZSlot* __restrict__ tab, uint64_t mask, uint64_t seed,
                                                 int32_t max_probe, uint64_t key, double v, DevStatus* st) {
@@ -395,8 +198,8 @@ __global__ __launch_bounds__(kExpBlock) void k_expand_acc(const unsigned long lo
   for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const uint64_t p0 = t * kExpTile;
     const uint64_t p1 = (p0 + kExpTile < products) ? p0 + kExpTile : products;
-    if (threadIdx.x == 0) s_range[0] = upper_bound_u64(poff, 0, nx + 1, p0) - 1;
-    if (threadIdx.x == 64) s_range[1] = upper_bound_u64(poff, 0, nx + 1, p1 - 1) - 1;
+    if (threadIdx.x == 0) s_range[0] = upper_bound_idx(poff, 0, nx + 1, p0) - 1;
+    if (threadIdx.x == 64) s_range[1] = upper_bound_idx(poff, 0, nx + 1, p1 - 1) - 1;
     __syncthreads();
     const int64_t xlo = s_range[0], xhi = s_range[1];
     const int64_t nloc = xhi - xlo + 1;  // X entries overlapping the tile
@@ -422,7 +225,7 @@ __global__ __launch_bounds__(kExpBlock) void k_expand_acc(const unsigned long lo
         x = xlo + lo;
         px = s_poff[lo];
       } else {
-        x = upper_bound_u64(poff, xlo, xhi + 1, p) - 1;
+        x = upper_bound_idx(poff, xlo, xhi + 1, p) - 1;
         px = poff[x];
       }
       const XEntry xe = xrec[x];
@@ -447,9 +250,12 @@ struct OccupancyOp {
   int32_t* out_idx;
   double* out_val;
   int64_t out_cap;
+  const unsigned long long* base;
   __device__ unsigned long long get(int64_t i) const { return tab[i].key != kEmpty ? 1ull : 0ull; }
-  __device__ void put(int64_t i, unsigned long long pos, unsigned long long v) const {
-    if (!v || (int64_t)pos >= out_cap) return;
+  __device__ void put(int64_t i, unsigned long long rank, unsigned long long v) const {
+    if (!v) return;
+    const unsigned long long pos = rank + (base ? *base : 0ull);
+    if ((int64_t)pos >= out_cap) return;
     const ZSlot z = tab[i];
 #pragma unroll
     for (int m = 0; m < kMaxOutOrder; ++m)
@@ -461,8 +267,10 @@ struct OccupancyOp {
 struct FinCompact {
   int64_t* out_nnz;
   int64_t out_cap;
+  const unsigned long long* base;
   DevStatus* st;
-  __device__ void operator()(unsigned long long total) const {
+  __device__ void operator()(unsigned long long count) const {
+    const unsigned long long total = count + (base ? *base : 0ull);
     uint32_t err = st->err;
     if ((int64_t)total > out_cap) {
       err |= kErrCapacity;
@@ -527,10 +335,12 @@ hipError_t launch_fill_empty(void* slots16, int64_t nslots, DevStatus* st, hipSt
   return hipGetLastError();
 }
 
-hipError_t launch_y_count(const int32_t* yidx, int64_t nnz, KeyPack kc, YSlot* tab, uint64_t mask, uint64_t seed,
-                          int32_t max_probe, DevStatus* st, int num_cus, hipStream_t stream) {
+hipError_t launch_key_count(const int32_t* idx, int64_t nnz, KeyPack kc, YSlot* tab, uint64_t mask, uint64_t seed,
+                            int32_t max_probe, DevStatus* st, unsigned long long* distinct, int num_cus,
+                            hipStream_t stream) {
   if (nnz <= 0) return hipSuccess;
-  k_y_count<<<grid_for(nnz, 256, num_cus), 256, 0, stream>>>(yidx, nnz, kc, tab, mask, seed, max_probe, st);
+  k_key_count<<<grid_for(nnz, 256, num_cus), 256, 0, stream>>>(idx, nnz, kc, tab, mask, seed, max_probe, st,
+                                                                distinct);
   return hipGetLastError();
 }
 
@@ -539,11 +349,20 @@ hipError_t launch_scan_y_table(YSlot* tab, int64_t nslots, unsigned long long* t
 }
 
 hipError_t launch_y_scatter(const int32_t* yidx, const double* yval, int64_t nnz, KeyPack kc, KeyPack kf, Bounds b,
-                            YSlot* tab, uint64_t mask, uint64_t seed, int32_t max_probe, YEntry* yg, DevStatus* st,
-                            int num_cus, hipStream_t stream) {
+                            YSlot* tab, uint64_t mask, uint64_t seed, int32_t max_probe, YEntry* yg,
+                            unsigned long long* yset, uint64_t yset_mask, int32_t bits_y, DevStatus* st, int num_cus,
+                            hipStream_t stream) {
   if (nnz <= 0) return hipSuccess;
   k_y_scatter<<<grid_for(nnz, 256, num_cus), 256, 0, stream>>>(yidx, yval, nnz, kc, kf, b, tab, mask, seed,
-                                                                max_probe, yg, st);
+                                                                max_probe, yg, yset, yset_mask, bits_y, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_keys(unsigned long long* keys, int64_t n, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  int64_t g = (n + 255) / 256;
+  if (g > 65536) g = 65536;
+  k_fill_keys<<<dim3((unsigned)g), 256, 0, stream>>>(keys, n);
   return hipGetLastError();
 }
 
@@ -557,8 +376,8 @@ hipError_t launch_x_probe(const int32_t* xidx, const double* xval, int64_t nnz, 
 }
 
 hipError_t launch_scan_products(const uint32_t* xcnt, int64_t n, unsigned long long* poff,
-                                unsigned long long* tile_sums, DevStatus* st, hipStream_t stream) {
-  return device_scan(ProductScanOp{xcnt, poff}, n, tile_sums, FinProducts{poff + n, st}, stream);
+                                unsigned long long* tile_sums, unsigned long long* total, hipStream_t stream) {
+  return device_scan(ProductScanOp{xcnt, poff}, n, tile_sums, FinProducts{poff + n, total}, stream);
 }
 
 hipError_t launch_expand_acc(const unsigned long long* poff, int64_t nx, const XEntry* xrec, const uint32_t* xg,
@@ -575,10 +394,10 @@ hipError_t launch_expand_acc(const unsigned long long* poff, int64_t nx, const X
 }
 
 hipError_t launch_compact(const ZSlot* tab, int64_t nslots, KeyUnpack ku, int32_t* out_idx, double* out_val,
-                          int64_t out_cap, int64_t* out_nnz, unsigned long long* tile_sums, DevStatus* st,
-                          hipStream_t stream) {
-  return device_scan(OccupancyOp{tab, ku, out_idx, out_val, out_cap}, nslots, tile_sums,
-                     FinCompact{out_nnz, out_cap, st}, stream);
+                          int64_t out_cap, int64_t* out_nnz, const unsigned long long* base,
+                          unsigned long long* tile_sums, DevStatus* st, hipStream_t stream) {
+  return device_scan(OccupancyOp{tab, ku, out_idx, out_val, out_cap, base}, nslots, tile_sums,
+                     FinCompact{out_nnz, out_cap, base, st}, stream);
 }
 
 hipError_t launch_y_groups(const YSlot* tab, int64_t nslots, KeyUnpack ku, int32_t* key_coords, int64_t* counts,

@@ -1,0 +1,292 @@
+// Device primitives shared by the kernel translation units: hashing, key
+// packing, wave64/block scans and a device-wide exclusive scan.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/sptc.h"
+#include "sptc_internal.hpp"
+
+namespace sptc {
+namespace {
+
+// MurmurHash3 64-bit finalizer (Appleby, public domain): a bijective mixer
+// so that consecutive packed keys spread over the table.
+__device__ __forceinline__ uint64_t fmix64(uint64_t k) {
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdull;
+  k ^= k >> 33;
+  k *= 0xc4ceb9fe1a85ec53ull;
+  k ^= k >> 33;
+  return k;
+}
+
+__device__ __forceinline__ uint64_t pack_key(const int32_t* __restrict__ idx, int64_t nnz, int64_t e,
+                                             const KeyPack& kp) {
+  uint64_t k = 0;
+#pragma unroll
+  for (int t = 0; t < kMaxOrder; ++t) {
+    if (t < kp.n) {
+      const uint32_t c = (uint32_t)idx[(int64_t)kp.mode[t] * nnz + e];
+      k |= (uint64_t)(c & kp.mask[t]) << kp.shift[t];
+    }
+  }
+  return k;
+}
+
+// Checks every coordinate of entry e against its mode length.
+__device__ __forceinline__ bool coords_ok(const int32_t* __restrict__ idx, int64_t nnz, int64_t e, const Bounds& b) {
+  bool ok = true;
+#pragma unroll
+  for (int m = 0; m < kMaxOrder; ++m)
+    if (m < b.order) ok &= (uint32_t)idx[(int64_t)m * nnz + e] < (uint32_t)b.dim[m];
+  return ok;
+}
+
+__device__ __forceinline__ void record_error(DevStatus* st, uint32_t bits) { atomicOr(&st->err, bits); }
+
+__device__ __forceinline__ int status_of(uint32_t err) {
+  if (err & kErrCoord) return SPTC_ERR_INVALID_ARG;
+  if (err & kErrCapacity) return SPTC_ERR_CAPACITY;
+  if (err) return SPTC_ERR_INTERNAL;
+  return SPTC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// wave64 / block primitives, for u64 values and for pairs of u64 counters
+// ---------------------------------------------------------------------------
+
+struct U128 {
+  unsigned long long lo, hi;
+};
+__device__ __forceinline__ U128 operator+(U128 a, U128 b) { return U128{a.lo + b.lo, a.hi + b.hi}; }
+__device__ __forceinline__ U128 operator-(U128 a, U128 b) { return U128{a.lo - b.lo, a.hi - b.hi}; }
+__device__ __forceinline__ unsigned long long shfl_up_v(unsigned long long v, int d) { return __shfl_up(v, d, 64); }
+__device__ __forceinline__ U128 shfl_up_v(U128 v, int d) {
+  return U128{__shfl_up(v.lo, d, 64), __shfl_up(v.hi, d, 64)};
+}
+__device__ __forceinline__ unsigned long long shfl_xor_v(unsigned long long v, int d) { return __shfl_xor(v, d, 64); }
+__device__ __forceinline__ U128 shfl_xor_v(U128 v, int d) {
+  return U128{__shfl_xor(v.lo, d, 64), __shfl_xor(v.hi, d, 64)};
+}
+
+template <class V>
+__device__ __forceinline__ V wave_incl_scan_t(V v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const V t = shfl_up_v(v, d);
+    if (lane >= d) v = v + t;
+  }
+  return v;
+}
+
+template <class V>
+__device__ __forceinline__ V wave_sum_t(V v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v = v + shfl_xor_v(v, d);
+  return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_incl_scan(unsigned long long v) { return wave_incl_scan_t(v); }
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) { return wave_sum_t(v); }
+
+// Exclusive scan over the block; *total receives the block sum.  s_wave
+// holds BLOCK/64 + 1 entries.  Ends with a barrier so s_wave can be reused.
+template <int BLOCK, class V>
+__device__ __forceinline__ V block_excl_scan_t(V v, V* s_wave, V* total) {
+  constexpr int W = BLOCK / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const V incl = wave_incl_scan_t(v);
+  if (lane == 63) s_wave[wave] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    V run{};
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const V t = s_wave[w];
+      s_wave[w] = run;
+      run = run + t;
+    }
+    s_wave[W] = run;
+  }
+  __syncthreads();
+  const V excl = s_wave[wave] + incl - v;
+  *total = s_wave[W];
+  __syncthreads();
+  return excl;
+}
+
+template <int BLOCK>
+__device__ __forceinline__ unsigned long long block_excl_scan(unsigned long long v, unsigned long long* s_wave,
+                                                             unsigned long long* total) {
+  return block_excl_scan_t<BLOCK>(v, s_wave, total);
+}
+
+template <int BLOCK, class V>
+__device__ __forceinline__ V block_sum_t(V v, V* s_wave) {
+  constexpr int W = BLOCK / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  v = wave_sum_t(v);
+  if (lane == 0) s_wave[wave] = v;
+  __syncthreads();
+  V t{};
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int w = 0; w < W; ++w) t = t + s_wave[w];
+  }
+  __syncthreads();
+  return t;  // valid in thread 0
+}
+
+template <int BLOCK>
+__device__ __forceinline__ unsigned long long block_sum(unsigned long long v, unsigned long long* s_wave) {
+  return block_sum_t<BLOCK>(v, s_wave);
+}
+
+// ---------------------------------------------------------------------------
+// Device-wide exclusive scan: reduce tiles, scan tile sums, rescan tiles.
+// An Op supplies get(i) -> V (u64 or U128) and put(i, exclusive_prefix,
+// value).  The tile-sum buffer holds scan_tiles(n) + 1 values of V.
+// ---------------------------------------------------------------------------
+
+template <class Op, class V>
+__global__ __launch_bounds__(kScanBlock) void k_tile_reduce(Op op, int64_t n, V* tile_sums) {
+  __shared__ V s_wave[kScanBlock / 64 + 1];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  V s{};
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t i = base + (int64_t)k * kScanBlock + threadIdx.x;
+    if (i < n) s = s + op.get(i);
+  }
+  s = block_sum_t<kScanBlock>(s, s_wave);
+  if (threadIdx.x == 0) tile_sums[blockIdx.x] = s;
+}
+
+constexpr int kTopBlock = 1024;
+constexpr int kTopItems = 8;
+
+// Single block: exclusive scan of tile sums in place; fin(total) runs on
+// thread 0 at the end.
+template <class Fin, class V>
+__global__ __launch_bounds__(kTopBlock) void k_scan_tile_sums(V* sums, int64_t ntiles, Fin fin) {
+  __shared__ V s_wave[kTopBlock / 64 + 1];
+  V carry{};
+  for (int64_t base = 0; base < ntiles; base += (int64_t)kTopBlock * kTopItems) {
+    V v[kTopItems];
+    V local{};
+    const int64_t first = base + (int64_t)threadIdx.x * kTopItems;
+#pragma unroll
+    for (int k = 0; k < kTopItems; ++k) {
+      v[k] = (first + k < ntiles) ? sums[first + k] : V{};
+      local = local + v[k];
+    }
+    V total;
+    V run = carry + block_excl_scan_t<kTopBlock>(local, s_wave, &total);
+#pragma unroll
+    for (int k = 0; k < kTopItems; ++k) {
+      if (first + k < ntiles) sums[first + k] = run;
+      run = run + v[k];
+    }
+    carry = carry + total;
+  }
+  if (threadIdx.x == 0) fin(carry);
+}
+
+template <class Op, class V>
+__global__ __launch_bounds__(kScanBlock) void k_tile_scan(Op op, int64_t n, const V* tile_offsets) {
+  __shared__ V s_wave[kScanBlock / 64 + 1];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  V carry = tile_offsets[blockIdx.x];
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t chunk = base + (int64_t)k * kScanBlock;
+    if (chunk >= n) break;  // uniform across the block
+    const int64_t i = chunk + threadIdx.x;
+    const V v = i < n ? op.get(i) : V{};
+    V total;
+    const V excl = block_excl_scan_t<kScanBlock>(v, s_wave, &total);
+    if (i < n) op.put(i, carry + excl, v);
+    carry = carry + total;
+  }
+}
+
+struct FinNone {
+  template <class V>
+  __device__ void operator()(V) const {}
+};
+
+// tile_sums: device scratch of at least scan_tiles(n) + 1 values of the Op's
+// value type (U128 needs twice the u64 count).
+template <class Op, class Fin>
+hipError_t device_scan(Op op, int64_t n, void* tile_sums, Fin fin, hipStream_t stream) {
+  using V = decltype(op.get(0));
+  V* ts = static_cast<V*>(tile_sums);
+  const int64_t tiles = scan_tiles(n);
+  if (tiles > 0) {
+    k_tile_reduce<Op, V><<<dim3((unsigned)tiles), dim3(kScanBlock), 0, stream>>>(op, n, ts);
+  }
+  k_scan_tile_sums<Fin, V><<<1, kTopBlock, 0, stream>>>(ts, tiles, fin);
+  if (tiles > 0) {
+    k_tile_scan<Op, V><<<dim3((unsigned)tiles), dim3(kScanBlock), 0, stream>>>(op, n, ts);
+  }
+  return hipGetLastError();
+}
+
+// Finds `key` in a YSlot table; returns the slot or -1.
+__device__ __forceinline__ int64_t find_slot(const YSlot* __restrict__ tab, uint64_t key, uint64_t mask,
+                                             uint64_t seed, int32_t max_probe) {
+  uint64_t s = fmix64(key ^ seed) & mask;
+  for (int32_t probe = 0; probe < max_probe; ++probe) {
+    const unsigned long long k = tab[s].key;
+    if (k == key) return (int64_t)s;
+    if (k == kEmpty) return -1;
+    s = (s + 1) & mask;
+  }
+  return -1;
+}
+
+// First index in [lo, hi) with a[i] > v (hi if none).
+template <class T, class V>
+__device__ __forceinline__ int64_t upper_bound_idx(const T* a, int64_t lo, int64_t hi, V v) {
+  while (lo < hi) {
+    const int64_t mid = lo + ((hi - lo) >> 1);
+    if (a[mid] <= v)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ unsigned wave_incl_scan_u32(unsigned v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const unsigned t = __shfl_up(v, d, 64);
+    if (lane >= d) v += t;
+  }
+  return v;
+}
+
+__device__ __forceinline__ unsigned long long lanemask_lt() {
+  const int lane = threadIdx.x & 63;
+  return lane ? (~0ull >> (64 - lane)) : 0ull;
+}
+
+// Orders this wave's LDS accesses (an LDS table private to one wave).
+__device__ __forceinline__ void wave_lds_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+
+inline unsigned grid_for(int64_t n, int block, int num_cus, int per_cu = 16) {
+  int64_t g = (n + block - 1) / block;
+  const int64_t cap = (int64_t)num_cus * per_cu;
+  if (g > cap) g = cap;
+  if (g < 1) g = 1;
+  return (unsigned)g;
+}
+
+}  // namespace
+}  // namespace sptc

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -135,6 +136,33 @@ struct sptc_plan_s {
   ZSlot* ztab = nullptr;
   int64_t ztab_slots = 0;
   unsigned long long* ztile_sums = nullptr;
+  int64_t expand_nx = 0;         // X entries the global-hash expansion walks
+  int64_t expand_products = 0;   // products it expands
+
+  // grouped path
+  YSlot* xtab = nullptr;
+  int64_t xtab_slots = 0;
+  int32_t max_probe_x = 0;
+  GroupRec* groups = nullptr;
+  XRec* xr = nullptr;
+  unsigned long long* eoff = nullptr;
+  uint32_t* dlist = nullptr;
+  uint32_t* wlist = nullptr;
+  uint32_t* blist = nullptr;
+  uint32_t* glist = nullptr;
+  unsigned long long* dpos = nullptr;
+  unsigned long long* yset = nullptr;
+  int64_t yset_slots = 0;
+  uint32_t* gn = nullptr;
+  unsigned long long* goff = nullptr;
+  unsigned long long* gl_eoff = nullptr;
+  unsigned long long* etile_sums = nullptr;
+  int64_t x_groups = 0, nd = 0, nw = 0, nb = 0, ngl = 0;
+  int64_t direct_products = 0;
+  int32_t ydup = 0;
+  int32_t dense = 0;
+  uint64_t ycells = 0;
+  KeyUnpack ux{}, uy{};
 
   int64_t products = 0, y_groups = 0, out_bound = 0;
   int64_t workspace = 0;
@@ -202,6 +230,8 @@ sptc_status check_options(const sptc_options& o) {
   if (!(o.load_factor > 0.0 && o.load_factor <= 0.95))
     return fail(SPTC_ERR_INVALID_ARG, "load_factor %g outside (0, 0.95]", o.load_factor);
   if (o.max_probe < 0) return fail(SPTC_ERR_INVALID_ARG, "max_probe %d < 0", o.max_probe);
+  if (o.mode != SPTC_MODE_GROUPED && o.mode != SPTC_MODE_GLOBAL)
+    return fail(SPTC_ERR_INVALID_ARG, "unknown mode %d", o.mode);
   if (o.out_table_slots != 0 && (o.out_table_slots < 2 || (o.out_table_slots & (o.out_table_slots - 1))))
     return fail(SPTC_ERR_INVALID_ARG, "out_table_slots %lld is not a power of two >= 2",
                 (long long)o.out_table_slots);
@@ -254,76 +284,183 @@ sptc_status status_from_bits(uint32_t err) {
   return SPTC_OK;
 }
 
-sptc_status plan_body(sptc_plan_s* P, const sptc_coo* X, const sptc_coo* Y, const int32_t* cx, const int32_t* cy) {
-  const hipStream_t s = P->stream;
-  // Y table sized from the number of distinct keys it can hold.
-  std::vector<int32_t> cyv(cy, cy + P->nc), cxv(cx, cx + P->nc);
-  const int64_t key_space = sat_prod(Y->dims, cyv);
-  const int64_t y_bound = std::min<int64_t>(P->ny, key_space);
-  P->ytab_slots = pow2_at_least((double)y_bound / P->opt.load_factor);
-  P->max_probe_y = P->opt.max_probe > 0 ? P->opt.max_probe : (int32_t)std::min<int64_t>(P->ytab_slots, 1 << 30);
+sptc_status read_status(sptc_plan_s* P, DevStatus* host) {
+  HIP_TRY(hipMemcpyAsync(host, P->st, sizeof *host, hipMemcpyDeviceToHost, P->stream));
+  HIP_TRY(hipStreamSynchronize(P->stream));
+  return status_from_bits(host->err);
+}
 
+int64_t out_cells(const sptc_plan_s* P) {
+  int64_t cells = 1;
+  for (int32_t m = 0; m < P->out_order; ++m) {
+    if (cells > ((int64_t)1 << 62) / P->out_dims[m]) return (int64_t)1 << 62;
+    cells *= P->out_dims[m];
+  }
+  return cells;
+}
+
+// Output hash for the products that are accumulated in device memory.
+sptc_status size_out_table(sptc_plan_s* P, int64_t products) {
+  const int64_t bound = std::min<int64_t>(products, out_cells(P));
+  if (P->opt.out_table_slots > 0)
+    P->ztab_slots = P->opt.out_table_slots;
+  else
+    P->ztab_slots = pow2_at_least((double)bound / P->opt.load_factor);
+  P->max_probe_z = P->opt.max_probe > 0 ? P->opt.max_probe : (int32_t)std::min<int64_t>(P->ztab_slots, 1 << 30);
   sptc_status st;
-  if ((st = P->allocate_n(P->ytab_slots, &P->ytab))) return st;
-  if ((st = P->allocate_n(P->ny, &P->yg))) return st;
-  if ((st = P->allocate_n(P->nx, &P->xrec))) return st;
-  if ((st = P->allocate_n(P->nx, &P->xg))) return st;
-  if ((st = P->allocate_n(P->nx, &P->xcnt))) return st;
-  if ((st = P->allocate_n(P->nx + 1, &P->poff))) return st;
-  const int64_t tiles = std::max<int64_t>(scan_tiles(P->ytab_slots), scan_tiles(P->nx));
-  if ((st = P->allocate_n(tiles + 1, &P->tile_sums))) return st;
-  if ((st = P->allocate_n(1, &P->st))) return st;
-  if ((st = P->allocate_n(2, &P->scratch))) return st;
+  if ((st = P->allocate_n(P->ztab_slots, &P->ztab))) return st;
+  if ((st = P->allocate_n(scan_tiles(P->ztab_slots) + 1, &P->ztile_sums))) return st;
+  return SPTC_OK;
+}
 
+// A1-A3: Y grouped by contracting key (both modes).
+sptc_status plan_group_y(sptc_plan_s* P, const sptc_coo* Y) {
+  const hipStream_t s = P->stream;
   const uint64_t ymask = (uint64_t)P->ytab_slots - 1;
   const uint64_t seed = P->opt.hash_seed;
-  HIP_TRY(hipMemsetAsync(P->st, 0, sizeof(DevStatus), s));
   HIP_TRY(mark(P, s, SPTC_STAGE_Y_COUNT, 0));
   HIP_TRY(launch_fill_empty(P->ytab, P->ytab_slots, nullptr, s));
-  HIP_TRY(launch_y_count(Y->idx, P->ny, P->y_c, P->ytab, ymask, seed, P->max_probe_y, P->st, P->num_cus, s));
+  HIP_TRY(launch_key_count(Y->idx, P->ny, P->y_c, P->ytab, ymask, seed, P->max_probe_y, P->st, &P->st->groups,
+                           P->num_cus, s));
   HIP_TRY(mark(P, s, SPTC_STAGE_Y_COUNT, 1));
   HIP_TRY(mark(P, s, SPTC_STAGE_Y_SCAN, 0));
   HIP_TRY(launch_scan_y_table(P->ytab, P->ytab_slots, P->tile_sums, s));
   HIP_TRY(mark(P, s, SPTC_STAGE_Y_SCAN, 1));
   HIP_TRY(mark(P, s, SPTC_STAGE_Y_SCATTER, 0));
+  if (P->yset) HIP_TRY(launch_fill_keys(P->yset, P->yset_slots, s));
   HIP_TRY(launch_y_scatter(Y->idx, Y->val, P->ny, P->y_c, P->y_f, P->yb, P->ytab, ymask, seed, P->max_probe_y,
-                           P->yg, P->st, P->num_cus, s));
+                           P->yg, P->yset, (uint64_t)P->yset_slots - 1, P->bits_fy, P->st, P->num_cus, s));
   HIP_TRY(mark(P, s, SPTC_STAGE_Y_SCATTER, 1));
+  return SPTC_OK;
+}
+
+sptc_status plan_global(sptc_plan_s* P, const sptc_coo* X) {
+  const hipStream_t s = P->stream;
+  const uint64_t ymask = (uint64_t)P->ytab_slots - 1;
+  sptc_status st;
+  if ((st = P->allocate_n(P->nx, &P->xrec))) return st;
+  if ((st = P->allocate_n(P->nx, &P->xg))) return st;
+  if ((st = P->allocate_n(P->nx, &P->xcnt))) return st;
+  if ((st = P->allocate_n(P->nx + 1, &P->poff))) return st;
   HIP_TRY(mark(P, s, SPTC_STAGE_X_PROBE, 0));
-  HIP_TRY(launch_x_probe(X->idx, X->val, P->nx, P->x_c, P->x_f, P->xb, P->ytab, ymask, seed, P->max_probe_y,
-                         P->xrec, P->xg, P->xcnt, P->st, P->num_cus, s));
+  HIP_TRY(launch_x_probe(X->idx, X->val, P->nx, P->x_c, P->x_f, P->xb, P->ytab, ymask, P->opt.hash_seed,
+                         P->max_probe_y, P->xrec, P->xg, P->xcnt, P->st, P->num_cus, s));
   HIP_TRY(mark(P, s, SPTC_STAGE_X_PROBE, 1));
   HIP_TRY(mark(P, s, SPTC_STAGE_P_SCAN, 0));
-  HIP_TRY(launch_scan_products(P->xcnt, P->nx, P->poff, P->tile_sums, P->st, s));
+  HIP_TRY(launch_scan_products(P->xcnt, P->nx, P->poff, P->tile_sums, &P->st->products, s));
+  HIP_TRY(mark(P, s, SPTC_STAGE_P_SCAN, 1));
+  DevStatus host{};
+  if ((st = read_status(P, &host))) return st;
+  P->products = (int64_t)host.products;
+  P->y_groups = (int64_t)host.groups;
+  P->out_bound = std::min<int64_t>(P->products, out_cells(P));
+  P->expand_nx = P->nx;
+  P->expand_products = P->products;
+  return size_out_table(P, P->products);
+}
+
+// X grouped by free key (section 4.1), then its groups sorted into
+// accumulation classes.  Groups too large for LDS are gathered for the
+// device-memory output hash.
+sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
+  const hipStream_t s = P->stream;
+  const uint64_t ymask = (uint64_t)P->ytab_slots - 1;
+  const uint64_t xmask = (uint64_t)P->xtab_slots - 1;
+  const uint64_t seed = P->opt.hash_seed;
+  sptc_status st;
+  if ((st = P->allocate_n(P->xtab_slots, &P->xtab))) return st;
+  if ((st = P->allocate_n(P->nx, &P->groups))) return st;
+  if ((st = P->allocate_n(P->nx, &P->xr))) return st;
+  if ((st = P->allocate_n(P->nx + 1, &P->eoff))) return st;
+  if ((st = P->allocate_n(P->nx, &P->dlist))) return st;
+  if ((st = P->allocate_n(P->nx, &P->wlist))) return st;
+  if ((st = P->allocate_n(P->nx, &P->blist))) return st;
+  if ((st = P->allocate_n(P->nx, &P->glist))) return st;
+  if ((st = P->allocate_n(P->nx + 1, &P->dpos))) return st;
+
+  HIP_TRY(mark(P, s, SPTC_STAGE_X_PROBE, 0));
+  HIP_TRY(launch_fill_empty(P->xtab, P->xtab_slots, nullptr, s));
+  HIP_TRY(launch_key_count(X->idx, P->nx, P->x_f, P->xtab, xmask, seed, P->max_probe_x, P->st, nullptr,
+                           P->num_cus, s));
+  HIP_TRY(launch_scan_x_table(P->xtab, P->xtab_slots, P->groups, P->tile_sums, P->st, s));
+  HIP_TRY(launch_x_scatter(X->idx, X->val, P->nx, P->x_f, P->x_c, P->xb, P->xtab, xmask, P->max_probe_x, P->ytab,
+                           ymask, P->max_probe_y, seed, P->xr, P->st, P->num_cus, s));
+  HIP_TRY(mark(P, s, SPTC_STAGE_X_PROBE, 1));
+  HIP_TRY(mark(P, s, SPTC_STAGE_P_SCAN, 0));
+  HIP_TRY(launch_scan_entries(P->xr, P->nx, P->eoff, P->tile_sums, P->st, s));
+  HIP_TRY(launch_classify(P->groups, P->nx, P->eoff, P->ycells, P->dense, P->dlist, P->wlist, P->blist, P->glist,
+                          P->tile_sums, P->st, s));
+  HIP_TRY(launch_scan_direct(P->groups, P->dlist, P->nx, P->eoff, P->dpos, P->tile_sums, P->st, s));
   HIP_TRY(mark(P, s, SPTC_STAGE_P_SCAN, 1));
 
   DevStatus host{};
-  HIP_TRY(hipMemcpyAsync(&host, P->st, sizeof host, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  if ((st = status_from_bits(host.err))) return st;
+  if ((st = read_status(P, &host))) return st;
   P->products = (int64_t)host.products;
   P->y_groups = (int64_t)host.groups;
+  P->out_bound = std::min<int64_t>(P->products, out_cells(P));
+  P->x_groups = (int64_t)host.xgroups;
+  P->nd = (int64_t)(host.class_lo & 0xffffffffull);
+  P->nw = (int64_t)(host.class_lo >> 32);
+  P->nb = (int64_t)host.class_hi;
+  P->ngl = P->x_groups - P->nd - P->nw - P->nb;
+  P->direct_products = (int64_t)host.direct_products;
+  P->ydup = host.ydup ? 1 : 0;
+  if (P->ngl < 0) return fail(SPTC_ERR_INTERNAL, "group classes do not add up");
+  if ((st = P->allocate_n(P->x_groups, &P->gn))) return st;
+  if ((st = P->allocate_n(P->x_groups, &P->goff))) return st;
+  if ((st = P->allocate_n(scan_tiles(P->nw) + 1, &P->etile_sums))) return st;
+  if (P->ngl == 0) return SPTC_OK;
 
-  // Output hash sized from the exact product count (section 4.3's bound,
-  // over all of X), capped by the number of output cells.
-  std::vector<int32_t> none;
-  int64_t cells = 1;
-  for (int32_t m = 0; m < P->out_order; ++m) {
-    if (cells > ((int64_t)1 << 62) / P->out_dims[m]) {
-      cells = (int64_t)1 << 62;
-      break;
-    }
-    cells *= P->out_dims[m];
+  if ((st = P->allocate_n(P->ngl, &P->gl_eoff))) return st;
+  HIP_TRY(launch_scan_global_entries(P->groups, P->glist, P->ngl, P->gl_eoff, P->tile_sums, P->st, s));
+  if ((st = read_status(P, &host))) return st;
+  P->expand_nx = (int64_t)host.global_entries;
+  if ((st = P->allocate_n(P->expand_nx, &P->xrec))) return st;
+  if ((st = P->allocate_n(P->expand_nx, &P->xg))) return st;
+  if ((st = P->allocate_n(P->expand_nx, &P->xcnt))) return st;
+  if ((st = P->allocate_n(P->expand_nx + 1, &P->poff))) return st;
+  HIP_TRY(launch_gather_global(P->groups, P->glist, P->ngl, P->gl_eoff, P->xr, P->xrec, P->xg, P->xcnt, P->num_cus,
+                               s));
+  HIP_TRY(launch_scan_products(P->xcnt, P->expand_nx, P->poff, P->tile_sums, &P->st->global_products, s));
+  if ((st = read_status(P, &host))) return st;
+  P->expand_products = (int64_t)host.global_products;
+  return size_out_table(P, P->expand_products);
+}
+
+sptc_status plan_body(sptc_plan_s* P, const sptc_coo* X, const sptc_coo* Y, const int32_t* cx, const int32_t* cy) {
+  // Key tables sized from the number of distinct keys they can hold.
+  std::vector<int32_t> cyv(cy, cy + P->nc), fx;
+  for (int32_t m = 0; m < X->order; ++m)
+    if (std::find(cx, cx + P->nc, m) == cx + P->nc) fx.push_back(m);
+  const int64_t y_bound = std::min<int64_t>(P->ny, sat_prod(Y->dims, cyv));
+  P->ytab_slots = pow2_at_least((double)y_bound / P->opt.load_factor);
+  P->max_probe_y = P->opt.max_probe > 0 ? P->opt.max_probe : (int32_t)std::min<int64_t>(P->ytab_slots, 1 << 30);
+  const bool grouped = P->opt.mode == SPTC_MODE_GROUPED;
+  if (grouped) {
+    const int64_t x_bound = std::min<int64_t>(P->nx, sat_prod(X->dims, fx));
+    P->xtab_slots = pow2_at_least((double)x_bound / P->opt.load_factor);
+    P->max_probe_x = P->opt.max_probe > 0 ? P->opt.max_probe : (int32_t)std::min<int64_t>(P->xtab_slots, 1 << 30);
   }
-  P->out_bound = std::min<int64_t>(P->products, cells);
-  if (P->opt.out_table_slots > 0)
-    P->ztab_slots = P->opt.out_table_slots;
-  else
-    P->ztab_slots = pow2_at_least((double)P->out_bound / P->opt.load_factor);
-  P->max_probe_z = P->opt.max_probe > 0 ? P->opt.max_probe : (int32_t)std::min<int64_t>(P->ztab_slots, 1 << 30);
-  if ((st = P->allocate_n(P->ztab_slots, &P->ztab))) return st;
-  if ((st = P->allocate_n(scan_tiles(P->ztab_slots) + 1, &P->ztile_sums))) return st;
-  return SPTC_OK;
+
+  sptc_status st;
+  if ((st = P->allocate_n(P->ytab_slots, &P->ytab))) return st;
+  if ((st = P->allocate_n(P->ny, &P->yg))) return st;
+  const int64_t tiles = std::max<int64_t>({scan_tiles(P->ytab_slots), scan_tiles(P->xtab_slots), scan_tiles(P->nx)});
+  if ((st = P->allocate_n(2 * (tiles + 1), &P->tile_sums))) return st;  // room for pair-valued scans
+  // Y coordinate set (grouped mode): finds repeated Y coordinates, which the
+  // direct class cannot have.  Needs the full Y coordinate in 63 bits.
+  const bool yset = grouped && P->bits_c + P->bits_fy <= 63;
+  if (yset) {
+    P->yset_slots = pow2_at_least((double)std::max<int64_t>(P->ny, 1) / P->opt.load_factor);
+    if ((st = P->allocate_n(P->yset_slots, &P->yset))) return st;
+  }
+  if ((st = P->allocate_n(1, &P->st))) return st;
+  if ((st = P->allocate_n(2, &P->scratch))) return st;
+  HIP_TRY(hipMemsetAsync(P->st, 0, sizeof(DevStatus), P->stream));
+  if (grouped && !yset)  // repeats cannot be ruled out: no direct class
+    HIP_TRY(hipMemsetAsync(reinterpret_cast<char*>(P->st) + offsetof(DevStatus, ydup), 1, 1, P->stream));
+  if ((st = plan_group_y(P, Y))) return st;
+  return grouped ? plan_grouped(P, X) : plan_global(P, X);
 }
 
 }  // namespace
@@ -338,6 +475,7 @@ void sptc_default_options(sptc_options* opt) {
   opt->hash_seed = 0x9e3779b97f4a7c15ull;
   opt->out_table_slots = 0;
   opt->stage_events = nullptr;
+  opt->mode = SPTC_MODE_GROUPED;
 }
 
 sptc_status sptc_plan(sptc_plan_t* plan, const sptc_coo* X, const sptc_coo* Y, int32_t ncontract, const int32_t* cx,
@@ -405,6 +543,10 @@ sptc_status sptc_plan(sptc_plan_t* plan, const sptc_coo* X, const sptc_coo* Y, i
   add_unpack(P->out_unpack, P->y_f, 0);
   add_unpack(P->ykey_unpack, P->y_c, 0);
   add_unpack(P->yfree_unpack, P->y_f, 0);
+  add_unpack(P->ux, P->x_f, 0);
+  add_unpack(P->uy, P->y_f, 0);
+  P->ycells = (uint64_t)sat_prod(Y->dims, fy);
+  P->dense = P->bits_fy <= kDenseBits ? 1 : 0;
   P->xb = make_bounds(X, o.validate);
   P->yb = make_bounds(Y, o.validate);
   if (P->bits_c > 63) {
@@ -456,6 +598,13 @@ sptc_status sptc_plan_info(sptc_plan_t P, sptc_info* info) {
   info->key_bits_contract = P->bits_c;
   info->key_bits_x_free = P->bits_fx;
   info->key_bits_y_free = P->bits_fy;
+  info->mode = P->opt.mode;
+  info->x_groups = P->x_groups;
+  info->direct_groups = P->nd;
+  info->direct_products = P->direct_products;
+  info->wave_groups = P->nw;
+  info->block_groups = P->nb;
+  info->global_groups = P->ngl;
   return SPTC_OK;
 }
 
@@ -467,17 +616,58 @@ sptc_status sptc_execute(sptc_plan_t P, int32_t* out_idx, double* out_val, int64
   if (out_cap > 0 && !out_val) return fail(SPTC_ERR_INVALID_ARG, "out_val is NULL");
   if (out_cap > 0 && P->out_order > 0 && !out_idx) return fail(SPTC_ERR_INVALID_ARG, "out_idx is NULL");
   const hipStream_t s = static_cast<hipStream_t>(stream);
+  if (P->opt.mode == SPTC_MODE_GROUPED) {
+    HIP_TRY(launch_reset_status(P->st, s));
+    GroupArgs a{};
+    a.groups = P->groups;
+    a.xr = P->xr;
+    a.eoff = P->eoff;
+    a.yg = P->yg;
+    a.ny = P->ny;
+    a.ycells = P->ycells;
+    a.seed = P->opt.hash_seed;
+    a.bits_y = P->bits_fy;
+    a.ux = P->ux;
+    a.uy = P->uy;
+    a.gn = P->gn;
+    a.goff = P->goff;
+    a.out_idx = out_idx;
+    a.out_val = out_val;
+    a.out_cap = out_cap;
+    a.st = P->st;
+    HIP_TRY(mark(P, s, SPTC_STAGE_GROUP_COUNT, 0));
+    HIP_TRY(launch_group_wave(a, P->wlist, P->nw, 0, P->num_cus, s));
+    HIP_TRY(mark(P, s, SPTC_STAGE_GROUP_COUNT, 1));
+    HIP_TRY(mark(P, s, SPTC_STAGE_GROUP_FILL, 0));
+    HIP_TRY(launch_scan_group_counts(P->gn, P->wlist, P->nw, (uint64_t)P->direct_products, P->goff, P->etile_sums,
+                                     P->st, s));
+    HIP_TRY(launch_group_wave(a, P->wlist, P->nw, 1, P->num_cus, s));
+    HIP_TRY(mark(P, s, SPTC_STAGE_GROUP_FILL, 1));
+    HIP_TRY(mark(P, s, SPTC_STAGE_DIRECT, 0));
+    HIP_TRY(launch_group_direct(a, P->dlist, P->dpos, P->nd, (uint64_t)P->direct_products, P->num_cus, s));
+    HIP_TRY(mark(P, s, SPTC_STAGE_DIRECT, 1));
+    HIP_TRY(mark(P, s, SPTC_STAGE_BLOCK, 0));
+    HIP_TRY(launch_group_block(a, P->blist, P->nb, P->dense, P->num_cus, s));
+    HIP_TRY(mark(P, s, SPTC_STAGE_BLOCK, 1));
+    if (P->ngl == 0) {
+      HIP_TRY(mark(P, s, SPTC_STAGE_COMPACT, 0));
+      HIP_TRY(launch_finalize(out_nnz, out_cap, P->st, s));
+      HIP_TRY(mark(P, s, SPTC_STAGE_COMPACT, 1));
+      return SPTC_OK;
+    }
+  }
+  const bool grouped = P->opt.mode == SPTC_MODE_GROUPED;
   const uint64_t zmask = (uint64_t)P->ztab_slots - 1;
   HIP_TRY(mark(P, s, SPTC_STAGE_OUT_CLEAR, 0));
-  HIP_TRY(launch_fill_empty(P->ztab, P->ztab_slots, P->st, s));
+  HIP_TRY(launch_fill_empty(P->ztab, P->ztab_slots, grouped ? nullptr : P->st, s));
   HIP_TRY(mark(P, s, SPTC_STAGE_OUT_CLEAR, 1));
   HIP_TRY(mark(P, s, SPTC_STAGE_EXPAND, 0));
-  HIP_TRY(launch_expand_acc(P->poff, P->nx, P->xrec, P->xg, P->yg, P->ny, P->bits_fy, P->ztab, zmask,
-                            P->opt.hash_seed, P->max_probe_z, (uint64_t)P->products, P->st, P->num_cus, s));
+  HIP_TRY(launch_expand_acc(P->poff, P->expand_nx, P->xrec, P->xg, P->yg, P->ny, P->bits_fy, P->ztab, zmask,
+                            P->opt.hash_seed, P->max_probe_z, (uint64_t)P->expand_products, P->st, P->num_cus, s));
   HIP_TRY(mark(P, s, SPTC_STAGE_EXPAND, 1));
   HIP_TRY(mark(P, s, SPTC_STAGE_COMPACT, 0));
-  HIP_TRY(launch_compact(P->ztab, P->ztab_slots, P->out_unpack, out_idx, out_val, out_cap, out_nnz, P->ztile_sums,
-                         P->st, s));
+  HIP_TRY(launch_compact(P->ztab, P->ztab_slots, P->out_unpack, out_idx, out_val, out_cap, out_nnz,
+                         grouped ? &P->st->out_base : nullptr, P->ztile_sums, P->st, s));
   HIP_TRY(mark(P, s, SPTC_STAGE_COMPACT, 1));
   return SPTC_OK;
 }
@@ -545,8 +735,23 @@ sptc_status sptc_plan_y_grouped(sptc_plan_t P, int32_t* free_coords, double* val
   return SPTC_OK;
 }
 
+sptc_status sptc_plan_x_groups(sptc_plan_t P, int32_t* free_coords, int64_t* counts, int64_t* products, int64_t cap,
+                               int64_t* ngroups, void* stream) {
+  if (!P || !ngroups) return fail(SPTC_ERR_INVALID_ARG, "plan or ngroups is NULL");
+  if (P->opt.mode != SPTC_MODE_GROUPED) return fail(SPTC_ERR_INVALID_ARG, "the plan does not group X");
+  *ngroups = P->x_groups;
+  if (P->x_groups > cap)
+    return fail(SPTC_ERR_CAPACITY, "%lld groups exceed cap %lld", (long long)P->x_groups, (long long)cap);
+  if (P->x_groups > 0 && (!counts || !products || (P->ux.n > 0 && !free_coords)))
+    return fail(SPTC_ERR_INVALID_ARG, "output pointer is NULL");
+  HIP_TRY(launch_x_groups(P->groups, P->x_groups, P->eoff, P->ux, free_coords, counts, products, cap,
+                          static_cast<hipStream_t>(stream)));
+  return SPTC_OK;
+}
+
 sptc_status sptc_plan_x_counts(sptc_plan_t P, int64_t* counts, void* stream) {
   if (!P) return fail(SPTC_ERR_INVALID_ARG, "plan is NULL");
+  if (P->opt.mode != SPTC_MODE_GLOBAL) return fail(SPTC_ERR_INVALID_ARG, "per-X counts exist in global mode only");
   if (P->nx > 0 && !counts) return fail(SPTC_ERR_INVALID_ARG, "counts is NULL");
   HIP_TRY(launch_x_counts(P->poff, P->nx, counts, static_cast<hipStream_t>(stream)));
   return SPTC_OK;

@@ -67,13 +67,42 @@ struct alignas(16) XEntry {
   double v;
 };
 
+// A grouped X entry (X grouped by free key): its Y group (start, count) and value.
+struct alignas(16) XRec {
+  unsigned int ystart;
+  unsigned int ycnt;
+  double v;
+};
+
+// An X group: packed X free key, and its run [start, start + count) of XRec.
+struct alignas(16) GroupRec {
+  unsigned long long phi;
+  unsigned int start;
+  unsigned int count;
+};
+
 // Device-side scalars of a plan.
 struct alignas(16) DevStatus {
-  unsigned long long products;  // P
-  unsigned long long groups;    // distinct contracting keys of Y
-  unsigned int err;             // kErr* bits
-  unsigned int pad[3];
+  unsigned long long products;         // P
+  unsigned long long groups;           // distinct contracting keys of Y
+  unsigned long long xgroups;          // distinct free keys of X (grouped path)
+  unsigned long long class_lo;         // direct-class groups (low 32 bits) | wave-class groups (high 32 bits)
+  unsigned long long class_hi;         // block-class groups
+  unsigned long long direct_products;  // products (= outputs) of the direct class
+  unsigned long long global_entries;   // X entries of groups accumulated in the global hash
+  unsigned long long global_products;  // their products
+  unsigned long long out_base;         // output cursor: outputs placed so far
+  unsigned int err;                    // kErr* bits
+  unsigned int ydup;                   // nonzero: Y holds a repeated coordinate
+  unsigned int pad[2];
 };
+
+// Capacities of the LDS accumulators (distinct outputs per X group).
+constexpr int kWaveSlots = 512;    // LDS hash slots per wave
+constexpr int kWaveCap = 358;      // largest distinct-output bound a wave takes (load <= 0.7)
+constexpr int kBlockSlots = 4096;  // LDS hash slots per workgroup
+constexpr int kBlockCap = 2867;    // largest distinct-output bound a workgroup hash takes
+constexpr int kDenseBits = 13;     // dense LDS accumulator when the Y free key has <= 13 bits
 
 // ---- launchers (kernels.hip) ----
 // Each returns the hipError_t of its launch(es); all work goes on `stream`.
@@ -81,8 +110,11 @@ struct alignas(16) DevStatus {
 // Sets every 16-byte slot to {key = kEmpty, 0}; clears st->err when st is given.
 hipError_t launch_fill_empty(void* slots16, int64_t nslots, DevStatus* st, hipStream_t stream);
 
-hipError_t launch_y_count(const int32_t* yidx, int64_t nnz, KeyPack kc, YSlot* tab, uint64_t mask,
-                          uint64_t seed, int32_t max_probe, DevStatus* st, int num_cus, hipStream_t stream);
+// Counts entries per packed key (the modes in kc) in an open-addressing table;
+// *distinct is incremented once per new key.
+hipError_t launch_key_count(const int32_t* idx, int64_t nnz, KeyPack kc, YSlot* tab, uint64_t mask, uint64_t seed,
+                            int32_t max_probe, DevStatus* st, unsigned long long* distinct, int num_cus,
+                            hipStream_t stream);
 
 // Exclusive scan support: tile sums need ceil(n / kScanTile) u64 entries.
 constexpr int kScanBlock = 256;
@@ -93,28 +125,122 @@ inline int64_t scan_tiles(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
 // Y table: count field -> inclusive end offset stored in `start`.
 hipError_t launch_scan_y_table(YSlot* tab, int64_t nslots, unsigned long long* tile_sums, hipStream_t stream);
 
+// Also inserts every full Y coordinate ((contracting key << bits_y) | free
+// key) into yset (kEmpty-filled, yset_mask + 1 slots) when yset is given, and
+// sets st->ydup on a repeat.
 hipError_t launch_y_scatter(const int32_t* yidx, const double* yval, int64_t nnz, KeyPack kc, KeyPack kf,
                             Bounds b, YSlot* tab, uint64_t mask, uint64_t seed, int32_t max_probe, YEntry* yg,
-                            DevStatus* st, int num_cus, hipStream_t stream);
+                            unsigned long long* yset, uint64_t yset_mask, int32_t bits_y, DevStatus* st, int num_cus,
+                            hipStream_t stream);
+
+// Sets n 8-byte words to kEmpty.
+hipError_t launch_fill_keys(unsigned long long* keys, int64_t n, hipStream_t stream);
 
 hipError_t launch_x_probe(const int32_t* xidx, const double* xval, int64_t nnz, KeyPack kc, KeyPack kf, Bounds b,
                           const YSlot* tab, uint64_t mask, uint64_t seed, int32_t max_probe, XEntry* xrec,
                           uint32_t* xg, uint32_t* xcnt, DevStatus* st, int num_cus, hipStream_t stream);
 
-// poff[i] = sum of xcnt[0..i), poff[n] = P, and P also into st->products.
+// poff[i] = sum of xcnt[0..i), poff[n] = total, and the total also into *total.
 hipError_t launch_scan_products(const uint32_t* xcnt, int64_t n, unsigned long long* poff,
-                                unsigned long long* tile_sums, DevStatus* st, hipStream_t stream);
+                                unsigned long long* tile_sums, unsigned long long* total, hipStream_t stream);
 
 hipError_t launch_expand_acc(const unsigned long long* poff, int64_t nx, const XEntry* xrec, const uint32_t* xg,
                              const YEntry* yg, int64_t ny, int32_t bits_y, ZSlot* tab, uint64_t mask, uint64_t seed,
                              int32_t max_probe, uint64_t products, DevStatus* st, int num_cus,
                              hipStream_t stream);
 
-// Two-pass compaction of the output hash to COO; writes nnz (or the negated
-// status on error) to *out_nnz.
+// Two-pass compaction of the output hash to COO, written from position
+// *base (0 when base is NULL); writes *base + nnz (or the negated status on
+// error) to *out_nnz.
 hipError_t launch_compact(const ZSlot* tab, int64_t nslots, KeyUnpack ku, int32_t* out_idx, double* out_val,
-                          int64_t out_cap, int64_t* out_nnz, unsigned long long* tile_sums, DevStatus* st,
-                          hipStream_t stream);
+                          int64_t out_cap, int64_t* out_nnz, const unsigned long long* base,
+                          unsigned long long* tile_sums, DevStatus* st, hipStream_t stream);
+
+// ---- grouped path (grouped.hip) ----
+
+// X table (keyed by X free key) -> dense group records; the table's start
+// field becomes each group's end offset for the scatter.
+hipError_t launch_scan_x_table(YSlot* tab, int64_t nslots, GroupRec* groups, void* tile_sums, DevStatus* st,
+                               hipStream_t stream);
+
+// Scatter X into its groups, probing Y's table for every entry.
+hipError_t launch_x_scatter(const int32_t* xidx, const double* xval, int64_t nnz, KeyPack kf, KeyPack kc, Bounds b,
+                            YSlot* xtab, uint64_t xmask, int32_t max_probe_x, const YSlot* ytab, uint64_t ymask,
+                            int32_t max_probe_y, uint64_t seed, XRec* xr, DevStatus* st, int num_cus,
+                            hipStream_t stream);
+
+// eoff[i] = products of grouped X entries before i; eoff[n] = P.
+hipError_t launch_scan_entries(const XRec* xr, int64_t n, unsigned long long* eoff, void* tile_sums, DevStatus* st,
+                               hipStream_t stream);
+
+// Sorts groups into direct / wave / block / global accumulation classes
+// (lists of group ids); counts land in st->class_lo / class_hi.
+hipError_t launch_classify(const GroupRec* groups, int64_t max_groups, const unsigned long long* eoff,
+                           uint64_t ycells, int32_t dense, uint32_t* dlist, uint32_t* wlist, uint32_t* blist,
+                           uint32_t* glist, void* tile_sums, DevStatus* st, hipStream_t stream);
+
+// dpos[i] = products of direct-class groups before list entry i; dpos[nd] and
+// st->direct_products = their total.  Scans max_groups entries, bounded on
+// the device by the direct count.
+hipError_t launch_scan_direct(const GroupRec* groups, const uint32_t* dlist, int64_t max_groups,
+                              const unsigned long long* eoff, unsigned long long* dpos, void* tile_sums,
+                              DevStatus* st, hipStream_t stream);
+
+// Entries of the global-class groups, gathered for the global hash.
+hipError_t launch_scan_global_entries(const GroupRec* groups, const uint32_t* glist, int64_t ngl,
+                                      unsigned long long* gl_eoff, void* tile_sums, DevStatus* st,
+                                      hipStream_t stream);
+hipError_t launch_gather_global(const GroupRec* groups, const uint32_t* glist, int64_t ngl,
+                                const unsigned long long* gl_eoff, const XRec* xr, XEntry* xrec, uint32_t* xg,
+                                uint32_t* xcnt, int num_cus, hipStream_t stream);
+
+// Per-group accumulation in LDS.  fill = 0: count each group's outputs into
+// gn[g]; fill = 1: write them from goff[g].
+struct GroupArgs {
+  const GroupRec* groups;
+  const XRec* xr;
+  const unsigned long long* eoff;
+  const YEntry* yg;
+  int64_t ny;
+  uint64_t ycells;
+  uint64_t seed;
+  int32_t bits_y;
+  KeyUnpack ux;  // X free key -> X free coordinates (output rows 0..)
+  KeyUnpack uy;  // Y free key -> Y free coordinates (following rows)
+  uint32_t* gn;
+  const unsigned long long* goff;
+  int32_t* out_idx;
+  double* out_val;
+  int64_t out_cap;
+  DevStatus* st;
+};
+hipError_t launch_group_wave(const GroupArgs& a, const uint32_t* wlist, int64_t nw, int fill, int num_cus,
+                             hipStream_t stream);
+
+// Block class, single pass: each workgroup accumulates a group, reserves its
+// outputs with one atomic on st->out_base and writes them.
+hipError_t launch_group_block(const GroupArgs& a, const uint32_t* blist, int64_t nb, int dense, int num_cus,
+                              hipStream_t stream);
+
+// Direct class: single-entry groups against a Y without repeated coordinates
+// have one output per product; writes output q for product q in [0, nprod).
+hipError_t launch_group_direct(const GroupArgs& a, const uint32_t* dlist, const unsigned long long* dpos, int64_t nd,
+                               uint64_t nprod, int num_cus, hipStream_t stream);
+
+// goff[g] = base + outputs of wave-list groups before g; st->out_base = base
+// + their total.
+hipError_t launch_scan_group_counts(const uint32_t* gn, const uint32_t* wlist, int64_t nw, uint64_t base,
+                                    unsigned long long* goff, void* tile_sums, DevStatus* st, hipStream_t stream);
+
+// *out_nnz = st->out_base, or the negated status.
+hipError_t launch_finalize(int64_t* out_nnz, int64_t out_cap, DevStatus* st, hipStream_t stream);
+
+// Clears st->err and st->out_base.
+hipError_t launch_reset_status(DevStatus* st, hipStream_t stream);
+
+// Inspection: group g's X free coordinates ([nfx][cap]), entry count and product count.
+hipError_t launch_x_groups(const GroupRec* groups, int64_t ng, const unsigned long long* eoff, KeyUnpack ku,
+                           int32_t* coords, int64_t* counts, int64_t* products, int64_t cap, hipStream_t stream);
 
 // Inspection helpers.
 hipError_t launch_y_groups(const YSlot* tab, int64_t nslots, KeyUnpack ku, int32_t* key_coords, int64_t* counts,

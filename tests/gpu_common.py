@@ -20,14 +20,21 @@ def to_device(p):
     return sptc.DeviceCoo.from_host(p.X), sptc.DeviceCoo.from_host(p.Y)
 
 
-def run_gpu(p, options=None, allocator="pool"):
+MODES = {"grouped": 0, "global": 1}
+
+
+def run_gpu(p, options=None, allocator="pool", mode=None):
     """Plan + execute on cuda:0; returns (plan info dict, idx numpy, val numpy)."""
     import paper_2410_10094_amd as sptc
     X, Y = to_device(p)
+    if mode is not None:
+        options = options or sptc.default_options()
+        options.mode = MODES[mode]
     with sptc.plan(X, Y, p.cx, p.cy, options=options, allocator=allocator) as pl:
         idx, val = pl.execute()
         info = dict(products=pl.products, out_nnz_bound=pl.out_nnz_bound, y_groups=pl.y_groups,
-                    out_order=pl.out_order, out_dims=pl.out_dims, out_table_slots=pl.out_table_slots)
+                    out_order=pl.out_order, out_dims=pl.out_dims, out_table_slots=pl.out_table_slots,
+                    mode=pl.mode, x_groups=pl.x_groups, classes=pl.group_classes)
         return info, idx.cpu().numpy(), val.cpu().numpy()
 
 

@@ -42,10 +42,11 @@ def _problems():
 PROBLEMS = _problems()
 
 
+@pytest.mark.parametrize("mode", ["grouped", "global"])
 @pytest.mark.parametrize("p", PROBLEMS, ids=lambda p: p.name)
-def test_parity_against_oracle(p):
-    log(f"[parity] {p.name} nnz {p.X.nnz}x{p.Y.nnz} cx={p.cx} cy={p.cy}")
-    info, gidx, gval = run_gpu(p)
+def test_parity_against_oracle(p, mode):
+    log(f"[parity] {p.name} {mode} nnz {p.X.nnz}x{p.Y.nnz} cx={p.cx} cy={p.cy}")
+    info, gidx, gval = run_gpu(p, mode=mode)
     per_x, total = oracle.match_counts(p.X, p.Y, p.cx, p.cy)
     assert info["products"] == total
     ref = assert_parity(p, gidx, gval)
@@ -83,19 +84,112 @@ def test_stage_y_groups_and_grouped_array():
 
 
 def test_stage_x_probe_counts():
-    """Pass 1: per-X product counts equal the oracle's match counts exactly,
-    and P is their sum."""
+    """Pass 1 (global mode): per-X product counts equal the oracle's match
+    counts exactly, and P is their sum."""
     import paper_2410_10094_amd as sptc
     for p in [W.plain(), W.imbalanced(nnz_x=100_000, nnz_y=10_000, xdims=(1 << 12, 1 << 10, 1 << 10),
                                       ydims=(1 << 10, 1 << 8, 1 << 6))]:
         log(f"[stage-B] {p.name}")
         X, Y = to_device(p)
-        with sptc.plan(X, Y, p.cx, p.cy) as pl:
+        with sptc.plan(X, Y, p.cx, p.cy, options=sptc.default_options(mode=1)) as pl:
             counts = pl.x_counts().cpu().numpy()
             P = pl.products
         per_x, total = oracle.match_counts(p.X, p.Y, p.cx, p.cy)
         np.testing.assert_array_equal(counts, per_x)
         assert P == total
+
+
+def test_stage_x_groups():
+    """X grouped by free key (section 4.1): one group per distinct X free
+    tuple, with the number of X entries carrying it and the sum of their
+    product counts (the bound of section 4.3), all exact."""
+    import paper_2410_10094_amd as sptc
+    for p in [W.block_sparse(n=24, block=4), W.plain(),
+              W.random_problem(92, 4, 3, 1, 2, 7, 5000, 3000, duplicates=True)]:
+        log(f"[stage-X] {p.name}")
+        X, Y = to_device(p)
+        with sptc.plan(X, Y, p.cx, p.cy) as pl:
+            coords, counts, prods = (t.cpu().numpy() for t in pl.x_groups_table())
+            ng, P = pl.x_groups, pl.products
+        fx = [m for m in range(p.X.order) if m not in p.cx]
+        per_x, total = oracle.match_counts(p.X, p.Y, p.cx, p.cy)
+        keys = [tuple(p.X.idx[fx, e].tolist()) for e in range(p.X.nnz)]
+        want = {}
+        for k, c in zip(keys, per_x.tolist()):
+            n, s_ = want.get(k, (0, 0))
+            want[k] = (n + 1, s_ + c)
+        got = {tuple(coords[:, g].tolist()): (int(counts[g]), int(prods[g])) for g in range(ng)}
+        assert ng == len(want) and got == want
+        assert P == total == int(prods.sum())
+
+
+def _class_problems():
+    """One problem per accumulation class of the grouped path."""
+    rng = np.random.default_rng(33)
+    out = []
+    # direct: single-entry X groups, Y without repeated coordinates
+    out.append(("direct", W.imbalanced(nnz_x=50_000, nnz_y=20_000, xdims=(1 << 12, 1 << 10, 1 << 10),
+                                       ydims=(1 << 10, 1 << 8, 1 << 6))))
+    # wave: groups of ~20 X entries with a few hundred products each
+    out.append(("wave", W.random_problem(34, 3, 3, 1, 1, 1, 1, 1)))
+    X = Coo((16, 8, 32), W.unique_coords(rng, (16, 8, 32), 3000), W.nonzero_uniform(rng, 3000))
+    Y = Coo((32, 20, 20), W.unique_coords(rng, (32, 20, 20), 400), W.nonzero_uniform(rng, 400))
+    out[-1] = ("wave", Problem("wave-groups", X, Y, (2,), (0,)))
+    # block, dense: Y free key of 12 bits, large groups
+    out.append(("block", W.block_sparse(n=16, block=4, p_block=0.6, p_fill=0.8)))
+    # block, hash: Y free key wider than 13 bits, <= 2867 distinct outputs per group
+    X = Coo((200, 40), np.stack([rng.integers(0, 200, 3000), rng.integers(0, 40, 3000)]).astype(np.int32),
+            W.nonzero_uniform(rng, 3000))
+    Y = Coo((40, 1 << 16), np.stack([rng.integers(0, 40, 2000), rng.integers(0, 1 << 16, 2000)]).astype(np.int32),
+            W.nonzero_uniform(rng, 2000))
+    out.append(("block", Problem("block-hash", X, Y, (1,), (0,))))
+    # global: groups with more distinct outputs than a workgroup's LDS holds
+    X = Coo((3, 8), np.stack([rng.integers(0, 3, 200), rng.integers(0, 8, 200)]).astype(np.int32),
+            W.nonzero_uniform(rng, 200))
+    Y = Coo((8, 1 << 20), np.stack([rng.integers(0, 8, 40_000), rng.integers(0, 1 << 20, 40_000)]).astype(np.int32),
+            W.nonzero_uniform(rng, 40_000))
+    out.append(("global_", Problem("global-class", X, Y, (1,), (0,))))
+    # heavy accumulation: tiny Y free space, many products per output
+    X = Coo((4, 64), np.stack([rng.integers(0, 4, 5000), rng.integers(0, 64, 5000)]).astype(np.int32),
+            W.nonzero_uniform(rng, 5000))
+    Y = Coo((64, 3), np.stack([rng.integers(0, 64, 4000), rng.integers(0, 3, 4000)]).astype(np.int32),
+            W.nonzero_uniform(rng, 4000))
+    out.append(("block", Problem("heavy-accumulation", X, Y, (1,), (0,))))
+    # many small entries per group in a block group: product-parallel walk
+    X = Coo((2, 20_000), np.stack([rng.integers(0, 2, 40_000), rng.integers(0, 20_000, 40_000)]).astype(np.int32),
+            W.nonzero_uniform(rng, 40_000))
+    Y = Coo((20_000, 64), np.stack([rng.integers(0, 20_000, 24_000), rng.integers(0, 64, 24_000)]).astype(np.int32),
+            W.nonzero_uniform(rng, 24_000))
+    out.append(("block", Problem("block-product-parallel", X, Y, (1,), (0,))))
+    return out
+
+
+def test_repeated_y_coordinates_disable_direct_class():
+    """With a repeated Y coordinate a single-entry X group can have two
+    products on one output, so the direct class must not be used."""
+    rng = np.random.default_rng(35)
+    X = Coo((1000, 50), W.unique_coords(rng, (1000, 50), 2000), W.nonzero_uniform(rng, 2000))
+    yc = W.unique_coords(rng, (50, 100), 800)
+    yc = np.concatenate([yc, yc[:, :5]], axis=1)  # five coordinates appear twice
+    Y = Coo((50, 100), yc, W.nonzero_uniform(rng, yc.shape[1]))
+    p = Problem("y-repeats", X, Y, (1,), (0,))
+    log("[ydup]")
+    info, gidx, gval = run_gpu(p, mode="grouped")
+    assert info["classes"]["direct"] == 0
+    assert_parity(p, gidx, gval)
+    q = Problem("y-unique", X, Coo((50, 100), yc[:, :800], W.nonzero_uniform(rng, 800)), (1,), (0,))
+    info, gidx, gval = run_gpu(q, mode="grouped")
+    assert info["classes"]["direct"] > 0
+    assert_parity(q, gidx, gval)
+
+
+@pytest.mark.parametrize("cls,p", _class_problems(), ids=lambda v: v if isinstance(v, str) else v.name)
+def test_grouped_accumulation_classes(cls, p):
+    log(f"[class] {cls} {p.name}")
+    info, gidx, gval = run_gpu(p, mode="grouped")
+    assert info["classes"][cls] > 0, info["classes"]
+    assert sum(info["classes"].values()) == info["x_groups"]
+    assert_parity(p, gidx, gval)
 
 
 def _edge_problems():
@@ -137,10 +231,11 @@ def _edge_problems():
     return out
 
 
+@pytest.mark.parametrize("mode", ["grouped", "global"])
 @pytest.mark.parametrize("p", _edge_problems(), ids=lambda p: p.name)
-def test_edge_cases(p):
-    log(f"[edge] {p.name}")
-    info, gidx, gval = run_gpu(p)
+def test_edge_cases(p, mode):
+    log(f"[edge] {p.name} {mode}")
+    info, gidx, gval = run_gpu(p, mode=mode)
     assert_parity(p, gidx, gval)
 
 
@@ -194,7 +289,7 @@ def test_undersized_output_table_reports_capacity():
     p = W.plain(seed=6, n=16, nnz=400)
     log("[tiny-table]")
     X, Y = to_device(p)
-    opt = sptc.default_options(out_table_slots=64)
+    opt = sptc.default_options(out_table_slots=64, mode=1)
     with sptc.plan(X, Y, p.cx, p.cy, options=opt) as pl:
         with pytest.raises(sptc.SptcError) as e:
             pl.execute()
