@@ -81,6 +81,18 @@ def algorithmic_bytes(stage, p, products, nnz_z, x_groups=0, mode="grouped", inf
     return 0
 
 
+def survey_byte_model(p, products, nnz_z):
+    """Whole-step byte model of the survey's plan, which prices a
+    global-hash design: inputs once, grouped Y written and read, pass-1
+    records, 24 B of output-hash traffic per product, and the compaction.  The
+    grouped path keeps the per-product traffic in LDS, so its real HBM bytes
+    are far lower; this figure is kept for comparison only."""
+    nx, ny = p.X.nnz, p.Y.nnz
+    nz_order = p.X.order + p.Y.order - 2 * len(p.cx)
+    return (nx * (4 * p.X.order + 8) + ny * (4 * p.Y.order + 8) + 32 * ny + 16 * nx + 24 * products
+            + nnz_z * (16 + 4 * nz_order + 8))
+
+
 def time_oracle(p, products_total, max_seconds=25.0):
     """The CPU oracle on a bounded sample: a prefix of X against all of Y,
     sized so one run takes about max_seconds at most.  Returns the record."""
@@ -195,10 +207,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="block-sparse", choices=sorted(DESCRIPTIONS))
-    ap.add_argument("--also", default="plain,imbalanced,block-sparse-1.5M",
+    ap.add_argument("--workload", default="block-sparse-1.5M", choices=sorted(DESCRIPTIONS))
+    ap.add_argument("--also", default="block-sparse,imbalanced,plain",
                     help="comma-separated extra workloads reported under 'also' ('' for none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (known bytes for scaling HBM counters) and exit")
     ap.add_argument("--mode", default="grouped", choices=["grouped", "global"],
                     help="accumulation strategy: per-X-group LDS tables (default) or one global hash")
     args = ap.parse_args()
@@ -211,6 +225,16 @@ def main():
 
     import torch
     torch.cuda.set_device(0)
+
+    if args.calibrate_copy:
+        n = args.calibrate_copy * (1 << 20) // 8
+        src = torch.randn(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes_read": n * 8, "calibrate_copy_bytes_written": n * 8, "launches": 3}))
+        return
 
     r = run_workload(args.workload, args.steps, args.warmup, mode=args.mode)
     p = r["problem"]
@@ -240,6 +264,11 @@ def main():
                    "parallelism": "single GPU"},
         "output_nnz_per_s": r["nnz_z"] / r["sec"],
         "roofline": roofline_of(r),
+        "survey_byte_model": {"bytes_per_step": survey_byte_model(p, r["products"], r["nnz_z"]),
+                              "achieved_GBps": round(survey_byte_model(p, r["products"], r["nnz_z"]) / r["sec"] / 1e9,
+                                                     1),
+                              "frac_of_8TBps": round(survey_byte_model(p, r["products"], r["nnz_z"]) / r["sec"]
+                                                     / (HBM_PEAK_GBS * 1e9), 4)},
         "cpu_baseline": cpu,
         "stage_ms": {k: round(v, 4) for k, v in r["stage_ms"].items()},
         "plan": r["info"],

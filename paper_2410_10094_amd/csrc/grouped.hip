@@ -60,6 +60,51 @@ struct FinXGroups {
   __device__ void operator()(unsigned long long total) const { st->xgroups = total & 0xffffffffull; }
 };
 
+// X entry e's record: its Y group (start, count; count 0 when Y has no entry
+// with its contracting key) and its value.
+__device__ __forceinline__ XRec probe_y(const int32_t* __restrict__ xidx, int64_t nnz, int64_t e, const KeyPack& kc,
+                                        const YSlot* __restrict__ ytab, uint64_t ymask, int32_t max_probe_y,
+                                        uint64_t seed, double v) {
+  const uint64_t ckey = pack_key(xidx, nnz, e, kc);
+  uint64_t ys = slot_of(ckey, kc, seed, ymask);
+  XRec r;
+  r.ystart = 0;
+  r.ycnt = 0;
+  r.v = v;
+  for (int32_t probe = 0; probe < max_probe_y; ++probe) {
+    const YSlot slot = ytab[ys];
+    if (slot.key == ckey) {
+      r.ystart = slot.start;
+      r.ycnt = slot.count;
+      break;
+    }
+    if (slot.key == kEmpty) break;
+    ys = (ys + 1) & ymask;
+  }
+  return r;
+}
+
+// The rest of a probe of Y's table whose home slot held another key.
+__device__ __noinline__ XRec probe_y_from(const YSlot* __restrict__ ytab, uint64_t ymask, int32_t max_probe_y,
+                                          uint64_t home, uint64_t ckey, double v) {
+  XRec r;
+  r.ystart = 0;
+  r.ycnt = 0;
+  r.v = v;
+  uint64_t s = home;
+  for (int32_t probe = 1; probe < max_probe_y; ++probe) {
+    s = (s + 1) & ymask;
+    const YSlot cur = ytab[s];
+    if (cur.key == ckey) {
+      r.ystart = cur.start;
+      r.ycnt = cur.count;
+      break;
+    }
+    if (cur.key == kEmpty) break;
+  }
+  return r;
+}
+
 // Places every X entry in its group's run and records its Y group.
 __global__ __launch_bounds__(256) void k_x_scatter(const int32_t* __restrict__ xidx, const double* __restrict__ xval,
                                                    int64_t nnz, KeyPack kf, KeyPack kc, Bounds b,
@@ -70,7 +115,7 @@ __global__ __launch_bounds__(256) void k_x_scatter(const int32_t* __restrict__ x
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
     if (b.check && !coords_ok(xidx, nnz, e, b)) record_error(st, kErrCoord);
     const uint64_t fkey = pack_key(xidx, nnz, e, kf);
-    const int64_t s = find_slot(xtab, fkey, xmask, seed, max_probe_x);
+    const int64_t s = find_slot(xtab, fkey, kf, xmask, seed, max_probe_x);
     if (s < 0) {
       record_error(st, kErrInternal);
       continue;
@@ -80,25 +125,55 @@ __global__ __launch_bounds__(256) void k_x_scatter(const int32_t* __restrict__ x
       record_error(st, kErrInternal);
       continue;
     }
-    const uint64_t ckey = pack_key(xidx, nnz, e, kc);
-    uint64_t ys = fmix64(ckey ^ seed) & ymask;
-    unsigned start = 0, count = 0;
-    for (int32_t probe = 0; probe < max_probe_y; ++probe) {
-      const YSlot slot = ytab[ys];
-      if (slot.key == ckey) {
-        start = slot.start;
-        count = slot.count;
-        break;
-      }
-      if (slot.key == kEmpty) break;
-      ys = (ys + 1) & ymask;
-    }
-    XRec r;
-    r.ystart = start;
-    r.ycnt = count;
-    r.v = xval[e];
-    xr[pos] = r;
+    xr[pos] = probe_y(xidx, nnz, e, kc, ytab, ymask, max_probe_y, seed, xval[e]);
   }
+}
+
+// Aggregated variant for a direct-addressed X table (small X free keys).
+__global__ __launch_bounds__(kAggBlock) void k_x_scatter_agg(const int32_t* __restrict__ xidx,
+                                                             const double* __restrict__ xval, int64_t nnz, KeyPack kf,
+                                                             KeyPack kc, Bounds b, YSlot* __restrict__ xtab,
+                                                             unsigned nslots, const YSlot* __restrict__ ytab,
+                                                             uint64_t ymask, int32_t max_probe_y, uint64_t seed,
+                                                             XRec* __restrict__ xr, DevStatus* st) {
+  extern __shared__ unsigned s_agg[];
+  place_chunk(xidx, nnz, kf, xtab, nslots, s_agg, s_agg + nslots,
+              [&](const int64_t* e, const uint64_t*, const unsigned* pos, const bool* ok) {
+                uint64_t ckey[kAggUnroll], ys[kAggUnroll];
+                YSlot slot[kAggUnroll];
+                double v[kAggUnroll];
+#pragma unroll
+                for (int u = 0; u < kAggUnroll; ++u) {
+                  ckey[u] = ok[u] ? pack_key(xidx, nnz, e[u], kc) : 0ull;
+                  ys[u] = slot_of(ckey[u], kc, seed, ymask);
+                }
+#pragma unroll
+                for (int u = 0; u < kAggUnroll; ++u) {  // first probes and values, all in flight together
+                  if (!ok[u]) continue;
+                  slot[u] = ytab[ys[u]];
+                  v[u] = xval[e[u]];
+                }
+#pragma unroll
+                for (int u = 0; u < kAggUnroll; ++u) {
+                  if (!ok[u]) continue;
+                  if (b.check && !coords_ok(xidx, nnz, e[u], b)) record_error(st, kErrCoord);
+                  if ((int64_t)pos[u] >= nnz) {
+                    record_error(st, kErrInternal);
+                    continue;
+                  }
+                  XRec r;
+                  r.ystart = 0;
+                  r.ycnt = 0;
+                  r.v = v[u];
+                  if (slot[u].key == ckey[u]) {
+                    r.ystart = slot[u].start;
+                    r.ycnt = slot[u].count;
+                  } else if (slot[u].key != kEmpty) {
+                    r = probe_y_from(ytab, ymask, max_probe_y, ys[u], ckey[u], v[u]);
+                  }
+                  xr[pos[u]] = r;
+                }
+              });
 }
 
 struct EntryScanOp {
@@ -249,16 +324,22 @@ __device__ __forceinline__ bool lds_accumulate(ZSlot* tab, unsigned tmask, unsig
   return false;
 }
 
+// Output entry `pos`: X free coordinates from phix, Y free coordinates from
+// phiy, value v.  Streaming stores: the COO is written once and never read
+// here, so it should not displace Y and the tables from the caches.
 __device__ __forceinline__ void write_output(const GroupArgs& a, unsigned long long pos, unsigned long long phix,
                                              unsigned long long phiy, double v) {
 #pragma unroll
   for (int m = 0; m < kMaxOrder; ++m)
-    if (m < a.ux.n) a.out_idx[(int64_t)m * a.out_cap + (int64_t)pos] = (int32_t)((phix >> a.ux.shift[m]) & a.ux.mask[m]);
+    if (m < a.ux.n)
+      __builtin_nontemporal_store((int32_t)((phix >> a.ux.shift[m]) & a.ux.mask[m]),
+                                  &a.out_idx[(int64_t)m * a.out_cap + (int64_t)pos]);
 #pragma unroll
   for (int m = 0; m < kMaxOrder; ++m)
     if (m < a.uy.n)
-      a.out_idx[(int64_t)(a.ux.n + m) * a.out_cap + (int64_t)pos] = (int32_t)((phiy >> a.uy.shift[m]) & a.uy.mask[m]);
-  a.out_val[pos] = v;
+      __builtin_nontemporal_store((int32_t)((phiy >> a.uy.shift[m]) & a.uy.mask[m]),
+                                  &a.out_idx[(int64_t)(a.ux.n + m) * a.out_cap + (int64_t)pos]);
+  __builtin_nontemporal_store(v, &a.out_val[pos]);
 }
 
 struct WaveScratch {
@@ -347,9 +428,36 @@ __global__ __launch_bounds__(kGBlock) void k_group_wave(GroupArgs a, const uint3
   }
 }
 
+// A dense accumulator cell was reached by some product (see k_group_block).
+__device__ __forceinline__ bool dense_reached(const double* acc, const unsigned char* flag, unsigned s) {
+  return __double_as_longlong(acc[s]) != (long long)0x8000000000000000ull || flag[s] != 0;
+}
+
+// Ascending bitonic sort of a[0, n) in LDS (n a power of two, n <= blockDim.x),
+// one element per thread; every thread of the block must call it.
+__device__ __forceinline__ void bitonic_sort_lds(unsigned long long* a, unsigned n) {
+  const unsigned i = threadIdx.x;
+  for (unsigned k = 2; k <= n; k <<= 1) {
+    for (unsigned j = k >> 1; j > 0; j >>= 1) {
+      const unsigned ixj = i ^ j;
+      if (i < n && ixj > i) {
+        const unsigned long long x = a[i], y = a[ixj];
+        if ((x > y) == ((i & k) == 0)) {
+          a[i] = y;
+          a[ixj] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // Block class: one 1024-thread workgroup per group, accumulating in a dense
-// LDS array indexed by the Y free key (with a presence flag per cell) or in an
-// LDS hash of up to kBlockSlots slots.  When the group's X entries average
+// LDS array indexed by the Y free key or in an LDS hash of up to kBlockSlots
+// slots.  Dense cells start at -0.0: adding any nonzero product leaves a
+// value other than -0.0 (an exact cancellation rounds to +0.0), so a cell was
+// reached iff its bits changed; only a product that is itself zero (a zero
+// input value, or underflow) sets the cell's flag explicitly.  When the group's X entries average
 // many products, each wave walks whole Y runs (coalesced, no search);
 // otherwise the products are spread over all threads by a search over the
 // staged entry offsets.  Then the group's outputs are counted, reserved with
@@ -380,7 +488,7 @@ __global__ __launch_bounds__(kBBlock) void k_group_block(GroupArgs a, const uint
     const unsigned tmask = tsize - 1;
     for (unsigned s = tid; s < tsize; s += kBBlock) {
       if (DENSE) {
-        acc[s] = 0.0;
+        acc[s] = -0.0;
         flag[s] = 0;
       } else {
         tab[s].key = kEmpty;
@@ -393,24 +501,84 @@ __global__ __launch_bounds__(kBBlock) void k_group_block(GroupArgs a, const uint
       if (DENSE) {
         const unsigned cell = (unsigned)key & tmask;
         atomicAdd(&acc[cell], pv);
-        flag[cell] = 1;
+        if (pv == 0.0) flag[cell] = 1;
       } else if (!lds_accumulate(tab, tmask, key, pv, a.seed)) {
         record_error(a.st, kErrCapacity);
       }
     };
 
     if (b >= 32ull * G.count) {
-      // entry-parallel: a wave per X entry, lanes over its Y run
-      for (unsigned e = wave; e < G.count; e += kWaves) {
-        const XRec r = a.xr[G.start + e];
-        if ((unsigned long long)r.ystart + r.ycnt > (unsigned long long)a.ny) {
-          record_error(a.st, kErrInternal);
-          continue;
+      // entry-parallel.  Entries come in chunks of kBChunk, sorted by the
+      // start of their Y run: every workgroup walks Y in the same order, so
+      // the groups running at once on an XCD read the same Y runs together
+      // and share them through its L2.  Each wave takes kEU entries at a time
+      // (kEU independent loads in flight per lane); the waves of a workgroup
+      // stay within kWaves * kEU consecutive entries of the sorted order.
+      constexpr unsigned kEU = DENSE ? 8 : 4;
+      for (unsigned base = 0; base < G.count; base += kBChunk) {
+        const unsigned n = G.count - base < (unsigned)kBChunk ? G.count - base : (unsigned)kBChunk;
+        unsigned long long key = ~0ull;
+        if (tid < n) {
+          XRec r = a.xr[G.start + base + tid];
+          if ((unsigned long long)r.ystart + r.ycnt > (unsigned long long)a.ny) {
+            record_error(a.st, kErrInternal);
+            r.ycnt = 0;
+          }
+          s_ys[tid] = r.ycnt;
+          s_v[tid] = r.v;
+          key = ((unsigned long long)r.ystart << 32) | tid;
         }
-        for (unsigned j = lane; j < r.ycnt; j += 64) {
-          const YEntry ye = a.yg[r.ystart + j];
-          accumulate(ye.phi, __dmul_rn(r.v, ye.v));
+        s_off[tid] = key;
+        __syncthreads();
+        unsigned nsort = 2;
+        while (nsort < n) nsort <<= 1;
+        bitonic_sort_lds(s_off, nsort);
+        for (unsigned r0 = wave; r0 < n; r0 += kWaves * kEU) {
+          unsigned ys[kEU], cnt[kEU];
+          double xv[kEU];
+          unsigned m = 0;
+#pragma unroll
+          for (unsigned u = 0; u < kEU; ++u) {
+            const unsigned rank = r0 + u * kWaves;
+            cnt[u] = 0;
+            ys[u] = 0;
+            xv[u] = 0.0;
+            if (rank < n) {
+              const unsigned long long k = s_off[rank];
+              const unsigned li = (unsigned)(k & 0xffffffffull);
+              ys[u] = (unsigned)(k >> 32);
+              cnt[u] = s_ys[li];
+              xv[u] = s_v[li];
+            }
+            m = cnt[u] > m ? cnt[u] : m;
+          }
+          if (DENSE) {  // compact copy of Y: 10 bytes per product
+            for (unsigned j = lane; j < m; j += 64) {
+              unsigned yk[kEU];
+              double yv[kEU];
+#pragma unroll
+              for (unsigned u = 0; u < kEU; ++u)
+                if (j < cnt[u]) {
+                  yk[u] = a.ykey16[ys[u] + j];
+                  yv[u] = a.yval[ys[u] + j];
+                }
+#pragma unroll
+              for (unsigned u = 0; u < kEU; ++u)
+                if (j < cnt[u]) accumulate(yk[u], __dmul_rn(xv[u], yv[u]));
+            }
+          } else {
+            for (unsigned j = lane; j < m; j += 64) {
+              YEntry ye[kEU];
+#pragma unroll
+              for (unsigned u = 0; u < kEU; ++u)
+                if (j < cnt[u]) ye[u] = a.yg[ys[u] + j];
+#pragma unroll
+              for (unsigned u = 0; u < kEU; ++u)
+                if (j < cnt[u]) accumulate(ye[u].phi, __dmul_rn(xv[u], ye[u].v));
+            }
+          }
         }
+        __syncthreads();
       }
     } else {
       // product-parallel over chunks of kBChunk entries
@@ -455,7 +623,8 @@ __global__ __launch_bounds__(kBBlock) void k_group_block(GroupArgs a, const uint
 
     // count, reserve, write
     unsigned long long n = 0;
-    for (unsigned s = tid; s < tsize; s += kBBlock) n += DENSE ? (flag[s] ? 1u : 0u) : (tab[s].key != kEmpty ? 1u : 0u);
+    for (unsigned s = tid; s < tsize; s += kBBlock)
+      n += DENSE ? (dense_reached(acc, flag, s) ? 1u : 0u) : (tab[s].key != kEmpty ? 1u : 0u);
     n = block_sum<kBBlock>(n, s_wave);
     if (tid == 0) s_base = atomicAdd(&a.st->out_base, n);
     __syncthreads();
@@ -467,7 +636,7 @@ __global__ __launch_bounds__(kBBlock) void k_group_block(GroupArgs a, const uint
       unsigned long long key;
       double val;
       if (DENSE) {
-        occ = flag[s] != 0;
+        occ = dense_reached(acc, flag, s);
         key = s;
         val = acc[s];
       } else {
@@ -488,18 +657,23 @@ __global__ __launch_bounds__(kBBlock) void k_group_block(GroupArgs a, const uint
   }
 }
 
-// Direct class: output q is product q of the direct list.  Product-space
-// tiles stage the slice of dpos they overlap in LDS; each lane finds its
-// group by binary search there.  Lanes take consecutive products, so the Y
-// loads and the COO stores coalesce.
+// Direct class: output q is product q of the direct list.  A product-space
+// tile finds the groups it overlaps, stages their offsets, X records and free
+// keys in LDS, and each lane maps its products to groups by binary search
+// there.  Lanes take consecutive products, so the Y loads and the COO stores
+// coalesce; each lane keeps kDItems Y loads in flight.
 constexpr int kDBlock = 256;
 constexpr int kDItems = 8;
 constexpr int kDTile = kDBlock * kDItems;
+constexpr int kDGroups = 1024;  // groups staged per tile; more fall back to global loads
 
 __global__ __launch_bounds__(kDBlock) void k_group_direct(GroupArgs a, const uint32_t* __restrict__ dlist,
                                                           const unsigned long long* __restrict__ dpos, int64_t nd,
                                                           uint64_t nprod) {
-  __shared__ unsigned long long s_pos[kDTile + 1];
+  __shared__ unsigned long long s_pos[kDGroups + 1];
+  __shared__ unsigned long long s_phi[kDGroups];
+  __shared__ double s_v[kDGroups];
+  __shared__ unsigned s_ys[kDGroups];
   __shared__ int64_t s_range[2];
   const uint64_t ntiles = (nprod + kDTile - 1) / kDTile;
   for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -510,15 +684,27 @@ __global__ __launch_bounds__(kDBlock) void k_group_direct(GroupArgs a, const uin
     __syncthreads();
     const int64_t ilo = s_range[0], ihi = s_range[1];
     const int64_t nloc = ihi - ilo + 1;
-    const bool staged = nloc <= kDTile;
-    if (staged)
-      for (int64_t k = threadIdx.x; k <= nloc; k += kDBlock) s_pos[k] = dpos[ilo + k];
+    const bool staged = nloc <= kDGroups;
+    if (staged) {
+      for (int64_t k = threadIdx.x; k < nloc; k += kDBlock) {
+        const GroupRec G = a.groups[dlist[ilo + k]];
+        const XRec r = a.xr[G.start];
+        s_pos[k] = dpos[ilo + k];
+        s_phi[k] = G.phi;
+        s_v[k] = r.v;
+        s_ys[k] = r.ystart;
+      }
+      if (threadIdx.x == 0) s_pos[nloc] = dpos[ihi + 1];
+    }
     __syncthreads();
+    unsigned long long ys[kDItems], phx[kDItems];
+    double xv[kDItems];
+    YEntry ye[kDItems];
+#pragma unroll
     for (int it = 0; it < kDItems; ++it) {
       const uint64_t q = p0 + (uint64_t)it * kDBlock + threadIdx.x;
-      if (q >= p1) break;
-      int64_t li;
-      unsigned long long qs;
+      ys[it] = ~0ull;
+      if (q >= p1) continue;
       if (staged) {
         int lo = 0, hi = (int)nloc - 1;
         while (lo < hi) {
@@ -528,21 +714,72 @@ __global__ __launch_bounds__(kDBlock) void k_group_direct(GroupArgs a, const uin
           else
             hi = mid - 1;
         }
-        li = ilo + lo;
-        qs = s_pos[lo];
+        ys[it] = (unsigned long long)s_ys[lo] + (q - s_pos[lo]);
+        phx[it] = s_phi[lo];
+        xv[it] = s_v[lo];
       } else {
-        li = upper_bound_idx(dpos, ilo, ihi + 1, q) - 1;
-        qs = dpos[li];
+        const int64_t li = upper_bound_idx(dpos, ilo, ihi + 1, q) - 1;
+        const GroupRec G = a.groups[dlist[li]];
+        const XRec r = a.xr[G.start];
+        ys[it] = (unsigned long long)r.ystart + (q - dpos[li]);
+        phx[it] = G.phi;
+        xv[it] = r.v;
       }
-      const GroupRec G = a.groups[dlist[li]];
-      const XRec r = a.xr[G.start];
-      const unsigned long long y = (unsigned long long)r.ystart + (q - qs);
-      if (y >= (unsigned long long)a.ny) {
+      if (ys[it] >= (unsigned long long)a.ny) {
         record_error(a.st, kErrInternal);
-        continue;
+        ys[it] = ~0ull;
       }
-      const YEntry ye = a.yg[y];
-      if ((int64_t)q < a.out_cap) write_output(a, q, G.phi, ye.phi, __dmul_rn(r.v, ye.v));
+    }
+#pragma unroll
+    for (int it = 0; it < kDItems; ++it)
+      if (ys[it] != ~0ull) ye[it] = a.yg[ys[it]];
+#pragma unroll
+    for (int it = 0; it < kDItems; ++it) {
+      const uint64_t q = p0 + (uint64_t)it * kDBlock + threadIdx.x;
+      if (ys[it] != ~0ull && (int64_t)q < a.out_cap)
+        write_output(a, q, phx[it], ye[it].phi, __dmul_rn(xv[it], ye[it].v));
+    }
+    __syncthreads();
+  }
+}
+
+// Sorts each Y run (a Y group's entries in the grouped array) of 2..1024
+// entries by Y free key, one workgroup per Y table slot.  Order within a run
+// is free (section 4.1.3); sorted runs let the lanes of a wave that walk a run
+// hit consecutive dense accumulator cells, i.e. distinct LDS banks.
+__global__ __launch_bounds__(kBBlock) void k_sort_y_runs(const YSlot* __restrict__ ytab, int64_t nslots,
+                                                         YEntry* __restrict__ yg, int64_t ny,
+                                                         uint16_t* __restrict__ ykey16, double* __restrict__ yval) {
+  __shared__ unsigned long long s_key[kBBlock];
+  __shared__ YEntry s_ent[kBBlock];
+  for (int64_t slot = blockIdx.x; slot < nslots; slot += gridDim.x) {
+    const YSlot t = ytab[slot];
+    if (t.key == kEmpty || t.count == 0 || (unsigned long long)t.start + t.count > (unsigned long long)ny)
+      continue;  // uniform across the block
+    const unsigned n = t.count, tid = threadIdx.x;
+    if (n > (unsigned)kBBlock) {  // too long to sort here: copy as is
+      for (unsigned j = tid; j < n; j += kBBlock) {
+        const YEntry e = yg[t.start + j];
+        ykey16[t.start + j] = (uint16_t)e.phi;
+        yval[t.start + j] = e.v;
+      }
+      continue;
+    }
+    unsigned long long key = ~0ull;
+    if (tid < n) {
+      s_ent[tid] = yg[t.start + tid];
+      key = (s_ent[tid].phi << 11) | tid;  // phi has <= kDenseBits bits here; tid < 2048
+    }
+    s_key[tid] = key;
+    __syncthreads();
+    unsigned nsort = 2;
+    while (nsort < n) nsort <<= 1;
+    bitonic_sort_lds(s_key, nsort);
+    if (tid < n) {
+      const YEntry e = s_ent[(unsigned)(s_key[tid] & 2047ull)];
+      yg[t.start + tid] = e;
+      ykey16[t.start + tid] = (uint16_t)e.phi;
+      yval[t.start + tid] = e.v;
     }
     __syncthreads();
   }
@@ -611,6 +848,16 @@ hipError_t launch_x_scatter(const int32_t* xidx, const double* xval, int64_t nnz
   if (nnz <= 0) return hipSuccess;
   k_x_scatter<<<grid_for(nnz, 256, num_cus), 256, 0, stream>>>(xidx, xval, nnz, kf, kc, b, xtab, xmask, max_probe_x,
                                                                 ytab, ymask, max_probe_y, seed, xr, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_x_scatter_agg(const int32_t* xidx, const double* xval, int64_t nnz, KeyPack kf, KeyPack kc,
+                                Bounds b, YSlot* xtab, unsigned nslots, const YSlot* ytab, uint64_t ymask,
+                                int32_t max_probe_y, uint64_t seed, XRec* xr, DevStatus* st, hipStream_t stream) {
+  if (nnz <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)((nnz + kAggChunk - 1) / kAggChunk);
+  k_x_scatter_agg<<<grid, kAggBlock, (size_t)nslots * 8, stream>>>(xidx, xval, nnz, kf, kc, b, xtab, nslots, ytab,
+                                                                    ymask, max_probe_y, seed, xr, st);
   return hipGetLastError();
 }
 
@@ -694,6 +941,14 @@ hipError_t launch_group_direct(const GroupArgs& a, const uint32_t* dlist, const 
 hipError_t launch_scan_group_counts(const uint32_t* gn, const uint32_t* wlist, int64_t nw, uint64_t base,
                                     unsigned long long* goff, void* tile_sums, DevStatus* st, hipStream_t stream) {
   return device_scan(ListScanOp{gn, wlist, goff, base}, nw, tile_sums, FinOutBase{st, base}, stream);
+}
+
+hipError_t launch_sort_y_runs(const YSlot* ytab, int64_t nslots, YEntry* yg, int64_t ny, uint16_t* ykey16,
+                              double* yval, int num_cus, hipStream_t stream) {
+  if (nslots <= 0 || ny <= 0) return hipSuccess;
+  int64_t grid = nslots < (int64_t)num_cus * 2 ? nslots : (int64_t)num_cus * 2;
+  k_sort_y_runs<<<dim3((unsigned)grid), kBBlock, 0, stream>>>(ytab, nslots, yg, ny, ykey16, yval);
+  return hipGetLastError();
 }
 
 hipError_t launch_finalize(int64_t* out_nnz, int64_t out_cap, DevStatus* st, hipStream_t stream) {

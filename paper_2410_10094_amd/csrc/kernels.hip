@@ -37,7 +37,7 @@ __global__ __launch_bounds__(256) void k_key_count(const int32_t* __restrict__ i
                                                    unsigned long long* distinct) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
     const uint64_t key = pack_key(idx, nnz, e, kc);
-    uint64_t s = fmix64(key ^ seed) & mask;
+    uint64_t s = slot_of(key, kc, seed, mask);
     int32_t probe = 0;
     for (;;) {
       const unsigned long long prev = atomicCAS(&tab[s].key, (unsigned long long)kEmpty, (unsigned long long)key);
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(256) void k_y_scatter(const int32_t* __restrict__ y
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
     if (b.check && !coords_ok(yidx, nnz, e, b)) record_error(st, kErrCoord);
     const uint64_t key = pack_key(yidx, nnz, e, kc);
-    const int64_t s = find_slot(tab, key, mask, seed, max_probe);
+    const int64_t s = find_slot(tab, key, kc, mask, seed, max_probe);
     if (s < 0) {
       record_error(st, kErrInternal);
       continue;
@@ -120,7 +120,7 @@ __global__ __launch_bounds__(256) void k_x_probe(const int32_t* __restrict__ xid
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
     if (b.check && !coords_ok(xidx, nnz, e, b)) record_error(st, kErrCoord);
     const uint64_t key = pack_key(xidx, nnz, e, kc);
-    uint64_t s = fmix64(key ^ seed) & mask;
+    uint64_t s = slot_of(key, kc, seed, mask);
     unsigned start = 0, count = 0;
     for (int32_t probe = 0; probe < max_probe; ++probe) {
       const YSlot slot = tab[s];
@@ -259,8 +259,10 @@ struct OccupancyOp {
     const ZSlot z = tab[i];
 #pragma unroll
     for (int m = 0; m < kMaxOutOrder; ++m)
-      if (m < ku.n) out_idx[(int64_t)m * out_cap + (int64_t)pos] = (int32_t)((z.key >> ku.shift[m]) & ku.mask[m]);
-    out_val[pos] = z.val;
+      if (m < ku.n)
+        __builtin_nontemporal_store((int32_t)((z.key >> ku.shift[m]) & ku.mask[m]),
+                                    &out_idx[(int64_t)m * out_cap + (int64_t)pos]);
+    __builtin_nontemporal_store(z.val, &out_val[pos]);
   }
 };
 
@@ -321,6 +323,70 @@ __global__ void k_x_counts(const unsigned long long* __restrict__ poff, int64_t 
     counts[e] = (int64_t)(poff[e + 1] - poff[e]);
 }
 
+
+// ---------------------------------------------------------------------------
+// Direct-addressed small-key tables, aggregated per workgroup in LDS
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kAggBlock) void k_key_count_agg(const int32_t* __restrict__ idx, int64_t nnz, KeyPack kc,
+                                                             YSlot* __restrict__ tab, unsigned nslots,
+                                                             unsigned long long* distinct) {
+  extern __shared__ unsigned s_cnt[];
+  for (unsigned s = threadIdx.x; s < nslots; s += kAggBlock) s_cnt[s] = 0u;
+  __syncthreads();
+  for_chunk_batches(idx, nnz, kc, [&](const int64_t*, const uint64_t* keys, const bool* ok) {
+#pragma unroll
+    for (int u = 0; u < kAggUnroll; ++u)
+      if (ok[u]) atomicAdd(&s_cnt[(unsigned)keys[u]], 1u);
+  });
+  __syncthreads();
+  for (unsigned s = threadIdx.x; s < nslots; s += kAggBlock) {
+    const unsigned c = s_cnt[s];
+    if (!c) continue;
+    tab[s].key = s;  // every writer stores the same key
+    const unsigned prev = atomicAdd(&tab[s].count, c);
+    if (prev == 0u && distinct) atomicAdd(distinct, 1ull);
+  }
+}
+
+__global__ __launch_bounds__(kAggBlock) void k_y_scatter_agg(const int32_t* __restrict__ yidx,
+                                                             const double* __restrict__ yval, int64_t nnz, KeyPack kc,
+                                                             KeyPack kf, Bounds b, YSlot* __restrict__ tab,
+                                                             unsigned nslots, YEntry* __restrict__ yg,
+                                                             unsigned long long* __restrict__ yset,
+                                                             uint64_t yset_mask, uint64_t seed, int32_t bits_y,
+                                                             DevStatus* st) {
+  extern __shared__ unsigned s_agg[];
+  place_chunk(yidx, nnz, kc, tab, nslots, s_agg, s_agg + nslots,
+              [&](const int64_t* e, const uint64_t* keys, const unsigned* pos, const bool* ok) {
+                bool good[kAggUnroll];
+                unsigned long long full[kAggUnroll];
+#pragma unroll
+                for (int u = 0; u < kAggUnroll; ++u) {
+                  good[u] = ok[u];
+                  full[u] = 0ull;
+                  if (!ok[u]) continue;
+                  if (b.check && !coords_ok(yidx, nnz, e[u], b)) record_error(st, kErrCoord);
+                  if ((int64_t)pos[u] >= nnz) {
+                    record_error(st, kErrInternal);
+                    good[u] = false;
+                    continue;
+                  }
+                  YEntry ent;
+                  ent.phi = pack_key(yidx, nnz, e[u], kf);
+                  ent.v = yval[e[u]];
+                  yg[pos[u]] = ent;
+                  full[u] = (keys[u] << bits_y) | ent.phi;
+                }
+                if (yset) {
+                  bool seen[kAggUnroll];
+                  set_insert_batch(yset, yset_mask, seed, full, good, seen);
+#pragma unroll
+                  for (int u = 0; u < kAggUnroll; ++u)
+                    if (seen[u]) st->ydup = 1u;
+                }
+              });
+}
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -355,6 +421,25 @@ hipError_t launch_y_scatter(const int32_t* yidx, const double* yval, int64_t nnz
   if (nnz <= 0) return hipSuccess;
   k_y_scatter<<<grid_for(nnz, 256, num_cus), 256, 0, stream>>>(yidx, yval, nnz, kc, kf, b, tab, mask, seed,
                                                                 max_probe, yg, yset, yset_mask, bits_y, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_key_count_agg(const int32_t* idx, int64_t nnz, KeyPack kc, YSlot* tab, unsigned nslots,
+                                unsigned long long* distinct, hipStream_t stream) {
+  if (nnz <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)((nnz + kAggChunk - 1) / kAggChunk);
+  k_key_count_agg<<<grid, kAggBlock, (size_t)nslots * 4, stream>>>(idx, nnz, kc, tab, nslots, distinct);
+  return hipGetLastError();
+}
+
+hipError_t launch_y_scatter_agg(const int32_t* yidx, const double* yval, int64_t nnz, KeyPack kc, KeyPack kf,
+                                Bounds b, YSlot* tab, unsigned nslots, YEntry* yg, unsigned long long* yset,
+                                uint64_t yset_mask, uint64_t seed, int32_t bits_y, DevStatus* st,
+                                hipStream_t stream) {
+  if (nnz <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)((nnz + kAggChunk - 1) / kAggChunk);
+  k_y_scatter_agg<<<grid, kAggBlock, (size_t)nslots * 8, stream>>>(yidx, yval, nnz, kc, kf, b, tab, nslots, yg,
+                                                                    yset, yset_mask, seed, bits_y, st);
   return hipGetLastError();
 }
 

@@ -233,10 +233,15 @@ hipError_t device_scan(Op op, int64_t n, void* tile_sums, Fin fin, hipStream_t s
   return hipGetLastError();
 }
 
+// Home slot of a key in a table keyed by kp's packing.
+__device__ __forceinline__ uint64_t slot_of(uint64_t key, const KeyPack& kp, uint64_t seed, uint64_t mask) {
+  return kp.ident ? (key & mask) : (fmix64(key ^ seed) & mask);
+}
+
 // Finds `key` in a YSlot table; returns the slot or -1.
-__device__ __forceinline__ int64_t find_slot(const YSlot* __restrict__ tab, uint64_t key, uint64_t mask,
-                                             uint64_t seed, int32_t max_probe) {
-  uint64_t s = fmix64(key ^ seed) & mask;
+__device__ __forceinline__ int64_t find_slot(const YSlot* __restrict__ tab, uint64_t key, const KeyPack& kp,
+                                             uint64_t mask, uint64_t seed, int32_t max_probe) {
+  uint64_t s = slot_of(key, kp, seed, mask);
   for (int32_t probe = 0; probe < max_probe; ++probe) {
     const unsigned long long k = tab[s].key;
     if (k == key) return (int64_t)s;
@@ -278,6 +283,93 @@ __device__ __forceinline__ unsigned long long lanemask_lt() {
 __device__ __forceinline__ void wave_lds_fence() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   __builtin_amdgcn_wave_barrier();
+}
+
+// ---------------------------------------------------------------------------
+// Per-workgroup LDS aggregation over a chunk of entries (small key spaces)
+// ---------------------------------------------------------------------------
+
+constexpr int kAggBlock = 256;
+constexpr int kAggChunk = 4096;  // entries per workgroup
+constexpr int kAggUnroll = 8;    // entries a thread handles at once (independent memory ops in flight)
+
+// Walks this workgroup's chunk kAggUnroll entries per thread at a time: f
+// receives the entry indices, their packed keys and which are in range.
+template <class F>
+__device__ __forceinline__ void for_chunk_batches(const int32_t* __restrict__ idx, int64_t nnz, const KeyPack& kp,
+                                                  F f) {
+  const int64_t c0 = (int64_t)blockIdx.x * kAggChunk;
+  const int64_t c1 = c0 + kAggChunk < nnz ? c0 + kAggChunk : nnz;
+  for (int64_t base = c0 + threadIdx.x; base < c1; base += (int64_t)kAggBlock * kAggUnroll) {
+    int64_t e[kAggUnroll];
+    uint64_t keys[kAggUnroll];
+    bool ok[kAggUnroll];
+#pragma unroll
+    for (int u = 0; u < kAggUnroll; ++u) {
+      e[u] = base + (int64_t)u * kAggBlock;
+      ok[u] = e[u] < c1;
+      keys[u] = ok[u] ? pack_key(idx, nnz, e[u], kp) : 0ull;
+    }
+    f(e, keys, ok);
+  }
+}
+
+// Counts this workgroup's chunk per key in LDS, reserves one run per key
+// present (taking from the group's end offset in the table), then hands
+// every batch of entries with their positions to place(e, key, pos, ok).
+template <class F>
+__device__ __forceinline__ void place_chunk(const int32_t* __restrict__ idx, int64_t nnz, const KeyPack& kc,
+                                            YSlot* __restrict__ tab, unsigned nslots, unsigned* s_cnt,
+                                            unsigned* s_base, F place) {
+  for (unsigned s = threadIdx.x; s < nslots; s += kAggBlock) s_cnt[s] = 0u;
+  __syncthreads();
+  for_chunk_batches(idx, nnz, kc, [&](const int64_t*, const uint64_t* keys, const bool* ok) {
+#pragma unroll
+    for (int u = 0; u < kAggUnroll; ++u)
+      if (ok[u]) atomicAdd(&s_cnt[(unsigned)keys[u]], 1u);
+  });
+  __syncthreads();
+  for (unsigned s = threadIdx.x; s < nslots; s += kAggBlock) {
+    const unsigned c = s_cnt[s];
+    if (c) s_base[s] = atomicSub(&tab[s].start, c) - c;
+    s_cnt[s] = 0u;
+  }
+  __syncthreads();
+  for_chunk_batches(idx, nnz, kc, [&](const int64_t* e, const uint64_t* keys, const bool* ok) {
+    unsigned pos[kAggUnroll];
+#pragma unroll
+    for (int u = 0; u < kAggUnroll; ++u)
+      pos[u] = ok[u] ? s_base[(unsigned)keys[u]] + atomicAdd(&s_cnt[(unsigned)keys[u]], 1u) : 0u;
+    place(e, keys, pos, ok);
+  });
+}
+
+// Inserts kAggUnroll keys into a kEmpty-filled set of 8-byte slots (first
+// probes issued together); returns, per key, whether it was already there.
+__device__ __forceinline__ void set_insert_batch(unsigned long long* __restrict__ set, uint64_t mask, uint64_t seed,
+                                                 const unsigned long long* keys, const bool* ok, bool* seen) {
+  uint64_t h[kAggUnroll];
+  unsigned long long prev[kAggUnroll];
+#pragma unroll
+  for (int u = 0; u < kAggUnroll; ++u) {
+    h[u] = fmix64(keys[u] ^ seed) & mask;
+    prev[u] = ok[u] ? atomicCAS(&set[h[u]], (unsigned long long)kEmpty, keys[u]) : (unsigned long long)kEmpty;
+  }
+#pragma unroll
+  for (int u = 0; u < kAggUnroll; ++u) {
+    seen[u] = ok[u] && prev[u] == keys[u];
+    if (!ok[u] || prev[u] == kEmpty || prev[u] == keys[u]) continue;
+    uint64_t s = h[u];
+    for (uint64_t probe = 0; probe < mask; ++probe) {  // collision: continue probing
+      s = (s + 1) & mask;
+      const unsigned long long p = atomicCAS(&set[s], (unsigned long long)kEmpty, keys[u]);
+      if (p == kEmpty) break;
+      if (p == keys[u]) {
+        seen[u] = true;
+        break;
+      }
+    }
+  }
 }
 
 inline unsigned grid_for(int64_t n, int block, int num_cus, int per_cu = 16) {

@@ -151,6 +151,8 @@ struct sptc_plan_s {
   uint32_t* blist = nullptr;
   uint32_t* glist = nullptr;
   unsigned long long* dpos = nullptr;
+  uint16_t* ykey16 = nullptr;  // dense Y free keys: compact copy of grouped Y
+  double* yval = nullptr;
   unsigned long long* yset = nullptr;
   int64_t yset_slots = 0;
   uint32_t* gn = nullptr;
@@ -161,6 +163,7 @@ struct sptc_plan_s {
   int64_t direct_products = 0;
   int32_t ydup = 0;
   int32_t dense = 0;
+  int32_t y_agg = 0, x_agg = 0;  // small keys: LDS-aggregated count and scatter
   uint64_t ycells = 0;
   KeyUnpack ux{}, uy{};
 
@@ -320,16 +323,25 @@ sptc_status plan_group_y(sptc_plan_s* P, const sptc_coo* Y) {
   const uint64_t seed = P->opt.hash_seed;
   HIP_TRY(mark(P, s, SPTC_STAGE_Y_COUNT, 0));
   HIP_TRY(launch_fill_empty(P->ytab, P->ytab_slots, nullptr, s));
-  HIP_TRY(launch_key_count(Y->idx, P->ny, P->y_c, P->ytab, ymask, seed, P->max_probe_y, P->st, &P->st->groups,
-                           P->num_cus, s));
+  if (P->y_agg)
+    HIP_TRY(launch_key_count_agg(Y->idx, P->ny, P->y_c, P->ytab, (unsigned)P->ytab_slots, &P->st->groups, s));
+  else
+    HIP_TRY(launch_key_count(Y->idx, P->ny, P->y_c, P->ytab, ymask, seed, P->max_probe_y, P->st, &P->st->groups,
+                             P->num_cus, s));
   HIP_TRY(mark(P, s, SPTC_STAGE_Y_COUNT, 1));
   HIP_TRY(mark(P, s, SPTC_STAGE_Y_SCAN, 0));
   HIP_TRY(launch_scan_y_table(P->ytab, P->ytab_slots, P->tile_sums, s));
   HIP_TRY(mark(P, s, SPTC_STAGE_Y_SCAN, 1));
   HIP_TRY(mark(P, s, SPTC_STAGE_Y_SCATTER, 0));
   if (P->yset) HIP_TRY(launch_fill_keys(P->yset, P->yset_slots, s));
-  HIP_TRY(launch_y_scatter(Y->idx, Y->val, P->ny, P->y_c, P->y_f, P->yb, P->ytab, ymask, seed, P->max_probe_y,
-                           P->yg, P->yset, (uint64_t)P->yset_slots - 1, P->bits_fy, P->st, P->num_cus, s));
+  if (P->y_agg)
+    HIP_TRY(launch_y_scatter_agg(Y->idx, Y->val, P->ny, P->y_c, P->y_f, P->yb, P->ytab, (unsigned)P->ytab_slots,
+                                 P->yg, P->yset, (uint64_t)P->yset_slots - 1, seed, P->bits_fy, P->st, s));
+  else
+    HIP_TRY(launch_y_scatter(Y->idx, Y->val, P->ny, P->y_c, P->y_f, P->yb, P->ytab, ymask, seed, P->max_probe_y,
+                             P->yg, P->yset, (uint64_t)P->yset_slots - 1, P->bits_fy, P->st, P->num_cus, s));
+  if (P->opt.mode == SPTC_MODE_GROUPED && P->dense)
+    HIP_TRY(launch_sort_y_runs(P->ytab, P->ytab_slots, P->yg, P->ny, P->ykey16, P->yval, P->num_cus, s));
   HIP_TRY(mark(P, s, SPTC_STAGE_Y_SCATTER, 1));
   return SPTC_OK;
 }
@@ -380,11 +392,18 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
 
   HIP_TRY(mark(P, s, SPTC_STAGE_X_PROBE, 0));
   HIP_TRY(launch_fill_empty(P->xtab, P->xtab_slots, nullptr, s));
-  HIP_TRY(launch_key_count(X->idx, P->nx, P->x_f, P->xtab, xmask, seed, P->max_probe_x, P->st, nullptr,
-                           P->num_cus, s));
+  if (P->x_agg)
+    HIP_TRY(launch_key_count_agg(X->idx, P->nx, P->x_f, P->xtab, (unsigned)P->xtab_slots, nullptr, s));
+  else
+    HIP_TRY(launch_key_count(X->idx, P->nx, P->x_f, P->xtab, xmask, seed, P->max_probe_x, P->st, nullptr,
+                             P->num_cus, s));
   HIP_TRY(launch_scan_x_table(P->xtab, P->xtab_slots, P->groups, P->tile_sums, P->st, s));
-  HIP_TRY(launch_x_scatter(X->idx, X->val, P->nx, P->x_f, P->x_c, P->xb, P->xtab, xmask, P->max_probe_x, P->ytab,
-                           ymask, P->max_probe_y, seed, P->xr, P->st, P->num_cus, s));
+  if (P->x_agg)
+    HIP_TRY(launch_x_scatter_agg(X->idx, X->val, P->nx, P->x_f, P->x_c, P->xb, P->xtab, (unsigned)P->xtab_slots,
+                                 P->ytab, ymask, P->max_probe_y, seed, P->xr, P->st, s));
+  else
+    HIP_TRY(launch_x_scatter(X->idx, X->val, P->nx, P->x_f, P->x_c, P->xb, P->xtab, xmask, P->max_probe_x, P->ytab,
+                             ymask, P->max_probe_y, seed, P->xr, P->st, P->num_cus, s));
   HIP_TRY(mark(P, s, SPTC_STAGE_X_PROBE, 1));
   HIP_TRY(mark(P, s, SPTC_STAGE_P_SCAN, 0));
   HIP_TRY(launch_scan_entries(P->xr, P->nx, P->eoff, P->tile_sums, P->st, s));
@@ -433,25 +452,31 @@ sptc_status plan_body(sptc_plan_s* P, const sptc_coo* X, const sptc_coo* Y, cons
   for (int32_t m = 0; m < X->order; ++m)
     if (std::find(cx, cx + P->nc, m) == cx + P->nc) fx.push_back(m);
   const int64_t y_bound = std::min<int64_t>(P->ny, sat_prod(Y->dims, cyv));
-  P->ytab_slots = pow2_at_least((double)y_bound / P->opt.load_factor);
+  P->ytab_slots = P->y_c.ident ? std::max<int64_t>((int64_t)1 << P->bits_c, 2)
+                               : pow2_at_least((double)y_bound / P->opt.load_factor);
   P->max_probe_y = P->opt.max_probe > 0 ? P->opt.max_probe : (int32_t)std::min<int64_t>(P->ytab_slots, 1 << 30);
   const bool grouped = P->opt.mode == SPTC_MODE_GROUPED;
   if (grouped) {
     const int64_t x_bound = std::min<int64_t>(P->nx, sat_prod(X->dims, fx));
-    P->xtab_slots = pow2_at_least((double)x_bound / P->opt.load_factor);
+    P->xtab_slots = P->x_f.ident ? std::max<int64_t>((int64_t)1 << P->bits_fx, 2)
+                                 : pow2_at_least((double)x_bound / P->opt.load_factor);
     P->max_probe_x = P->opt.max_probe > 0 ? P->opt.max_probe : (int32_t)std::min<int64_t>(P->xtab_slots, 1 << 30);
   }
 
   sptc_status st;
   if ((st = P->allocate_n(P->ytab_slots, &P->ytab))) return st;
   if ((st = P->allocate_n(P->ny, &P->yg))) return st;
+  if (grouped && P->dense) {
+    if ((st = P->allocate_n(P->ny, &P->ykey16))) return st;
+    if ((st = P->allocate_n(P->ny, &P->yval))) return st;
+  }
   const int64_t tiles = std::max<int64_t>({scan_tiles(P->ytab_slots), scan_tiles(P->xtab_slots), scan_tiles(P->nx)});
   if ((st = P->allocate_n(2 * (tiles + 1), &P->tile_sums))) return st;  // room for pair-valued scans
   // Y coordinate set (grouped mode): finds repeated Y coordinates, which the
   // direct class cannot have.  Needs the full Y coordinate in 63 bits.
   const bool yset = grouped && P->bits_c + P->bits_fy <= 63;
   if (yset) {
-    P->yset_slots = pow2_at_least((double)std::max<int64_t>(P->ny, 1) / P->opt.load_factor);
+    P->yset_slots = pow2_at_least(4.0 * (double)std::max<int64_t>(P->ny, 1));  // sparse: short probes
     if ((st = P->allocate_n(P->yset_slots, &P->yset))) return st;
   }
   if ((st = P->allocate_n(1, &P->st))) return st;
@@ -543,6 +568,13 @@ sptc_status sptc_plan(sptc_plan_t* plan, const sptc_coo* X, const sptc_coo* Y, i
   add_unpack(P->out_unpack, P->y_f, 0);
   add_unpack(P->ykey_unpack, P->y_c, 0);
   add_unpack(P->yfree_unpack, P->y_f, 0);
+  // Small keys index their tables directly; the contracting key's choice
+  // holds for X's probes of Y's table too.
+  P->y_c.ident = P->x_c.ident = P->bits_c <= kIdentBits ? 1 : 0;
+  P->x_f.ident = P->bits_fx <= kIdentBits ? 1 : 0;
+  P->y_f.ident = 0;
+  P->y_agg = P->bits_c <= kAggBits ? 1 : 0;
+  P->x_agg = (o.mode == SPTC_MODE_GROUPED && P->bits_fx <= kAggBits) ? 1 : 0;
   add_unpack(P->ux, P->x_f, 0);
   add_unpack(P->uy, P->y_f, 0);
   P->ycells = (uint64_t)sat_prod(Y->dims, fy);
@@ -623,6 +655,8 @@ sptc_status sptc_execute(sptc_plan_t P, int32_t* out_idx, double* out_val, int64
     a.xr = P->xr;
     a.eoff = P->eoff;
     a.yg = P->yg;
+    a.ykey16 = P->ykey16;
+    a.yval = P->yval;
     a.ny = P->ny;
     a.ycells = P->ycells;
     a.seed = P->opt.hash_seed;

@@ -25,7 +25,14 @@ struct KeyPack {
   int32_t mode[kMaxOrder];
   int32_t shift[kMaxOrder];
   uint32_t mask[kMaxOrder];  // (1 << bits) - 1: keeps any coordinate inside its field
+  int32_t ident;             // the table keyed by this pack is direct-addressed (slot = key)
 };
+
+// Keys of at most this many bits index their table directly (no hashing,
+// no probing); of at most kAggBits bits, their counting and placement are
+// also aggregated per workgroup in LDS before touching the table.
+constexpr int kIdentBits = 16;
+constexpr int kAggBits = 13;
 
 // Coordinate bounds of one tensor (validation).
 struct Bounds {
@@ -116,6 +123,11 @@ hipError_t launch_key_count(const int32_t* idx, int64_t nnz, KeyPack kc, YSlot* 
                             int32_t max_probe, DevStatus* st, unsigned long long* distinct, int num_cus,
                             hipStream_t stream);
 
+// The same for a direct-addressed table of nslots <= 2^kAggBits slots,
+// counting per workgroup in LDS first.
+hipError_t launch_key_count_agg(const int32_t* idx, int64_t nnz, KeyPack kc, YSlot* tab, unsigned nslots,
+                                unsigned long long* distinct, hipStream_t stream);
+
 // Exclusive scan support: tile sums need ceil(n / kScanTile) u64 entries.
 constexpr int kScanBlock = 256;
 constexpr int kScanItems = 16;
@@ -132,6 +144,13 @@ hipError_t launch_y_scatter(const int32_t* yidx, const double* yval, int64_t nnz
                             Bounds b, YSlot* tab, uint64_t mask, uint64_t seed, int32_t max_probe, YEntry* yg,
                             unsigned long long* yset, uint64_t yset_mask, int32_t bits_y, DevStatus* st, int num_cus,
                             hipStream_t stream);
+
+// Y scatter for a direct-addressed Y table of nslots <= 2^kAggBits slots:
+// each workgroup counts its entries per key in LDS, reserves one run per key
+// and places its entries inside the runs.
+hipError_t launch_y_scatter_agg(const int32_t* yidx, const double* yval, int64_t nnz, KeyPack kc, KeyPack kf,
+                                Bounds b, YSlot* tab, unsigned nslots, YEntry* yg, unsigned long long* yset,
+                                uint64_t yset_mask, uint64_t seed, int32_t bits_y, DevStatus* st, hipStream_t stream);
 
 // Sets n 8-byte words to kEmpty.
 hipError_t launch_fill_keys(unsigned long long* keys, int64_t n, hipStream_t stream);
@@ -162,6 +181,12 @@ hipError_t launch_compact(const ZSlot* tab, int64_t nslots, KeyUnpack ku, int32_
 // field becomes each group's end offset for the scatter.
 hipError_t launch_scan_x_table(YSlot* tab, int64_t nslots, GroupRec* groups, void* tile_sums, DevStatus* st,
                                hipStream_t stream);
+
+// X scatter for a direct-addressed X table of nslots <= 2^kAggBits slots,
+// aggregated per workgroup in LDS like the Y scatter.
+hipError_t launch_x_scatter_agg(const int32_t* xidx, const double* xval, int64_t nnz, KeyPack kf, KeyPack kc,
+                                Bounds b, YSlot* xtab, unsigned nslots, const YSlot* ytab, uint64_t ymask,
+                                int32_t max_probe_y, uint64_t seed, XRec* xr, DevStatus* st, hipStream_t stream);
 
 // Scatter X into its groups, probing Y's table for every entry.
 hipError_t launch_x_scatter(const int32_t* xidx, const double* xval, int64_t nnz, KeyPack kf, KeyPack kc, Bounds b,
@@ -201,6 +226,8 @@ struct GroupArgs {
   const XRec* xr;
   const unsigned long long* eoff;
   const YEntry* yg;
+  const uint16_t* ykey16;  // dense Y free keys: the grouped Y keys as 16-bit cells (else NULL)
+  const double* yval;      // and the grouped Y values
   int64_t ny;
   uint64_t ycells;
   uint64_t seed;
@@ -234,6 +261,12 @@ hipError_t launch_scan_group_counts(const uint32_t* gn, const uint32_t* wlist, i
 
 // *out_nnz = st->out_base, or the negated status.
 hipError_t launch_finalize(int64_t* out_nnz, int64_t out_cap, DevStatus* st, hipStream_t stream);
+
+// Sorts Y runs of 2..1024 entries by Y free key (dense Y free keys only) and
+// writes the compact copy of grouped Y (16-bit keys, values) the dense
+// accumulators read.
+hipError_t launch_sort_y_runs(const YSlot* ytab, int64_t nslots, YEntry* yg, int64_t ny, uint16_t* ykey16,
+                              double* yval, int num_cus, hipStream_t stream);
 
 // Clears st->err and st->out_base.
 hipError_t launch_reset_status(DevStatus* st, hipStream_t stream);
