@@ -34,8 +34,12 @@
  *    nonzero e.  Values are IEEE double.  Repeated coordinates are allowed and
  *    act as separate terms.
  *  - Coordinates are packed into 64-bit keys with ceil(log2 I_k) bits per
- *    mode.  The packed X-free plus Y-free width must be at most 63 bits
- *    (else SPTC_ERR_KEY_OVERFLOW); so must the contracting key.
+ *    mode.  The contracting key, the X free key and the Y free key must each
+ *    fit 63 bits (else SPTC_ERR_KEY_OVERFLOW).  Their output key may be
+ *    wider: the grouped mode never packs X free and Y free coordinates
+ *    together except under the dense id of the X free key (its group,
+ *    section 4.1.2).  The global mode packs them and needs both to fit 63
+ *    bits together.
  *  - "device" pointers are HIP device memory (or memory the GPU can address,
  *    e.g. pinned host memory where stated); "host" pointers are read by the
  *    calling thread only during the call.

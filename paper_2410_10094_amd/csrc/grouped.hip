@@ -283,12 +283,13 @@ __global__ __launch_bounds__(256) void k_gather_global(const GroupRec* __restric
   const int lane = threadIdx.x & 63;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < ngl; i += nwaves) {
-    const GroupRec G = groups[glist[i]];
+    const uint32_t g = glist[i];
+    const GroupRec G = groups[g];
     const unsigned long long base = gl_eoff[i];
     for (unsigned e = lane; e < G.count; e += 64) {
       const XRec r = xr[G.start + e];
       XEntry x;
-      x.phi = G.phi;
+      x.phi = g;  // the group id stands for the X free key in the table key
       x.v = r.v;
       xrec[base + e] = x;
       xg[base + e] = r.ystart;

@@ -282,6 +282,41 @@ struct FinCompact {
   }
 };
 
+// Grouped path, global class: table keys are (group id << bits_y) | Y free
+// key, so the X free coordinates come from the group's record.  (The group id
+// is the dense small id of the X free key; it keeps keys within 63 bits when
+// the packed X free key and Y free key together would not fit.)
+struct GroupedOccupancyOp {
+  const ZSlot* tab;
+  const GroupRec* groups;
+  KeyUnpack ux, uy;
+  int32_t bits_y;
+  int32_t* out_idx;
+  double* out_val;
+  int64_t out_cap;
+  const unsigned long long* base;
+  __device__ unsigned long long get(int64_t i) const { return tab[i].key != kEmpty ? 1ull : 0ull; }
+  __device__ void put(int64_t i, unsigned long long rank, unsigned long long v) const {
+    if (!v) return;
+    const unsigned long long pos = rank + *base;
+    if ((int64_t)pos >= out_cap) return;
+    const ZSlot z = tab[i];
+    const unsigned long long phix = groups[z.key >> bits_y].phi;
+    const unsigned long long phiy = bits_y ? (z.key & (~0ull >> (64 - bits_y))) : 0ull;
+#pragma unroll
+    for (int m = 0; m < kMaxOrder; ++m)
+      if (m < ux.n)
+        __builtin_nontemporal_store((int32_t)((phix >> ux.shift[m]) & ux.mask[m]),
+                                    &out_idx[(int64_t)m * out_cap + (int64_t)pos]);
+#pragma unroll
+    for (int m = 0; m < kMaxOrder; ++m)
+      if (m < uy.n)
+        __builtin_nontemporal_store((int32_t)((phiy >> uy.shift[m]) & uy.mask[m]),
+                                    &out_idx[(int64_t)(ux.n + m) * out_cap + (int64_t)pos]);
+    __builtin_nontemporal_store(z.val, &out_val[pos]);
+  }
+};
+
 // Inspection: occupied Y table slots -> (key coordinates, count, start).
 struct YGroupsOp {
   const YSlot* tab;
@@ -483,6 +518,14 @@ hipError_t launch_compact(const ZSlot* tab, int64_t nslots, KeyUnpack ku, int32_
                           unsigned long long* tile_sums, DevStatus* st, hipStream_t stream) {
   return device_scan(OccupancyOp{tab, ku, out_idx, out_val, out_cap, base}, nslots, tile_sums,
                      FinCompact{out_nnz, out_cap, base, st}, stream);
+}
+
+hipError_t launch_compact_grouped(const ZSlot* tab, int64_t nslots, const GroupRec* groups, KeyUnpack ux,
+                                  KeyUnpack uy, int32_t bits_y, int32_t* out_idx, double* out_val, int64_t out_cap,
+                                  int64_t* out_nnz, const unsigned long long* base, unsigned long long* tile_sums,
+                                  DevStatus* st, hipStream_t stream) {
+  return device_scan(GroupedOccupancyOp{tab, groups, ux, uy, bits_y, out_idx, out_val, out_cap, base}, nslots,
+                     tile_sums, FinCompact{out_nnz, out_cap, base, st}, stream);
 }
 
 hipError_t launch_y_groups(const YSlot* tab, int64_t nslots, KeyUnpack ku, int32_t* key_coords, int64_t* counts,

@@ -430,6 +430,10 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
   if ((st = P->allocate_n(scan_tiles(P->nw) + 1, &P->etile_sums))) return st;
   if (P->ngl == 0) return SPTC_OK;
 
+  // The global class keys its table by (group id << Y free bits) | Y free key.
+  if (bits_for(P->x_groups) + P->bits_fy > 63)
+    return fail(SPTC_ERR_KEY_OVERFLOW, "%lld X groups and a %d-bit Y free key do not fit a 63-bit key",
+                (long long)P->x_groups, P->bits_fy);
   if ((st = P->allocate_n(P->ngl, &P->gl_eoff))) return st;
   HIP_TRY(launch_scan_global_entries(P->groups, P->glist, P->ngl, P->gl_eoff, P->tile_sums, P->st, s));
   if ((st = read_status(P, &host))) return st;
@@ -581,14 +585,16 @@ sptc_status sptc_plan(sptc_plan_t* plan, const sptc_coo* X, const sptc_coo* Y, i
   P->dense = P->bits_fy <= kDenseBits ? 1 : 0;
   P->xb = make_bounds(X, o.validate);
   P->yb = make_bounds(Y, o.validate);
-  if (P->bits_c > 63) {
+  if (P->bits_c > 63 || P->bits_fx > 63 || P->bits_fy > 63) {
+    const int32_t bc = P->bits_c, bx = P->bits_fx, by = P->bits_fy;
     delete P;
-    return fail(SPTC_ERR_KEY_OVERFLOW, "contracting key needs %d bits (> 63)", bits_cx);
+    return fail(SPTC_ERR_KEY_OVERFLOW, "packed keys need %d (contracting), %d (X free), %d (Y free) bits; at most 63",
+                bc, bx, by);
   }
-  if (P->bits_fx + P->bits_fy > 63) {
-    int32_t b = P->bits_fx + P->bits_fy;
+  if (o.mode == SPTC_MODE_GLOBAL && P->bits_fx + P->bits_fy > 63) {
+    const int32_t b = P->bits_fx + P->bits_fy;
     delete P;
-    return fail(SPTC_ERR_KEY_OVERFLOW, "output key needs %d bits (> 63)", b);
+    return fail(SPTC_ERR_KEY_OVERFLOW, "output key needs %d bits (> 63); the grouped mode handles it", b);
   }
 
   DeviceInfo* di = nullptr;
@@ -700,8 +706,12 @@ sptc_status sptc_execute(sptc_plan_t P, int32_t* out_idx, double* out_val, int64
                             P->opt.hash_seed, P->max_probe_z, (uint64_t)P->expand_products, P->st, P->num_cus, s));
   HIP_TRY(mark(P, s, SPTC_STAGE_EXPAND, 1));
   HIP_TRY(mark(P, s, SPTC_STAGE_COMPACT, 0));
-  HIP_TRY(launch_compact(P->ztab, P->ztab_slots, P->out_unpack, out_idx, out_val, out_cap, out_nnz,
-                         grouped ? &P->st->out_base : nullptr, P->ztile_sums, P->st, s));
+  if (grouped)
+    HIP_TRY(launch_compact_grouped(P->ztab, P->ztab_slots, P->groups, P->ux, P->uy, P->bits_fy, out_idx, out_val,
+                                   out_cap, out_nnz, &P->st->out_base, P->ztile_sums, P->st, s));
+  else
+    HIP_TRY(launch_compact(P->ztab, P->ztab_slots, P->out_unpack, out_idx, out_val, out_cap, out_nnz, nullptr,
+                           P->ztile_sums, P->st, s));
   HIP_TRY(mark(P, s, SPTC_STAGE_COMPACT, 1));
   return SPTC_OK;
 }

@@ -175,6 +175,13 @@ hipError_t launch_compact(const ZSlot* tab, int64_t nslots, KeyUnpack ku, int32_
                           int64_t out_cap, int64_t* out_nnz, const unsigned long long* base,
                           unsigned long long* tile_sums, DevStatus* st, hipStream_t stream);
 
+// Grouped path, global class: compaction of a table keyed by
+// (group id << bits_y) | Y free key, written from position *base.
+hipError_t launch_compact_grouped(const ZSlot* tab, int64_t nslots, const GroupRec* groups, KeyUnpack ux,
+                                  KeyUnpack uy, int32_t bits_y, int32_t* out_idx, double* out_val, int64_t out_cap,
+                                  int64_t* out_nnz, const unsigned long long* base, unsigned long long* tile_sums,
+                                  DevStatus* st, hipStream_t stream);
+
 // ---- grouped path (grouped.hip) ----
 
 // X table (keyed by X free key) -> dense group records; the table's start
@@ -211,7 +218,8 @@ hipError_t launch_scan_direct(const GroupRec* groups, const uint32_t* dlist, int
                               const unsigned long long* eoff, unsigned long long* dpos, void* tile_sums,
                               DevStatus* st, hipStream_t stream);
 
-// Entries of the global-class groups, gathered for the global hash.
+// Entries of the global-class groups, gathered for the global hash; each
+// gathered record carries its group id in place of the packed X free key.
 hipError_t launch_scan_global_entries(const GroupRec* groups, const uint32_t* glist, int64_t ngl,
                                       unsigned long long* gl_eoff, void* tile_sums, DevStatus* st,
                                       hipStream_t stream);

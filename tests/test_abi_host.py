@@ -72,7 +72,9 @@ coo.keep = []
     ("null_idx", B.ERR_INVALID_ARG),
     ("null_tensor", B.ERR_INVALID_ARG),
     ("too_many_pairs", B.ERR_INVALID_ARG),
-    ("output_key_overflow", B.ERR_KEY_OVERFLOW),
+    ("output_key_overflow_global_mode", B.ERR_KEY_OVERFLOW),
+    ("free_key_overflow", B.ERR_KEY_OVERFLOW),
+    ("bad_mode", B.ERR_INVALID_ARG),
     ("bad_load_factor", B.ERR_INVALID_ARG),
     ("bad_table_slots", B.ERR_INVALID_ARG),
 ])
@@ -98,9 +100,18 @@ def test_plan_validation(case, status):
         X = None
     elif case == "too_many_pairs":
         cx, cy = [0, 1, 2, 0], [0, 1, 2, 1]
-    elif case == "output_key_overflow":
+    elif case == "output_key_overflow_global_mode":
+        # X free 60 bits + Y free 23 bits: only the grouped mode can take it
         X = coo((1 << 30, 1 << 30, 10))
         Y = coo((10, 1 << 20, 7))
+        opt = B.default_options()
+        opt.mode = B.MODE_GLOBAL
+    elif case == "free_key_overflow":
+        X = coo((1 << 30, 1 << 30, 1 << 30, 10))  # 90-bit X free key
+        cx = [3]
+    elif case == "bad_mode":
+        opt = B.default_options()
+        opt.mode = 7
     elif case == "bad_load_factor":
         opt = B.default_options()
         opt.load_factor = 1.5

@@ -164,6 +164,39 @@ def _class_problems():
     return out
 
 
+def _wide_key_problems():
+    """Output keys wider than 63 bits: X free and Y free keys each fit, their
+    concatenation does not."""
+    rng = np.random.default_rng(36)
+    out = []
+    # direct and wave classes: 60-bit X free key, 40-bit Y free key
+    X = Coo((1 << 30, 1 << 30, 6), np.stack([rng.integers(0, 1 << 30, 3000), rng.integers(0, 1 << 30, 3000),
+                                             rng.integers(0, 6, 3000)]).astype(np.int32), W.nonzero_uniform(rng, 3000))
+    X.idx[:, 2000:] = X.idx[:, :1000]  # 1000 two-entry groups (wave class), 1000 single-entry (direct)
+    X.idx[2, 2000:] = (X.idx[2, :1000] + 1) % 6
+    Y = Coo((6, 1 << 20, 1 << 20), np.stack([rng.integers(0, 6, 500), rng.integers(0, 1 << 20, 500),
+                                             rng.integers(0, 1 << 20, 500)]).astype(np.int32),
+            W.nonzero_uniform(rng, 500))
+    out.append(Problem("wide-100-bits", X, Y, (2,), (0,)))
+    # global class: one X group reaching 40000 distinct Y free keys
+    X = Coo((1 << 31, 1 << 31, 4), np.array([[7] * 4, [9] * 4, [0, 1, 2, 3]], np.int32), W.nonzero_uniform(rng, 4))
+    Y = Coo((4, 1 << 20), np.stack([rng.integers(0, 4, 40_000), rng.integers(0, 1 << 20, 40_000)]).astype(np.int32),
+            W.nonzero_uniform(rng, 40_000))
+    out.append(Problem("wide-global-class", X, Y, (2,), (0,)))
+    return out
+
+
+@pytest.mark.parametrize("p", _wide_key_problems(), ids=lambda p: p.name)
+def test_output_keys_wider_than_63_bits(p):
+    log(f"[wide] {p.name}")
+    info, gidx, gval = run_gpu(p, mode="grouped")
+    assert_parity(p, gidx, gval)
+    if p.name == "wide-global-class":
+        assert info["classes"]["global_"] > 0
+    else:
+        assert info["classes"]["direct"] > 0 and info["classes"]["wave"] > 0
+
+
 def test_repeated_y_coordinates_disable_direct_class():
     """With a repeated Y coordinate a single-entry X group can have two
     products on one output, so the direct class must not be used."""
