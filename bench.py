@@ -184,6 +184,126 @@ def run_workload(name, steps, warmup, with_events=True, mode="grouped"):
     return dict(problem=p, products=products, nnz_z=nnz_z, sec=sec, stage_ms=stage_ms, info=info, mode=mode)
 
 
+def generate_draws(count, seed, workers):
+    """Draws of the batched workload, generated in worker processes (before
+    the GPU is touched)."""
+    import multiprocessing as mp
+
+    from paper_2410_10094_amd import workloads as W
+    if workers <= 1 or count <= 4:
+        return [W.batched_draw(seed, i) for i in range(count)]
+    with mp.get_context("fork").Pool(workers) as pool:
+        return pool.starmap(W.batched_draw, [(seed, i) for i in range(count)], chunksize=2)
+
+
+def percentile(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if xs else None
+
+
+def sub_batches(draws, budget):
+    """Consecutive runs of draws whose expected products stay within budget."""
+    from paper_2410_10094_amd import binding as B
+    from paper_2410_10094_amd import workloads as W
+    out, cur, acc = [], [], 0.0
+    for i, p in enumerate(draws):
+        e = W.expected_products(p)
+        if cur and (acc + e > budget or len(cur) >= B.BATCH_MAX):
+            out.append(cur)
+            cur, acc = [], 0.0
+        cur.append(i)
+        acc += e
+    if cur:
+        out.append(cur)
+    return out
+
+
+def run_batched(draws, steps, warmup, budget):
+    """The batched workload two ways, each step covering every draw:
+    per-call (sptc_plan + sptc_execute per contraction) and batched
+    (sptc_batch_plan + sptc_batch_execute per sub-batch of at most `budget`
+    expected products).  Latency of a contraction: per-call, its own plan +
+    execute; batched, its sub-batch's plan + execute (all members complete
+    together)."""
+    import torch
+
+    import paper_2410_10094_amd as sptc
+    dev = [(sptc.DeviceCoo.from_host(p.X), sptc.DeviceCoo.from_host(p.Y)) for p in draws]
+    torch.cuda.synchronize()
+    groups = sub_batches(draws, budget)
+
+    # per-call: one output buffer sized for the largest bound
+    bounds, orders, products = [], [], []
+    for (X, Y), p in zip(dev, draws):
+        with sptc.plan(X, Y, p.cx, p.cy) as pl:
+            bounds.append(pl.out_nnz_bound)
+            orders.append(pl.out_order)
+            products.append(pl.products)
+    total_products = sum(products)
+    cap = max(bounds)
+    oidx = torch.empty((max(orders) * max(cap, 1),), dtype=torch.int32, device="cuda")
+    oval = torch.empty(max(cap, 1), dtype=torch.float64, device="cuda")
+    onnz = torch.empty(len(draws), dtype=torch.int64, device="cuda")
+
+    def per_call(lat):
+        for i, ((X, Y), p) in enumerate(zip(dev, draws)):
+            t0 = time.perf_counter()
+            pl = sptc.plan(X, Y, p.cx, p.cy)
+            k = pl.out_order
+            pl.execute_into(oidx[: max(k, 1) * max(cap, 1)].view(max(k, 1), max(cap, 1)), oval, cap, onnz[i:i + 1])
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - t0)
+            pl.close()
+
+    # batched: buffers sized for the largest sub-batch
+    need_i = need_v = need_s = 0
+    for g in groups:
+        with sptc.batch([(dev[i][0], dev[i][1], draws[i].cx, draws[i].cy) for i in g]) as bt:
+            need_i, need_v = max(need_i, bt.idx_elems), max(need_v, bt.val_elems)
+            need_s = max(need_s, bt.scratch_bytes)
+    bidx = torch.empty(max(need_i, 1), dtype=torch.int32, device="cuda")
+    bval = torch.empty(max(need_v, 1), dtype=torch.float64, device="cuda")
+    bnnz = torch.empty(len(draws), dtype=torch.int64, device="cuda")
+    bscr = torch.empty(max(need_s, 1), dtype=torch.uint8, device="cuda")
+
+    def batched(lat):
+        for g in groups:
+            t0 = time.perf_counter()
+            bt = sptc.batch([(dev[i][0], dev[i][1], draws[i].cx, draws[i].cy) for i in g])
+            bt.execute_into(bidx, bval, bnnz[g[0]:g[0] + len(g)], bscr)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            lat.extend([dt] * len(g))
+            bt.close()
+
+    res = {}
+    for name, fn, nnz in (("per_call", per_call, onnz), ("batched", batched, bnnz)):
+        for _ in range(warmup):
+            fn([])
+        torch.cuda.synchronize()
+        lat = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn(lat)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / steps
+        bad = int((nnz < 0).sum().item())
+        if bad:
+            raise RuntimeError(f"{name}: {bad} contractions reported an error")
+        res[name] = {"sec_per_step": round(sec, 5), "products_per_s": total_products / sec,
+                     "latency_ms_p50": round(percentile(lat, 50) * 1e3, 4),
+                     "latency_ms_p99": round(percentile(lat, 99) * 1e3, 4)}
+    res["batched"]["sub_batches"] = len(groups)
+    res["batched"]["sub_batch_budget_expected_products"] = budget
+    res["speedup_batched_vs_per_call"] = round(res["per_call"]["sec_per_step"] / res["batched"]["sec_per_step"], 3)
+    res["contractions"] = len(draws)
+    res["products"] = total_products
+    res["nnz_x_total"] = sum(p.X.nnz for p in draws)
+    res["nnz_y_total"] = sum(p.Y.nnz for p in draws)
+    res["steps"] = steps
+    return res
+
+
 def roofline_of(r):
     p = r["problem"]
     stage = max(r["stage_ms"], key=lambda s: r["stage_ms"][s])
@@ -215,6 +335,10 @@ def main():
                     help="only run a plain device copy of MIB MiB (known bytes for scaling HBM counters) and exit")
     ap.add_argument("--mode", default="grouped", choices=["grouped", "global"],
                     help="accumulation strategy: per-X-group LDS tables (default) or one global hash")
+    ap.add_argument("--batched", type=int, default=512, metavar="COUNT",
+                    help="draws of the batched workload timed per-call and batched (0: skip)")
+    ap.add_argument("--batch-budget", type=float, default=1.0e9,
+                    help="expected products per sub-batch of the batched leg")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -222,6 +346,12 @@ def main():
         sys.exit(2)
     if args.steps < 1:
         sys.exit("--steps must be >= 1")
+
+    draws = None
+    if args.batched and not args.calibrate_copy:
+        workers = max(1, min(16, len(os.sched_getaffinity(0))))
+        from paper_2410_10094_amd.workloads import BASE_SEED
+        draws = generate_draws(args.batched, BASE_SEED + 4, workers)
 
     import torch
     torch.cuda.set_device(0)
@@ -241,6 +371,12 @@ def main():
     also = []
     for name in [a for a in args.also.split(",") if a and a != args.workload]:
         also.append(summary(name, run_workload(name, max(3, args.steps // 2), max(1, args.warmup), mode=args.mode)))
+
+    batched = None
+    if draws:
+        batched = run_batched(draws, max(1, args.steps // 5), 1, args.batch_budget)
+        batched["workload"] = (f"{len(draws)} draws: orders 3-5, dims U[32,4096], nnz log-U[1e3,1e6], "
+                               "1-2 contracted pairs, FP64 U[-1,1)")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -273,6 +409,7 @@ def main():
         "stage_ms": {k: round(v, 4) for k, v in r["stage_ms"].items()},
         "plan": r["info"],
         "also": also,
+        "batched": batched,
     }
     print(json.dumps(line), flush=True)
 

@@ -95,8 +95,8 @@ typedef struct sptc_allocator {
 
 /* A COO tensor (section 2.1, Fig. 1).  dims: host [order].  idx: device
  * int32 [order][nnz] mode-major.  val: device double [nnz].  Both device
- * arrays are borrowed: they must stay valid and unchanged while any plan
- * built from them is executed (the plan reads X and Y when built). */
+ * arrays are borrowed: sptc_plan reads them (on its stream) before it
+ * returns; a plan keeps its own copies and never reads them again. */
 typedef struct sptc_coo {
   int32_t order;
   const int64_t* dims;
@@ -233,6 +233,49 @@ SPTC_API sptc_status sptc_plan_x_counts(sptc_plan_t plan, int64_t* counts, void*
  * SPTC_ERR_CAPACITY is returned.  Enqueued on `stream`. */
 SPTC_API sptc_status sptc_plan_x_groups(sptc_plan_t plan, int32_t* free_coords, int64_t* counts, int64_t* products,
                                         int64_t cap, int64_t* ngroups, void* stream);
+
+/* ---- Batched contraction: many independent contractions in shared launches ----
+ *
+ * count contractions (X[b], Y[b], ncontract[b], cx[b], cy[b]) are planned and
+ * executed together: every entry is keyed with its contraction's index, so
+ * one pass of the grouped pipeline serves all of them, and a final pass
+ * sorts the outputs back into one COO per contraction.  1 <= count <= 4096.
+ * Each contraction follows the rules of sptc_plan; the contraction index
+ * plus its widest contracting key and its widest X free key must each fit
+ * 62 bits.  Options apply to the whole batch (mode must be GROUPED). */
+typedef struct sptc_batch_s* sptc_batch_t;
+
+/* Plans the batch; synchronises `stream` a few times.  Arrays are host
+ * arrays of `count` entries; cx[b] / cy[b] point to ncontract[b] modes. */
+SPTC_API sptc_status sptc_batch_plan(sptc_batch_t* batch, int32_t count, const sptc_coo* X, const sptc_coo* Y,
+                                     const int32_t* ncontract, const int32_t* const* cx, const int32_t* const* cy,
+                                     const sptc_options* opt, const sptc_allocator* alloc, void* stream);
+
+/* Buffers the batch needs (host outputs): int32 elements for all index
+ * rows, double elements for all values, bytes of execute scratch (device
+ * memory the caller lends to each sptc_batch_execute; it grows with the
+ * product count of pass 1, section 4.3) and bytes of workspace the batch
+ * itself holds.  Any pointer may be NULL. */
+SPTC_API sptc_status sptc_batch_sizes(sptc_batch_t batch, int64_t* idx_elems, int64_t* val_elems,
+                                      int64_t* scratch_bytes, int64_t* workspace_bytes);
+
+/* Contraction b's sizes (info: out_order, out_dims, products,
+ * out_nnz_bound and key_bits_*; the plan-wide fields are zero) and where its
+ * output sits: index row m at out_idx + idx_offset + m * info.out_nnz_bound,
+ * values at out_val + val_offset. */
+SPTC_API sptc_status sptc_batch_info(sptc_batch_t batch, int32_t b, sptc_info* info, int64_t* idx_offset,
+                                     int64_t* val_offset);
+
+/* Executes every contraction.  out_idx / out_val: device buffers of the
+ * sizes sptc_batch_sizes reports; out_nnz: device int64 [count] receiving
+ * each contraction's nnz (or the negated status); scratch: device memory of
+ * scratch_bytes, 256-byte aligned, not used by anything else until the
+ * enqueued work ends (NULL when scratch_bytes is 0).  Like sptc_execute it
+ * never synchronises, allocates or copies to the host. */
+SPTC_API sptc_status sptc_batch_execute(sptc_batch_t batch, int32_t* out_idx, double* out_val, int64_t* out_nnz,
+                                        void* scratch, void* stream);
+
+SPTC_API void sptc_batch_free(sptc_batch_t batch);
 
 #ifdef __cplusplus
 }

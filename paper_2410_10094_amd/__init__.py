@@ -19,7 +19,7 @@ from typing import Optional, Sequence
 from . import binding as _b
 from .binding import SptcError
 
-__all__ = ["DeviceCoo", "Plan", "plan", "contract", "SptcError", "default_options"]
+__all__ = ["DeviceCoo", "Plan", "plan", "contract", "Batch", "batch", "SptcError", "default_options"]
 
 
 def _torch():
@@ -103,7 +103,7 @@ class _TorchAllocator:
 class Plan:
     """A contraction plan (``sptc_plan``): Y grouped, X probed, products
     counted and the output hash sized.  ``execute`` may run any number of
-    times; the plan borrows X's and Y's device arrays."""
+    times; X's and Y's device arrays are read only while the plan is built."""
 
     def __init__(self, X: DeviceCoo, Y: DeviceCoo, cx: Sequence[int], cy: Sequence[int], options=None,
                  allocator: str = "pool", stream=None):
@@ -240,6 +240,134 @@ class Plan:
         counts = torch.empty(max(self.X.nnz, 1), dtype=torch.int64, device=self.X.val.device)
         _b.check(_b.load().sptc_plan_x_counts(self._h, counts.data_ptr(), _stream_handle(None)))
         return counts[: self.X.nnz]
+
+
+class Batch:
+    """Many independent contractions planned and executed together
+    (``sptc_batch_plan``): one pass of the grouped pipeline serves all of
+    them, and each gets its own COO output."""
+
+    def __init__(self, problems: Sequence[tuple], options=None, allocator: str = "pool", stream=None):
+        """problems: sequence of ``(X, Y, cx, cy)`` with DeviceCoo X and Y."""
+        torch = _torch()
+        lib = _b.load()
+        n = len(problems)
+        if not 1 <= n <= _b.BATCH_MAX:
+            raise ValueError(f"a batch holds 1..{_b.BATCH_MAX} contractions")
+        self.count = n
+        self._stream = _stream_handle(stream)
+        self.device = problems[0][0].val.device
+        xs = (_b.Coo * n)()
+        ys = (_b.Coo * n)()
+        nc = (ctypes.c_int32 * n)()
+        cxp = (ctypes.c_void_p * n)()
+        cyp = (ctypes.c_void_p * n)()
+        keep = []
+        for b, (X, Y, cx, cy) in enumerate(problems):
+            if len(cx) != len(cy):
+                raise ValueError("cx and cy must have the same length")
+            xs[b], kx = X.as_c()
+            ys[b], ky = Y.as_c()
+            acx, acy = _b.int_array(cx), _b.int_array(cy)
+            keep += [kx, ky, acx, acy]
+            nc[b] = len(cx)
+            cxp[b] = ctypes.cast(acx, ctypes.c_void_p)
+            cyp[b] = ctypes.cast(acy, ctypes.c_void_p)
+        opt = options if options is not None else _b.default_options()
+        self._allocator = None
+        alloc_ptr = None
+        if allocator == "torch":
+            self._allocator = _TorchAllocator(self.device.index if self.device.index is not None
+                                              else torch.cuda.current_device())
+            alloc_ptr = ctypes.byref(self._allocator.struct)
+        elif allocator != "pool":
+            raise ValueError("allocator must be 'pool' or 'torch'")
+        h = ctypes.c_void_p()
+        self._h = None
+        _b.check(lib.sptc_batch_plan(ctypes.byref(h), n, xs, ys, nc, cxp, cyp, ctypes.byref(opt), alloc_ptr,
+                                     self._stream))
+        self._h = h
+        ie, ve, sc, ws = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _b.check(lib.sptc_batch_sizes(self._h, ctypes.byref(ie), ctypes.byref(ve), ctypes.byref(sc),
+                                      ctypes.byref(ws)))
+        self.idx_elems, self.val_elems = ie.value, ve.value
+        self.scratch_bytes, self.workspace_bytes = sc.value, ws.value
+        self.items = []
+        for b in range(n):
+            info = _b.Info()
+            io, vo = ctypes.c_int64(), ctypes.c_int64()
+            _b.check(lib.sptc_batch_info(self._h, b, ctypes.byref(info), ctypes.byref(io), ctypes.byref(vo)))
+            self.items.append(dict(out_order=info.out_order,
+                                   out_dims=tuple(info.out_dims[m] for m in range(info.out_order)),
+                                   products=info.products, out_nnz_bound=info.out_nnz_bound,
+                                   idx_offset=io.value, val_offset=vo.value))
+        self.products = sum(it["products"] for it in self.items)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _b.load().sptc_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def output_bytes(self):
+        """Device bytes of outputs plus execute scratch: what pass 1's
+        product counts say one execute needs beyond the batch itself."""
+        return 4 * self.idx_elems + 8 * self.val_elems + self.scratch_bytes + 8 * self.count
+
+    def allocate_outputs(self):
+        """(idx, val, nnz, scratch) device tensors for execute_into."""
+        torch = _torch()
+        idx = torch.empty(max(self.idx_elems, 1), dtype=torch.int32, device=self.device)
+        val = torch.empty(max(self.val_elems, 1), dtype=torch.float64, device=self.device)
+        nnz = torch.empty(self.count, dtype=torch.int64, device=self.device)
+        scratch = torch.empty(max(self.scratch_bytes, 1), dtype=torch.uint8, device=self.device)
+        return idx, val, nnz, scratch
+
+    def execute_into(self, out_idx, out_val, out_nnz, scratch, stream=None):
+        """Enqueue ``sptc_batch_execute`` (no synchronisation).  ``scratch``
+        holds at least ``scratch_bytes`` and starts 256-byte aligned (torch's
+        allocations do)."""
+        if self.scratch_bytes and scratch.numel() * scratch.element_size() < self.scratch_bytes:
+            raise ValueError("scratch smaller than scratch_bytes")
+        _b.check(_b.load().sptc_batch_execute(self._h, out_idx.data_ptr(), out_val.data_ptr(), out_nnz.data_ptr(),
+                                              scratch.data_ptr() if self.scratch_bytes else None,
+                                              _stream_handle(stream)))
+
+    def views(self, out_idx, out_val, nnz_host):
+        """Per-contraction ``(idx [out_order, nnz], val [nnz])`` views of the
+        shared output buffers, given the nnz array on the host."""
+        res = []
+        for it, n in zip(self.items, nnz_host):
+            n = int(n)
+            if n < 0:
+                raise SptcError(-n, "reported by the device during batch execute")
+            cap, k = it["out_nnz_bound"], it["out_order"]
+            idx = out_idx[it["idx_offset"]: it["idx_offset"] + k * cap].view(k, cap)[:, :n]
+            val = out_val[it["val_offset"]: it["val_offset"] + n]
+            res.append((idx, val))
+        return res
+
+    def execute(self, stream=None):
+        """Run every contraction; returns a list of ``(idx, val)`` device
+        tensors (synchronises to read the nnz)."""
+        idx, val, nnz, scratch = self.allocate_outputs()
+        self.execute_into(idx, val, nnz, scratch, stream)
+        return self.views(idx, val, nnz.cpu().tolist())
+
+
+def batch(problems: Sequence[tuple], options=None, allocator: str = "pool", stream=None) -> Batch:
+    return Batch(problems, options=options, allocator=allocator, stream=stream)
 
 
 def plan(X: DeviceCoo, Y: DeviceCoo, cx: Sequence[int], cy: Sequence[int], options=None, allocator: str = "pool",

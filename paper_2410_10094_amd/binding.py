@@ -20,8 +20,11 @@ OK, ERR_INVALID_ARG, ERR_DIM_MISMATCH, ERR_KEY_OVERFLOW, ERR_OUT_OF_MEMORY, ERR_
 EXPORTS = (
     "sptc_default_options", "sptc_plan", "sptc_plan_info", "sptc_execute", "sptc_plan_status", "sptc_free",
     "sptc_status_string", "sptc_last_error", "sptc_plan_y_groups", "sptc_plan_y_grouped", "sptc_plan_x_counts",
-    "sptc_plan_set_stage_events", "sptc_plan_x_groups",
+    "sptc_plan_set_stage_events", "sptc_plan_x_groups", "sptc_batch_plan", "sptc_batch_sizes", "sptc_batch_info",
+    "sptc_batch_execute", "sptc_batch_free",
 )
+
+BATCH_MAX = 4096
 
 MODE_GROUPED, MODE_GLOBAL = 0, 1
 
@@ -105,6 +108,18 @@ def load():
     lib.sptc_plan_set_stage_events.restype = st
     lib.sptc_plan_x_groups.argtypes = [P, P, P, P, i64, ctypes.POINTER(i64), P]
     lib.sptc_plan_x_groups.restype = st
+    lib.sptc_batch_plan.argtypes = [ctypes.POINTER(P), i32, ctypes.POINTER(Coo), ctypes.POINTER(Coo), P, P, P,
+                                    ctypes.POINTER(Options), ctypes.POINTER(Allocator), P]
+    lib.sptc_batch_plan.restype = st
+    lib.sptc_batch_sizes.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                     ctypes.POINTER(i64)]
+    lib.sptc_batch_sizes.restype = st
+    lib.sptc_batch_info.argtypes = [P, i32, ctypes.POINTER(Info), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.sptc_batch_info.restype = st
+    lib.sptc_batch_execute.argtypes = [P, P, P, P, P, P]
+    lib.sptc_batch_execute.restype = st
+    lib.sptc_batch_free.argtypes = [P]
+    lib.sptc_batch_free.restype = None
     _lib = lib
     return lib
 

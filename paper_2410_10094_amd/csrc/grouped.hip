@@ -907,6 +907,20 @@ hipError_t launch_group_wave(const GroupArgs& a, const uint32_t* wlist, int64_t 
   return hipGetLastError();
 }
 
+// Dynamic LDS of the block class: a dense array of up to 2^kDenseBits cells
+// (8-byte value + 1-byte flag each) or a kBlockSlots-slot hash of 16-byte
+// slots.  Both exceed the default 64 KiB limit only in the dense case.
+constexpr size_t kBlockDenseLds = ((size_t)1 << kDenseBits) * 9;
+constexpr size_t kBlockHashLds = (size_t)kBlockSlots * 16;
+
+hipError_t prepare_group_block() {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_group_block<true>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kBlockDenseLds);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_group_block<false>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kBlockHashLds);
+}
+
 hipError_t launch_group_block(const GroupArgs& a, const uint32_t* blist, int64_t nb, int dense, int num_cus,
                               hipStream_t stream) {
   if (nb <= 0) return hipSuccess;
@@ -914,17 +928,9 @@ hipError_t launch_group_block(const GroupArgs& a, const uint32_t* blist, int64_t
   if (dense) {
     unsigned cells = 1u << a.bits_y;
     if (cells < (unsigned)kBBlock) cells = kBBlock;
-    const size_t lds = (size_t)cells * 9;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_group_block<true>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    k_group_block<true><<<grid, kBBlock, lds, stream>>>(a, blist, nb, cells);
+    k_group_block<true><<<grid, kBBlock, (size_t)cells * 9, stream>>>(a, blist, nb, cells);
   } else {
-    const size_t lds = (size_t)kBlockSlots * 16;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_group_block<false>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    k_group_block<false><<<grid, kBBlock, lds, stream>>>(a, blist, nb, 0u);
+    k_group_block<false><<<grid, kBBlock, kBlockHashLds, stream>>>(a, blist, nb, 0u);
   }
   return hipGetLastError();
 }

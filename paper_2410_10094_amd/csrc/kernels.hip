@@ -90,7 +90,7 @@ __global__ __launch_bounds__(256) void k_y_scatter(const int32_t* __restrict__ y
     ent.v = yval[e];
     yg[pos] = ent;
     if (yset) {  // a repeated full coordinate marks Y as having duplicates
-      const unsigned long long full = (key << bits_y) | ent.phi;
+      const unsigned long long full = full_y_key(key, ent.phi, bits_y);
       uint64_t h = fmix64(full ^ seed) & yset_mask;
       for (uint64_t probe = 0; probe <= yset_mask; ++probe) {
         const unsigned long long prev = atomicCAS(&yset[h], (unsigned long long)kEmpty, full);
@@ -411,7 +411,7 @@ __global__ __launch_bounds__(kAggBlock) void k_y_scatter_agg(const int32_t* __re
                   ent.phi = pack_key(yidx, nnz, e[u], kf);
                   ent.v = yval[e[u]];
                   yg[pos[u]] = ent;
-                  full[u] = (keys[u] << bits_y) | ent.phi;
+                  full[u] = full_y_key(keys[u], ent.phi, bits_y);
                 }
                 if (yset) {
                   bool seen[kAggUnroll];

@@ -233,6 +233,16 @@ hipError_t device_scan(Op op, int64_t n, void* tile_sums, Fin fin, hipStream_t s
   return hipGetLastError();
 }
 
+// Key of a whole Y coordinate for the repeated-coordinate check:
+// (contracting key << bits_y) | free key when that fits 63 bits (bits_y >= 0);
+// otherwise (bits_y < 0) a 64-bit mix of the two, where a collision can only
+// report a repeat that is not there (which merely disables an optimisation).
+__device__ __forceinline__ unsigned long long full_y_key(uint64_t ckey, uint64_t fkey, int32_t bits_y) {
+  if (bits_y >= 0) return (ckey << bits_y) | fkey;
+  unsigned long long h = fmix64(ckey * 0x9e3779b97f4a7c15ull ^ fmix64(fkey + 0x632be59bd9b4e019ull));
+  return h == kEmpty ? h - 1 : h;
+}
+
 // Home slot of a key in a table keyed by kp's packing.
 __device__ __forceinline__ uint64_t slot_of(uint64_t key, const KeyPack& kp, uint64_t seed, uint64_t mask) {
   return kp.ident ? (key & mask) : (fmix64(key ^ seed) & mask);

@@ -98,16 +98,62 @@ sptc_status configure_pool(int dev, DeviceInfo* d) {
 
 }  // namespace
 
-struct sptc_plan_s {
+// Device memory owned by a plan or batch: through the caller's allocator, or
+// the device's stream-ordered pool.
+struct Workspace {
   struct Buf {
     void* p;
     size_t bytes;
   };
-
-  int device = 0;
   hipStream_t stream = nullptr;
   bool has_alloc = false;
   sptc_allocator alloc{};
+  std::vector<Buf> bufs;
+  int64_t workspace = 0;
+
+  sptc_status allocate(size_t bytes, void** out) {
+    bytes = std::max<size_t>(bytes, 16);
+    bytes = (bytes + 255) & ~(size_t)255;
+    void* p = nullptr;
+    if (has_alloc) {
+      p = alloc.alloc(bytes, stream, alloc.ctx);
+      if (!p) return fail(SPTC_ERR_OUT_OF_MEMORY, "allocator returned NULL for %zu bytes", bytes);
+    } else {
+      hipError_t e = hipMallocAsync(&p, bytes, stream);
+      if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return fail(SPTC_ERR_OUT_OF_MEMORY, "hipMallocAsync(%zu bytes): %s", bytes, hipGetErrorString(e));
+      }
+    }
+    bufs.push_back({p, bytes});
+    workspace += (int64_t)bytes;
+    *out = p;
+    return SPTC_OK;
+  }
+
+  template <class T>
+  sptc_status allocate_n(int64_t n, T** out) {
+    void* p = nullptr;
+    sptc_status s = allocate(sizeof(T) * (size_t)std::max<int64_t>(n, 1), &p);
+    *out = static_cast<T*>(p);
+    return s;
+  }
+
+  void release_all() {
+    for (auto it = bufs.rbegin(); it != bufs.rend(); ++it) {
+      if (has_alloc) {
+        if (alloc.release) alloc.release(it->p, it->bytes, stream, alloc.ctx);
+      } else {
+        (void)hipFreeAsync(it->p, stream);
+      }
+    }
+    bufs.clear();
+    workspace = 0;
+  }
+};
+
+struct sptc_plan_s : Workspace {
+  int device = 0;
   sptc_options opt{};
   int num_cus = 1;
 
@@ -122,7 +168,6 @@ struct sptc_plan_s {
   Bounds xb{}, yb{};
   KeyUnpack out_unpack{}, ykey_unpack{}, yfree_unpack{};
 
-  std::vector<Buf> bufs;
   YSlot* ytab = nullptr;
   int64_t ytab_slots = 0;
   YEntry* yg = nullptr;
@@ -168,48 +213,37 @@ struct sptc_plan_s {
   KeyUnpack ux{}, uy{};
 
   int64_t products = 0, y_groups = 0, out_bound = 0;
-  int64_t workspace = 0;
   int32_t max_probe_y = 0, max_probe_z = 0;
+};
 
-  sptc_status allocate(size_t bytes, void** out) {
-    bytes = std::max<size_t>(bytes, 16);
-    bytes = (bytes + 255) & ~(size_t)255;
-    void* p = nullptr;
-    if (has_alloc) {
-      p = alloc.alloc(bytes, stream, alloc.ctx);
-      if (!p) return fail(SPTC_ERR_OUT_OF_MEMORY, "allocator returned NULL for %zu bytes", bytes);
-    } else {
-      hipError_t e = hipMallocAsync(&p, bytes, stream);
-      if (e != hipSuccess || !p) {
-        (void)hipGetLastError();
-        return fail(SPTC_ERR_OUT_OF_MEMORY, "hipMallocAsync(%zu bytes): %s", bytes, hipGetErrorString(e));
-      }
-    }
-    bufs.push_back({p, bytes});
-    workspace += (int64_t)bytes;
-    *out = p;
-    return SPTC_OK;
-  }
 
-  template <class T>
-  sptc_status allocate_n(int64_t n, T** out) {
-    void* p = nullptr;
-    sptc_status s = allocate(sizeof(T) * (size_t)std::max<int64_t>(n, 1), &p);
-    *out = static_cast<T*>(p);
-    return s;
-  }
+// Key layout of one contraction: contracting key in cx/cy order, free keys
+// in ascending mode order; the output is X free coordinates then Y free ones.
+struct Layout {
+  KeyPack x_c{}, y_c{}, x_f{}, y_f{};
+  int32_t bits_c = 0, bits_fx = 0, bits_fy = 0, nfy = 0, out_order = 0;
+  int64_t out_dims[SPTC_MAX_OUT_ORDER] = {};
+  Bounds xb{}, yb{};
+  KeyUnpack ux{}, uy{};
+  uint64_t ycells = 1;
+};
 
-  void release_all() {
-    for (auto it = bufs.rbegin(); it != bufs.rend(); ++it) {
-      if (has_alloc) {
-        if (alloc.release) alloc.release(it->p, it->bytes, stream, alloc.ctx);
-      } else {
-        (void)hipFreeAsync(it->p, stream);
-      }
-    }
-    bufs.clear();
-    workspace = 0;
-  }
+// A batch: the packed problem's plan plus each contraction's output layout.
+struct sptc_batch_s : Workspace {
+  int32_t count = 0;
+  sptc_plan_s* inner = nullptr;  // plan of the packed problem
+  BatchWidths w{};
+  struct Item {
+    Layout L;
+    int64_t products = 0, bound = 0, idx_off = 0, val_off = 0;
+  };
+  std::vector<Item> items;
+  BatchOut* outs = nullptr;  // device [count]
+  int64_t tcap = 0;          // packed outputs in the caller's scratch: 4 int32 index rows and a double row of tcap
+  int64_t scratch_bytes = 0;
+  int64_t* tnnz = nullptr;
+  unsigned long long* cursor = nullptr;
+  int64_t idx_elems = 0, val_elems = 0;
 };
 
 namespace {
@@ -316,6 +350,10 @@ sptc_status size_out_table(sptc_plan_s* P, int64_t products) {
   return SPTC_OK;
 }
 
+// Shift of the Y free key in the repeated-coordinate check, or -1 when the
+// whole coordinate does not fit 63 bits and the check hashes it instead.
+int32_t yset_bits(const sptc_plan_s* P) { return P->bits_c + P->bits_fy <= 63 ? P->bits_fy : -1; }
+
 // A1-A3: Y grouped by contracting key (both modes).
 sptc_status plan_group_y(sptc_plan_s* P, const sptc_coo* Y) {
   const hipStream_t s = P->stream;
@@ -336,10 +374,10 @@ sptc_status plan_group_y(sptc_plan_s* P, const sptc_coo* Y) {
   if (P->yset) HIP_TRY(launch_fill_keys(P->yset, P->yset_slots, s));
   if (P->y_agg)
     HIP_TRY(launch_y_scatter_agg(Y->idx, Y->val, P->ny, P->y_c, P->y_f, P->yb, P->ytab, (unsigned)P->ytab_slots,
-                                 P->yg, P->yset, (uint64_t)P->yset_slots - 1, seed, P->bits_fy, P->st, s));
+                                 P->yg, P->yset, (uint64_t)P->yset_slots - 1, seed, yset_bits(P), P->st, s));
   else
     HIP_TRY(launch_y_scatter(Y->idx, Y->val, P->ny, P->y_c, P->y_f, P->yb, P->ytab, ymask, seed, P->max_probe_y,
-                             P->yg, P->yset, (uint64_t)P->yset_slots - 1, P->bits_fy, P->st, P->num_cus, s));
+                             P->yg, P->yset, (uint64_t)P->yset_slots - 1, yset_bits(P), P->st, P->num_cus, s));
   if (P->opt.mode == SPTC_MODE_GROUPED && P->dense)
     HIP_TRY(launch_sort_y_runs(P->ytab, P->ytab_slots, P->yg, P->ny, P->ykey16, P->yval, P->num_cus, s));
   HIP_TRY(mark(P, s, SPTC_STAGE_Y_SCATTER, 1));
@@ -425,6 +463,7 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
   P->direct_products = (int64_t)host.direct_products;
   P->ydup = host.ydup ? 1 : 0;
   if (P->ngl < 0) return fail(SPTC_ERR_INTERNAL, "group classes do not add up");
+  if (P->nb > 0) HIP_TRY(prepare_group_block());
   if ((st = P->allocate_n(P->x_groups, &P->gn))) return st;
   if ((st = P->allocate_n(P->x_groups, &P->goff))) return st;
   if ((st = P->allocate_n(scan_tiles(P->nw) + 1, &P->etile_sums))) return st;
@@ -477,8 +516,8 @@ sptc_status plan_body(sptc_plan_s* P, const sptc_coo* X, const sptc_coo* Y, cons
   const int64_t tiles = std::max<int64_t>({scan_tiles(P->ytab_slots), scan_tiles(P->xtab_slots), scan_tiles(P->nx)});
   if ((st = P->allocate_n(2 * (tiles + 1), &P->tile_sums))) return st;  // room for pair-valued scans
   // Y coordinate set (grouped mode): finds repeated Y coordinates, which the
-  // direct class cannot have.  Needs the full Y coordinate in 63 bits.
-  const bool yset = grouped && P->bits_c + P->bits_fy <= 63;
+  // direct class cannot have.
+  const bool yset = grouped;
   if (yset) {
     P->yset_slots = pow2_at_least(4.0 * (double)std::max<int64_t>(P->ny, 1));  // sparse: short probes
     if ((st = P->allocate_n(P->yset_slots, &P->yset))) return st;
@@ -486,10 +525,215 @@ sptc_status plan_body(sptc_plan_s* P, const sptc_coo* X, const sptc_coo* Y, cons
   if ((st = P->allocate_n(1, &P->st))) return st;
   if ((st = P->allocate_n(2, &P->scratch))) return st;
   HIP_TRY(hipMemsetAsync(P->st, 0, sizeof(DevStatus), P->stream));
-  if (grouped && !yset)  // repeats cannot be ruled out: no direct class
-    HIP_TRY(hipMemsetAsync(reinterpret_cast<char*>(P->st) + offsetof(DevStatus, ydup), 1, 1, P->stream));
   if ((st = plan_group_y(P, Y))) return st;
   return grouped ? plan_grouped(P, X) : plan_global(P, X);
+}
+
+// Argument checks shared by single and batched plans (section 2.2: paired
+// modes must have equal length).
+sptc_status check_problem(const sptc_coo* X, const sptc_coo* Y, int32_t ncontract, const int32_t* cx,
+                          const int32_t* cy) {
+  sptc_status st;
+  if ((st = check_coo(X, "X"))) return st;
+  if ((st = check_coo(Y, "Y"))) return st;
+  if (ncontract < 0 || ncontract > X->order || ncontract > Y->order)
+    return fail(SPTC_ERR_INVALID_ARG, "ncontract %d outside 0..min(order_X, order_Y)", ncontract);
+  if (ncontract > 0 && (!cx || !cy)) return fail(SPTC_ERR_INVALID_ARG, "cx or cy is NULL");
+  for (int32_t t = 0; t < ncontract; ++t) {
+    if (cx[t] < 0 || cx[t] >= X->order) return fail(SPTC_ERR_INVALID_ARG, "cx[%d] = %d out of range", t, cx[t]);
+    if (cy[t] < 0 || cy[t] >= Y->order) return fail(SPTC_ERR_INVALID_ARG, "cy[%d] = %d out of range", t, cy[t]);
+    for (int32_t u = 0; u < t; ++u)
+      if (cx[u] == cx[t] || cy[u] == cy[t]) return fail(SPTC_ERR_INVALID_ARG, "a mode is contracted twice");
+  }
+  for (int32_t t = 0; t < ncontract; ++t)
+    if (X->dims[cx[t]] != Y->dims[cy[t]])
+      return fail(SPTC_ERR_DIM_MISMATCH, "X mode %d has length %lld but Y mode %d has length %lld", cx[t],
+                  (long long)X->dims[cx[t]], cy[t], (long long)Y->dims[cy[t]]);
+  return SPTC_OK;
+}
+
+void make_layout(const sptc_coo* X, const sptc_coo* Y, int32_t ncontract, const int32_t* cx, const int32_t* cy,
+                 int32_t validate, Layout* L) {
+  std::vector<int32_t> cxv(cx, cx + ncontract), cyv(cy, cy + ncontract), fx, fy;
+  for (int32_t m = 0; m < X->order; ++m)
+    if (std::find(cxv.begin(), cxv.end(), m) == cxv.end()) fx.push_back(m);
+  for (int32_t m = 0; m < Y->order; ++m)
+    if (std::find(cyv.begin(), cyv.end(), m) == cyv.end()) fy.push_back(m);
+  int32_t bits_cy = 0;
+  L->x_c = make_pack(X->dims, cxv, &L->bits_c);
+  L->y_c = make_pack(Y->dims, cyv, &bits_cy);
+  L->x_f = make_pack(X->dims, fx, &L->bits_fx);
+  L->y_f = make_pack(Y->dims, fy, &L->bits_fy);
+  // Small keys index their tables directly; the contracting key's choice
+  // holds for X's probes of Y's table too.
+  L->y_c.ident = L->x_c.ident = L->bits_c <= kIdentBits ? 1 : 0;
+  L->x_f.ident = L->bits_fx <= kIdentBits ? 1 : 0;
+  L->y_f.ident = 0;
+  L->nfy = (int32_t)fy.size();
+  L->out_order = (int32_t)(fx.size() + fy.size());
+  int32_t k = 0;
+  for (int32_t m : fx) L->out_dims[k++] = X->dims[m];
+  for (int32_t m : fy) L->out_dims[k++] = Y->dims[m];
+  add_unpack(L->ux, L->x_f, 0);
+  add_unpack(L->uy, L->y_f, 0);
+  L->ycells = (uint64_t)sat_prod(Y->dims, fy);
+  L->xb = make_bounds(X, validate);
+  L->yb = make_bounds(Y, validate);
+}
+
+sptc_status check_key_widths(const Layout& L, int32_t mode) {
+  if (L.bits_c > 63 || L.bits_fx > 63 || L.bits_fy > 63)
+    return fail(SPTC_ERR_KEY_OVERFLOW, "packed keys need %d (contracting), %d (X free), %d (Y free) bits; at most 63",
+                L.bits_c, L.bits_fx, L.bits_fy);
+  if (mode == SPTC_MODE_GLOBAL && L.bits_fx + L.bits_fy > 63)
+    return fail(SPTC_ERR_KEY_OVERFLOW, "output key needs %d bits (> 63); the grouped mode handles it",
+                L.bits_fx + L.bits_fy);
+  return SPTC_OK;
+}
+
+constexpr int32_t kBatchMax = 4096;  // k_batch_unpack keeps 12 bytes per contraction in LDS
+constexpr int64_t kPackTile = 8192;
+
+int64_t layout_cells(const Layout& L) {
+  int64_t cells = 1;
+  for (int32_t m = 0; m < L.out_order; ++m) {
+    if (cells > ((int64_t)1 << 62) / L.out_dims[m]) return (int64_t)1 << 62;
+    cells *= L.out_dims[m];
+  }
+  return cells;
+}
+
+// Packs every contraction's entries with its index as key prefix, plans the
+// packed problem, then sizes each contraction's output from its products.
+sptc_status batch_body(sptc_batch_s* B, const sptc_coo* X, const sptc_coo* Y, const sptc_options& o) {
+  const hipStream_t s = B->stream;
+  const int32_t count = B->count;
+  const int32_t wb = bits_for(count);
+  int32_t wc = 0, wx = 0, wy = 0;
+  int64_t nx = 0, ny = 0;
+  for (const auto& it : B->items) {
+    wc = std::max(wc, it.L.bits_c);
+    wx = std::max(wx, it.L.bits_fx);
+    wy = std::max(wy, it.L.bits_fy);
+  }
+  if (wb + wc > 62 || wb + wx > 62 || wy > 62)
+    return fail(SPTC_ERR_KEY_OVERFLOW, "batch keys need %d (contracting), %d (X free), %d (Y free) bits; at most 62",
+                wb + wc, wb + wx, wy);
+  B->w.wc = wc;
+  B->w.wx = wx;
+  B->w.wy = wy;
+  B->w.lo_c = std::min(wb + wc, 31);
+  B->w.lo_x = std::min(wb + wx, 31);
+  B->w.lo_y = std::min(wy, 31);
+
+  std::vector<BatchIn> in(count);
+  std::vector<PackTile> tiles;
+  for (int32_t b = 0; b < count; ++b) {
+    const Layout& L = B->items[b].L;
+    BatchIn& d = in[b];
+    d.xidx = X[b].idx;
+    d.xval = X[b].val;
+    d.yidx = Y[b].idx;
+    d.yval = Y[b].val;
+    d.nx = X[b].nnz;
+    d.ny = Y[b].nnz;
+    d.xoff = nx;
+    d.yoff = ny;
+    d.xc = L.x_c;
+    d.yc = L.y_c;
+    d.xf = L.x_f;
+    d.yf = L.y_f;
+    d.xb = L.xb;
+    d.yb = L.yb;
+    for (int64_t e = 0; e < d.nx; e += kPackTile) tiles.push_back({b, 0, e, std::min(d.nx, e + kPackTile)});
+    for (int64_t e = 0; e < d.ny; e += kPackTile) tiles.push_back({b, 1, e, std::min(d.ny, e + kPackTile)});
+    nx += d.nx;
+    ny += d.ny;
+  }
+  if (nx > (int64_t)0xfffffffeLL || ny > (int64_t)0xfffffffeLL)
+    return fail(SPTC_ERR_INVALID_ARG, "batch holds %lld X and %lld Y entries; at most 2^32-2 each", (long long)nx,
+                (long long)ny);
+
+  // Packed inputs live only until the packed plan has copied what it needs.
+  Workspace pk;
+  pk.stream = s;
+  pk.has_alloc = B->has_alloc;
+  pk.alloc = B->alloc;
+  struct Release {
+    Workspace& w;
+    ~Release() { w.release_all(); }
+  } release{pk};
+  BatchIn* in_d = nullptr;
+  PackTile* tiles_d = nullptr;
+  int32_t *px = nullptr, *py = nullptr;
+  double *pxv = nullptr, *pyv = nullptr;
+  unsigned* err = nullptr;
+  sptc_status st;
+  if ((st = pk.allocate_n(count, &in_d))) return st;
+  if ((st = pk.allocate_n((int64_t)tiles.size(), &tiles_d))) return st;
+  if ((st = pk.allocate_n(4 * nx, &px))) return st;
+  if ((st = pk.allocate_n(nx, &pxv))) return st;
+  if ((st = pk.allocate_n(4 * ny, &py))) return st;
+  if ((st = pk.allocate_n(ny, &pyv))) return st;
+  if ((st = pk.allocate_n(1, &err))) return st;
+  HIP_TRY(hipMemcpyAsync(in_d, in.data(), sizeof(BatchIn) * count, hipMemcpyHostToDevice, s));
+  if (!tiles.empty())
+    HIP_TRY(hipMemcpyAsync(tiles_d, tiles.data(), sizeof(PackTile) * tiles.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemsetAsync(err, 0, sizeof(unsigned), s));
+  HIP_TRY(launch_batch_pack(in_d, tiles_d, (int64_t)tiles.size(), B->w, px, pxv, nx, py, pyv, ny, err, s));
+  unsigned herr = 0;
+  HIP_TRY(hipMemcpyAsync(&herr, err, sizeof herr, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if ((st = status_from_bits(herr))) return st;
+
+  const int32_t kc = wb + wc, kx = wb + wx;
+  const int64_t xdims[4] = {(int64_t)1 << (kc - B->w.lo_c), (int64_t)1 << B->w.lo_c, (int64_t)1 << (kx - B->w.lo_x),
+                            (int64_t)1 << B->w.lo_x};
+  const int64_t ydims[4] = {xdims[0], xdims[1], (int64_t)1 << (wy - B->w.lo_y), (int64_t)1 << B->w.lo_y};
+  const sptc_coo PX{4, xdims, nx, px, pxv}, PY{4, ydims, ny, py, pyv};
+  const int32_t cmodes[2] = {0, 1};
+  sptc_options io = o;
+  io.validate = 0;  // packed coordinates are in range by construction; the pack checked the originals
+  sptc_plan_t inner = nullptr;
+  if ((st = sptc_plan(&inner, &PX, &PY, 2, cmodes, cmodes, &io, B->has_alloc ? &B->alloc : nullptr, s))) return st;
+  B->inner = inner;
+
+  // Products per contraction, from the packed plan's X groups.
+  unsigned long long* pb = nullptr;
+  if ((st = pk.allocate_n(count, &pb))) return st;
+  HIP_TRY(launch_zero_u64(pb, count, s));
+  HIP_TRY(launch_batch_products(inner->groups, inner->x_groups, inner->eoff, wx, count, pb, s));
+  std::vector<unsigned long long> hpb(count);
+  HIP_TRY(hipMemcpyAsync(hpb.data(), pb, sizeof(unsigned long long) * count, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  int64_t total = 0;
+  std::vector<BatchOut> outs(count);
+  for (int32_t b = 0; b < count; ++b) {
+    auto& it = B->items[b];
+    it.products = (int64_t)hpb[b];
+    total += it.products;
+    it.bound = std::min<int64_t>(it.products, layout_cells(it.L));
+    it.idx_off = B->idx_elems;
+    it.val_off = B->val_elems;
+    B->idx_elems += (int64_t)it.L.out_order * it.bound;
+    B->val_elems += it.bound;
+    outs[b].ux = it.L.ux;
+    outs[b].uy = it.L.uy;
+    outs[b].idx_off = it.idx_off;
+    outs[b].val_off = it.val_off;
+    outs[b].cap = it.bound;
+  }
+  if (total != inner->products)
+    return fail(SPTC_ERR_INTERNAL, "per-contraction products add up to %lld, not %lld", (long long)total,
+                (long long)inner->products);
+  B->tcap = inner->out_bound;
+  B->scratch_bytes = B->tcap * (int64_t)(sizeof(double) + 4 * sizeof(int32_t));
+  if ((st = B->allocate_n(count, &B->outs))) return st;
+  if ((st = B->allocate_n(1, &B->tnnz))) return st;
+  if ((st = B->allocate_n(count, &B->cursor))) return st;
+  HIP_TRY(hipMemcpyAsync(B->outs, outs.data(), sizeof(BatchOut) * count, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));  // host arrays above are copied before they go out of scope
+  return SPTC_OK;
 }
 
 }  // namespace
@@ -512,35 +756,16 @@ sptc_status sptc_plan(sptc_plan_t* plan, const sptc_coo* X, const sptc_coo* Y, i
   if (!plan) return fail(SPTC_ERR_INVALID_ARG, "plan is NULL");
   *plan = nullptr;
   sptc_status st;
-  if ((st = check_coo(X, "X"))) return st;
-  if ((st = check_coo(Y, "Y"))) return st;
-  if (ncontract < 0 || ncontract > X->order || ncontract > Y->order)
-    return fail(SPTC_ERR_INVALID_ARG, "ncontract %d outside 0..min(order_X, order_Y)", ncontract);
-  if (ncontract > 0 && (!cx || !cy)) return fail(SPTC_ERR_INVALID_ARG, "cx or cy is NULL");
-  for (int32_t t = 0; t < ncontract; ++t) {
-    if (cx[t] < 0 || cx[t] >= X->order) return fail(SPTC_ERR_INVALID_ARG, "cx[%d] = %d out of range", t, cx[t]);
-    if (cy[t] < 0 || cy[t] >= Y->order) return fail(SPTC_ERR_INVALID_ARG, "cy[%d] = %d out of range", t, cy[t]);
-    for (int32_t u = 0; u < t; ++u)
-      if (cx[u] == cx[t] || cy[u] == cy[t]) return fail(SPTC_ERR_INVALID_ARG, "a mode is contracted twice");
-  }
-  for (int32_t t = 0; t < ncontract; ++t)
-    if (X->dims[cx[t]] != Y->dims[cy[t]])
-      return fail(SPTC_ERR_DIM_MISMATCH, "X mode %d has length %lld but Y mode %d has length %lld", cx[t],
-                  (long long)X->dims[cx[t]], cy[t], (long long)Y->dims[cy[t]]);
+  if ((st = check_problem(X, Y, ncontract, cx, cy))) return st;
   sptc_options o;
   sptc_default_options(&o);
   if (opt) o = *opt;
   if ((st = check_options(o))) return st;
   if (alloc && (!alloc->alloc || !alloc->release))
     return fail(SPTC_ERR_INVALID_ARG, "allocator must provide alloc and release");
-
-  // Key layout: contracting key in cx/cy order, free keys in ascending mode
-  // order, output key = (X free << Y free bits) | Y free.
-  std::vector<int32_t> cxv(cx, cx + ncontract), cyv(cy, cy + ncontract), fx, fy;
-  for (int32_t m = 0; m < X->order; ++m)
-    if (std::find(cxv.begin(), cxv.end(), m) == cxv.end()) fx.push_back(m);
-  for (int32_t m = 0; m < Y->order; ++m)
-    if (std::find(cyv.begin(), cyv.end(), m) == cyv.end()) fy.push_back(m);
+  Layout L;
+  make_layout(X, Y, ncontract, cx, cy, o.validate, &L);
+  if ((st = check_key_widths(L, o.mode))) return st;
 
   sptc_plan_s* P = new (std::nothrow) sptc_plan_s();
   if (!P) return fail(SPTC_ERR_OUT_OF_MEMORY, "host allocation failed");
@@ -555,47 +780,30 @@ sptc_status sptc_plan(sptc_plan_t* plan, const sptc_coo* X, const sptc_coo* Y, i
   P->nc = ncontract;
   P->nx = X->nnz;
   P->ny = Y->nnz;
-  int32_t bits_cx = 0, bits_cy = 0;
-  P->x_c = make_pack(X->dims, cxv, &bits_cx);
-  P->y_c = make_pack(Y->dims, cyv, &bits_cy);
-  P->x_f = make_pack(X->dims, fx, &P->bits_fx);
-  P->y_f = make_pack(Y->dims, fy, &P->bits_fy);
-  P->bits_c = bits_cx;
-  P->nfy = (int32_t)fy.size();
-  P->out_order = (int32_t)(fx.size() + fy.size());
-  {
-    int32_t k = 0;
-    for (int32_t m : fx) P->out_dims[k++] = X->dims[m];
-    for (int32_t m : fy) P->out_dims[k++] = Y->dims[m];
+  P->x_c = L.x_c;
+  P->y_c = L.y_c;
+  P->x_f = L.x_f;
+  P->y_f = L.y_f;
+  P->bits_c = L.bits_c;
+  P->bits_fx = L.bits_fx;
+  P->bits_fy = L.bits_fy;
+  P->nfy = L.nfy;
+  P->out_order = L.out_order;
+  for (int32_t m = 0; m < L.out_order; ++m) P->out_dims[m] = L.out_dims[m];
+  if (L.bits_fx + L.bits_fy <= 63) {  // packed output key (global mode, global class)
+    add_unpack(P->out_unpack, P->x_f, P->bits_fy);
+    add_unpack(P->out_unpack, P->y_f, 0);
   }
-  add_unpack(P->out_unpack, P->x_f, P->bits_fy);
-  add_unpack(P->out_unpack, P->y_f, 0);
   add_unpack(P->ykey_unpack, P->y_c, 0);
   add_unpack(P->yfree_unpack, P->y_f, 0);
-  // Small keys index their tables directly; the contracting key's choice
-  // holds for X's probes of Y's table too.
-  P->y_c.ident = P->x_c.ident = P->bits_c <= kIdentBits ? 1 : 0;
-  P->x_f.ident = P->bits_fx <= kIdentBits ? 1 : 0;
-  P->y_f.ident = 0;
   P->y_agg = P->bits_c <= kAggBits ? 1 : 0;
   P->x_agg = (o.mode == SPTC_MODE_GROUPED && P->bits_fx <= kAggBits) ? 1 : 0;
-  add_unpack(P->ux, P->x_f, 0);
-  add_unpack(P->uy, P->y_f, 0);
-  P->ycells = (uint64_t)sat_prod(Y->dims, fy);
+  P->ux = L.ux;
+  P->uy = L.uy;
+  P->ycells = L.ycells;
   P->dense = P->bits_fy <= kDenseBits ? 1 : 0;
-  P->xb = make_bounds(X, o.validate);
-  P->yb = make_bounds(Y, o.validate);
-  if (P->bits_c > 63 || P->bits_fx > 63 || P->bits_fy > 63) {
-    const int32_t bc = P->bits_c, bx = P->bits_fx, by = P->bits_fy;
-    delete P;
-    return fail(SPTC_ERR_KEY_OVERFLOW, "packed keys need %d (contracting), %d (X free), %d (Y free) bits; at most 63",
-                bc, bx, by);
-  }
-  if (o.mode == SPTC_MODE_GLOBAL && P->bits_fx + P->bits_fy > 63) {
-    const int32_t b = P->bits_fx + P->bits_fy;
-    delete P;
-    return fail(SPTC_ERR_KEY_OVERFLOW, "output key needs %d bits (> 63); the grouped mode handles it", b);
-  }
+  P->xb = L.xb;
+  P->yb = L.yb;
 
   DeviceInfo* di = nullptr;
   hipError_t e = hipGetDevice(&P->device);
@@ -799,6 +1007,114 @@ sptc_status sptc_plan_x_counts(sptc_plan_t P, int64_t* counts, void* stream) {
   if (P->nx > 0 && !counts) return fail(SPTC_ERR_INVALID_ARG, "counts is NULL");
   HIP_TRY(launch_x_counts(P->poff, P->nx, counts, static_cast<hipStream_t>(stream)));
   return SPTC_OK;
+}
+
+sptc_status sptc_batch_plan(sptc_batch_t* batch, int32_t count, const sptc_coo* X, const sptc_coo* Y,
+                            const int32_t* ncontract, const int32_t* const* cx, const int32_t* const* cy,
+                            const sptc_options* opt, const sptc_allocator* alloc, void* stream) {
+  if (!batch) return fail(SPTC_ERR_INVALID_ARG, "batch is NULL");
+  *batch = nullptr;
+  if (count < 1 || count > kBatchMax) return fail(SPTC_ERR_INVALID_ARG, "count %d outside 1..%d", count, kBatchMax);
+  if (!X || !Y || !ncontract || !cx || !cy) return fail(SPTC_ERR_INVALID_ARG, "a batch array is NULL");
+  sptc_options o;
+  sptc_default_options(&o);
+  if (opt) o = *opt;
+  sptc_status st;
+  if ((st = check_options(o))) return st;
+  if (o.mode != SPTC_MODE_GROUPED) return fail(SPTC_ERR_INVALID_ARG, "batches run in the grouped mode only");
+  if (alloc && (!alloc->alloc || !alloc->release))
+    return fail(SPTC_ERR_INVALID_ARG, "allocator must provide alloc and release");
+  sptc_batch_s* B = new (std::nothrow) sptc_batch_s();
+  if (!B) return fail(SPTC_ERR_OUT_OF_MEMORY, "host allocation failed");
+  B->count = count;
+  B->items.resize(count);
+  for (int32_t b = 0; b < count; ++b) {
+    st = check_problem(&X[b], &Y[b], ncontract[b], cx[b], cy[b]);
+    if (st == SPTC_OK) {
+      make_layout(&X[b], &Y[b], ncontract[b], cx[b], cy[b], o.validate, &B->items[b].L);
+      st = check_key_widths(B->items[b].L, o.mode);
+    }
+    if (st != SPTC_OK) {
+      g_last_error = "contraction " + std::to_string(b) + ": " + g_last_error;
+      delete B;
+      return st;
+    }
+  }
+  B->stream = static_cast<hipStream_t>(stream);
+  if (alloc) {
+    B->has_alloc = true;
+    B->alloc = *alloc;
+  }
+  st = batch_body(B, X, Y, o);
+  if (st != SPTC_OK) {
+    std::string msg = g_last_error;
+    (void)hipStreamSynchronize(B->stream);
+    if (B->inner) sptc_free(B->inner);
+    B->release_all();
+    delete B;
+    g_last_error = msg;
+    return st;
+  }
+  *batch = B;
+  return SPTC_OK;
+}
+
+sptc_status sptc_batch_sizes(sptc_batch_t B, int64_t* idx_elems, int64_t* val_elems, int64_t* scratch_bytes,
+                             int64_t* workspace_bytes) {
+  if (!B) return fail(SPTC_ERR_INVALID_ARG, "batch is NULL");
+  if (idx_elems) *idx_elems = B->idx_elems;
+  if (val_elems) *val_elems = B->val_elems;
+  if (scratch_bytes) *scratch_bytes = B->scratch_bytes;
+  if (workspace_bytes) *workspace_bytes = B->workspace + (B->inner ? B->inner->workspace : 0);
+  return SPTC_OK;
+}
+
+sptc_status sptc_batch_info(sptc_batch_t B, int32_t b, sptc_info* info, int64_t* idx_offset, int64_t* val_offset) {
+  if (!B) return fail(SPTC_ERR_INVALID_ARG, "batch is NULL");
+  if (b < 0 || b >= B->count) return fail(SPTC_ERR_INVALID_ARG, "contraction %d outside 0..%d", b, B->count - 1);
+  const auto& it = B->items[b];
+  if (info) {
+    std::memset(info, 0, sizeof *info);
+    info->out_order = it.L.out_order;
+    for (int32_t m = 0; m < it.L.out_order; ++m) info->out_dims[m] = it.L.out_dims[m];
+    info->products = it.products;
+    info->out_nnz_bound = it.bound;
+    info->key_bits_contract = it.L.bits_c;
+    info->key_bits_x_free = it.L.bits_fx;
+    info->key_bits_y_free = it.L.bits_fy;
+  }
+  if (idx_offset) *idx_offset = it.idx_off;
+  if (val_offset) *val_offset = it.val_off;
+  return SPTC_OK;
+}
+
+sptc_status sptc_batch_execute(sptc_batch_t B, int32_t* out_idx, double* out_val, int64_t* out_nnz, void* scratch,
+                               void* stream) {
+  if (!B) return fail(SPTC_ERR_INVALID_ARG, "batch is NULL");
+  if (!out_nnz) return fail(SPTC_ERR_INVALID_ARG, "out_nnz is NULL");
+  if (B->val_elems > 0 && !out_val) return fail(SPTC_ERR_INVALID_ARG, "out_val is NULL");
+  if (B->idx_elems > 0 && !out_idx) return fail(SPTC_ERR_INVALID_ARG, "out_idx is NULL");
+  if (B->scratch_bytes > 0 && !scratch) return fail(SPTC_ERR_INVALID_ARG, "scratch is NULL");
+  if (reinterpret_cast<uintptr_t>(scratch) % 256) return fail(SPTC_ERR_INVALID_ARG, "scratch is not 256-byte aligned");
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  // packed outputs: values first (8-byte aligned), then 4 index rows
+  double* tval = static_cast<double*>(scratch);
+  int32_t* tidx = reinterpret_cast<int32_t*>(tval + B->tcap);
+  sptc_status st;
+  if ((st = sptc_execute(B->inner, tidx, tval, B->tcap, B->tnnz, stream))) return st;
+  HIP_TRY(launch_zero_u64(B->cursor, B->count, s));
+  HIP_TRY(launch_batch_unpack(tidx, tval, B->tcap, B->tnnz, B->w, B->count, B->outs, out_idx, out_val, B->cursor,
+                              s));
+  HIP_TRY(launch_batch_finalize(B->tnnz, B->cursor, B->outs, B->count, out_nnz, s));
+  return SPTC_OK;
+}
+
+void sptc_batch_free(sptc_batch_t B) {
+  if (!B) return;
+  (void)hipStreamSynchronize(B->stream);
+  if (B->inner) sptc_free(B->inner);
+  B->release_all();
+  delete B;
 }
 
 }  // extern "C"

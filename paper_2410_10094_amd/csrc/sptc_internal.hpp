@@ -254,6 +254,9 @@ hipError_t launch_group_wave(const GroupArgs& a, const uint32_t* wlist, int64_t 
 
 // Block class, single pass: each workgroup accumulates a group, reserves its
 // outputs with one atomic on st->out_base and writes them.
+// Raises the block-class kernels' dynamic LDS limit on the current device;
+// called once per plan so that execute issues kernel launches only.
+hipError_t prepare_group_block();
 hipError_t launch_group_block(const GroupArgs& a, const uint32_t* blist, int64_t nb, int dense, int num_cus,
                               hipStream_t stream);
 
@@ -290,5 +293,58 @@ hipError_t launch_y_groups(const YSlot* tab, int64_t nslots, KeyUnpack ku, int32
 hipError_t launch_y_grouped(const YEntry* yg, int64_t nnz, KeyUnpack ku, int32_t* free_coords, double* vals,
                             hipStream_t stream);
 hipError_t launch_x_counts(const unsigned long long* poff, int64_t nx, int64_t* counts, hipStream_t stream);
+
+// ---- batched contraction (batch.hip) ----
+
+// One contraction of a batch, as the pack kernel reads it.
+struct BatchIn {
+  const int32_t* xidx;
+  const double* xval;
+  const int32_t* yidx;
+  const double* yval;
+  int64_t nx, ny, xoff, yoff;  // nnz and place in the concatenation
+  KeyPack xc, yc, xf, yf;      // contracting and free keys
+  Bounds xb, yb;
+};
+
+// A run of one contraction's X (side 0) or Y (side 1) entries to pack.
+struct PackTile {
+  int32_t b;
+  int32_t side;
+  int64_t start, end;
+};
+
+// Where contraction b's output goes and how to decode it.
+struct BatchOut {
+  KeyUnpack ux, uy;
+  int64_t idx_off, val_off, cap;
+};
+
+// Packed key widths: a key of w bits is stored as (key >> lo, key & (2^lo - 1)).
+struct BatchWidths {
+  int32_t wc, wx;        // contracting / X free key widths before the index prefix
+  int32_t lo_c, lo_x, lo_y;
+  int32_t wy;
+};
+
+hipError_t launch_batch_pack(const BatchIn* in, const PackTile* tiles, int64_t ntiles, BatchWidths w, int32_t* px,
+                             double* pxv, int64_t nx_total, int32_t* py, double* pyv, int64_t ny_total,
+                             unsigned* err, hipStream_t stream);
+
+// Per contraction: the sum of its groups' product counts.
+hipError_t launch_batch_products(const GroupRec* groups, int64_t ngroups, const unsigned long long* eoff,
+                                 int32_t wx, int32_t count, unsigned long long* pb, hipStream_t stream);
+
+// Zeroes n 8-byte words.
+hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t stream);
+
+// Sorts the packed outputs (4 index rows: X free key hi/lo, Y free key
+// hi/lo) into the contractions' outputs; cursor[b] ends as b's nnz.
+hipError_t launch_batch_unpack(const int32_t* tidx, const double* tval, int64_t tcap, const int64_t* tnnz,
+                               BatchWidths w, int32_t count, const BatchOut* outs, int32_t* out_idx, double* out_val,
+                               unsigned long long* cursor, hipStream_t stream);
+
+hipError_t launch_batch_finalize(const int64_t* tnnz, const unsigned long long* cursor, const BatchOut* outs,
+                                 int32_t count, int64_t* out_nnz, hipStream_t stream);
 
 }  // namespace sptc

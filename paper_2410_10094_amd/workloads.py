@@ -216,42 +216,50 @@ def random_problem(seed: int, order_x: int, order_y: int, ncontract: int, dim_lo
     return Problem(f"random-{seed}", make(rx, xd, nnz_x), make(ry, yd, nnz_y), cx, cy)
 
 
-def batched_draws(seed: int = BASE_SEED + 4, count: int = 512, max_products: int = 1 << 28,
-                  nnz_lo: float = 1e3, nnz_hi: float = 1e6) -> List[Problem]:
-    """Draws of the batched workload: orders of X and Y uniform in {3,4,5},
-    1-2 contracted pairs on distinct random modes, every dim uniform in
-    [32, 4096] with Y's contracted dims copied from X's, nnz log-uniform in
+def batched_draw(seed: int, i: int, max_products: int = 1 << 28, nnz_lo: float = 1e3,
+                 nnz_hi: float = 1e6) -> Problem:
+    """Draw ``i`` of the batched workload: orders of X and Y uniform in
+    {3,4,5}, 1-2 contracted pairs on distinct random modes, every dim uniform
+    in [32, 4096] with Y's contracted dims copied from X's, nnz log-uniform in
     [nnz_lo, nnz_hi] clamped to 10% density, distinct coordinates, values
     U[-1,1).  A draw whose expected product count for uniform coordinates,
     nnz_X * nnz_Y / (product of the contracted dims), exceeds
-    ``max_products`` is redrawn."""
-    root = np.random.SeedSequence(int(seed))
-    out = []
-    for i, child in enumerate(root.spawn(count)):
-        attempt = 0
-        while True:
-            ss = np.random.SeedSequence(child.entropy, spawn_key=child.spawn_key + (attempt,))
-            rng, rx, ry = [np.random.Generator(np.random.PCG64(s)) for s in ss.spawn(3)]
-            ox, oy = int(rng.integers(3, 6)), int(rng.integers(3, 6))
-            nc = int(rng.integers(1, 3))
-            xd = [int(d) for d in rng.integers(32, 4097, size=ox)]
-            yd = [int(d) for d in rng.integers(32, 4097, size=oy)]
-            cx = [int(c) for c in rng.permutation(ox)[:nc]]
-            cy = [int(c) for c in rng.permutation(oy)[:nc]]
-            for a, b in zip(cx, cy):
-                yd[b] = xd[a]
-            nx = int(round(math.exp(rng.uniform(math.log(nnz_lo), math.log(nnz_hi)))))
-            ny = int(round(math.exp(rng.uniform(math.log(nnz_lo), math.log(nnz_hi)))))
-            nx = min(nx, max(1, math.prod(xd) // 10))
-            ny = min(ny, max(1, math.prod(yd) // 10))
-            expected = nx * ny / math.prod(xd[c] for c in cx)
-            if expected <= max_products:
-                X = Coo(xd, unique_coords(rx, xd, nx), nonzero_uniform(rx, nx))
-                Y = Coo(yd, unique_coords(ry, yd, ny), nonzero_uniform(ry, ny))
-                out.append(Problem(f"batched-{i}", X, Y, cx, cy))
-                break
-            attempt += 1
-    return out
+    ``max_products`` is redrawn.  Draw i depends only on (seed, i)."""
+    child = np.random.SeedSequence(int(seed), spawn_key=(int(i),))
+    attempt = 0
+    while True:
+        ss = np.random.SeedSequence(child.entropy, spawn_key=child.spawn_key + (attempt,))
+        rng, rx, ry = [np.random.Generator(np.random.PCG64(s)) for s in ss.spawn(3)]
+        ox, oy = int(rng.integers(3, 6)), int(rng.integers(3, 6))
+        nc = int(rng.integers(1, 3))
+        xd = [int(d) for d in rng.integers(32, 4097, size=ox)]
+        yd = [int(d) for d in rng.integers(32, 4097, size=oy)]
+        cx = [int(c) for c in rng.permutation(ox)[:nc]]
+        cy = [int(c) for c in rng.permutation(oy)[:nc]]
+        for a, b in zip(cx, cy):
+            yd[b] = xd[a]
+        nx = int(round(math.exp(rng.uniform(math.log(nnz_lo), math.log(nnz_hi)))))
+        ny = int(round(math.exp(rng.uniform(math.log(nnz_lo), math.log(nnz_hi)))))
+        nx = min(nx, max(1, math.prod(xd) // 10))
+        ny = min(ny, max(1, math.prod(yd) // 10))
+        expected = nx * ny / math.prod(xd[c] for c in cx)
+        if expected <= max_products:
+            X = Coo(xd, unique_coords(rx, xd, nx), nonzero_uniform(rx, nx))
+            Y = Coo(yd, unique_coords(ry, yd, ny), nonzero_uniform(ry, ny))
+            return Problem(f"batched-{i}", X, Y, cx, cy)
+        attempt += 1
+
+
+def batched_draws(seed: int = BASE_SEED + 4, count: int = 512, max_products: int = 1 << 28,
+                  nnz_lo: float = 1e3, nnz_hi: float = 1e6) -> List[Problem]:
+    """The first ``count`` draws of the batched workload (batched_draw)."""
+    return [batched_draw(seed, i, max_products, nnz_lo, nnz_hi) for i in range(count)]
+
+
+def expected_products(p: Problem) -> float:
+    """nnz_X * nnz_Y / (product of the contracted dims): the product count
+    for independent uniform coordinates."""
+    return p.X.nnz * p.Y.nnz / math.prod(p.X.dims[c] for c in p.cx)
 
 
 def paper_set(seed: int, mode_len: int, nnz: int, order_x: int = 5, order_y: int = 4) -> Problem:

@@ -137,3 +137,60 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="missing"):
         B.load()
+
+
+def _batch_plan(problems, opt=None, count=None):
+    """problems: list of (X, Y, cx, cy) sptc_coo structs and mode lists."""
+    lib = B.load()
+    n = len(problems)
+    xs = (B.Coo * max(n, 1))(*[p[0] for p in problems])
+    ys = (B.Coo * max(n, 1))(*[p[1] for p in problems])
+    nc = (ctypes.c_int32 * max(n, 1))(*[len(p[2]) for p in problems])
+    arrs = [(B.int_array(p[2]), B.int_array(p[3])) for p in problems]
+    cxp = (ctypes.c_void_p * max(n, 1))(*[ctypes.cast(a, ctypes.c_void_p).value for a, _ in arrs])
+    cyp = (ctypes.c_void_p * max(n, 1))(*[ctypes.cast(b, ctypes.c_void_p).value for _, b in arrs])
+    h = ctypes.c_void_p(12345)
+    st = lib.sptc_batch_plan(ctypes.byref(h), n if count is None else count, xs, ys, nc, cxp, cyp,
+                             ctypes.byref(opt) if opt is not None else None, None, None)
+    return st, h.value
+
+
+@pytest.mark.parametrize("case,status", [
+    ("zero_count", B.ERR_INVALID_ARG),
+    ("count_too_big", B.ERR_INVALID_ARG),
+    ("global_mode", B.ERR_INVALID_ARG),
+    ("bad_member", B.ERR_DIM_MISMATCH),
+    ("member_key_overflow", B.ERR_KEY_OVERFLOW),
+    ("batch_key_overflow", B.ERR_KEY_OVERFLOW),
+])
+def test_batch_plan_validation(case, status):
+    good = (coo((8, 9, 10)), coo((10, 9, 7)), [2], [0])
+    probs, opt, count = [good, good], None, None
+    if case == "zero_count":
+        count = 0
+    elif case == "count_too_big":
+        count = B.BATCH_MAX + 1
+    elif case == "global_mode":
+        opt = B.default_options()
+        opt.mode = B.MODE_GLOBAL
+    elif case == "bad_member":
+        probs = [good, (coo((8, 9, 10)), coo((10, 9, 7)), [1], [0])]
+    elif case == "member_key_overflow":
+        probs = [good, (coo((1 << 30, 1 << 30, 1 << 30, 10)), coo((10, 9, 7)), [3], [0])]
+    elif case == "batch_key_overflow":
+        # a 62-bit X free key leaves no room for the contraction index
+        probs = [good, (coo((1 << 31, 1 << 31, 10)), coo((10, 9, 7)), [2], [0])]
+    st, h = _batch_plan(probs, opt, count)
+    assert st == status, (st, B.last_error())
+    assert h is None
+    if case == "bad_member":
+        assert B.last_error().startswith("contraction 1:")
+
+
+def test_batch_functions_reject_null():
+    lib = B.load()
+    assert lib.sptc_batch_execute(None, None, None, None, None, None) == B.ERR_INVALID_ARG
+    assert lib.sptc_batch_sizes(None, None, None, None, None) == B.ERR_INVALID_ARG
+    assert lib.sptc_batch_info(None, 0, None, None, None) == B.ERR_INVALID_ARG
+    lib.sptc_batch_free(None)
+    assert lib.sptc_batch_plan(None, 1, None, None, None, None, None, None, None, None) == B.ERR_INVALID_ARG
