@@ -202,20 +202,11 @@ def percentile(xs, q):
 
 
 def sub_batches(draws, budget):
-    """Consecutive runs of draws whose expected products stay within budget."""
-    from paper_2410_10094_amd import binding as B
+    """Batches of draws: bucketed by Y free key class, cut at `budget`
+    expected products."""
+    from paper_2410_10094_amd import sched
     from paper_2410_10094_amd import workloads as W
-    out, cur, acc = [], [], 0.0
-    for i, p in enumerate(draws):
-        e = W.expected_products(p)
-        if cur and (acc + e > budget or len(cur) >= B.BATCH_MAX):
-            out.append(cur)
-            cur, acc = [], 0.0
-        cur.append(i)
-        acc += e
-    if cur:
-        out.append(cur)
-    return out
+    return sched.make_batches(draws, W.expected_products, lambda p: sched.shape_class(p.Y.dims, p.cy), budget)
 
 
 def run_batched(draws, steps, warmup, budget):
@@ -266,15 +257,31 @@ def run_batched(draws, steps, warmup, budget):
     bnnz = torch.empty(len(draws), dtype=torch.int64, device="cuda")
     bscr = torch.empty(max(need_s, 1), dtype=torch.uint8, device="cuda")
 
-    def batched(lat):
-        for g in groups:
+    from paper_2410_10094_amd import binding as B
+    nst = len(B.STAGES)
+    stream = torch.cuda.current_stream()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2 * nst)] for _ in groups]
+    for row in evs:
+        for e in row:
+            e.record(stream)
+    ev_arrays = [(ctypes.c_void_p * (2 * nst))(*[e.cuda_event for e in row]) for row in evs]
+    stage_ms = {s: 0.0 for s in B.STAGES}
+
+    def batched(lat, timed=False):
+        for k, g in enumerate(groups):
+            opt = sptc.default_options()
+            if timed:
+                opt.stage_events = ctypes.cast(ev_arrays[k], ctypes.POINTER(ctypes.c_void_p))
             t0 = time.perf_counter()
-            bt = sptc.batch([(dev[i][0], dev[i][1], draws[i].cx, draws[i].cy) for i in g])
+            bt = sptc.batch([(dev[i][0], dev[i][1], draws[i].cx, draws[i].cy) for i in g], options=opt)
             bt.execute_into(bidx, bval, bnnz[g[0]:g[0] + len(g)], bscr)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             lat.extend([dt] * len(g))
             bt.close()
+            if timed:
+                for j, sname in enumerate(B.STAGES):
+                    stage_ms[sname] += evs[k][2 * j].elapsed_time(evs[k][2 * j + 1])
 
     res = {}
     for name, fn, nnz in (("per_call", per_call, onnz), ("batched", batched, bnnz)):
@@ -284,7 +291,7 @@ def run_batched(draws, steps, warmup, budget):
         lat = []
         t0 = time.perf_counter()
         for _ in range(steps):
-            fn(lat)
+            fn(lat) if fn is per_call else fn(lat, timed=True)
         torch.cuda.synchronize()
         sec = (time.perf_counter() - t0) / steps
         bad = int((nnz < 0).sum().item())
@@ -293,7 +300,9 @@ def run_batched(draws, steps, warmup, budget):
         res[name] = {"sec_per_step": round(sec, 5), "products_per_s": total_products / sec,
                      "latency_ms_p50": round(percentile(lat, 50) * 1e3, 4),
                      "latency_ms_p99": round(percentile(lat, 99) * 1e3, 4)}
+    res["batched"]["stage_ms_per_step"] = {k: round(v / steps, 3) for k, v in stage_ms.items() if v > 0.01 * steps}
     res["batched"]["sub_batches"] = len(groups)
+    res["batched"]["sub_batch_sizes"] = [len(g) for g in groups]
     res["batched"]["sub_batch_budget_expected_products"] = budget
     res["speedup_batched_vs_per_call"] = round(res["per_call"]["sec_per_step"] / res["batched"]["sec_per_step"], 3)
     res["contractions"] = len(draws)
@@ -319,7 +328,8 @@ def summary(name, r):
     return {"workload": name, "products": r["products"], "out_nnz": r["nnz_z"],
             "ms_per_step": round(r["sec"] * 1e3, 4), "products_per_s": r["products"] / r["sec"],
             "output_nnz_per_s": r["nnz_z"] / r["sec"],
-            "stage_ms": {k: round(v, 4) for k, v in r["stage_ms"].items()}, "roofline": roofline_of(r)}
+            "stage_ms": {k: round(v, 4) for k, v in r["stage_ms"].items() if not k.startswith("batch_")},
+            "roofline": roofline_of(r)}
 
 
 def main():
@@ -406,7 +416,7 @@ def main():
                               "frac_of_8TBps": round(survey_byte_model(p, r["products"], r["nnz_z"]) / r["sec"]
                                                      / (HBM_PEAK_GBS * 1e9), 4)},
         "cpu_baseline": cpu,
-        "stage_ms": {k: round(v, 4) for k, v in r["stage_ms"].items()},
+        "stage_ms": {k: round(v, 4) for k, v in r["stage_ms"].items() if not k.startswith("batch_")},
         "plan": r["info"],
         "also": also,
         "batched": batched,

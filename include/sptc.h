@@ -119,7 +119,9 @@ typedef enum sptc_stage {
   SPTC_STAGE_GROUP_FILL = 9,  /* grouped path, small groups: prefix sum of the counts, accumulate again, write */
   SPTC_STAGE_DIRECT = 10,     /* grouped path, single-entry groups: write every product as an output */
   SPTC_STAGE_BLOCK = 11,      /* grouped path, large groups: accumulate in LDS, reserve and write */
-  SPTC_NUM_STAGES = 12
+  SPTC_STAGE_BATCH_PACK = 12,   /* batch plan: key every contraction's entries with its index */
+  SPTC_STAGE_BATCH_UNPACK = 13, /* batch execute: place packed outputs in each contraction's COO */
+  SPTC_NUM_STAGES = 14
 } sptc_stage;
 
 /* Accumulation strategy.

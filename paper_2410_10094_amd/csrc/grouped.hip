@@ -289,7 +289,7 @@ __global__ __launch_bounds__(256) void k_gather_global(const GroupRec* __restric
     for (unsigned e = lane; e < G.count; e += 64) {
       const XRec r = xr[G.start + e];
       XEntry x;
-      x.phi = g;  // the group id stands for the X free key in the table key
+      x.phi = (unsigned long long)i;  // the group's place in glist stands for its X free key in the table key
       x.v = r.v;
       xrec[base + e] = x;
       xg[base + e] = r.ystart;

@@ -289,6 +289,7 @@ struct FinCompact {
 struct GroupedOccupancyOp {
   const ZSlot* tab;
   const GroupRec* groups;
+  const uint32_t* glist;  // table key >> bits_y indexes this list of group ids
   KeyUnpack ux, uy;
   int32_t bits_y;
   int32_t* out_idx;
@@ -301,7 +302,7 @@ struct GroupedOccupancyOp {
     const unsigned long long pos = rank + *base;
     if ((int64_t)pos >= out_cap) return;
     const ZSlot z = tab[i];
-    const unsigned long long phix = groups[z.key >> bits_y].phi;
+    const unsigned long long phix = groups[glist[z.key >> bits_y]].phi;
     const unsigned long long phiy = bits_y ? (z.key & (~0ull >> (64 - bits_y))) : 0ull;
 #pragma unroll
     for (int m = 0; m < kMaxOrder; ++m)
@@ -520,11 +521,11 @@ hipError_t launch_compact(const ZSlot* tab, int64_t nslots, KeyUnpack ku, int32_
                      FinCompact{out_nnz, out_cap, base, st}, stream);
 }
 
-hipError_t launch_compact_grouped(const ZSlot* tab, int64_t nslots, const GroupRec* groups, KeyUnpack ux,
-                                  KeyUnpack uy, int32_t bits_y, int32_t* out_idx, double* out_val, int64_t out_cap,
-                                  int64_t* out_nnz, const unsigned long long* base, unsigned long long* tile_sums,
-                                  DevStatus* st, hipStream_t stream) {
-  return device_scan(GroupedOccupancyOp{tab, groups, ux, uy, bits_y, out_idx, out_val, out_cap, base}, nslots,
+hipError_t launch_compact_grouped(const ZSlot* tab, int64_t nslots, const GroupRec* groups, const uint32_t* glist,
+                                  KeyUnpack ux, KeyUnpack uy, int32_t bits_y, int32_t* out_idx, double* out_val,
+                                  int64_t out_cap, int64_t* out_nnz, const unsigned long long* base,
+                                  unsigned long long* tile_sums, DevStatus* st, hipStream_t stream) {
+  return device_scan(GroupedOccupancyOp{tab, groups, glist, ux, uy, bits_y, out_idx, out_val, out_cap, base}, nslots,
                      tile_sums, FinCompact{out_nnz, out_cap, base, st}, stream);
 }
 

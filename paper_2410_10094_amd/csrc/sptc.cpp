@@ -308,10 +308,14 @@ Bounds make_bounds(const sptc_coo* T, int32_t check) {
 }
 
 // Records the stage's begin (0) or end (1) event when the caller asked for it.
-hipError_t mark(const sptc_plan_s* P, hipStream_t s, int stage, int end) {
-  if (!P->opt.stage_events) return hipSuccess;
-  void* ev = P->opt.stage_events[2 * stage + end];
+hipError_t mark_events(void* const* events, hipStream_t s, int stage, int end) {
+  if (!events) return hipSuccess;
+  void* ev = events[2 * stage + end];
   return ev ? hipEventRecord(static_cast<hipEvent_t>(ev), s) : hipSuccess;
+}
+
+hipError_t mark(const sptc_plan_s* P, hipStream_t s, int stage, int end) {
+  return mark_events(P->opt.stage_events, s, stage, end);
 }
 
 sptc_status status_from_bits(uint32_t err) {
@@ -469,10 +473,10 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
   if ((st = P->allocate_n(scan_tiles(P->nw) + 1, &P->etile_sums))) return st;
   if (P->ngl == 0) return SPTC_OK;
 
-  // The global class keys its table by (group id << Y free bits) | Y free key.
-  if (bits_for(P->x_groups) + P->bits_fy > 63)
-    return fail(SPTC_ERR_KEY_OVERFLOW, "%lld X groups and a %d-bit Y free key do not fit a 63-bit key",
-                (long long)P->x_groups, P->bits_fy);
+  // The global class keys its table by (place in glist << Y free bits) | Y free key.
+  if (bits_for(P->ngl) + P->bits_fy > 63)
+    return fail(SPTC_ERR_KEY_OVERFLOW, "%lld groups too large for LDS and a %d-bit Y free key do not fit a 63-bit key",
+                (long long)P->ngl, P->bits_fy);
   if ((st = P->allocate_n(P->ngl, &P->gl_eoff))) return st;
   HIP_TRY(launch_scan_global_entries(P->groups, P->glist, P->ngl, P->gl_eoff, P->tile_sums, P->st, s));
   if ((st = read_status(P, &host))) return st;
@@ -680,7 +684,9 @@ sptc_status batch_body(sptc_batch_s* B, const sptc_coo* X, const sptc_coo* Y, co
   if (!tiles.empty())
     HIP_TRY(hipMemcpyAsync(tiles_d, tiles.data(), sizeof(PackTile) * tiles.size(), hipMemcpyHostToDevice, s));
   HIP_TRY(hipMemsetAsync(err, 0, sizeof(unsigned), s));
+  HIP_TRY(mark_events(o.stage_events, s, SPTC_STAGE_BATCH_PACK, 0));
   HIP_TRY(launch_batch_pack(in_d, tiles_d, (int64_t)tiles.size(), B->w, px, pxv, nx, py, pyv, ny, err, s));
+  HIP_TRY(mark_events(o.stage_events, s, SPTC_STAGE_BATCH_PACK, 1));
   unsigned herr = 0;
   HIP_TRY(hipMemcpyAsync(&herr, err, sizeof herr, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -915,8 +921,8 @@ sptc_status sptc_execute(sptc_plan_t P, int32_t* out_idx, double* out_val, int64
   HIP_TRY(mark(P, s, SPTC_STAGE_EXPAND, 1));
   HIP_TRY(mark(P, s, SPTC_STAGE_COMPACT, 0));
   if (grouped)
-    HIP_TRY(launch_compact_grouped(P->ztab, P->ztab_slots, P->groups, P->ux, P->uy, P->bits_fy, out_idx, out_val,
-                                   out_cap, out_nnz, &P->st->out_base, P->ztile_sums, P->st, s));
+    HIP_TRY(launch_compact_grouped(P->ztab, P->ztab_slots, P->groups, P->glist, P->ux, P->uy, P->bits_fy, out_idx,
+                                   out_val, out_cap, out_nnz, &P->st->out_base, P->ztile_sums, P->st, s));
   else
     HIP_TRY(launch_compact(P->ztab, P->ztab_slots, P->out_unpack, out_idx, out_val, out_cap, out_nnz, nullptr,
                            P->ztile_sums, P->st, s));
@@ -1102,10 +1108,13 @@ sptc_status sptc_batch_execute(sptc_batch_t B, int32_t* out_idx, double* out_val
   int32_t* tidx = reinterpret_cast<int32_t*>(tval + B->tcap);
   sptc_status st;
   if ((st = sptc_execute(B->inner, tidx, tval, B->tcap, B->tnnz, stream))) return st;
+  void* const* ev = B->inner->opt.stage_events;
+  HIP_TRY(mark_events(ev, s, SPTC_STAGE_BATCH_UNPACK, 0));
   HIP_TRY(launch_zero_u64(B->cursor, B->count, s));
   HIP_TRY(launch_batch_unpack(tidx, tval, B->tcap, B->tnnz, B->w, B->count, B->outs, out_idx, out_val, B->cursor,
                               s));
   HIP_TRY(launch_batch_finalize(B->tnnz, B->cursor, B->outs, B->count, out_nnz, s));
+  HIP_TRY(mark_events(ev, s, SPTC_STAGE_BATCH_UNPACK, 1));
   return SPTC_OK;
 }
 

@@ -177,10 +177,10 @@ hipError_t launch_compact(const ZSlot* tab, int64_t nslots, KeyUnpack ku, int32_
 
 // Grouped path, global class: compaction of a table keyed by
 // (group id << bits_y) | Y free key, written from position *base.
-hipError_t launch_compact_grouped(const ZSlot* tab, int64_t nslots, const GroupRec* groups, KeyUnpack ux,
-                                  KeyUnpack uy, int32_t bits_y, int32_t* out_idx, double* out_val, int64_t out_cap,
-                                  int64_t* out_nnz, const unsigned long long* base, unsigned long long* tile_sums,
-                                  DevStatus* st, hipStream_t stream);
+hipError_t launch_compact_grouped(const ZSlot* tab, int64_t nslots, const GroupRec* groups, const uint32_t* glist,
+                                  KeyUnpack ux, KeyUnpack uy, int32_t bits_y, int32_t* out_idx, double* out_val,
+                                  int64_t out_cap, int64_t* out_nnz, const unsigned long long* base,
+                                  unsigned long long* tile_sums, DevStatus* st, hipStream_t stream);
 
 // ---- grouped path (grouped.hip) ----
 

@@ -183,6 +183,18 @@ def _wide_key_problems():
     Y = Coo((4, 1 << 20), np.stack([rng.integers(0, 4, 40_000), rng.integers(0, 1 << 20, 40_000)]).astype(np.int32),
             W.nonzero_uniform(rng, 40_000))
     out.append(Problem("wide-global-class", X, Y, (2,), (0,)))
+    # global class among 70000 X groups with a 48-bit Y free key: 17 bits of
+    # group id plus 48 would not fit a 63-bit table key; the place in the
+    # global class's list (one group) does.  Most X entries meet no Y entry.
+    nx = 70_000
+    lin = rng.choice(1 << 24, nx, replace=False)
+    X = Coo((1 << 12, 1 << 12, 8), np.stack([lin >> 12, lin & 4095, rng.integers(4, 8, nx)]).astype(np.int32),
+            W.nonzero_uniform(rng, nx))
+    X.idx[:, :4] = np.array([[lin[0] >> 12] * 4, [lin[0] & 4095] * 4, [0, 1, 2, 3]], np.int32)
+    ny = 3200
+    Y = Coo((8,) + (1 << 12,) * 4, np.stack([np.arange(ny) % 4] + [rng.integers(0, 1 << 12, ny) for _ in range(4)])
+            .astype(np.int32), W.nonzero_uniform(rng, ny))
+    out.append(Problem("wide-global-class-many-groups", X, Y, (2,), (0,)))
     return out
 
 
@@ -191,7 +203,7 @@ def test_output_keys_wider_than_63_bits(p):
     log(f"[wide] {p.name}")
     info, gidx, gval = run_gpu(p, mode="grouped")
     assert_parity(p, gidx, gval)
-    if p.name == "wide-global-class":
+    if p.name.startswith("wide-global-class"):
         assert info["classes"]["global_"] > 0
     else:
         assert info["classes"]["direct"] > 0 and info["classes"]["wave"] > 0
