@@ -209,7 +209,48 @@ def sub_batches(draws, budget):
     return sched.make_batches(draws, W.expected_products, lambda p: sched.shape_class(p.Y.dims, p.cy), budget)
 
 
-def run_batched(draws, steps, warmup, budget):
+def upload(draws):
+    import torch
+
+    import paper_2410_10094_amd as sptc
+    dev = [(sptc.DeviceCoo.from_host(p.X), sptc.DeviceCoo.from_host(p.Y)) for p in draws]
+    torch.cuda.synchronize()
+    return dev
+
+
+def run_served(draws, dev, seconds, rate, budget_bytes, batch_products, max_batch, seed):
+    """Poisson arrivals at `rate` per second for `seconds`; each request is a
+    draw picked uniformly from the pool (inputs resident in HBM).  Served
+    with continuous batching under the memory budget."""
+    import numpy as np
+
+    from paper_2410_10094_amd import sched, serve
+    from paper_2410_10094_amd import workloads as W
+    arrivals = serve.poisson_arrivals(rate, seconds, seed)
+    picks = np.random.default_rng(seed + 1).integers(0, len(draws), size=len(arrivals))
+    reqs = [serve.Request(i, dev[k][0], dev[k][1], draws[k].cx, draws[k].cy, float(a),
+                          expected_products=W.expected_products(draws[k]),
+                          klass=sched.shape_class(draws[k].Y.dims, draws[k].cy))
+            for i, (a, k) in enumerate(zip(arrivals, picks))]
+    srv = serve.Server(serve.TorchBackend(arena_bytes=budget_bytes), budget_bytes=budget_bytes,
+                       batch_products=batch_products, max_batch=max_batch)
+    t0 = time.perf_counter()
+    done = srv.run(reqs)
+    wall = time.perf_counter() - t0
+    out = serve.latency_summary(done)
+    products = sum(r.products for r in done)
+    out.update({"offered_requests_per_s": rate, "arrival_seconds": seconds, "wall_seconds": round(wall, 3),
+                "requests_per_s": len(done) / wall, "products": products, "products_per_s": products / wall,
+                "batches": srv.batches, "mean_batch": round(len(done) / max(srv.batches, 1), 2),
+                "peak_bytes": srv.peak_used, "budget_bytes": budget_bytes, "waits_for_memory": srv.waits_for_memory,
+                "batch_products": batch_products, "max_batch": max_batch})
+    for k in ("latency_ms_p50", "latency_ms_p99", "latency_ms_max", "latency_ms_mean"):
+        if k in out:
+            out[k] = round(out[k], 3)
+    return out
+
+
+def run_batched(draws, dev, steps, warmup, budget):
     """The batched workload two ways, each step covering every draw:
     per-call (sptc_plan + sptc_execute per contraction) and batched
     (sptc_batch_plan + sptc_batch_execute per sub-batch of at most `budget`
@@ -219,8 +260,6 @@ def run_batched(draws, steps, warmup, budget):
     import torch
 
     import paper_2410_10094_amd as sptc
-    dev = [(sptc.DeviceCoo.from_host(p.X), sptc.DeviceCoo.from_host(p.Y)) for p in draws]
-    torch.cuda.synchronize()
     groups = sub_batches(draws, budget)
 
     # per-call: one output buffer sized for the largest bound
@@ -349,6 +388,12 @@ def main():
                     help="draws of the batched workload timed per-call and batched (0: skip)")
     ap.add_argument("--batch-budget", type=float, default=1.0e9,
                     help="expected products per sub-batch of the batched leg")
+    ap.add_argument("--serve", type=float, default=3.0, metavar="SECONDS",
+                    help="seconds of Poisson arrivals for the served leg (0: skip); the pool is the batched draws")
+    ap.add_argument("--serve-rate", type=float, default=2000.0, help="arrivals per second of the served leg")
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0, help="device-memory budget of the served leg")
+    ap.add_argument("--serve-batch-products", type=float, default=1e9,
+                    help="expected products per served batch")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -357,10 +402,10 @@ def main():
     if args.steps < 1:
         sys.exit("--steps must be >= 1")
 
+    from paper_2410_10094_amd.workloads import BASE_SEED
     draws = None
     if args.batched and not args.calibrate_copy:
         workers = max(1, min(16, len(os.sched_getaffinity(0))))
-        from paper_2410_10094_amd.workloads import BASE_SEED
         draws = generate_draws(args.batched, BASE_SEED + 4, workers)
 
     import torch
@@ -382,11 +427,21 @@ def main():
     for name in [a for a in args.also.split(",") if a and a != args.workload]:
         also.append(summary(name, run_workload(name, max(3, args.steps // 2), max(1, args.warmup), mode=args.mode)))
 
-    batched = None
+    batched = served = None
     if draws:
-        batched = run_batched(draws, max(1, args.steps // 5), 1, args.batch_budget)
+        dev = upload(draws)
+        batched = run_batched(draws, dev, max(1, args.steps // 5), 1, args.batch_budget)
         batched["workload"] = (f"{len(draws)} draws: orders 3-5, dims U[32,4096], nnz log-U[1e3,1e6], "
                                "1-2 contracted pairs, FP64 U[-1,1)")
+        if args.serve > 0:
+            budget = int(args.serve_budget_gb * (1 << 30))
+            served = {"workload": f"Poisson arrivals, each request one of the {len(draws)} batched draws "
+                                  "picked uniformly, inputs resident in HBM"}
+            served["batched"] = run_served(draws, dev, args.serve, args.serve_rate, budget,
+                                           args.serve_batch_products, 4096, BASE_SEED + 5)
+            # the same arrivals served one request per launch
+            served["per_call"] = run_served(draws, dev, min(args.serve, 1.0), args.serve_rate, budget,
+                                            args.serve_batch_products, 1, BASE_SEED + 5)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -420,6 +475,7 @@ def main():
         "plan": r["info"],
         "also": also,
         "batched": batched,
+        "served": served,
     }
     print(json.dumps(line), flush=True)
 

@@ -1,0 +1,298 @@
+"""Serving loop: contractions arrive over time and are admitted, batched and
+executed continuously under a device-memory budget.
+
+One host thread runs the loop.  Arrived requests wait in a FIFO queue.  When
+fewer than ``max_inflight`` batches are on the device, the loop takes the
+queued requests of the head request's shape class (sched.shape_class), up to
+``batch_products`` expected products, and plans them as one batch on the
+plan stream: this is pass 1, which counts every member's products and so
+fixes the output and scratch bytes its execution needs.  The batch is
+admitted to the execute stream once its workspace plus those bytes fit in
+what the budget has left; until then it waits, and the loop keeps retiring
+finished batches.  Planning the next batch overlaps on the device with the
+batches executing on the other stream, and requests that arrive meanwhile
+join the next batch.  A request's latency runs from its arrival to the end
+of its batch's execution on the device clock.
+
+Before planning, the loop also checks that an estimate of the batch's own
+workspace (from its nonzero counts) fits, so that a batch waiting for memory
+does not hold more than the budget allows.
+
+The device work goes through a backend (TorchBackend: the HIP library on a
+GPU); the policy itself is plain host code."""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+from typing import Any, Callable, Deque, List, Optional, Sequence
+
+from . import sched
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    X: Any
+    Y: Any
+    cx: Sequence[int]
+    cy: Sequence[int]
+    arrival: float                    # seconds after the server starts
+    expected_products: float = 0.0    # admission hint before pass 1
+    klass: str = ""
+    products: int = 0                 # pass 1 count
+    done: float = -1.0                # device-clock completion, seconds after start
+    result: Any = None                # (idx, val) device views, when kept
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+@dataclasses.dataclass
+class _Batch:
+    members: List[Request]
+    handle: Any
+    need: int          # workspace + outputs + scratch bytes
+    token: Any = None
+
+
+class RingArena:
+    """First-in first-out suballocator over one device buffer.  Batches
+    execute on one stream, so they finish, and give their chunk back, in the
+    order they took it."""
+
+    ALIGN = 256
+
+    def __init__(self, nbytes: int):
+        self.size = int(nbytes)
+        self.chunks: Deque = collections.deque()  # (start, end), oldest first
+
+    def alloc(self, n: int) -> Optional[int]:
+        """Start offset of a free chunk of n bytes, or None."""
+        n = (int(n) + self.ALIGN - 1) // self.ALIGN * self.ALIGN
+        if not self.chunks:
+            start = 0 if n <= self.size else None
+        else:
+            tail, head = self.chunks[0][0], self.chunks[-1][1]
+            if head > tail:  # used: [tail, head)
+                start = head if head + n <= self.size else (0 if n <= tail else None)
+            else:            # wrapped; free: [head, tail)
+                start = head if head + n <= tail else None
+        if start is not None:
+            self.chunks.append((start, start + n))
+        return start
+
+    def release(self, start: int):
+        if not self.chunks or self.chunks[0][0] != start:
+            raise RuntimeError("arena chunks must be released oldest first")
+        self.chunks.popleft()
+
+
+class TorchBackend:
+    """Runs batches with sptc_batch_* on one GPU: a plan stream and an
+    execute stream (both at the default priority).  Outputs and execute
+    scratch come from one preallocated ring arena; the batches' own
+    workspace from the library's stream-ordered pool."""
+
+    def __init__(self, arena_bytes: int, keep_results: bool = False, options=None):
+        import torch
+        self.torch = torch
+        self.plan_stream = torch.cuda.Stream()
+        self.exec_stream = torch.cuda.Stream()
+        self.keep_results = keep_results
+        self.options = options
+        self.t0_event = torch.cuda.Event(enable_timing=True)
+        self.t0_host = 0.0
+        self.arena = RingArena(arena_bytes)
+        self.buf = torch.empty(max(int(arena_bytes), 1), dtype=torch.uint8, device="cuda")
+
+    def start(self) -> float:
+        """Marks time zero on both clocks; returns the host time of it."""
+        torch = self.torch
+        torch.cuda.synchronize()
+        self.t0_event.record(self.exec_stream)
+        self.t0_event.synchronize()
+        self.t0_host = time.perf_counter()
+        return self.t0_host
+
+    def estimate(self, members: List[Request]) -> int:
+        """Workspace bytes a batch of these members holds (before pass 1):
+        about 96 bytes per nonzero of X and Y plus a fixed part."""
+        return 96 * sum(r.X.nnz + r.Y.nnz for r in members) + (1 << 20)
+
+    def plan(self, members: List[Request]):
+        from . import Batch
+        b = Batch([(r.X, r.Y, r.cx, r.cy) for r in members], options=self.options, stream=self.plan_stream)
+        for r, it in zip(members, b.items):
+            r.products = it["products"]
+        return b, b.workspace_bytes + b.output_bytes()
+
+    def launch(self, b):
+        """Enqueues the batch; None when the arena has no room yet."""
+        torch = self.torch
+        a = RingArena.ALIGN
+        rnd = lambda n: (n + a - 1) // a * a
+        parts = [rnd(4 * max(b.idx_elems, 1)), rnd(8 * max(b.val_elems, 1)), rnd(8 * b.count),
+                 rnd(max(b.scratch_bytes, 1))]
+        start = self.arena.alloc(sum(parts))
+        if start is None:
+            return None
+        offs = [start]
+        for n in parts[:-1]:
+            offs.append(offs[-1] + n)
+        idx = self.buf[offs[0]:offs[0] + 4 * max(b.idx_elems, 1)].view(torch.int32)
+        val = self.buf[offs[1]:offs[1] + 8 * max(b.val_elems, 1)].view(torch.float64)
+        nnz = self.buf[offs[2]:offs[2] + 8 * b.count].view(torch.int64)
+        scratch = self.buf[offs[3]:offs[3] + max(b.scratch_bytes, 1)]
+        b.execute_into(idx, val, nnz, scratch, stream=self.exec_stream)
+        ev = torch.cuda.Event(enable_timing=True)
+        ev.record(self.exec_stream)
+        return ((idx, val, nnz, scratch), ev, start)
+
+    def done(self, token) -> bool:
+        return token[1].query()
+
+    def finish_time(self, token) -> float:
+        return self.t0_event.elapsed_time(token[1]) * 1e-3
+
+    def results(self, b, token, members: List[Request]):
+        """Kept results are copied out of the arena, which is reused."""
+        if not self.keep_results:
+            return
+        idx, val, nnz, _ = token[0]
+        for r, (i, v) in zip(members, b.views(idx, val, nnz.cpu().tolist())):
+            r.result = (i.clone(), v.clone())
+
+    def check(self, b, token):
+        """Raises if any member reported an error status."""
+        nnz = token[0][2]
+        with self.torch.cuda.stream(self.exec_stream):
+            bad = int((nnz < 0).sum().item())
+        if bad:
+            raise RuntimeError(f"{bad} contractions of a batch reported an error")
+
+    def release(self, b, token):
+        b.close()
+        self.arena.release(token[2])
+
+
+class Server:
+    def __init__(self, backend, budget_bytes: int = 64 << 30, max_inflight: int = 2,
+                 batch_products: float = 5e8, max_batch: int = sched.BATCH_MAX,
+                 clock: Callable[[], float] = time.perf_counter, idle_wait: float = 50e-6):
+        self.backend = backend
+        self.budget = int(budget_bytes)
+        self.max_inflight = max_inflight
+        self.batch_products = batch_products
+        self.max_batch = max_batch
+        self.clock = clock
+        self.idle_wait = idle_wait
+        self.used = 0
+        self.peak_used = 0
+        self.batches = 0
+        self.waits_for_memory = 0
+
+    def _select(self, queue: Deque[Request]) -> List[int]:
+        """Positions in the queue of the next batch: the head request's shape
+        class, FIFO within it, up to the product and count caps (the head
+        always goes)."""
+        head = queue[0]
+        picked, acc = [], 0.0
+        for k, r in enumerate(queue):
+            if r.klass != head.klass:
+                continue
+            if picked and (acc + r.expected_products > self.batch_products or len(picked) >= self.max_batch):
+                break
+            picked.append(k)
+            acc += r.expected_products
+        return picked
+
+    @staticmethod
+    def _remove(queue: Deque[Request], picked: List[int]) -> List[Request]:
+        chosen = set(picked)
+        members = [r for k, r in enumerate(queue) if k in chosen]
+        rest = [r for k, r in enumerate(queue) if k not in chosen]
+        queue.clear()
+        queue.extend(rest)
+        return members
+
+    def run(self, requests: Sequence[Request]) -> List[Request]:
+        """Serves requests (sorted by arrival) to completion; returns them."""
+        be = self.backend
+        pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+        queue: Deque[Request] = collections.deque()
+        inflight: List[_Batch] = []
+        staged: Optional[_Batch] = None
+        done: List[Request] = []
+        t0 = be.start()
+        while pending or queue or inflight or staged:
+            now = self.clock() - t0
+            while pending and pending[0].arrival <= now:
+                queue.append(pending.popleft())
+            progressed = False
+            for b in [b for b in inflight if be.done(b.token)]:
+                be.check(b.handle, b.token)
+                t = be.finish_time(b.token)
+                for r in b.members:
+                    r.done = t
+                be.results(b.handle, b.token, b.members)
+                be.release(b.handle, b.token)
+                self.used -= b.need
+                inflight.remove(b)
+                done.extend(b.members)
+                progressed = True
+            if staged is None and queue and len(inflight) < self.max_inflight:
+                picked = self._select(queue)
+                if self.used + be.estimate([queue[k] for k in picked]) <= self.budget or not inflight:
+                    members = self._remove(queue, picked)
+                    handle, need = be.plan(members)
+                    if need > self.budget:
+                        raise RuntimeError(f"a batch of {len(members)} needs {need} bytes, above the budget "
+                                           f"{self.budget}; lower batch_products")
+                    staged = _Batch(members, handle, need)
+                    progressed = True
+                else:
+                    self.waits_for_memory += 1
+            if staged is not None and len(inflight) < self.max_inflight:
+                token = be.launch(staged.handle) if self.used + staged.need <= self.budget else None
+                if token is not None:
+                    staged.token = token
+                    self.used += staged.need
+                    self.peak_used = max(self.peak_used, self.used)
+                    self.batches += 1
+                    inflight.append(staged)
+                    staged = None
+                    progressed = True
+                elif not progressed:
+                    self.waits_for_memory += 1
+            if not progressed:
+                if pending and not queue and not inflight and staged is None:
+                    wait = pending[0].arrival - (self.clock() - t0)
+                    if wait > 0:
+                        time.sleep(min(wait, 1e-3))
+                elif self.idle_wait > 0:
+                    time.sleep(self.idle_wait)
+        return done
+
+
+def poisson_arrivals(rate: float, seconds: float, seed: int):
+    """Arrival times of a Poisson process of ``rate`` per second over
+    ``seconds``, seeded."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    n_max = int(rate * seconds * 1.5 + 100)
+    t = np.cumsum(rng.exponential(1.0 / rate, size=n_max))
+    while t[-1] < seconds:
+        t = np.concatenate([t, t[-1] + np.cumsum(rng.exponential(1.0 / rate, size=n_max))])
+    return t[t < seconds]
+
+
+def latency_summary(done: Sequence[Request]):
+    import numpy as np
+    lat = np.array([r.latency for r in done], dtype=np.float64)
+    if lat.size == 0:
+        return {"requests": 0}
+    return {"requests": int(lat.size), "latency_ms_p50": float(np.percentile(lat, 50) * 1e3),
+            "latency_ms_p99": float(np.percentile(lat, 99) * 1e3), "latency_ms_max": float(lat.max() * 1e3),
+            "latency_ms_mean": float(lat.mean() * 1e3)}

@@ -1,0 +1,59 @@
+"""Serving loop on the GPU: requests arriving over time are batched
+continuously under a memory budget, and each result is the same alone and in
+the mix (coordinates bit-exact after sorting, values within the tolerance),
+and matches the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2410_10094_amd import sched, serve
+from paper_2410_10094_amd import workloads as W
+from tests import helpers as H
+from tests.gpu_common import assert_parity, log, run_gpu, to_device
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _pool():
+    ps = W.batched_draws(seed=91, count=24, nnz_lo=1e2, nnz_hi=2e4)
+    ps += [W.plain(seed=92, n=32, nnz=3000), W.block_sparse(n=16, block=4, p_block=0.3),
+           W.random_problem(93, 3, 3, 1, 3, 40, 3000, 3000, duplicates=True)]
+    return ps
+
+
+def test_served_results_match_alone_and_oracle():
+    pool = _pool()
+    dev = [to_device(p) for p in pool]
+    torch.cuda.synchronize()
+    arrivals = serve.poisson_arrivals(4000.0, 0.05, 5)[:80]
+    rng = np.random.default_rng(6)
+    picks = rng.integers(0, len(pool), size=len(arrivals))
+    reqs = []
+    for i, (a, k) in enumerate(zip(arrivals, picks)):
+        p = pool[k]
+        reqs.append(serve.Request(i, dev[k][0], dev[k][1], p.cx, p.cy, float(a),
+                                  expected_products=W.expected_products(p), klass=sched.shape_class(p.Y.dims, p.cy)))
+    log(f"[serve] {len(reqs)} requests over {arrivals[-1]:.3f} s")
+    srv = serve.Server(serve.TorchBackend(arena_bytes=96 << 20, keep_results=True), budget_bytes=96 << 20,
+                       batch_products=4e5)
+    done = srv.run(reqs)
+    log(f"[serve] batches {srv.batches} peak {srv.peak_used} waits {srv.waits_for_memory}")
+    assert len(done) == len(reqs)
+    assert srv.batches > 1 and srv.peak_used <= 96 << 20
+    refs, alone = {}, {}
+    for r in sorted(done, key=lambda r: r.rid):
+        k = int(picks[r.rid])
+        p = pool[k]
+        if k not in refs:
+            refs[k] = oracle.contract(p.X, p.Y, p.cx, p.cy)
+            _, ai, av = run_gpu(p)
+            alone[k] = H.sort_coo(ai, av)
+            assert_parity(p, ai, av, ref=refs[k])
+        assert r.done >= r.arrival
+        idx, val = r.result
+        gi, gv = idx.cpu().numpy(), val.cpu().numpy()
+        assert_parity(p, gi, gv, ref=refs[k])
+        si, sv = H.sort_coo(gi, gv)
+        np.testing.assert_array_equal(si, alone[k][0])
+        H.assert_values_close(sv, alone[k][1], refs[k].absval, refs[k].terms, rel=2e-12)
