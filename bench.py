@@ -286,15 +286,13 @@ def run_batched(draws, dev, steps, warmup, budget):
             pl.close()
 
     # batched: buffers sized for the largest sub-batch
-    need_i = need_v = need_s = 0
+    need_i = need_v = 0
     for g in groups:
         with sptc.batch([(dev[i][0], dev[i][1], draws[i].cx, draws[i].cy) for i in g]) as bt:
             need_i, need_v = max(need_i, bt.idx_elems), max(need_v, bt.val_elems)
-            need_s = max(need_s, bt.scratch_bytes)
     bidx = torch.empty(max(need_i, 1), dtype=torch.int32, device="cuda")
     bval = torch.empty(max(need_v, 1), dtype=torch.float64, device="cuda")
     bnnz = torch.empty(len(draws), dtype=torch.int64, device="cuda")
-    bscr = torch.empty(max(need_s, 1), dtype=torch.uint8, device="cuda")
 
     from paper_2410_10094_amd import binding as B
     nst = len(B.STAGES)
@@ -313,7 +311,7 @@ def run_batched(draws, dev, steps, warmup, budget):
                 opt.stage_events = ctypes.cast(ev_arrays[k], ctypes.POINTER(ctypes.c_void_p))
             t0 = time.perf_counter()
             bt = sptc.batch([(dev[i][0], dev[i][1], draws[i].cx, draws[i].cy) for i in g], options=opt)
-            bt.execute_into(bidx, bval, bnnz[g[0]:g[0] + len(g)], bscr)
+            bt.execute_into(bidx, bval, bnnz[g[0]:g[0] + len(g)])
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             lat.extend([dt] * len(g))

@@ -240,8 +240,8 @@ SPTC_API sptc_status sptc_plan_x_groups(sptc_plan_t plan, int32_t* free_coords, 
  *
  * count contractions (X[b], Y[b], ncontract[b], cx[b], cy[b]) are planned and
  * executed together: every entry is keyed with its contraction's index, so
- * one pass of the grouped pipeline serves all of them, and a final pass
- * sorts the outputs back into one COO per contraction.  1 <= count <= 4096.
+ * one pass of the grouped pipeline serves all of them, with the key tables
+ * cut into one region per contraction.  1 <= count <= 4096.
  * Each contraction follows the rules of sptc_plan; the contraction index
  * plus its widest contracting key and its widest X free key must each fit
  * 62 bits.  Options apply to the whole batch (mode must be GROUPED). */
@@ -253,13 +253,12 @@ SPTC_API sptc_status sptc_batch_plan(sptc_batch_t* batch, int32_t count, const s
                                      const int32_t* ncontract, const int32_t* const* cx, const int32_t* const* cy,
                                      const sptc_options* opt, const sptc_allocator* alloc, void* stream);
 
-/* Buffers the batch needs (host outputs): int32 elements for all index
- * rows, double elements for all values, bytes of execute scratch (device
- * memory the caller lends to each sptc_batch_execute; it grows with the
- * product count of pass 1, section 4.3) and bytes of workspace the batch
- * itself holds.  Any pointer may be NULL. */
+/* Output buffers the batch needs (host outputs): int32 elements for all
+ * index rows and double elements for all values, both sized from pass 1's
+ * product counts (section 4.3), and the bytes of device workspace the batch
+ * holds.  Any pointer may be NULL. */
 SPTC_API sptc_status sptc_batch_sizes(sptc_batch_t batch, int64_t* idx_elems, int64_t* val_elems,
-                                      int64_t* scratch_bytes, int64_t* workspace_bytes);
+                                      int64_t* workspace_bytes);
 
 /* Contraction b's sizes (info: out_order, out_dims, products,
  * out_nnz_bound and key_bits_*; the plan-wide fields are zero) and where its
@@ -268,14 +267,13 @@ SPTC_API sptc_status sptc_batch_sizes(sptc_batch_t batch, int64_t* idx_elems, in
 SPTC_API sptc_status sptc_batch_info(sptc_batch_t batch, int32_t b, sptc_info* info, int64_t* idx_offset,
                                      int64_t* val_offset);
 
-/* Executes every contraction.  out_idx / out_val: device buffers of the
- * sizes sptc_batch_sizes reports; out_nnz: device int64 [count] receiving
- * each contraction's nnz (or the negated status); scratch: device memory of
- * scratch_bytes, 256-byte aligned, not used by anything else until the
- * enqueued work ends (NULL when scratch_bytes is 0).  Like sptc_execute it
- * never synchronises, allocates or copies to the host. */
+/* Executes every contraction, writing each output straight into its
+ * contraction's region.  out_idx / out_val: device buffers of the sizes
+ * sptc_batch_sizes reports; out_nnz: device int64 [count] receiving each
+ * contraction's nnz (or the negated status).  Like sptc_execute it never
+ * synchronises, allocates or copies to the host. */
 SPTC_API sptc_status sptc_batch_execute(sptc_batch_t batch, int32_t* out_idx, double* out_val, int64_t* out_nnz,
-                                        void* scratch, void* stream);
+                                        void* stream);
 
 SPTC_API void sptc_batch_free(sptc_batch_t batch);
 

@@ -287,11 +287,9 @@ class Batch:
         _b.check(lib.sptc_batch_plan(ctypes.byref(h), n, xs, ys, nc, cxp, cyp, ctypes.byref(opt), alloc_ptr,
                                      self._stream))
         self._h = h
-        ie, ve, sc, ws = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
-        _b.check(lib.sptc_batch_sizes(self._h, ctypes.byref(ie), ctypes.byref(ve), ctypes.byref(sc),
-                                      ctypes.byref(ws)))
-        self.idx_elems, self.val_elems = ie.value, ve.value
-        self.scratch_bytes, self.workspace_bytes = sc.value, ws.value
+        ie, ve, ws = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _b.check(lib.sptc_batch_sizes(self._h, ctypes.byref(ie), ctypes.byref(ve), ctypes.byref(ws)))
+        self.idx_elems, self.val_elems, self.workspace_bytes = ie.value, ve.value, ws.value
         self.items = []
         for b in range(n):
             info = _b.Info()
@@ -321,27 +319,21 @@ class Batch:
         self.close()
 
     def output_bytes(self):
-        """Device bytes of outputs plus execute scratch: what pass 1's
-        product counts say one execute needs beyond the batch itself."""
-        return 4 * self.idx_elems + 8 * self.val_elems + self.scratch_bytes + 8 * self.count
+        """Device bytes of the outputs: what pass 1's product counts say one
+        execute needs beyond the batch itself."""
+        return 4 * self.idx_elems + 8 * self.val_elems + 8 * self.count
 
     def allocate_outputs(self):
-        """(idx, val, nnz, scratch) device tensors for execute_into."""
+        """(idx, val, nnz) device tensors for execute_into."""
         torch = _torch()
         idx = torch.empty(max(self.idx_elems, 1), dtype=torch.int32, device=self.device)
         val = torch.empty(max(self.val_elems, 1), dtype=torch.float64, device=self.device)
         nnz = torch.empty(self.count, dtype=torch.int64, device=self.device)
-        scratch = torch.empty(max(self.scratch_bytes, 1), dtype=torch.uint8, device=self.device)
-        return idx, val, nnz, scratch
+        return idx, val, nnz
 
-    def execute_into(self, out_idx, out_val, out_nnz, scratch, stream=None):
-        """Enqueue ``sptc_batch_execute`` (no synchronisation).  ``scratch``
-        holds at least ``scratch_bytes`` and starts 256-byte aligned (torch's
-        allocations do)."""
-        if self.scratch_bytes and scratch.numel() * scratch.element_size() < self.scratch_bytes:
-            raise ValueError("scratch smaller than scratch_bytes")
+    def execute_into(self, out_idx, out_val, out_nnz, stream=None):
+        """Enqueue ``sptc_batch_execute`` (no synchronisation)."""
         _b.check(_b.load().sptc_batch_execute(self._h, out_idx.data_ptr(), out_val.data_ptr(), out_nnz.data_ptr(),
-                                              scratch.data_ptr() if self.scratch_bytes else None,
                                               _stream_handle(stream)))
 
     def views(self, out_idx, out_val, nnz_host):
@@ -361,8 +353,8 @@ class Batch:
     def execute(self, stream=None):
         """Run every contraction; returns a list of ``(idx, val)`` device
         tensors (synchronises to read the nnz)."""
-        idx, val, nnz, scratch = self.allocate_outputs()
-        self.execute_into(idx, val, nnz, scratch, stream)
+        idx, val, nnz = self.allocate_outputs()
+        self.execute_into(idx, val, nnz, stream)
         return self.views(idx, val, nnz.cpu().tolist())
 
 

@@ -111,12 +111,11 @@ def load():
     lib.sptc_batch_plan.argtypes = [ctypes.POINTER(P), i32, ctypes.POINTER(Coo), ctypes.POINTER(Coo), P, P, P,
                                     ctypes.POINTER(Options), ctypes.POINTER(Allocator), P]
     lib.sptc_batch_plan.restype = st
-    lib.sptc_batch_sizes.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
-                                     ctypes.POINTER(i64)]
+    lib.sptc_batch_sizes.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.sptc_batch_sizes.restype = st
     lib.sptc_batch_info.argtypes = [P, i32, ctypes.POINTER(Info), ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.sptc_batch_info.restype = st
-    lib.sptc_batch_execute.argtypes = [P, P, P, P, P, P]
+    lib.sptc_batch_execute.argtypes = [P, P, P, P, P]
     lib.sptc_batch_execute.restype = st
     lib.sptc_batch_free.argtypes = [P]
     lib.sptc_batch_free.restype = None

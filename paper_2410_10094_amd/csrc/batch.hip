@@ -3,8 +3,10 @@
 // Each contraction b's entries are rewritten as packed keys prefixed with b
 // (contracting key (b, kappa), X free key (b, phiX); the Y free key as is),
 // so entries of different contractions never match and never share an X
-// group.  One pass of the grouped pipeline then serves the whole batch, and
-// the outputs are sorted back into one COO per contraction.
+// group.  One pass of the grouped pipeline then serves the whole batch; its
+// key tables are cut into per-contraction regions, so every list of groups
+// is ordered by contraction and each output goes straight to its
+// contraction's COO.
 #include <hip/hip_runtime.h>
 
 #include "../../include/sptc.h"
@@ -15,8 +17,6 @@ namespace sptc {
 namespace {
 
 constexpr int kPackBlock = 256;
-
-__device__ __forceinline__ uint64_t low_mask(int bits) { return bits >= 64 ? ~0ull : ((1ull << bits) - 1ull); }
 
 // Writes a key of up to 62 bits as two int32 coordinates (high, low).
 __device__ __forceinline__ void put_split(int32_t* idx, int64_t n, int row, int64_t g, uint64_t key, int lo) {
@@ -79,72 +79,61 @@ __global__ void k_zero_u64(unsigned long long* __restrict__ p, int64_t n) {
     p[i] = 0ull;
 }
 
-// Places every packed output in its contraction's COO: per workgroup chunk,
-// count outputs per contraction in LDS, reserve one run per contraction with
-// a single atomic on its cursor, then decode and write.
-constexpr int kUnpackBlock = 256;
-constexpr int64_t kUnpackChunk = 4096;
+// First place in `list` (ordered by contraction) whose group belongs to a
+// contraction >= b.
+__device__ __forceinline__ int64_t first_of(const GroupRec* __restrict__ groups, const uint32_t* __restrict__ list,
+                                            int64_t n, int32_t wx, uint64_t b) {
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = lo + ((hi - lo) >> 1);
+    if ((groups[list[mid]].phi >> wx) < b)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
 
-__global__ __launch_bounds__(kUnpackBlock) void k_batch_unpack(const int32_t* __restrict__ tidx,
-                                                               const double* __restrict__ tval, int64_t tcap,
-                                                               const int64_t* __restrict__ tnnz, BatchWidths w,
-                                                               int32_t count, const BatchOut* __restrict__ outs,
-                                                               int32_t* __restrict__ out_idx,
-                                                               double* __restrict__ out_val,
-                                                               unsigned long long* __restrict__ cursor) {
-  extern __shared__ unsigned long long s_u[];
-  unsigned long long* s_base = s_u;                            // [count]
-  unsigned* s_cnt = reinterpret_cast<unsigned*>(s_u + count);  // [count]
-  const int64_t n = *tnnz < tcap ? *tnnz : tcap;               // negative (an error): nothing to place
-  const int64_t c0 = (int64_t)blockIdx.x * kUnpackChunk;
-  if (c0 >= n) return;  // uniform across the block
-  const int64_t c1 = c0 + kUnpackChunk < n ? c0 + kUnpackChunk : n;
-  for (int32_t b = threadIdx.x; b < count; b += kUnpackBlock) s_cnt[b] = 0u;
-  __syncthreads();
-  auto batch_of = [&](int64_t o) -> uint32_t {
-    const uint64_t phix = ((uint64_t)(uint32_t)tidx[o] << w.lo_x) | (uint32_t)tidx[tcap + o];
-    return (uint32_t)(phix >> w.wx);
-  };
-  for (int64_t o = c0 + threadIdx.x; o < c1; o += kUnpackBlock) {
-    const uint32_t b = batch_of(o);
-    if (b < (uint32_t)count) atomicAdd(&s_cnt[b], 1u);
-  }
-  __syncthreads();
-  for (int32_t b = threadIdx.x; b < count; b += kUnpackBlock) {
-    const unsigned c = s_cnt[b];
-    if (c) s_base[b] = atomicAdd(&cursor[b], (unsigned long long)c);
-    s_cnt[b] = 0u;
-  }
-  __syncthreads();
-  for (int64_t o = c0 + threadIdx.x; o < c1; o += kUnpackBlock) {
-    const uint64_t phix = ((uint64_t)(uint32_t)tidx[o] << w.lo_x) | (uint32_t)tidx[tcap + o];
-    const uint64_t phiy = ((uint64_t)(uint32_t)tidx[2 * tcap + o] << w.lo_y) | (uint32_t)tidx[3 * tcap + o];
-    const uint32_t b = (uint32_t)(phix >> w.wx);
-    if (b >= (uint32_t)count) continue;
-    const unsigned long long pos = s_base[b] + atomicAdd(&s_cnt[b], 1u);
-    const BatchOut& d = outs[b];
-    if ((int64_t)pos >= d.cap) continue;
-    const uint64_t fx = phix & low_mask(w.wx);
-#pragma unroll
-    for (int m = 0; m < kMaxOrder; ++m)
-      if (m < d.ux.n)
-        __builtin_nontemporal_store((int32_t)((fx >> d.ux.shift[m]) & d.ux.mask[m]),
-                                    &out_idx[d.idx_off + (int64_t)m * d.cap + (int64_t)pos]);
-#pragma unroll
-    for (int m = 0; m < kMaxOrder; ++m)
-      if (m < d.uy.n)
-        __builtin_nontemporal_store((int32_t)((phiy >> d.uy.shift[m]) & d.uy.mask[m]),
-                                    &out_idx[d.idx_off + (int64_t)(d.ux.n + m) * d.cap + (int64_t)pos]);
-    __builtin_nontemporal_store(tval[o], &out_val[d.val_off + (int64_t)pos]);
+__global__ void k_batch_segments(const GroupRec* __restrict__ groups, const uint32_t* __restrict__ dlist, int64_t nd,
+                                 const unsigned long long* __restrict__ dpos, const uint32_t* __restrict__ wlist,
+                                 int64_t nw, int32_t wx, int32_t count, BatchSeg* __restrict__ seg) {
+  for (int32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < count; b += gridDim.x * blockDim.x) {
+    const int64_t dlo = first_of(groups, dlist, nd, wx, (uint64_t)b);
+    const int64_t dhi = first_of(groups, dlist, nd, wx, (uint64_t)b + 1);
+    BatchSeg s;
+    s.dshift = dlo < dhi ? dpos[dlo] : 0ull;
+    s.dcount = dlo < dhi ? dpos[dhi] - dpos[dlo] : 0ull;
+    s.wshift = 0ull;
+    s.cursor = 0ull;
+    s.wlo = (uint32_t)first_of(groups, wlist, nw, wx, (uint64_t)b);
+    s.whi = (uint32_t)first_of(groups, wlist, nw, wx, (uint64_t)b + 1);
+    seg[b] = s;
   }
 }
 
-__global__ void k_batch_finalize(const int64_t* __restrict__ tnnz, const unsigned long long* __restrict__ cursor,
+__global__ void k_batch_bases(const uint32_t* __restrict__ wlist, const uint32_t* __restrict__ gn,
+                              const unsigned long long* __restrict__ goff, int32_t count, BatchSeg* __restrict__ seg) {
+  for (int32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < count; b += gridDim.x * blockDim.x) {
+    BatchSeg s = seg[b];
+    unsigned long long wstart = 0ull, wcount = 0ull;
+    if (s.whi > s.wlo) {
+      const uint32_t first = wlist[s.wlo], last = wlist[s.whi - 1];
+      wstart = goff[first];
+      wcount = goff[last] + gn[last] - wstart;
+    }
+    s.wshift = wstart - s.dcount;  // modulo 2^64: numbering - wshift = place in b's COO
+    s.cursor = s.dcount + wcount;
+    seg[b] = s;
+  }
+}
+
+__global__ void k_batch_finalize(const DevStatus* __restrict__ st, const BatchSeg* __restrict__ seg,
                                  const BatchOut* __restrict__ outs, int32_t count, int64_t* __restrict__ out_nnz) {
   for (int32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < count; b += gridDim.x * blockDim.x) {
-    const int64_t t = *tnnz;
-    const unsigned long long c = cursor[b];
-    out_nnz[b] = t < 0 ? t : ((int64_t)c > outs[b].cap ? -(int64_t)SPTC_ERR_CAPACITY : (int64_t)c);
+    const uint32_t err = st->err;
+    const unsigned long long c = seg[b].cursor;
+    out_nnz[b] = err ? -(int64_t)status_of(err)
+                     : ((int64_t)c > outs[b].cap ? -(int64_t)SPTC_ERR_CAPACITY : (int64_t)c);
   }
 }
 
@@ -175,20 +164,25 @@ hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t stream)
   return hipGetLastError();
 }
 
-hipError_t launch_batch_unpack(const int32_t* tidx, const double* tval, int64_t tcap, const int64_t* tnnz,
-                               BatchWidths w, int32_t count, const BatchOut* outs, int32_t* out_idx, double* out_val,
-                               unsigned long long* cursor, hipStream_t stream) {
-  if (tcap <= 0) return hipSuccess;
-  const unsigned grid = (unsigned)((tcap + kUnpackChunk - 1) / kUnpackChunk);
-  k_batch_unpack<<<grid, kUnpackBlock, (size_t)count * 12, stream>>>(tidx, tval, tcap, tnnz, w, count, outs, out_idx,
-                                                                      out_val, cursor);
+hipError_t launch_batch_segments(const GroupRec* groups, const uint32_t* dlist, int64_t nd,
+                                 const unsigned long long* dpos, const uint32_t* wlist, int64_t nw, int32_t wx,
+                                 int32_t count, BatchSeg* seg, hipStream_t stream) {
+  const int32_t g = (count + 255) / 256;
+  k_batch_segments<<<g < 1 ? 1 : g, 256, 0, stream>>>(groups, dlist, nd, dpos, wlist, nw, wx, count, seg);
   return hipGetLastError();
 }
 
-hipError_t launch_batch_finalize(const int64_t* tnnz, const unsigned long long* cursor, const BatchOut* outs,
-                                 int32_t count, int64_t* out_nnz, hipStream_t stream) {
+hipError_t launch_batch_bases(const uint32_t* wlist, const uint32_t* gn, const unsigned long long* goff, int32_t count,
+                              BatchSeg* seg, hipStream_t stream) {
   const int32_t g = (count + 255) / 256;
-  k_batch_finalize<<<g < 1 ? 1 : g, 256, 0, stream>>>(tnnz, cursor, outs, count, out_nnz);
+  k_batch_bases<<<g < 1 ? 1 : g, 256, 0, stream>>>(wlist, gn, goff, count, seg);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_finalize(const DevStatus* st, const BatchSeg* seg, const BatchOut* outs, int32_t count,
+                                 int64_t* out_nnz, hipStream_t stream) {
+  const int32_t g = (count + 255) / 256;
+  k_batch_finalize<<<g < 1 ? 1 : g, 256, 0, stream>>>(st, seg, outs, count, out_nnz);
   return hipGetLastError();
 }
 

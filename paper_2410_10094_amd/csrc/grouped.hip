@@ -63,38 +63,37 @@ struct FinXGroups {
 // X entry e's record: its Y group (start, count; count 0 when Y has no entry
 // with its contracting key) and its value.
 __device__ __forceinline__ XRec probe_y(const int32_t* __restrict__ xidx, int64_t nnz, int64_t e, const KeyPack& kc,
-                                        const YSlot* __restrict__ ytab, uint64_t ymask, int32_t max_probe_y,
+                                        const YSlot* __restrict__ ytab, const TabGeom& yg, int32_t max_probe_y,
                                         uint64_t seed, double v) {
   const uint64_t ckey = pack_key(xidx, nnz, e, kc);
-  uint64_t ys = slot_of(ckey, kc, seed, ymask);
+  ProbeSeq p = probe_seq(ckey, yg, seed);
   XRec r;
   r.ystart = 0;
   r.ycnt = 0;
   r.v = v;
   for (int32_t probe = 0; probe < max_probe_y; ++probe) {
-    const YSlot slot = ytab[ys];
+    const YSlot slot = ytab[p.slot()];
     if (slot.key == ckey) {
       r.ystart = slot.start;
       r.ycnt = slot.count;
       break;
     }
     if (slot.key == kEmpty) break;
-    ys = (ys + 1) & ymask;
+    p.next();
   }
   return r;
 }
 
 // The rest of a probe of Y's table whose home slot held another key.
-__device__ __noinline__ XRec probe_y_from(const YSlot* __restrict__ ytab, uint64_t ymask, int32_t max_probe_y,
-                                          uint64_t home, uint64_t ckey, double v) {
+__device__ __noinline__ XRec probe_y_from(const YSlot* __restrict__ ytab, ProbeSeq p, int32_t max_probe_y,
+                                          uint64_t ckey, double v) {
   XRec r;
   r.ystart = 0;
   r.ycnt = 0;
   r.v = v;
-  uint64_t s = home;
   for (int32_t probe = 1; probe < max_probe_y; ++probe) {
-    s = (s + 1) & ymask;
-    const YSlot cur = ytab[s];
+    p.next();
+    const YSlot cur = ytab[p.slot()];
     if (cur.key == ckey) {
       r.ystart = cur.start;
       r.ycnt = cur.count;
@@ -108,14 +107,14 @@ __device__ __noinline__ XRec probe_y_from(const YSlot* __restrict__ ytab, uint64
 // Places every X entry in its group's run and records its Y group.
 __global__ __launch_bounds__(256) void k_x_scatter(const int32_t* __restrict__ xidx, const double* __restrict__ xval,
                                                    int64_t nnz, KeyPack kf, KeyPack kc, Bounds b,
-                                                   YSlot* __restrict__ xtab, uint64_t xmask, int32_t max_probe_x,
-                                                   const YSlot* __restrict__ ytab, uint64_t ymask,
+                                                   YSlot* __restrict__ xtab, TabGeom xg, int32_t max_probe_x,
+                                                   const YSlot* __restrict__ ytab, TabGeom yg,
                                                    int32_t max_probe_y, uint64_t seed, XRec* __restrict__ xr,
                                                    DevStatus* st) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
     if (b.check && !coords_ok(xidx, nnz, e, b)) record_error(st, kErrCoord);
     const uint64_t fkey = pack_key(xidx, nnz, e, kf);
-    const int64_t s = find_slot(xtab, fkey, kf, xmask, seed, max_probe_x);
+    const int64_t s = find_slot(xtab, fkey, xg, seed, max_probe_x);
     if (s < 0) {
       record_error(st, kErrInternal);
       continue;
@@ -125,7 +124,7 @@ __global__ __launch_bounds__(256) void k_x_scatter(const int32_t* __restrict__ x
       record_error(st, kErrInternal);
       continue;
     }
-    xr[pos] = probe_y(xidx, nnz, e, kc, ytab, ymask, max_probe_y, seed, xval[e]);
+    xr[pos] = probe_y(xidx, nnz, e, kc, ytab, yg, max_probe_y, seed, xval[e]);
   }
 }
 
@@ -134,23 +133,24 @@ __global__ __launch_bounds__(kAggBlock) void k_x_scatter_agg(const int32_t* __re
                                                              const double* __restrict__ xval, int64_t nnz, KeyPack kf,
                                                              KeyPack kc, Bounds b, YSlot* __restrict__ xtab,
                                                              unsigned nslots, const YSlot* __restrict__ ytab,
-                                                             uint64_t ymask, int32_t max_probe_y, uint64_t seed,
+                                                             TabGeom yg, int32_t max_probe_y, uint64_t seed,
                                                              XRec* __restrict__ xr, DevStatus* st) {
   extern __shared__ unsigned s_agg[];
   place_chunk(xidx, nnz, kf, xtab, nslots, s_agg, s_agg + nslots,
               [&](const int64_t* e, const uint64_t*, const unsigned* pos, const bool* ok) {
-                uint64_t ckey[kAggUnroll], ys[kAggUnroll];
+                uint64_t ckey[kAggUnroll];
+                ProbeSeq ys[kAggUnroll];
                 YSlot slot[kAggUnroll];
                 double v[kAggUnroll];
 #pragma unroll
                 for (int u = 0; u < kAggUnroll; ++u) {
                   ckey[u] = ok[u] ? pack_key(xidx, nnz, e[u], kc) : 0ull;
-                  ys[u] = slot_of(ckey[u], kc, seed, ymask);
+                  ys[u] = probe_seq(ckey[u], yg, seed);
                 }
 #pragma unroll
                 for (int u = 0; u < kAggUnroll; ++u) {  // first probes and values, all in flight together
                   if (!ok[u]) continue;
-                  slot[u] = ytab[ys[u]];
+                  slot[u] = ytab[ys[u].slot()];
                   v[u] = xval[e[u]];
                 }
 #pragma unroll
@@ -169,7 +169,7 @@ __global__ __launch_bounds__(kAggBlock) void k_x_scatter_agg(const int32_t* __re
                     r.ystart = slot[u].start;
                     r.ycnt = slot[u].count;
                   } else if (slot[u].key != kEmpty) {
-                    r = probe_y_from(ytab, ymask, max_probe_y, ys[u], ckey[u], v[u]);
+                    r = probe_y_from(ytab, ys[u], max_probe_y, ckey[u], v[u]);
                   }
                   xr[pos[u]] = r;
                 }
@@ -413,6 +413,8 @@ __global__ __launch_bounds__(kGBlock) void k_group_wave(GroupArgs a, const uint3
       if (lane == 0) a.gn[g] = n;
     } else {
       const unsigned long long base = a.goff[g];
+      const uint32_t bb = a.bout ? (uint32_t)(G.phi >> a.bwx) : 0u;
+      const unsigned long long shift = a.bout ? a.bseg[bb].wshift : 0ull;
       unsigned long long run = 0;
       for (unsigned s0 = 0; s0 < tsize; s0 += 64) {
         const ZSlot z = tab[s0 + lane];
@@ -420,7 +422,10 @@ __global__ __launch_bounds__(kGBlock) void k_group_wave(GroupArgs a, const uint3
         const unsigned long long m = __ballot(occ);
         if (occ) {
           const unsigned long long pos = base + run + (unsigned long long)__popcll(m & lanemask_lt());
-          if ((int64_t)pos < a.out_cap) write_output(a, pos, G.phi, z.key, z.val);
+          if (a.bout)
+            batch_store(a.bout, a.out_idx, a.out_val, a.bwx, bb, pos - shift, G.phi, z.key, z.val, a.st);
+          else if ((int64_t)pos < a.out_cap)
+            write_output(a, pos, G.phi, z.key, z.val);
         }
         run += (unsigned long long)__popcll(m);
       }
@@ -627,7 +632,7 @@ __global__ __launch_bounds__(kBBlock) void k_group_block(GroupArgs a, const uint
     for (unsigned s = tid; s < tsize; s += kBBlock)
       n += DENSE ? (dense_reached(acc, flag, s) ? 1u : 0u) : (tab[s].key != kEmpty ? 1u : 0u);
     n = block_sum<kBBlock>(n, s_wave);
-    if (tid == 0) s_base = atomicAdd(&a.st->out_base, n);
+    if (tid == 0) s_base = atomicAdd(a.bout ? &a.bseg[G.phi >> a.bwx].cursor : &a.st->out_base, n);
     __syncthreads();
     const unsigned long long obase = s_base;
     unsigned long long run = 0;
@@ -650,7 +655,10 @@ __global__ __launch_bounds__(kBBlock) void k_group_block(GroupArgs a, const uint
       const unsigned long long r = block_excl_scan<kBBlock>(occ ? 1ull : 0ull, s_wave, &tot);
       if (occ) {
         const unsigned long long pos = obase + run + r;
-        if ((int64_t)pos < a.out_cap) write_output(a, pos, G.phi, key, val);
+        if (a.bout)
+          batch_store(a.bout, a.out_idx, a.out_val, a.bwx, (uint32_t)(G.phi >> a.bwx), pos, G.phi, key, val, a.st);
+        else if ((int64_t)pos < a.out_cap)
+          write_output(a, pos, G.phi, key, val);
       }
       run += tot;
     }
@@ -675,6 +683,7 @@ __global__ __launch_bounds__(kDBlock) void k_group_direct(GroupArgs a, const uin
   __shared__ unsigned long long s_phi[kDGroups];
   __shared__ double s_v[kDGroups];
   __shared__ unsigned s_ys[kDGroups];
+  __shared__ unsigned long long s_sh[kDGroups];  // batch: the group's contraction's direct shift
   __shared__ int64_t s_range[2];
   const uint64_t ntiles = (nprod + kDTile - 1) / kDTile;
   for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -694,11 +703,12 @@ __global__ __launch_bounds__(kDBlock) void k_group_direct(GroupArgs a, const uin
         s_phi[k] = G.phi;
         s_v[k] = r.v;
         s_ys[k] = r.ystart;
+        s_sh[k] = a.bout ? a.bseg[G.phi >> a.bwx].dshift : 0ull;
       }
       if (threadIdx.x == 0) s_pos[nloc] = dpos[ihi + 1];
     }
     __syncthreads();
-    unsigned long long ys[kDItems], phx[kDItems];
+    unsigned long long ys[kDItems], phx[kDItems], dsh[kDItems];
     double xv[kDItems];
     YEntry ye[kDItems];
 #pragma unroll
@@ -718,6 +728,7 @@ __global__ __launch_bounds__(kDBlock) void k_group_direct(GroupArgs a, const uin
         ys[it] = (unsigned long long)s_ys[lo] + (q - s_pos[lo]);
         phx[it] = s_phi[lo];
         xv[it] = s_v[lo];
+        dsh[it] = s_sh[lo];
       } else {
         const int64_t li = upper_bound_idx(dpos, ilo, ihi + 1, q) - 1;
         const GroupRec G = a.groups[dlist[li]];
@@ -725,6 +736,7 @@ __global__ __launch_bounds__(kDBlock) void k_group_direct(GroupArgs a, const uin
         ys[it] = (unsigned long long)r.ystart + (q - dpos[li]);
         phx[it] = G.phi;
         xv[it] = r.v;
+        dsh[it] = a.bout ? a.bseg[G.phi >> a.bwx].dshift : 0ull;
       }
       if (ys[it] >= (unsigned long long)a.ny) {
         record_error(a.st, kErrInternal);
@@ -737,7 +749,11 @@ __global__ __launch_bounds__(kDBlock) void k_group_direct(GroupArgs a, const uin
 #pragma unroll
     for (int it = 0; it < kDItems; ++it) {
       const uint64_t q = p0 + (uint64_t)it * kDBlock + threadIdx.x;
-      if (ys[it] != ~0ull && (int64_t)q < a.out_cap)
+      if (ys[it] == ~0ull) continue;
+      if (a.bout)
+        batch_store(a.bout, a.out_idx, a.out_val, a.bwx, (uint32_t)(phx[it] >> a.bwx), q - dsh[it], phx[it],
+                    ye[it].phi, __dmul_rn(xv[it], ye[it].v), a.st);
+      else if ((int64_t)q < a.out_cap)
         write_output(a, q, phx[it], ye[it].phi, __dmul_rn(xv[it], ye[it].v));
     }
     __syncthreads();
@@ -843,22 +859,22 @@ hipError_t launch_scan_x_table(YSlot* tab, int64_t nslots, GroupRec* groups, voi
 }
 
 hipError_t launch_x_scatter(const int32_t* xidx, const double* xval, int64_t nnz, KeyPack kf, KeyPack kc, Bounds b,
-                            YSlot* xtab, uint64_t xmask, int32_t max_probe_x, const YSlot* ytab, uint64_t ymask,
+                            YSlot* xtab, TabGeom xg, int32_t max_probe_x, const YSlot* ytab, TabGeom yg,
                             int32_t max_probe_y, uint64_t seed, XRec* xr, DevStatus* st, int num_cus,
                             hipStream_t stream) {
   if (nnz <= 0) return hipSuccess;
-  k_x_scatter<<<grid_for(nnz, 256, num_cus), 256, 0, stream>>>(xidx, xval, nnz, kf, kc, b, xtab, xmask, max_probe_x,
-                                                                ytab, ymask, max_probe_y, seed, xr, st);
+  k_x_scatter<<<grid_for(nnz, 256, num_cus), 256, 0, stream>>>(xidx, xval, nnz, kf, kc, b, xtab, xg, max_probe_x,
+                                                                ytab, yg, max_probe_y, seed, xr, st);
   return hipGetLastError();
 }
 
 hipError_t launch_x_scatter_agg(const int32_t* xidx, const double* xval, int64_t nnz, KeyPack kf, KeyPack kc,
-                                Bounds b, YSlot* xtab, unsigned nslots, const YSlot* ytab, uint64_t ymask,
+                                Bounds b, YSlot* xtab, unsigned nslots, const YSlot* ytab, TabGeom yg,
                                 int32_t max_probe_y, uint64_t seed, XRec* xr, DevStatus* st, hipStream_t stream) {
   if (nnz <= 0) return hipSuccess;
   const unsigned grid = (unsigned)((nnz + kAggChunk - 1) / kAggChunk);
   k_x_scatter_agg<<<grid, kAggBlock, (size_t)nslots * 8, stream>>>(xidx, xval, nnz, kf, kc, b, xtab, nslots, ytab,
-                                                                    ymask, max_probe_y, seed, xr, st);
+                                                                    yg, max_probe_y, seed, xr, st);
   return hipGetLastError();
 }
 

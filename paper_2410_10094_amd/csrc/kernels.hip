@@ -32,14 +32,15 @@ __global__ void k_fill_empty(uint4* __restrict__ slots, int64_t n, DevStatus* st
 // A1: count entries per packed key (Y by contracting key; X by free key on
 // the grouped path) in an open-addressing table with linear probing.
 __global__ __launch_bounds__(256) void k_key_count(const int32_t* __restrict__ idx, int64_t nnz, KeyPack kc,
-                                                   YSlot* __restrict__ tab, uint64_t mask, uint64_t seed,
+                                                   YSlot* __restrict__ tab, TabGeom g, uint64_t seed,
                                                    int32_t max_probe, DevStatus* st,
                                                    unsigned long long* distinct) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
     const uint64_t key = pack_key(idx, nnz, e, kc);
-    uint64_t s = slot_of(key, kc, seed, mask);
+    ProbeSeq p = probe_seq(key, g, seed);
     int32_t probe = 0;
     for (;;) {
+      const uint64_t s = p.slot();
       const unsigned long long prev = atomicCAS(&tab[s].key, (unsigned long long)kEmpty, (unsigned long long)key);
       if (prev == kEmpty || prev == key) {
         atomicAdd(&tab[s].count, 1u);
@@ -50,7 +51,7 @@ __global__ __launch_bounds__(256) void k_key_count(const int32_t* __restrict__ i
         record_error(st, kErrCapacity);
         break;
       }
-      s = (s + 1) & mask;
+      p.next();
     }
   }
 }
@@ -68,14 +69,14 @@ struct YTableScanOp {
 // the group's run and decrement).
 __global__ __launch_bounds__(256) void k_y_scatter(const int32_t* __restrict__ yidx, const double* __restrict__ yval,
                                                    int64_t nnz, KeyPack kc, KeyPack kf, Bounds b,
-                                                   YSlot* __restrict__ tab, uint64_t mask, uint64_t seed,
+                                                   YSlot* __restrict__ tab, TabGeom g, uint64_t seed,
                                                    int32_t max_probe, YEntry* __restrict__ yg,
                                                    unsigned long long* __restrict__ yset, uint64_t yset_mask,
                                                    int32_t bits_y, DevStatus* st) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
     if (b.check && !coords_ok(yidx, nnz, e, b)) record_error(st, kErrCoord);
     const uint64_t key = pack_key(yidx, nnz, e, kc);
-    const int64_t s = find_slot(tab, key, kc, mask, seed, max_probe);
+    const int64_t s = find_slot(tab, key, g, seed, max_probe);
     if (s < 0) {
       record_error(st, kErrInternal);
       continue;
@@ -113,24 +114,24 @@ __global__ void k_fill_keys(unsigned long long* __restrict__ keys, int64_t n) {
 // B1: each X entry finds its Y group: start and count (0 on a miss).
 __global__ __launch_bounds__(256) void k_x_probe(const int32_t* __restrict__ xidx, const double* __restrict__ xval,
                                                  int64_t nnz, KeyPack kc, KeyPack kf, Bounds b,
-                                                 const YSlot* __restrict__ tab, uint64_t mask, uint64_t seed,
+                                                 const YSlot* __restrict__ tab, TabGeom g, uint64_t seed,
                                                  int32_t max_probe, XEntry* __restrict__ xrec,
                                                  uint32_t* __restrict__ xg, uint32_t* __restrict__ xcnt,
                                                  DevStatus* st) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
     if (b.check && !coords_ok(xidx, nnz, e, b)) record_error(st, kErrCoord);
     const uint64_t key = pack_key(xidx, nnz, e, kc);
-    uint64_t s = slot_of(key, kc, seed, mask);
+    ProbeSeq p = probe_seq(key, g, seed);
     unsigned start = 0, count = 0;
     for (int32_t probe = 0; probe < max_probe; ++probe) {
-      const YSlot slot = tab[s];
+      const YSlot slot = tab[p.slot()];
       if (slot.key == key) {
         start = slot.start;
         count = slot.count;
         break;
       }
       if (slot.key == kEmpty) break;
-      s = (s + 1) & mask;
+      p.next();
     }
     XEntry ent;
     ent.phi = pack_key(xidx, nnz, e, kf);
@@ -296,14 +297,24 @@ struct GroupedOccupancyOp {
   double* out_val;
   int64_t out_cap;
   const unsigned long long* base;
+  const BatchOut* bout;  // batch: outputs go to the contraction's region, in place order
+  BatchSeg* bseg;
+  int32_t bwx;
+  DevStatus* st;
   __device__ unsigned long long get(int64_t i) const { return tab[i].key != kEmpty ? 1ull : 0ull; }
   __device__ void put(int64_t i, unsigned long long rank, unsigned long long v) const {
     if (!v) return;
-    const unsigned long long pos = rank + *base;
-    if ((int64_t)pos >= out_cap) return;
     const ZSlot z = tab[i];
     const unsigned long long phix = groups[glist[z.key >> bits_y]].phi;
     const unsigned long long phiy = bits_y ? (z.key & (~0ull >> (64 - bits_y))) : 0ull;
+    if (bout) {
+      const uint32_t b = (uint32_t)(phix >> bwx);
+      const unsigned long long place = wave_reserve(bseg, b);
+      batch_store(bout, out_idx, out_val, bwx, b, place, phix, phiy, z.val, st);
+      return;
+    }
+    const unsigned long long pos = rank + *base;
+    if ((int64_t)pos >= out_cap) return;
 #pragma unroll
     for (int m = 0; m < kMaxOrder; ++m)
       if (m < ux.n)
@@ -437,11 +448,11 @@ hipError_t launch_fill_empty(void* slots16, int64_t nslots, DevStatus* st, hipSt
   return hipGetLastError();
 }
 
-hipError_t launch_key_count(const int32_t* idx, int64_t nnz, KeyPack kc, YSlot* tab, uint64_t mask, uint64_t seed,
+hipError_t launch_key_count(const int32_t* idx, int64_t nnz, KeyPack kc, YSlot* tab, TabGeom g, uint64_t seed,
                             int32_t max_probe, DevStatus* st, unsigned long long* distinct, int num_cus,
                             hipStream_t stream) {
   if (nnz <= 0) return hipSuccess;
-  k_key_count<<<grid_for(nnz, 256, num_cus), 256, 0, stream>>>(idx, nnz, kc, tab, mask, seed, max_probe, st,
+  k_key_count<<<grid_for(nnz, 256, num_cus), 256, 0, stream>>>(idx, nnz, kc, tab, g, seed, max_probe, st,
                                                                 distinct);
   return hipGetLastError();
 }
@@ -451,11 +462,11 @@ hipError_t launch_scan_y_table(YSlot* tab, int64_t nslots, unsigned long long* t
 }
 
 hipError_t launch_y_scatter(const int32_t* yidx, const double* yval, int64_t nnz, KeyPack kc, KeyPack kf, Bounds b,
-                            YSlot* tab, uint64_t mask, uint64_t seed, int32_t max_probe, YEntry* yg,
+                            YSlot* tab, TabGeom g, uint64_t seed, int32_t max_probe, YEntry* yg,
                             unsigned long long* yset, uint64_t yset_mask, int32_t bits_y, DevStatus* st, int num_cus,
                             hipStream_t stream) {
   if (nnz <= 0) return hipSuccess;
-  k_y_scatter<<<grid_for(nnz, 256, num_cus), 256, 0, stream>>>(yidx, yval, nnz, kc, kf, b, tab, mask, seed,
+  k_y_scatter<<<grid_for(nnz, 256, num_cus), 256, 0, stream>>>(yidx, yval, nnz, kc, kf, b, tab, g, seed,
                                                                 max_probe, yg, yset, yset_mask, bits_y, st);
   return hipGetLastError();
 }
@@ -488,10 +499,10 @@ hipError_t launch_fill_keys(unsigned long long* keys, int64_t n, hipStream_t str
 }
 
 hipError_t launch_x_probe(const int32_t* xidx, const double* xval, int64_t nnz, KeyPack kc, KeyPack kf, Bounds b,
-                          const YSlot* tab, uint64_t mask, uint64_t seed, int32_t max_probe, XEntry* xrec,
+                          const YSlot* tab, TabGeom g, uint64_t seed, int32_t max_probe, XEntry* xrec,
                           uint32_t* xg, uint32_t* xcnt, DevStatus* st, int num_cus, hipStream_t stream) {
   if (nnz <= 0) return hipSuccess;
-  k_x_probe<<<grid_for(nnz, 256, num_cus), 256, 0, stream>>>(xidx, xval, nnz, kc, kf, b, tab, mask, seed, max_probe,
+  k_x_probe<<<grid_for(nnz, 256, num_cus), 256, 0, stream>>>(xidx, xval, nnz, kc, kf, b, tab, g, seed, max_probe,
                                                               xrec, xg, xcnt, st);
   return hipGetLastError();
 }
@@ -524,9 +535,11 @@ hipError_t launch_compact(const ZSlot* tab, int64_t nslots, KeyUnpack ku, int32_
 hipError_t launch_compact_grouped(const ZSlot* tab, int64_t nslots, const GroupRec* groups, const uint32_t* glist,
                                   KeyUnpack ux, KeyUnpack uy, int32_t bits_y, int32_t* out_idx, double* out_val,
                                   int64_t out_cap, int64_t* out_nnz, const unsigned long long* base,
-                                  unsigned long long* tile_sums, DevStatus* st, hipStream_t stream) {
-  return device_scan(GroupedOccupancyOp{tab, groups, glist, ux, uy, bits_y, out_idx, out_val, out_cap, base}, nslots,
-                     tile_sums, FinCompact{out_nnz, out_cap, base, st}, stream);
+                                  unsigned long long* tile_sums, DevStatus* st, const BatchOut* bout, BatchSeg* bseg,
+                                  int32_t bwx, hipStream_t stream) {
+  return device_scan(GroupedOccupancyOp{tab, groups, glist, ux, uy, bits_y, out_idx, out_val, out_cap, base, bout,
+                                        bseg, bwx, st},
+                     nslots, tile_sums, FinCompact{out_nnz, out_cap, base, st}, stream);
 }
 
 hipError_t launch_y_groups(const YSlot* tab, int64_t nslots, KeyUnpack ku, int32_t* key_coords, int64_t* counts,

@@ -244,19 +244,46 @@ __device__ __forceinline__ unsigned long long full_y_key(uint64_t ckey, uint64_t
 }
 
 // Home slot of a key in a table keyed by kp's packing.
-__device__ __forceinline__ uint64_t slot_of(uint64_t key, const KeyPack& kp, uint64_t seed, uint64_t mask) {
-  return kp.ident ? (key & mask) : (fmix64(key ^ seed) & mask);
+// Calls f(i) with i in a scalar register when every active lane of the wave
+// holds the same i (the common case: lanes walk one contraction's entries),
+// so that what f loads through i comes from scalar loads; else f(i) per lane.
+template <class F>
+__device__ __forceinline__ void with_uniform(uint32_t i, F&& f) {
+  const uint32_t i0 = __builtin_amdgcn_readfirstlane(i);
+  if (__ballot(i != i0) == 0ull)
+    f(i0);
+  else
+    f(i);
+}
+
+// Linear probing inside a key's table or region: slot() = base + off.
+struct ProbeSeq {
+  uint64_t base, mask, off;
+  __device__ __forceinline__ uint64_t slot() const { return base + off; }
+  __device__ __forceinline__ void next() { off = (off + 1) & mask; }
+};
+
+__device__ __forceinline__ ProbeSeq probe_seq(uint64_t key, const TabGeom& g, uint64_t seed) {
+  if (g.reg) {
+    ProbeSeq p;
+    with_uniform((uint32_t)(key >> g.pshift), [&](uint32_t b) {
+      const Region r = g.reg[b];
+      p = ProbeSeq{r.base, r.mask, (r.ident ? key : fmix64(key ^ seed)) & r.mask};
+    });
+    return p;
+  }
+  return ProbeSeq{0ull, g.mask, (g.ident ? key : fmix64(key ^ seed)) & g.mask};
 }
 
 // Finds `key` in a YSlot table; returns the slot or -1.
-__device__ __forceinline__ int64_t find_slot(const YSlot* __restrict__ tab, uint64_t key, const KeyPack& kp,
-                                             uint64_t mask, uint64_t seed, int32_t max_probe) {
-  uint64_t s = slot_of(key, kp, seed, mask);
+__device__ __forceinline__ int64_t find_slot(const YSlot* __restrict__ tab, uint64_t key, const TabGeom& g,
+                                             uint64_t seed, int32_t max_probe) {
+  ProbeSeq p = probe_seq(key, g, seed);
   for (int32_t probe = 0; probe < max_probe; ++probe) {
-    const unsigned long long k = tab[s].key;
-    if (k == key) return (int64_t)s;
+    const unsigned long long k = tab[p.slot()].key;
+    if (k == key) return (int64_t)p.slot();
     if (k == kEmpty) return -1;
-    s = (s + 1) & mask;
+    p.next();
   }
   return -1;
 }
@@ -378,6 +405,56 @@ __device__ __forceinline__ void set_insert_batch(unsigned long long* __restrict_
         seen[u] = true;
         break;
       }
+    }
+  }
+}
+
+__device__ __forceinline__ uint64_t low_mask(int bits) { return bits >= 64 ? ~0ull : ((1ull << bits) - 1ull); }
+
+// Output `pos` of contraction b of a batch, in b's COO region: X free
+// coordinates from phix (b's index above bit bwx), Y free ones from phiy.
+__device__ __forceinline__ void batch_store_at(const BatchOut* __restrict__ bout, int32_t* __restrict__ out_idx,
+                                               double* __restrict__ out_val, int32_t bwx, uint32_t b,
+                                               unsigned long long pos, uint64_t phix, uint64_t phiy, double v,
+                                               DevStatus* st) {
+  const BatchOut& d = bout[b];
+  if ((int64_t)pos >= d.cap) {
+    record_error(st, kErrCapacity);
+    return;
+  }
+  const uint64_t fx = phix & low_mask(bwx);
+  const int nx = d.ux.n, ny = d.uy.n;
+  int32_t* row = out_idx + d.idx_off + (int64_t)pos;
+#pragma unroll
+  for (int m = 0; m < kMaxOrder; ++m)
+    if (m < nx) __builtin_nontemporal_store((int32_t)((fx >> d.ux.shift[m]) & d.ux.mask[m]), row + (int64_t)m * d.cap);
+#pragma unroll
+  for (int m = 0; m < kMaxOrder; ++m)
+    if (m < ny)
+      __builtin_nontemporal_store((int32_t)((phiy >> d.uy.shift[m]) & d.uy.mask[m]), row + (int64_t)(nx + m) * d.cap);
+  __builtin_nontemporal_store(v, &out_val[d.val_off + (int64_t)pos]);
+}
+
+__device__ __forceinline__ void batch_store(const BatchOut* __restrict__ bout, int32_t* __restrict__ out_idx,
+                                            double* __restrict__ out_val, int32_t bwx, uint32_t b,
+                                            unsigned long long pos, uint64_t phix, uint64_t phiy, double v,
+                                            DevStatus* st) {
+  with_uniform(b, [&](uint32_t bu) { batch_store_at(bout, out_idx, out_val, bwx, bu, pos, phix, phiy, v, st); });
+}
+
+// Reserves one place per calling lane from seg[b].cursor: one atomic per
+// distinct b among the wave's active lanes.
+__device__ __forceinline__ unsigned long long wave_reserve(BatchSeg* seg, uint32_t b) {
+  const unsigned lane = threadIdx.x & 63u;
+  for (;;) {
+    const uint32_t bl = __builtin_amdgcn_readfirstlane(b);
+    const unsigned long long m = __ballot(b == bl);
+    if (b == bl) {
+      const int leader = __ffsll((long long)m) - 1;
+      unsigned long long base = 0ull;
+      if ((int)lane == leader) base = atomicAdd(&seg[bl].cursor, (unsigned long long)__popcll(m));
+      base = __shfl(base, leader, 64);
+      return base + (unsigned long long)__popcll(m & ((1ull << lane) - 1ull));
     }
   }
 }

@@ -177,7 +177,7 @@ struct sptc_plan_s : Workspace {
   unsigned long long* poff = nullptr;
   unsigned long long* tile_sums = nullptr;
   DevStatus* st = nullptr;
-  int64_t* scratch = nullptr;
+  int64_t* readback = nullptr;  // device counts read back by the inspection calls
   ZSlot* ztab = nullptr;
   int64_t ztab_slots = 0;
   unsigned long long* ztile_sums = nullptr;
@@ -214,6 +214,20 @@ struct sptc_plan_s : Workspace {
 
   int64_t products = 0, y_groups = 0, out_bound = 0;
   int32_t max_probe_y = 0, max_probe_z = 0;
+
+  // key table geometry; a batch's packed problem has one region per contraction
+  TabGeom ygeom{}, xgeom{};
+  std::vector<Region> xreg_h;
+  Region* xreg = nullptr;
+};
+
+// Per-contraction regions of the X free key table of a batch's packed
+// problem (keys >> xshift give the contraction): the X groups, and so every
+// list of groups, come out ordered by contraction.  Y's table stays one
+// hashed array.
+struct BatchRegions {
+  std::vector<Region> x;
+  int32_t xshift = 0;
 };
 
 
@@ -226,6 +240,7 @@ struct Layout {
   Bounds xb{}, yb{};
   KeyUnpack ux{}, uy{};
   uint64_t ycells = 1;
+  int64_t c_cells = 1, fx_cells = 1;  // contracting / X free key spaces (saturating)
 };
 
 // A batch: the packed problem's plan plus each contraction's output layout.
@@ -239,10 +254,8 @@ struct sptc_batch_s : Workspace {
   };
   std::vector<Item> items;
   BatchOut* outs = nullptr;  // device [count]
-  int64_t tcap = 0;          // packed outputs in the caller's scratch: 4 int32 index rows and a double row of tcap
-  int64_t scratch_bytes = 0;
-  int64_t* tnnz = nullptr;
-  unsigned long long* cursor = nullptr;
+  BatchSeg* seg = nullptr;   // device [count]
+  int64_t* tnnz = nullptr;   // the packed plan's own output count (unused)
   int64_t idx_elems = 0, val_elems = 0;
 };
 
@@ -361,15 +374,14 @@ int32_t yset_bits(const sptc_plan_s* P) { return P->bits_c + P->bits_fy <= 63 ? 
 // A1-A3: Y grouped by contracting key (both modes).
 sptc_status plan_group_y(sptc_plan_s* P, const sptc_coo* Y) {
   const hipStream_t s = P->stream;
-  const uint64_t ymask = (uint64_t)P->ytab_slots - 1;
   const uint64_t seed = P->opt.hash_seed;
   HIP_TRY(mark(P, s, SPTC_STAGE_Y_COUNT, 0));
   HIP_TRY(launch_fill_empty(P->ytab, P->ytab_slots, nullptr, s));
   if (P->y_agg)
     HIP_TRY(launch_key_count_agg(Y->idx, P->ny, P->y_c, P->ytab, (unsigned)P->ytab_slots, &P->st->groups, s));
   else
-    HIP_TRY(launch_key_count(Y->idx, P->ny, P->y_c, P->ytab, ymask, seed, P->max_probe_y, P->st, &P->st->groups,
-                             P->num_cus, s));
+    HIP_TRY(launch_key_count(Y->idx, P->ny, P->y_c, P->ytab, P->ygeom, seed, P->max_probe_y, P->st,
+                             &P->st->groups, P->num_cus, s));
   HIP_TRY(mark(P, s, SPTC_STAGE_Y_COUNT, 1));
   HIP_TRY(mark(P, s, SPTC_STAGE_Y_SCAN, 0));
   HIP_TRY(launch_scan_y_table(P->ytab, P->ytab_slots, P->tile_sums, s));
@@ -380,7 +392,7 @@ sptc_status plan_group_y(sptc_plan_s* P, const sptc_coo* Y) {
     HIP_TRY(launch_y_scatter_agg(Y->idx, Y->val, P->ny, P->y_c, P->y_f, P->yb, P->ytab, (unsigned)P->ytab_slots,
                                  P->yg, P->yset, (uint64_t)P->yset_slots - 1, seed, yset_bits(P), P->st, s));
   else
-    HIP_TRY(launch_y_scatter(Y->idx, Y->val, P->ny, P->y_c, P->y_f, P->yb, P->ytab, ymask, seed, P->max_probe_y,
+    HIP_TRY(launch_y_scatter(Y->idx, Y->val, P->ny, P->y_c, P->y_f, P->yb, P->ytab, P->ygeom, seed, P->max_probe_y,
                              P->yg, P->yset, (uint64_t)P->yset_slots - 1, yset_bits(P), P->st, P->num_cus, s));
   if (P->opt.mode == SPTC_MODE_GROUPED && P->dense)
     HIP_TRY(launch_sort_y_runs(P->ytab, P->ytab_slots, P->yg, P->ny, P->ykey16, P->yval, P->num_cus, s));
@@ -390,14 +402,13 @@ sptc_status plan_group_y(sptc_plan_s* P, const sptc_coo* Y) {
 
 sptc_status plan_global(sptc_plan_s* P, const sptc_coo* X) {
   const hipStream_t s = P->stream;
-  const uint64_t ymask = (uint64_t)P->ytab_slots - 1;
   sptc_status st;
   if ((st = P->allocate_n(P->nx, &P->xrec))) return st;
   if ((st = P->allocate_n(P->nx, &P->xg))) return st;
   if ((st = P->allocate_n(P->nx, &P->xcnt))) return st;
   if ((st = P->allocate_n(P->nx + 1, &P->poff))) return st;
   HIP_TRY(mark(P, s, SPTC_STAGE_X_PROBE, 0));
-  HIP_TRY(launch_x_probe(X->idx, X->val, P->nx, P->x_c, P->x_f, P->xb, P->ytab, ymask, P->opt.hash_seed,
+  HIP_TRY(launch_x_probe(X->idx, X->val, P->nx, P->x_c, P->x_f, P->xb, P->ytab, P->ygeom, P->opt.hash_seed,
                          P->max_probe_y, P->xrec, P->xg, P->xcnt, P->st, P->num_cus, s));
   HIP_TRY(mark(P, s, SPTC_STAGE_X_PROBE, 1));
   HIP_TRY(mark(P, s, SPTC_STAGE_P_SCAN, 0));
@@ -418,8 +429,6 @@ sptc_status plan_global(sptc_plan_s* P, const sptc_coo* X) {
 // device-memory output hash.
 sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
   const hipStream_t s = P->stream;
-  const uint64_t ymask = (uint64_t)P->ytab_slots - 1;
-  const uint64_t xmask = (uint64_t)P->xtab_slots - 1;
   const uint64_t seed = P->opt.hash_seed;
   sptc_status st;
   if ((st = P->allocate_n(P->xtab_slots, &P->xtab))) return st;
@@ -437,15 +446,15 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
   if (P->x_agg)
     HIP_TRY(launch_key_count_agg(X->idx, P->nx, P->x_f, P->xtab, (unsigned)P->xtab_slots, nullptr, s));
   else
-    HIP_TRY(launch_key_count(X->idx, P->nx, P->x_f, P->xtab, xmask, seed, P->max_probe_x, P->st, nullptr,
+    HIP_TRY(launch_key_count(X->idx, P->nx, P->x_f, P->xtab, P->xgeom, seed, P->max_probe_x, P->st, nullptr,
                              P->num_cus, s));
   HIP_TRY(launch_scan_x_table(P->xtab, P->xtab_slots, P->groups, P->tile_sums, P->st, s));
   if (P->x_agg)
     HIP_TRY(launch_x_scatter_agg(X->idx, X->val, P->nx, P->x_f, P->x_c, P->xb, P->xtab, (unsigned)P->xtab_slots,
-                                 P->ytab, ymask, P->max_probe_y, seed, P->xr, P->st, s));
+                                 P->ytab, P->ygeom, P->max_probe_y, seed, P->xr, P->st, s));
   else
-    HIP_TRY(launch_x_scatter(X->idx, X->val, P->nx, P->x_f, P->x_c, P->xb, P->xtab, xmask, P->max_probe_x, P->ytab,
-                             ymask, P->max_probe_y, seed, P->xr, P->st, P->num_cus, s));
+    HIP_TRY(launch_x_scatter(X->idx, X->val, P->nx, P->x_f, P->x_c, P->xb, P->xtab, P->xgeom, P->max_probe_x,
+                             P->ytab, P->ygeom, P->max_probe_y, seed, P->xr, P->st, P->num_cus, s));
   HIP_TRY(mark(P, s, SPTC_STAGE_X_PROBE, 1));
   HIP_TRY(mark(P, s, SPTC_STAGE_P_SCAN, 0));
   HIP_TRY(launch_scan_entries(P->xr, P->nx, P->eoff, P->tile_sums, P->st, s));
@@ -493,24 +502,39 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
   return size_out_table(P, P->expand_products);
 }
 
-sptc_status plan_body(sptc_plan_s* P, const sptc_coo* X, const sptc_coo* Y, const int32_t* cx, const int32_t* cy) {
+sptc_status plan_body(sptc_plan_s* P, const sptc_coo* X, const sptc_coo* Y, const int32_t* cx, const int32_t* cy,
+                      const BatchRegions* br) {
   // Key tables sized from the number of distinct keys they can hold.
   std::vector<int32_t> cyv(cy, cy + P->nc), fx;
   for (int32_t m = 0; m < X->order; ++m)
     if (std::find(cx, cx + P->nc, m) == cx + P->nc) fx.push_back(m);
+  const bool grouped = P->opt.mode == SPTC_MODE_GROUPED;
   const int64_t y_bound = std::min<int64_t>(P->ny, sat_prod(Y->dims, cyv));
   P->ytab_slots = P->y_c.ident ? std::max<int64_t>((int64_t)1 << P->bits_c, 2)
                                : pow2_at_least((double)y_bound / P->opt.load_factor);
-  P->max_probe_y = P->opt.max_probe > 0 ? P->opt.max_probe : (int32_t)std::min<int64_t>(P->ytab_slots, 1 << 30);
-  const bool grouped = P->opt.mode == SPTC_MODE_GROUPED;
-  if (grouped) {
-    const int64_t x_bound = std::min<int64_t>(P->nx, sat_prod(X->dims, fx));
-    P->xtab_slots = P->x_f.ident ? std::max<int64_t>((int64_t)1 << P->bits_fx, 2)
-                                 : pow2_at_least((double)x_bound / P->opt.load_factor);
-    P->max_probe_x = P->opt.max_probe > 0 ? P->opt.max_probe : (int32_t)std::min<int64_t>(P->xtab_slots, 1 << 30);
+  if (br) {  // one X region per contraction, laid out by the batch
+    P->xreg_h = br->x;
+    P->xtab_slots = (int64_t)(br->x.back().base + br->x.back().mask + 1);
+  } else {
+    if (grouped) {
+      const int64_t x_bound = std::min<int64_t>(P->nx, sat_prod(X->dims, fx));
+      P->xtab_slots = P->x_f.ident ? std::max<int64_t>((int64_t)1 << P->bits_fx, 2)
+                                   : pow2_at_least((double)x_bound / P->opt.load_factor);
+    }
   }
+  P->max_probe_y = P->opt.max_probe > 0 ? P->opt.max_probe : (int32_t)std::min<int64_t>(P->ytab_slots, 1 << 30);
+  if (grouped)
+    P->max_probe_x = P->opt.max_probe > 0 ? P->opt.max_probe : (int32_t)std::min<int64_t>(P->xtab_slots, 1 << 30);
+  P->ygeom = TabGeom{(uint64_t)P->ytab_slots - 1, nullptr, 0, P->y_c.ident};
+  P->xgeom = TabGeom{(uint64_t)P->xtab_slots - 1, nullptr, 0, P->x_f.ident};
 
   sptc_status st;
+  if (br) {
+    if ((st = P->allocate_n((int64_t)br->x.size(), &P->xreg))) return st;
+    HIP_TRY(hipMemcpyAsync(P->xreg, P->xreg_h.data(), sizeof(Region) * P->xreg_h.size(), hipMemcpyHostToDevice,
+                           P->stream));
+    P->xgeom = TabGeom{0, P->xreg, br->xshift, 0};
+  }
   if ((st = P->allocate_n(P->ytab_slots, &P->ytab))) return st;
   if ((st = P->allocate_n(P->ny, &P->yg))) return st;
   if (grouped && P->dense) {
@@ -527,7 +551,7 @@ sptc_status plan_body(sptc_plan_s* P, const sptc_coo* X, const sptc_coo* Y, cons
     if ((st = P->allocate_n(P->yset_slots, &P->yset))) return st;
   }
   if ((st = P->allocate_n(1, &P->st))) return st;
-  if ((st = P->allocate_n(2, &P->scratch))) return st;
+  if ((st = P->allocate_n(2, &P->readback))) return st;
   HIP_TRY(hipMemsetAsync(P->st, 0, sizeof(DevStatus), P->stream));
   if ((st = plan_group_y(P, Y))) return st;
   return grouped ? plan_grouped(P, X) : plan_global(P, X);
@@ -581,6 +605,8 @@ void make_layout(const sptc_coo* X, const sptc_coo* Y, int32_t ncontract, const 
   add_unpack(L->ux, L->x_f, 0);
   add_unpack(L->uy, L->y_f, 0);
   L->ycells = (uint64_t)sat_prod(Y->dims, fy);
+  L->c_cells = sat_prod(X->dims, cxv);
+  L->fx_cells = sat_prod(X->dims, fx);
   L->xb = make_bounds(X, validate);
   L->yb = make_bounds(Y, validate);
 }
@@ -595,6 +621,178 @@ sptc_status check_key_widths(const Layout& L, int32_t mode) {
   return SPTC_OK;
 }
 
+// sptc_plan, or (br != nullptr) the plan of a batch's packed problem, whose
+// key tables are cut into the batch's per-contraction regions.
+sptc_status plan_create(sptc_plan_t* plan, const sptc_coo* X, const sptc_coo* Y, int32_t ncontract, const int32_t* cx,
+                        const int32_t* cy, const sptc_options* opt, const sptc_allocator* alloc, void* stream,
+                        const BatchRegions* br) {
+  if (!plan) return fail(SPTC_ERR_INVALID_ARG, "plan is NULL");
+  *plan = nullptr;
+  sptc_status st;
+  if ((st = check_problem(X, Y, ncontract, cx, cy))) return st;
+  sptc_options o;
+  sptc_default_options(&o);
+  if (opt) o = *opt;
+  if ((st = check_options(o))) return st;
+  if (alloc && (!alloc->alloc || !alloc->release))
+    return fail(SPTC_ERR_INVALID_ARG, "allocator must provide alloc and release");
+  Layout L;
+  make_layout(X, Y, ncontract, cx, cy, o.validate, &L);
+  if ((st = check_key_widths(L, o.mode))) return st;
+  if (br) {  // regions decide direct addressing of X free keys per contraction
+    if (o.mode != SPTC_MODE_GROUPED) return fail(SPTC_ERR_INTERNAL, "table regions need the grouped mode");
+    L.x_f.ident = 0;
+  }
+
+  sptc_plan_s* P = new (std::nothrow) sptc_plan_s();
+  if (!P) return fail(SPTC_ERR_OUT_OF_MEMORY, "host allocation failed");
+  P->opt = o;
+  P->stream = static_cast<hipStream_t>(stream);
+  if (alloc) {
+    P->has_alloc = true;
+    P->alloc = *alloc;
+  }
+  P->ox = X->order;
+  P->oy = Y->order;
+  P->nc = ncontract;
+  P->nx = X->nnz;
+  P->ny = Y->nnz;
+  P->x_c = L.x_c;
+  P->y_c = L.y_c;
+  P->x_f = L.x_f;
+  P->y_f = L.y_f;
+  P->bits_c = L.bits_c;
+  P->bits_fx = L.bits_fx;
+  P->bits_fy = L.bits_fy;
+  P->nfy = L.nfy;
+  P->out_order = L.out_order;
+  for (int32_t m = 0; m < L.out_order; ++m) P->out_dims[m] = L.out_dims[m];
+  if (L.bits_fx + L.bits_fy <= 63) {  // packed output key (global mode, global class)
+    add_unpack(P->out_unpack, P->x_f, P->bits_fy);
+    add_unpack(P->out_unpack, P->y_f, 0);
+  }
+  add_unpack(P->ykey_unpack, P->y_c, 0);
+  add_unpack(P->yfree_unpack, P->y_f, 0);
+  P->y_agg = P->bits_c <= kAggBits ? 1 : 0;
+  P->x_agg = (!br && o.mode == SPTC_MODE_GROUPED && P->bits_fx <= kAggBits) ? 1 : 0;
+  P->ux = L.ux;
+  P->uy = L.uy;
+  P->ycells = L.ycells;
+  P->dense = P->bits_fy <= kDenseBits ? 1 : 0;
+  P->xb = L.xb;
+  P->yb = L.yb;
+
+  DeviceInfo* di = nullptr;
+  hipError_t e = hipGetDevice(&P->device);
+  if (e != hipSuccess) {
+    delete P;
+    return hip_fail(e, "hipGetDevice");
+  }
+  if ((st = device_info(P->device, &di)) || (!P->has_alloc && (st = configure_pool(P->device, di)))) {
+    delete P;
+    return st;
+  }
+  P->num_cus = di->num_cus;
+
+  st = plan_body(P, X, Y, cx, cy, br);
+  if (st != SPTC_OK) {
+    std::string msg = g_last_error;
+    (void)hipStreamSynchronize(P->stream);
+    P->release_all();
+    delete P;
+    g_last_error = msg;
+    return st;
+  }
+  *plan = P;
+  return SPTC_OK;
+}
+
+// Outputs of a batch's packed plan: per-contraction COO regions, positions
+// and nnz (out_nnz of execute_plan then only receives the packed total).
+struct BatchExec {
+  const BatchOut* bout;
+  BatchSeg* bseg;
+  int32_t bwx;
+  int32_t count;
+  int64_t* out_nnz;
+};
+
+sptc_status execute_plan(sptc_plan_s* P, int32_t* out_idx, double* out_val, int64_t out_cap, int64_t* out_nnz,
+                         hipStream_t s, const BatchExec* bx) {
+  if (bx) out_cap = INT64_MAX;  // capacity is checked per contraction
+  if (P->opt.mode == SPTC_MODE_GROUPED) {
+    HIP_TRY(launch_reset_status(P->st, s));
+    GroupArgs a{};
+    a.groups = P->groups;
+    a.xr = P->xr;
+    a.eoff = P->eoff;
+    a.yg = P->yg;
+    a.ykey16 = P->ykey16;
+    a.yval = P->yval;
+    a.ny = P->ny;
+    a.ycells = P->ycells;
+    a.seed = P->opt.hash_seed;
+    a.bits_y = P->bits_fy;
+    a.ux = P->ux;
+    a.uy = P->uy;
+    a.gn = P->gn;
+    a.goff = P->goff;
+    a.out_idx = out_idx;
+    a.out_val = out_val;
+    a.out_cap = out_cap;
+    a.st = P->st;
+    if (bx) {
+      a.bout = bx->bout;
+      a.bseg = bx->bseg;
+      a.bwx = bx->bwx;
+    }
+    HIP_TRY(mark(P, s, SPTC_STAGE_GROUP_COUNT, 0));
+    HIP_TRY(launch_group_wave(a, P->wlist, P->nw, 0, P->num_cus, s));
+    HIP_TRY(mark(P, s, SPTC_STAGE_GROUP_COUNT, 1));
+    HIP_TRY(mark(P, s, SPTC_STAGE_GROUP_FILL, 0));
+    HIP_TRY(launch_scan_group_counts(P->gn, P->wlist, P->nw, (uint64_t)P->direct_products, P->goff, P->etile_sums,
+                                     P->st, s));
+    if (bx) HIP_TRY(launch_batch_bases(P->wlist, P->gn, P->goff, bx->count, bx->bseg, s));
+    HIP_TRY(launch_group_wave(a, P->wlist, P->nw, 1, P->num_cus, s));
+    HIP_TRY(mark(P, s, SPTC_STAGE_GROUP_FILL, 1));
+    HIP_TRY(mark(P, s, SPTC_STAGE_DIRECT, 0));
+    HIP_TRY(launch_group_direct(a, P->dlist, P->dpos, P->nd, (uint64_t)P->direct_products, P->num_cus, s));
+    HIP_TRY(mark(P, s, SPTC_STAGE_DIRECT, 1));
+    HIP_TRY(mark(P, s, SPTC_STAGE_BLOCK, 0));
+    HIP_TRY(launch_group_block(a, P->blist, P->nb, P->dense, P->num_cus, s));
+    HIP_TRY(mark(P, s, SPTC_STAGE_BLOCK, 1));
+    if (P->ngl == 0) {
+      HIP_TRY(mark(P, s, SPTC_STAGE_COMPACT, 0));
+      if (bx)
+        HIP_TRY(launch_batch_finalize(P->st, bx->bseg, bx->bout, bx->count, bx->out_nnz, s));
+      else
+        HIP_TRY(launch_finalize(out_nnz, out_cap, P->st, s));
+      HIP_TRY(mark(P, s, SPTC_STAGE_COMPACT, 1));
+      return SPTC_OK;
+    }
+  }
+  const bool grouped = P->opt.mode == SPTC_MODE_GROUPED;
+  const uint64_t zmask = (uint64_t)P->ztab_slots - 1;
+  HIP_TRY(mark(P, s, SPTC_STAGE_OUT_CLEAR, 0));
+  HIP_TRY(launch_fill_empty(P->ztab, P->ztab_slots, grouped ? nullptr : P->st, s));
+  HIP_TRY(mark(P, s, SPTC_STAGE_OUT_CLEAR, 1));
+  HIP_TRY(mark(P, s, SPTC_STAGE_EXPAND, 0));
+  HIP_TRY(launch_expand_acc(P->poff, P->expand_nx, P->xrec, P->xg, P->yg, P->ny, P->bits_fy, P->ztab, zmask,
+                            P->opt.hash_seed, P->max_probe_z, (uint64_t)P->expand_products, P->st, P->num_cus, s));
+  HIP_TRY(mark(P, s, SPTC_STAGE_EXPAND, 1));
+  HIP_TRY(mark(P, s, SPTC_STAGE_COMPACT, 0));
+  if (grouped) {
+    HIP_TRY(launch_compact_grouped(P->ztab, P->ztab_slots, P->groups, P->glist, P->ux, P->uy, P->bits_fy, out_idx,
+                                   out_val, out_cap, out_nnz, &P->st->out_base, P->ztile_sums, P->st,
+                                   bx ? bx->bout : nullptr, bx ? bx->bseg : nullptr, bx ? bx->bwx : 0, s));
+    if (bx) HIP_TRY(launch_batch_finalize(P->st, bx->bseg, bx->bout, bx->count, bx->out_nnz, s));
+  } else
+    HIP_TRY(launch_compact(P->ztab, P->ztab_slots, P->out_unpack, out_idx, out_val, out_cap, out_nnz, nullptr,
+                           P->ztile_sums, P->st, s));
+  HIP_TRY(mark(P, s, SPTC_STAGE_COMPACT, 1));
+  return SPTC_OK;
+}
+
 constexpr int32_t kBatchMax = 4096;  // k_batch_unpack keeps 12 bytes per contraction in LDS
 constexpr int64_t kPackTile = 8192;
 
@@ -605,6 +803,23 @@ int64_t layout_cells(const Layout& L) {
     cells *= L.out_dims[m];
   }
   return cells;
+}
+
+// A contraction's region of a batch key table, for n keys of `bits` bits:
+// directly addressed when that costs at most 4x the hashed size.
+Region make_region(int32_t bits, int64_t n, double load_factor, uint64_t* next_base) {
+  const int64_t hashed = pow2_at_least((double)std::max<int64_t>(n, 1) / load_factor);
+  Region r{};
+  r.base = *next_base;
+  if (bits <= kIdentBits && ((int64_t)1 << bits) <= 4 * hashed) {
+    r.mask = (uint32_t)(std::max<int64_t>((int64_t)1 << bits, 2) - 1);
+    r.ident = 1;
+  } else {
+    r.mask = (uint32_t)(hashed - 1);
+    r.ident = 0;
+  }
+  *next_base += (uint64_t)r.mask + 1;
+  return r;
 }
 
 // Packs every contraction's entries with its index as key prefix, plans the
@@ -700,8 +915,16 @@ sptc_status batch_body(sptc_batch_s* B, const sptc_coo* X, const sptc_coo* Y, co
   const int32_t cmodes[2] = {0, 1};
   sptc_options io = o;
   io.validate = 0;  // packed coordinates are in range by construction; the pack checked the originals
+  BatchRegions br;
+  br.xshift = wx;
+  uint64_t xbase = 0;
+  for (int32_t b = 0; b < count; ++b) {
+    const Layout& L = B->items[b].L;
+    br.x.push_back(make_region(L.bits_fx, std::min<int64_t>(in[b].nx, L.fx_cells), o.load_factor, &xbase));
+  }
   sptc_plan_t inner = nullptr;
-  if ((st = sptc_plan(&inner, &PX, &PY, 2, cmodes, cmodes, &io, B->has_alloc ? &B->alloc : nullptr, s))) return st;
+  if ((st = plan_create(&inner, &PX, &PY, 2, cmodes, cmodes, &io, B->has_alloc ? &B->alloc : nullptr, s, &br)))
+    return st;
   B->inner = inner;
 
   // Products per contraction, from the packed plan's X groups.
@@ -732,12 +955,12 @@ sptc_status batch_body(sptc_batch_s* B, const sptc_coo* X, const sptc_coo* Y, co
   if (total != inner->products)
     return fail(SPTC_ERR_INTERNAL, "per-contraction products add up to %lld, not %lld", (long long)total,
                 (long long)inner->products);
-  B->tcap = inner->out_bound;
-  B->scratch_bytes = B->tcap * (int64_t)(sizeof(double) + 4 * sizeof(int32_t));
   if ((st = B->allocate_n(count, &B->outs))) return st;
+  if ((st = B->allocate_n(count, &B->seg))) return st;
   if ((st = B->allocate_n(1, &B->tnnz))) return st;
-  if ((st = B->allocate_n(count, &B->cursor))) return st;
   HIP_TRY(hipMemcpyAsync(B->outs, outs.data(), sizeof(BatchOut) * count, hipMemcpyHostToDevice, s));
+  HIP_TRY(launch_batch_segments(inner->groups, inner->dlist, inner->nd, inner->dpos, inner->wlist, inner->nw, wx, count,
+                                B->seg, s));
   HIP_TRY(hipStreamSynchronize(s));  // host arrays above are copied before they go out of scope
   return SPTC_OK;
 }
@@ -759,81 +982,7 @@ void sptc_default_options(sptc_options* opt) {
 
 sptc_status sptc_plan(sptc_plan_t* plan, const sptc_coo* X, const sptc_coo* Y, int32_t ncontract, const int32_t* cx,
                       const int32_t* cy, const sptc_options* opt, const sptc_allocator* alloc, void* stream) {
-  if (!plan) return fail(SPTC_ERR_INVALID_ARG, "plan is NULL");
-  *plan = nullptr;
-  sptc_status st;
-  if ((st = check_problem(X, Y, ncontract, cx, cy))) return st;
-  sptc_options o;
-  sptc_default_options(&o);
-  if (opt) o = *opt;
-  if ((st = check_options(o))) return st;
-  if (alloc && (!alloc->alloc || !alloc->release))
-    return fail(SPTC_ERR_INVALID_ARG, "allocator must provide alloc and release");
-  Layout L;
-  make_layout(X, Y, ncontract, cx, cy, o.validate, &L);
-  if ((st = check_key_widths(L, o.mode))) return st;
-
-  sptc_plan_s* P = new (std::nothrow) sptc_plan_s();
-  if (!P) return fail(SPTC_ERR_OUT_OF_MEMORY, "host allocation failed");
-  P->opt = o;
-  P->stream = static_cast<hipStream_t>(stream);
-  if (alloc) {
-    P->has_alloc = true;
-    P->alloc = *alloc;
-  }
-  P->ox = X->order;
-  P->oy = Y->order;
-  P->nc = ncontract;
-  P->nx = X->nnz;
-  P->ny = Y->nnz;
-  P->x_c = L.x_c;
-  P->y_c = L.y_c;
-  P->x_f = L.x_f;
-  P->y_f = L.y_f;
-  P->bits_c = L.bits_c;
-  P->bits_fx = L.bits_fx;
-  P->bits_fy = L.bits_fy;
-  P->nfy = L.nfy;
-  P->out_order = L.out_order;
-  for (int32_t m = 0; m < L.out_order; ++m) P->out_dims[m] = L.out_dims[m];
-  if (L.bits_fx + L.bits_fy <= 63) {  // packed output key (global mode, global class)
-    add_unpack(P->out_unpack, P->x_f, P->bits_fy);
-    add_unpack(P->out_unpack, P->y_f, 0);
-  }
-  add_unpack(P->ykey_unpack, P->y_c, 0);
-  add_unpack(P->yfree_unpack, P->y_f, 0);
-  P->y_agg = P->bits_c <= kAggBits ? 1 : 0;
-  P->x_agg = (o.mode == SPTC_MODE_GROUPED && P->bits_fx <= kAggBits) ? 1 : 0;
-  P->ux = L.ux;
-  P->uy = L.uy;
-  P->ycells = L.ycells;
-  P->dense = P->bits_fy <= kDenseBits ? 1 : 0;
-  P->xb = L.xb;
-  P->yb = L.yb;
-
-  DeviceInfo* di = nullptr;
-  hipError_t e = hipGetDevice(&P->device);
-  if (e != hipSuccess) {
-    delete P;
-    return hip_fail(e, "hipGetDevice");
-  }
-  if ((st = device_info(P->device, &di)) || (!P->has_alloc && (st = configure_pool(P->device, di)))) {
-    delete P;
-    return st;
-  }
-  P->num_cus = di->num_cus;
-
-  st = plan_body(P, X, Y, cx, cy);
-  if (st != SPTC_OK) {
-    std::string msg = g_last_error;
-    (void)hipStreamSynchronize(P->stream);
-    P->release_all();
-    delete P;
-    g_last_error = msg;
-    return st;
-  }
-  *plan = P;
-  return SPTC_OK;
+  return plan_create(plan, X, Y, ncontract, cx, cy, opt, alloc, stream, nullptr);
 }
 
 sptc_status sptc_plan_info(sptc_plan_t P, sptc_info* info) {
@@ -867,67 +1016,7 @@ sptc_status sptc_execute(sptc_plan_t P, int32_t* out_idx, double* out_val, int64
   if (out_cap < 0) return fail(SPTC_ERR_INVALID_ARG, "out_cap < 0");
   if (out_cap > 0 && !out_val) return fail(SPTC_ERR_INVALID_ARG, "out_val is NULL");
   if (out_cap > 0 && P->out_order > 0 && !out_idx) return fail(SPTC_ERR_INVALID_ARG, "out_idx is NULL");
-  const hipStream_t s = static_cast<hipStream_t>(stream);
-  if (P->opt.mode == SPTC_MODE_GROUPED) {
-    HIP_TRY(launch_reset_status(P->st, s));
-    GroupArgs a{};
-    a.groups = P->groups;
-    a.xr = P->xr;
-    a.eoff = P->eoff;
-    a.yg = P->yg;
-    a.ykey16 = P->ykey16;
-    a.yval = P->yval;
-    a.ny = P->ny;
-    a.ycells = P->ycells;
-    a.seed = P->opt.hash_seed;
-    a.bits_y = P->bits_fy;
-    a.ux = P->ux;
-    a.uy = P->uy;
-    a.gn = P->gn;
-    a.goff = P->goff;
-    a.out_idx = out_idx;
-    a.out_val = out_val;
-    a.out_cap = out_cap;
-    a.st = P->st;
-    HIP_TRY(mark(P, s, SPTC_STAGE_GROUP_COUNT, 0));
-    HIP_TRY(launch_group_wave(a, P->wlist, P->nw, 0, P->num_cus, s));
-    HIP_TRY(mark(P, s, SPTC_STAGE_GROUP_COUNT, 1));
-    HIP_TRY(mark(P, s, SPTC_STAGE_GROUP_FILL, 0));
-    HIP_TRY(launch_scan_group_counts(P->gn, P->wlist, P->nw, (uint64_t)P->direct_products, P->goff, P->etile_sums,
-                                     P->st, s));
-    HIP_TRY(launch_group_wave(a, P->wlist, P->nw, 1, P->num_cus, s));
-    HIP_TRY(mark(P, s, SPTC_STAGE_GROUP_FILL, 1));
-    HIP_TRY(mark(P, s, SPTC_STAGE_DIRECT, 0));
-    HIP_TRY(launch_group_direct(a, P->dlist, P->dpos, P->nd, (uint64_t)P->direct_products, P->num_cus, s));
-    HIP_TRY(mark(P, s, SPTC_STAGE_DIRECT, 1));
-    HIP_TRY(mark(P, s, SPTC_STAGE_BLOCK, 0));
-    HIP_TRY(launch_group_block(a, P->blist, P->nb, P->dense, P->num_cus, s));
-    HIP_TRY(mark(P, s, SPTC_STAGE_BLOCK, 1));
-    if (P->ngl == 0) {
-      HIP_TRY(mark(P, s, SPTC_STAGE_COMPACT, 0));
-      HIP_TRY(launch_finalize(out_nnz, out_cap, P->st, s));
-      HIP_TRY(mark(P, s, SPTC_STAGE_COMPACT, 1));
-      return SPTC_OK;
-    }
-  }
-  const bool grouped = P->opt.mode == SPTC_MODE_GROUPED;
-  const uint64_t zmask = (uint64_t)P->ztab_slots - 1;
-  HIP_TRY(mark(P, s, SPTC_STAGE_OUT_CLEAR, 0));
-  HIP_TRY(launch_fill_empty(P->ztab, P->ztab_slots, grouped ? nullptr : P->st, s));
-  HIP_TRY(mark(P, s, SPTC_STAGE_OUT_CLEAR, 1));
-  HIP_TRY(mark(P, s, SPTC_STAGE_EXPAND, 0));
-  HIP_TRY(launch_expand_acc(P->poff, P->expand_nx, P->xrec, P->xg, P->yg, P->ny, P->bits_fy, P->ztab, zmask,
-                            P->opt.hash_seed, P->max_probe_z, (uint64_t)P->expand_products, P->st, P->num_cus, s));
-  HIP_TRY(mark(P, s, SPTC_STAGE_EXPAND, 1));
-  HIP_TRY(mark(P, s, SPTC_STAGE_COMPACT, 0));
-  if (grouped)
-    HIP_TRY(launch_compact_grouped(P->ztab, P->ztab_slots, P->groups, P->glist, P->ux, P->uy, P->bits_fy, out_idx,
-                                   out_val, out_cap, out_nnz, &P->st->out_base, P->ztile_sums, P->st, s));
-  else
-    HIP_TRY(launch_compact(P->ztab, P->ztab_slots, P->out_unpack, out_idx, out_val, out_cap, out_nnz, nullptr,
-                           P->ztile_sums, P->st, s));
-  HIP_TRY(mark(P, s, SPTC_STAGE_COMPACT, 1));
-  return SPTC_OK;
+  return execute_plan(P, out_idx, out_val, out_cap, out_nnz, static_cast<hipStream_t>(stream), nullptr);
 }
 
 sptc_status sptc_plan_set_stage_events(sptc_plan_t P, void** events) {
@@ -976,10 +1065,10 @@ sptc_status sptc_plan_y_groups(sptc_plan_t P, int32_t* key_coords, int64_t* coun
   if (cap > 0 && (!counts || !starts || (P->nc > 0 && !key_coords)))
     return fail(SPTC_ERR_INVALID_ARG, "output pointer is NULL");
   const hipStream_t s = static_cast<hipStream_t>(stream);
-  HIP_TRY(launch_y_groups(P->ytab, P->ytab_slots, P->ykey_unpack, key_coords, counts, starts, cap, P->scratch,
+  HIP_TRY(launch_y_groups(P->ytab, P->ytab_slots, P->ykey_unpack, key_coords, counts, starts, cap, P->readback,
                           P->tile_sums, P->st, s));
   int64_t n = 0;
-  HIP_TRY(hipMemcpyAsync(&n, P->scratch, sizeof n, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(&n, P->readback, sizeof n, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   if (n != P->y_groups) return fail(SPTC_ERR_INTERNAL, "group count %lld != %lld", (long long)n,
                                     (long long)P->y_groups);
@@ -1065,12 +1154,10 @@ sptc_status sptc_batch_plan(sptc_batch_t* batch, int32_t count, const sptc_coo* 
   return SPTC_OK;
 }
 
-sptc_status sptc_batch_sizes(sptc_batch_t B, int64_t* idx_elems, int64_t* val_elems, int64_t* scratch_bytes,
-                             int64_t* workspace_bytes) {
+sptc_status sptc_batch_sizes(sptc_batch_t B, int64_t* idx_elems, int64_t* val_elems, int64_t* workspace_bytes) {
   if (!B) return fail(SPTC_ERR_INVALID_ARG, "batch is NULL");
   if (idx_elems) *idx_elems = B->idx_elems;
   if (val_elems) *val_elems = B->val_elems;
-  if (scratch_bytes) *scratch_bytes = B->scratch_bytes;
   if (workspace_bytes) *workspace_bytes = B->workspace + (B->inner ? B->inner->workspace : 0);
   return SPTC_OK;
 }
@@ -1094,28 +1181,13 @@ sptc_status sptc_batch_info(sptc_batch_t B, int32_t b, sptc_info* info, int64_t*
   return SPTC_OK;
 }
 
-sptc_status sptc_batch_execute(sptc_batch_t B, int32_t* out_idx, double* out_val, int64_t* out_nnz, void* scratch,
-                               void* stream) {
+sptc_status sptc_batch_execute(sptc_batch_t B, int32_t* out_idx, double* out_val, int64_t* out_nnz, void* stream) {
   if (!B) return fail(SPTC_ERR_INVALID_ARG, "batch is NULL");
   if (!out_nnz) return fail(SPTC_ERR_INVALID_ARG, "out_nnz is NULL");
   if (B->val_elems > 0 && !out_val) return fail(SPTC_ERR_INVALID_ARG, "out_val is NULL");
   if (B->idx_elems > 0 && !out_idx) return fail(SPTC_ERR_INVALID_ARG, "out_idx is NULL");
-  if (B->scratch_bytes > 0 && !scratch) return fail(SPTC_ERR_INVALID_ARG, "scratch is NULL");
-  if (reinterpret_cast<uintptr_t>(scratch) % 256) return fail(SPTC_ERR_INVALID_ARG, "scratch is not 256-byte aligned");
-  const hipStream_t s = static_cast<hipStream_t>(stream);
-  // packed outputs: values first (8-byte aligned), then 4 index rows
-  double* tval = static_cast<double*>(scratch);
-  int32_t* tidx = reinterpret_cast<int32_t*>(tval + B->tcap);
-  sptc_status st;
-  if ((st = sptc_execute(B->inner, tidx, tval, B->tcap, B->tnnz, stream))) return st;
-  void* const* ev = B->inner->opt.stage_events;
-  HIP_TRY(mark_events(ev, s, SPTC_STAGE_BATCH_UNPACK, 0));
-  HIP_TRY(launch_zero_u64(B->cursor, B->count, s));
-  HIP_TRY(launch_batch_unpack(tidx, tval, B->tcap, B->tnnz, B->w, B->count, B->outs, out_idx, out_val, B->cursor,
-                              s));
-  HIP_TRY(launch_batch_finalize(B->tnnz, B->cursor, B->outs, B->count, out_nnz, s));
-  HIP_TRY(mark_events(ev, s, SPTC_STAGE_BATCH_UNPACK, 1));
-  return SPTC_OK;
+  const BatchExec bx{B->outs, B->seg, B->w.wx, B->count, out_nnz};
+  return execute_plan(B->inner, out_idx, out_val, 0, B->tnnz, static_cast<hipStream_t>(stream), &bx);
 }
 
 void sptc_batch_free(sptc_batch_t B) {

@@ -8,6 +8,9 @@
 namespace sptc {
 
 constexpr uint64_t kEmpty = ~0ull;  // key of an unused hash slot; real keys use <= 63 bits
+struct BatchOut;
+struct BatchSeg;
+
 constexpr int kMaxOrder = 16;
 constexpr int kMaxOutOrder = 32;
 
@@ -39,6 +42,23 @@ struct Bounds {
   int32_t order;
   uint32_t dim[kMaxOrder];  // mode lengths (<= 2^31)
   int32_t check;            // nonzero: validate
+};
+
+// Geometry of an open-addressing key table.  A single contraction's table
+// is one power-of-two array (hashed, or directly addressed when `ident`).
+// A batch's table is cut into one region per contraction: a key's region is
+// reg[key >> pshift], and probing wraps inside the region.
+struct Region {
+  unsigned long long base;  // first slot
+  uint32_t mask;            // slots - 1 (a power of two)
+  int32_t ident;            // directly addressed by the key's low bits
+};
+
+struct TabGeom {
+  uint64_t mask;      // whole table (reg == nullptr)
+  const Region* reg;  // regions, or nullptr
+  int32_t pshift;     // key >> pshift selects the region
+  int32_t ident;      // whole table directly addressed (reg == nullptr)
 };
 
 // Decodes an output key into out_order coordinates.
@@ -119,7 +139,7 @@ hipError_t launch_fill_empty(void* slots16, int64_t nslots, DevStatus* st, hipSt
 
 // Counts entries per packed key (the modes in kc) in an open-addressing table;
 // *distinct is incremented once per new key.
-hipError_t launch_key_count(const int32_t* idx, int64_t nnz, KeyPack kc, YSlot* tab, uint64_t mask, uint64_t seed,
+hipError_t launch_key_count(const int32_t* idx, int64_t nnz, KeyPack kc, YSlot* tab, TabGeom g, uint64_t seed,
                             int32_t max_probe, DevStatus* st, unsigned long long* distinct, int num_cus,
                             hipStream_t stream);
 
@@ -141,7 +161,7 @@ hipError_t launch_scan_y_table(YSlot* tab, int64_t nslots, unsigned long long* t
 // key) into yset (kEmpty-filled, yset_mask + 1 slots) when yset is given, and
 // sets st->ydup on a repeat.
 hipError_t launch_y_scatter(const int32_t* yidx, const double* yval, int64_t nnz, KeyPack kc, KeyPack kf,
-                            Bounds b, YSlot* tab, uint64_t mask, uint64_t seed, int32_t max_probe, YEntry* yg,
+                            Bounds b, YSlot* tab, TabGeom g, uint64_t seed, int32_t max_probe, YEntry* yg,
                             unsigned long long* yset, uint64_t yset_mask, int32_t bits_y, DevStatus* st, int num_cus,
                             hipStream_t stream);
 
@@ -156,7 +176,7 @@ hipError_t launch_y_scatter_agg(const int32_t* yidx, const double* yval, int64_t
 hipError_t launch_fill_keys(unsigned long long* keys, int64_t n, hipStream_t stream);
 
 hipError_t launch_x_probe(const int32_t* xidx, const double* xval, int64_t nnz, KeyPack kc, KeyPack kf, Bounds b,
-                          const YSlot* tab, uint64_t mask, uint64_t seed, int32_t max_probe, XEntry* xrec,
+                          const YSlot* tab, TabGeom g, uint64_t seed, int32_t max_probe, XEntry* xrec,
                           uint32_t* xg, uint32_t* xcnt, DevStatus* st, int num_cus, hipStream_t stream);
 
 // poff[i] = sum of xcnt[0..i), poff[n] = total, and the total also into *total.
@@ -180,7 +200,8 @@ hipError_t launch_compact(const ZSlot* tab, int64_t nslots, KeyUnpack ku, int32_
 hipError_t launch_compact_grouped(const ZSlot* tab, int64_t nslots, const GroupRec* groups, const uint32_t* glist,
                                   KeyUnpack ux, KeyUnpack uy, int32_t bits_y, int32_t* out_idx, double* out_val,
                                   int64_t out_cap, int64_t* out_nnz, const unsigned long long* base,
-                                  unsigned long long* tile_sums, DevStatus* st, hipStream_t stream);
+                                  unsigned long long* tile_sums, DevStatus* st, const BatchOut* bout, BatchSeg* bseg,
+                                  int32_t bwx, hipStream_t stream);
 
 // ---- grouped path (grouped.hip) ----
 
@@ -192,12 +213,12 @@ hipError_t launch_scan_x_table(YSlot* tab, int64_t nslots, GroupRec* groups, voi
 // X scatter for a direct-addressed X table of nslots <= 2^kAggBits slots,
 // aggregated per workgroup in LDS like the Y scatter.
 hipError_t launch_x_scatter_agg(const int32_t* xidx, const double* xval, int64_t nnz, KeyPack kf, KeyPack kc,
-                                Bounds b, YSlot* xtab, unsigned nslots, const YSlot* ytab, uint64_t ymask,
+                                Bounds b, YSlot* xtab, unsigned nslots, const YSlot* ytab, TabGeom yg,
                                 int32_t max_probe_y, uint64_t seed, XRec* xr, DevStatus* st, hipStream_t stream);
 
 // Scatter X into its groups, probing Y's table for every entry.
 hipError_t launch_x_scatter(const int32_t* xidx, const double* xval, int64_t nnz, KeyPack kf, KeyPack kc, Bounds b,
-                            YSlot* xtab, uint64_t xmask, int32_t max_probe_x, const YSlot* ytab, uint64_t ymask,
+                            YSlot* xtab, TabGeom xg, int32_t max_probe_x, const YSlot* ytab, TabGeom yg,
                             int32_t max_probe_y, uint64_t seed, XRec* xr, DevStatus* st, int num_cus,
                             hipStream_t stream);
 
@@ -248,6 +269,11 @@ struct GroupArgs {
   double* out_val;
   int64_t out_cap;
   DevStatus* st;
+  // Batch (bout != NULL): outputs go to each contraction's own COO region;
+  // X free key >> bwx is the contraction.
+  const BatchOut* bout;
+  BatchSeg* bseg;
+  int32_t bwx;
 };
 hipError_t launch_group_wave(const GroupArgs& a, const uint32_t* wlist, int64_t nw, int fill, int num_cus,
                              hipStream_t stream);
@@ -320,6 +346,20 @@ struct BatchOut {
   int64_t idx_off, val_off, cap;
 };
 
+// Contraction b's output positions.  The grouped pipeline numbers direct
+// outputs, then wave outputs, across the whole batch; with the batch's key
+// tables cut into per-contraction regions, b's groups and so its direct and
+// wave outputs are contiguous in that numbering.  b's COO takes its direct
+// outputs first, its wave outputs next, then block and global class outputs
+// from `cursor`, which ends as b's nnz.
+struct BatchSeg {
+  unsigned long long dshift;  // numbering of b's first direct output
+  unsigned long long dcount;  // b's direct outputs
+  unsigned long long wshift;  // numbering of b's first wave output, minus dcount
+  unsigned long long cursor;
+  uint32_t wlo, whi;          // b's wave groups: wlist[wlo, whi)
+};
+
 // Packed key widths: a key of w bits is stored as (key >> lo, key & (2^lo - 1)).
 struct BatchWidths {
   int32_t wc, wx;        // contracting / X free key widths before the index prefix
@@ -338,13 +378,20 @@ hipError_t launch_batch_products(const GroupRec* groups, int64_t ngroups, const 
 // Zeroes n 8-byte words.
 hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t stream);
 
-// Sorts the packed outputs (4 index rows: X free key hi/lo, Y free key
-// hi/lo) into the contractions' outputs; cursor[b] ends as b's nnz.
-hipError_t launch_batch_unpack(const int32_t* tidx, const double* tval, int64_t tcap, const int64_t* tnnz,
-                               BatchWidths w, int32_t count, const BatchOut* outs, int32_t* out_idx, double* out_val,
-                               unsigned long long* cursor, hipStream_t stream);
+// Plan time: each contraction's direct outputs and wave groups, from the
+// contraction-ordered direct and wave lists.
+hipError_t launch_batch_segments(const GroupRec* groups, const uint32_t* dlist, int64_t nd,
+                                 const unsigned long long* dpos, const uint32_t* wlist, int64_t nw, int32_t wx,
+                                 int32_t count, BatchSeg* seg, hipStream_t stream);
 
-hipError_t launch_batch_finalize(const int64_t* tnnz, const unsigned long long* cursor, const BatchOut* outs,
-                                 int32_t count, int64_t* out_nnz, hipStream_t stream);
+// Execute time, after the wave outputs are counted and numbered: each
+// contraction's wave shift and the start of its block/global outputs.
+hipError_t launch_batch_bases(const uint32_t* wlist, const uint32_t* gn, const unsigned long long* goff, int32_t count,
+                              BatchSeg* seg, hipStream_t stream);
+
+// out_nnz[b] = b's nnz, or the negated status when the pipeline or b's
+// region reported an error.
+hipError_t launch_batch_finalize(const DevStatus* st, const BatchSeg* seg, const BatchOut* outs, int32_t count,
+                                 int64_t* out_nnz, hipStream_t stream);
 
 }  // namespace sptc

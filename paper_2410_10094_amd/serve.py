@@ -6,7 +6,7 @@ fewer than ``max_inflight`` batches are on the device, the loop takes the
 queued requests of the head request's shape class (sched.shape_class), up to
 ``batch_products`` expected products, and plans them as one batch on the
 plan stream: this is pass 1, which counts every member's products and so
-fixes the output and scratch bytes its execution needs.  The batch is
+fixes the output bytes its execution needs.  The batch is
 admitted to the execute stream once its workspace plus those bytes fit in
 what the budget has left; until then it waits, and the loop keeps retiring
 finished batches.  Planning the next batch overlaps on the device with the
@@ -53,7 +53,7 @@ class Request:
 class _Batch:
     members: List[Request]
     handle: Any
-    need: int          # workspace + outputs + scratch bytes
+    need: int          # workspace + output bytes
     token: Any = None
 
 
@@ -91,9 +91,9 @@ class RingArena:
 
 class TorchBackend:
     """Runs batches with sptc_batch_* on one GPU: a plan stream and an
-    execute stream (both at the default priority).  Outputs and execute
-    scratch come from one preallocated ring arena; the batches' own
-    workspace from the library's stream-ordered pool."""
+    execute stream (both at the default priority).  Outputs come from one
+    preallocated ring arena; the batches' own workspace from the library's
+    stream-ordered pool."""
 
     def __init__(self, arena_bytes: int, keep_results: bool = False, options=None):
         import torch
@@ -133,8 +133,7 @@ class TorchBackend:
         torch = self.torch
         a = RingArena.ALIGN
         rnd = lambda n: (n + a - 1) // a * a
-        parts = [rnd(4 * max(b.idx_elems, 1)), rnd(8 * max(b.val_elems, 1)), rnd(8 * b.count),
-                 rnd(max(b.scratch_bytes, 1))]
+        parts = [rnd(4 * max(b.idx_elems, 1)), rnd(8 * max(b.val_elems, 1)), rnd(8 * b.count)]
         start = self.arena.alloc(sum(parts))
         if start is None:
             return None
@@ -144,11 +143,10 @@ class TorchBackend:
         idx = self.buf[offs[0]:offs[0] + 4 * max(b.idx_elems, 1)].view(torch.int32)
         val = self.buf[offs[1]:offs[1] + 8 * max(b.val_elems, 1)].view(torch.float64)
         nnz = self.buf[offs[2]:offs[2] + 8 * b.count].view(torch.int64)
-        scratch = self.buf[offs[3]:offs[3] + max(b.scratch_bytes, 1)]
-        b.execute_into(idx, val, nnz, scratch, stream=self.exec_stream)
+        b.execute_into(idx, val, nnz, stream=self.exec_stream)
         ev = torch.cuda.Event(enable_timing=True)
         ev.record(self.exec_stream)
-        return ((idx, val, nnz, scratch), ev, start)
+        return ((idx, val, nnz), ev, start)
 
     def done(self, token) -> bool:
         return token[1].query()
@@ -160,7 +158,7 @@ class TorchBackend:
         """Kept results are copied out of the arena, which is reused."""
         if not self.keep_results:
             return
-        idx, val, nnz, _ = token[0]
+        idx, val, nnz = token[0]
         for r, (i, v) in zip(members, b.views(idx, val, nnz.cpu().tolist())):
             r.result = (i.clone(), v.clone())
 

@@ -189,8 +189,8 @@ def test_batch_plan_validation(case, status):
 
 def test_batch_functions_reject_null():
     lib = B.load()
-    assert lib.sptc_batch_execute(None, None, None, None, None, None) == B.ERR_INVALID_ARG
-    assert lib.sptc_batch_sizes(None, None, None, None, None) == B.ERR_INVALID_ARG
+    assert lib.sptc_batch_execute(None, None, None, None, None) == B.ERR_INVALID_ARG
+    assert lib.sptc_batch_sizes(None, None, None, None) == B.ERR_INVALID_ARG
     assert lib.sptc_batch_info(None, 0, None, None, None) == B.ERR_INVALID_ARG
     lib.sptc_batch_free(None)
     assert lib.sptc_batch_plan(None, 1, None, None, None, None, None, None, None, None) == B.ERR_INVALID_ARG

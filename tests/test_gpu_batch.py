@@ -124,16 +124,16 @@ def test_batch_execute_is_graph_capturable():
         refs = [oracle.contract(p.X, p.Y, p.cx, p.cy) for p in ps]
         for p, r, (i, v) in zip(ps, refs, bt.execute()):
             assert_parity(p, i.cpu().numpy(), v.cpu().numpy(), ref=r)
-        idx, val, nnz, scratch = bt.allocate_outputs()
+        idx, val, nnz = bt.allocate_outputs()
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s):
-            bt.execute_into(idx, val, nnz, scratch, stream=s)  # warm-up outside capture
+            bt.execute_into(idx, val, nnz, stream=s)  # warm-up outside capture
         torch.cuda.current_stream().wait_stream(s)
         torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g, stream=s):
-            bt.execute_into(idx, val, nnz, scratch, stream=s)
+            bt.execute_into(idx, val, nnz, stream=s)
         for rep in range(3):
             idx.fill_(-1)
             val.fill_(float("nan"))

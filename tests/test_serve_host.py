@@ -17,7 +17,7 @@ class _T:
 class FakeBackend:
     """Batches run one after another; a batch of P products takes
     P * sec_per_product + overhead seconds.  Each request carries
-    `need_bytes` (outputs + scratch after pass 1)."""
+    `need_bytes` (output bytes after pass 1)."""
 
     def __init__(self, sec_per_product=1e-9, overhead=2e-4):
         self.spp = sec_per_product
