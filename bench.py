@@ -181,7 +181,7 @@ def run_workload(name, steps, warmup, with_events=True, mode="grouped"):
     stage_ms = {}
     for s, sname in enumerate(B.STAGES):
         stage_ms[sname] = sum(evs[k][2 * s].elapsed_time(evs[k][2 * s + 1]) for k in range(steps)) / steps
-    return dict(problem=p, products=products, nnz_z=nnz_z, sec=sec, stage_ms=stage_ms, info=info, mode=mode)
+    return dict(problem=p, products=products, nnz_z=nnz_z, sec=sec, stage_ms=stage_ms, info=info, mode=mode, name=name)
 
 
 def generate_draws(count, seed, workers):
@@ -350,6 +350,44 @@ def run_batched(draws, dev, steps, warmup, budget):
     return res
 
 
+# HBM traffic of a dominant kernel, from two committed rocprofv3 --pmc runs
+# (FETCH_SIZE, then WRITE_SIZE), keyed by (workload, stage).  A figure only
+# holds while the kernel's sources are the ones profiled.
+TRAFFIC_PROFILES = {("block-sparse-1.5M", "block"): "block_dense_block-sparse-1.5M_hbm_counters.md"}
+KERNEL_SOURCES = ("paper_2410_10094_amd/csrc/grouped.hip", "paper_2410_10094_amd/csrc/prim.hpp",
+                  "paper_2410_10094_amd/csrc/sptc_internal.hpp")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, stage):
+    """Bytes per launch from the committed counter summary, or None when
+    there is none or the kernel changed since it was taken."""
+    name = TRAFFIC_PROFILES.get((workload, stage))
+    path = os.path.join(ROOT, "profiles", name) if name else None
+    if not path or not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                fields[k.strip()] = v.strip().strip("`")
+    if fields.get("source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return int(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def roofline_of(r):
     p = r["problem"]
     stage = max(r["stage_ms"], key=lambda s: r["stage_ms"][s])
@@ -357,8 +395,8 @@ def roofline_of(r):
     bytes_alg = algorithmic_bytes(stage, p, r["products"], r["nnz_z"], r["info"]["x_groups"], r["mode"], r["info"])
     achieved = bytes_alg / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
     return {"kernel": stage, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "ms_per_launch": round(ms, 4),
-            "algorithmic_bytes_per_launch": bytes_alg}
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(r["name"], stage),
+            "ms_per_launch": round(ms, 4), "algorithmic_bytes_per_launch": bytes_alg}
 
 
 def summary(name, r):

@@ -120,8 +120,9 @@ typedef enum sptc_stage {
   SPTC_STAGE_DIRECT = 10,     /* grouped path, single-entry groups: write every product as an output */
   SPTC_STAGE_BLOCK = 11,      /* grouped path, large groups: accumulate in LDS, reserve and write */
   SPTC_STAGE_BATCH_PACK = 12,   /* batch plan: key every contraction's entries with its index */
-  SPTC_STAGE_BATCH_UNPACK = 13, /* batch execute: place packed outputs in each contraction's COO */
-  SPTC_NUM_STAGES = 14
+  SPTC_STAGE_BATCH_SEGMENTS = 13, /* batch plan: products and output segments per contraction */
+  SPTC_STAGE_X_SORT = 14,       /* grouped plan: dense block groups' X entries sorted by Y run */
+  SPTC_NUM_STAGES = 15
 } sptc_stage;
 
 /* Accumulation strategy.

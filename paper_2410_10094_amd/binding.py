@@ -29,7 +29,7 @@ BATCH_MAX = 4096
 MODE_GROUPED, MODE_GLOBAL = 0, 1
 
 STAGES = ("y_count", "y_scan", "y_scatter", "x_probe", "p_scan", "out_clear", "expand", "compact", "group_count",
-          "group_fill", "direct", "block", "batch_pack", "batch_unpack")
+          "group_fill", "direct", "block", "batch_pack", "batch_segments", "x_sort")
 
 
 class Coo(ctypes.Structure):

@@ -195,6 +195,7 @@ struct sptc_plan_s : Workspace {
   uint32_t* wlist = nullptr;
   uint32_t* blist = nullptr;
   uint32_t* glist = nullptr;
+  uint32_t* bneff = nullptr;  // dense block class: entries with a Y match, per listed group (sorted first)
   unsigned long long* dpos = nullptr;
   uint16_t* ykey16 = nullptr;  // dense Y free keys: compact copy of grouped Y
   double* yval = nullptr;
@@ -476,7 +477,15 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
   P->direct_products = (int64_t)host.direct_products;
   P->ydup = host.ydup ? 1 : 0;
   if (P->ngl < 0) return fail(SPTC_ERR_INTERNAL, "group classes do not add up");
-  if (P->nb > 0) HIP_TRY(prepare_group_block());
+  if (P->nb > 0) {
+    HIP_TRY(prepare_group_block());
+    if (P->dense) {
+      if ((st = P->allocate_n(P->nb, &P->bneff))) return st;
+      HIP_TRY(mark(P, s, SPTC_STAGE_X_SORT, 0));
+      HIP_TRY(launch_sort_block_entries(P->groups, P->blist, P->nb, P->xr, P->bneff, P->num_cus, s));
+      HIP_TRY(mark(P, s, SPTC_STAGE_X_SORT, 1));
+    }
+  }
   if ((st = P->allocate_n(P->x_groups, &P->gn))) return st;
   if ((st = P->allocate_n(P->x_groups, &P->goff))) return st;
   if ((st = P->allocate_n(scan_tiles(P->nw) + 1, &P->etile_sums))) return st;
@@ -759,7 +768,7 @@ sptc_status execute_plan(sptc_plan_s* P, int32_t* out_idx, double* out_val, int6
     HIP_TRY(launch_group_direct(a, P->dlist, P->dpos, P->nd, (uint64_t)P->direct_products, P->num_cus, s));
     HIP_TRY(mark(P, s, SPTC_STAGE_DIRECT, 1));
     HIP_TRY(mark(P, s, SPTC_STAGE_BLOCK, 0));
-    HIP_TRY(launch_group_block(a, P->blist, P->nb, P->dense, P->num_cus, s));
+    HIP_TRY(launch_group_block(a, P->blist, P->nb, P->dense, P->bneff, P->num_cus, s));
     HIP_TRY(mark(P, s, SPTC_STAGE_BLOCK, 1));
     if (P->ngl == 0) {
       HIP_TRY(mark(P, s, SPTC_STAGE_COMPACT, 0));
@@ -930,6 +939,7 @@ sptc_status batch_body(sptc_batch_s* B, const sptc_coo* X, const sptc_coo* Y, co
   // Products per contraction, from the packed plan's X groups.
   unsigned long long* pb = nullptr;
   if ((st = pk.allocate_n(count, &pb))) return st;
+  HIP_TRY(mark_events(o.stage_events, s, SPTC_STAGE_BATCH_SEGMENTS, 0));
   HIP_TRY(launch_zero_u64(pb, count, s));
   HIP_TRY(launch_batch_products(inner->groups, inner->x_groups, inner->eoff, wx, count, pb, s));
   std::vector<unsigned long long> hpb(count);
@@ -961,6 +971,7 @@ sptc_status batch_body(sptc_batch_s* B, const sptc_coo* X, const sptc_coo* Y, co
   HIP_TRY(hipMemcpyAsync(B->outs, outs.data(), sizeof(BatchOut) * count, hipMemcpyHostToDevice, s));
   HIP_TRY(launch_batch_segments(inner->groups, inner->dlist, inner->nd, inner->dpos, inner->wlist, inner->nw, wx, count,
                                 B->seg, s));
+  HIP_TRY(mark_events(o.stage_events, s, SPTC_STAGE_BATCH_SEGMENTS, 1));
   HIP_TRY(hipStreamSynchronize(s));  // host arrays above are copied before they go out of scope
   return SPTC_OK;
 }

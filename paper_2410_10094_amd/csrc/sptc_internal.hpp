@@ -283,8 +283,14 @@ hipError_t launch_group_wave(const GroupArgs& a, const uint32_t* wlist, int64_t 
 // Raises the block-class kernels' dynamic LDS limit on the current device;
 // called once per plan so that execute issues kernel launches only.
 hipError_t prepare_group_block();
-hipError_t launch_group_block(const GroupArgs& a, const uint32_t* blist, int64_t nb, int dense, int num_cus,
-                              hipStream_t stream);
+// Dense block class: neff[i] is filled by launch_sort_block_entries.
+hipError_t launch_group_block(const GroupArgs& a, const uint32_t* blist, int64_t nb, int dense, const uint32_t* neff,
+                              int num_cus, hipStream_t stream);
+
+// Plan time, dense block class: sorts each listed group's X entries by Y run
+// (groups of at most 4096 entries) and counts those with a Y match into neff.
+hipError_t launch_sort_block_entries(const GroupRec* groups, const uint32_t* blist, int64_t nb, XRec* xr,
+                                     uint32_t* neff, int num_cus, hipStream_t stream);
 
 // Direct class: single-entry groups against a Y without repeated coordinates
 // have one output per product; writes output q for product q in [0, nprod).

@@ -350,3 +350,58 @@ def test_out_of_range_coordinate_is_rejected():
     with pytest.raises(sptc.SptcError) as e:
         sptc.plan(X, Y, p.cx, p.cy)
     assert e.value.status == 1
+
+
+def _co_problems():
+    """Dense block-class groups in numbers that make a workgroup accumulate
+    several groups at once (co-accumulation), with entries spread over
+    several merge windows, explicit zero values, repeated X coordinates, and
+    a group too large to be sorted at plan time (its set falls back)."""
+    rng = np.random.default_rng(71)
+    out = []
+
+    def y_dense(C, per):
+        ny = C * per
+        yi = np.stack([np.repeat(np.arange(C), per), rng.integers(0, 64, ny), rng.integers(0, 64, ny)])
+        return Coo((C, 64, 64), yi.astype(np.int32), W.nonzero_uniform(rng, ny))
+
+    # ~2000 groups (four per workgroup), most with ~20 entries, every 50th with ~700
+    C = 1024
+    cols = []
+    for g in range(2000):
+        n = 700 if g % 50 == 0 else int(rng.integers(8, 32))
+        ks = rng.choice(C, n, replace=False)
+        cols.append(np.stack([np.full(n, g // 40), np.full(n, g % 40), ks]))
+    xi = np.concatenate(cols, axis=1).astype(np.int32)
+    xv = W.nonzero_uniform(rng, xi.shape[1])
+    xv[::97] = 0.0  # zero products still make outputs
+    dup = xi[:, :300:7]  # repeated X coordinates (additive)
+    xi = np.concatenate([xi, dup], axis=1)
+    xv = np.concatenate([xv, W.nonzero_uniform(rng, dup.shape[1])])
+    out.append(Problem("co-2000-groups", Coo((50, 40, C), xi, xv), y_dense(C, 30), (2,), (0,)))
+    # ~300 groups (two per workgroup)
+    cols = []
+    for g in range(300):
+        n = int(rng.integers(40, 400))
+        cols.append(np.stack([np.full(n, g // 20), np.full(n, g % 20), rng.choice(C, n, replace=False)]))
+    xi = np.concatenate(cols, axis=1).astype(np.int32)
+    out.append(Problem("co-300-groups", Coo((15, 20, C), xi, W.nonzero_uniform(rng, xi.shape[1])),
+                       y_dense(C, 20), (2,), (0,)))
+    # a group of 5000 entries among 2000 small ones: its set is walked per group
+    C2 = 8192
+    cols = [np.stack([np.zeros(5000, int), np.zeros(5000, int), rng.choice(C2, 5000, replace=False)])]
+    for g in range(1, 2000):
+        n = int(rng.integers(10, 20))
+        cols.append(np.stack([np.full(n, g // 40), np.full(n, g % 40), rng.choice(C2, n, replace=False)]))
+    xi = np.concatenate(cols, axis=1).astype(np.int32)
+    out.append(Problem("co-fallback", Coo((50, 40, C2), xi, W.nonzero_uniform(rng, xi.shape[1])),
+                       y_dense(C2, 40), (2,), (0,)))
+    return out
+
+
+@pytest.mark.parametrize("p", _co_problems(), ids=lambda p: p.name)
+def test_dense_block_co_accumulation(p):
+    log(f"[co] {p.name} nnz {p.X.nnz}x{p.Y.nnz}")
+    info, gidx, gval = run_gpu(p)
+    assert info["classes"]["block"] > 100, info["classes"]
+    assert_parity(p, gidx, gval)
