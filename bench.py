@@ -201,12 +201,16 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if xs else None
 
 
+def klass(p):
+    from paper_2410_10094_amd import sched
+    return sched.shape_class(p.Y.dims, p.cy)
+
+
 def sub_batches(draws, budget):
     """Batches of draws: bucketed by Y free key class, cut at `budget`
     expected products."""
     from paper_2410_10094_amd import sched
-    from paper_2410_10094_amd import workloads as W
-    return sched.make_batches(draws, W.expected_products, lambda p: sched.shape_class(p.Y.dims, p.cy), budget)
+    return sched.make_batches(draws, sched.estimate_products, klass, budget)
 
 
 def upload(draws):
@@ -218,22 +222,22 @@ def upload(draws):
     return dev
 
 
-def run_served(draws, dev, seconds, rate, budget_bytes, batch_products, max_batch, seed):
+def run_served(draws, dev, seconds, rate, budget_bytes, batch_products, max_batch, seed, load_factor=1 / 1.3):
     """Poisson arrivals at `rate` per second for `seconds`; each request is a
     draw picked uniformly from the pool (inputs resident in HBM).  Served
     with continuous batching under the memory budget."""
     import numpy as np
 
     from paper_2410_10094_amd import sched, serve
-    from paper_2410_10094_amd import workloads as W
     arrivals = serve.poisson_arrivals(rate, seconds, seed)
     picks = np.random.default_rng(seed + 1).integers(0, len(draws), size=len(arrivals))
     reqs = [serve.Request(i, dev[k][0], dev[k][1], draws[k].cx, draws[k].cy, float(a),
-                          expected_products=W.expected_products(draws[k]),
+                          expected_products=sched.estimate_products(draws[k]),
                           klass=sched.shape_class(draws[k].Y.dims, draws[k].cy))
             for i, (a, k) in enumerate(zip(arrivals, picks))]
-    srv = serve.Server(serve.TorchBackend(arena_bytes=budget_bytes), budget_bytes=budget_bytes,
-                       batch_products=batch_products, max_batch=max_batch)
+    import paper_2410_10094_amd as sptc
+    backend = serve.TorchBackend(arena_bytes=budget_bytes, options=sptc.default_options(load_factor=load_factor))
+    srv = serve.Server(backend, budget_bytes=budget_bytes, batch_products=batch_products, max_batch=max_batch)
     t0 = time.perf_counter()
     done = srv.run(reqs)
     wall = time.perf_counter() - t0
@@ -250,7 +254,18 @@ def run_served(draws, dev, seconds, rate, budget_bytes, batch_products, max_batc
     return out
 
 
-def run_batched(draws, dev, steps, warmup, budget):
+def autotune_batched(draws, dev, sample):
+    """Load factor and batch budget for the batched legs, tuned on the first
+    `sample` draws (outside every timed region)."""
+    from paper_2410_10094_amd import autotune
+    sub = draws[:sample]
+    tuner = autotune.Autotuner()
+    run = autotune.torch_batch_runner(sub, dev[:sample], klass)
+    run(1 / 1.3, 1e9)  # warm the pools before timing candidates
+    return tuner.tune(autotune.signature(sub, klass), run)
+
+
+def run_batched(draws, dev, steps, warmup, budget, load_factor=1 / 1.3):
     """The batched workload two ways, each step covering every draw:
     per-call (sptc_plan + sptc_execute per contraction) and batched
     (sptc_batch_plan + sptc_batch_execute per sub-batch of at most `budget`
@@ -264,8 +279,9 @@ def run_batched(draws, dev, steps, warmup, budget):
 
     # per-call: one output buffer sized for the largest bound
     bounds, orders, products = [], [], []
+    opts = lambda: sptc.default_options(load_factor=load_factor)
     for (X, Y), p in zip(dev, draws):
-        with sptc.plan(X, Y, p.cx, p.cy) as pl:
+        with sptc.plan(X, Y, p.cx, p.cy, options=opts()) as pl:
             bounds.append(pl.out_nnz_bound)
             orders.append(pl.out_order)
             products.append(pl.products)
@@ -278,7 +294,7 @@ def run_batched(draws, dev, steps, warmup, budget):
     def per_call(lat):
         for i, ((X, Y), p) in enumerate(zip(dev, draws)):
             t0 = time.perf_counter()
-            pl = sptc.plan(X, Y, p.cx, p.cy)
+            pl = sptc.plan(X, Y, p.cx, p.cy, options=opts())
             k = pl.out_order
             pl.execute_into(oidx[: max(k, 1) * max(cap, 1)].view(max(k, 1), max(cap, 1)), oval, cap, onnz[i:i + 1])
             torch.cuda.synchronize()
@@ -288,7 +304,7 @@ def run_batched(draws, dev, steps, warmup, budget):
     # batched: buffers sized for the largest sub-batch
     need_i = need_v = 0
     for g in groups:
-        with sptc.batch([(dev[i][0], dev[i][1], draws[i].cx, draws[i].cy) for i in g]) as bt:
+        with sptc.batch([(dev[i][0], dev[i][1], draws[i].cx, draws[i].cy) for i in g], options=opts()) as bt:
             need_i, need_v = max(need_i, bt.idx_elems), max(need_v, bt.val_elems)
     bidx = torch.empty(max(need_i, 1), dtype=torch.int32, device="cuda")
     bval = torch.empty(max(need_v, 1), dtype=torch.float64, device="cuda")
@@ -306,7 +322,7 @@ def run_batched(draws, dev, steps, warmup, budget):
 
     def batched(lat, timed=False):
         for k, g in enumerate(groups):
-            opt = sptc.default_options()
+            opt = opts()
             if timed:
                 opt.stage_events = ctypes.cast(ev_arrays[k], ctypes.POINTER(ctypes.c_void_p))
             t0 = time.perf_counter()
@@ -338,6 +354,7 @@ def run_batched(draws, dev, steps, warmup, budget):
                      "latency_ms_p50": round(percentile(lat, 50) * 1e3, 4),
                      "latency_ms_p99": round(percentile(lat, 99) * 1e3, 4)}
     res["batched"]["stage_ms_per_step"] = {k: round(v / steps, 3) for k, v in stage_ms.items() if v > 0.01 * steps}
+    res["load_factor"] = load_factor
     res["batched"]["sub_batches"] = len(groups)
     res["batched"]["sub_batch_sizes"] = [len(g) for g in groups]
     res["batched"]["sub_batch_budget_expected_products"] = budget
@@ -388,6 +405,58 @@ def measured_traffic(workload, stage):
         return None
 
 
+def time_problem(p, steps, warmup):
+    """Seconds per plan + execute of one problem (inputs resident)."""
+    import torch
+
+    import paper_2410_10094_amd as sptc
+    X, Y = sptc.DeviceCoo.from_host(p.X), sptc.DeviceCoo.from_host(p.Y)
+    with sptc.plan(X, Y, p.cx, p.cy) as pl0:
+        idx, val, nnz, cap = pl0.allocate_outputs()
+        products = pl0.products
+
+    def step():
+        with sptc.plan(X, Y, p.cx, p.cy) as pl:
+            pl.execute_into(idx, val, cap, nnz)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    n = int(nnz.item())
+    if n < 0:
+        raise RuntimeError(f"{p.name}: device reported status {-n}")
+    return sec, products, n
+
+
+def run_sweep(steps):
+    """The shapes of the paper's synthetic sets (Table 1, sets 1 and 2): all
+    modes of length 50 or 100, order-5 (A) and order-4 (B) tensors of
+    50K-500K random entries, contracted on modes 1 and 2; A x A, A x B, B x B,
+    and B x A (operand swap, section 5.4)."""
+    from paper_2410_10094_amd import workloads as W
+    rows = []
+    for set_no, mode_len in ((1, 50), (2, 100)):
+        for nnz in (50_000, 100_000, 200_000, 300_000, 500_000):
+            for ox, oy in ((5, 5), (5, 4), (4, 4)):
+                p = W.paper_set(W.BASE_SEED + 10 * set_no + ox + oy, mode_len, nnz, ox, oy)
+                sec, P, n = time_problem(p, steps, 1)
+                row = {"set": set_no, "nnz": nnz, "orders": f"{ox}x{oy}", "products": P, "out_nnz": n,
+                       "ms": round(sec * 1e3, 4), "products_per_s": P / sec}
+                if ox != oy:  # operand swap: Y x X on the same data
+                    from paper_2410_10094_amd.workloads import Problem
+                    q = Problem(p.name + "-swap", p.Y, p.X, p.cy, p.cx)
+                    sec2, P2, n2 = time_problem(q, steps, 1)
+                    assert P2 == P and n2 == n
+                    row["swap_ms"] = round(sec2 * 1e3, 4)
+                rows.append(row)
+    return rows
+
+
 def roofline_of(r):
     p = r["problem"]
     stage = max(r["stage_ms"], key=lambda s: r["stage_ms"][s])
@@ -423,7 +492,10 @@ def main():
     ap.add_argument("--batched", type=int, default=512, metavar="COUNT",
                     help="draws of the batched workload timed per-call and batched (0: skip)")
     ap.add_argument("--batch-budget", type=float, default=1.0e9,
-                    help="expected products per sub-batch of the batched leg")
+                    help="expected products per sub-batch of the batched leg (without --autotune)")
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="1: tune load factor and batch budget on the first 128 draws before the batched legs")
+    ap.add_argument("--sweep", type=int, default=1, help="1: time the paper's synthetic-set shapes (Table 1, sets 1-2)")
     ap.add_argument("--serve", type=float, default=3.0, metavar="SECONDS",
                     help="seconds of Poisson arrivals for the served leg (0: skip); the pool is the batched draws")
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="arrivals per second of the served leg")
@@ -466,7 +538,11 @@ def main():
     batched = served = None
     if draws:
         dev = upload(draws)
-        batched = run_batched(draws, dev, max(1, args.steps // 5), 1, args.batch_budget)
+        tuned = autotune_batched(draws, dev, min(len(draws), 128)) if args.autotune else None
+        budget = tuned["batch_products"] if tuned else args.batch_budget
+        lf = tuned["load_factor"] if tuned else 1 / 1.3
+        batched = run_batched(draws, dev, max(1, args.steps // 5), 1, budget, lf)
+        batched["autotune"] = tuned
         batched["workload"] = (f"{len(draws)} draws: orders 3-5, dims U[32,4096], nnz log-U[1e3,1e6], "
                                "1-2 contracted pairs, FP64 U[-1,1)")
         if args.serve > 0:
@@ -474,10 +550,12 @@ def main():
             served = {"workload": f"Poisson arrivals, each request one of the {len(draws)} batched draws "
                                   "picked uniformly, inputs resident in HBM"}
             served["batched"] = run_served(draws, dev, args.serve, args.serve_rate, budget,
-                                           args.serve_batch_products, 4096, BASE_SEED + 5)
+                                           args.serve_batch_products, 4096, BASE_SEED + 5, lf)
             # the same arrivals served one request per launch
             served["per_call"] = run_served(draws, dev, min(args.serve, 1.0), args.serve_rate, budget,
-                                            args.serve_batch_products, 1, BASE_SEED + 5)
+                                            args.serve_batch_products, 1, BASE_SEED + 5, lf)
+
+    sweep = run_sweep(2) if args.sweep else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -512,6 +590,7 @@ def main():
         "also": also,
         "batched": batched,
         "served": served,
+        "paper_set_sweep": sweep,
     }
     print(json.dumps(line), flush=True)
 

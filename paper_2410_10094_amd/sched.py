@@ -26,6 +26,16 @@ def shape_class(y_dims: Sequence[int], cy: Sequence[int]) -> str:
     return "dense" if y_free_bits(y_dims, cy) <= DENSE_Y_BITS else "hash"
 
 
+def estimate_products(p) -> float:
+    """Cost estimate of a contraction before pass 1: nnz_X * nnz_Y over the
+    product of the contracted dims (exact in expectation for independent
+    uniform coordinates)."""
+    cells = 1
+    for c in p.cx:
+        cells *= int(p.X.dims[c])
+    return p.X.nnz * p.Y.nnz / max(cells, 1)
+
+
 def make_batches(items: Sequence, cost: Callable[[object], float], klass: Callable[[object], str],
                  budget: float, max_count: int = BATCH_MAX) -> List[List[int]]:
     """Indices of ``items`` cut into batches: same class within a batch,

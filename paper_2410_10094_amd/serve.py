@@ -178,11 +178,19 @@ class TorchBackend:
 class Server:
     def __init__(self, backend, budget_bytes: int = 64 << 30, max_inflight: int = 2,
                  batch_products: float = 5e8, max_batch: int = sched.BATCH_MAX,
-                 clock: Callable[[], float] = time.perf_counter, idle_wait: float = 50e-6):
+                 clock: Callable[[], float] = time.perf_counter, idle_wait: float = 50e-6,
+                 bytes_per_product: Optional[float] = 40.0):
+        """bytes_per_product: rough device bytes a batch needs per product
+        (its output COO entry, 4 B per output mode + 8 B value, plus
+        workspace); batches are kept to budget / (max_inflight *
+        bytes_per_product) expected products so that max_inflight of them fit
+        at once.  None: no such cap."""
         self.backend = backend
         self.budget = int(budget_bytes)
         self.max_inflight = max_inflight
         self.batch_products = batch_products
+        if bytes_per_product:
+            self.batch_products = min(batch_products, budget_bytes / (max_inflight * bytes_per_product))
         self.max_batch = max_batch
         self.clock = clock
         self.idle_wait = idle_wait

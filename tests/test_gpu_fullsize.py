@@ -44,18 +44,17 @@ def _key_sum_identity(p):
     return math.fsum(sx[ix] * sy[iy]), math.fsum(ax[ix] * ay[iy])
 
 
-def _check_large(p, nsamples=3000):
-    import paper_2410_10094_amd as sptc
-    X, Y = to_device(p)
-    log(f"[full] {p.name}: planning")
-    with sptc.plan(X, Y, p.cx, p.cy) as pl:
-        idx, val = pl.execute()
-        P, bound, dims = pl.products, pl.out_nnz_bound, pl.out_dims
+def _check_output(p, idx, val, P, bound, dims, nsamples, seed=20241010):
+    """Properties that hold at any size, then sampled outputs evaluated one
+    by one by the oracle."""
     nnz = val.shape[0]
-    log(f"[full] {p.name}: P={P} nnz={nnz}")
     _, total = oracle.match_counts(p.X, p.Y, p.cx, p.cy)
     assert P == total
-    assert 0 < nnz <= min(P, bound)
+    assert nnz <= min(P, bound)
+    if total == 0:
+        assert nnz == 0
+        return
+    assert nnz > 0
     for m, d in enumerate(dims):
         assert int(idx[m].min()) >= 0 and int(idx[m].max()) < d
     lin = _linear(idx, dims)
@@ -63,14 +62,24 @@ def _check_large(p, nsamples=3000):
     assert bool((slin[1:] > slin[:-1]).all()), "duplicate output coordinates"
     ident, scale = _key_sum_identity(p)
     assert abs(float(val.sum()) - ident) <= 1e-10 * scale
-    # sampled outputs, evaluated one by one by the oracle
-    q = oracle.sample_outputs(p.X, p.Y, p.cx, p.cy, nsamples, seed=20241010)
+    q = oracle.sample_outputs(p.X, p.Y, p.cx, p.cy, nsamples, seed=seed)
     ref_val, ref_abs, ref_terms = oracle.values_at(p.X, p.Y, p.cx, p.cy, q)
     qlin = _linear(torch.from_numpy(q).to(idx.device), dims)
     pos = torch.searchsorted(slin, qlin).clamp(max=nnz - 1)
     assert bool((slin[pos] == qlin).all()), "a sampled output coordinate is missing"
     got = val[order[pos]].cpu().numpy()
     H.assert_values_close(got, ref_val, ref_abs, ref_terms)
+
+
+def _check_large(p, nsamples=3000):
+    import paper_2410_10094_amd as sptc
+    X, Y = to_device(p)
+    log(f"[full] {p.name}: planning")
+    with sptc.plan(X, Y, p.cx, p.cy) as pl:
+        idx, val = pl.execute()
+        P, bound, dims = pl.products, pl.out_nnz_bound, pl.out_dims
+    log(f"[full] {p.name}: P={P} nnz={val.shape[0]}")
+    _check_output(p, idx, val, P, bound, dims, nsamples)
     log(f"[full] {p.name}: ok")
 
 
@@ -90,3 +99,26 @@ def test_block_sparse_1p5m_sampled():
 
 def test_imbalanced_full_size_sampled():
     _check_large(W.imbalanced())
+
+
+def test_batched_workload_full_size_draws():
+    """The first 64 full-size draws of the batched workload, cut into batches
+    as the benchmark cuts them (by Y free key class, at most 1e9 expected
+    products each) and executed with sptc_batch_*; every member is checked by
+    the properties above and sampled outputs."""
+    import paper_2410_10094_amd as sptc
+    from paper_2410_10094_amd import sched
+    draws = [W.batched_draw(W.BASE_SEED + 4, i) for i in range(64)]
+    cut = sched.make_batches(draws, sched.estimate_products, lambda p: sched.shape_class(p.Y.dims, p.cy), 1e9)
+    dev = [to_device(p) for p in draws]
+    checked = 0
+    for members in cut:
+        log(f"[full] batch of {len(members)}: planning")
+        with sptc.batch([(dev[i][0], dev[i][1], draws[i].cx, draws[i].cy) for i in members]) as bt:
+            res = bt.execute()
+            for i, it, (idx, val) in zip(members, bt.items, res):
+                _check_output(draws[i], idx, val, it["products"], it["out_nnz_bound"], it["out_dims"], 200,
+                              seed=1000 + i)
+                checked += 1
+        log(f"[full] batch of {len(members)}: ok")
+    assert checked == 64

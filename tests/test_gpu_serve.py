@@ -33,7 +33,7 @@ def test_served_results_match_alone_and_oracle():
     for i, (a, k) in enumerate(zip(arrivals, picks)):
         p = pool[k]
         reqs.append(serve.Request(i, dev[k][0], dev[k][1], p.cx, p.cy, float(a),
-                                  expected_products=W.expected_products(p), klass=sched.shape_class(p.Y.dims, p.cy)))
+                                  expected_products=sched.estimate_products(p), klass=sched.shape_class(p.Y.dims, p.cy)))
     log(f"[serve] {len(reqs)} requests over {arrivals[-1]:.3f} s")
     srv = serve.Server(serve.TorchBackend(arena_bytes=96 << 20, keep_results=True), budget_bytes=96 << 20,
                        batch_products=4e5)

@@ -111,7 +111,7 @@ def test_memory_budget_holds_back_batches():
     reqs = _requests(120, 100_000, 3)
     be = FakeBackend(sec_per_product=2e-9)
     budget = 400_000
-    srv = serve.Server(be, budget_bytes=budget, batch_products=2e6, max_inflight=3)
+    srv = serve.Server(be, budget_bytes=budget, batch_products=2e6, max_inflight=3, bytes_per_product=None)
     done = srv.run(reqs)
     assert len(done) == 120
     assert srv.peak_used <= budget
@@ -193,3 +193,51 @@ def test_ring_arena_never_overlaps():
                 for (s2, e2) in live:
                     assert e <= s2 or s >= e2
                 live.append((s, e))
+
+
+def test_autotuner_picks_fastest_and_caches(tmp_path):
+    from paper_2410_10094_amd import autotune
+    calls = []
+
+    def run(lf, bud):
+        calls.append((lf, bud))
+        return abs(lf - 0.625) + abs(bud - 5e8) / 1e9  # fastest at (0.625, 5e8)
+
+    path = str(tmp_path / "tune.json")
+    t = autotune.Autotuner(path)
+    rec = t.tune("k", run)
+    assert (rec["load_factor"], rec["batch_products"]) == (0.625, 5e8)
+    assert len(calls) == len(autotune.LOAD_FACTORS) * len(autotune.BATCH_BUDGETS)
+    again = autotune.Autotuner(path).tune("k", run)  # from the cache: no new timings
+    assert again["load_factor"] == 0.625 and len(calls) == 16
+
+
+def test_autotuner_tie_prefers_larger_load_factor_and_batch():
+    from paper_2410_10094_amd import autotune
+    assert autotune.choose({(0.5, 1e9): 1.0, (0.9, 1e9): 1.0, (0.9, 2e9): 1.0, (0.5, 2e8): 2.0}) == (0.9, 2e9)
+
+
+def test_scheduler_cost_estimate_and_classes():
+    from paper_2410_10094_amd import sched
+
+    class C:
+        def __init__(self, dims, nnz):
+            self.dims, self.nnz = dims, nnz
+
+    class Prob:
+        X = C((10, 20, 30), 600)
+        Y = C((30, 8, 8), 90)
+        cx, cy = (2,), (0,)
+
+    assert sched.estimate_products(Prob) == 600 * 90 / 30
+    assert sched.shape_class((30, 8, 8), (0,)) == "dense"  # 6 bits of Y free key
+    assert sched.shape_class((30, 4096, 4096), (0,)) == "hash"  # 24 bits
+    b = sched.make_batches([1, 2, 3, 4, 5], lambda x: x, lambda x: "odd" if x % 2 else "even", 4)
+    assert b == [[0, 2], [1], [3], [4]]  # one class per batch, arrival order, cost within 4
+
+
+def test_batches_sized_so_in_flight_batches_fit():
+    srv = serve.Server(FakeBackend(), budget_bytes=64 << 30, batch_products=1e9, max_inflight=2)
+    assert srv.batch_products == (64 << 30) / (2 * 40.0)
+    srv = serve.Server(FakeBackend(), budget_bytes=1 << 40, batch_products=1e9, max_inflight=2)
+    assert srv.batch_products == 1e9
