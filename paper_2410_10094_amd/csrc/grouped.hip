@@ -973,13 +973,15 @@ __global__ __launch_bounds__(kBBlock) void k_group_block_dense(GroupArgs a, cons
 // there.  Lanes take consecutive products, so the Y loads and the COO stores
 // coalesce; each lane keeps kDItems Y loads in flight.
 constexpr int kDBlock = 256;
-constexpr int kDItems = 8;
-constexpr int kDTile = kDBlock * kDItems;
+constexpr int kDItemsOne = 8;    // products in flight per lane, one contraction
+constexpr int kDItemsBatch = 5;  // and in a batch (the per-contraction decode takes registers)
 constexpr int kDGroups = 1024;  // groups staged per tile; more fall back to global loads
 
+template <bool BATCH, int kDItems>
 __global__ __launch_bounds__(kDBlock) void k_group_direct(GroupArgs a, const uint32_t* __restrict__ dlist,
                                                           const unsigned long long* __restrict__ dpos, int64_t nd,
                                                           uint64_t nprod) {
+  constexpr int kDTile = kDBlock * kDItems;
   __shared__ unsigned long long s_pos[kDGroups + 1];
   __shared__ unsigned long long s_phi[kDGroups];
   __shared__ double s_v[kDGroups];
@@ -1004,12 +1006,12 @@ __global__ __launch_bounds__(kDBlock) void k_group_direct(GroupArgs a, const uin
         s_phi[k] = G.phi;
         s_v[k] = r.v;
         s_ys[k] = r.ystart;
-        s_sh[k] = a.bout ? a.bseg[G.phi >> a.bwx].dshift : 0ull;
+        if constexpr (BATCH) s_sh[k] = a.bseg[G.phi >> a.bwx].dshift;
       }
       if (threadIdx.x == 0) s_pos[nloc] = dpos[ihi + 1];
     }
     __syncthreads();
-    unsigned long long ys[kDItems], phx[kDItems], dsh[kDItems];
+    unsigned long long ys[kDItems], phx[kDItems], dsh[BATCH ? kDItems : 1];
     double xv[kDItems];
     YEntry ye[kDItems];
 #pragma unroll
@@ -1029,7 +1031,7 @@ __global__ __launch_bounds__(kDBlock) void k_group_direct(GroupArgs a, const uin
         ys[it] = (unsigned long long)s_ys[lo] + (q - s_pos[lo]);
         phx[it] = s_phi[lo];
         xv[it] = s_v[lo];
-        dsh[it] = s_sh[lo];
+        if constexpr (BATCH) dsh[it] = s_sh[lo];
       } else {
         const int64_t li = upper_bound_idx(dpos, ilo, ihi + 1, q) - 1;
         const GroupRec G = a.groups[dlist[li]];
@@ -1037,7 +1039,7 @@ __global__ __launch_bounds__(kDBlock) void k_group_direct(GroupArgs a, const uin
         ys[it] = (unsigned long long)r.ystart + (q - dpos[li]);
         phx[it] = G.phi;
         xv[it] = r.v;
-        dsh[it] = a.bout ? a.bseg[G.phi >> a.bwx].dshift : 0ull;
+        if constexpr (BATCH) dsh[it] = a.bseg[G.phi >> a.bwx].dshift;
       }
       if (ys[it] >= (unsigned long long)a.ny) {
         record_error(a.st, kErrInternal);
@@ -1051,7 +1053,7 @@ __global__ __launch_bounds__(kDBlock) void k_group_direct(GroupArgs a, const uin
     for (int it = 0; it < kDItems; ++it) {
       const uint64_t q = p0 + (uint64_t)it * kDBlock + threadIdx.x;
       if (ys[it] == ~0ull) continue;
-      if (a.bout)
+      if constexpr (BATCH)
         batch_store(a.bout, a.out_idx, a.out_val, a.bwx, (uint32_t)(phx[it] >> a.bwx), q - dsh[it], phx[it],
                     ye[it].phi, __dmul_rn(xv[it], ye[it].v), a.st);
       else if ((int64_t)q < a.out_cap)
@@ -1304,10 +1306,14 @@ hipError_t launch_group_block(const GroupArgs& a, const uint32_t* blist, int64_t
 hipError_t launch_group_direct(const GroupArgs& a, const uint32_t* dlist, const unsigned long long* dpos, int64_t nd,
                                uint64_t nprod, int num_cus, hipStream_t stream) {
   if (nd <= 0 || nprod == 0) return hipSuccess;
-  const uint64_t tiles = (nprod + kDTile - 1) / kDTile;
+  const int items = a.bout ? kDItemsBatch : kDItemsOne;
+  const uint64_t tile = (uint64_t)kDBlock * items, tiles = (nprod + tile - 1) / tile;
   uint64_t g = (uint64_t)num_cus * 8;
   if (g > tiles) g = tiles;
-  k_group_direct<<<dim3((unsigned)g), kDBlock, 0, stream>>>(a, dlist, dpos, nd, nprod);
+  if (a.bout)
+    k_group_direct<true, kDItemsBatch><<<dim3((unsigned)g), kDBlock, 0, stream>>>(a, dlist, dpos, nd, nprod);
+  else
+    k_group_direct<false, kDItemsOne><<<dim3((unsigned)g), kDBlock, 0, stream>>>(a, dlist, dpos, nd, nprod);
   return hipGetLastError();
 }
 
