@@ -704,15 +704,23 @@ __device__ __forceinline__ void bitonic_sort_lds_n(unsigned long long* a, unsign
 // and records how many have one (neff).  Order within a group is free
 // (section 4.1.3); the sorted order lets co-accumulation below merge the
 // entries of several groups by Y run.
-__global__ __launch_bounds__(kBBlock) void k_sort_block_entries(const GroupRec* __restrict__ groups,
+// Two launches share the work: THREADS = 256 sorts the groups of at most
+// kSortSmall entries (small LDS, many workgroups per CU), THREADS = 1024 the
+// larger ones; each skips the other's groups.
+constexpr int kSortSmall = 1024;
+
+template <int THREADS, int MAXN>
+__global__ __launch_bounds__(THREADS) void k_sort_block_entries(const GroupRec* __restrict__ groups,
                                                                 const uint32_t* __restrict__ blist, int64_t nb,
                                                                 XRec* __restrict__ xr, uint32_t* __restrict__ neff) {
   extern __shared__ __align__(16) unsigned char s_dyn[];
-  unsigned long long* s_key = reinterpret_cast<unsigned long long*>(s_dyn);  // [kCoSortMax]
-  XRec* s_rec = reinterpret_cast<XRec*>(s_dyn + (size_t)kCoSortMax * 8);     // [kCoSortMax]
+  unsigned long long* s_key = reinterpret_cast<unsigned long long*>(s_dyn);  // [MAXN]
+  XRec* s_rec = reinterpret_cast<XRec*>(s_dyn + (size_t)MAXN * 8);           // [MAXN]
   __shared__ unsigned s_n;
+  constexpr bool kSmall = MAXN <= kSortSmall;
   for (int64_t i = blockIdx.x; i < nb; i += gridDim.x) {
     const GroupRec G = groups[blist[i]];
+    if (kSmall ? G.count > (unsigned)MAXN : G.count <= (unsigned)kSortSmall) continue;  // the other launch's
     if (G.count > (unsigned)kCoSortMax) {  // uniform: left unsorted, not co-accumulated
       if (threadIdx.x == 0) neff[i] = G.count;
       continue;
@@ -721,7 +729,7 @@ __global__ __launch_bounds__(kBBlock) void k_sort_block_entries(const GroupRec* 
     while (nsort < G.count) nsort <<= 1;
     if (threadIdx.x == 0) s_n = 0u;
     __syncthreads();
-    for (unsigned e = threadIdx.x; e < nsort; e += kBBlock) {
+    for (unsigned e = threadIdx.x; e < nsort; e += THREADS) {
       unsigned long long key = ~0ull;
       if (e < G.count) {
         const XRec r = xr[G.start + e];
@@ -733,7 +741,7 @@ __global__ __launch_bounds__(kBBlock) void k_sort_block_entries(const GroupRec* 
     }
     __syncthreads();
     bitonic_sort_lds_n(s_key, nsort);
-    for (unsigned e = threadIdx.x; e < G.count; e += kBBlock)
+    for (unsigned e = threadIdx.x; e < G.count; e += THREADS)
       xr[G.start + e] = s_rec[(unsigned)(s_key[e] & 0xffffffffull)];
     if (threadIdx.x == 0) neff[i] = s_n;
     __syncthreads();
@@ -1231,6 +1239,7 @@ hipError_t launch_group_wave(const GroupArgs& a, const uint32_t* wlist, int64_t 
 // within kCoLds; the plan-time sort stages kCoSortMax keys and records.
 constexpr size_t kBlockHashLds = (size_t)kBlockSlots * 16;
 constexpr size_t kSortLds = (size_t)kCoSortMax * (8 + sizeof(XRec));
+constexpr size_t kSortSmallLds = (size_t)kSortSmall * (8 + sizeof(XRec));
 
 // Groups a dense workgroup co-accumulates for `cells` accumulator cells.
 static unsigned co_groups(unsigned cells) {
@@ -1270,7 +1279,7 @@ hipError_t prepare_group_block() {
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_group_block_dense),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)kCoLds);
   if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sort_block_entries),
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sort_block_entries<kBBlock, kCoSortMax>),
                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSortLds);
   if (e != hipSuccess) return e;
   return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_group_block<false>),
@@ -1280,8 +1289,10 @@ hipError_t prepare_group_block() {
 hipError_t launch_sort_block_entries(const GroupRec* groups, const uint32_t* blist, int64_t nb, XRec* xr,
                                      uint32_t* neff, int num_cus, hipStream_t stream) {
   if (nb <= 0) return hipSuccess;
-  const unsigned grid = grid_for(nb * kBBlock, kBBlock, num_cus, 2);
-  k_sort_block_entries<<<grid, kBBlock, kSortLds, stream>>>(groups, blist, nb, xr, neff);
+  k_sort_block_entries<256, kSortSmall><<<grid_for(nb * 256, 256, num_cus, 8), 256, kSortSmallLds, stream>>>(
+      groups, blist, nb, xr, neff);
+  k_sort_block_entries<kBBlock, kCoSortMax><<<grid_for(nb * kBBlock, kBBlock, num_cus, 2), kBBlock, kSortLds,
+                                                stream>>>(groups, blist, nb, xr, neff);
   return hipGetLastError();
 }
 
