@@ -1075,27 +1075,42 @@ __global__ __launch_bounds__(kDBlock) void k_group_direct(GroupArgs a, const uin
 // entries by Y free key, one workgroup per Y table slot.  Order within a run
 // is free (section 4.1.3); sorted runs let the lanes of a wave that walk a run
 // hit consecutive dense accumulator cells, i.e. distinct LDS banks.
+// Dense Y free keys only; it also finds repeated Y coordinates (two entries
+// of one run with the same free key) with a per-run bitmap of the
+// 2^kDenseBits keys, which the direct class needs to know about.
 __global__ __launch_bounds__(kBBlock) void k_sort_y_runs(const YSlot* __restrict__ ytab, int64_t nslots,
                                                          YEntry* __restrict__ yg, int64_t ny,
-                                                         uint16_t* __restrict__ ykey16, double* __restrict__ yval) {
+                                                         uint16_t* __restrict__ ykey16, double* __restrict__ yval,
+                                                         DevStatus* st) {
   __shared__ unsigned long long s_key[kBBlock];
   __shared__ YEntry s_ent[kBBlock];
+  __shared__ unsigned s_seen[(1u << kDenseBits) / 32];
+  constexpr unsigned kSeenWords = (1u << kDenseBits) / 32;
+  auto seen_before = [&](unsigned long long phi) {
+    const unsigned c = (unsigned)phi & ((1u << kDenseBits) - 1u), bit = 1u << (c & 31);
+    return (atomicOr(&s_seen[c >> 5], bit) & bit) != 0u;
+  };
   for (int64_t slot = blockIdx.x; slot < nslots; slot += gridDim.x) {
     const YSlot t = ytab[slot];
     if (t.key == kEmpty || t.count == 0 || (unsigned long long)t.start + t.count > (unsigned long long)ny)
       continue;  // uniform across the block
     const unsigned n = t.count, tid = threadIdx.x;
+    for (unsigned w = tid; w < kSeenWords; w += kBBlock) s_seen[w] = 0u;
+    __syncthreads();
     if (n > (unsigned)kBBlock) {  // too long to sort here: copy as is
       for (unsigned j = tid; j < n; j += kBBlock) {
         const YEntry e = yg[t.start + j];
+        if (seen_before(e.phi)) st->ydup = 1u;
         ykey16[t.start + j] = (uint16_t)e.phi;
         yval[t.start + j] = e.v;
       }
+      __syncthreads();
       continue;
     }
     unsigned long long key = ~0ull;
     if (tid < n) {
       s_ent[tid] = yg[t.start + tid];
+      if (seen_before(s_ent[tid].phi)) st->ydup = 1u;
       key = (s_ent[tid].phi << 11) | tid;  // phi has <= kDenseBits bits here; tid < 2048
     }
     s_key[tid] = key;
@@ -1334,10 +1349,10 @@ hipError_t launch_scan_group_counts(const uint32_t* gn, const uint32_t* wlist, i
 }
 
 hipError_t launch_sort_y_runs(const YSlot* ytab, int64_t nslots, YEntry* yg, int64_t ny, uint16_t* ykey16,
-                              double* yval, int num_cus, hipStream_t stream) {
+                              double* yval, DevStatus* st, int num_cus, hipStream_t stream) {
   if (nslots <= 0 || ny <= 0) return hipSuccess;
   int64_t grid = nslots < (int64_t)num_cus * 2 ? nslots : (int64_t)num_cus * 2;
-  k_sort_y_runs<<<dim3((unsigned)grid), kBBlock, 0, stream>>>(ytab, nslots, yg, ny, ykey16, yval);
+  k_sort_y_runs<<<dim3((unsigned)grid), kBBlock, 0, stream>>>(ytab, nslots, yg, ny, ykey16, yval, st);
   return hipGetLastError();
 }
 

@@ -396,7 +396,7 @@ sptc_status plan_group_y(sptc_plan_s* P, const sptc_coo* Y) {
     HIP_TRY(launch_y_scatter(Y->idx, Y->val, P->ny, P->y_c, P->y_f, P->yb, P->ytab, P->ygeom, seed, P->max_probe_y,
                              P->yg, P->yset, (uint64_t)P->yset_slots - 1, yset_bits(P), P->st, P->num_cus, s));
   if (P->opt.mode == SPTC_MODE_GROUPED && P->dense)
-    HIP_TRY(launch_sort_y_runs(P->ytab, P->ytab_slots, P->yg, P->ny, P->ykey16, P->yval, P->num_cus, s));
+    HIP_TRY(launch_sort_y_runs(P->ytab, P->ytab_slots, P->yg, P->ny, P->ykey16, P->yval, P->st, P->num_cus, s));
   HIP_TRY(mark(P, s, SPTC_STAGE_Y_SCATTER, 1));
   return SPTC_OK;
 }
@@ -553,8 +553,9 @@ sptc_status plan_body(sptc_plan_s* P, const sptc_coo* X, const sptc_coo* Y, cons
   const int64_t tiles = std::max<int64_t>({scan_tiles(P->ytab_slots), scan_tiles(P->xtab_slots), scan_tiles(P->nx)});
   if ((st = P->allocate_n(2 * (tiles + 1), &P->tile_sums))) return st;  // room for pair-valued scans
   // Y coordinate set (grouped mode): finds repeated Y coordinates, which the
-  // direct class cannot have.
-  const bool yset = grouped;
+  // direct class cannot have.  With a dense Y free key the run sort finds
+  // them instead.
+  const bool yset = grouped && !P->dense;
   if (yset) {
     P->yset_slots = pow2_at_least(4.0 * (double)std::max<int64_t>(P->ny, 1));  // sparse: short probes
     if ((st = P->allocate_n(P->yset_slots, &P->yset))) return st;

@@ -309,7 +309,7 @@ hipError_t launch_finalize(int64_t* out_nnz, int64_t out_cap, DevStatus* st, hip
 // writes the compact copy of grouped Y (16-bit keys, values) the dense
 // accumulators read.
 hipError_t launch_sort_y_runs(const YSlot* ytab, int64_t nslots, YEntry* yg, int64_t ny, uint16_t* ykey16,
-                              double* yval, int num_cus, hipStream_t stream);
+                              double* yval, DevStatus* st, int num_cus, hipStream_t stream);
 
 // Clears st->err and st->out_base.
 hipError_t launch_reset_status(DevStatus* st, hipStream_t stream);

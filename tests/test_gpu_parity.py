@@ -209,20 +209,25 @@ def test_output_keys_wider_than_63_bits(p):
         assert info["classes"]["direct"] > 0 and info["classes"]["wave"] > 0
 
 
-def test_repeated_y_coordinates_disable_direct_class():
+@pytest.mark.parametrize("kind", ["dense", "dense-long-runs", "hashed"])
+def test_repeated_y_coordinates_disable_direct_class(kind):
     """With a repeated Y coordinate a single-entry X group can have two
-    products on one output, so the direct class must not be used."""
+    products on one output, so the direct class must not be used.  Dense Y
+    free keys find repeats in the run sort (runs up to 1024 entries sorted,
+    longer ones copied), others in a device set."""
     rng = np.random.default_rng(35)
-    X = Coo((1000, 50), W.unique_coords(rng, (1000, 50), 2000), W.nonzero_uniform(rng, 2000))
-    yc = W.unique_coords(rng, (50, 100), 800)
+    nc, ny_free, ny = {"dense": (50, 100, 800), "dense-long-runs": (4, 5000, 6000),
+                       "hashed": (50, 1 << 20, 800)}[kind]
+    X = Coo((1000, nc), W.unique_coords(rng, (1000, nc), 2000), W.nonzero_uniform(rng, 2000))
+    yc = W.unique_coords(rng, (nc, ny_free), ny)
     yc = np.concatenate([yc, yc[:, :5]], axis=1)  # five coordinates appear twice
-    Y = Coo((50, 100), yc, W.nonzero_uniform(rng, yc.shape[1]))
-    p = Problem("y-repeats", X, Y, (1,), (0,))
-    log("[ydup]")
+    Y = Coo((nc, ny_free), yc, W.nonzero_uniform(rng, yc.shape[1]))
+    p = Problem(f"y-repeats-{kind}", X, Y, (1,), (0,))
+    log(f"[ydup] {kind}")
     info, gidx, gval = run_gpu(p, mode="grouped")
     assert info["classes"]["direct"] == 0
     assert_parity(p, gidx, gval)
-    q = Problem("y-unique", X, Coo((50, 100), yc[:, :800], W.nonzero_uniform(rng, 800)), (1,), (0,))
+    q = Problem(f"y-unique-{kind}", X, Coo((nc, ny_free), yc[:, :ny], W.nonzero_uniform(rng, ny)), (1,), (0,))
     info, gidx, gval = run_gpu(q, mode="grouped")
     assert info["classes"]["direct"] > 0
     assert_parity(q, gidx, gval)
