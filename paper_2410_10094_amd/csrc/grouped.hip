@@ -44,6 +44,7 @@ constexpr unsigned long long kWaveMaxProducts = 16384;  // beyond this a group g
 struct XTableScanOp {
   YSlot* tab;
   GroupRec* groups;
+  bool run_end;  // start = end of run (placement takes and decrements), else its beginning
   __device__ unsigned long long get(int64_t i) const {
     const YSlot s = tab[i];
     return s.key != kEmpty ? (((unsigned long long)s.count << 32) | 1ull) : 0ull;
@@ -56,7 +57,7 @@ struct XTableScanOp {
     g.start = (unsigned)(excl >> 32);
     g.count = count;
     groups[(unsigned)(excl & 0xffffffffull)] = g;
-    tab[i].start = g.start + count;  // end of the run: the scatter takes and decrements
+    tab[i].start = run_end ? g.start + count : g.start;
   }
 };
 
@@ -136,12 +137,13 @@ __global__ __launch_bounds__(256) void k_x_scatter(const int32_t* __restrict__ x
 // Aggregated variant for a direct-addressed X table (small X free keys).
 __global__ __launch_bounds__(kAggBlock) void k_x_scatter_agg(const int32_t* __restrict__ xidx,
                                                              const double* __restrict__ xval, int64_t nnz, KeyPack kf,
-                                                             KeyPack kc, Bounds b, YSlot* __restrict__ xtab,
-                                                             unsigned nslots, const YSlot* __restrict__ ytab,
+                                                             KeyPack kc, Bounds b, const YSlot* __restrict__ xtab,
+                                                             unsigned nslots, const unsigned* __restrict__ choff,
+                                                             const YSlot* __restrict__ ytab,
                                                              TabGeom yg, int32_t max_probe_y, uint64_t seed,
                                                              XRec* __restrict__ xr, DevStatus* st) {
   extern __shared__ unsigned s_agg[];
-  place_chunk(xidx, nnz, kf, xtab, nslots, s_agg, s_agg + nslots,
+  place_chunk(xidx, nnz, kf, nslots, choff, s_agg, s_agg + nslots,
               [&](const int64_t* e, const uint64_t*, const unsigned* pos, const bool* ok) {
                 uint64_t ckey[kAggUnroll];
                 ProbeSeq ys[kAggUnroll];
@@ -1179,9 +1181,9 @@ __global__ void k_x_groups(const GroupRec* __restrict__ groups, int64_t ng, cons
 // Launchers
 // ---------------------------------------------------------------------------
 
-hipError_t launch_scan_x_table(YSlot* tab, int64_t nslots, GroupRec* groups, void* tile_sums, DevStatus* st,
-                               hipStream_t stream) {
-  return device_scan(XTableScanOp{tab, groups}, nslots, tile_sums, FinXGroups{st}, stream);
+hipError_t launch_scan_x_table(YSlot* tab, int64_t nslots, GroupRec* groups, bool run_end, void* tile_sums,
+                               DevStatus* st, hipStream_t stream) {
+  return device_scan(XTableScanOp{tab, groups, run_end}, nslots, tile_sums, FinXGroups{st}, stream);
 }
 
 hipError_t launch_x_scatter(const int32_t* xidx, const double* xval, int64_t nnz, KeyPack kf, KeyPack kc, Bounds b,
@@ -1195,12 +1197,13 @@ hipError_t launch_x_scatter(const int32_t* xidx, const double* xval, int64_t nnz
 }
 
 hipError_t launch_x_scatter_agg(const int32_t* xidx, const double* xval, int64_t nnz, KeyPack kf, KeyPack kc,
-                                Bounds b, YSlot* xtab, unsigned nslots, const YSlot* ytab, TabGeom yg,
-                                int32_t max_probe_y, uint64_t seed, XRec* xr, DevStatus* st, hipStream_t stream) {
+                                Bounds b, const YSlot* xtab, unsigned nslots, const unsigned* choff, const YSlot* ytab,
+                                TabGeom yg, int32_t max_probe_y, uint64_t seed, XRec* xr, DevStatus* st,
+                                hipStream_t stream) {
   if (nnz <= 0) return hipSuccess;
-  const unsigned grid = (unsigned)((nnz + kAggChunk - 1) / kAggChunk);
-  k_x_scatter_agg<<<grid, kAggBlock, (size_t)nslots * 8, stream>>>(xidx, xval, nnz, kf, kc, b, xtab, nslots, ytab,
-                                                                    yg, max_probe_y, seed, xr, st);
+  const unsigned grid = (unsigned)agg_chunks(nnz);
+  k_x_scatter_agg<<<grid, kAggBlock, (size_t)nslots * 8, stream>>>(xidx, xval, nnz, kf, kc, b, xtab, nslots, choff,
+                                                                    ytab, yg, max_probe_y, seed, xr, st);
   return hipGetLastError();
 }
 

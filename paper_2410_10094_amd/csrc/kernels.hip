@@ -57,11 +57,14 @@ __global__ __launch_bounds__(256) void k_key_count(const int32_t* __restrict__ i
 }
 
 // A2 op: count -> inclusive end offset of the group, kept in `start`.
+// run_end: start = end of the run (placement takes and decrements), else
+// start = its beginning (placement from per-chunk offsets).
 struct YTableScanOp {
   YSlot* tab;
+  bool run_end;
   __device__ unsigned long long get(int64_t i) const { return tab[i].count; }
   __device__ void put(int64_t i, unsigned long long excl, unsigned long long v) const {
-    if (v) tab[i].start = (unsigned)(excl + v);
+    if (v) tab[i].start = (unsigned)(run_end ? excl + v : excl);
   }
 };
 
@@ -375,9 +378,10 @@ __global__ void k_x_counts(const unsigned long long* __restrict__ poff, int64_t 
 // Direct-addressed small-key tables, aggregated per workgroup in LDS
 // ---------------------------------------------------------------------------
 
+// Small key spaces, count: each workgroup histograms its chunk in LDS and
+// writes the histogram as row `chunk` of hist (no global atomics).
 __global__ __launch_bounds__(kAggBlock) void k_key_count_agg(const int32_t* __restrict__ idx, int64_t nnz, KeyPack kc,
-                                                             YSlot* __restrict__ tab, unsigned nslots,
-                                                             unsigned long long* distinct) {
+                                                             unsigned nslots, unsigned* __restrict__ hist) {
   extern __shared__ unsigned s_cnt[];
   for (unsigned s = threadIdx.x; s < nslots; s += kAggBlock) s_cnt[s] = 0u;
   __syncthreads();
@@ -387,24 +391,56 @@ __global__ __launch_bounds__(kAggBlock) void k_key_count_agg(const int32_t* __re
       if (ok[u]) atomicAdd(&s_cnt[(unsigned)keys[u]], 1u);
   });
   __syncthreads();
-  for (unsigned s = threadIdx.x; s < nslots; s += kAggBlock) {
-    const unsigned c = s_cnt[s];
-    if (!c) continue;
-    tab[s].key = s;  // every writer stores the same key
-    const unsigned prev = atomicAdd(&tab[s].count, c);
-    if (prev == 0u && distinct) atomicAdd(distinct, 1ull);
+  unsigned* row = hist + (size_t)blockIdx.x * nslots;
+  for (unsigned s = threadIdx.x; s < nslots; s += kAggBlock) row[s] = s_cnt[s];
+}
+
+// The chunk histograms, taken key-major (key s, then chunk w), become by an
+// exclusive scan in place the first position of key s's entries of chunk w:
+// the start of s's run plus the entries of s in earlier chunks.
+struct AggOffsetsOp {
+  unsigned* hist;  // [nchunks][nslots]
+  int64_t nchunks;
+  unsigned nslots;
+  __device__ unsigned* cell(int64_t i) const {
+    return hist + (size_t)(i % nchunks) * nslots + (size_t)(i / nchunks);
   }
+  __device__ unsigned long long get(int64_t i) const { return *cell(i); }
+  __device__ void put(int64_t i, unsigned long long excl, unsigned long long) const { *cell(i) = (unsigned)excl; }
+};
+
+struct FinAggTotal {
+  unsigned long long* total;
+  __device__ void operator()(unsigned long long t) const { *total = t; }
+};
+
+// Key table from the scanned histograms: key s's run starts at its chunk-0
+// position and ends where key s + 1's starts.
+__global__ void k_agg_table(const unsigned* __restrict__ hist, unsigned nslots, const unsigned long long* total,
+                            YSlot* __restrict__ tab, unsigned long long* distinct) {
+  const unsigned s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nslots) return;
+  const unsigned start = hist[s];
+  const unsigned end = s + 1 < nslots ? hist[s + 1] : (unsigned)*total;
+  if (end == start) return;
+  YSlot t;
+  t.key = s;
+  t.count = end - start;
+  t.start = start;
+  tab[s] = t;
+  if (distinct) atomicAdd(distinct, 1ull);
 }
 
 __global__ __launch_bounds__(kAggBlock) void k_y_scatter_agg(const int32_t* __restrict__ yidx,
                                                              const double* __restrict__ yval, int64_t nnz, KeyPack kc,
-                                                             KeyPack kf, Bounds b, YSlot* __restrict__ tab,
-                                                             unsigned nslots, YEntry* __restrict__ yg,
+                                                             KeyPack kf, Bounds b, const YSlot* __restrict__ tab,
+                                                             unsigned nslots, const unsigned* __restrict__ choff,
+                                                             YEntry* __restrict__ yg,
                                                              unsigned long long* __restrict__ yset,
                                                              uint64_t yset_mask, uint64_t seed, int32_t bits_y,
                                                              DevStatus* st) {
   extern __shared__ unsigned s_agg[];
-  place_chunk(yidx, nnz, kc, tab, nslots, s_agg, s_agg + nslots,
+  place_chunk(yidx, nnz, kc, nslots, choff, s_agg, s_agg + nslots,
               [&](const int64_t* e, const uint64_t* keys, const unsigned* pos, const bool* ok) {
                 bool good[kAggUnroll];
                 unsigned long long full[kAggUnroll];
@@ -457,8 +493,9 @@ hipError_t launch_key_count(const int32_t* idx, int64_t nnz, KeyPack kc, YSlot* 
   return hipGetLastError();
 }
 
-hipError_t launch_scan_y_table(YSlot* tab, int64_t nslots, unsigned long long* tile_sums, hipStream_t stream) {
-  return device_scan(YTableScanOp{tab}, nslots, tile_sums, FinNone{}, stream);
+hipError_t launch_scan_y_table(YSlot* tab, int64_t nslots, bool run_end, unsigned long long* tile_sums,
+                               hipStream_t stream) {
+  return device_scan(YTableScanOp{tab, run_end}, nslots, tile_sums, FinNone{}, stream);
 }
 
 hipError_t launch_y_scatter(const int32_t* yidx, const double* yval, int64_t nnz, KeyPack kc, KeyPack kf, Bounds b,
@@ -472,20 +509,28 @@ hipError_t launch_y_scatter(const int32_t* yidx, const double* yval, int64_t nnz
 }
 
 hipError_t launch_key_count_agg(const int32_t* idx, int64_t nnz, KeyPack kc, YSlot* tab, unsigned nslots,
+                                unsigned* hist, unsigned long long* total, unsigned long long* tile_sums,
                                 unsigned long long* distinct, hipStream_t stream) {
   if (nnz <= 0) return hipSuccess;
-  const unsigned grid = (unsigned)((nnz + kAggChunk - 1) / kAggChunk);
-  k_key_count_agg<<<grid, kAggBlock, (size_t)nslots * 4, stream>>>(idx, nnz, kc, tab, nslots, distinct);
+  const int64_t chunks = agg_chunks(nnz);
+  k_key_count_agg<<<(unsigned)chunks, kAggBlock, (size_t)nslots * 4, stream>>>(idx, nnz, kc, nslots, hist);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = device_scan(AggOffsetsOp{hist, chunks, nslots}, chunks * (int64_t)nslots, tile_sums, FinAggTotal{total},
+                  stream);
+  if (e != hipSuccess) return e;
+  k_agg_table<<<(nslots + 255) / 256, 256, 0, stream>>>(hist, nslots, total, tab, distinct);
   return hipGetLastError();
 }
 
 hipError_t launch_y_scatter_agg(const int32_t* yidx, const double* yval, int64_t nnz, KeyPack kc, KeyPack kf,
-                                Bounds b, YSlot* tab, unsigned nslots, YEntry* yg, unsigned long long* yset,
+                                Bounds b, const YSlot* tab, unsigned nslots, const unsigned* choff, YEntry* yg,
+                                unsigned long long* yset,
                                 uint64_t yset_mask, uint64_t seed, int32_t bits_y, DevStatus* st,
                                 hipStream_t stream) {
   if (nnz <= 0) return hipSuccess;
-  const unsigned grid = (unsigned)((nnz + kAggChunk - 1) / kAggChunk);
-  k_y_scatter_agg<<<grid, kAggBlock, (size_t)nslots * 8, stream>>>(yidx, yval, nnz, kc, kf, b, tab, nslots, yg,
+  const unsigned grid = (unsigned)agg_chunks(nnz);
+  k_y_scatter_agg<<<grid, kAggBlock, (size_t)nslots * 8, stream>>>(yidx, yval, nnz, kc, kf, b, tab, nslots, choff, yg,
                                                                     yset, yset_mask, seed, bits_y, st);
   return hipGetLastError();
 }

@@ -327,7 +327,6 @@ __device__ __forceinline__ void wave_lds_fence() {
 // ---------------------------------------------------------------------------
 
 constexpr int kAggBlock = 256;
-constexpr int kAggChunk = 4096;  // entries per workgroup
 constexpr int kAggUnroll = 8;    // entries a thread handles at once (independent memory ops in flight)
 
 // Walks this workgroup's chunk kAggUnroll entries per thread at a time: f
@@ -351,25 +350,18 @@ __device__ __forceinline__ void for_chunk_batches(const int32_t* __restrict__ id
   }
 }
 
-// Counts this workgroup's chunk per key in LDS, reserves one run per key
-// present (taking from the group's end offset in the table), then hands
-// every batch of entries with their positions to place(e, key, pos, ok).
+// Places this workgroup's chunk: key s's entries of this chunk start at
+// choff[chunk][s] (the start of s's run plus s's entries in earlier chunks)
+// and follow in chunk order; hands every batch of entries with their
+// positions to place(e, key, pos, ok).  No global atomics.
 template <class F>
 __device__ __forceinline__ void place_chunk(const int32_t* __restrict__ idx, int64_t nnz, const KeyPack& kc,
-                                            YSlot* __restrict__ tab, unsigned nslots, unsigned* s_cnt,
+                                            unsigned nslots, const unsigned* __restrict__ choff, unsigned* s_cnt,
                                             unsigned* s_base, F place) {
-  for (unsigned s = threadIdx.x; s < nslots; s += kAggBlock) s_cnt[s] = 0u;
-  __syncthreads();
-  for_chunk_batches(idx, nnz, kc, [&](const int64_t*, const uint64_t* keys, const bool* ok) {
-#pragma unroll
-    for (int u = 0; u < kAggUnroll; ++u)
-      if (ok[u]) atomicAdd(&s_cnt[(unsigned)keys[u]], 1u);
-  });
-  __syncthreads();
+  const unsigned* row = choff + (size_t)blockIdx.x * nslots;
   for (unsigned s = threadIdx.x; s < nslots; s += kAggBlock) {
-    const unsigned c = s_cnt[s];
-    if (c) s_base[s] = atomicSub(&tab[s].start, c) - c;
     s_cnt[s] = 0u;
+    s_base[s] = row[s];
   }
   __syncthreads();
   for_chunk_batches(idx, nnz, kc, [&](const int64_t* e, const uint64_t* keys, const bool* ok) {

@@ -210,6 +210,9 @@ struct sptc_plan_s : Workspace {
   int32_t ydup = 0;
   int32_t dense = 0;
   int32_t y_agg = 0, x_agg = 0;  // small keys: LDS-aggregated count and scatter
+  unsigned* yhist = nullptr;     // their per-chunk histograms, then (key, chunk) positions
+  unsigned* xhist = nullptr;
+  unsigned long long* agg_total = nullptr;
   uint64_t ycells = 0;
   KeyUnpack ux{}, uy{};
 
@@ -376,22 +379,26 @@ int32_t yset_bits(const sptc_plan_s* P) { return P->bits_c + P->bits_fy <= 63 ? 
 sptc_status plan_group_y(sptc_plan_s* P, const sptc_coo* Y) {
   const hipStream_t s = P->stream;
   const uint64_t seed = P->opt.hash_seed;
+  sptc_status st;
+  if (P->y_agg && (st = P->allocate_n(agg_chunks(P->ny) * P->ytab_slots, &P->yhist))) return st;
   HIP_TRY(mark(P, s, SPTC_STAGE_Y_COUNT, 0));
   HIP_TRY(launch_fill_empty(P->ytab, P->ytab_slots, nullptr, s));
   if (P->y_agg)
-    HIP_TRY(launch_key_count_agg(Y->idx, P->ny, P->y_c, P->ytab, (unsigned)P->ytab_slots, &P->st->groups, s));
+    HIP_TRY(launch_key_count_agg(Y->idx, P->ny, P->y_c, P->ytab, (unsigned)P->ytab_slots, P->yhist, P->agg_total,
+                                 P->tile_sums, &P->st->groups, s));
   else
     HIP_TRY(launch_key_count(Y->idx, P->ny, P->y_c, P->ytab, P->ygeom, seed, P->max_probe_y, P->st,
                              &P->st->groups, P->num_cus, s));
   HIP_TRY(mark(P, s, SPTC_STAGE_Y_COUNT, 1));
   HIP_TRY(mark(P, s, SPTC_STAGE_Y_SCAN, 0));
-  HIP_TRY(launch_scan_y_table(P->ytab, P->ytab_slots, P->tile_sums, s));
+  if (!P->y_agg) HIP_TRY(launch_scan_y_table(P->ytab, P->ytab_slots, true, P->tile_sums, s));
   HIP_TRY(mark(P, s, SPTC_STAGE_Y_SCAN, 1));
   HIP_TRY(mark(P, s, SPTC_STAGE_Y_SCATTER, 0));
   if (P->yset) HIP_TRY(launch_fill_keys(P->yset, P->yset_slots, s));
   if (P->y_agg)
     HIP_TRY(launch_y_scatter_agg(Y->idx, Y->val, P->ny, P->y_c, P->y_f, P->yb, P->ytab, (unsigned)P->ytab_slots,
-                                 P->yg, P->yset, (uint64_t)P->yset_slots - 1, seed, yset_bits(P), P->st, s));
+                                 P->yhist, P->yg, P->yset, (uint64_t)P->yset_slots - 1, seed, yset_bits(P), P->st,
+                                 s));
   else
     HIP_TRY(launch_y_scatter(Y->idx, Y->val, P->ny, P->y_c, P->y_f, P->yb, P->ytab, P->ygeom, seed, P->max_probe_y,
                              P->yg, P->yset, (uint64_t)P->yset_slots - 1, yset_bits(P), P->st, P->num_cus, s));
@@ -442,17 +449,20 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
   if ((st = P->allocate_n(P->nx, &P->glist))) return st;
   if ((st = P->allocate_n(P->nx + 1, &P->dpos))) return st;
 
+  if (P->x_agg && (st = P->allocate_n(agg_chunks(P->nx) * P->xtab_slots, &P->xhist))) return st;
+
   HIP_TRY(mark(P, s, SPTC_STAGE_X_PROBE, 0));
   HIP_TRY(launch_fill_empty(P->xtab, P->xtab_slots, nullptr, s));
   if (P->x_agg)
-    HIP_TRY(launch_key_count_agg(X->idx, P->nx, P->x_f, P->xtab, (unsigned)P->xtab_slots, nullptr, s));
+    HIP_TRY(launch_key_count_agg(X->idx, P->nx, P->x_f, P->xtab, (unsigned)P->xtab_slots, P->xhist, P->agg_total,
+                                 P->tile_sums, nullptr, s));
   else
     HIP_TRY(launch_key_count(X->idx, P->nx, P->x_f, P->xtab, P->xgeom, seed, P->max_probe_x, P->st, nullptr,
                              P->num_cus, s));
-  HIP_TRY(launch_scan_x_table(P->xtab, P->xtab_slots, P->groups, P->tile_sums, P->st, s));
+  HIP_TRY(launch_scan_x_table(P->xtab, P->xtab_slots, P->groups, !P->x_agg, P->tile_sums, P->st, s));
   if (P->x_agg)
     HIP_TRY(launch_x_scatter_agg(X->idx, X->val, P->nx, P->x_f, P->x_c, P->xb, P->xtab, (unsigned)P->xtab_slots,
-                                 P->ytab, P->ygeom, P->max_probe_y, seed, P->xr, P->st, s));
+                                 P->xhist, P->ytab, P->ygeom, P->max_probe_y, seed, P->xr, P->st, s));
   else
     HIP_TRY(launch_x_scatter(X->idx, X->val, P->nx, P->x_f, P->x_c, P->xb, P->xtab, P->xgeom, P->max_probe_x,
                              P->ytab, P->ygeom, P->max_probe_y, seed, P->xr, P->st, P->num_cus, s));
@@ -550,7 +560,9 @@ sptc_status plan_body(sptc_plan_s* P, const sptc_coo* X, const sptc_coo* Y, cons
     if ((st = P->allocate_n(P->ny, &P->ykey16))) return st;
     if ((st = P->allocate_n(P->ny, &P->yval))) return st;
   }
-  const int64_t tiles = std::max<int64_t>({scan_tiles(P->ytab_slots), scan_tiles(P->xtab_slots), scan_tiles(P->nx)});
+  const int64_t tiles = std::max<int64_t>({scan_tiles(P->ytab_slots), scan_tiles(P->xtab_slots), scan_tiles(P->nx),
+                                          scan_tiles(agg_chunks(P->ny) * P->ytab_slots),
+                                          scan_tiles(agg_chunks(P->nx) * P->xtab_slots)});
   if ((st = P->allocate_n(2 * (tiles + 1), &P->tile_sums))) return st;  // room for pair-valued scans
   // Y coordinate set (grouped mode): finds repeated Y coordinates, which the
   // direct class cannot have.  With a dense Y free key the run sort finds
@@ -561,6 +573,7 @@ sptc_status plan_body(sptc_plan_s* P, const sptc_coo* X, const sptc_coo* Y, cons
     if ((st = P->allocate_n(P->yset_slots, &P->yset))) return st;
   }
   if ((st = P->allocate_n(1, &P->st))) return st;
+  if ((st = P->allocate_n(1, &P->agg_total))) return st;
   if ((st = P->allocate_n(2, &P->readback))) return st;
   HIP_TRY(hipMemsetAsync(P->st, 0, sizeof(DevStatus), P->stream));
   if ((st = plan_group_y(P, Y))) return st;

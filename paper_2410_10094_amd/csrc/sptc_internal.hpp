@@ -36,6 +36,9 @@ struct KeyPack {
 // also aggregated per workgroup in LDS before touching the table.
 constexpr int kIdentBits = 16;
 constexpr int kAggBits = 13;
+constexpr int kAggChunk = 4096;  // entries per workgroup of the aggregated count and placement
+
+inline int64_t agg_chunks(int64_t nnz) { return (nnz + kAggChunk - 1) / kAggChunk; }
 
 // Coordinate bounds of one tensor (validation).
 struct Bounds {
@@ -143,9 +146,14 @@ hipError_t launch_key_count(const int32_t* idx, int64_t nnz, KeyPack kc, YSlot* 
                             int32_t max_probe, DevStatus* st, unsigned long long* distinct, int num_cus,
                             hipStream_t stream);
 
-// The same for a direct-addressed table of nslots <= 2^kAggBits slots,
-// counting per workgroup in LDS first.
+// The same for a direct-addressed table of nslots <= 2^kAggBits slots:
+// each workgroup histograms a chunk of kAggChunk entries in LDS into row
+// `chunk` of hist [agg_chunks(nnz)][nslots]; a key-major scan turns the rows
+// into each (key, chunk)'s first position, and the table gets every key's
+// count and run start (no global atomics).  tile_sums: scan scratch for
+// agg_chunks(nnz) * nslots elements; total: one device u64.
 hipError_t launch_key_count_agg(const int32_t* idx, int64_t nnz, KeyPack kc, YSlot* tab, unsigned nslots,
+                                unsigned* hist, unsigned long long* total, unsigned long long* tile_sums,
                                 unsigned long long* distinct, hipStream_t stream);
 
 // Exclusive scan support: tile sums need ceil(n / kScanTile) u64 entries.
@@ -154,8 +162,10 @@ constexpr int kScanItems = 16;
 constexpr int64_t kScanTile = (int64_t)kScanBlock * kScanItems;
 inline int64_t scan_tiles(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
 
-// Y table: count field -> inclusive end offset stored in `start`.
-hipError_t launch_scan_y_table(YSlot* tab, int64_t nslots, unsigned long long* tile_sums, hipStream_t stream);
+// Y table: count field -> offset of the key's run stored in `start`: its end
+// (run_end, for placement that takes and decrements) or its beginning.
+hipError_t launch_scan_y_table(YSlot* tab, int64_t nslots, bool run_end, unsigned long long* tile_sums,
+                               hipStream_t stream);
 
 // Also inserts every full Y coordinate ((contracting key << bits_y) | free
 // key) into yset (kEmpty-filled, yset_mask + 1 slots) when yset is given, and
@@ -166,11 +176,12 @@ hipError_t launch_y_scatter(const int32_t* yidx, const double* yval, int64_t nnz
                             hipStream_t stream);
 
 // Y scatter for a direct-addressed Y table of nslots <= 2^kAggBits slots:
-// each workgroup counts its entries per key in LDS, reserves one run per key
-// and places its entries inside the runs.
+// each workgroup places its chunk at the run starts plus the chunk offsets
+// (choff: the hist rows left by launch_key_count_agg).
 hipError_t launch_y_scatter_agg(const int32_t* yidx, const double* yval, int64_t nnz, KeyPack kc, KeyPack kf,
-                                Bounds b, YSlot* tab, unsigned nslots, YEntry* yg, unsigned long long* yset,
-                                uint64_t yset_mask, uint64_t seed, int32_t bits_y, DevStatus* st, hipStream_t stream);
+                                Bounds b, const YSlot* tab, unsigned nslots, const unsigned* choff, YEntry* yg,
+                                unsigned long long* yset, uint64_t yset_mask, uint64_t seed, int32_t bits_y,
+                                DevStatus* st, hipStream_t stream);
 
 // Sets n 8-byte words to kEmpty.
 hipError_t launch_fill_keys(unsigned long long* keys, int64_t n, hipStream_t stream);
@@ -206,15 +217,16 @@ hipError_t launch_compact_grouped(const ZSlot* tab, int64_t nslots, const GroupR
 // ---- grouped path (grouped.hip) ----
 
 // X table (keyed by X free key) -> dense group records; the table's start
-// field becomes each group's end offset for the scatter.
-hipError_t launch_scan_x_table(YSlot* tab, int64_t nslots, GroupRec* groups, void* tile_sums, DevStatus* st,
-                               hipStream_t stream);
+// field becomes each group's end (run_end) or start offset for the scatter.
+hipError_t launch_scan_x_table(YSlot* tab, int64_t nslots, GroupRec* groups, bool run_end, void* tile_sums,
+                               DevStatus* st, hipStream_t stream);
 
 // X scatter for a direct-addressed X table of nslots <= 2^kAggBits slots,
 // aggregated per workgroup in LDS like the Y scatter.
 hipError_t launch_x_scatter_agg(const int32_t* xidx, const double* xval, int64_t nnz, KeyPack kf, KeyPack kc,
-                                Bounds b, YSlot* xtab, unsigned nslots, const YSlot* ytab, TabGeom yg,
-                                int32_t max_probe_y, uint64_t seed, XRec* xr, DevStatus* st, hipStream_t stream);
+                                Bounds b, const YSlot* xtab, unsigned nslots, const unsigned* choff, const YSlot* ytab,
+                                TabGeom yg, int32_t max_probe_y, uint64_t seed, XRec* xr, DevStatus* st,
+                                hipStream_t stream);
 
 // Scatter X into its groups, probing Y's table for every entry.
 hipError_t launch_x_scatter(const int32_t* xidx, const double* xval, int64_t nnz, KeyPack kf, KeyPack kc, Bounds b,
