@@ -213,6 +213,17 @@ def sub_batches(draws, budget):
     return sched.make_batches(draws, sched.estimate_products, klass, budget)
 
 
+def release_cached_memory():
+    """Give memory cached by torch and by the library's pool back to the
+    device between legs, so that each leg starts from the same state."""
+    import torch
+
+    import paper_2410_10094_amd as sptc
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    sptc.pool_trim(0)
+
+
 def upload(draws):
     import torch
 
@@ -543,6 +554,7 @@ def main():
         lf = tuned["load_factor"] if tuned else 1 / 1.3
         batched = run_batched(draws, dev, max(1, args.steps // 5), 1, budget, lf)
         batched["autotune"] = tuned
+        release_cached_memory()
         batched["workload"] = (f"{len(draws)} draws: orders 3-5, dims U[32,4096], nnz log-U[1e3,1e6], "
                                "1-2 contracted pairs, FP64 U[-1,1)")
         if args.serve > 0:

@@ -16,16 +16,19 @@
  * The output is COO (section 2.1, Fig. 1) in no particular order: the method
  * never sorts (section 4.1.3), and a sorted output is optional (section 1).
  *
- * Method (sections 4.1-4.3 and the footnote to section 4.4): Y's nonzeros are
- * grouped by their contracting-mode key in a device open-addressing hash with
- * linear probing (section 2.3.1; the probing table for Y of section 4.2),
- * counted, prefix-summed and scattered into a grouped array (the counting
- * sort of section 4.1.1 and the array form of Y of section 4.2).  Every X
- * nonzero probes that table for its group; the exact number of products P
- * (the upper bound of section 4.3, taken over all of X) sizes an output hash
- * keyed by the packed free coordinates.  Products are accumulated there with
- * FP64 atomics and the table is compacted to COO by count, prefix sum and fill
- * (writeback, section 2.5).
+ * Method (sections 4.1-4.3).  Y's nonzeros are grouped by their
+ * contracting-mode key in a device open-addressing table (section 2.3.1; the
+ * probing table for Y of section 4.2): counted, prefix-summed and placed in
+ * a grouped array (the counting sort of section 4.1.1 and the array form of
+ * Y of section 4.2).  X's nonzeros are grouped the same way by their free
+ * key (section 4.1), and each X entry looks up the run of Y entries that
+ * share its contracting key.  The product count of a group (the bound of
+ * section 4.3) chooses how the group accumulates: single-entry groups write
+ * every product as an output; small groups accumulate in a wave's LDS hash,
+ * large ones in a workgroup's dense LDS array or LDS hash; groups too large
+ * for LDS go to a device-memory hash (the footnote to section 4.4), compacted
+ * by count, prefix sum and fill (writeback, section 2.5).  The GLOBAL mode
+ * sends every product to that device hash.
  *
  * Conventions
  *  - Modes and coordinates are 0-based; 0 <= i_k < I_k (section 2.1.1).
@@ -277,6 +280,15 @@ SPTC_API sptc_status sptc_batch_execute(sptc_batch_t batch, int32_t* out_idx, do
                                         void* stream);
 
 SPTC_API void sptc_batch_free(sptc_batch_t batch);
+
+/* ---- Memory ----
+ *
+ * Without a caller allocator, workspace comes from the current device's
+ * stream-ordered pool, configured to keep freed blocks cached for the next
+ * plan.  sptc_pool_trim returns cached memory above keep_bytes to the
+ * device (hipMemPoolTrimTo); memory of live plans is unaffected.  For
+ * callers that switch between workloads with different footprints. */
+SPTC_API sptc_status sptc_pool_trim(size_t keep_bytes);
 
 #ifdef __cplusplus
 }

@@ -19,7 +19,7 @@ from typing import Optional, Sequence
 from . import binding as _b
 from .binding import SptcError
 
-__all__ = ["DeviceCoo", "Plan", "plan", "contract", "Batch", "batch", "SptcError", "default_options"]
+__all__ = ["DeviceCoo", "Plan", "plan", "contract", "Batch", "batch", "SptcError", "default_options", "pool_trim"]
 
 
 def _torch():
@@ -100,6 +100,23 @@ class _TorchAllocator:
         self.struct = _b.Allocator(self._alloc, self._release, None)
 
 
+def _resolve_allocator(allocator, device):
+    """(keep-alive object, sptc_allocator pointer or None) for an allocator
+    argument: "pool" (the device's stream-ordered pool), "torch" (torch's
+    caching allocator) or any object whose ``struct`` is a binding.Allocator
+    (kept alive as long as the plan or batch)."""
+    if isinstance(allocator, str):
+        if allocator == "pool":
+            return None, None
+        if allocator == "torch":
+            a = _TorchAllocator(device.index if device.index is not None else _torch().cuda.current_device())
+            return a, ctypes.byref(a.struct)
+        raise ValueError("allocator must be 'pool', 'torch' or an object with an Allocator struct")
+    if not isinstance(getattr(allocator, "struct", None), _b.Allocator):
+        raise ValueError("allocator must be 'pool', 'torch' or an object with an Allocator struct")
+    return allocator, ctypes.byref(allocator.struct)
+
+
 class Plan:
     """A contraction plan (``sptc_plan``): Y grouped, X probed, products
     counted and the output hash sized.  ``execute`` may run any number of
@@ -118,14 +135,7 @@ class Plan:
         cY, ky = Y.as_c()
         acx, acy = _b.int_array(self.cx), _b.int_array(self.cy)
         opt = options if options is not None else _b.default_options()
-        self._allocator = None
-        alloc_ptr = None
-        if allocator == "torch":
-            self._allocator = _TorchAllocator(X.val.device.index if X.val.device.index is not None
-                                              else torch.cuda.current_device())
-            alloc_ptr = ctypes.byref(self._allocator.struct)
-        elif allocator != "pool":
-            raise ValueError("allocator must be 'pool' or 'torch'")
+        self._allocator, alloc_ptr = _resolve_allocator(allocator, X.val.device)
         h = ctypes.c_void_p()
         self._h = None
         _b.check(lib.sptc_plan(ctypes.byref(h), ctypes.byref(cX), ctypes.byref(cY), len(self.cx), acx, acy,
@@ -274,14 +284,7 @@ class Batch:
             cxp[b] = ctypes.cast(acx, ctypes.c_void_p)
             cyp[b] = ctypes.cast(acy, ctypes.c_void_p)
         opt = options if options is not None else _b.default_options()
-        self._allocator = None
-        alloc_ptr = None
-        if allocator == "torch":
-            self._allocator = _TorchAllocator(self.device.index if self.device.index is not None
-                                              else torch.cuda.current_device())
-            alloc_ptr = ctypes.byref(self._allocator.struct)
-        elif allocator != "pool":
-            raise ValueError("allocator must be 'pool' or 'torch'")
+        self._allocator, alloc_ptr = _resolve_allocator(allocator, self.device)
         h = ctypes.c_void_p()
         self._h = None
         _b.check(lib.sptc_batch_plan(ctypes.byref(h), n, xs, ys, nc, cxp, cyp, ctypes.byref(opt), alloc_ptr,
@@ -356,6 +359,12 @@ class Batch:
         idx, val, nnz = self.allocate_outputs()
         self.execute_into(idx, val, nnz, stream)
         return self.views(idx, val, nnz.cpu().tolist())
+
+
+def pool_trim(keep_bytes: int = 0):
+    """Return workspace memory cached in the device's stream-ordered pool
+    (above keep_bytes) to the device (sptc_pool_trim)."""
+    _b.check(_b.load().sptc_pool_trim(int(keep_bytes)))
 
 
 def batch(problems: Sequence[tuple], options=None, allocator: str = "pool", stream=None) -> Batch:

@@ -21,7 +21,7 @@ EXPORTS = (
     "sptc_default_options", "sptc_plan", "sptc_plan_info", "sptc_execute", "sptc_plan_status", "sptc_free",
     "sptc_status_string", "sptc_last_error", "sptc_plan_y_groups", "sptc_plan_y_grouped", "sptc_plan_x_counts",
     "sptc_plan_set_stage_events", "sptc_plan_x_groups", "sptc_batch_plan", "sptc_batch_sizes", "sptc_batch_info",
-    "sptc_batch_execute", "sptc_batch_free",
+    "sptc_batch_execute", "sptc_batch_free", "sptc_pool_trim",
 )
 
 BATCH_MAX = 4096
@@ -119,6 +119,8 @@ def load():
     lib.sptc_batch_execute.restype = st
     lib.sptc_batch_free.argtypes = [P]
     lib.sptc_batch_free.restype = None
+    lib.sptc_pool_trim.argtypes = [ctypes.c_size_t]
+    lib.sptc_pool_trim.restype = st
     _lib = lib
     return lib
 

@@ -1215,6 +1215,15 @@ sptc_status sptc_batch_execute(sptc_batch_t B, int32_t* out_idx, double* out_val
   return execute_plan(B->inner, out_idx, out_val, 0, B->tnnz, static_cast<hipStream_t>(stream), &bx);
 }
 
+sptc_status sptc_pool_trim(size_t keep_bytes) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  hipMemPool_t pool;
+  HIP_TRY(hipDeviceGetDefaultMemPool(&pool, dev));
+  HIP_TRY(hipMemPoolTrimTo(pool, keep_bytes));
+  return SPTC_OK;
+}
+
 void sptc_batch_free(sptc_batch_t B) {
   if (!B) return;
   (void)hipStreamSynchronize(B->stream);

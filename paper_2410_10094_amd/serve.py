@@ -16,10 +16,14 @@ of its batch's execution on the device clock.
 
 Before planning, the loop also checks that an estimate of the batch's own
 workspace (from its nonzero counts) fits, so that a batch waiting for memory
-does not hold more than the budget allows.
+does not hold more than the budget allows.  A backend may also decline to
+plan a batch for lack of room (its plan returns None): the members go back
+to the queue in arrival order and planning resumes after the next batch in
+flight is released.
 
 The device work goes through a backend (TorchBackend: the HIP library on a
-GPU); the policy itself is plain host code."""
+GPU, all of its memory in one preallocated arena); the policy itself is
+plain host code."""
 from __future__ import annotations
 
 import collections
@@ -88,12 +92,72 @@ class RingArena:
             raise RuntimeError("arena chunks must be released oldest first")
         self.chunks.popleft()
 
+    def release_last(self, start: int):
+        """Gives back the newest chunk (undoing an allocation that failed
+        part-way)."""
+        if not self.chunks or self.chunks[-1][0] != start:
+            raise RuntimeError("only the newest arena chunk can be released last")
+        self.chunks.pop()
+
+    @staticmethod
+    def rounded(n: int) -> int:
+        return (int(n) + RingArena.ALIGN - 1) // RingArena.ALIGN * RingArena.ALIGN
+
+
+class ArenaAllocator:
+    """sptc_allocator over a RingArena for one batch: every buffer the
+    library asks for while planning comes from the arena, in order.  The
+    library's per-buffer releases are ignored (a buffer it frees early stays
+    reserved); the owner gives all chunks back together, oldest first, when
+    the batch is released, or newest first when planning failed."""
+
+    def __init__(self, arena: RingArena, base_ptr: int):
+        from . import binding as B
+        self.arena = arena
+        self.chunks: List[int] = []
+        self.bytes = 0
+
+        def alloc(nbytes, stream, ctx):
+            start = arena.alloc(nbytes)
+            if start is None:
+                return None  # the library reports SPTC_ERR_OUT_OF_MEMORY
+            self.chunks.append(start)
+            self.bytes += RingArena.rounded(nbytes)
+            return base_ptr + start
+
+        def release(ptr, nbytes, stream, ctx):
+            pass
+
+        self._alloc = B.ALLOC_FN(alloc)
+        self._release = B.RELEASE_FN(release)
+        self.struct = B.Allocator(self._alloc, self._release, None)
+
+    def take(self, nbytes: int) -> Optional[int]:
+        """An extra chunk (the outputs) after the library's buffers."""
+        start = self.arena.alloc(nbytes)
+        if start is not None:
+            self.chunks.append(start)
+            self.bytes += RingArena.rounded(nbytes)
+        return start
+
+    def give_back(self):
+        for start in self.chunks:
+            self.arena.release(start)
+        self.chunks = []
+
+    def undo(self):
+        for start in reversed(self.chunks):
+            self.arena.release_last(start)
+        self.chunks = []
+
 
 class TorchBackend:
     """Runs batches with sptc_batch_* on one GPU: a plan stream and an
-    execute stream (both at the default priority).  Outputs come from one
-    preallocated ring arena; the batches' own workspace from the library's
-    stream-ordered pool."""
+    execute stream (both at the default priority).  One preallocated ring
+    arena holds every batch's memory: the library's workspace (through an
+    ArenaAllocator) and then the outputs, both taken when the batch is
+    planned, so that serving makes no device allocation at all and a batch
+    that has been planned can always launch."""
 
     def __init__(self, arena_bytes: int, keep_results: bool = False, options=None):
         import torch
@@ -122,31 +186,53 @@ class TorchBackend:
         return 96 * sum(r.X.nnz + r.Y.nnz for r in members) + (1 << 20)
 
     def plan(self, members: List[Request]):
-        from . import Batch
-        b = Batch([(r.X, r.Y, r.cx, r.cy) for r in members], options=self.options, stream=self.plan_stream)
-        for r, it in zip(members, b.items):
-            r.products = it["products"]
-        return b, b.workspace_bytes + b.output_bytes()
-
-    def launch(self, b):
-        """Enqueues the batch; None when the arena has no room yet."""
-        torch = self.torch
+        """(handle, bytes held) or None when the arena has no room for the
+        batch until an earlier batch is released."""
+        from . import Batch, SptcError
+        from . import binding as B
+        al = ArenaAllocator(self.arena, self.buf.data_ptr())
+        try:
+            b = Batch([(r.X, r.Y, r.cx, r.cy) for r in members], options=self.options, allocator=al,
+                      stream=self.plan_stream)
+        except SptcError as e:
+            al.undo()  # the library synchronised its stream before reporting
+            if e.status == B.ERR_OUT_OF_MEMORY:
+                return None
+            raise
         a = RingArena.ALIGN
         rnd = lambda n: (n + a - 1) // a * a
         parts = [rnd(4 * max(b.idx_elems, 1)), rnd(8 * max(b.val_elems, 1)), rnd(8 * b.count)]
-        start = self.arena.alloc(sum(parts))
+        start = al.take(sum(parts))
         if start is None:
+            b.close()
+            al.undo()
             return None
         offs = [start]
         for n in parts[:-1]:
             offs.append(offs[-1] + n)
-        idx = self.buf[offs[0]:offs[0] + 4 * max(b.idx_elems, 1)].view(torch.int32)
-        val = self.buf[offs[1]:offs[1] + 8 * max(b.val_elems, 1)].view(torch.float64)
-        nnz = self.buf[offs[2]:offs[2] + 8 * b.count].view(torch.int64)
+        torch = self.torch
+        b.serve_out = (self.buf[offs[0]:offs[0] + 4 * max(b.idx_elems, 1)].view(torch.int32),
+                       self.buf[offs[1]:offs[1] + 8 * max(b.val_elems, 1)].view(torch.float64),
+                       self.buf[offs[2]:offs[2] + 8 * b.count].view(torch.int64))
+        b.serve_alloc = al
+        for r, it in zip(members, b.items):
+            r.products = it["products"]
+        return b, al.bytes
+
+    def launch(self, b):
+        """Enqueues the batch (its memory is already held)."""
+        torch = self.torch
+        idx, val, nnz = b.serve_out
         b.execute_into(idx, val, nnz, stream=self.exec_stream)
+        # the counts travel to pinned host memory behind the batch, so that a
+        # finished batch is checked without waiting on the execute stream
+        # (which by then may hold the next batch)
+        nnz_host = torch.empty(b.count, dtype=torch.int64, pin_memory=True)
+        with torch.cuda.stream(self.exec_stream):
+            nnz_host.copy_(nnz, non_blocking=True)
         ev = torch.cuda.Event(enable_timing=True)
         ev.record(self.exec_stream)
-        return ((idx, val, nnz), ev, start)
+        return ((idx, val, nnz, nnz_host), ev)
 
     def done(self, token) -> bool:
         return token[1].query()
@@ -158,21 +244,25 @@ class TorchBackend:
         """Kept results are copied out of the arena, which is reused."""
         if not self.keep_results:
             return
-        idx, val, nnz = token[0]
-        for r, (i, v) in zip(members, b.views(idx, val, nnz.cpu().tolist())):
-            r.result = (i.clone(), v.clone())
+        torch = self.torch
+        idx, val, _, nnz_host = token[0]
+        with torch.cuda.stream(self.exec_stream):
+            for r, (i, v) in zip(members, b.views(idx, val, nnz_host.tolist())):
+                r.result = (i.clone(), v.clone())
+        # the next plan may reuse this part of the arena on the plan stream
+        ev = torch.cuda.Event()
+        ev.record(self.exec_stream)
+        self.plan_stream.wait_event(ev)
 
     def check(self, b, token):
-        """Raises if any member reported an error status."""
-        nnz = token[0][2]
-        with self.torch.cuda.stream(self.exec_stream):
-            bad = int((nnz < 0).sum().item())
+        """Raises if any member reported an error status (host copy, no wait)."""
+        bad = sum(1 for n in token[0][3].tolist() if n < 0)
         if bad:
             raise RuntimeError(f"{bad} contractions of a batch reported an error")
 
     def release(self, b, token):
         b.close()
-        self.arena.release(token[2])
+        b.serve_alloc.give_back()
 
 
 class Server:
@@ -230,6 +320,7 @@ class Server:
         queue: Deque[Request] = collections.deque()
         inflight: List[_Batch] = []
         staged: Optional[_Batch] = None
+        plan_blocked = False
         done: List[Request] = []
         t0 = be.start()
         while pending or queue or inflight or staged:
@@ -248,16 +339,28 @@ class Server:
                 inflight.remove(b)
                 done.extend(b.members)
                 progressed = True
-            if staged is None and queue and len(inflight) < self.max_inflight:
+                plan_blocked = False
+            if staged is None and queue and len(inflight) < self.max_inflight and not plan_blocked:
                 picked = self._select(queue)
                 if self.used + be.estimate([queue[k] for k in picked]) <= self.budget or not inflight:
                     members = self._remove(queue, picked)
-                    handle, need = be.plan(members)
-                    if need > self.budget:
-                        raise RuntimeError(f"a batch of {len(members)} needs {need} bytes, above the budget "
-                                           f"{self.budget}; lower batch_products")
-                    staged = _Batch(members, handle, need)
-                    progressed = True
+                    planned = be.plan(members)
+                    if planned is None:
+                        # no room until a batch in flight is released
+                        if not inflight:
+                            raise RuntimeError(f"a batch of {len(members)} does not fit the device memory of "
+                                               f"{self.budget} bytes even alone; lower batch_products")
+                        queue.extend(members)
+                        queue = collections.deque(sorted(queue, key=lambda r: (r.arrival, r.rid)))
+                        plan_blocked = True
+                        self.waits_for_memory += 1
+                    else:
+                        handle, need = planned
+                        if need > self.budget:
+                            raise RuntimeError(f"a batch of {len(members)} needs {need} bytes, above the budget "
+                                               f"{self.budget}; lower batch_products")
+                        staged = _Batch(members, handle, need)
+                        progressed = True
                 else:
                     self.waits_for_memory += 1
             if staged is not None and len(inflight) < self.max_inflight:

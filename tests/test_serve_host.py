@@ -128,6 +128,71 @@ def test_in_flight_batches_never_exceed_the_limit():
     assert len(be.launched) == srv.batches
 
 
+class DecliningBackend(FakeBackend):
+    """Holds each batch's bytes from plan to release in a ring arena of
+    `capacity` bytes, as the GPU backend does; plan returns None when the
+    arena has no room."""
+
+    def __init__(self, capacity, **kw):
+        super().__init__(**kw)
+        self.arena = serve.RingArena(capacity)
+        self.declined = 0
+
+    def plan(self, members):
+        need = sum(r.need_bytes for r in members)
+        start = self.arena.alloc(need)
+        if start is None:
+            self.declined += 1
+            return None
+        handle, _ = super().plan(members)
+        return (handle, start), serve.RingArena.rounded(need)
+
+    def launch(self, handle):
+        return super().launch(handle[0])
+
+    def release(self, b, token):
+        self.arena.release(b[1])
+
+
+def test_declined_plans_are_retried_in_arrival_order():
+    reqs = _requests(300, 200_000, 11)
+    by_id = {r.rid: r for r in reqs}
+    be = DecliningBackend(capacity=2 << 20, sec_per_product=1e-9)
+    # at most 16 members of at most 100 KB: every batch fits the arena alone
+    srv = serve.Server(be, budget_bytes=1 << 30, batch_products=1e7, max_batch=16, max_inflight=3,
+                       bytes_per_product=None)
+    done = srv.run(reqs)
+    assert sorted(r.rid for r in done) == list(range(300))
+    assert be.declined > 0 and srv.waits_for_memory >= be.declined
+    assert not be.arena.chunks
+    for ids in be.planned:
+        assert ids == sorted(ids) and len({by_id[i].klass for i in ids}) == 1
+    # FIFO within a class survives the requeueing: each class is planned in arrival order
+    for k in ("dense", "hash"):
+        seq = [i for ids in be.planned for i in ids if by_id[i].klass == k]
+        assert seq == sorted(seq)
+
+
+def test_declined_plan_with_nothing_in_flight_is_an_error():
+    reqs = _requests(3, 1000, 12)
+    for r in reqs:
+        r.need_bytes = 10 << 20
+    with pytest.raises(RuntimeError, match="even alone"):
+        serve.Server(DecliningBackend(capacity=1 << 20), budget_bytes=1 << 30).run(reqs)
+
+
+def test_arena_allocator_undo_and_give_back():
+    a = serve.RingArena(1 << 16)
+    first = a.alloc(1000)
+    s1, s2 = a.alloc(300), a.alloc(5000)
+    a.release_last(s2)
+    a.release_last(s1)
+    with pytest.raises(RuntimeError):
+        a.release_last(s1)
+    assert a.alloc(256) == serve.RingArena.rounded(1000)
+    a.release(first)
+
+
 def test_batch_above_the_budget_is_an_error():
     reqs = _requests(5, 1000, 5)
     for r in reqs:
