@@ -127,7 +127,7 @@ def time_oracle(p, products_total, max_seconds=25.0):
             "output_nnz_per_s": r.nnz / dt}
 
 
-def run_workload(name, steps, warmup, with_events=True, mode="grouped"):
+def run_workload(name, steps, warmup, with_events=True, mode="grouped", block_mfma=-1):
     import torch
 
     import paper_2410_10094_amd as sptc
@@ -141,14 +141,14 @@ def run_workload(name, steps, warmup, with_events=True, mode="grouped"):
 
     mode_id = {"grouped": B.MODE_GROUPED, "global": B.MODE_GLOBAL}[mode]
     # Output buffers are sized once (the bound is the same every step).
-    with sptc.plan(X, Y, p.cx, p.cy, options=sptc.default_options(mode=mode_id)) as pl0:
+    with sptc.plan(X, Y, p.cx, p.cy, options=sptc.default_options(mode=mode_id, block_mfma=block_mfma)) as pl0:
         out_idx, out_val, out_nnz, cap = pl0.allocate_outputs()
         products = pl0.products
         out_slots = pl0.out_table_slots
         info = dict(mode=mode, y_groups=pl0.y_groups, y_table_slots=pl0.y_table_slots, out_table_slots=out_slots,
                     workspace_bytes=pl0.workspace_bytes, key_bits=pl0.key_bits, x_groups=pl0.x_groups,
                     group_classes=pl0.group_classes, direct_groups=pl0.group_classes["direct"],
-                    direct_products=pl0.direct_products)
+                    direct_products=pl0.direct_products, block_mfma=pl0.block_mfma)
 
     nst = len(B.STAGES)
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2 * nst)] for _ in range(steps)]
@@ -159,7 +159,7 @@ def run_workload(name, steps, warmup, with_events=True, mode="grouped"):
     assert all(e.cuda_event for row in evs for e in row)
 
     def step(k=None):
-        opt = sptc.default_options(mode=mode_id)
+        opt = sptc.default_options(mode=mode_id, block_mfma=block_mfma)
         if k is not None and with_events:
             opt.stage_events = ctypes.cast(ev_arrays[k], ctypes.POINTER(ctypes.c_void_p))
         pl = sptc.plan(X, Y, p.cx, p.cy, options=opt)
@@ -500,6 +500,8 @@ def main():
                     help="only run a plain device copy of MIB MiB (known bytes for scaling HBM counters) and exit")
     ap.add_argument("--mode", default="grouped", choices=["grouped", "global"],
                     help="accumulation strategy: per-X-group LDS tables (default) or one global hash")
+    ap.add_argument("--block-mfma", type=int, default=-1, choices=[-1, 0, 1],
+                    help="dense block class on the FP64 matrix cores: -1 the plan's cost rule, 0 never, 1 when eligible")
     ap.add_argument("--batched", type=int, default=512, metavar="COUNT",
                     help="draws of the batched workload timed per-call and batched (0: skip)")
     ap.add_argument("--batch-budget", type=float, default=1.0e9,
@@ -540,11 +542,12 @@ def main():
         print(json.dumps({"calibrate_copy_bytes_read": n * 8, "calibrate_copy_bytes_written": n * 8, "launches": 3}))
         return
 
-    r = run_workload(args.workload, args.steps, args.warmup, mode=args.mode)
+    r = run_workload(args.workload, args.steps, args.warmup, mode=args.mode, block_mfma=args.block_mfma)
     p = r["problem"]
     also = []
     for name in [a for a in args.also.split(",") if a and a != args.workload]:
-        also.append(summary(name, run_workload(name, max(3, args.steps // 2), max(1, args.warmup), mode=args.mode)))
+        also.append(summary(name, run_workload(name, max(3, args.steps // 2), max(1, args.warmup), mode=args.mode,
+                                               block_mfma=args.block_mfma)))
 
     batched = served = None
     if draws:

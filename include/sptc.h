@@ -27,8 +27,10 @@
  * every product as an output; small groups accumulate in a wave's LDS hash,
  * large ones in a workgroup's dense LDS array or LDS hash; groups too large
  * for LDS go to a device-memory hash (the footnote to section 4.4), compacted
- * by count, prefix sum and fill (writeback, section 2.5).  The GLOBAL mode
- * sends every product to that device hash.
+ * by count, prefix sum and fill (writeback, section 2.5).  When X and Y are
+ * dense enough, the large groups with a dense Y free key may instead run as
+ * a dense FP64 product on the matrix cores (sptc_options.block_mfma).  The
+ * GLOBAL mode sends every product to that device hash.
  *
  * Conventions
  *  - Modes and coordinates are 0-based; 0 <= i_k < I_k (section 2.1.1).
@@ -148,6 +150,12 @@ typedef struct sptc_options {
                                 stream before stage s and entry 2s+1 after it (NULL entries skipped);
                                 the caller owns the events and keeps the array alive */
   int32_t mode;              /* sptc_mode; default SPTC_MODE_GROUPED */
+  int32_t block_mfma;        /* grouped mode, dense Y free key, sptc_plan only: run the block class
+                                as a dense product on the FP64 matrix cores.  -1 (default): when
+                                eligible and rows x columns x runs is at most 8x the class's
+                                products; 0: never; 1: whenever eligible.  Eligible: every value of
+                                the class and of Y finite, and dense X and Y panels of at most 8 GiB.
+                                sptc_info.block_mfma reports the choice. */
 } sptc_options;
 
 /* Sizes fixed by sptc_plan. */
@@ -166,6 +174,7 @@ typedef struct sptc_info {
   int64_t wave_groups, block_groups, global_groups;  /* grouped mode: groups per accumulation class */
   int64_t direct_groups;                   /* grouped mode: single-entry groups written directly */
   int64_t direct_products;                 /* their products (= their outputs) */
+  int32_t block_mfma;                      /* 1: the block class runs on the matrix cores */
 } sptc_info;
 
 typedef struct sptc_plan_s* sptc_plan_t;

@@ -157,6 +157,7 @@ class Plan:
         self.group_classes = dict(direct=info.direct_groups, wave=info.wave_groups, block=info.block_groups,
                                   global_=info.global_groups)
         self.direct_products = info.direct_products
+        self.block_mfma = bool(info.block_mfma)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -40,7 +40,8 @@ class Coo(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("load_factor", ctypes.c_double), ("validate", ctypes.c_int32), ("max_probe", ctypes.c_int32),
                 ("hash_seed", ctypes.c_uint64), ("out_table_slots", ctypes.c_int64),
-                ("stage_events", ctypes.POINTER(ctypes.c_void_p)), ("mode", ctypes.c_int32)]
+                ("stage_events", ctypes.POINTER(ctypes.c_void_p)), ("mode", ctypes.c_int32),
+                ("block_mfma", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -51,7 +52,7 @@ class Info(ctypes.Structure):
                 ("key_bits_x_free", ctypes.c_int32), ("key_bits_y_free", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("x_groups", ctypes.c_int64), ("wave_groups", ctypes.c_int64), ("block_groups", ctypes.c_int64),
                 ("global_groups", ctypes.c_int64), ("direct_groups", ctypes.c_int64),
-                ("direct_products", ctypes.c_int64)]
+                ("direct_products", ctypes.c_int64), ("block_mfma", ctypes.c_int32)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)

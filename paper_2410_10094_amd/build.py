@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB_PATH = os.path.join(HERE, "libsptc.so")
 SOURCES = [os.path.join(CSRC, "kernels.hip"), os.path.join(CSRC, "grouped.hip"), os.path.join(CSRC, "batch.hip"),
-           os.path.join(CSRC, "sptc.cpp")]
+           os.path.join(CSRC, "block_mfma.hip"), os.path.join(CSRC, "sptc.cpp")]
 HEADERS = [os.path.join(CSRC, "sptc_internal.hpp"), os.path.join(CSRC, "prim.hpp"), os.path.join(ROOT, "include", "sptc.h")]
 ARCH = "gfx950"
 
@@ -30,6 +30,9 @@ HIPCC_FLAGS = [
     "-munsafe-fp-atomics",
     # no packed FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA operands and accumulators in VGPRs: without it the FP64 MFMA
+    # accumulators are copied between AGPRs and VGPRs around every step
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-fvisibility=hidden",
 ]
 

@@ -1,0 +1,383 @@
+// Block class on the matrix cores.
+//
+// With a dense Y free key (at most kDenseBits bits) and one contraction, the
+// block class is a product of two sparse matrices: rows are the block-class
+// X groups (X free keys), the inner dimension the Y runs (contracting keys,
+// section 4.1: X and Y are grouped by them), columns the Y free cells that
+// occur.  Row g holds the X entries of group g at their runs, and run k holds
+// the Y entries of contracting key k at their cells, so entry (g, c) of the
+// product sums every matching x * y of the output coordinate (g's X free key,
+// c) -- the contraction of Eq. 4 for those outputs.  When X and Y are dense
+// enough that rows x columns x runs is within a small factor of the products
+// this class would otherwise walk, the product is computed densely: each
+// workgroup owns a kMfmaRows x kMfmaCols output tile, and for every step of
+// kMfmaK runs scatters the tile's X and Y entries into zeroed LDS tiles and
+// multiplies them with v_mfma_f64_16x16x4f64.  Which outputs exist is
+// structural (some matching pair, whatever the values), so alongside the
+// values each step ORs per-row and per-column bitmasks of the runs present:
+// output (g, c) exists when the masks of g and c share a run in some step.
+//
+// The plan writes X and Y as dense panels laid out block by block in the
+// order the tiles read them, with the run masks beside them, so that a step
+// is two contiguous 16 KiB copies into LDS (loaded a step ahead into
+// registers) followed by the MFMA; the work is that of a dense product over
+// the padded rows, columns and runs, which the plan weighs against the
+// products before it takes this class.
+//
+// Every product is an exact FP64 multiply whose sums are rounded in another
+// order than the walk's (MFMA accumulates with fused multiply-adds), inside
+// the reordering bound that both paths meet.  Zero padding contributes exact
+// zeros, which is why the plan takes this class only when every value
+// involved is finite (0 * Inf would be NaN).
+#include <hip/hip_runtime.h>
+
+#include "../../include/sptc.h"
+#include "prim.hpp"
+#include "sptc_internal.hpp"
+
+namespace sptc {
+namespace {
+
+constexpr int kMBlock = 256;               // 4 waves: wave w computes rows [16w, 16w + 16) of the tile
+constexpr int kAStride = kMfmaRows + 16;   // LDS row of the X block (transposed), in doubles (padded)
+constexpr int kBStride = kMfmaCols + 16;   // LDS row of the Y block, in doubles (padded)
+constexpr int kAPairs = kMfmaK * kMfmaRows / 2 / kMBlock;  // 16-byte loads per thread and step
+constexpr int kBPairs = kMfmaK * kMfmaCols / 2 / kMBlock;
+constexpr unsigned kXcdsM = 8;            // MI355X: 8 XCDs, each with its own L2
+constexpr int kMSurveyBlock = 256;
+static_assert(kMfmaRows == 64 && kMfmaCols == 64 && kMfmaK == 32, "tile shape is fixed by the lane layout below");
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
+
+// ---------------------------------------------------------------------------
+// Plan time
+// ---------------------------------------------------------------------------
+
+// One wave per block group: its products, and whether its values are finite.
+__global__ __launch_bounds__(kMSurveyBlock) void k_mfma_survey_groups(const GroupRec* __restrict__ groups,
+                                                                      const uint32_t* __restrict__ blist, int64_t nb,
+                                                                      const unsigned long long* __restrict__ eoff,
+                                                                      const XRec* __restrict__ xr, MfmaSurvey* sv) {
+  const unsigned lane = threadIdx.x & 63;
+  const int64_t waves = (int64_t)gridDim.x * (kMSurveyBlock / 64);
+  for (int64_t i = (int64_t)blockIdx.x * (kMSurveyBlock / 64) + (threadIdx.x >> 6); i < nb; i += waves) {
+    const GroupRec G = groups[blist[i]];
+    bool bad = false;
+    for (unsigned e = lane; e < G.count; e += 64) bad |= !isfinite(xr[G.start + e].v);
+    if (__ballot(bad) && lane == 0) atomicOr(&sv->nonfinite, 1u);
+    if (lane == 0) atomicAdd(&sv->block_products, eoff[G.start + G.count] - eoff[G.start]);
+  }
+}
+
+// Y values finite, and the Y free cells that occur (LDS bitmap per workgroup).
+__global__ __launch_bounds__(kMSurveyBlock) void k_mfma_survey_y(const uint16_t* __restrict__ ykey16,
+                                                                 const double* __restrict__ yval, int64_t ny,
+                                                                 MfmaSurvey* sv) {
+  constexpr unsigned kWords = (1u << kDenseBits) / 32;
+  __shared__ unsigned s_bits[kWords];
+  for (unsigned w = threadIdx.x; w < kWords; w += kMSurveyBlock) s_bits[w] = 0u;
+  __syncthreads();
+  bool bad = false;
+  for (int64_t j = (int64_t)blockIdx.x * kMSurveyBlock + threadIdx.x; j < ny;
+       j += (int64_t)gridDim.x * kMSurveyBlock) {
+    const unsigned c = ykey16[j] & ((1u << kDenseBits) - 1u);
+    atomicOr(&s_bits[c >> 5], 1u << (c & 31));
+    bad |= !isfinite(yval[j]);
+  }
+  if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(&sv->nonfinite, 1u);
+  __syncthreads();
+  for (unsigned w = threadIdx.x; w < kWords; w += kMSurveyBlock)
+    if (s_bits[w]) atomicOr(&sv->colbits[w], s_bits[w]);
+}
+
+// Runs: the non-empty Y table slots in slot order, which is the order of
+// their starts (the table scan placed the runs in slot order).
+struct MfmaRunOp {
+  const YSlot* tab;
+  unsigned* run_start;
+  unsigned* runid;  // [ny]: at each run's start, the run's index
+  unsigned ny;
+  __device__ unsigned long long get(int64_t i) const { return tab[i].count > 0u ? 1ull : 0ull; }
+  __device__ void put(int64_t i, unsigned long long excl, unsigned long long v) const {
+    if (!v) return;
+    const unsigned s = tab[i].start;
+    run_start[excl] = s;
+    if (s < ny) runid[s] = (unsigned)excl;
+  }
+};
+
+struct FinRuns {
+  MfmaSurvey* sv;
+  unsigned* run_start;
+  unsigned ny;
+  __device__ void operator()(unsigned long long total) const {
+    sv->nruns = (unsigned)total;
+    run_start[total] = ny;
+  }
+};
+
+// Columns: occurring cells numbered in key order (one workgroup, 8 cells per thread).
+__global__ __launch_bounds__(1024) void k_mfma_cols(const MfmaSurvey* sv, uint16_t* __restrict__ colid,
+                                                    uint16_t* __restrict__ cellof) {
+  static_assert((1u << kDenseBits) == 8 * 1024, "8 cells per thread");
+  __shared__ unsigned long long s_wave[1024 / 64 + 1];
+  const unsigned t = threadIdx.x;
+  const unsigned bits = (sv->colbits[t >> 2] >> ((t & 3) * 8)) & 0xffu;
+  unsigned long long total;
+  unsigned long long col = block_excl_scan<1024>((unsigned long long)__popc(bits), s_wave, &total);
+  for (unsigned b = 0; b < 8; ++b) {
+    const unsigned cell = 8 * t + b;
+    if ((bits >> b) & 1u) {
+      colid[cell] = (uint16_t)col;
+      cellof[col] = (uint16_t)cell;
+      ++col;
+    } else {
+      colid[cell] = 0xffffu;
+    }
+  }
+}
+
+// X into its panel, one wave per block group (row i % 64 of row tile
+// i / 64): each entry with a Y match is added at (its run's step, run in the
+// step, row) and sets its run's bit in the row's mask.  Repeated X
+// coordinates add up.
+__global__ __launch_bounds__(256) void k_mfma_x_panel(const GroupRec* __restrict__ groups,
+                                                      const uint32_t* __restrict__ blist, int64_t nb,
+                                                      const XRec* __restrict__ xr, const unsigned* __restrict__ runid,
+                                                      const unsigned* __restrict__ run_start, unsigned nruns,
+                                                      unsigned nsteps, double* __restrict__ a,
+                                                      unsigned* __restrict__ am, DevStatus* st) {
+  const unsigned lane = threadIdx.x & 63;
+  const int64_t waves = (int64_t)gridDim.x * (256 / 64);
+  const unsigned yend = run_start[nruns];
+  for (int64_t i = (int64_t)blockIdx.x * (256 / 64) + (threadIdx.x >> 6); i < nb; i += waves) {
+    const GroupRec G = groups[blist[i]];
+    const unsigned row = (unsigned)(i % kMfmaRows);
+    const size_t blk0 = (size_t)(i / kMfmaRows) * nsteps;
+    for (unsigned e = lane; e < G.count; e += 64) {
+      const XRec r = xr[G.start + e];
+      if (!r.ycnt) continue;
+      const unsigned k = r.ystart < yend ? runid[r.ystart] : 0xffffffffu;
+      if (k >= nruns || run_start[k] != r.ystart) {
+        record_error(st, kErrInternal);
+        continue;
+      }
+      const size_t blk = blk0 + k / kMfmaK;
+      atomicAdd(&a[(blk * kMfmaK + k % kMfmaK) * kMfmaRows + row], r.v);
+      atomicOr(&am[blk * kMfmaRows + row], 1u << (k % kMfmaK));
+    }
+  }
+}
+
+// Y into its panel, one wave per run, the column numbering staged in LDS.
+// Repeated Y coordinates add up.
+__global__ __launch_bounds__(256) void k_mfma_y_panel(const unsigned* __restrict__ run_start, unsigned nruns,
+                                                      int64_t ny, const uint16_t* __restrict__ ykey16,
+                                                      const double* __restrict__ yval,
+                                                      const uint16_t* __restrict__ colid, unsigned nsteps,
+                                                      unsigned ncols, double* __restrict__ b,
+                                                      unsigned* __restrict__ bm, DevStatus* st) {
+  constexpr unsigned kCells = 1u << kDenseBits;
+  __shared__ uint16_t s_col[kCells];
+  for (unsigned q = threadIdx.x; q < kCells; q += 256) s_col[q] = colid[q];
+  __syncthreads();
+  const unsigned lane = threadIdx.x & 63;
+  const unsigned waves = gridDim.x * (256 / 64);
+  for (unsigned k = blockIdx.x * (256 / 64) + (threadIdx.x >> 6); k < nruns; k += waves) {
+    const unsigned s = run_start[k], e = run_start[k + 1];
+    if (e < s || (int64_t)e > ny) {  // runs ascend inside [0, ny) by construction
+      if (lane == 0) record_error(st, kErrInternal);
+      continue;
+    }
+    for (unsigned j = s + lane; j < e; j += 64) {
+      const unsigned c = s_col[ykey16[j] & (kCells - 1u)];
+      if (c >= ncols) {
+        record_error(st, kErrInternal);
+        continue;
+      }
+      const size_t blk = (size_t)(c / kMfmaCols) * nsteps + k / kMfmaK;
+      atomicAdd(&b[(blk * kMfmaK + k % kMfmaK) * kMfmaCols + c % kMfmaCols], yval[j]);
+      atomicOr(&bm[blk * kMfmaCols + c % kMfmaCols], 1u << (k % kMfmaK));
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Execute
+// ---------------------------------------------------------------------------
+
+// One thread's share of a step's blocks, 16 bytes per load, and for
+// threads [0, kMfmaRows) a row mask, [kMfmaRows, + kMfmaCols) a column mask.
+struct StepRegs {
+  v2d a[kAPairs], b[kBPairs];
+  unsigned mask;
+};
+
+__device__ __forceinline__ void load_step(const MfmaPlan& m, size_t ablk, size_t bblk, StepRegs& r) {
+  const unsigned t = threadIdx.x;
+  const v2d* a2 = reinterpret_cast<const v2d*>(m.a + ablk * (kMfmaK * kMfmaRows));
+  const v2d* b2 = reinterpret_cast<const v2d*>(m.b + bblk * (kMfmaK * kMfmaCols));
+#pragma unroll
+  for (int u = 0; u < kAPairs; ++u) r.a[u] = a2[t + u * kMBlock];
+#pragma unroll
+  for (int u = 0; u < kBPairs; ++u) r.b[u] = b2[t + u * kMBlock];
+  r.mask = t < kMfmaRows ? m.am[ablk * kMfmaRows + t]
+                         : (t < kMfmaRows + kMfmaCols ? m.bm[bblk * kMfmaCols + t - kMfmaRows] : 0u);
+}
+
+__device__ __forceinline__ void store_step(const StepRegs& r, double* s_at, double* s_b, unsigned* s_amask,
+                                           unsigned* s_bmask) {
+  const unsigned t = threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < kAPairs; ++u) {
+    const unsigned q = 2 * (t + u * kMBlock);  // first double of the pair in the kMfmaK x kMfmaRows block
+    *reinterpret_cast<v2d*>(&s_at[(q / kMfmaRows) * kAStride + q % kMfmaRows]) = r.a[u];
+  }
+#pragma unroll
+  for (int u = 0; u < kBPairs; ++u) {
+    const unsigned q = 2 * (t + u * kMBlock);
+    *reinterpret_cast<v2d*>(&s_b[(q / kMfmaCols) * kBStride + q % kMfmaCols]) = r.b[u];
+  }
+  if (t < kMfmaRows)
+    s_amask[t] = r.mask;
+  else if (t < kMfmaRows + kMfmaCols)
+    s_bmask[t - kMfmaRows] = r.mask;
+}
+
+__global__ __launch_bounds__(kMBlock, 3) void k_group_block_mfma(GroupArgs a, const uint32_t* __restrict__ blist,
+                                                              int64_t nb, MfmaPlan m) {
+  static_assert(kMfmaRows + kMfmaCols <= kMBlock, "one thread per row and column mask");
+  __shared__ __align__(16) double s_at[kMfmaK * kAStride];  // X block transposed: [run][row]
+  __shared__ __align__(16) double s_b[kMfmaK * kBStride];   // Y block: [run][column]
+  __shared__ unsigned s_amask[kMfmaRows], s_bmask[kMfmaCols];
+  __shared__ unsigned long long s_phi[kMfmaRows];
+  __shared__ unsigned s_cell[kMfmaCols];
+  __shared__ unsigned long long s_wave[kMBlock / 64 + 1];
+  __shared__ unsigned long long s_base;
+
+  const unsigned tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const unsigned nrt = (unsigned)((nb + kMfmaRows - 1) / kMfmaRows), nct = m.nct, nsteps = m.nsteps;
+  const int64_t tiles = (int64_t)nrt * nct;
+  // XCD-aware order: workgroups go round-robin over the XCDs, and each XCD
+  // takes a contiguous range of tiles, row tile major, so that the
+  // workgroups running together on an XCD share X panels in its L2.
+  const unsigned nxcd = gridDim.x % kXcdsM == 0 ? kXcdsM : 1u;
+  const unsigned xcd = blockIdx.x % nxcd, per_xcd = gridDim.x / nxcd;
+  const int64_t lo = tiles * xcd / nxcd, hi = tiles * (xcd + 1) / nxcd;
+
+  for (int64_t tile = lo + blockIdx.x / nxcd; tile < hi; tile += per_xcd) {
+    const unsigned rt = (unsigned)(tile / nct), ct = (unsigned)(tile % nct);
+    if (tid < kMfmaRows) {
+      const int64_t i = (int64_t)rt * kMfmaRows + tid;
+      s_phi[tid] = i < nb ? a.groups[blist[i]].phi : 0ull;
+    } else if (tid < kMfmaRows + kMfmaCols) {
+      const unsigned c = ct * kMfmaCols + (tid - kMfmaRows);
+      s_cell[tid - kMfmaRows] = c < m.ncols ? m.cellof[c] : 0u;
+    }
+    // the wave's 16 rows x 64 columns as 4 MFMA tiles
+    v4d acc[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[c] = v4d{0.0, 0.0, 0.0, 0.0};
+    // bit 4c + q: output (row 16 wave + (lane >> 4) + 4q, column 16c + (lane & 15)) exists
+    unsigned sbits = 0u;
+    const size_t ablk0 = (size_t)rt * nsteps, bblk0 = (size_t)ct * nsteps;
+    const unsigned last = nsteps - 1;
+    // software pipeline two steps deep: step s's blocks are loaded into
+    // registers (buffers 0 / 1 alternate) while steps s - 2 and s - 1
+    // multiply; loads past the last step reload it (unconditional loads keep
+    // no branch between a load and its use)
+    StepRegs r0, r1;
+    load_step(m, ablk0, bblk0, r0);
+    load_step(m, ablk0 + min(1u, last), bblk0 + min(1u, last), r1);
+    auto step_body = [&](StepRegs& r, unsigned step) {
+      __syncthreads();  // the previous step's MFMA has read the blocks
+      store_step(r, s_at, s_b, s_amask, s_bmask);
+      load_step(m, ablk0 + min(step + 2, last), bblk0 + min(step + 2, last), r);
+      __syncthreads();
+      // D (16 x 16) += A (16 x 4) B (4 x 16): lane holds A[lane & 15][lane >> 4],
+      // B[lane >> 4][lane & 15], and D rows (lane >> 4) + 4q of column lane & 15.
+#pragma unroll
+      for (unsigned s4 = 0; s4 < (unsigned)kMfmaK / 4; ++s4) {
+        const unsigned kr = 4 * s4 + (lane >> 4);
+        const double av = s_at[kr * kAStride + 16 * wave + (lane & 15)];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const double bv = s_b[kr * kBStride + 16 * c + (lane & 15)];
+          acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[c], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const unsigned bmk = s_bmask[16 * c + (lane & 15)];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (s_amask[16 * wave + (lane >> 4) + 4 * q] & bmk) sbits |= 1u << (4 * c + q);
+      }
+    };
+    for (unsigned step = 0; step + 1 < nsteps; step += 2) {
+      step_body(r0, step);
+      step_body(r1, step + 1);
+    }
+    if (nsteps & 1u) step_body(r0, last);
+
+    // outputs: one reservation per tile
+    unsigned long long total;
+    unsigned long long pos = block_excl_scan<kMBlock>((unsigned long long)__popc(sbits), s_wave, &total);
+    if (tid == 0) s_base = total ? atomicAdd(&a.st->out_base, total) : 0ull;
+    __syncthreads();
+    pos += s_base;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if ((sbits >> (4 * c + q)) & 1u) {
+          const unsigned row = 16 * wave + (lane >> 4) + 4 * q, col = 16 * c + (lane & 15);
+          if ((int64_t)pos < a.out_cap) write_output(a, pos, s_phi[row], s_cell[col], acc[c][q]);
+          ++pos;
+        }
+    __syncthreads();  // the next tile rewrites the row and column tables
+  }
+}
+
+}  // namespace
+
+hipError_t launch_mfma_survey(const GroupRec* groups, const uint32_t* blist, int64_t nb,
+                              const unsigned long long* eoff, const XRec* xr, const YSlot* ytab, int64_t yslots,
+                              const uint16_t* ykey16, const double* yval, int64_t ny, unsigned* run_start,
+                              unsigned* runid, MfmaSurvey* sv, void* tile_sums, int num_cus, hipStream_t stream) {
+  if (nb > 0)
+    k_mfma_survey_groups<<<grid_for(nb * 64, kMSurveyBlock, num_cus, 8), kMSurveyBlock, 0, stream>>>(
+        groups, blist, nb, eoff, xr, sv);
+  if (ny > 0)
+    k_mfma_survey_y<<<grid_for(ny, kMSurveyBlock, num_cus, 4), kMSurveyBlock, 0, stream>>>(ykey16, yval, ny, sv);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return device_scan(MfmaRunOp{ytab, run_start, runid, (unsigned)ny}, yslots, tile_sums,
+                     FinRuns{sv, run_start, (unsigned)ny}, stream);
+}
+
+hipError_t launch_mfma_panels(const MfmaSurvey* sv, const GroupRec* groups, const uint32_t* blist, int64_t nb,
+                              const XRec* xr, const unsigned* run_start, const unsigned* runid, unsigned nruns,
+                              const uint16_t* ykey16, const double* yval, int64_t ny, uint16_t* colid,
+                              uint16_t* cellof, unsigned ncols, unsigned nsteps, double* a, unsigned* am, double* b,
+                              unsigned* bm, DevStatus* st, int num_cus, hipStream_t stream) {
+  k_mfma_cols<<<1, 1024, 0, stream>>>(sv, colid, cellof);
+  k_mfma_x_panel<<<grid_for(nb * 64, 256, num_cus, 8), 256, 0, stream>>>(groups, blist, nb, xr, runid, run_start,
+                                                                         nruns, nsteps, a, am, st);
+  k_mfma_y_panel<<<grid_for((int64_t)nruns * 64, 256, num_cus, 8), 256, 0, stream>>>(
+      run_start, nruns, ny, ykey16, yval, colid, nsteps, ncols, b, bm, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_group_block_mfma(const GroupArgs& a, const uint32_t* blist, int64_t nb, const MfmaPlan& m,
+                                   int num_cus, hipStream_t stream) {
+  if (nb <= 0 || m.nsteps == 0 || m.nct == 0) return hipSuccess;
+  const int64_t tiles = ((nb + kMfmaRows - 1) / kMfmaRows) * (int64_t)m.nct;
+  unsigned grid = grid_for(tiles * kMBlock, kMBlock, num_cus, 3);
+  if (grid >= kXcdsM) grid -= grid % kXcdsM;  // whole rounds over the XCDs
+  k_group_block_mfma<<<grid, kMBlock, 0, stream>>>(a, blist, nb, m);
+  return hipGetLastError();
+}
+
+}  // namespace sptc

@@ -31,7 +31,6 @@ constexpr unsigned kXcds = 8;                          // MI355X: 8 XCDs, each w
 constexpr int kBChunk = 1024;
 constexpr int kCoWin = 1024;           // co-accumulation: X entries merged per window
 constexpr int kCoMaxGroups = 4;        // co-accumulation: groups per workgroup, at most
-constexpr int kCoSortMax = 4096;       // groups sorted at plan time (and co-accumulated): at most this many entries
 constexpr size_t kCoLds = 135 * 1024;  // co-accumulation: dynamic LDS for the accumulators (+ ~24 KiB static <= 160 KiB)                           // X entries staged per chunk (product-parallel walk)
 constexpr unsigned long long kWaveMaxProducts = 16384;  // beyond this a group goes to a workgroup
 
@@ -332,23 +331,6 @@ __device__ __forceinline__ bool lds_accumulate(ZSlot* tab, unsigned tmask, unsig
   return false;
 }
 
-// Output entry `pos`: X free coordinates from phix, Y free coordinates from
-// phiy, value v.  Streaming stores: the COO is written once and never read
-// here, so it should not displace Y and the tables from the caches.
-__device__ __forceinline__ void write_output(const GroupArgs& a, unsigned long long pos, unsigned long long phix,
-                                             unsigned long long phiy, double v) {
-#pragma unroll
-  for (int m = 0; m < kMaxOrder; ++m)
-    if (m < a.ux.n)
-      __builtin_nontemporal_store((int32_t)((phix >> a.ux.shift[m]) & a.ux.mask[m]),
-                                  &a.out_idx[(int64_t)m * a.out_cap + (int64_t)pos]);
-#pragma unroll
-  for (int m = 0; m < kMaxOrder; ++m)
-    if (m < a.uy.n)
-      __builtin_nontemporal_store((int32_t)((phiy >> a.uy.shift[m]) & a.uy.mask[m]),
-                                  &a.out_idx[(int64_t)(a.ux.n + m) * a.out_cap + (int64_t)pos]);
-  __builtin_nontemporal_store(v, &a.out_val[pos]);
-}
 
 struct WaveScratch {
   unsigned long long off[64];

@@ -401,6 +401,24 @@ __device__ __forceinline__ void set_insert_batch(unsigned long long* __restrict_
   }
 }
 
+// Output entry `pos`: X free coordinates from phix, Y free coordinates from
+// phiy, value v.  Streaming stores: the COO is written once and never read
+// here, so it should not displace Y and the tables from the caches.
+__device__ __forceinline__ void write_output(const GroupArgs& a, unsigned long long pos, unsigned long long phix,
+                                             unsigned long long phiy, double v) {
+#pragma unroll
+  for (int m = 0; m < kMaxOrder; ++m)
+    if (m < a.ux.n)
+      __builtin_nontemporal_store((int32_t)((phix >> a.ux.shift[m]) & a.ux.mask[m]),
+                                  &a.out_idx[(int64_t)m * a.out_cap + (int64_t)pos]);
+#pragma unroll
+  for (int m = 0; m < kMaxOrder; ++m)
+    if (m < a.uy.n)
+      __builtin_nontemporal_store((int32_t)((phiy >> a.uy.shift[m]) & a.uy.mask[m]),
+                                  &a.out_idx[(int64_t)(a.ux.n + m) * a.out_cap + (int64_t)pos]);
+  __builtin_nontemporal_store(v, &a.out_val[pos]);
+}
+
 __device__ __forceinline__ uint64_t low_mask(int bits) { return bits >= 64 ? ~0ull : ((1ull << bits) - 1ull); }
 
 // Output `pos` of contraction b of a batch, in b's COO region: X free

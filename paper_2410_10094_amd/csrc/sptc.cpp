@@ -196,6 +196,13 @@ struct sptc_plan_s : Workspace {
   uint32_t* blist = nullptr;
   uint32_t* glist = nullptr;
   uint32_t* bneff = nullptr;  // dense block class: entries with a Y match, per listed group (sorted first)
+  int32_t block_mfma = 0;     // dense block class on the matrix cores
+  MfmaSurvey* msv = nullptr;
+  unsigned* run_start = nullptr;
+  uint16_t* colid = nullptr;
+  uint16_t* cellof = nullptr;
+  MfmaPlan mplan{};
+  bool in_batch = false;      // the packed plan of a batch
   unsigned long long* dpos = nullptr;
   uint16_t* ykey16 = nullptr;  // dense Y free keys: compact copy of grouped Y
   double* yval = nullptr;
@@ -286,6 +293,7 @@ sptc_status check_options(const sptc_options& o) {
   if (o.max_probe < 0) return fail(SPTC_ERR_INVALID_ARG, "max_probe %d < 0", o.max_probe);
   if (o.mode != SPTC_MODE_GROUPED && o.mode != SPTC_MODE_GLOBAL)
     return fail(SPTC_ERR_INVALID_ARG, "unknown mode %d", o.mode);
+  if (o.block_mfma < -1 || o.block_mfma > 1) return fail(SPTC_ERR_INVALID_ARG, "block_mfma %d not in -1..1", o.block_mfma);
   if (o.out_table_slots != 0 && (o.out_table_slots < 2 || (o.out_table_slots & (o.out_table_slots - 1))))
     return fail(SPTC_ERR_INVALID_ARG, "out_table_slots %lld is not a power of two >= 2",
                 (long long)o.out_table_slots);
@@ -435,6 +443,64 @@ sptc_status plan_global(sptc_plan_s* P, const sptc_coo* X) {
 // X grouped by free key (section 4.1), then its groups sorted into
 // accumulation classes.  Groups too large for LDS are gathered for the
 // device-memory output hash.
+// Rows x columns x runs of the matrix-core block class (padded to whole
+// tiles) may be this many times its products.  Measured on the block-sparse
+// 48^4 workload (work 12.9x its products): the dense product takes 1.03 ms
+// where the walk takes 1.33 ms, but building the panels adds ~0.25 ms to the
+// plan, so the two break even near 13x; below 8x the matrix cores win
+// clearly (at 4x by about 4x on the kernel).
+constexpr double kMfmaWorkRatio = 8.0;
+// Largest dense X and Y panels the class builds (bytes); beyond, the walk.
+constexpr int64_t kMfmaMaxPanelBytes = (int64_t)8 << 30;
+
+// Dense block class on the matrix cores: survey, decision, bucketed records.
+sptc_status plan_block_mfma(sptc_plan_s* P) {
+  const hipStream_t s = P->stream;
+  sptc_status st;
+  const int64_t runs_cap = std::min<int64_t>(P->ytab_slots, P->ny) + 1;
+  if ((st = P->allocate_n(1, &P->msv))) return st;
+  unsigned* runid = nullptr;
+  if ((st = P->allocate_n(runs_cap, &P->run_start))) return st;
+  if ((st = P->allocate_n(P->ny, &runid))) return st;
+  HIP_TRY(hipMemsetAsync(P->msv, 0, sizeof(MfmaSurvey), s));
+  HIP_TRY(launch_mfma_survey(P->groups, P->blist, P->nb, P->eoff, P->xr, P->ytab, P->ytab_slots, P->ykey16, P->yval,
+                             P->ny, P->run_start, runid, P->msv, P->tile_sums, P->num_cus, s));
+  MfmaSurvey hs{};
+  HIP_TRY(hipMemcpyAsync(&hs, P->msv, sizeof hs, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (hs.nonfinite || hs.nruns == 0) return SPTC_OK;
+  unsigned cells = 0;
+  for (unsigned w : hs.colbits) cells += (unsigned)__builtin_popcount(w);
+  if (cells == 0) return SPTC_OK;
+  const int64_t nsteps = (hs.nruns + kMfmaK - 1) / kMfmaK, nrt = (P->nb + kMfmaRows - 1) / kMfmaRows,
+                nct = (cells + kMfmaCols - 1) / kMfmaCols;
+  const double work = (double)(nrt * kMfmaRows) * (double)(nct * kMfmaCols) * (double)(nsteps * kMfmaK);
+  if (P->opt.block_mfma < 0 && work > kMfmaWorkRatio * (double)hs.block_products) return SPTC_OK;
+  // dense panels of X and Y (with their run masks)
+  const int64_t ablocks = nrt * nsteps, bblocks = nct * nsteps;
+  const int64_t panel_bytes =
+      ablocks * (kMfmaK * kMfmaRows * 8 + kMfmaRows * 4) + bblocks * (kMfmaK * kMfmaCols * 8 + kMfmaCols * 4);
+  if (panel_bytes > kMfmaMaxPanelBytes) return SPTC_OK;
+  double *pa = nullptr, *pb = nullptr;
+  unsigned *am = nullptr, *bm = nullptr;
+  if ((st = P->allocate_n((int64_t)1 << kDenseBits, &P->colid))) return st;
+  if ((st = P->allocate_n(cells, &P->cellof))) return st;
+  if ((st = P->allocate_n(ablocks * kMfmaK * kMfmaRows, &pa))) return st;
+  if ((st = P->allocate_n(ablocks * kMfmaRows, &am))) return st;
+  if ((st = P->allocate_n(bblocks * kMfmaK * kMfmaCols, &pb))) return st;
+  if ((st = P->allocate_n(bblocks * kMfmaCols, &bm))) return st;
+  HIP_TRY(hipMemsetAsync(pa, 0, sizeof(double) * ablocks * kMfmaK * kMfmaRows, s));
+  HIP_TRY(hipMemsetAsync(am, 0, sizeof(unsigned) * ablocks * kMfmaRows, s));
+  HIP_TRY(hipMemsetAsync(pb, 0, sizeof(double) * bblocks * kMfmaK * kMfmaCols, s));
+  HIP_TRY(hipMemsetAsync(bm, 0, sizeof(unsigned) * bblocks * kMfmaCols, s));
+  HIP_TRY(launch_mfma_panels(P->msv, P->groups, P->blist, P->nb, P->xr, P->run_start, runid, hs.nruns, P->ykey16,
+                             P->yval, P->ny, P->colid, P->cellof, cells, (unsigned)nsteps, pa, am, pb, bm, P->st,
+                             P->num_cus, s));
+  P->mplan = MfmaPlan{pa, am, pb, bm, P->cellof, (unsigned)nsteps, cells, (unsigned)nct};
+  P->block_mfma = 1;
+  return SPTC_OK;
+}
+
 sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
   const hipStream_t s = P->stream;
   const uint64_t seed = P->opt.hash_seed;
@@ -492,7 +558,9 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
     if (P->dense) {
       if ((st = P->allocate_n(P->nb, &P->bneff))) return st;
       HIP_TRY(mark(P, s, SPTC_STAGE_X_SORT, 0));
-      HIP_TRY(launch_sort_block_entries(P->groups, P->blist, P->nb, P->xr, P->bneff, P->num_cus, s));
+      if (!P->in_batch && P->opt.block_mfma != 0 && (st = plan_block_mfma(P))) return st;
+      if (!P->block_mfma)  // the walk merges each group's entries in Y-run order
+        HIP_TRY(launch_sort_block_entries(P->groups, P->blist, P->nb, P->xr, P->bneff, P->num_cus, s));
       HIP_TRY(mark(P, s, SPTC_STAGE_X_SORT, 1));
     }
   }
@@ -670,6 +738,7 @@ sptc_status plan_create(sptc_plan_t* plan, const sptc_coo* X, const sptc_coo* Y,
   sptc_plan_s* P = new (std::nothrow) sptc_plan_s();
   if (!P) return fail(SPTC_ERR_OUT_OF_MEMORY, "host allocation failed");
   P->opt = o;
+  P->in_batch = br != nullptr;
   P->stream = static_cast<hipStream_t>(stream);
   if (alloc) {
     P->has_alloc = true;
@@ -782,7 +851,10 @@ sptc_status execute_plan(sptc_plan_s* P, int32_t* out_idx, double* out_val, int6
     HIP_TRY(launch_group_direct(a, P->dlist, P->dpos, P->nd, (uint64_t)P->direct_products, P->num_cus, s));
     HIP_TRY(mark(P, s, SPTC_STAGE_DIRECT, 1));
     HIP_TRY(mark(P, s, SPTC_STAGE_BLOCK, 0));
-    HIP_TRY(launch_group_block(a, P->blist, P->nb, P->dense, P->bneff, P->num_cus, s));
+    if (P->block_mfma)
+      HIP_TRY(launch_group_block_mfma(a, P->blist, P->nb, P->mplan, P->num_cus, s));
+    else
+      HIP_TRY(launch_group_block(a, P->blist, P->nb, P->dense, P->bneff, P->num_cus, s));
     HIP_TRY(mark(P, s, SPTC_STAGE_BLOCK, 1));
     if (P->ngl == 0) {
       HIP_TRY(mark(P, s, SPTC_STAGE_COMPACT, 0));
@@ -1003,6 +1075,7 @@ void sptc_default_options(sptc_options* opt) {
   opt->out_table_slots = 0;
   opt->stage_events = nullptr;
   opt->mode = SPTC_MODE_GROUPED;
+  opt->block_mfma = -1;
 }
 
 sptc_status sptc_plan(sptc_plan_t* plan, const sptc_coo* X, const sptc_coo* Y, int32_t ncontract, const int32_t* cx,
@@ -1031,6 +1104,7 @@ sptc_status sptc_plan_info(sptc_plan_t P, sptc_info* info) {
   info->wave_groups = P->nw;
   info->block_groups = P->nb;
   info->global_groups = P->ngl;
+  info->block_mfma = P->block_mfma;
   return SPTC_OK;
 }
 

@@ -133,6 +133,39 @@ constexpr int kWaveCap = 358;      // largest distinct-output bound a wave takes
 constexpr int kBlockSlots = 4096;  // LDS hash slots per workgroup
 constexpr int kBlockCap = 2867;    // largest distinct-output bound a workgroup hash takes
 constexpr int kDenseBits = 13;     // dense LDS accumulator when the Y free key has <= 13 bits
+constexpr int kCoSortMax = 4096;   // block groups sorted at plan time (and co-accumulated): at most this many entries
+
+// Block class on the matrix cores (dense Y free keys, one contraction).
+// The block groups are the rows, the Y runs (distinct contracting keys) the
+// inner dimension and the Y free cells that occur in Y the columns of a
+// product computed in FP64 MFMA tiles of kMfmaRows x kMfmaCols over inner
+// steps of kMfmaK runs.
+constexpr int kMfmaRows = 64;
+constexpr int kMfmaCols = 64;
+constexpr int kMfmaK = 32;
+
+// Plan-time survey, read back to decide whether the class may run there.
+struct alignas(16) MfmaSurvey {
+  unsigned long long block_products;  // products of the block-class groups
+  unsigned nonfinite;                 // a block-class X value or a Y value is Inf or NaN
+  unsigned nruns;                     // Y runs
+  unsigned colbits[(1u << kDenseBits) / 32];  // Y free cells that occur
+};
+
+// What the matrix-core block kernel reads besides GroupArgs: X and Y as
+// dense panels, one block per (tile, step) -- X transposed,
+// a[((rt * nsteps + s) * kMfmaK + k) * kMfmaRows + row], Y
+// b[((ct * nsteps + s) * kMfmaK + k) * kMfmaCols + col] -- and per (tile,
+// step) the runs each row and column holds an entry of,
+// am[(rt * nsteps + s) * kMfmaRows + row] (bit k), bm likewise.
+struct MfmaPlan {
+  const double* a;
+  const unsigned* am;
+  const double* b;
+  const unsigned* bm;
+  const uint16_t* cellof;  // [ncols]: Y free key of each column
+  unsigned nsteps, ncols, nct;
+};
 
 // ---- launchers (kernels.hip) ----
 // Each returns the hipError_t of its launch(es); all work goes on `stream`.
@@ -303,6 +336,25 @@ hipError_t launch_group_block(const GroupArgs& a, const uint32_t* blist, int64_t
 // (groups of at most 4096 entries) and counts those with a Y match into neff.
 hipError_t launch_sort_block_entries(const GroupRec* groups, const uint32_t* blist, int64_t nb, XRec* xr,
                                      uint32_t* neff, int num_cus, hipStream_t stream);
+
+// Matrix-core block class, plan time.  survey: the block groups' products
+// and value check, the Y value check, the run list (run_start[0..nruns],
+// the last entry ny; runid[ny] gets each run's index at its start) and the
+// occurring Y free cells; sv must be zeroed first.  Then, once the host has
+// chosen the class: columns (colid [2^kDenseBits], cellof [ncols]) and the
+// panels of MfmaPlan, which must be zeroed first.
+hipError_t launch_mfma_survey(const GroupRec* groups, const uint32_t* blist, int64_t nb,
+                              const unsigned long long* eoff, const XRec* xr, const YSlot* ytab, int64_t yslots,
+                              const uint16_t* ykey16, const double* yval, int64_t ny, unsigned* run_start,
+                              unsigned* runid, MfmaSurvey* sv, void* tile_sums, int num_cus, hipStream_t stream);
+hipError_t launch_mfma_panels(const MfmaSurvey* sv, const GroupRec* groups, const uint32_t* blist, int64_t nb,
+                              const XRec* xr, const unsigned* run_start, const unsigned* runid, unsigned nruns,
+                              const uint16_t* ykey16, const double* yval, int64_t ny, uint16_t* colid,
+                              uint16_t* cellof, unsigned ncols, unsigned nsteps, double* a, unsigned* am, double* b,
+                              unsigned* bm, DevStatus* st, int num_cus, hipStream_t stream);
+// Execute: every block group's outputs (one atomic per tile on st->out_base).
+hipError_t launch_group_block_mfma(const GroupArgs& a, const uint32_t* blist, int64_t nb, const MfmaPlan& m,
+                                   int num_cus, hipStream_t stream);
 
 // Direct class: single-entry groups against a Y without repeated coordinates
 // have one output per product; writes output q for product q in [0, nprod).

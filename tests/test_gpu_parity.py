@@ -404,9 +404,15 @@ def _co_problems():
     return out
 
 
+@pytest.mark.parametrize("mfma", [0, 1], ids=["walk", "mfma"])
 @pytest.mark.parametrize("p", _co_problems(), ids=lambda p: p.name)
-def test_dense_block_co_accumulation(p):
-    log(f"[co] {p.name} nnz {p.X.nnz}x{p.Y.nnz}")
-    info, gidx, gval = run_gpu(p)
+def test_dense_block_co_accumulation(p, mfma):
+    """Both block-class kernels: the sparse walk (co-accumulation, with its
+    per-group fallback for the group too large to sort) and the matrix-core
+    product."""
+    import paper_2410_10094_amd as sptc
+    log(f"[co] {p.name} nnz {p.X.nnz}x{p.Y.nnz} block_mfma {mfma}")
+    info, gidx, gval = run_gpu(p, options=sptc.default_options(block_mfma=mfma))
     assert info["classes"]["block"] > 100, info["classes"]
+    assert info["block_mfma"] == (mfma == 1)
     assert_parity(p, gidx, gval)
