@@ -70,25 +70,38 @@ __global__ __launch_bounds__(kMSurveyBlock) void k_mfma_survey_groups(const Grou
   }
 }
 
-// Y values finite, and the Y free cells that occur (LDS bitmap per workgroup).
-__global__ __launch_bounds__(kMSurveyBlock) void k_mfma_survey_y(const uint16_t* __restrict__ ykey16,
-                                                                 const double* __restrict__ yval, int64_t ny,
+// Y values finite.
+__global__ __launch_bounds__(kMSurveyBlock) void k_mfma_survey_y(const double* __restrict__ yval, int64_t ny,
                                                                  MfmaSurvey* sv) {
-  constexpr unsigned kWords = (1u << kDenseBits) / 32;
-  __shared__ unsigned s_bits[kWords];
-  for (unsigned w = threadIdx.x; w < kWords; w += kMSurveyBlock) s_bits[w] = 0u;
-  __syncthreads();
   bool bad = false;
+  for (int64_t j = (int64_t)blockIdx.x * kMSurveyBlock + threadIdx.x; j < ny;
+       j += (int64_t)gridDim.x * kMSurveyBlock)
+    bad |= !isfinite(yval[j]);
+  if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(&sv->nonfinite, 1u);
+}
+
+// The Y free cells that occur (LDS bitmap per workgroup, ORed into colbits).
+__global__ __launch_bounds__(kMSurveyBlock) void k_y_cells(const uint16_t* __restrict__ ykey16, int64_t ny,
+                                                           unsigned* __restrict__ colbits) {
+  __shared__ unsigned s_bits[kCellWords];
+  for (unsigned w = threadIdx.x; w < (unsigned)kCellWords; w += kMSurveyBlock) s_bits[w] = 0u;
+  __syncthreads();
   for (int64_t j = (int64_t)blockIdx.x * kMSurveyBlock + threadIdx.x; j < ny;
        j += (int64_t)gridDim.x * kMSurveyBlock) {
     const unsigned c = ykey16[j] & ((1u << kDenseBits) - 1u);
     atomicOr(&s_bits[c >> 5], 1u << (c & 31));
-    bad |= !isfinite(yval[j]);
   }
-  if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(&sv->nonfinite, 1u);
   __syncthreads();
-  for (unsigned w = threadIdx.x; w < kWords; w += kMSurveyBlock)
-    if (s_bits[w]) atomicOr(&sv->colbits[w], s_bits[w]);
+  for (unsigned w = threadIdx.x; w < (unsigned)kCellWords; w += kMSurveyBlock)
+    if (s_bits[w]) atomicOr(&colbits[w], s_bits[w]);
+}
+
+__global__ __launch_bounds__(kMSurveyBlock) void k_y_cell_count(const unsigned* __restrict__ colbits, DevStatus* st) {
+  __shared__ unsigned long long s_wave[kMSurveyBlock / 64 + 1];
+  unsigned long long n = 0;
+  for (unsigned w = threadIdx.x; w < (unsigned)kCellWords; w += kMSurveyBlock) n += (unsigned)__popc(colbits[w]);
+  n = block_sum<kMSurveyBlock>(n, s_wave);
+  if (threadIdx.x == 0) st->ycols = (unsigned)n;
 }
 
 // Runs: the non-empty Y table slots in slot order, which is the order of
@@ -118,12 +131,12 @@ struct FinRuns {
 };
 
 // Columns: occurring cells numbered in key order (one workgroup, 8 cells per thread).
-__global__ __launch_bounds__(1024) void k_mfma_cols(const MfmaSurvey* sv, uint16_t* __restrict__ colid,
+__global__ __launch_bounds__(1024) void k_mfma_cols(const unsigned* __restrict__ colbits, uint16_t* __restrict__ colid,
                                                     uint16_t* __restrict__ cellof) {
   static_assert((1u << kDenseBits) == 8 * 1024, "8 cells per thread");
   __shared__ unsigned long long s_wave[1024 / 64 + 1];
   const unsigned t = threadIdx.x;
-  const unsigned bits = (sv->colbits[t >> 2] >> ((t & 3) * 8)) & 0xffu;
+  const unsigned bits = (colbits[t >> 2] >> ((t & 3) * 8)) & 0xffu;
   unsigned long long total;
   unsigned long long col = block_excl_scan<1024>((unsigned long long)__popc(bits), s_wave, &total);
   for (unsigned b = 0; b < 8; ++b) {
@@ -350,19 +363,27 @@ hipError_t launch_mfma_survey(const GroupRec* groups, const uint32_t* blist, int
     k_mfma_survey_groups<<<grid_for(nb * 64, kMSurveyBlock, num_cus, 8), kMSurveyBlock, 0, stream>>>(
         groups, blist, nb, eoff, xr, sv);
   if (ny > 0)
-    k_mfma_survey_y<<<grid_for(ny, kMSurveyBlock, num_cus, 4), kMSurveyBlock, 0, stream>>>(ykey16, yval, ny, sv);
+    k_mfma_survey_y<<<grid_for(ny, kMSurveyBlock, num_cus, 4), kMSurveyBlock, 0, stream>>>(yval, ny, sv);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return device_scan(MfmaRunOp{ytab, run_start, runid, (unsigned)ny}, yslots, tile_sums,
                      FinRuns{sv, run_start, (unsigned)ny}, stream);
 }
 
-hipError_t launch_mfma_panels(const MfmaSurvey* sv, const GroupRec* groups, const uint32_t* blist, int64_t nb,
+hipError_t launch_y_cells(const uint16_t* ykey16, int64_t ny, unsigned* colbits, DevStatus* st, int num_cus,
+                          hipStream_t stream) {
+  if (ny > 0)
+    k_y_cells<<<grid_for(ny, kMSurveyBlock, num_cus, 1), kMSurveyBlock, 0, stream>>>(ykey16, ny, colbits);
+  k_y_cell_count<<<1, kMSurveyBlock, 0, stream>>>(colbits, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_mfma_panels(const unsigned* colbits, const GroupRec* groups, const uint32_t* blist, int64_t nb,
                               const XRec* xr, const unsigned* run_start, const unsigned* runid, unsigned nruns,
                               const uint16_t* ykey16, const double* yval, int64_t ny, uint16_t* colid,
                               uint16_t* cellof, unsigned ncols, unsigned nsteps, double* a, unsigned* am, double* b,
                               unsigned* bm, DevStatus* st, int num_cus, hipStream_t stream) {
-  k_mfma_cols<<<1, 1024, 0, stream>>>(sv, colid, cellof);
+  k_mfma_cols<<<1, 1024, 0, stream>>>(colbits, colid, cellof);
   k_mfma_x_panel<<<grid_for(nb * 64, 256, num_cus, 8), 256, 0, stream>>>(groups, blist, nb, xr, runid, run_start,
                                                                          nruns, nsteps, a, am, st);
   k_mfma_y_panel<<<grid_for((int64_t)nruns * 64, 256, num_cus, 8), 256, 0, stream>>>(

@@ -197,6 +197,8 @@ struct sptc_plan_s : Workspace {
   uint32_t* glist = nullptr;
   uint32_t* bneff = nullptr;  // dense block class: entries with a Y match, per listed group (sorted first)
   int32_t block_mfma = 0;     // dense block class on the matrix cores
+  unsigned* ycolbits = nullptr;  // dense Y free key: the cells that occur (bitmap)
+  unsigned ycols = 0;            // and their number
   MfmaSurvey* msv = nullptr;
   unsigned* run_start = nullptr;
   uint16_t* colid = nullptr;
@@ -410,8 +412,10 @@ sptc_status plan_group_y(sptc_plan_s* P, const sptc_coo* Y) {
   else
     HIP_TRY(launch_y_scatter(Y->idx, Y->val, P->ny, P->y_c, P->y_f, P->yb, P->ytab, P->ygeom, seed, P->max_probe_y,
                              P->yg, P->yset, (uint64_t)P->yset_slots - 1, yset_bits(P), P->st, P->num_cus, s));
-  if (P->opt.mode == SPTC_MODE_GROUPED && P->dense)
+  if (P->opt.mode == SPTC_MODE_GROUPED && P->dense) {
     HIP_TRY(launch_sort_y_runs(P->ytab, P->ytab_slots, P->yg, P->ny, P->ykey16, P->yval, P->st, P->num_cus, s));
+    HIP_TRY(launch_y_cells(P->ykey16, P->ny, P->ycolbits, P->st, P->num_cus, s));
+  }
   HIP_TRY(mark(P, s, SPTC_STAGE_Y_SCATTER, 1));
   return SPTC_OK;
 }
@@ -453,7 +457,23 @@ constexpr double kMfmaWorkRatio = 8.0;
 // Largest dense X and Y panels the class builds (bytes); beyond, the walk.
 constexpr int64_t kMfmaMaxPanelBytes = (int64_t)8 << 30;
 
-// Dense block class on the matrix cores: survey, decision, bucketed records.
+// Rows x columns x runs of the matrix-core product, padded to whole tiles.
+double mfma_work(int64_t rows, int64_t cols, int64_t runs) {
+  const auto up = [](int64_t v, int64_t t) { return (double)((v + t - 1) / t * t); };
+  return up(rows, kMfmaRows) * up(cols, kMfmaCols) * up(runs, kMfmaK);
+}
+
+// Before any survey: a single contraction, not ruled out by the option, and
+// (under the cost rule) work within the ratio of what the plan already
+// knows -- the products outside the direct class bound the block class's.
+bool mfma_candidate(const sptc_plan_s* P) {
+  if (P->in_batch || P->opt.block_mfma == 0 || P->ycols == 0) return false;
+  if (P->opt.block_mfma > 0) return true;
+  const double bound = (double)(P->products - P->direct_products);
+  return mfma_work(P->nb, P->ycols, P->y_groups) <= kMfmaWorkRatio * bound;
+}
+
+// Dense block class on the matrix cores: survey, decision, panels.
 sptc_status plan_block_mfma(sptc_plan_s* P) {
   const hipStream_t s = P->stream;
   sptc_status st;
@@ -468,14 +488,12 @@ sptc_status plan_block_mfma(sptc_plan_s* P) {
   MfmaSurvey hs{};
   HIP_TRY(hipMemcpyAsync(&hs, P->msv, sizeof hs, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  if (hs.nonfinite || hs.nruns == 0) return SPTC_OK;
-  unsigned cells = 0;
-  for (unsigned w : hs.colbits) cells += (unsigned)__builtin_popcount(w);
-  if (cells == 0) return SPTC_OK;
+  const unsigned cells = P->ycols;
+  if (hs.nonfinite || hs.nruns == 0 || cells == 0) return SPTC_OK;
   const int64_t nsteps = (hs.nruns + kMfmaK - 1) / kMfmaK, nrt = (P->nb + kMfmaRows - 1) / kMfmaRows,
                 nct = (cells + kMfmaCols - 1) / kMfmaCols;
-  const double work = (double)(nrt * kMfmaRows) * (double)(nct * kMfmaCols) * (double)(nsteps * kMfmaK);
-  if (P->opt.block_mfma < 0 && work > kMfmaWorkRatio * (double)hs.block_products) return SPTC_OK;
+  if (P->opt.block_mfma < 0 && mfma_work(P->nb, cells, hs.nruns) > kMfmaWorkRatio * (double)hs.block_products)
+    return SPTC_OK;
   // dense panels of X and Y (with their run masks)
   const int64_t ablocks = nrt * nsteps, bblocks = nct * nsteps;
   const int64_t panel_bytes =
@@ -493,7 +511,7 @@ sptc_status plan_block_mfma(sptc_plan_s* P) {
   HIP_TRY(hipMemsetAsync(am, 0, sizeof(unsigned) * ablocks * kMfmaRows, s));
   HIP_TRY(hipMemsetAsync(pb, 0, sizeof(double) * bblocks * kMfmaK * kMfmaCols, s));
   HIP_TRY(hipMemsetAsync(bm, 0, sizeof(unsigned) * bblocks * kMfmaCols, s));
-  HIP_TRY(launch_mfma_panels(P->msv, P->groups, P->blist, P->nb, P->xr, P->run_start, runid, hs.nruns, P->ykey16,
+  HIP_TRY(launch_mfma_panels(P->ycolbits, P->groups, P->blist, P->nb, P->xr, P->run_start, runid, hs.nruns, P->ykey16,
                              P->yval, P->ny, P->colid, P->cellof, cells, (unsigned)nsteps, pa, am, pb, bm, P->st,
                              P->num_cus, s));
   P->mplan = MfmaPlan{pa, am, pb, bm, P->cellof, (unsigned)nsteps, cells, (unsigned)nct};
@@ -552,13 +570,14 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
   P->ngl = P->x_groups - P->nd - P->nw - P->nb;
   P->direct_products = (int64_t)host.direct_products;
   P->ydup = host.ydup ? 1 : 0;
+  P->ycols = host.ycols;
   if (P->ngl < 0) return fail(SPTC_ERR_INTERNAL, "group classes do not add up");
   if (P->nb > 0) {
     HIP_TRY(prepare_group_block());
     if (P->dense) {
       if ((st = P->allocate_n(P->nb, &P->bneff))) return st;
       HIP_TRY(mark(P, s, SPTC_STAGE_X_SORT, 0));
-      if (!P->in_batch && P->opt.block_mfma != 0 && (st = plan_block_mfma(P))) return st;
+      if (mfma_candidate(P) && (st = plan_block_mfma(P))) return st;
       if (!P->block_mfma)  // the walk merges each group's entries in Y-run order
         HIP_TRY(launch_sort_block_entries(P->groups, P->blist, P->nb, P->xr, P->bneff, P->num_cus, s));
       HIP_TRY(mark(P, s, SPTC_STAGE_X_SORT, 1));
@@ -627,6 +646,8 @@ sptc_status plan_body(sptc_plan_s* P, const sptc_coo* X, const sptc_coo* Y, cons
   if (grouped && P->dense) {
     if ((st = P->allocate_n(P->ny, &P->ykey16))) return st;
     if ((st = P->allocate_n(P->ny, &P->yval))) return st;
+    if ((st = P->allocate_n(kCellWords, &P->ycolbits))) return st;
+    HIP_TRY(hipMemsetAsync(P->ycolbits, 0, sizeof(unsigned) * kCellWords, P->stream));
   }
   const int64_t tiles = std::max<int64_t>({scan_tiles(P->ytab_slots), scan_tiles(P->xtab_slots), scan_tiles(P->nx),
                                           scan_tiles(agg_chunks(P->ny) * P->ytab_slots),

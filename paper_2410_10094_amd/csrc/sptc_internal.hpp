@@ -124,7 +124,8 @@ struct alignas(16) DevStatus {
   unsigned long long out_base;         // output cursor: outputs placed so far
   unsigned int err;                    // kErr* bits
   unsigned int ydup;                   // nonzero: Y holds a repeated coordinate
-  unsigned int pad[2];
+  unsigned int ycols;                  // dense Y free key: distinct Y free cells that occur
+  unsigned int pad;
 };
 
 // Capacities of the LDS accumulators (distinct outputs per X group).
@@ -149,8 +150,8 @@ struct alignas(16) MfmaSurvey {
   unsigned long long block_products;  // products of the block-class groups
   unsigned nonfinite;                 // a block-class X value or a Y value is Inf or NaN
   unsigned nruns;                     // Y runs
-  unsigned colbits[(1u << kDenseBits) / 32];  // Y free cells that occur
 };
+constexpr int kCellWords = (1 << kDenseBits) / 32;  // bitmap of the dense Y free cells
 
 // What the matrix-core block kernel reads besides GroupArgs: X and Y as
 // dense panels, one block per (tile, step) -- X transposed,
@@ -337,17 +338,21 @@ hipError_t launch_group_block(const GroupArgs& a, const uint32_t* blist, int64_t
 hipError_t launch_sort_block_entries(const GroupRec* groups, const uint32_t* blist, int64_t nb, XRec* xr,
                                      uint32_t* neff, int num_cus, hipStream_t stream);
 
+// Dense Y free keys: the cells that occur (colbits, kCellWords words,
+// zeroed first) and their number in st->ycols.
+hipError_t launch_y_cells(const uint16_t* ykey16, int64_t ny, unsigned* colbits, DevStatus* st, int num_cus,
+                          hipStream_t stream);
 // Matrix-core block class, plan time.  survey: the block groups' products
-// and value check, the Y value check, the run list (run_start[0..nruns],
-// the last entry ny; runid[ny] gets each run's index at its start) and the
-// occurring Y free cells; sv must be zeroed first.  Then, once the host has
-// chosen the class: columns (colid [2^kDenseBits], cellof [ncols]) and the
-// panels of MfmaPlan, which must be zeroed first.
+// and value check, the Y value check and the run list (run_start[0..nruns],
+// the last entry ny; runid[ny] gets each run's index at its start); sv must
+// be zeroed first.  Then, once the host has chosen the class: columns
+// (colid [2^kDenseBits], cellof [ncols], from colbits) and the panels of
+// MfmaPlan, which must be zeroed first.
 hipError_t launch_mfma_survey(const GroupRec* groups, const uint32_t* blist, int64_t nb,
                               const unsigned long long* eoff, const XRec* xr, const YSlot* ytab, int64_t yslots,
                               const uint16_t* ykey16, const double* yval, int64_t ny, unsigned* run_start,
                               unsigned* runid, MfmaSurvey* sv, void* tile_sums, int num_cus, hipStream_t stream);
-hipError_t launch_mfma_panels(const MfmaSurvey* sv, const GroupRec* groups, const uint32_t* blist, int64_t nb,
+hipError_t launch_mfma_panels(const unsigned* colbits, const GroupRec* groups, const uint32_t* blist, int64_t nb,
                               const XRec* xr, const unsigned* run_start, const unsigned* runid, unsigned nruns,
                               const uint16_t* ykey16, const double* yval, int64_t ny, uint16_t* colid,
                               uint16_t* cellof, unsigned ncols, unsigned nsteps, double* a, unsigned* am, double* b,
