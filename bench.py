@@ -23,6 +23,7 @@ if ROOT not in sys.path:
 
 METRIC = "products/s + output nnz/s vs HBM roofline; batched/served p50/p99 vs per-call"
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+FP64_MFMA_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix, published
 
 DESCRIPTIONS = {
     "plain": "plain order-3 SpTC: 64^3 x 64^3, 2,621 nnz each (1%), X mode 2 with Y mode 0",
@@ -148,7 +149,8 @@ def run_workload(name, steps, warmup, with_events=True, mode="grouped", block_mf
         info = dict(mode=mode, y_groups=pl0.y_groups, y_table_slots=pl0.y_table_slots, out_table_slots=out_slots,
                     workspace_bytes=pl0.workspace_bytes, key_bits=pl0.key_bits, x_groups=pl0.x_groups,
                     group_classes=pl0.group_classes, direct_groups=pl0.group_classes["direct"],
-                    direct_products=pl0.direct_products, block_mfma=pl0.block_mfma)
+                    direct_products=pl0.direct_products, block_mfma=pl0.block_mfma,
+                    block_mfma_work=pl0.block_mfma_work)
 
     nst = len(B.STAGES)
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2 * nst)] for _ in range(steps)]
@@ -381,9 +383,9 @@ def run_batched(draws, dev, steps, warmup, budget, load_factor=1 / 1.3):
 # HBM traffic of a dominant kernel, from two committed rocprofv3 --pmc runs
 # (FETCH_SIZE, then WRITE_SIZE), keyed by (workload, stage).  A figure only
 # holds while the kernel's sources are the ones profiled.
-TRAFFIC_PROFILES = {("block-sparse-1.5M", "block"): "block_dense_block-sparse-1.5M_hbm_counters.md"}
-KERNEL_SOURCES = ("paper_2410_10094_amd/csrc/grouped.hip", "paper_2410_10094_amd/csrc/prim.hpp",
-                  "paper_2410_10094_amd/csrc/sptc_internal.hpp")
+TRAFFIC_PROFILES = {("block-sparse-1.5M", "block"): "block_mfma_block-sparse-1.5M_hbm_counters.md"}
+KERNEL_SOURCES = ("paper_2410_10094_amd/csrc/grouped.hip", "paper_2410_10094_amd/csrc/block_mfma.hip",
+                  "paper_2410_10094_amd/csrc/prim.hpp", "paper_2410_10094_amd/csrc/sptc_internal.hpp")
 
 
 def kernel_source_hash():
@@ -474,9 +476,18 @@ def roofline_of(r):
     ms = r["stage_ms"][stage]
     bytes_alg = algorithmic_bytes(stage, p, r["products"], r["nnz_z"], r["info"]["x_groups"], r["mode"], r["info"])
     achieved = bytes_alg / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
-    return {"kernel": stage, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(r["name"], stage),
-            "ms_per_launch": round(ms, 4), "algorithmic_bytes_per_launch": bytes_alg}
+    out = {"kernel": stage, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(r["name"], stage),
+           "ms_per_launch": round(ms, 4), "algorithmic_bytes_per_launch": bytes_alg}
+    work = r["info"].get("block_mfma_work", 0)
+    if stage == "block" and r["info"].get("block_mfma") and work and ms > 0:
+        # the block class ran as a dense FP64 product: its multiply-adds over
+        # the padded tiles against the matrix cores' FP64 peak
+        dense = 2.0 * work / (ms * 1e-3) / 1e12
+        out["matrix_cores"] = {"kernel": "k_group_block_mfma", "dense_flops_per_launch": 2 * work,
+                               "achieved_tflops": round(dense, 2), "peak_tflops": FP64_MFMA_PEAK_TFLOPS,
+                               "frac": round(dense / FP64_MFMA_PEAK_TFLOPS, 4)}
+    return out
 
 
 def summary(name, r):

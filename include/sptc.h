@@ -152,7 +152,7 @@ typedef struct sptc_options {
   int32_t mode;              /* sptc_mode; default SPTC_MODE_GROUPED */
   int32_t block_mfma;        /* grouped mode, dense Y free key, sptc_plan only: run the block class
                                 as a dense product on the FP64 matrix cores.  -1 (default): when
-                                eligible and rows x columns x runs is at most 8x the class's
+                                eligible and rows x columns x runs is at most 14x the class's
                                 products; 0: never; 1: whenever eligible.  Eligible: every value of
                                 the class and of Y finite, and dense X and Y panels of at most 8 GiB.
                                 sptc_info.block_mfma reports the choice. */
@@ -175,6 +175,7 @@ typedef struct sptc_info {
   int64_t direct_groups;                   /* grouped mode: single-entry groups written directly */
   int64_t direct_products;                 /* their products (= their outputs) */
   int32_t block_mfma;                      /* 1: the block class runs on the matrix cores */
+  int64_t block_mfma_work;                 /* then: padded rows x columns x runs (multiply-adds) */
 } sptc_info;
 
 typedef struct sptc_plan_s* sptc_plan_t;
@@ -292,11 +293,14 @@ SPTC_API void sptc_batch_free(sptc_batch_t batch);
 
 /* ---- Memory ----
  *
- * Without a caller allocator, workspace comes from the current device's
- * stream-ordered pool, configured to keep freed blocks cached for the next
- * plan.  sptc_pool_trim returns cached memory above keep_bytes to the
- * device (hipMemPoolTrimTo); memory of live plans is unaffected.  For
- * callers that switch between workloads with different footprints. */
+ * Without a caller allocator, workspace comes in slabs from the current
+ * device's stream-ordered pool.  Slabs of freed plans and batches are kept
+ * by the library (per device, with an event recorded on the freeing stream
+ * that a reuse on another stream waits for) and reused by later plans, so a
+ * warmed-up caller makes no pool calls.  sptc_pool_trim gives cached slabs
+ * above keep_bytes back to the pool and trims the pool to keep_bytes
+ * (hipMemPoolTrimTo); memory of live plans is unaffected.  An allocation
+ * that fails first releases the cache and retries. */
 SPTC_API sptc_status sptc_pool_trim(size_t keep_bytes);
 
 #ifdef __cplusplus

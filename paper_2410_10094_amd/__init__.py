@@ -158,6 +158,7 @@ class Plan:
                                   global_=info.global_groups)
         self.direct_products = info.direct_products
         self.block_mfma = bool(info.block_mfma)
+        self.block_mfma_work = info.block_mfma_work
 
     def close(self):
         if getattr(self, "_h", None):

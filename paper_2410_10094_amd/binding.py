@@ -52,7 +52,8 @@ class Info(ctypes.Structure):
                 ("key_bits_x_free", ctypes.c_int32), ("key_bits_y_free", ctypes.c_int32), ("mode", ctypes.c_int32),
                 ("x_groups", ctypes.c_int64), ("wave_groups", ctypes.c_int64), ("block_groups", ctypes.c_int64),
                 ("global_groups", ctypes.c_int64), ("direct_groups", ctypes.c_int64),
-                ("direct_products", ctypes.c_int64), ("block_mfma", ctypes.c_int32)]
+                ("direct_products", ctypes.c_int64), ("block_mfma", ctypes.c_int32),
+                ("block_mfma_work", ctypes.c_int64)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)

@@ -54,32 +54,6 @@ typedef double v2d __attribute__((ext_vector_type(2)));
 // Plan time
 // ---------------------------------------------------------------------------
 
-// One wave per block group: its products, and whether its values are finite.
-__global__ __launch_bounds__(kMSurveyBlock) void k_mfma_survey_groups(const GroupRec* __restrict__ groups,
-                                                                      const uint32_t* __restrict__ blist, int64_t nb,
-                                                                      const unsigned long long* __restrict__ eoff,
-                                                                      const XRec* __restrict__ xr, MfmaSurvey* sv) {
-  const unsigned lane = threadIdx.x & 63;
-  const int64_t waves = (int64_t)gridDim.x * (kMSurveyBlock / 64);
-  for (int64_t i = (int64_t)blockIdx.x * (kMSurveyBlock / 64) + (threadIdx.x >> 6); i < nb; i += waves) {
-    const GroupRec G = groups[blist[i]];
-    bool bad = false;
-    for (unsigned e = lane; e < G.count; e += 64) bad |= !isfinite(xr[G.start + e].v);
-    if (__ballot(bad) && lane == 0) atomicOr(&sv->nonfinite, 1u);
-    if (lane == 0) atomicAdd(&sv->block_products, eoff[G.start + G.count] - eoff[G.start]);
-  }
-}
-
-// Y values finite.
-__global__ __launch_bounds__(kMSurveyBlock) void k_mfma_survey_y(const double* __restrict__ yval, int64_t ny,
-                                                                 MfmaSurvey* sv) {
-  bool bad = false;
-  for (int64_t j = (int64_t)blockIdx.x * kMSurveyBlock + threadIdx.x; j < ny;
-       j += (int64_t)gridDim.x * kMSurveyBlock)
-    bad |= !isfinite(yval[j]);
-  if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(&sv->nonfinite, 1u);
-}
-
 // The Y free cells that occur (LDS bitmap per workgroup, ORed into colbits).
 __global__ __launch_bounds__(kMSurveyBlock) void k_y_cells(const uint16_t* __restrict__ ykey16, int64_t ny,
                                                            unsigned* __restrict__ colbits) {
@@ -157,10 +131,11 @@ __global__ __launch_bounds__(1024) void k_mfma_cols(const unsigned* __restrict__
 // coordinates add up.
 __global__ __launch_bounds__(256) void k_mfma_x_panel(const GroupRec* __restrict__ groups,
                                                       const uint32_t* __restrict__ blist, int64_t nb,
+                                                      const unsigned long long* __restrict__ eoff,
                                                       const XRec* __restrict__ xr, const unsigned* __restrict__ runid,
                                                       const unsigned* __restrict__ run_start, unsigned nruns,
                                                       unsigned nsteps, double* __restrict__ a,
-                                                      unsigned* __restrict__ am, DevStatus* st) {
+                                                      unsigned* __restrict__ am, MfmaSurvey* sv, DevStatus* st) {
   const unsigned lane = threadIdx.x & 63;
   const int64_t waves = (int64_t)gridDim.x * (256 / 64);
   const unsigned yend = run_start[nruns];
@@ -168,8 +143,11 @@ __global__ __launch_bounds__(256) void k_mfma_x_panel(const GroupRec* __restrict
     const GroupRec G = groups[blist[i]];
     const unsigned row = (unsigned)(i % kMfmaRows);
     const size_t blk0 = (size_t)(i / kMfmaRows) * nsteps;
+    if (lane == 0) atomicAdd(&sv->block_products, eoff[G.start + G.count] - eoff[G.start]);
+    bool bad = false;
     for (unsigned e = lane; e < G.count; e += 64) {
       const XRec r = xr[G.start + e];
+      bad |= !isfinite(r.v);
       if (!r.ycnt) continue;
       const unsigned k = r.ystart < yend ? runid[r.ystart] : 0xffffffffu;
       if (k >= nruns || run_start[k] != r.ystart) {
@@ -180,6 +158,7 @@ __global__ __launch_bounds__(256) void k_mfma_x_panel(const GroupRec* __restrict
       atomicAdd(&a[(blk * kMfmaK + k % kMfmaK) * kMfmaRows + row], r.v);
       atomicOr(&am[blk * kMfmaRows + row], 1u << (k % kMfmaK));
     }
+    if (__ballot(bad) && lane == 0) atomicOr(&sv->nonfinite, 1u);
   }
 }
 
@@ -190,7 +169,7 @@ __global__ __launch_bounds__(256) void k_mfma_y_panel(const unsigned* __restrict
                                                       const double* __restrict__ yval,
                                                       const uint16_t* __restrict__ colid, unsigned nsteps,
                                                       unsigned ncols, double* __restrict__ b,
-                                                      unsigned* __restrict__ bm, DevStatus* st) {
+                                                      unsigned* __restrict__ bm, MfmaSurvey* sv, DevStatus* st) {
   constexpr unsigned kCells = 1u << kDenseBits;
   __shared__ uint16_t s_col[kCells];
   for (unsigned q = threadIdx.x; q < kCells; q += 256) s_col[q] = colid[q];
@@ -210,7 +189,9 @@ __global__ __launch_bounds__(256) void k_mfma_y_panel(const unsigned* __restrict
         continue;
       }
       const size_t blk = (size_t)(c / kMfmaCols) * nsteps + k / kMfmaK;
-      atomicAdd(&b[(blk * kMfmaK + k % kMfmaK) * kMfmaCols + c % kMfmaCols], yval[j]);
+      const double v = yval[j];
+      if (!isfinite(v)) atomicOr(&sv->nonfinite, 1u);
+      atomicAdd(&b[(blk * kMfmaK + k % kMfmaK) * kMfmaCols + c % kMfmaCols], v);
       atomicOr(&bm[blk * kMfmaCols + c % kMfmaCols], 1u << (k % kMfmaK));
     }
   }
@@ -355,17 +336,8 @@ __global__ __launch_bounds__(kMBlock, 3) void k_group_block_mfma(GroupArgs a, co
 
 }  // namespace
 
-hipError_t launch_mfma_survey(const GroupRec* groups, const uint32_t* blist, int64_t nb,
-                              const unsigned long long* eoff, const XRec* xr, const YSlot* ytab, int64_t yslots,
-                              const uint16_t* ykey16, const double* yval, int64_t ny, unsigned* run_start,
-                              unsigned* runid, MfmaSurvey* sv, void* tile_sums, int num_cus, hipStream_t stream) {
-  if (nb > 0)
-    k_mfma_survey_groups<<<grid_for(nb * 64, kMSurveyBlock, num_cus, 8), kMSurveyBlock, 0, stream>>>(
-        groups, blist, nb, eoff, xr, sv);
-  if (ny > 0)
-    k_mfma_survey_y<<<grid_for(ny, kMSurveyBlock, num_cus, 4), kMSurveyBlock, 0, stream>>>(yval, ny, sv);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+hipError_t launch_mfma_runs(const YSlot* ytab, int64_t yslots, int64_t ny, unsigned* run_start, unsigned* runid,
+                            MfmaSurvey* sv, void* tile_sums, hipStream_t stream) {
   return device_scan(MfmaRunOp{ytab, run_start, runid, (unsigned)ny}, yslots, tile_sums,
                      FinRuns{sv, run_start, (unsigned)ny}, stream);
 }
@@ -379,15 +351,16 @@ hipError_t launch_y_cells(const uint16_t* ykey16, int64_t ny, unsigned* colbits,
 }
 
 hipError_t launch_mfma_panels(const unsigned* colbits, const GroupRec* groups, const uint32_t* blist, int64_t nb,
-                              const XRec* xr, const unsigned* run_start, const unsigned* runid, unsigned nruns,
-                              const uint16_t* ykey16, const double* yval, int64_t ny, uint16_t* colid,
-                              uint16_t* cellof, unsigned ncols, unsigned nsteps, double* a, unsigned* am, double* b,
-                              unsigned* bm, DevStatus* st, int num_cus, hipStream_t stream) {
+                              const unsigned long long* eoff, const XRec* xr, const unsigned* run_start,
+                              const unsigned* runid, unsigned nruns, const uint16_t* ykey16, const double* yval,
+                              int64_t ny, uint16_t* colid, uint16_t* cellof, unsigned ncols, unsigned nsteps,
+                              double* a, unsigned* am, double* b, unsigned* bm, MfmaSurvey* sv, DevStatus* st,
+                              int num_cus, hipStream_t stream) {
   k_mfma_cols<<<1, 1024, 0, stream>>>(colbits, colid, cellof);
-  k_mfma_x_panel<<<grid_for(nb * 64, 256, num_cus, 8), 256, 0, stream>>>(groups, blist, nb, xr, runid, run_start,
-                                                                         nruns, nsteps, a, am, st);
+  k_mfma_x_panel<<<grid_for(nb * 64, 256, num_cus, 8), 256, 0, stream>>>(groups, blist, nb, eoff, xr, runid,
+                                                                         run_start, nruns, nsteps, a, am, sv, st);
   k_mfma_y_panel<<<grid_for((int64_t)nruns * 64, 256, num_cus, 8), 256, 0, stream>>>(
-      run_start, nruns, ny, ykey16, yval, colid, nsteps, ncols, b, bm, st);
+      run_start, nruns, ny, ykey16, yval, colid, nsteps, ncols, b, bm, sv, st);
   return hipGetLastError();
 }
 

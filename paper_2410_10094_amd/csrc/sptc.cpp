@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -96,20 +97,84 @@ sptc_status configure_pool(int dev, DeviceInfo* d) {
   return SPTC_OK;
 }
 
+// Slabs given back by released plans and batches, per device, kept for the
+// next ones: after a warm-up, planning makes no pool call at all (growing
+// the stream-ordered pool inside hipMallocAsync has stalled single calls for
+// seconds, and each call costs microseconds).  A slab carries an event
+// recorded on the releasing stream; a reuse on another stream waits for it.
+struct CachedSlab {
+  void* p;
+  size_t bytes;
+  hipEvent_t ready;
+};
+std::mutex g_cache_mu;
+std::multimap<size_t, CachedSlab> g_cache[64];
+size_t g_cached_bytes[64];
+
+// A cached slab of at least `bytes` (and at most twice that), or p = NULL.
+CachedSlab cache_take(int dev, size_t bytes) {
+  std::lock_guard<std::mutex> lock(g_cache_mu);
+  auto& c = g_cache[dev];
+  auto it = c.lower_bound(bytes);
+  if (it == c.end() || it->first > 2 * bytes) return CachedSlab{nullptr, 0, nullptr};
+  CachedSlab sl = it->second;
+  c.erase(it);
+  g_cached_bytes[dev] -= sl.bytes;
+  return sl;
+}
+
+void cache_put(int dev, const CachedSlab& sl) {
+  std::lock_guard<std::mutex> lock(g_cache_mu);
+  g_cache[dev].emplace(sl.bytes, sl);
+  g_cached_bytes[dev] += sl.bytes;
+}
+
+// Frees cached slabs of `dev` (largest first) until at most keep_bytes stay.
+sptc_status cache_trim(int dev, size_t keep_bytes) {
+  std::vector<CachedSlab> out;
+  {
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    auto& c = g_cache[dev];
+    while (!c.empty() && g_cached_bytes[dev] > keep_bytes) {
+      auto it = std::prev(c.end());
+      out.push_back(it->second);
+      g_cached_bytes[dev] -= it->first;
+      c.erase(it);
+    }
+  }
+  for (const CachedSlab& sl : out) {
+    if (sl.ready) {
+      HIP_TRY(hipEventSynchronize(sl.ready));
+      HIP_TRY(hipEventDestroy(sl.ready));
+    }
+    HIP_TRY(hipFreeAsync(sl.p, nullptr));  // back to the pool (the slab is idle)
+  }
+  return SPTC_OK;
+}
+
 }  // namespace
 
-// Device memory owned by a plan or batch: through the caller's allocator, or
-// the device's stream-ordered pool.
+// Device memory owned by a plan or batch: through the caller's allocator
+// (one call per buffer), or slabs from the device (the slab cache above,
+// else the stream-ordered pool).  Buffers are carved out of the slabs -- a
+// buffer above the current slab's room opens a new one of max(buffer,
+// kSlabMin doubling up to kSlabMax) -- so a plan holds a handful of slabs,
+// not one allocation per buffer.
 struct Workspace {
   struct Buf {
     void* p;
     size_t bytes;
+    hipEvent_t ready;  // slabs: the event they came with from the cache, if any
   };
+  static constexpr size_t kSlabMin = (size_t)8 << 20;
+  static constexpr size_t kSlabMax = (size_t)256 << 20;
   hipStream_t stream = nullptr;
   bool has_alloc = false;
   sptc_allocator alloc{};
-  std::vector<Buf> bufs;
-  int64_t workspace = 0;
+  int slab_device = -1;
+  std::vector<Buf> bufs;  // caller's buffers, or the slabs
+  size_t slab_used = 0, slab_next = kSlabMin;
+  int64_t workspace = 0;  // bytes held
 
   sptc_status allocate(size_t bytes, void** out) {
     bytes = std::max<size_t>(bytes, 16);
@@ -118,16 +183,37 @@ struct Workspace {
     if (has_alloc) {
       p = alloc.alloc(bytes, stream, alloc.ctx);
       if (!p) return fail(SPTC_ERR_OUT_OF_MEMORY, "allocator returned NULL for %zu bytes", bytes);
-    } else {
-      hipError_t e = hipMallocAsync(&p, bytes, stream);
-      if (e != hipSuccess || !p) {
-        (void)hipGetLastError();
-        return fail(SPTC_ERR_OUT_OF_MEMORY, "hipMallocAsync(%zu bytes): %s", bytes, hipGetErrorString(e));
-      }
+      bufs.push_back({p, bytes, nullptr});
+      workspace += (int64_t)bytes;
+      *out = p;
+      return SPTC_OK;
     }
-    bufs.push_back({p, bytes});
-    workspace += (int64_t)bytes;
-    *out = p;
+    if (bufs.empty() || slab_used + bytes > bufs.back().bytes) {
+      if (slab_device < 0) HIP_TRY(hipGetDevice(&slab_device));
+      const size_t sz = std::max(bytes, slab_next);
+      CachedSlab sl = cache_take(slab_device, sz);
+      if (sl.p) {
+        if (sl.ready) HIP_TRY(hipStreamWaitEvent(stream, sl.ready, 0));
+      } else {
+        hipError_t e = hipMallocAsync(&sl.p, sz, stream);
+        if (e != hipSuccess || !sl.p) {
+          (void)hipGetLastError();
+          // memory held in the cache may be what is missing: give it back and retry once
+          if (cache_trim(slab_device, 0) != SPTC_OK || hipMallocAsync(&sl.p, sz, stream) != hipSuccess || !sl.p) {
+            (void)hipGetLastError();
+            return fail(SPTC_ERR_OUT_OF_MEMORY, "hipMallocAsync(%zu bytes): %s", sz, hipGetErrorString(e));
+          }
+        }
+        sl.bytes = sz;
+        sl.ready = nullptr;
+      }
+      bufs.push_back({sl.p, sl.bytes, sl.ready});
+      workspace += (int64_t)sl.bytes;
+      slab_used = 0;
+      slab_next = std::min(slab_next * 2, kSlabMax);
+    }
+    *out = static_cast<char*>(bufs.back().p) + slab_used;
+    slab_used += bytes;
     return SPTC_OK;
   }
 
@@ -143,11 +229,24 @@ struct Workspace {
     for (auto it = bufs.rbegin(); it != bufs.rend(); ++it) {
       if (has_alloc) {
         if (alloc.release) alloc.release(it->p, it->bytes, stream, alloc.ctx);
-      } else {
-        (void)hipFreeAsync(it->p, stream);
+        continue;
       }
+      // back to the cache, ready once the stream's work so far is done
+      hipEvent_t ev = it->ready;
+      if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFreeAsync(it->p, stream);
+        continue;
+      }
+      if (hipEventRecord(ev, stream) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipStreamSynchronize(stream);
+      }
+      cache_put(slab_device, CachedSlab{it->p, it->bytes, ev});
     }
     bufs.clear();
+    slab_used = 0;
+    slab_next = kSlabMin;
     workspace = 0;
   }
 };
@@ -450,10 +549,11 @@ sptc_status plan_global(sptc_plan_s* P, const sptc_coo* X) {
 // Rows x columns x runs of the matrix-core block class (padded to whole
 // tiles) may be this many times its products.  Measured on the block-sparse
 // 48^4 workload (work 12.9x its products): the dense product takes 1.03 ms
-// where the walk takes 1.33 ms, but building the panels adds ~0.25 ms to the
-// plan, so the two break even near 13x; below 8x the matrix cores win
-// clearly (at 4x by about 4x on the kernel).
-constexpr double kMfmaWorkRatio = 8.0;
+// where the walk takes 1.33 ms, and building the panels costs 0.28 ms where
+// the walk's sort costs 0.09 ms -- 2.03 against 2.08 ms per step.  Per unit,
+// the walk spends about 18x what the dense product spends per multiply-add,
+// and the panels' fixed cost brings the break-even to about 14x.
+constexpr double kMfmaWorkRatio = 14.0;
 // Largest dense X and Y panels the class builds (bytes); beyond, the walk.
 constexpr int64_t kMfmaMaxPanelBytes = (int64_t)8 << 30;
 
@@ -473,47 +573,51 @@ bool mfma_candidate(const sptc_plan_s* P) {
   return mfma_work(P->nb, P->ycols, P->y_groups) <= kMfmaWorkRatio * bound;
 }
 
-// Dense block class on the matrix cores: survey, decision, panels.
+// Dense block class on the matrix cores: the panels are built from what the
+// plan knows (rows, columns that occur, runs) while the class is surveyed,
+// and one read-back then decides.
 sptc_status plan_block_mfma(sptc_plan_s* P) {
   const hipStream_t s = P->stream;
   sptc_status st;
-  const int64_t runs_cap = std::min<int64_t>(P->ytab_slots, P->ny) + 1;
-  if ((st = P->allocate_n(1, &P->msv))) return st;
-  unsigned* runid = nullptr;
-  if ((st = P->allocate_n(runs_cap, &P->run_start))) return st;
-  if ((st = P->allocate_n(P->ny, &runid))) return st;
-  HIP_TRY(hipMemsetAsync(P->msv, 0, sizeof(MfmaSurvey), s));
-  HIP_TRY(launch_mfma_survey(P->groups, P->blist, P->nb, P->eoff, P->xr, P->ytab, P->ytab_slots, P->ykey16, P->yval,
-                             P->ny, P->run_start, runid, P->msv, P->tile_sums, P->num_cus, s));
-  MfmaSurvey hs{};
-  HIP_TRY(hipMemcpyAsync(&hs, P->msv, sizeof hs, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
   const unsigned cells = P->ycols;
-  if (hs.nonfinite || hs.nruns == 0 || cells == 0) return SPTC_OK;
-  const int64_t nsteps = (hs.nruns + kMfmaK - 1) / kMfmaK, nrt = (P->nb + kMfmaRows - 1) / kMfmaRows,
+  const int64_t nruns = P->y_groups;
+  if (cells == 0 || nruns <= 0) return SPTC_OK;
+  const int64_t nsteps = (nruns + kMfmaK - 1) / kMfmaK, nrt = (P->nb + kMfmaRows - 1) / kMfmaRows,
                 nct = (cells + kMfmaCols - 1) / kMfmaCols;
-  if (P->opt.block_mfma < 0 && mfma_work(P->nb, cells, hs.nruns) > kMfmaWorkRatio * (double)hs.block_products)
-    return SPTC_OK;
-  // dense panels of X and Y (with their run masks)
   const int64_t ablocks = nrt * nsteps, bblocks = nct * nsteps;
   const int64_t panel_bytes =
       ablocks * (kMfmaK * kMfmaRows * 8 + kMfmaRows * 4) + bblocks * (kMfmaK * kMfmaCols * 8 + kMfmaCols * 4);
   if (panel_bytes > kMfmaMaxPanelBytes) return SPTC_OK;
+  const int64_t runs_cap = std::min<int64_t>(P->ytab_slots, P->ny) + 1;
+  unsigned* runid = nullptr;
   double *pa = nullptr, *pb = nullptr;
   unsigned *am = nullptr, *bm = nullptr;
+  if ((st = P->allocate_n(1, &P->msv))) return st;
+  if ((st = P->allocate_n(runs_cap, &P->run_start))) return st;
+  if ((st = P->allocate_n(P->ny, &runid))) return st;
   if ((st = P->allocate_n((int64_t)1 << kDenseBits, &P->colid))) return st;
   if ((st = P->allocate_n(cells, &P->cellof))) return st;
   if ((st = P->allocate_n(ablocks * kMfmaK * kMfmaRows, &pa))) return st;
   if ((st = P->allocate_n(ablocks * kMfmaRows, &am))) return st;
   if ((st = P->allocate_n(bblocks * kMfmaK * kMfmaCols, &pb))) return st;
   if ((st = P->allocate_n(bblocks * kMfmaCols, &bm))) return st;
+  HIP_TRY(hipMemsetAsync(P->msv, 0, sizeof(MfmaSurvey), s));
   HIP_TRY(hipMemsetAsync(pa, 0, sizeof(double) * ablocks * kMfmaK * kMfmaRows, s));
   HIP_TRY(hipMemsetAsync(am, 0, sizeof(unsigned) * ablocks * kMfmaRows, s));
   HIP_TRY(hipMemsetAsync(pb, 0, sizeof(double) * bblocks * kMfmaK * kMfmaCols, s));
   HIP_TRY(hipMemsetAsync(bm, 0, sizeof(unsigned) * bblocks * kMfmaCols, s));
-  HIP_TRY(launch_mfma_panels(P->ycolbits, P->groups, P->blist, P->nb, P->xr, P->run_start, runid, hs.nruns, P->ykey16,
-                             P->yval, P->ny, P->colid, P->cellof, cells, (unsigned)nsteps, pa, am, pb, bm, P->st,
-                             P->num_cus, s));
+  HIP_TRY(launch_mfma_runs(P->ytab, P->ytab_slots, P->ny, P->run_start, runid, P->msv, P->tile_sums, s));
+  HIP_TRY(launch_mfma_panels(P->ycolbits, P->groups, P->blist, P->nb, P->eoff, P->xr, P->run_start, runid,
+                             (unsigned)nruns, P->ykey16, P->yval, P->ny, P->colid, P->cellof, cells, (unsigned)nsteps,
+                             pa, am, pb, bm, P->msv, P->st, P->num_cus, s));
+  MfmaSurvey hs{};
+  HIP_TRY(hipMemcpyAsync(&hs, P->msv, sizeof hs, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (hs.nruns != (unsigned)nruns) return fail(SPTC_ERR_INTERNAL, "%u Y runs in the table, %lld counted", hs.nruns,
+                                               (long long)nruns);
+  if (hs.nonfinite) return SPTC_OK;
+  if (P->opt.block_mfma < 0 && mfma_work(P->nb, cells, nruns) > kMfmaWorkRatio * (double)hs.block_products)
+    return SPTC_OK;
   P->mplan = MfmaPlan{pa, am, pb, bm, P->cellof, (unsigned)nsteps, cells, (unsigned)nct};
   P->block_mfma = 1;
   return SPTC_OK;
@@ -1126,6 +1230,7 @@ sptc_status sptc_plan_info(sptc_plan_t P, sptc_info* info) {
   info->block_groups = P->nb;
   info->global_groups = P->ngl;
   info->block_mfma = P->block_mfma;
+  info->block_mfma_work = P->block_mfma ? (int64_t)mfma_work(P->nb, P->mplan.ncols, P->y_groups) : 0;
   return SPTC_OK;
 }
 
@@ -1313,6 +1418,8 @@ sptc_status sptc_batch_execute(sptc_batch_t B, int32_t* out_idx, double* out_val
 sptc_status sptc_pool_trim(size_t keep_bytes) {
   int dev = 0;
   HIP_TRY(hipGetDevice(&dev));
+  sptc_status st = cache_trim(dev, keep_bytes);
+  if (st != SPTC_OK) return st;
   hipMemPool_t pool;
   HIP_TRY(hipDeviceGetDefaultMemPool(&pool, dev));
   HIP_TRY(hipMemPoolTrimTo(pool, keep_bytes));

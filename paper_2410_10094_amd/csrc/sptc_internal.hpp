@@ -342,21 +342,20 @@ hipError_t launch_sort_block_entries(const GroupRec* groups, const uint32_t* bli
 // zeroed first) and their number in st->ycols.
 hipError_t launch_y_cells(const uint16_t* ykey16, int64_t ny, unsigned* colbits, DevStatus* st, int num_cus,
                           hipStream_t stream);
-// Matrix-core block class, plan time.  survey: the block groups' products
-// and value check, the Y value check and the run list (run_start[0..nruns],
-// the last entry ny; runid[ny] gets each run's index at its start); sv must
-// be zeroed first.  Then, once the host has chosen the class: columns
-// (colid [2^kDenseBits], cellof [ncols], from colbits) and the panels of
-// MfmaPlan, which must be zeroed first.
-hipError_t launch_mfma_survey(const GroupRec* groups, const uint32_t* blist, int64_t nb,
-                              const unsigned long long* eoff, const XRec* xr, const YSlot* ytab, int64_t yslots,
-                              const uint16_t* ykey16, const double* yval, int64_t ny, unsigned* run_start,
-                              unsigned* runid, MfmaSurvey* sv, void* tile_sums, int num_cus, hipStream_t stream);
+// Matrix-core block class, plan time.  runs: the run list
+// (run_start[0..nruns], the last entry ny; runid[ny] gets each run's index
+// at its start; sv->nruns).  panels: columns (colid [2^kDenseBits], cellof
+// [ncols], from colbits) and the panels of MfmaPlan, which must be zeroed
+// first, while surveying the class into sv (zeroed first): its products and
+// whether its X values and the Y values are finite.
+hipError_t launch_mfma_runs(const YSlot* ytab, int64_t yslots, int64_t ny, unsigned* run_start, unsigned* runid,
+                            MfmaSurvey* sv, void* tile_sums, hipStream_t stream);
 hipError_t launch_mfma_panels(const unsigned* colbits, const GroupRec* groups, const uint32_t* blist, int64_t nb,
-                              const XRec* xr, const unsigned* run_start, const unsigned* runid, unsigned nruns,
-                              const uint16_t* ykey16, const double* yval, int64_t ny, uint16_t* colid,
-                              uint16_t* cellof, unsigned ncols, unsigned nsteps, double* a, unsigned* am, double* b,
-                              unsigned* bm, DevStatus* st, int num_cus, hipStream_t stream);
+                              const unsigned long long* eoff, const XRec* xr, const unsigned* run_start,
+                              const unsigned* runid, unsigned nruns, const uint16_t* ykey16, const double* yval,
+                              int64_t ny, uint16_t* colid, uint16_t* cellof, unsigned ncols, unsigned nsteps,
+                              double* a, unsigned* am, double* b, unsigned* bm, MfmaSurvey* sv, DevStatus* st,
+                              int num_cus, hipStream_t stream);
 // Execute: every block group's outputs (one atomic per tile on st->out_base).
 hipError_t launch_group_block_mfma(const GroupArgs& a, const uint32_t* blist, int64_t nb, const MfmaPlan& m,
                                    int num_cus, hipStream_t stream);
