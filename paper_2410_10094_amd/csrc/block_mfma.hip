@@ -39,7 +39,8 @@ namespace sptc {
 namespace {
 
 constexpr int kMBlock = 256;               // 4 waves: wave w computes rows [16w, 16w + 16) of the tile
-constexpr int kAStride = kMfmaRows + 16;   // LDS row of the X block (transposed), in doubles (padded)
+constexpr int kAStride = kMfmaK + 2;       // LDS row of the X block ([row][run]), in doubles: 16-byte
+                                           // stores, and the 16 rows an MFMA operand reads in distinct banks
 constexpr int kBStride = kMfmaCols + 16;   // LDS row of the Y block, in doubles (padded)
 constexpr int kAPairs = kMfmaK * kMfmaRows / 2 / kMBlock;  // 16-byte loads per thread and step
 constexpr int kBPairs = kMfmaK * kMfmaCols / 2 / kMBlock;
@@ -125,75 +126,123 @@ __global__ __launch_bounds__(1024) void k_mfma_cols(const unsigned* __restrict__
   }
 }
 
-// X into its panel, one wave per block group (row i % 64 of row tile
-// i / 64): each entry with a Y match is added at (its run's step, run in the
-// step, row) and sets its run's bit in the row's mask.  Repeated X
-// coordinates add up.
-__global__ __launch_bounds__(256) void k_mfma_x_panel(const GroupRec* __restrict__ groups,
-                                                      const uint32_t* __restrict__ blist, int64_t nb,
-                                                      const unsigned long long* __restrict__ eoff,
-                                                      const XRec* __restrict__ xr, const unsigned* __restrict__ runid,
-                                                      const unsigned* __restrict__ run_start, unsigned nruns,
-                                                      unsigned nsteps, double* __restrict__ a,
-                                                      unsigned* __restrict__ am, MfmaSurvey* sv, DevStatus* st) {
-  const unsigned lane = threadIdx.x & 63;
-  const int64_t waves = (int64_t)gridDim.x * (256 / 64);
+// X into its panel, one wave per row (block group i, or a padding row past
+// nb): the row's entries are added into an LDS copy of a chunk of its panel
+// row (kXChunk runs; repeated X coordinates add up), with a bit per run in
+// the chunk's step masks, and the chunk is then written out whole (zeros
+// included), so the panel needs no clearing and no global atomics.  The
+// class's products and the finiteness of its values are surveyed on the way.
+constexpr unsigned kXChunk = 1920;  // runs per LDS chunk (60 steps)
+constexpr unsigned kXWaves = 4;
+static_assert(kXChunk % kMfmaK == 0, "chunks of whole steps");
+
+__global__ __launch_bounds__(64 * kXWaves) void k_mfma_x_panel(const GroupRec* __restrict__ groups,
+                                                               const uint32_t* __restrict__ blist, int64_t nb,
+                                                               const unsigned long long* __restrict__ eoff,
+                                                               const XRec* __restrict__ xr,
+                                                               const unsigned* __restrict__ runid,
+                                                               const unsigned* __restrict__ run_start,
+                                                               unsigned nruns, unsigned nsteps,
+                                                               double* __restrict__ a, unsigned* __restrict__ am,
+                                                               MfmaSurvey* sv, DevStatus* st) {
+  __shared__ double s_v[kXWaves][kXChunk];
+  __shared__ unsigned s_m[kXWaves][kXChunk / kMfmaK];
+  const unsigned lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double* v = s_v[w];
+  unsigned* msk = s_m[w];
+  const int64_t rows = (nb + kMfmaRows - 1) / kMfmaRows * kMfmaRows;
+  const size_t K = (size_t)nsteps * kMfmaK;
   const unsigned yend = run_start[nruns];
-  for (int64_t i = (int64_t)blockIdx.x * (256 / 64) + (threadIdx.x >> 6); i < nb; i += waves) {
-    const GroupRec G = groups[blist[i]];
-    const unsigned row = (unsigned)(i % kMfmaRows);
-    const size_t blk0 = (size_t)(i / kMfmaRows) * nsteps;
-    if (lane == 0) atomicAdd(&sv->block_products, eoff[G.start + G.count] - eoff[G.start]);
+  const int64_t waves = (int64_t)gridDim.x * kXWaves;
+  for (int64_t i = (int64_t)blockIdx.x * kXWaves + w; i < rows; i += waves) {
+    GroupRec G{0ull, 0u, 0u};
+    if (i < nb) {
+      G = groups[blist[i]];
+      if (lane == 0) atomicAdd(&sv->block_products, eoff[G.start + G.count] - eoff[G.start]);
+    }
     bool bad = false;
-    for (unsigned e = lane; e < G.count; e += 64) {
-      const XRec r = xr[G.start + e];
-      bad |= !isfinite(r.v);
-      if (!r.ycnt) continue;
-      const unsigned k = r.ystart < yend ? runid[r.ystart] : 0xffffffffu;
-      if (k >= nruns || run_start[k] != r.ystart) {
-        record_error(st, kErrInternal);
-        continue;
+    for (size_t k0 = 0; k0 < K; k0 += kXChunk) {
+      const unsigned nk = (unsigned)(K - k0 < kXChunk ? K - k0 : kXChunk);
+      for (unsigned j = lane; j < nk; j += 64) v[j] = 0.0;
+      for (unsigned j = lane; j < nk / kMfmaK; j += 64) msk[j] = 0u;
+      wave_lds_fence();
+      for (unsigned e = lane; e < G.count; e += 64) {
+        const XRec r = xr[G.start + e];
+        if (k0 == 0) bad |= !isfinite(r.v);
+        if (!r.ycnt) continue;
+        const unsigned k = r.ystart < yend ? runid[r.ystart] : 0xffffffffu;
+        if (k >= nruns || run_start[k] != r.ystart) {
+          if (k0 == 0) record_error(st, kErrInternal);
+          continue;
+        }
+        if (k < k0 || k >= k0 + nk) continue;
+        const unsigned kk = (unsigned)(k - k0);
+        atomicAdd(&v[kk], r.v);
+        atomicOr(&msk[kk / kMfmaK], 1u << (kk % kMfmaK));
       }
-      const size_t blk = blk0 + k / kMfmaK;
-      atomicAdd(&a[(blk * kMfmaK + k % kMfmaK) * kMfmaRows + row], r.v);
-      atomicOr(&am[blk * kMfmaRows + row], 1u << (k % kMfmaK));
+      wave_lds_fence();
+      double* dst = a + (size_t)i * K + k0;  // 16-byte aligned: K and k0 are even
+      for (unsigned j = 2 * lane; j < nk; j += 128)
+        *reinterpret_cast<v2d*>(dst + j) = v2d{v[j], v[j + 1]};
+      for (unsigned j = lane; j < nk / kMfmaK; j += 64) am[(size_t)i * nsteps + k0 / kMfmaK + j] = msk[j];
+      wave_lds_fence();
     }
     if (__ballot(bad) && lane == 0) atomicOr(&sv->nonfinite, 1u);
   }
 }
 
-// Y into its panel, one wave per run, the column numbering staged in LDS.
-// Repeated Y coordinates add up.
-__global__ __launch_bounds__(256) void k_mfma_y_panel(const unsigned* __restrict__ run_start, unsigned nruns,
-                                                      int64_t ny, const uint16_t* __restrict__ ykey16,
-                                                      const double* __restrict__ yval,
-                                                      const uint16_t* __restrict__ colid, unsigned nsteps,
-                                                      unsigned ncols, double* __restrict__ b,
-                                                      unsigned* __restrict__ bm, MfmaSurvey* sv, DevStatus* st) {
+// Y into its panel, one workgroup per step (its 32 runs), the column
+// numbering staged in LDS: values are stored into the zeroed panel (added
+// when Y repeats a coordinate), and the step's column masks are ORed in LDS
+// and written out whole, so they need no clearing and no global atomics.
+constexpr unsigned kYBlock = 512;
+__global__ __launch_bounds__(kYBlock) void k_mfma_y_panel(const unsigned* __restrict__ run_start, unsigned nruns,
+                                                          int64_t ny, const uint16_t* __restrict__ ykey16,
+                                                          const double* __restrict__ yval,
+                                                          const uint16_t* __restrict__ colid, unsigned nsteps,
+                                                          unsigned ncols, unsigned nct, int ydup,
+                                                          double* __restrict__ b, unsigned* __restrict__ bm,
+                                                          MfmaSurvey* sv, DevStatus* st) {
   constexpr unsigned kCells = 1u << kDenseBits;
   __shared__ uint16_t s_col[kCells];
-  for (unsigned q = threadIdx.x; q < kCells; q += 256) s_col[q] = colid[q];
-  __syncthreads();
-  const unsigned lane = threadIdx.x & 63;
-  const unsigned waves = gridDim.x * (256 / 64);
-  for (unsigned k = blockIdx.x * (256 / 64) + (threadIdx.x >> 6); k < nruns; k += waves) {
-    const unsigned s = run_start[k], e = run_start[k + 1];
-    if (e < s || (int64_t)e > ny) {  // runs ascend inside [0, ny) by construction
-      if (lane == 0) record_error(st, kErrInternal);
-      continue;
+  __shared__ unsigned s_mask[kCells + kMfmaCols];  // nct * 64 <= kCells + 63
+  __shared__ unsigned s_run[kMfmaK + 1];
+  for (unsigned q = threadIdx.x; q < kCells; q += kYBlock) s_col[q] = colid[q];
+  const unsigned ncp = nct * kMfmaCols;
+  for (unsigned step = blockIdx.x; step < nsteps; step += gridDim.x) {
+    for (unsigned q = threadIdx.x; q < ncp; q += kYBlock) s_mask[q] = 0u;
+    if (threadIdx.x <= kMfmaK) {
+      const unsigned k = step * kMfmaK + threadIdx.x;
+      s_run[threadIdx.x] = run_start[k < nruns ? k : nruns];
     }
-    for (unsigned j = s + lane; j < e; j += 64) {
+    __syncthreads();
+    // the step's entries: runs of the step are contiguous in grouped Y
+    const unsigned lo = s_run[0], hi = s_run[kMfmaK];
+    bool bad = lo > hi || (int64_t)hi > ny;  // runs ascend inside [0, ny) by construction
+    for (unsigned j = bad ? hi : lo + threadIdx.x; j < hi; j += kYBlock) {
+      unsigned kk = 0;  // run of j within the step
+#pragma unroll
+      for (unsigned half = kMfmaK / 2; half > 0; half >>= 1)
+        if (s_run[kk + half] <= j) kk += half;
       const unsigned c = s_col[ykey16[j] & (kCells - 1u)];
       if (c >= ncols) {
         record_error(st, kErrInternal);
         continue;
       }
-      const size_t blk = (size_t)(c / kMfmaCols) * nsteps + k / kMfmaK;
       const double v = yval[j];
       if (!isfinite(v)) atomicOr(&sv->nonfinite, 1u);
-      atomicAdd(&b[(blk * kMfmaK + k % kMfmaK) * kMfmaCols + c % kMfmaCols], v);
-      atomicOr(&bm[blk * kMfmaCols + c % kMfmaCols], 1u << (k % kMfmaK));
+      double* dst = &b[(((size_t)(c / kMfmaCols) * nsteps + step) * kMfmaK + kk) * kMfmaCols + c % kMfmaCols];
+      if (ydup)
+        atomicAdd(dst, v);
+      else
+        *dst = v;
+      atomicOr(&s_mask[c], 1u << kk);
     }
+    if (bad && threadIdx.x == 0) record_error(st, kErrInternal);
+    __syncthreads();
+    for (unsigned q = threadIdx.x; q < ncp; q += kYBlock)
+      bm[((size_t)(q / kMfmaCols) * nsteps + step) * kMfmaCols + q % kMfmaCols] = s_mask[q];
+    __syncthreads();
   }
 }
 
@@ -208,15 +257,21 @@ struct StepRegs {
   unsigned mask;
 };
 
-__device__ __forceinline__ void load_step(const MfmaPlan& m, size_t ablk, size_t bblk, StepRegs& r) {
+// A step's X block: rows rt * 64 .. + 63 of the row-major X panel at runs
+// step * 32 .. + 31, 16 threads per row (256 contiguous bytes); the Y block
+// is the contiguous 32 x 64 block of its panel.
+__device__ __forceinline__ void load_step(const MfmaPlan& m, const double* arow, size_t arow0, size_t K,
+                                          unsigned step, size_t bblk, StepRegs& r) {
   const unsigned t = threadIdx.x;
-  const v2d* a2 = reinterpret_cast<const v2d*>(m.a + ablk * (kMfmaK * kMfmaRows));
   const v2d* b2 = reinterpret_cast<const v2d*>(m.b + bblk * (kMfmaK * kMfmaCols));
+  // arow: this thread's first X row (t / 16) at its pair (t % 16); pair u is
+  // 16 u rows further (kMBlock / 16 rows per u)
 #pragma unroll
-  for (int u = 0; u < kAPairs; ++u) r.a[u] = a2[t + u * kMBlock];
+  for (int u = 0; u < kAPairs; ++u)
+    r.a[u] = *reinterpret_cast<const v2d*>(arow + (size_t)u * (kMBlock / (kMfmaK / 2)) * K + (size_t)step * kMfmaK);
 #pragma unroll
   for (int u = 0; u < kBPairs; ++u) r.b[u] = b2[t + u * kMBlock];
-  r.mask = t < kMfmaRows ? m.am[ablk * kMfmaRows + t]
+  r.mask = t < kMfmaRows ? m.am[(arow0 + t) * (K / kMfmaK) + step]
                          : (t < kMfmaRows + kMfmaCols ? m.bm[bblk * kMfmaCols + t - kMfmaRows] : 0u);
 }
 
@@ -224,9 +279,9 @@ __device__ __forceinline__ void store_step(const StepRegs& r, double* s_at, doub
                                            unsigned* s_bmask) {
   const unsigned t = threadIdx.x;
 #pragma unroll
-  for (int u = 0; u < kAPairs; ++u) {
-    const unsigned q = 2 * (t + u * kMBlock);  // first double of the pair in the kMfmaK x kMfmaRows block
-    *reinterpret_cast<v2d*>(&s_at[(q / kMfmaRows) * kAStride + q % kMfmaRows]) = r.a[u];
+  for (int u = 0; u < kAPairs; ++u) {  // [row][run], as the panel
+    const unsigned p = t + u * kMBlock, row = p / (kMfmaK / 2), kp = p % (kMfmaK / 2);
+    *reinterpret_cast<v2d*>(&s_at[row * kAStride + 2 * kp]) = r.a[u];
   }
 #pragma unroll
   for (int u = 0; u < kBPairs; ++u) {
@@ -242,7 +297,7 @@ __device__ __forceinline__ void store_step(const StepRegs& r, double* s_at, doub
 __global__ __launch_bounds__(kMBlock, 3) void k_group_block_mfma(GroupArgs a, const uint32_t* __restrict__ blist,
                                                               int64_t nb, MfmaPlan m) {
   static_assert(kMfmaRows + kMfmaCols <= kMBlock, "one thread per row and column mask");
-  __shared__ __align__(16) double s_at[kMfmaK * kAStride];  // X block transposed: [run][row]
+  __shared__ __align__(16) double s_at[kMfmaRows * kAStride];  // X block: [row][run]
   __shared__ __align__(16) double s_b[kMfmaK * kBStride];   // Y block: [run][column]
   __shared__ unsigned s_amask[kMfmaRows], s_bmask[kMfmaCols];
   __shared__ unsigned long long s_phi[kMfmaRows];
@@ -275,26 +330,27 @@ __global__ __launch_bounds__(kMBlock, 3) void k_group_block_mfma(GroupArgs a, co
     for (int c = 0; c < 4; ++c) acc[c] = v4d{0.0, 0.0, 0.0, 0.0};
     // bit 4c + q: output (row 16 wave + (lane >> 4) + 4q, column 16c + (lane & 15)) exists
     unsigned sbits = 0u;
-    const size_t ablk0 = (size_t)rt * nsteps, bblk0 = (size_t)ct * nsteps;
+    const size_t arow0 = (size_t)rt * kMfmaRows, K = (size_t)nsteps * kMfmaK, bblk0 = (size_t)ct * nsteps;
+    const double* arow = m.a + (arow0 + tid / (kMfmaK / 2)) * K + 2 * (tid % (kMfmaK / 2));
     const unsigned last = nsteps - 1;
     // software pipeline two steps deep: step s's blocks are loaded into
     // registers (buffers 0 / 1 alternate) while steps s - 2 and s - 1
     // multiply; loads past the last step reload it (unconditional loads keep
     // no branch between a load and its use)
     StepRegs r0, r1;
-    load_step(m, ablk0, bblk0, r0);
-    load_step(m, ablk0 + min(1u, last), bblk0 + min(1u, last), r1);
+    load_step(m, arow, arow0, K, 0, bblk0, r0);
+    load_step(m, arow, arow0, K, min(1u, last), bblk0 + min(1u, last), r1);
     auto step_body = [&](StepRegs& r, unsigned step) {
       __syncthreads();  // the previous step's MFMA has read the blocks
       store_step(r, s_at, s_b, s_amask, s_bmask);
-      load_step(m, ablk0 + min(step + 2, last), bblk0 + min(step + 2, last), r);
+      load_step(m, arow, arow0, K, min(step + 2, last), bblk0 + min(step + 2, last), r);
       __syncthreads();
       // D (16 x 16) += A (16 x 4) B (4 x 16): lane holds A[lane & 15][lane >> 4],
       // B[lane >> 4][lane & 15], and D rows (lane >> 4) + 4q of column lane & 15.
 #pragma unroll
       for (unsigned s4 = 0; s4 < (unsigned)kMfmaK / 4; ++s4) {
         const unsigned kr = 4 * s4 + (lane >> 4);
-        const double av = s_at[kr * kAStride + 16 * wave + (lane & 15)];
+        const double av = s_at[(16 * wave + (lane & 15)) * kAStride + kr];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           const double bv = s_b[kr * kBStride + 16 * c + (lane & 15)];
@@ -315,21 +371,32 @@ __global__ __launch_bounds__(kMBlock, 3) void k_group_block_mfma(GroupArgs a, co
     }
     if (nsteps & 1u) step_body(r0, last);
 
-    // outputs: one reservation per tile
+    // outputs: one reservation per tile; inside a wave, the outputs of one
+    // accumulator register go to consecutive positions in lane order, so
+    // that each store instruction writes contiguous memory
     unsigned long long total;
-    unsigned long long pos = block_excl_scan<kMBlock>((unsigned long long)__popc(sbits), s_wave, &total);
+    unsigned mine = (unsigned)__popc(sbits);
+    // per-wave total, then the wave's base by a block scan over the waves
+    unsigned wtotal = mine;
+    for (int off = 32; off > 0; off >>= 1) wtotal += __shfl_xor(wtotal, off);
+    unsigned long long wbase = block_excl_scan<kMBlock>(lane == 0 ? (unsigned long long)wtotal : 0ull, s_wave, &total);
+    wbase = __shfl(wbase, 0);
     if (tid == 0) s_base = total ? atomicAdd(&a.st->out_base, total) : 0ull;
     __syncthreads();
-    pos += s_base;
+    unsigned long long run = s_base + wbase;
 #pragma unroll
     for (int c = 0; c < 4; ++c)
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if ((sbits >> (4 * c + q)) & 1u) {
+      for (int q = 0; q < 4; ++q) {
+        const bool has = (sbits >> (4 * c + q)) & 1u;
+        const unsigned long long m = __ballot(has);
+        if (has) {
+          const unsigned long long pos = run + __popcll(m & ((1ull << lane) - 1ull));
           const unsigned row = 16 * wave + (lane >> 4) + 4 * q, col = 16 * c + (lane & 15);
           if ((int64_t)pos < a.out_cap) write_output(a, pos, s_phi[row], s_cell[col], acc[c][q]);
-          ++pos;
         }
+        run += __popcll(m);
+      }
     __syncthreads();  // the next tile rewrites the row and column tables
   }
 }
@@ -354,13 +421,15 @@ hipError_t launch_mfma_panels(const unsigned* colbits, const GroupRec* groups, c
                               const unsigned long long* eoff, const XRec* xr, const unsigned* run_start,
                               const unsigned* runid, unsigned nruns, const uint16_t* ykey16, const double* yval,
                               int64_t ny, uint16_t* colid, uint16_t* cellof, unsigned ncols, unsigned nsteps,
-                              double* a, unsigned* am, double* b, unsigned* bm, MfmaSurvey* sv, DevStatus* st,
-                              int num_cus, hipStream_t stream) {
+                              int ydup, double* a, unsigned* am, double* b, unsigned* bm, MfmaSurvey* sv,
+                              DevStatus* st, int num_cus, hipStream_t stream) {
   k_mfma_cols<<<1, 1024, 0, stream>>>(colbits, colid, cellof);
-  k_mfma_x_panel<<<grid_for(nb * 64, 256, num_cus, 8), 256, 0, stream>>>(groups, blist, nb, eoff, xr, runid,
-                                                                         run_start, nruns, nsteps, a, am, sv, st);
-  k_mfma_y_panel<<<grid_for((int64_t)nruns * 64, 256, num_cus, 8), 256, 0, stream>>>(
-      run_start, nruns, ny, ykey16, yval, colid, nsteps, ncols, b, bm, sv, st);
+  const int64_t xrows = (nb + kMfmaRows - 1) / kMfmaRows * kMfmaRows;
+  k_mfma_x_panel<<<grid_for(xrows * 64, 64 * kXWaves, num_cus, 4), 64 * kXWaves, 0, stream>>>(
+      groups, blist, nb, eoff, xr, runid, run_start, nruns, nsteps, a, am, sv, st);
+  const unsigned nct = (ncols + kMfmaCols - 1) / kMfmaCols;
+  k_mfma_y_panel<<<grid_for((int64_t)nsteps * kYBlock, kYBlock, num_cus, 2), kYBlock, 0, stream>>>(
+      run_start, nruns, ny, ykey16, yval, colid, nsteps, ncols, nct, ydup, b, bm, sv, st);
   return hipGetLastError();
 }
 

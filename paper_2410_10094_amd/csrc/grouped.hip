@@ -1055,13 +1055,15 @@ __global__ __launch_bounds__(kDBlock) void k_group_direct(GroupArgs a, const uin
   }
 }
 
-// Sorts each Y run (a Y group's entries in the grouped array) of 2..1024
-// entries by Y free key, one workgroup per Y table slot.  Order within a run
-// is free (section 4.1.3); sorted runs let the lanes of a wave that walk a run
-// hit consecutive dense accumulator cells, i.e. distinct LDS banks.
-// Dense Y free keys only; it also finds repeated Y coordinates (two entries
-// of one run with the same free key) with a per-run bitmap of the
-// 2^kDenseBits keys, which the direct class needs to know about.
+// SORT: sorts each Y run (a Y group's entries in the grouped array) of
+// 2..1024 entries by Y free key, one workgroup per Y table slot.  Order
+// within a run is free (section 4.1.3); sorted runs let the lanes of a wave
+// that walk a run hit consecutive dense accumulator cells, i.e. distinct LDS
+// banks.  Either way (dense Y free keys only) it writes the compact copy of
+// grouped Y and finds repeated Y coordinates (two entries of one run with
+// the same free key) with a per-run bitmap of the 2^kDenseBits keys, which
+// the direct class needs to know about.
+template <bool SORT>
 __global__ __launch_bounds__(kBBlock) void k_sort_y_runs(const YSlot* __restrict__ ytab, int64_t nslots,
                                                          YEntry* __restrict__ yg, int64_t ny,
                                                          uint16_t* __restrict__ ykey16, double* __restrict__ yval,
@@ -1081,7 +1083,7 @@ __global__ __launch_bounds__(kBBlock) void k_sort_y_runs(const YSlot* __restrict
     const unsigned n = t.count, tid = threadIdx.x;
     for (unsigned w = tid; w < kSeenWords; w += kBBlock) s_seen[w] = 0u;
     __syncthreads();
-    if (n > (unsigned)kBBlock) {  // too long to sort here: copy as is
+    if (!SORT || n > (unsigned)kBBlock) {  // copy as is (too long to sort here)
       for (unsigned j = tid; j < n; j += kBBlock) {
         const YEntry e = yg[t.start + j];
         if (seen_before(e.phi)) st->ydup = 1u;
@@ -1334,10 +1336,13 @@ hipError_t launch_scan_group_counts(const uint32_t* gn, const uint32_t* wlist, i
 }
 
 hipError_t launch_sort_y_runs(const YSlot* ytab, int64_t nslots, YEntry* yg, int64_t ny, uint16_t* ykey16,
-                              double* yval, DevStatus* st, int num_cus, hipStream_t stream) {
+                              double* yval, DevStatus* st, bool sort, int num_cus, hipStream_t stream) {
   if (nslots <= 0 || ny <= 0) return hipSuccess;
   int64_t grid = nslots < (int64_t)num_cus * 2 ? nslots : (int64_t)num_cus * 2;
-  k_sort_y_runs<<<dim3((unsigned)grid), kBBlock, 0, stream>>>(ytab, nslots, yg, ny, ykey16, yval, st);
+  if (sort)
+    k_sort_y_runs<true><<<dim3((unsigned)grid), kBBlock, 0, stream>>>(ytab, nslots, yg, ny, ykey16, yval, st);
+  else
+    k_sort_y_runs<false><<<dim3((unsigned)grid), kBBlock, 0, stream>>>(ytab, nslots, yg, ny, ykey16, yval, st);
   return hipGetLastError();
 }
 

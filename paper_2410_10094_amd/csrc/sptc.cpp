@@ -512,7 +512,8 @@ sptc_status plan_group_y(sptc_plan_s* P, const sptc_coo* Y) {
     HIP_TRY(launch_y_scatter(Y->idx, Y->val, P->ny, P->y_c, P->y_f, P->yb, P->ytab, P->ygeom, seed, P->max_probe_y,
                              P->yg, P->yset, (uint64_t)P->yset_slots - 1, yset_bits(P), P->st, P->num_cus, s));
   if (P->opt.mode == SPTC_MODE_GROUPED && P->dense) {
-    HIP_TRY(launch_sort_y_runs(P->ytab, P->ytab_slots, P->yg, P->ny, P->ykey16, P->yval, P->st, P->num_cus, s));
+    // the runs are sorted later, for the block walk only (plan_grouped)
+    HIP_TRY(launch_sort_y_runs(P->ytab, P->ytab_slots, P->yg, P->ny, P->ykey16, P->yval, P->st, false, P->num_cus, s));
     HIP_TRY(launch_y_cells(P->ykey16, P->ny, P->ycolbits, P->st, P->num_cus, s));
   }
   HIP_TRY(mark(P, s, SPTC_STAGE_Y_SCATTER, 1));
@@ -548,12 +549,13 @@ sptc_status plan_global(sptc_plan_s* P, const sptc_coo* X) {
 // device-memory output hash.
 // Rows x columns x runs of the matrix-core block class (padded to whole
 // tiles) may be this many times its products.  Measured on the block-sparse
-// 48^4 workload (work 12.9x its products): the dense product takes 1.03 ms
-// where the walk takes 1.33 ms, and building the panels costs 0.28 ms where
-// the walk's sort costs 0.09 ms -- 2.03 against 2.08 ms per step.  Per unit,
-// the walk spends about 18x what the dense product spends per multiply-add,
-// and the panels' fixed cost brings the break-even to about 14x.
-constexpr double kMfmaWorkRatio = 14.0;
+// 48^4 workload (work 12.9x its products): the dense product takes 0.59 ms
+// where the walk takes 1.33 ms, and the panels cost 0.18 ms of plan time
+// where the walk's sorts cost 0.2 ms.  Per unit the walk spends about 30x
+// what the dense product spends per multiply-add; the panels' cost, which
+// grows with the padded rows and columns rather than the products, brings
+// the break-even down to about 24x.
+constexpr double kMfmaWorkRatio = 24.0;
 // Largest dense X and Y panels the class builds (bytes); beyond, the walk.
 constexpr int64_t kMfmaMaxPanelBytes = (int64_t)8 << 30;
 
@@ -602,14 +604,11 @@ sptc_status plan_block_mfma(sptc_plan_s* P) {
   if ((st = P->allocate_n(bblocks * kMfmaK * kMfmaCols, &pb))) return st;
   if ((st = P->allocate_n(bblocks * kMfmaCols, &bm))) return st;
   HIP_TRY(hipMemsetAsync(P->msv, 0, sizeof(MfmaSurvey), s));
-  HIP_TRY(hipMemsetAsync(pa, 0, sizeof(double) * ablocks * kMfmaK * kMfmaRows, s));
-  HIP_TRY(hipMemsetAsync(am, 0, sizeof(unsigned) * ablocks * kMfmaRows, s));
   HIP_TRY(hipMemsetAsync(pb, 0, sizeof(double) * bblocks * kMfmaK * kMfmaCols, s));
-  HIP_TRY(hipMemsetAsync(bm, 0, sizeof(unsigned) * bblocks * kMfmaCols, s));
   HIP_TRY(launch_mfma_runs(P->ytab, P->ytab_slots, P->ny, P->run_start, runid, P->msv, P->tile_sums, s));
   HIP_TRY(launch_mfma_panels(P->ycolbits, P->groups, P->blist, P->nb, P->eoff, P->xr, P->run_start, runid,
                              (unsigned)nruns, P->ykey16, P->yval, P->ny, P->colid, P->cellof, cells, (unsigned)nsteps,
-                             pa, am, pb, bm, P->msv, P->st, P->num_cus, s));
+                             P->ydup, pa, am, pb, bm, P->msv, P->st, P->num_cus, s));
   MfmaSurvey hs{};
   HIP_TRY(hipMemcpyAsync(&hs, P->msv, sizeof hs, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -682,8 +681,13 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
       if ((st = P->allocate_n(P->nb, &P->bneff))) return st;
       HIP_TRY(mark(P, s, SPTC_STAGE_X_SORT, 0));
       if (mfma_candidate(P) && (st = plan_block_mfma(P))) return st;
-      if (!P->block_mfma)  // the walk merges each group's entries in Y-run order
+      if (!P->block_mfma) {
+        // the walk merges each group's entries in Y-run order, and walks
+        // runs sorted by Y free key (consecutive accumulator cells)
+        HIP_TRY(launch_sort_y_runs(P->ytab, P->ytab_slots, P->yg, P->ny, P->ykey16, P->yval, P->st, true,
+                                   P->num_cus, s));
         HIP_TRY(launch_sort_block_entries(P->groups, P->blist, P->nb, P->xr, P->bneff, P->num_cus, s));
+      }
       HIP_TRY(mark(P, s, SPTC_STAGE_X_SORT, 1));
     }
   }

@@ -153,12 +153,12 @@ struct alignas(16) MfmaSurvey {
 };
 constexpr int kCellWords = (1 << kDenseBits) / 32;  // bitmap of the dense Y free cells
 
-// What the matrix-core block kernel reads besides GroupArgs: X and Y as
-// dense panels, one block per (tile, step) -- X transposed,
-// a[((rt * nsteps + s) * kMfmaK + k) * kMfmaRows + row], Y
-// b[((ct * nsteps + s) * kMfmaK + k) * kMfmaCols + col] -- and per (tile,
-// step) the runs each row and column holds an entry of,
-// am[(rt * nsteps + s) * kMfmaRows + row] (bit k), bm likewise.
+// What the matrix-core block kernel reads besides GroupArgs: X as a dense
+// row-major panel over the padded rows and runs, a[row * (nsteps * kMfmaK)
+// + run], with am[row * nsteps + step] the runs of each step the row holds
+// an entry of (bit k); Y as dense blocks, one per (column tile, step),
+// b[((ct * nsteps + s) * kMfmaK + k) * kMfmaCols + col], with
+// bm[(ct * nsteps + s) * kMfmaCols + col] likewise.
 struct MfmaPlan {
   const double* a;
   const unsigned* am;
@@ -346,16 +346,17 @@ hipError_t launch_y_cells(const uint16_t* ykey16, int64_t ny, unsigned* colbits,
 // (run_start[0..nruns], the last entry ny; runid[ny] gets each run's index
 // at its start; sv->nruns).  panels: columns (colid [2^kDenseBits], cellof
 // [ncols], from colbits) and the panels of MfmaPlan, which must be zeroed
-// first, while surveying the class into sv (zeroed first): its products and
-// whether its X values and the Y values are finite.
+// first (the Y blocks; the X panel and the masks are written whole), while
+// surveying the class into sv (zeroed first): its products and whether its X
+// values and the Y values are finite.
 hipError_t launch_mfma_runs(const YSlot* ytab, int64_t yslots, int64_t ny, unsigned* run_start, unsigned* runid,
                             MfmaSurvey* sv, void* tile_sums, hipStream_t stream);
 hipError_t launch_mfma_panels(const unsigned* colbits, const GroupRec* groups, const uint32_t* blist, int64_t nb,
                               const unsigned long long* eoff, const XRec* xr, const unsigned* run_start,
                               const unsigned* runid, unsigned nruns, const uint16_t* ykey16, const double* yval,
                               int64_t ny, uint16_t* colid, uint16_t* cellof, unsigned ncols, unsigned nsteps,
-                              double* a, unsigned* am, double* b, unsigned* bm, MfmaSurvey* sv, DevStatus* st,
-                              int num_cus, hipStream_t stream);
+                              int ydup, double* a, unsigned* am, double* b, unsigned* bm, MfmaSurvey* sv,
+                              DevStatus* st, int num_cus, hipStream_t stream);
 // Execute: every block group's outputs (one atomic per tile on st->out_base).
 hipError_t launch_group_block_mfma(const GroupArgs& a, const uint32_t* blist, int64_t nb, const MfmaPlan& m,
                                    int num_cus, hipStream_t stream);
@@ -373,11 +374,11 @@ hipError_t launch_scan_group_counts(const uint32_t* gn, const uint32_t* wlist, i
 // *out_nnz = st->out_base, or the negated status.
 hipError_t launch_finalize(int64_t* out_nnz, int64_t out_cap, DevStatus* st, hipStream_t stream);
 
-// Sorts Y runs of 2..1024 entries by Y free key (dense Y free keys only) and
-// writes the compact copy of grouped Y (16-bit keys, values) the dense
-// accumulators read.
+// Dense Y free keys: writes the compact copy of grouped Y (16-bit keys,
+// values) the dense accumulators read and flags repeated Y coordinates;
+// with sort, first sorts each run of 2..1024 entries by Y free key.
 hipError_t launch_sort_y_runs(const YSlot* ytab, int64_t nslots, YEntry* yg, int64_t ny, uint16_t* ykey16,
-                              double* yval, DevStatus* st, int num_cus, hipStream_t stream);
+                              double* yval, DevStatus* st, bool sort, int num_cus, hipStream_t stream);
 
 // Clears st->err and st->out_base.
 hipError_t launch_reset_status(DevStatus* st, hipStream_t stream);
