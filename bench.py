@@ -484,9 +484,11 @@ def roofline_of(r):
         # the block class ran as a dense FP64 product: its multiply-adds over
         # the padded tiles against the matrix cores' FP64 peak
         dense = 2.0 * work / (ms * 1e-3) / 1e12
+        useful = 2.0 * r["products"] / (ms * 1e-3) / 1e12
         out["matrix_cores"] = {"kernel": "k_group_block_mfma", "dense_flops_per_launch": 2 * work,
                                "achieved_tflops": round(dense, 2), "peak_tflops": FP64_MFMA_PEAK_TFLOPS,
-                               "frac": round(dense / FP64_MFMA_PEAK_TFLOPS, 4)}
+                               "frac": round(dense / FP64_MFMA_PEAK_TFLOPS, 4),
+                               "useful_flops_per_launch": 2 * r["products"], "useful_tflops": round(useful, 2)}
     return out
 
 
