@@ -104,3 +104,38 @@ def test_long_y_runs_and_large_groups():
     info, gidx, gval = run_gpu(q, options=_opts(1))
     assert info["classes"]["block"] > 0 and info["block_mfma"], info
     assert_parity(q, gidx, gval)
+
+
+def test_matrix_core_execute_is_graph_capturable():
+    """Execute enqueues kernels only, so a plan on the matrix cores can be
+    captured in a HIP graph; replays with eager work between them reproduce
+    the oracle's result."""
+    import paper_2410_10094_amd as sptc
+    from tests.gpu_common import to_device
+    import oracle
+    p = _dense_random(38, 700, 300, 900, 50_000, 50_000, name="graph")
+    ref = oracle.contract(p.X, p.Y, p.cx, p.cy)
+    X, Y = to_device(p)
+    with sptc.plan(X, Y, p.cx, p.cy, options=_opts(1)) as pl:
+        assert pl.block_mfma
+        idx, val, nnz, cap = pl.allocate_outputs()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            pl.execute_into(idx, val, cap, nnz, stream=s)  # warm-up outside capture
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            pl.execute_into(idx, val, cap, nnz, stream=s)
+        for rep in range(3):
+            idx.fill_(-1)
+            val.fill_(float("nan"))
+            nnz.fill_(-99)
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            n = int(nnz.item())
+            log(f"[mfma graph] replay {rep} nnz {n}")
+            assert n >= 0
+            assert_parity(p, idx[:, :n].cpu().numpy(), val[:n].cpu().numpy(), ref=ref)
