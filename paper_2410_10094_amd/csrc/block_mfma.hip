@@ -383,20 +383,55 @@ __global__ __launch_bounds__(kMBlock, 3) void k_group_block_mfma(GroupArgs a, co
     wbase = __shfl(wbase, 0);
     if (tid == 0) s_base = total ? atomicAdd(&a.st->out_base, total) : 0ull;
     __syncthreads();
-    unsigned long long run = s_base + wbase;
+    // position of each accumulator's output after the wave's base (~0u: no
+    // output, or past the capacity)
+    const unsigned long long base = s_base + wbase;
+    const unsigned long long room = (int64_t)base < a.out_cap ? (unsigned long long)a.out_cap - base : 0ull;
+    unsigned rel[4][4];
+    unsigned run = 0;
 #pragma unroll
     for (int c = 0; c < 4; ++c)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const bool has = (sbits >> (4 * c + q)) & 1u;
         const unsigned long long m = __ballot(has);
-        if (has) {
-          const unsigned long long pos = run + __popcll(m & ((1ull << lane) - 1ull));
-          const unsigned row = 16 * wave + (lane >> 4) + 4 * q, col = 16 * c + (lane & 15);
-          if ((int64_t)pos < a.out_cap) write_output(a, pos, s_phi[row], s_cell[col], acc[c][q]);
-        }
-        run += __popcll(m);
+        const unsigned r = run + (unsigned)__popcll(m & ((1ull << lane) - 1ull));
+        rel[c][q] = has && r < room ? r : ~0u;
+        run += (unsigned)__popcll(m);
       }
+    // one output row (coordinate mode) at a time: the loops over modes stay
+    // rolled, so the kernel's code stays small
+    unsigned long long rphi[4];
+    unsigned ccell[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) rphi[q] = s_phi[16 * wave + (lane >> 4) + 4 * q];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) ccell[c] = s_cell[16 * c + (lane & 15)];
+    const int nx = a.ux.n, ny = a.uy.n;
+    for (int d = 0; d < nx; ++d) {
+      const unsigned sh = a.ux.shift[d], bt = a.ux.bits[d];
+      int32_t* dst = a.out_idx + (int64_t)d * a.out_cap + (int64_t)base;
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (rel[c][q] != ~0u) __builtin_nontemporal_store(key_field(rphi[q], sh, bt), dst + rel[c][q]);
+    }
+    for (int d = 0; d < ny; ++d) {
+      const unsigned sh = a.uy.shift[d], bt = a.uy.bits[d];
+      int32_t* dst = a.out_idx + (int64_t)(nx + d) * a.out_cap + (int64_t)base;
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (rel[c][q] != ~0u) __builtin_nontemporal_store(key_field(ccell[c], sh, bt), dst + rel[c][q]);
+    }
+    double* vdst = a.out_val + base;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (rel[c][q] != ~0u) __builtin_nontemporal_store(acc[c][q], vdst + rel[c][q]);
     __syncthreads();  // the next tile rewrites the row and column tables
   }
 }

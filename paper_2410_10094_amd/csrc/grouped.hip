@@ -1041,15 +1041,40 @@ __global__ __launch_bounds__(kDBlock) void k_group_direct(GroupArgs a, const uin
 #pragma unroll
     for (int it = 0; it < kDItems; ++it)
       if (ys[it] != ~0ull) ye[it] = a.yg[ys[it]];
+    if constexpr (BATCH) {
 #pragma unroll
-    for (int it = 0; it < kDItems; ++it) {
-      const uint64_t q = p0 + (uint64_t)it * kDBlock + threadIdx.x;
-      if (ys[it] == ~0ull) continue;
-      if constexpr (BATCH)
+      for (int it = 0; it < kDItems; ++it) {
+        const uint64_t q = p0 + (uint64_t)it * kDBlock + threadIdx.x;
+        if (ys[it] == ~0ull) continue;
         batch_store(a.bout, a.out_idx, a.out_val, a.bwx, (uint32_t)(phx[it] >> a.bwx), q - dsh[it], phx[it],
                     ye[it].phi, __dmul_rn(xv[it], ye[it].v), a.st);
-      else if ((int64_t)q < a.out_cap)
-        write_output(a, q, phx[it], ye[it].phi, __dmul_rn(xv[it], ye[it].v));
+      }
+    } else {
+      // one output row (coordinate mode) at a time over all items: the
+      // loops over modes stay rolled, so the kernel's code stays small
+      const uint64_t q0 = p0 + threadIdx.x;
+      bool put[kDItems];
+#pragma unroll
+      for (int it = 0; it < kDItems; ++it)
+        put[it] = ys[it] != ~0ull && (int64_t)(q0 + (uint64_t)it * kDBlock) < a.out_cap;
+      const int nx = a.ux.n, ny = a.uy.n;
+      for (int d = 0; d < nx; ++d) {
+        const unsigned sh = a.ux.shift[d], bt = a.ux.bits[d];
+        int32_t* dst = a.out_idx + (int64_t)d * a.out_cap + (int64_t)q0;
+#pragma unroll
+        for (int it = 0; it < kDItems; ++it)
+          if (put[it]) __builtin_nontemporal_store(key_field(phx[it], sh, bt), dst + it * kDBlock);
+      }
+      for (int d = 0; d < ny; ++d) {
+        const unsigned sh = a.uy.shift[d], bt = a.uy.bits[d];
+        int32_t* dst = a.out_idx + (int64_t)(nx + d) * a.out_cap + (int64_t)q0;
+#pragma unroll
+        for (int it = 0; it < kDItems; ++it)
+          if (put[it]) __builtin_nontemporal_store(key_field(ye[it].phi, sh, bt), dst + it * kDBlock);
+      }
+#pragma unroll
+      for (int it = 0; it < kDItems; ++it)
+        if (put[it]) __builtin_nontemporal_store(__dmul_rn(xv[it], ye[it].v), a.out_val + q0 + it * kDBlock);
     }
     __syncthreads();
   }
@@ -1153,7 +1178,7 @@ __global__ void k_x_groups(const GroupRec* __restrict__ groups, int64_t ng, cons
     const GroupRec G = groups[g];
 #pragma unroll
     for (int m = 0; m < kMaxOrder; ++m)
-      if (m < ku.n) coords[(int64_t)m * cap + g] = (int32_t)((G.phi >> ku.shift[m]) & ku.mask[m]);
+      if (m < ku.n) coords[(int64_t)m * cap + g] = key_field(G.phi, ku.shift[m], ku.bits[m]);
     counts[g] = G.count;
     products[g] = (int64_t)(eoff[G.start + G.count] - eoff[G.start]);
   }

@@ -264,7 +264,7 @@ struct OccupancyOp {
 #pragma unroll
     for (int m = 0; m < kMaxOutOrder; ++m)
       if (m < ku.n)
-        __builtin_nontemporal_store((int32_t)((z.key >> ku.shift[m]) & ku.mask[m]),
+        __builtin_nontemporal_store(key_field(z.key, ku.shift[m], ku.bits[m]),
                                     &out_idx[(int64_t)m * out_cap + (int64_t)pos]);
     __builtin_nontemporal_store(z.val, &out_val[pos]);
   }
@@ -321,12 +321,12 @@ struct GroupedOccupancyOp {
 #pragma unroll
     for (int m = 0; m < kMaxOrder; ++m)
       if (m < ux.n)
-        __builtin_nontemporal_store((int32_t)((phix >> ux.shift[m]) & ux.mask[m]),
+        __builtin_nontemporal_store(key_field(phix, ux.shift[m], ux.bits[m]),
                                     &out_idx[(int64_t)m * out_cap + (int64_t)pos]);
 #pragma unroll
     for (int m = 0; m < kMaxOrder; ++m)
       if (m < uy.n)
-        __builtin_nontemporal_store((int32_t)((phiy >> uy.shift[m]) & uy.mask[m]),
+        __builtin_nontemporal_store(key_field(phiy, uy.shift[m], uy.bits[m]),
                                     &out_idx[(int64_t)(ux.n + m) * out_cap + (int64_t)pos]);
     __builtin_nontemporal_store(z.val, &out_val[pos]);
   }
@@ -346,7 +346,7 @@ struct YGroupsOp {
     const YSlot y = tab[i];
 #pragma unroll
     for (int m = 0; m < kMaxOrder; ++m)
-      if (m < ku.n) key_coords[(int64_t)m * cap + (int64_t)pos] = (int32_t)((y.key >> ku.shift[m]) & ku.mask[m]);
+      if (m < ku.n) key_coords[(int64_t)m * cap + (int64_t)pos] = key_field(y.key, ku.shift[m], ku.bits[m]);
     counts[pos] = y.count;
     starts[pos] = y.start;
   }
@@ -363,7 +363,7 @@ __global__ void k_y_grouped(const YEntry* __restrict__ yg, int64_t nnz, KeyUnpac
     const YEntry y = yg[e];
 #pragma unroll
     for (int m = 0; m < kMaxOrder; ++m)
-      if (m < ku.n) coords[(int64_t)m * nnz + e] = (int32_t)((y.phi >> ku.shift[m]) & ku.mask[m]);
+      if (m < ku.n) coords[(int64_t)m * nnz + e] = key_field(y.phi, ku.shift[m], ku.bits[m]);
     vals[e] = y.v;
   }
 }
@@ -395,40 +395,96 @@ __global__ __launch_bounds__(kAggBlock) void k_key_count_agg(const int32_t* __re
   for (unsigned s = threadIdx.x; s < nslots; s += kAggBlock) row[s] = s_cnt[s];
 }
 
-// The chunk histograms, taken key-major (key s, then chunk w), become by an
-// exclusive scan in place the first position of key s's entries of chunk w:
-// the start of s's run plus the entries of s in earlier chunks.
-struct AggOffsetsOp {
-  unsigned* hist;  // [nchunks][nslots]
-  int64_t nchunks;
-  unsigned nslots;
-  __device__ unsigned* cell(int64_t i) const {
-    return hist + (size_t)(i % nchunks) * nslots + (size_t)(i / nchunks);
+// The chunk histograms, taken key-major (key s, then chunk w), become the
+// first position of key s's entries of chunk w: the start of s's run plus
+// the entries of s in earlier chunks.  Two coalesced passes instead of one
+// scan in key-major order (whose reads stride across the rows):
+//
+// k_agg_colscan: one workgroup per kColSlots consecutive keys (a 128-byte
+// segment of every row); its kColRows thread rows split the chunks, sum
+// their share, scan those sums down each key's column in LDS and rewrite
+// their chunks with the column's exclusive prefix.  Key s's total lands in
+// row nchunks.
+constexpr int kColSlots = 32;
+constexpr int kColRows = kAggBlock / kColSlots;
+
+__global__ __launch_bounds__(kAggBlock) void k_agg_colscan(unsigned* __restrict__ hist, unsigned nchunks,
+                                                           unsigned nslots) {
+  __shared__ unsigned s_part[kColRows][kColSlots + 1];
+  const unsigned col = threadIdx.x % kColSlots, r = threadIdx.x / kColSlots;
+  const unsigned s = blockIdx.x * kColSlots + col;
+  const unsigned per = (nchunks + kColRows - 1) / kColRows;
+  const unsigned c0 = r * per < nchunks ? r * per : nchunks;
+  const unsigned c1 = c0 + per < nchunks ? c0 + per : nchunks;
+  unsigned sum = 0;
+  if (s < nslots) {
+#pragma unroll 4
+    for (unsigned c = c0; c < c1; ++c) sum += hist[(size_t)c * nslots + s];
   }
-  __device__ unsigned long long get(int64_t i) const { return *cell(i); }
-  __device__ void put(int64_t i, unsigned long long excl, unsigned long long) const { *cell(i) = (unsigned)excl; }
-};
+  s_part[r][col] = sum;
+  __syncthreads();
+  if (r == 0) {
+    unsigned run = 0;
+    for (int k = 0; k < kColRows; ++k) {
+      const unsigned t = s_part[k][col];
+      s_part[k][col] = run;
+      run += t;
+    }
+    if (s < nslots) hist[(size_t)nchunks * nslots + s] = run;
+  }
+  __syncthreads();
+  if (s < nslots) {
+    unsigned run = s_part[r][col];
+    for (unsigned c = c0; c < c1; ++c) {
+      unsigned* cell = hist + (size_t)c * nslots + s;
+      const unsigned v = *cell;
+      *cell = run;
+      run += v;
+    }
+  }
+}
 
-struct FinAggTotal {
-  unsigned long long* total;
-  __device__ void operator()(unsigned long long t) const { *total = t; }
-};
+// k_agg_slotscan (one workgroup): an exclusive scan of the key totals in
+// row nchunks turns them into run starts in place; every occurring key gets
+// its table entry (count and run start), and *total the entry count.
+constexpr unsigned kSlotsPerThread = 8;
+static_assert((1u << kAggBits) <= kAggBlock * kSlotsPerThread, "one workgroup scans every key");
 
-// Key table from the scanned histograms: key s's run starts at its chunk-0
-// position and ends where key s + 1's starts.
-__global__ void k_agg_table(const unsigned* __restrict__ hist, unsigned nslots, const unsigned long long* total,
-                            YSlot* __restrict__ tab, unsigned long long* distinct) {
-  const unsigned s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nslots) return;
-  const unsigned start = hist[s];
-  const unsigned end = s + 1 < nslots ? hist[s + 1] : (unsigned)*total;
-  if (end == start) return;
-  YSlot t;
-  t.key = s;
-  t.count = end - start;
-  t.start = start;
-  tab[s] = t;
-  if (distinct) atomicAdd(distinct, 1ull);
+__global__ __launch_bounds__(kAggBlock) void k_agg_slotscan(unsigned* __restrict__ hist, unsigned nchunks,
+                                                            unsigned nslots, unsigned long long* __restrict__ total,
+                                                            YSlot* __restrict__ tab,
+                                                            unsigned long long* __restrict__ distinct) {
+  __shared__ unsigned long long s_wave[kAggBlock / 64 + 1];
+  unsigned* row = hist + (size_t)nchunks * nslots;
+  const unsigned s0 = threadIdx.x * kSlotsPerThread;
+  unsigned cnt[kSlotsPerThread];
+  unsigned mine = 0, used = 0;
+#pragma unroll
+  for (unsigned k = 0; k < kSlotsPerThread; ++k) {
+    cnt[k] = s0 + k < nslots ? row[s0 + k] : 0u;
+    mine += cnt[k];
+    used += cnt[k] != 0u;
+  }
+  unsigned long long all;
+  unsigned long long run = block_excl_scan<kAggBlock>(mine, s_wave, &all);
+#pragma unroll
+  for (unsigned k = 0; k < kSlotsPerThread; ++k) {
+    if (s0 + k >= nslots) break;
+    row[s0 + k] = (unsigned)run;
+    if (cnt[k]) {
+      YSlot t;
+      t.key = s0 + k;
+      t.count = cnt[k];
+      t.start = (unsigned)run;
+      tab[s0 + k] = t;
+    }
+    run += cnt[k];
+  }
+  const unsigned long long nused = block_sum_t<kAggBlock>((unsigned long long)used, s_wave);
+  if (threadIdx.x == 0) {
+    *total = all;
+    if (distinct) atomicAdd(distinct, nused);
+  }
 }
 
 __global__ __launch_bounds__(kAggBlock) void k_y_scatter_agg(const int32_t* __restrict__ yidx,
@@ -509,17 +565,18 @@ hipError_t launch_y_scatter(const int32_t* yidx, const double* yval, int64_t nnz
 }
 
 hipError_t launch_key_count_agg(const int32_t* idx, int64_t nnz, KeyPack kc, YSlot* tab, unsigned nslots,
-                                unsigned* hist, unsigned long long* total, unsigned long long* tile_sums,
-                                unsigned long long* distinct, hipStream_t stream) {
+                                unsigned* hist, unsigned long long* total, unsigned long long* distinct,
+                                hipStream_t stream) {
   if (nnz <= 0) return hipSuccess;
-  const int64_t chunks = agg_chunks(nnz);
-  k_key_count_agg<<<(unsigned)chunks, kAggBlock, (size_t)nslots * 4, stream>>>(idx, nnz, kc, nslots, hist);
+  if (nslots > (1u << kAggBits)) return hipErrorInvalidValue;
+  const unsigned chunks = (unsigned)agg_chunks(nnz);
+  k_key_count_agg<<<chunks, kAggBlock, (size_t)nslots * 4, stream>>>(idx, nnz, kc, nslots, hist);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  e = device_scan(AggOffsetsOp{hist, chunks, nslots}, chunks * (int64_t)nslots, tile_sums, FinAggTotal{total},
-                  stream);
+  k_agg_colscan<<<(nslots + kColSlots - 1) / kColSlots, kAggBlock, 0, stream>>>(hist, chunks, nslots);
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_agg_table<<<(nslots + 255) / 256, 256, 0, stream>>>(hist, nslots, total, tab, distinct);
+  k_agg_slotscan<<<1, kAggBlock, 0, stream>>>(hist, chunks, nslots, total, tab, distinct);
   return hipGetLastError();
 }
 

@@ -28,7 +28,7 @@ __device__ __forceinline__ uint64_t pack_key(const int32_t* __restrict__ idx, in
   for (int t = 0; t < kMaxOrder; ++t) {
     if (t < kp.n) {
       const uint32_t c = (uint32_t)idx[(int64_t)kp.mode[t] * nnz + e];
-      k |= (uint64_t)(c & kp.mask[t]) << kp.shift[t];
+      k |= (uint64_t)(c & field_mask(kp.bits[t])) << kp.shift[t];
     }
   }
   return k;
@@ -326,8 +326,8 @@ __device__ __forceinline__ void wave_lds_fence() {
 // Per-workgroup LDS aggregation over a chunk of entries (small key spaces)
 // ---------------------------------------------------------------------------
 
-constexpr int kAggBlock = 256;
-constexpr int kAggUnroll = 8;    // entries a thread handles at once (independent memory ops in flight)
+constexpr int kAggBlock = 1024;
+constexpr int kAggUnroll = 4;    // entries a thread handles at once (independent memory ops in flight)
 
 // Walks this workgroup's chunk kAggUnroll entries per thread at a time: f
 // receives the entry indices, their packed keys and which are in range.
@@ -359,9 +359,10 @@ __device__ __forceinline__ void place_chunk(const int32_t* __restrict__ idx, int
                                             unsigned nslots, const unsigned* __restrict__ choff, unsigned* s_cnt,
                                             unsigned* s_base, F place) {
   const unsigned* row = choff + (size_t)blockIdx.x * nslots;
+  const unsigned* start = choff + (size_t)((nnz + kAggChunk - 1) / kAggChunk) * nslots;
   for (unsigned s = threadIdx.x; s < nslots; s += kAggBlock) {
     s_cnt[s] = 0u;
-    s_base[s] = row[s];
+    s_base[s] = start[s] + row[s];
   }
   __syncthreads();
   for_chunk_batches(idx, nnz, kc, [&](const int64_t* e, const uint64_t* keys, const bool* ok) {
@@ -409,12 +410,12 @@ __device__ __forceinline__ void write_output(const GroupArgs& a, unsigned long l
 #pragma unroll
   for (int m = 0; m < kMaxOrder; ++m)
     if (m < a.ux.n)
-      __builtin_nontemporal_store((int32_t)((phix >> a.ux.shift[m]) & a.ux.mask[m]),
+      __builtin_nontemporal_store(key_field(phix, a.ux.shift[m], a.ux.bits[m]),
                                   &a.out_idx[(int64_t)m * a.out_cap + (int64_t)pos]);
 #pragma unroll
   for (int m = 0; m < kMaxOrder; ++m)
     if (m < a.uy.n)
-      __builtin_nontemporal_store((int32_t)((phiy >> a.uy.shift[m]) & a.uy.mask[m]),
+      __builtin_nontemporal_store(key_field(phiy, a.uy.shift[m], a.uy.bits[m]),
                                   &a.out_idx[(int64_t)(a.ux.n + m) * a.out_cap + (int64_t)pos]);
   __builtin_nontemporal_store(v, &a.out_val[pos]);
 }
@@ -437,11 +438,11 @@ __device__ __forceinline__ void batch_store_at(const BatchOut* __restrict__ bout
   int32_t* row = out_idx + d.idx_off + (int64_t)pos;
 #pragma unroll
   for (int m = 0; m < kMaxOrder; ++m)
-    if (m < nx) __builtin_nontemporal_store((int32_t)((fx >> d.ux.shift[m]) & d.ux.mask[m]), row + (int64_t)m * d.cap);
+    if (m < nx) __builtin_nontemporal_store(key_field(fx, d.ux.shift[m], d.ux.bits[m]), row + (int64_t)m * d.cap);
 #pragma unroll
   for (int m = 0; m < kMaxOrder; ++m)
     if (m < ny)
-      __builtin_nontemporal_store((int32_t)((phiy >> d.uy.shift[m]) & d.uy.mask[m]), row + (int64_t)(nx + m) * d.cap);
+      __builtin_nontemporal_store(key_field(phiy, d.uy.shift[m], d.uy.bits[m]), row + (int64_t)(nx + m) * d.cap);
   __builtin_nontemporal_store(v, &out_val[d.val_off + (int64_t)pos]);
 }
 

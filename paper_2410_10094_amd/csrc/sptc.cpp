@@ -408,9 +408,9 @@ KeyPack make_pack(const int64_t* dims, const std::vector<int32_t>& modes, int32_
   int32_t shift = 0;
   for (int32_t k = kp.n - 1; k >= 0; --k) {
     const int32_t b = bits_for(dims[modes[k]]);
-    kp.mode[k] = modes[k];
-    kp.shift[k] = shift;
-    kp.mask[k] = b == 0 ? 0u : (uint32_t)((1ull << b) - 1ull);
+    kp.mode[k] = (uint8_t)modes[k];
+    kp.shift[k] = (uint8_t)shift;
+    kp.bits[k] = (uint8_t)b;
     shift += b;
   }
   *total_bits = shift;
@@ -419,8 +419,8 @@ KeyPack make_pack(const int64_t* dims, const std::vector<int32_t>& modes, int32_
 
 void add_unpack(KeyUnpack& ku, const KeyPack& kp, int32_t extra_shift) {
   for (int32_t k = 0; k < kp.n; ++k) {
-    ku.shift[ku.n] = kp.shift[k] + extra_shift;
-    ku.mask[ku.n] = kp.mask[k];
+    ku.shift[ku.n] = (uint8_t)(kp.shift[k] + extra_shift);
+    ku.bits[ku.n] = kp.bits[k];
     ku.n++;
   }
 }
@@ -489,12 +489,12 @@ sptc_status plan_group_y(sptc_plan_s* P, const sptc_coo* Y) {
   const hipStream_t s = P->stream;
   const uint64_t seed = P->opt.hash_seed;
   sptc_status st;
-  if (P->y_agg && (st = P->allocate_n(agg_chunks(P->ny) * P->ytab_slots, &P->yhist))) return st;
+  if (P->y_agg && (st = P->allocate_n((agg_chunks(P->ny) + 1) * P->ytab_slots, &P->yhist))) return st;
   HIP_TRY(mark(P, s, SPTC_STAGE_Y_COUNT, 0));
   HIP_TRY(launch_fill_empty(P->ytab, P->ytab_slots, nullptr, s));
   if (P->y_agg)
     HIP_TRY(launch_key_count_agg(Y->idx, P->ny, P->y_c, P->ytab, (unsigned)P->ytab_slots, P->yhist, P->agg_total,
-                                 P->tile_sums, &P->st->groups, s));
+                                 &P->st->groups, s));
   else
     HIP_TRY(launch_key_count(Y->idx, P->ny, P->y_c, P->ytab, P->ygeom, seed, P->max_probe_y, P->st,
                              &P->st->groups, P->num_cus, s));
@@ -636,13 +636,13 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
   if ((st = P->allocate_n(P->nx, &P->glist))) return st;
   if ((st = P->allocate_n(P->nx + 1, &P->dpos))) return st;
 
-  if (P->x_agg && (st = P->allocate_n(agg_chunks(P->nx) * P->xtab_slots, &P->xhist))) return st;
+  if (P->x_agg && (st = P->allocate_n((agg_chunks(P->nx) + 1) * P->xtab_slots, &P->xhist))) return st;
 
   HIP_TRY(mark(P, s, SPTC_STAGE_X_PROBE, 0));
   HIP_TRY(launch_fill_empty(P->xtab, P->xtab_slots, nullptr, s));
   if (P->x_agg)
     HIP_TRY(launch_key_count_agg(X->idx, P->nx, P->x_f, P->xtab, (unsigned)P->xtab_slots, P->xhist, P->agg_total,
-                                 P->tile_sums, nullptr, s));
+                                 nullptr, s));
   else
     HIP_TRY(launch_key_count(X->idx, P->nx, P->x_f, P->xtab, P->xgeom, seed, P->max_probe_x, P->st, nullptr,
                              P->num_cus, s));
@@ -757,9 +757,7 @@ sptc_status plan_body(sptc_plan_s* P, const sptc_coo* X, const sptc_coo* Y, cons
     if ((st = P->allocate_n(kCellWords, &P->ycolbits))) return st;
     HIP_TRY(hipMemsetAsync(P->ycolbits, 0, sizeof(unsigned) * kCellWords, P->stream));
   }
-  const int64_t tiles = std::max<int64_t>({scan_tiles(P->ytab_slots), scan_tiles(P->xtab_slots), scan_tiles(P->nx),
-                                          scan_tiles(agg_chunks(P->ny) * P->ytab_slots),
-                                          scan_tiles(agg_chunks(P->nx) * P->xtab_slots)});
+  const int64_t tiles = std::max<int64_t>({scan_tiles(P->ytab_slots), scan_tiles(P->xtab_slots), scan_tiles(P->nx)});
   if ((st = P->allocate_n(2 * (tiles + 1), &P->tile_sums))) return st;  // room for pair-valued scans
   // Y coordinate set (grouped mode): finds repeated Y coordinates, which the
   // direct class cannot have.  With a dense Y free key the run sort finds

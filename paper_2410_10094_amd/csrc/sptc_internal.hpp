@@ -23,13 +23,24 @@ enum : uint32_t {
 
 // Packs chosen modes of one COO tensor into a 64-bit key: coordinate of
 // mode[k] lands at bit shift[k] (the first listed mode is most significant).
+// Fields are bytes (mode < 16, shift < 64, width < 32) so that a kernel's
+// argument block stays small: every field of a pack lives in a handful of
+// scalar registers instead of 48.
 struct KeyPack {
   int32_t n;
-  int32_t mode[kMaxOrder];
-  int32_t shift[kMaxOrder];
-  uint32_t mask[kMaxOrder];  // (1 << bits) - 1: keeps any coordinate inside its field
-  int32_t ident;             // the table keyed by this pack is direct-addressed (slot = key)
+  int32_t ident;              // the table keyed by this pack is direct-addressed (slot = key)
+  uint8_t mode[kMaxOrder];
+  uint8_t shift[kMaxOrder];
+  uint8_t bits[kMaxOrder];    // field width: a coordinate keeps its low `bits` bits
 };
+
+// Mask of a field `bits` wide (bits <= 31).
+__host__ __device__ inline uint32_t field_mask(uint32_t bits) { return (1u << bits) - 1u; }
+
+// Coordinate stored at bit `shift` of `key` in a field `bits` wide.
+__host__ __device__ inline int32_t key_field(uint64_t key, uint32_t shift, uint32_t bits) {
+  return (int32_t)((uint32_t)(key >> shift) & field_mask(bits));
+}
 
 // Keys of at most this many bits index their table directly (no hashing,
 // no probing); of at most kAggBits bits, their counting and placement are
@@ -67,8 +78,8 @@ struct TabGeom {
 // Decodes an output key into out_order coordinates.
 struct KeyUnpack {
   int32_t n;
-  int32_t shift[kMaxOutOrder];
-  uint32_t mask[kMaxOutOrder];
+  uint8_t shift[kMaxOutOrder];
+  uint8_t bits[kMaxOutOrder];
 };
 
 // Slot of the Y contracting-key table: key, number of Y entries with that
@@ -182,13 +193,13 @@ hipError_t launch_key_count(const int32_t* idx, int64_t nnz, KeyPack kc, YSlot* 
 
 // The same for a direct-addressed table of nslots <= 2^kAggBits slots:
 // each workgroup histograms a chunk of kAggChunk entries in LDS into row
-// `chunk` of hist [agg_chunks(nnz)][nslots]; a key-major scan turns the rows
-// into each (key, chunk)'s first position, and the table gets every key's
-// count and run start (no global atomics).  tile_sums: scan scratch for
-// agg_chunks(nnz) * nslots elements; total: one device u64.
+// `chunk` of hist [agg_chunks(nnz) + 1][nslots]; column scans turn row w
+// into the entries of each key in chunks before w, and the last row into
+// each key's run start; the table gets every key's count and run start (no
+// global atomics).  total: one device u64 (the entry count).
 hipError_t launch_key_count_agg(const int32_t* idx, int64_t nnz, KeyPack kc, YSlot* tab, unsigned nslots,
-                                unsigned* hist, unsigned long long* total, unsigned long long* tile_sums,
-                                unsigned long long* distinct, hipStream_t stream);
+                                unsigned* hist, unsigned long long* total, unsigned long long* distinct,
+                                hipStream_t stream);
 
 // Exclusive scan support: tile sums need ceil(n / kScanTile) u64 entries.
 constexpr int kScanBlock = 256;
@@ -211,7 +222,8 @@ hipError_t launch_y_scatter(const int32_t* yidx, const double* yval, int64_t nnz
 
 // Y scatter for a direct-addressed Y table of nslots <= 2^kAggBits slots:
 // each workgroup places its chunk at the run starts plus the chunk offsets
-// (choff: the hist rows left by launch_key_count_agg).
+// (choff: the hist left by launch_key_count_agg; a key's entries of chunk w
+// start at the last row's entry plus row w's).
 hipError_t launch_y_scatter_agg(const int32_t* yidx, const double* yval, int64_t nnz, KeyPack kc, KeyPack kf,
                                 Bounds b, const YSlot* tab, unsigned nslots, const unsigned* choff, YEntry* yg,
                                 unsigned long long* yset, uint64_t yset_mask, uint64_t seed, int32_t bits_y,
