@@ -134,6 +134,7 @@ __global__ __launch_bounds__(1024) void k_mfma_cols(const unsigned* __restrict__
 // class's products and the finiteness of its values are surveyed on the way.
 constexpr unsigned kXChunk = 1920;  // runs per LDS chunk (60 steps)
 constexpr unsigned kXWaves = 4;
+constexpr unsigned kXUnroll = 4;  // entries per lane in flight
 static_assert(kXChunk % kMfmaK == 0, "chunks of whole steps");
 
 __global__ __launch_bounds__(64 * kXWaves) void k_mfma_x_panel(const GroupRec* __restrict__ groups,
@@ -166,19 +167,34 @@ __global__ __launch_bounds__(64 * kXWaves) void k_mfma_x_panel(const GroupRec* _
       for (unsigned j = lane; j < nk; j += 64) v[j] = 0.0;
       for (unsigned j = lane; j < nk / kMfmaK; j += 64) msk[j] = 0u;
       wave_lds_fence();
-      for (unsigned e = lane; e < G.count; e += 64) {
-        const XRec r = xr[G.start + e];
-        if (k0 == 0) bad |= !isfinite(r.v);
-        if (!r.ycnt) continue;
-        const unsigned k = r.ystart < yend ? runid[r.ystart] : 0xffffffffu;
-        if (k >= nruns || run_start[k] != r.ystart) {
-          if (k0 == 0) record_error(st, kErrInternal);
-          continue;
+      // kXUnroll entries per lane at a time: their record, run and run
+      // start loads are in flight together
+      for (unsigned e0 = 0; e0 < G.count; e0 += kXUnroll * 64) {
+        XRec r[kXUnroll];
+        unsigned k[kXUnroll], ks[kXUnroll];
+#pragma unroll
+        for (unsigned u = 0; u < kXUnroll; ++u) {
+          const unsigned e = e0 + u * 64 + lane;
+          r[u] = e < G.count ? xr[G.start + e] : XRec{0u, 0u, 0.0};
         }
-        if (k < k0 || k >= k0 + nk) continue;
-        const unsigned kk = (unsigned)(k - k0);
-        atomicAdd(&v[kk], r.v);
-        atomicOr(&msk[kk / kMfmaK], 1u << (kk % kMfmaK));
+#pragma unroll
+        for (unsigned u = 0; u < kXUnroll; ++u)
+          k[u] = r[u].ycnt && r[u].ystart < yend ? runid[r[u].ystart] : 0xffffffffu;
+#pragma unroll
+        for (unsigned u = 0; u < kXUnroll; ++u) ks[u] = k[u] < nruns ? run_start[k[u]] : 0xffffffffu;
+#pragma unroll
+        for (unsigned u = 0; u < kXUnroll; ++u) {
+          if (k0 == 0) bad |= !isfinite(r[u].v);
+          if (!r[u].ycnt) continue;
+          if (k[u] >= nruns || ks[u] != r[u].ystart) {
+            if (k0 == 0) record_error(st, kErrInternal);
+            continue;
+          }
+          if (k[u] < k0 || k[u] >= k0 + nk) continue;
+          const unsigned kk = (unsigned)(k[u] - k0);
+          atomicAdd(&v[kk], r[u].v);
+          atomicOr(&msk[kk / kMfmaK], 1u << (kk % kMfmaK));
+        }
       }
       wave_lds_fence();
       double* dst = a + (size_t)i * K + k0;  // 16-byte aligned: K and k0 are even
@@ -193,14 +209,15 @@ __global__ __launch_bounds__(64 * kXWaves) void k_mfma_x_panel(const GroupRec* _
 
 // Y into its panel, one workgroup per step (its 32 runs), the column
 // numbering staged in LDS: values are stored into the zeroed panel (added
-// when Y repeats a coordinate), and the step's column masks are ORed in LDS
-// and written out whole, so they need no clearing and no global atomics.
+// when Y repeats a coordinate).  A step's entries are split over `split`
+// workgroups; each ORs its column masks in LDS and then its nonzero words
+// into the zeroed mask panel.
 constexpr unsigned kYBlock = 512;
 __global__ __launch_bounds__(kYBlock) void k_mfma_y_panel(const unsigned* __restrict__ run_start, unsigned nruns,
                                                           int64_t ny, const uint16_t* __restrict__ ykey16,
                                                           const double* __restrict__ yval,
                                                           const uint16_t* __restrict__ colid, unsigned nsteps,
-                                                          unsigned ncols, unsigned nct, int ydup,
+                                                          unsigned split, unsigned ncols, unsigned nct, int ydup,
                                                           double* __restrict__ b, unsigned* __restrict__ bm,
                                                           MfmaSurvey* sv, DevStatus* st) {
   constexpr unsigned kCells = 1u << kDenseBits;
@@ -209,7 +226,9 @@ __global__ __launch_bounds__(kYBlock) void k_mfma_y_panel(const unsigned* __rest
   __shared__ unsigned s_run[kMfmaK + 1];
   for (unsigned q = threadIdx.x; q < kCells; q += kYBlock) s_col[q] = colid[q];
   const unsigned ncp = nct * kMfmaCols;
-  for (unsigned step = blockIdx.x; step < nsteps; step += gridDim.x) {
+  const unsigned items = nsteps * split;
+  for (unsigned w = blockIdx.x; w < items; w += gridDim.x) {
+    const unsigned step = w / split, part = w % split;
     for (unsigned q = threadIdx.x; q < ncp; q += kYBlock) s_mask[q] = 0u;
     if (threadIdx.x <= kMfmaK) {
       const unsigned k = step * kMfmaK + threadIdx.x;
@@ -218,8 +237,11 @@ __global__ __launch_bounds__(kYBlock) void k_mfma_y_panel(const unsigned* __rest
     __syncthreads();
     // the step's entries: runs of the step are contiguous in grouped Y
     const unsigned lo = s_run[0], hi = s_run[kMfmaK];
-    bool bad = lo > hi || (int64_t)hi > ny;  // runs ascend inside [0, ny) by construction
-    for (unsigned j = bad ? hi : lo + threadIdx.x; j < hi; j += kYBlock) {
+    const bool bad = lo > hi || (int64_t)hi > ny;  // runs ascend inside [0, ny) by construction
+    const unsigned len = bad ? 0u : hi - lo;
+    const unsigned plo = lo + (unsigned)((unsigned long long)len * part / split);
+    const unsigned phi = lo + (unsigned)((unsigned long long)len * (part + 1) / split);
+    for (unsigned j = plo + threadIdx.x; j < phi; j += kYBlock) {
       unsigned kk = 0;  // run of j within the step
 #pragma unroll
       for (unsigned half = kMfmaK / 2; half > 0; half >>= 1)
@@ -238,10 +260,10 @@ __global__ __launch_bounds__(kYBlock) void k_mfma_y_panel(const unsigned* __rest
         *dst = v;
       atomicOr(&s_mask[c], 1u << kk);
     }
-    if (bad && threadIdx.x == 0) record_error(st, kErrInternal);
+    if (bad && part == 0 && threadIdx.x == 0) record_error(st, kErrInternal);
     __syncthreads();
     for (unsigned q = threadIdx.x; q < ncp; q += kYBlock)
-      bm[((size_t)(q / kMfmaCols) * nsteps + step) * kMfmaCols + q % kMfmaCols] = s_mask[q];
+      if (s_mask[q]) atomicOr(&bm[((size_t)(q / kMfmaCols) * nsteps + step) * kMfmaCols + q % kMfmaCols], s_mask[q]);
     __syncthreads();
   }
 }
@@ -463,8 +485,14 @@ hipError_t launch_mfma_panels(const unsigned* colbits, const GroupRec* groups, c
   k_mfma_x_panel<<<grid_for(xrows * 64, 64 * kXWaves, num_cus, 4), 64 * kXWaves, 0, stream>>>(
       groups, blist, nb, eoff, xr, runid, run_start, nruns, nsteps, a, am, sv, st);
   const unsigned nct = (ncols + kMfmaCols - 1) / kMfmaCols;
-  k_mfma_y_panel<<<grid_for((int64_t)nsteps * kYBlock, kYBlock, num_cus, 2), kYBlock, 0, stream>>>(
-      run_start, nruns, ny, ykey16, yval, colid, nsteps, ncols, nct, ydup, b, bm, sv, st);
+  if (nsteps == 0) return hipGetLastError();
+  // about two workgroups per compute unit, each with at least a few
+  // entries per thread
+  const int64_t want = (2 * (int64_t)num_cus + nsteps - 1) / nsteps;
+  const int64_t room = ny / ((int64_t)nsteps * 4 * kYBlock);
+  const unsigned split = (unsigned)std::max<int64_t>(1, std::min(want, room));
+  k_mfma_y_panel<<<nsteps * split, kYBlock, 0, stream>>>(run_start, nruns, ny, ykey16, yval, colid, nsteps, split,
+                                                        ncols, nct, ydup, b, bm, sv, st);
   return hipGetLastError();
 }
 

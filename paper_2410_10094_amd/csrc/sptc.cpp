@@ -605,6 +605,7 @@ sptc_status plan_block_mfma(sptc_plan_s* P) {
   if ((st = P->allocate_n(bblocks * kMfmaCols, &bm))) return st;
   HIP_TRY(hipMemsetAsync(P->msv, 0, sizeof(MfmaSurvey), s));
   HIP_TRY(hipMemsetAsync(pb, 0, sizeof(double) * bblocks * kMfmaK * kMfmaCols, s));
+  HIP_TRY(hipMemsetAsync(bm, 0, sizeof(unsigned) * bblocks * kMfmaCols, s));
   HIP_TRY(launch_mfma_runs(P->ytab, P->ytab_slots, P->ny, P->run_start, runid, P->msv, P->tile_sums, s));
   HIP_TRY(launch_mfma_panels(P->ycolbits, P->groups, P->blist, P->nb, P->eoff, P->xr, P->run_start, runid,
                              (unsigned)nruns, P->ykey16, P->yval, P->ny, P->colid, P->cellof, cells, (unsigned)nsteps,

@@ -358,7 +358,7 @@ hipError_t launch_y_cells(const uint16_t* ykey16, int64_t ny, unsigned* colbits,
 // (run_start[0..nruns], the last entry ny; runid[ny] gets each run's index
 // at its start; sv->nruns).  panels: columns (colid [2^kDenseBits], cellof
 // [ncols], from colbits) and the panels of MfmaPlan, which must be zeroed
-// first (the Y blocks; the X panel and the masks are written whole), while
+// first (the Y blocks and their masks; the X panel is written whole), while
 // surveying the class into sv (zeroed first): its products and whether its X
 // values and the Y values are finite.
 hipError_t launch_mfma_runs(const YSlot* ytab, int64_t yslots, int64_t ny, unsigned* run_start, unsigned* runid,
