@@ -132,8 +132,8 @@ __global__ __launch_bounds__(1024) void k_mfma_cols(const unsigned* __restrict__
 // the chunk's step masks, and the chunk is then written out whole (zeros
 // included), so the panel needs no clearing and no global atomics.  The
 // class's products and the finiteness of its values are surveyed on the way.
-constexpr unsigned kXChunk = 1920;  // runs per LDS chunk (60 steps)
-constexpr unsigned kXWaves = 4;
+constexpr unsigned kXChunk = 2560;  // runs per LDS chunk (80 steps)
+constexpr unsigned kXWaves = 1;  // one-wave workgroups: LDS is taken per wave, so more rows fit a CU
 constexpr unsigned kXUnroll = 4;  // entries per lane in flight
 static_assert(kXChunk % kMfmaK == 0, "chunks of whole steps");
 
@@ -482,7 +482,7 @@ hipError_t launch_mfma_panels(const unsigned* colbits, const GroupRec* groups, c
                               DevStatus* st, int num_cus, hipStream_t stream) {
   k_mfma_cols<<<1, 1024, 0, stream>>>(colbits, colid, cellof);
   const int64_t xrows = (nb + kMfmaRows - 1) / kMfmaRows * kMfmaRows;
-  k_mfma_x_panel<<<grid_for(xrows * 64, 64 * kXWaves, num_cus, 4), 64 * kXWaves, 0, stream>>>(
+  k_mfma_x_panel<<<grid_for(xrows * 64, 64 * kXWaves, num_cus, 16), 64 * kXWaves, 0, stream>>>(
       groups, blist, nb, eoff, xr, runid, run_start, nruns, nsteps, a, am, sv, st);
   const unsigned nct = (ncols + kMfmaCols - 1) / kMfmaCols;
   if (nsteps == 0) return hipGetLastError();

@@ -219,6 +219,7 @@ struct ClassifyOp {
     if (dense || d <= (unsigned long long)kBlockCap) return U128{0ull, 1ull};
     return U128{0ull, 0ull};
   }
+  __device__ int64_t live(int64_t) const { return (int64_t)st->xgroups; }
   __device__ U128 get(int64_t g) const { return (unsigned long long)g < st->xgroups ? code(g) : U128{0ull, 0ull}; }
   __device__ void put(int64_t g, U128 excl, U128 v) const {
     if ((unsigned long long)g >= st->xgroups) return;
@@ -249,6 +250,7 @@ struct DirectScanOp {
   unsigned long long* dpos;
   const DevStatus* st;
   __device__ bool valid(int64_t i) const { return (unsigned long long)i < (st->class_lo & 0xffffffffull); }
+  __device__ int64_t live(int64_t) const { return (int64_t)(st->class_lo & 0xffffffffull); }
   __device__ unsigned long long get(int64_t i) const {
     if (!valid(i)) return 0ull;
     const GroupRec G = groups[dlist[i]];

@@ -4,6 +4,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+#include <utility>
+
 #include "../../include/sptc.h"
 #include "sptc_internal.hpp"
 
@@ -150,10 +153,33 @@ __device__ __forceinline__ unsigned long long block_sum(unsigned long long v, un
 // value).  The tile-sum buffer holds scan_tiles(n) + 1 values of V.
 // ---------------------------------------------------------------------------
 
+// An Op may also supply live(n): how many leading elements of the n are in
+// use, read on the device (a count an earlier kernel wrote); tiles past it
+// skip their work.
+template <class Op, class = void>
+struct HasLive : std::false_type {};
+template <class Op>
+struct HasLive<Op, std::void_t<decltype(std::declval<const Op&>().live(int64_t{}))>> : std::true_type {};
+
+template <class Op>
+__device__ __forceinline__ int64_t live_count(const Op& op, int64_t n) {
+  if constexpr (HasLive<Op>::value) {
+    const int64_t m = op.live(n);
+    return m < n ? m : n;
+  } else {
+    return n;
+  }
+}
+
 template <class Op, class V>
 __global__ __launch_bounds__(kScanBlock) void k_tile_reduce(Op op, int64_t n, V* tile_sums) {
   __shared__ V s_wave[kScanBlock / 64 + 1];
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  n = live_count(op, n);
+  if (base >= n) {  // uniform across the block
+    if (threadIdx.x == 0) tile_sums[blockIdx.x] = V{};
+    return;
+  }
   V s{};
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
@@ -198,6 +224,7 @@ template <class Op, class V>
 __global__ __launch_bounds__(kScanBlock) void k_tile_scan(Op op, int64_t n, const V* tile_offsets) {
   __shared__ V s_wave[kScanBlock / 64 + 1];
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  n = live_count(op, n);
   V carry = tile_offsets[blockIdx.x];
   for (int k = 0; k < kScanItems; ++k) {
     const int64_t chunk = base + (int64_t)k * kScanBlock;
