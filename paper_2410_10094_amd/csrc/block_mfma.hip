@@ -431,22 +431,22 @@ __global__ __launch_bounds__(kMBlock, 3) void k_group_block_mfma(GroupArgs a, co
     for (int c = 0; c < 4; ++c) ccell[c] = s_cell[16 * c + (lane & 15)];
     const int nx = a.ux.n, ny = a.uy.n;
     for (int d = 0; d < nx; ++d) {
-      const unsigned sh = a.ux.shift[d], bt = a.ux.bits[d];
+      const uint32_t fd = a.ux.field[d];
       int32_t* dst = a.out_idx + (int64_t)d * a.out_cap + (int64_t)base;
 #pragma unroll
       for (int c = 0; c < 4; ++c)
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-          if (rel[c][q] != ~0u) __builtin_nontemporal_store(key_field(rphi[q], sh, bt), dst + rel[c][q]);
+          if (rel[c][q] != ~0u) __builtin_nontemporal_store(key_field(rphi[q], fd), dst + rel[c][q]);
     }
     for (int d = 0; d < ny; ++d) {
-      const unsigned sh = a.uy.shift[d], bt = a.uy.bits[d];
+      const uint32_t fd = a.uy.field[d];
       int32_t* dst = a.out_idx + (int64_t)(nx + d) * a.out_cap + (int64_t)base;
 #pragma unroll
       for (int c = 0; c < 4; ++c)
 #pragma unroll
         for (int q = 0; q < 4; ++q)
-          if (rel[c][q] != ~0u) __builtin_nontemporal_store(key_field(ccell[c], sh, bt), dst + rel[c][q]);
+          if (rel[c][q] != ~0u) __builtin_nontemporal_store(key_field(ccell[c], fd), dst + rel[c][q]);
     }
     double* vdst = a.out_val + base;
 #pragma unroll

@@ -148,11 +148,12 @@ __global__ __launch_bounds__(kAggBlock) void k_x_scatter_agg(const int32_t* __re
                 ProbeSeq ys[kAggUnroll];
                 YSlot slot[kAggUnroll];
                 double v[kAggUnroll];
+                bool inb[kAggUnroll];
+                pack_keys<kAggUnroll>(xidx, nnz, e, ok, kc, ckey);
+                if (b.check)
+                  coords_ok_batch<kAggUnroll>(xidx, nnz, e, ok, b, inb);
 #pragma unroll
-                for (int u = 0; u < kAggUnroll; ++u) {
-                  ckey[u] = ok[u] ? pack_key(xidx, nnz, e[u], kc) : 0ull;
-                  ys[u] = probe_seq(ckey[u], yg, seed);
-                }
+                for (int u = 0; u < kAggUnroll; ++u) ys[u] = probe_seq(ckey[u], yg, seed);
 #pragma unroll
                 for (int u = 0; u < kAggUnroll; ++u) {  // first probes and values, all in flight together
                   if (!ok[u]) continue;
@@ -162,7 +163,7 @@ __global__ __launch_bounds__(kAggBlock) void k_x_scatter_agg(const int32_t* __re
 #pragma unroll
                 for (int u = 0; u < kAggUnroll; ++u) {
                   if (!ok[u]) continue;
-                  if (b.check && !coords_ok(xidx, nnz, e[u], b)) record_error(st, kErrCoord);
+                  if (b.check && !inb[u]) record_error(st, kErrCoord);
                   if ((int64_t)pos[u] >= nnz) {
                     record_error(st, kErrInternal);
                     continue;
@@ -1061,18 +1062,18 @@ __global__ __launch_bounds__(kDBlock) void k_group_direct(GroupArgs a, const uin
         put[it] = ys[it] != ~0ull && (int64_t)(q0 + (uint64_t)it * kDBlock) < a.out_cap;
       const int nx = a.ux.n, ny = a.uy.n;
       for (int d = 0; d < nx; ++d) {
-        const unsigned sh = a.ux.shift[d], bt = a.ux.bits[d];
+        const uint32_t fd = a.ux.field[d];
         int32_t* dst = a.out_idx + (int64_t)d * a.out_cap + (int64_t)q0;
 #pragma unroll
         for (int it = 0; it < kDItems; ++it)
-          if (put[it]) __builtin_nontemporal_store(key_field(phx[it], sh, bt), dst + it * kDBlock);
+          if (put[it]) __builtin_nontemporal_store(key_field(phx[it], fd), dst + it * kDBlock);
       }
       for (int d = 0; d < ny; ++d) {
-        const unsigned sh = a.uy.shift[d], bt = a.uy.bits[d];
+        const uint32_t fd = a.uy.field[d];
         int32_t* dst = a.out_idx + (int64_t)(nx + d) * a.out_cap + (int64_t)q0;
 #pragma unroll
         for (int it = 0; it < kDItems; ++it)
-          if (put[it]) __builtin_nontemporal_store(key_field(ye[it].phi, sh, bt), dst + it * kDBlock);
+          if (put[it]) __builtin_nontemporal_store(key_field(ye[it].phi, fd), dst + it * kDBlock);
       }
 #pragma unroll
       for (int it = 0; it < kDItems; ++it)
@@ -1180,7 +1181,7 @@ __global__ void k_x_groups(const GroupRec* __restrict__ groups, int64_t ng, cons
     const GroupRec G = groups[g];
 #pragma unroll
     for (int m = 0; m < kMaxOrder; ++m)
-      if (m < ku.n) coords[(int64_t)m * cap + g] = key_field(G.phi, ku.shift[m], ku.bits[m]);
+      if (m < ku.n) coords[(int64_t)m * cap + g] = key_field(G.phi, ku.field[m]);
     counts[g] = G.count;
     products[g] = (int64_t)(eoff[G.start + G.count] - eoff[G.start]);
   }

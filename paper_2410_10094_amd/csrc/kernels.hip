@@ -264,7 +264,7 @@ struct OccupancyOp {
 #pragma unroll
     for (int m = 0; m < kMaxOutOrder; ++m)
       if (m < ku.n)
-        __builtin_nontemporal_store(key_field(z.key, ku.shift[m], ku.bits[m]),
+        __builtin_nontemporal_store(key_field(z.key, ku.field[m]),
                                     &out_idx[(int64_t)m * out_cap + (int64_t)pos]);
     __builtin_nontemporal_store(z.val, &out_val[pos]);
   }
@@ -321,12 +321,12 @@ struct GroupedOccupancyOp {
 #pragma unroll
     for (int m = 0; m < kMaxOrder; ++m)
       if (m < ux.n)
-        __builtin_nontemporal_store(key_field(phix, ux.shift[m], ux.bits[m]),
+        __builtin_nontemporal_store(key_field(phix, ux.field[m]),
                                     &out_idx[(int64_t)m * out_cap + (int64_t)pos]);
 #pragma unroll
     for (int m = 0; m < kMaxOrder; ++m)
       if (m < uy.n)
-        __builtin_nontemporal_store(key_field(phiy, uy.shift[m], uy.bits[m]),
+        __builtin_nontemporal_store(key_field(phiy, uy.field[m]),
                                     &out_idx[(int64_t)(ux.n + m) * out_cap + (int64_t)pos]);
     __builtin_nontemporal_store(z.val, &out_val[pos]);
   }
@@ -346,7 +346,7 @@ struct YGroupsOp {
     const YSlot y = tab[i];
 #pragma unroll
     for (int m = 0; m < kMaxOrder; ++m)
-      if (m < ku.n) key_coords[(int64_t)m * cap + (int64_t)pos] = key_field(y.key, ku.shift[m], ku.bits[m]);
+      if (m < ku.n) key_coords[(int64_t)m * cap + (int64_t)pos] = key_field(y.key, ku.field[m]);
     counts[pos] = y.count;
     starts[pos] = y.start;
   }
@@ -363,7 +363,7 @@ __global__ void k_y_grouped(const YEntry* __restrict__ yg, int64_t nnz, KeyUnpac
     const YEntry y = yg[e];
 #pragma unroll
     for (int m = 0; m < kMaxOrder; ++m)
-      if (m < ku.n) coords[(int64_t)m * nnz + e] = key_field(y.phi, ku.shift[m], ku.bits[m]);
+      if (m < ku.n) coords[(int64_t)m * nnz + e] = key_field(y.phi, ku.field[m]);
     vals[e] = y.v;
   }
 }
@@ -498,24 +498,32 @@ __global__ __launch_bounds__(kAggBlock) void k_y_scatter_agg(const int32_t* __re
   extern __shared__ unsigned s_agg[];
   place_chunk(yidx, nnz, kc, nslots, choff, s_agg, s_agg + nslots,
               [&](const int64_t* e, const uint64_t* keys, const unsigned* pos, const bool* ok) {
-                bool good[kAggUnroll];
+                bool good[kAggUnroll], inb[kAggUnroll];
                 unsigned long long full[kAggUnroll];
+                uint64_t fk[kAggUnroll];
+                double v[kAggUnroll];
+                // every load of the batch in flight before any store
+                pack_keys<kAggUnroll>(yidx, nnz, e, ok, kf, fk);
+                if (b.check)
+                  coords_ok_batch<kAggUnroll>(yidx, nnz, e, ok, b, inb);
+#pragma unroll
+                for (int u = 0; u < kAggUnroll; ++u) v[u] = ok[u] ? yval[e[u]] : 0.0;
 #pragma unroll
                 for (int u = 0; u < kAggUnroll; ++u) {
                   good[u] = ok[u];
                   full[u] = 0ull;
                   if (!ok[u]) continue;
-                  if (b.check && !coords_ok(yidx, nnz, e[u], b)) record_error(st, kErrCoord);
+                  if (b.check && !inb[u]) record_error(st, kErrCoord);
                   if ((int64_t)pos[u] >= nnz) {
                     record_error(st, kErrInternal);
                     good[u] = false;
                     continue;
                   }
                   YEntry ent;
-                  ent.phi = pack_key(yidx, nnz, e[u], kf);
-                  ent.v = yval[e[u]];
+                  ent.phi = fk[u];
+                  ent.v = v[u];
                   yg[pos[u]] = ent;
-                  full[u] = full_y_key(keys[u], ent.phi, bits_y);
+                  full[u] = full_y_key(keys[u], fk[u], bits_y);
                 }
                 if (yset) {
                   bool seen[kAggUnroll];

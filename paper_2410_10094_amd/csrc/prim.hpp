@@ -24,25 +24,103 @@ __device__ __forceinline__ uint64_t fmix64(uint64_t k) {
   return k;
 }
 
+// An entry's coordinates are read kModeGroup modes at a time, every load of
+// a group issued before any is used (modes past n re-read mode n - 1, a
+// cache hit): an order-n key costs ceil(n / kModeGroup) memory round trips,
+// not n.  The loops over the modes stay rolled.
+constexpr int kModeGroup = 4;
+
 __device__ __forceinline__ uint64_t pack_key(const int32_t* __restrict__ idx, int64_t nnz, int64_t e,
                                              const KeyPack& kp) {
   uint64_t k = 0;
+  const int n = kp.n;
+  for (int t0 = 0; t0 < n; t0 += kModeGroup) {
+    uint32_t c[kModeGroup];
 #pragma unroll
-  for (int t = 0; t < kMaxOrder; ++t) {
-    if (t < kp.n) {
-      const uint32_t c = (uint32_t)idx[(int64_t)kp.mode[t] * nnz + e];
-      k |= (uint64_t)(c & field_mask(kp.bits[t])) << kp.shift[t];
+    for (int j = 0; j < kModeGroup; ++j) {
+      const int t = t0 + j < n ? t0 + j : n - 1;
+      c[j] = (uint32_t)idx[(int64_t)field_mode(kp.field[t]) * nnz + e];
+    }
+#pragma unroll
+    for (int j = 0; j < kModeGroup; ++j) {
+      if (t0 + j >= n) continue;
+      const uint32_t f = kp.field[t0 + j];
+      k |= (uint64_t)(c[j] & field_mask(field_bits(f))) << field_shift(f);
     }
   }
   return k;
 }
 
+// The keys of U entries at once (entry u is e[u], read only where ok[u]):
+// two modes of all U entries in flight together.
+template <int U>
+__device__ __forceinline__ void pack_keys(const int32_t* __restrict__ idx, int64_t nnz, const int64_t* e,
+                                          const bool* ok, const KeyPack& kp, uint64_t* keys) {
+#pragma unroll
+  for (int u = 0; u < U; ++u) keys[u] = 0ull;
+  const int n = kp.n;
+  for (int t0 = 0; t0 < n; t0 += 2) {
+    uint32_t c[2][U];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int t = t0 + j < n ? t0 + j : n - 1;
+      const int32_t* col = idx + (int64_t)field_mode(kp.field[t]) * nnz;
+#pragma unroll
+      for (int u = 0; u < U; ++u) c[j][u] = ok[u] ? (uint32_t)col[e[u]] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      if (t0 + j >= n) continue;
+      const uint32_t f = kp.field[t0 + j];
+      const uint32_t m = field_mask(field_bits(f));
+      const unsigned sh = field_shift(f);
+#pragma unroll
+      for (int u = 0; u < U; ++u) keys[u] |= (uint64_t)(c[j][u] & m) << sh;
+    }
+  }
+}
+
+// coords_ok for U entries at once (good[u]; entries with !ok[u] pass).
+template <int U>
+__device__ __forceinline__ void coords_ok_batch(const int32_t* __restrict__ idx, int64_t nnz, const int64_t* e,
+                                                const bool* ok, const Bounds& b, bool* good) {
+#pragma unroll
+  for (int u = 0; u < U; ++u) good[u] = true;
+  const int n = b.order;
+  for (int t0 = 0; t0 < n; t0 += 2) {
+    uint32_t c[2][U];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int t = t0 + j < n ? t0 + j : n - 1;
+      const int32_t* col = idx + (int64_t)t * nnz;
+#pragma unroll
+      for (int u = 0; u < U; ++u) c[j][u] = ok[u] ? (uint32_t)col[e[u]] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      if (t0 + j >= n) continue;
+      const uint32_t d = b.dim[t0 + j];
+#pragma unroll
+      for (int u = 0; u < U; ++u) good[u] = good[u] && c[j][u] < d;
+    }
+  }
+}
+
 // Checks every coordinate of entry e against its mode length.
 __device__ __forceinline__ bool coords_ok(const int32_t* __restrict__ idx, int64_t nnz, int64_t e, const Bounds& b) {
   bool ok = true;
+  const int n = b.order;
+  for (int t0 = 0; t0 < n; t0 += kModeGroup) {
+    uint32_t c[kModeGroup];
 #pragma unroll
-  for (int m = 0; m < kMaxOrder; ++m)
-    if (m < b.order) ok &= (uint32_t)idx[(int64_t)m * nnz + e] < (uint32_t)b.dim[m];
+    for (int j = 0; j < kModeGroup; ++j) {
+      const int t = t0 + j < n ? t0 + j : n - 1;
+      c[j] = (uint32_t)idx[(int64_t)t * nnz + e];
+    }
+#pragma unroll
+    for (int j = 0; j < kModeGroup; ++j)
+      if (t0 + j < n) ok &= c[j] < b.dim[t0 + j];
+  }
   return ok;
 }
 
@@ -371,8 +449,8 @@ __device__ __forceinline__ void for_chunk_batches(const int32_t* __restrict__ id
     for (int u = 0; u < kAggUnroll; ++u) {
       e[u] = base + (int64_t)u * kAggBlock;
       ok[u] = e[u] < c1;
-      keys[u] = ok[u] ? pack_key(idx, nnz, e[u], kp) : 0ull;
     }
+    pack_keys<kAggUnroll>(idx, nnz, e, ok, kp, keys);
     f(e, keys, ok);
   }
 }
@@ -387,9 +465,22 @@ __device__ __forceinline__ void place_chunk(const int32_t* __restrict__ idx, int
                                             unsigned* s_base, F place) {
   const unsigned* row = choff + (size_t)blockIdx.x * nslots;
   const unsigned* start = choff + (size_t)((nnz + kAggChunk - 1) / kAggChunk) * nslots;
-  for (unsigned s = threadIdx.x; s < nslots; s += kAggBlock) {
-    s_cnt[s] = 0u;
-    s_base[s] = start[s] + row[s];
+  // nslots <= 2^kAggBits: all of a thread's loads in flight at once
+  constexpr int kSlotIters = (1 << kAggBits) / kAggBlock;
+  static_assert(kSlotIters * kAggBlock == (1 << kAggBits), "whole rounds of slots");
+  unsigned sb[kSlotIters];
+#pragma unroll
+  for (int k = 0; k < kSlotIters; ++k) {
+    const unsigned s = threadIdx.x + k * kAggBlock < nslots ? threadIdx.x + k * kAggBlock : nslots - 1;
+    sb[k] = start[s] + row[s];  // unconditional (a clamped index), so no branch splits the loads
+  }
+#pragma unroll
+  for (int k = 0; k < kSlotIters; ++k) {
+    const unsigned s = threadIdx.x + k * kAggBlock;
+    if (s < nslots) {
+      s_cnt[s] = 0u;
+      s_base[s] = sb[k];
+    }
   }
   __syncthreads();
   for_chunk_batches(idx, nnz, kc, [&](const int64_t* e, const uint64_t* keys, const bool* ok) {
@@ -437,12 +528,12 @@ __device__ __forceinline__ void write_output(const GroupArgs& a, unsigned long l
 #pragma unroll
   for (int m = 0; m < kMaxOrder; ++m)
     if (m < a.ux.n)
-      __builtin_nontemporal_store(key_field(phix, a.ux.shift[m], a.ux.bits[m]),
+      __builtin_nontemporal_store(key_field(phix, a.ux.field[m]),
                                   &a.out_idx[(int64_t)m * a.out_cap + (int64_t)pos]);
 #pragma unroll
   for (int m = 0; m < kMaxOrder; ++m)
     if (m < a.uy.n)
-      __builtin_nontemporal_store(key_field(phiy, a.uy.shift[m], a.uy.bits[m]),
+      __builtin_nontemporal_store(key_field(phiy, a.uy.field[m]),
                                   &a.out_idx[(int64_t)(a.ux.n + m) * a.out_cap + (int64_t)pos]);
   __builtin_nontemporal_store(v, &a.out_val[pos]);
 }
@@ -465,11 +556,11 @@ __device__ __forceinline__ void batch_store_at(const BatchOut* __restrict__ bout
   int32_t* row = out_idx + d.idx_off + (int64_t)pos;
 #pragma unroll
   for (int m = 0; m < kMaxOrder; ++m)
-    if (m < nx) __builtin_nontemporal_store(key_field(fx, d.ux.shift[m], d.ux.bits[m]), row + (int64_t)m * d.cap);
+    if (m < nx) __builtin_nontemporal_store(key_field(fx, d.ux.field[m]), row + (int64_t)m * d.cap);
 #pragma unroll
   for (int m = 0; m < kMaxOrder; ++m)
     if (m < ny)
-      __builtin_nontemporal_store(key_field(phiy, d.uy.shift[m], d.uy.bits[m]), row + (int64_t)(nx + m) * d.cap);
+      __builtin_nontemporal_store(key_field(phiy, d.uy.field[m]), row + (int64_t)(nx + m) * d.cap);
   __builtin_nontemporal_store(v, &out_val[d.val_off + (int64_t)pos]);
 }
 

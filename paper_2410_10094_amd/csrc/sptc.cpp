@@ -408,9 +408,7 @@ KeyPack make_pack(const int64_t* dims, const std::vector<int32_t>& modes, int32_
   int32_t shift = 0;
   for (int32_t k = kp.n - 1; k >= 0; --k) {
     const int32_t b = bits_for(dims[modes[k]]);
-    kp.mode[k] = (uint8_t)modes[k];
-    kp.shift[k] = (uint8_t)shift;
-    kp.bits[k] = (uint8_t)b;
+    kp.field[k] = make_field((uint32_t)modes[k], (uint32_t)shift, (uint32_t)b);
     shift += b;
   }
   *total_bits = shift;
@@ -419,8 +417,7 @@ KeyPack make_pack(const int64_t* dims, const std::vector<int32_t>& modes, int32_
 
 void add_unpack(KeyUnpack& ku, const KeyPack& kp, int32_t extra_shift) {
   for (int32_t k = 0; k < kp.n; ++k) {
-    ku.shift[ku.n] = (uint8_t)(kp.shift[k] + extra_shift);
-    ku.bits[ku.n] = kp.bits[k];
+    ku.field[ku.n] = make_field(0u, field_shift(kp.field[k]) + (uint32_t)extra_shift, field_bits(kp.field[k]));
     ku.n++;
   }
 }

@@ -23,23 +23,28 @@ enum : uint32_t {
 
 // Packs chosen modes of one COO tensor into a 64-bit key: coordinate of
 // mode[k] lands at bit shift[k] (the first listed mode is most significant).
-// Fields are bytes (mode < 16, shift < 64, width < 32) so that a kernel's
-// argument block stays small: every field of a pack lives in a handful of
-// scalar registers instead of 48.
+// One word per field (mode < 16, shift < 64, width < 32 as bytes 0, 1, 2),
+// so that a kernel's argument block stays small and a field with a uniform
+// index is one scalar load.
 struct KeyPack {
   int32_t n;
   int32_t ident;              // the table keyed by this pack is direct-addressed (slot = key)
-  uint8_t mode[kMaxOrder];
-  uint8_t shift[kMaxOrder];
-  uint8_t bits[kMaxOrder];    // field width: a coordinate keeps its low `bits` bits
+  uint32_t field[kMaxOrder];  // make_field(mode, shift, width): a coordinate keeps its low `width` bits
 };
+
+__host__ __device__ inline uint32_t make_field(uint32_t mode, uint32_t shift, uint32_t bits) {
+  return mode | shift << 8 | bits << 16;
+}
+__host__ __device__ inline uint32_t field_mode(uint32_t f) { return f & 0xffu; }
+__host__ __device__ inline uint32_t field_shift(uint32_t f) { return (f >> 8) & 0xffu; }
+__host__ __device__ inline uint32_t field_bits(uint32_t f) { return (f >> 16) & 0xffu; }
 
 // Mask of a field `bits` wide (bits <= 31).
 __host__ __device__ inline uint32_t field_mask(uint32_t bits) { return (1u << bits) - 1u; }
 
-// Coordinate stored at bit `shift` of `key` in a field `bits` wide.
-__host__ __device__ inline int32_t key_field(uint64_t key, uint32_t shift, uint32_t bits) {
-  return (int32_t)((uint32_t)(key >> shift) & field_mask(bits));
+// Coordinate stored in field f of `key`.
+__host__ __device__ inline int32_t key_field(uint64_t key, uint32_t f) {
+  return (int32_t)((uint32_t)(key >> field_shift(f)) & field_mask(field_bits(f)));
 }
 
 // Keys of at most this many bits index their table directly (no hashing,
@@ -78,8 +83,7 @@ struct TabGeom {
 // Decodes an output key into out_order coordinates.
 struct KeyUnpack {
   int32_t n;
-  uint8_t shift[kMaxOutOrder];
-  uint8_t bits[kMaxOutOrder];
+  uint32_t field[kMaxOutOrder];  // make_field(0, shift, width)
 };
 
 // Slot of the Y contracting-key table: key, number of Y entries with that
