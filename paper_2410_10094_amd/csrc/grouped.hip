@@ -972,25 +972,38 @@ constexpr int kDItemsOne = 8;    // products in flight per lane, one contraction
 constexpr int kDItemsBatch = 5;  // and in a batch (the per-contraction decode takes registers)
 constexpr int kDGroups = 1024;  // groups staged per tile; more fall back to global loads
 
+// First direct group of every product-space tile: tile k's first product
+// (k * tile) lies in group tfirst[k], the nonempty group that holds it, and
+// tfirst[ntiles] = nd.  A thread per group writes the tiles starting in it.
+__global__ __launch_bounds__(256) void k_direct_tiles(const unsigned long long* __restrict__ dpos, int64_t nd,
+                                                      uint64_t tile, uint64_t ntiles, uint32_t* __restrict__ tfirst) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nd; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t lo = dpos[i], hi = dpos[i + 1];
+    for (uint64_t k = (lo + tile - 1) / tile; k < ntiles && k * tile < hi; ++k) tfirst[k] = (uint32_t)i;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) tfirst[ntiles] = (uint32_t)nd;
+}
+
 template <bool BATCH, int kDItems>
 __global__ __launch_bounds__(kDBlock) void k_group_direct(GroupArgs a, const uint32_t* __restrict__ dlist,
                                                           const unsigned long long* __restrict__ dpos, int64_t nd,
-                                                          uint64_t nprod) {
+                                                          uint64_t nprod, const uint32_t* __restrict__ tfirst) {
   constexpr int kDTile = kDBlock * kDItems;
   __shared__ unsigned long long s_pos[kDGroups + 1];
   __shared__ unsigned long long s_phi[kDGroups];
   __shared__ double s_v[kDGroups];
   __shared__ unsigned s_ys[kDGroups];
   __shared__ unsigned long long s_sh[kDGroups];  // batch: the group's contraction's direct shift
-  __shared__ int64_t s_range[2];
   const uint64_t ntiles = (nprod + kDTile - 1) / kDTile;
   for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const uint64_t p0 = t * kDTile;
     const uint64_t p1 = (p0 + kDTile < nprod) ? p0 + kDTile : nprod;
-    if (threadIdx.x == 0) s_range[0] = upper_bound_idx(dpos, 0, nd + 1, p0) - 1;
-    if (threadIdx.x == 64) s_range[1] = upper_bound_idx(dpos, 0, nd + 1, p1 - 1) - 1;
-    __syncthreads();
-    const int64_t ilo = s_range[0], ihi = s_range[1];
+    // the tile's groups: from the one holding p0 to the one holding p1 (or
+    // the last); groups past p1 - 1 start at or after p1, so no product of
+    // the tile maps to them
+    const int64_t f0 = tfirst[t], nxt = tfirst[t + 1];
+    const int64_t ilo = f0 < nd ? f0 : nd - 1;  // (clamped: indices stay inside the list)
+    const int64_t ihi = nxt < ilo ? ilo : (nxt < nd ? nxt : nd - 1);
     const int64_t nloc = ihi - ilo + 1;
     const bool staged = nloc <= kDGroups;
     if (staged) {
@@ -1009,20 +1022,30 @@ __global__ __launch_bounds__(kDBlock) void k_group_direct(GroupArgs a, const uin
     unsigned long long ys[kDItems], phx[kDItems], dsh[BATCH ? kDItems : 1];
     double xv[kDItems];
     YEntry ye[kDItems];
+    // staged: the last staged group starting at or before each item's
+    // product, by a branch-free binary search of all items in step (their
+    // LDS reads interleave); `top` is the largest power of two below nloc
+    int sg[kDItems];
+#pragma unroll
+    for (int it = 0; it < kDItems; ++it) sg[it] = 0;
+    if (staged && nloc > 1) {
+      const int top = 1 << (31 - __clz((int)nloc - 1));
+      for (int step = top; step > 0; step >>= 1) {
+#pragma unroll
+        for (int it = 0; it < kDItems; ++it) {
+          const uint64_t q = p0 + (uint64_t)it * kDBlock + threadIdx.x;
+          const int c = sg[it] + step;
+          if (c < (int)nloc && s_pos[c] <= q) sg[it] = c;
+        }
+      }
+    }
 #pragma unroll
     for (int it = 0; it < kDItems; ++it) {
       const uint64_t q = p0 + (uint64_t)it * kDBlock + threadIdx.x;
       ys[it] = ~0ull;
       if (q >= p1) continue;
       if (staged) {
-        int lo = 0, hi = (int)nloc - 1;
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (s_pos[mid] <= q)
-            lo = mid;
-          else
-            hi = mid - 1;
-        }
+        const int lo = sg[it];
         ys[it] = (unsigned long long)s_ys[lo] + (q - s_pos[lo]);
         phx[it] = s_phi[lo];
         xv[it] = s_v[lo];
@@ -1344,17 +1367,24 @@ hipError_t launch_group_block(const GroupArgs& a, const uint32_t* blist, int64_t
   return hipGetLastError();
 }
 
+int64_t direct_tile_bound(uint64_t nprod) {
+  const uint64_t tile = (uint64_t)kDBlock * (kDItemsBatch < kDItemsOne ? kDItemsBatch : kDItemsOne);
+  return (int64_t)((nprod + tile - 1) / tile) + 1;
+}
+
 hipError_t launch_group_direct(const GroupArgs& a, const uint32_t* dlist, const unsigned long long* dpos, int64_t nd,
-                               uint64_t nprod, int num_cus, hipStream_t stream) {
+                               uint64_t nprod, uint32_t* tfirst, int num_cus, hipStream_t stream) {
   if (nd <= 0 || nprod == 0) return hipSuccess;
+  if (nd >= (int64_t)UINT32_MAX) return hipErrorInvalidValue;
   const int items = a.bout ? kDItemsBatch : kDItemsOne;
   const uint64_t tile = (uint64_t)kDBlock * items, tiles = (nprod + tile - 1) / tile;
+  k_direct_tiles<<<grid_for(nd, 256, num_cus, 8), 256, 0, stream>>>(dpos, nd, tile, tiles, tfirst);
   uint64_t g = (uint64_t)num_cus * 8;
   if (g > tiles) g = tiles;
   if (a.bout)
-    k_group_direct<true, kDItemsBatch><<<dim3((unsigned)g), kDBlock, 0, stream>>>(a, dlist, dpos, nd, nprod);
+    k_group_direct<true, kDItemsBatch><<<dim3((unsigned)g), kDBlock, 0, stream>>>(a, dlist, dpos, nd, nprod, tfirst);
   else
-    k_group_direct<false, kDItemsOne><<<dim3((unsigned)g), kDBlock, 0, stream>>>(a, dlist, dpos, nd, nprod);
+    k_group_direct<false, kDItemsOne><<<dim3((unsigned)g), kDBlock, 0, stream>>>(a, dlist, dpos, nd, nprod, tfirst);
   return hipGetLastError();
 }
 

@@ -291,6 +291,7 @@ struct sptc_plan_s : Workspace {
   XRec* xr = nullptr;
   unsigned long long* eoff = nullptr;
   uint32_t* dlist = nullptr;
+  uint32_t* dtfirst = nullptr;  // direct class: each product tile's first group
   uint32_t* wlist = nullptr;
   uint32_t* blist = nullptr;
   uint32_t* glist = nullptr;
@@ -673,6 +674,9 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
   P->ydup = host.ydup ? 1 : 0;
   P->ycols = host.ycols;
   if (P->ngl < 0) return fail(SPTC_ERR_INTERNAL, "group classes do not add up");
+  if (P->nd > 0 && P->direct_products > 0 &&
+      (st = P->allocate_n(direct_tile_bound((uint64_t)P->direct_products), &P->dtfirst)))
+    return st;
   if (P->nb > 0) {
     HIP_TRY(prepare_group_block());
     if (P->dense) {
@@ -973,7 +977,7 @@ sptc_status execute_plan(sptc_plan_s* P, int32_t* out_idx, double* out_val, int6
     HIP_TRY(launch_group_wave(a, P->wlist, P->nw, 1, P->num_cus, s));
     HIP_TRY(mark(P, s, SPTC_STAGE_GROUP_FILL, 1));
     HIP_TRY(mark(P, s, SPTC_STAGE_DIRECT, 0));
-    HIP_TRY(launch_group_direct(a, P->dlist, P->dpos, P->nd, (uint64_t)P->direct_products, P->num_cus, s));
+    HIP_TRY(launch_group_direct(a, P->dlist, P->dpos, P->nd, (uint64_t)P->direct_products, P->dtfirst, P->num_cus, s));
     HIP_TRY(mark(P, s, SPTC_STAGE_DIRECT, 1));
     HIP_TRY(mark(P, s, SPTC_STAGE_BLOCK, 0));
     if (P->block_mfma)

@@ -379,8 +379,11 @@ hipError_t launch_group_block_mfma(const GroupArgs& a, const uint32_t* blist, in
 
 // Direct class: single-entry groups against a Y without repeated coordinates
 // have one output per product; writes output q for product q in [0, nprod).
+// tfirst: scratch of direct_tile_bound(nprod) u32 (each product tile's first
+// group, found first by a pass over the groups).
+int64_t direct_tile_bound(uint64_t nprod);
 hipError_t launch_group_direct(const GroupArgs& a, const uint32_t* dlist, const unsigned long long* dpos, int64_t nd,
-                               uint64_t nprod, int num_cus, hipStream_t stream);
+                               uint64_t nprod, uint32_t* tfirst, int num_cus, hipStream_t stream);
 
 // goff[g] = base + outputs of wave-list groups before g; st->out_base = base
 // + their total.
