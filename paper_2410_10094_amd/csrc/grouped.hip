@@ -89,6 +89,88 @@ __device__ __forceinline__ XRec probe_y(const int32_t* __restrict__ xidx, int64_
   return r;
 }
 
+// Compact X table for hashed X free keys of at most 31 bits (single
+// contraction): one 64-bit word per slot, key << 32 | count, kEmpty when
+// free, so a table takes half the memory (and cache) of YSlot and a new key
+// is claimed and counted by one compare-and-swap.  After the scan the low
+// half holds the end of the key's run, which placement decrements.
+constexpr unsigned long long kLow32 = 0xffffffffull;
+
+__global__ __launch_bounds__(256) void k_key_count32(const int32_t* __restrict__ idx, int64_t nnz, KeyPack kc,
+                                                     unsigned long long* __restrict__ tab, TabGeom g, uint64_t seed,
+                                                     int32_t max_probe, DevStatus* st) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t key = pack_key(idx, nnz, e, kc);
+    const unsigned long long want = (unsigned long long)key << 32 | 1ull;
+    ProbeSeq p = probe_seq(key, g, seed);
+    for (int32_t probe = 0;; p.next()) {
+      const uint64_t s = p.slot();
+      const unsigned long long prev = atomicCAS(&tab[s], kEmpty, want);
+      if (prev == kEmpty) break;
+      if ((prev >> 32) == key) {
+        atomicAdd(&tab[s], 1ull);
+        break;
+      }
+      if (++probe >= max_probe) {
+        record_error(st, kErrCapacity);
+        break;
+      }
+    }
+  }
+}
+
+struct XTable32ScanOp {
+  unsigned long long* tab;
+  GroupRec* groups;
+  __device__ unsigned long long get(int64_t i) const {
+    const unsigned long long w = tab[i];
+    return w != kEmpty ? ((w & kLow32) << 32 | 1ull) : 0ull;
+  }
+  __device__ void put(int64_t i, unsigned long long excl, unsigned long long v) const {
+    if (!v) return;
+    const unsigned long long key = tab[i] >> 32;
+    GroupRec g;
+    g.phi = key;
+    g.start = (unsigned)(excl >> 32);
+    g.count = (unsigned)(v >> 32);
+    groups[(unsigned)(excl & kLow32)] = g;
+    tab[i] = key << 32 | (unsigned long long)(g.start + g.count);
+  }
+};
+
+__global__ __launch_bounds__(256) void k_x_scatter32(const int32_t* __restrict__ xidx, const double* __restrict__ xval,
+                                                     int64_t nnz, KeyPack kf, KeyPack kc, Bounds b,
+                                                     unsigned long long* __restrict__ xtab, TabGeom xg,
+                                                     int32_t max_probe_x, const YSlot* __restrict__ ytab, TabGeom yg,
+                                                     int32_t max_probe_y, uint64_t seed, XRec* __restrict__ xr,
+                                                     DevStatus* st) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
+    if (b.check && !coords_ok(xidx, nnz, e, b)) record_error(st, kErrCoord);
+    const uint64_t fkey = pack_key(xidx, nnz, e, kf);
+    ProbeSeq p = probe_seq(fkey, xg, seed);
+    int64_t s = -1;
+    for (int32_t probe = 0; probe < max_probe_x; ++probe, p.next()) {
+      const unsigned long long w = xtab[p.slot()];  // the key half never changes once set
+      if (w == kEmpty) break;
+      if ((w >> 32) == fkey) {
+        s = (int64_t)p.slot();
+        break;
+      }
+    }
+    if (s < 0) {
+      record_error(st, kErrInternal);
+      continue;
+    }
+    const unsigned pos = (unsigned)((atomicSub(&xtab[s], 1ull) - 1ull) & kLow32);
+    if ((int64_t)pos >= nnz) {
+      record_error(st, kErrInternal);
+      continue;
+    }
+    xr[pos] = probe_y(xidx, nnz, e, kc, ytab, yg, max_probe_y, seed, xval[e]);
+  }
+}
+
+
 // The rest of a probe of Y's table whose home slot held another key.
 __device__ __noinline__ XRec probe_y_from(const YSlot* __restrict__ ytab, ProbeSeq p, int32_t max_probe_y,
                                           uint64_t ckey, double v) {
@@ -1219,6 +1301,25 @@ __global__ void k_x_groups(const GroupRec* __restrict__ groups, int64_t ng, cons
 hipError_t launch_scan_x_table(YSlot* tab, int64_t nslots, GroupRec* groups, bool run_end, void* tile_sums,
                                DevStatus* st, hipStream_t stream) {
   return device_scan(XTableScanOp{tab, groups, run_end}, nslots, tile_sums, FinXGroups{st}, stream);
+}
+
+hipError_t launch_x_table32(const int32_t* xidx, const double* xval, int64_t nnz, KeyPack kf, KeyPack kc, Bounds b,
+                            unsigned long long* xtab, TabGeom xg, int32_t max_probe_x, GroupRec* groups,
+                            const YSlot* ytab, TabGeom yg, int32_t max_probe_y, uint64_t seed, XRec* xr,
+                            void* tile_sums, DevStatus* st, int num_cus, hipStream_t stream) {
+  if (nnz <= 0) return hipSuccess;
+  if (xg.reg || xg.ident) return hipErrorInvalidValue;
+  const int64_t nslots = (int64_t)xg.mask + 1;
+  hipError_t e = launch_fill_keys(xtab, nslots, stream);
+  if (e != hipSuccess) return e;
+  k_key_count32<<<grid_for(nnz, 256, num_cus), 256, 0, stream>>>(xidx, nnz, kf, xtab, xg, seed, max_probe_x, st);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = device_scan(XTable32ScanOp{xtab, groups}, nslots, tile_sums, FinXGroups{st}, stream);
+  if (e != hipSuccess) return e;
+  k_x_scatter32<<<grid_for(nnz, 256, num_cus), 256, 0, stream>>>(xidx, xval, nnz, kf, kc, b, xtab, xg, max_probe_x,
+                                                                  ytab, yg, max_probe_y, seed, xr, st);
+  return hipGetLastError();
 }
 
 hipError_t launch_x_scatter(const int32_t* xidx, const double* xval, int64_t nnz, KeyPack kf, KeyPack kc, Bounds b,

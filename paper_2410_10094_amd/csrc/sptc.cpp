@@ -625,7 +625,14 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
   const hipStream_t s = P->stream;
   const uint64_t seed = P->opt.hash_seed;
   sptc_status st;
-  if ((st = P->allocate_n(P->xtab_slots, &P->xtab))) return st;
+  // hashed X free keys of at most 31 bits: the compact table
+  const bool x32 = !P->x_agg && !P->xgeom.reg && !P->xgeom.ident && P->bits_fx <= 31 && P->nx < (int64_t)UINT32_MAX;
+  unsigned long long* xtab32 = nullptr;
+  if (x32) {
+    if ((st = P->allocate_n(P->xtab_slots, &xtab32))) return st;
+  } else if ((st = P->allocate_n(P->xtab_slots, &P->xtab))) {
+    return st;
+  }
   if ((st = P->allocate_n(P->nx, &P->groups))) return st;
   if ((st = P->allocate_n(P->nx, &P->xr))) return st;
   if ((st = P->allocate_n(P->nx + 1, &P->eoff))) return st;
@@ -638,20 +645,26 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
   if (P->x_agg && (st = P->allocate_n((agg_chunks(P->nx) + 1) * P->xtab_slots, &P->xhist))) return st;
 
   HIP_TRY(mark(P, s, SPTC_STAGE_X_PROBE, 0));
-  HIP_TRY(launch_fill_empty(P->xtab, P->xtab_slots, nullptr, s));
-  if (P->x_agg)
-    HIP_TRY(launch_key_count_agg(X->idx, P->nx, P->x_f, P->xtab, (unsigned)P->xtab_slots, P->xhist, P->agg_total,
-                                 nullptr, s));
-  else
-    HIP_TRY(launch_key_count(X->idx, P->nx, P->x_f, P->xtab, P->xgeom, seed, P->max_probe_x, P->st, nullptr,
+  if (x32) {
+    HIP_TRY(launch_x_table32(X->idx, X->val, P->nx, P->x_f, P->x_c, P->xb, xtab32, P->xgeom, P->max_probe_x,
+                             P->groups, P->ytab, P->ygeom, P->max_probe_y, seed, P->xr, P->tile_sums, P->st,
                              P->num_cus, s));
-  HIP_TRY(launch_scan_x_table(P->xtab, P->xtab_slots, P->groups, !P->x_agg, P->tile_sums, P->st, s));
-  if (P->x_agg)
-    HIP_TRY(launch_x_scatter_agg(X->idx, X->val, P->nx, P->x_f, P->x_c, P->xb, P->xtab, (unsigned)P->xtab_slots,
-                                 P->xhist, P->ytab, P->ygeom, P->max_probe_y, seed, P->xr, P->st, s));
-  else
-    HIP_TRY(launch_x_scatter(X->idx, X->val, P->nx, P->x_f, P->x_c, P->xb, P->xtab, P->xgeom, P->max_probe_x,
-                             P->ytab, P->ygeom, P->max_probe_y, seed, P->xr, P->st, P->num_cus, s));
+  } else {
+    HIP_TRY(launch_fill_empty(P->xtab, P->xtab_slots, nullptr, s));
+    if (P->x_agg)
+      HIP_TRY(launch_key_count_agg(X->idx, P->nx, P->x_f, P->xtab, (unsigned)P->xtab_slots, P->xhist, P->agg_total,
+                                   nullptr, s));
+    else
+      HIP_TRY(launch_key_count(X->idx, P->nx, P->x_f, P->xtab, P->xgeom, seed, P->max_probe_x, P->st, nullptr,
+                               P->num_cus, s));
+    HIP_TRY(launch_scan_x_table(P->xtab, P->xtab_slots, P->groups, !P->x_agg, P->tile_sums, P->st, s));
+    if (P->x_agg)
+      HIP_TRY(launch_x_scatter_agg(X->idx, X->val, P->nx, P->x_f, P->x_c, P->xb, P->xtab, (unsigned)P->xtab_slots,
+                                   P->xhist, P->ytab, P->ygeom, P->max_probe_y, seed, P->xr, P->st, s));
+    else
+      HIP_TRY(launch_x_scatter(X->idx, X->val, P->nx, P->x_f, P->x_c, P->xb, P->xtab, P->xgeom, P->max_probe_x,
+                               P->ytab, P->ygeom, P->max_probe_y, seed, P->xr, P->st, P->num_cus, s));
+  }
   HIP_TRY(mark(P, s, SPTC_STAGE_X_PROBE, 1));
   HIP_TRY(mark(P, s, SPTC_STAGE_P_SCAN, 0));
   HIP_TRY(launch_scan_entries(P->xr, P->nx, P->eoff, P->tile_sums, P->st, s));
