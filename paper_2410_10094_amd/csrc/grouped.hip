@@ -93,8 +93,11 @@ __device__ __forceinline__ XRec probe_y(const int32_t* __restrict__ xidx, int64_
 // contraction): one 64-bit word per slot, key << 32 | count, kEmpty when
 // free, so a table takes half the memory (and cache) of YSlot and a new key
 // is claimed and counted by one compare-and-swap.  After the scan the low
-// half holds the end of the key's run, which placement decrements.
+// half holds the end of the key's run, which placement decrements, with
+// kSingle set when the key has one entry: that entry is placed without an
+// atomic (entry counts stay below 2^31).
 constexpr unsigned long long kLow32 = 0xffffffffull;
+constexpr unsigned long long kSingle = 1ull << 31;
 
 __global__ __launch_bounds__(256) void k_key_count32(const int32_t* __restrict__ idx, int64_t nnz, KeyPack kc,
                                                      unsigned long long* __restrict__ tab, TabGeom g, uint64_t seed,
@@ -134,7 +137,7 @@ struct XTable32ScanOp {
     g.start = (unsigned)(excl >> 32);
     g.count = (unsigned)(v >> 32);
     groups[(unsigned)(excl & kLow32)] = g;
-    tab[i] = key << 32 | (unsigned long long)(g.start + g.count);
+    tab[i] = key << 32 | (unsigned long long)(g.start + g.count) | (g.count == 1 ? kSingle : 0ull);
   }
 };
 
@@ -149,8 +152,9 @@ __global__ __launch_bounds__(256) void k_x_scatter32(const int32_t* __restrict__
     const uint64_t fkey = pack_key(xidx, nnz, e, kf);
     ProbeSeq p = probe_seq(fkey, xg, seed);
     int64_t s = -1;
+    unsigned long long w = kEmpty;
     for (int32_t probe = 0; probe < max_probe_x; ++probe, p.next()) {
-      const unsigned long long w = xtab[p.slot()];  // the key half never changes once set
+      w = xtab[p.slot()];  // the key half and kSingle never change once the scan set them
       if (w == kEmpty) break;
       if ((w >> 32) == fkey) {
         s = (int64_t)p.slot();
@@ -161,7 +165,8 @@ __global__ __launch_bounds__(256) void k_x_scatter32(const int32_t* __restrict__
       record_error(st, kErrInternal);
       continue;
     }
-    const unsigned pos = (unsigned)((atomicSub(&xtab[s], 1ull) - 1ull) & kLow32);
+    const unsigned pos = (w & kSingle) ? (unsigned)((w & (kSingle - 1ull)) - 1ull)
+                                       : (unsigned)((atomicSub(&xtab[s], 1ull) - 1ull) & (kSingle - 1ull));
     if ((int64_t)pos >= nnz) {
       record_error(st, kErrInternal);
       continue;

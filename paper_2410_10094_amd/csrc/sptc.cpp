@@ -626,7 +626,7 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
   const uint64_t seed = P->opt.hash_seed;
   sptc_status st;
   // hashed X free keys of at most 31 bits: the compact table
-  const bool x32 = !P->x_agg && !P->xgeom.reg && !P->xgeom.ident && P->bits_fx <= 31 && P->nx < (int64_t)UINT32_MAX;
+  const bool x32 = !P->x_agg && !P->xgeom.reg && !P->xgeom.ident && P->bits_fx <= 31 && P->nx < ((int64_t)1 << 31);
   unsigned long long* xtab32 = nullptr;
   if (x32) {
     if ((st = P->allocate_n(P->xtab_slots, &xtab32))) return st;

@@ -284,7 +284,7 @@ hipError_t launch_x_scatter(const int32_t* xidx, const double* xval, int64_t nnz
                             int32_t max_probe_y, uint64_t seed, XRec* xr, DevStatus* st, int num_cus,
                             hipStream_t stream);
 // The X grouping with the compact table (hashed X free keys of at most 31
-// bits, one contraction, a hashed geometry): fills xtab (mask + 1 64-bit
+// bits, fewer than 2^31 entries, one contraction, a hashed geometry): fills xtab (mask + 1 64-bit
 // slots), counts, scans into groups and places the records, as
 // launch_key_count + launch_scan_x_table + launch_x_scatter do with YSlot.
 hipError_t launch_x_table32(const int32_t* xidx, const double* xval, int64_t nnz, KeyPack kf, KeyPack kc, Bounds b,
