@@ -458,7 +458,28 @@ __global__ __launch_bounds__(kMBlock, 3) void k_group_block_mfma(GroupArgs a, co
   }
 }
 
+// Block survey: the block class's products, a thread per block group, one
+// atomic per wave.  (The scatter kernels flag non-finite values.)
+__global__ __launch_bounds__(256) void k_block_survey(const GroupRec* __restrict__ groups,
+                                                      const uint32_t* __restrict__ blist,
+                                                      const unsigned long long* __restrict__ eoff, DevStatus* st) {
+  const int64_t nb = (int64_t)st->class_hi;
+  unsigned long long prod = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += (int64_t)gridDim.x * blockDim.x) {
+    const GroupRec G = groups[blist[i]];
+    prod += eoff[G.start + G.count] - eoff[G.start];
+  }
+  for (int off = 32; off > 0; off >>= 1) prod += __shfl_xor(prod, off);
+  if ((threadIdx.x & 63) == 0 && prod) atomicAdd(&st->block_products, prod);
+}
+
 }  // namespace
+
+hipError_t launch_block_survey(const GroupRec* groups, const uint32_t* blist, const unsigned long long* eoff,
+                               DevStatus* st, int num_cus, hipStream_t stream) {
+  k_block_survey<<<(unsigned)(2 * num_cus), 256, 0, stream>>>(groups, blist, eoff, st);
+  return hipGetLastError();
+}
 
 hipError_t launch_mfma_runs(const YSlot* ytab, int64_t yslots, int64_t ny, unsigned* run_start, unsigned* runid,
                             MfmaSurvey* sv, void* tile_sums, hipStream_t stream) {

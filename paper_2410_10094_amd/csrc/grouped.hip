@@ -147,6 +147,7 @@ __global__ __launch_bounds__(256) void k_x_scatter32(const int32_t* __restrict__
                                                      int32_t max_probe_x, const YSlot* __restrict__ ytab, TabGeom yg,
                                                      int32_t max_probe_y, uint64_t seed, XRec* __restrict__ xr,
                                                      DevStatus* st) {
+  bool bad = false;  // a value is Inf or NaN
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
     if (b.check && !coords_ok(xidx, nnz, e, b)) record_error(st, kErrCoord);
     const uint64_t fkey = pack_key(xidx, nnz, e, kf);
@@ -171,8 +172,11 @@ __global__ __launch_bounds__(256) void k_x_scatter32(const int32_t* __restrict__
       record_error(st, kErrInternal);
       continue;
     }
-    xr[pos] = probe_y(xidx, nnz, e, kc, ytab, yg, max_probe_y, seed, xval[e]);
+    const double v = xval[e];
+    bad |= !isfinite(v);
+    xr[pos] = probe_y(xidx, nnz, e, kc, ytab, yg, max_probe_y, seed, v);
   }
+  if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(&st->nonfinite, 1u);
 }
 
 
@@ -203,6 +207,7 @@ __global__ __launch_bounds__(256) void k_x_scatter(const int32_t* __restrict__ x
                                                    const YSlot* __restrict__ ytab, TabGeom yg,
                                                    int32_t max_probe_y, uint64_t seed, XRec* __restrict__ xr,
                                                    DevStatus* st) {
+  bool bad = false;  // a value is Inf or NaN
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
     if (b.check && !coords_ok(xidx, nnz, e, b)) record_error(st, kErrCoord);
     const uint64_t fkey = pack_key(xidx, nnz, e, kf);
@@ -216,8 +221,11 @@ __global__ __launch_bounds__(256) void k_x_scatter(const int32_t* __restrict__ x
       record_error(st, kErrInternal);
       continue;
     }
-    xr[pos] = probe_y(xidx, nnz, e, kc, ytab, yg, max_probe_y, seed, xval[e]);
+    const double v = xval[e];
+    bad |= !isfinite(v);
+    xr[pos] = probe_y(xidx, nnz, e, kc, ytab, yg, max_probe_y, seed, v);
   }
+  if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(&st->nonfinite, 1u);
 }
 
 // Aggregated variant for a direct-addressed X table (small X free keys).
@@ -228,6 +236,7 @@ __global__ __launch_bounds__(kAggBlock) void k_x_scatter_agg(const int32_t* __re
                                                              const YSlot* __restrict__ ytab,
                                                              TabGeom yg, int32_t max_probe_y, uint64_t seed,
                                                              XRec* __restrict__ xr, DevStatus* st) {
+  bool bad = false;  // a value is Inf or NaN
   extern __shared__ unsigned s_agg[];
   place_chunk(xidx, nnz, kf, nslots, choff, s_agg, s_agg + nslots,
               [&](const int64_t* e, const uint64_t*, const unsigned* pos, const bool* ok) {
@@ -246,6 +255,7 @@ __global__ __launch_bounds__(kAggBlock) void k_x_scatter_agg(const int32_t* __re
                   if (!ok[u]) continue;
                   slot[u] = ytab[ys[u].slot()];
                   v[u] = xval[e[u]];
+                  bad |= !isfinite(v[u]);
                 }
 #pragma unroll
                 for (int u = 0; u < kAggUnroll; ++u) {
@@ -268,6 +278,7 @@ __global__ __launch_bounds__(kAggBlock) void k_x_scatter_agg(const int32_t* __re
                   xr[pos[u]] = r;
                 }
               });
+  if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(&st->nonfinite, 1u);
 }
 
 struct EntryScanOp {

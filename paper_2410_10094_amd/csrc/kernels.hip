@@ -76,6 +76,7 @@ __global__ __launch_bounds__(256) void k_y_scatter(const int32_t* __restrict__ y
                                                    int32_t max_probe, YEntry* __restrict__ yg,
                                                    unsigned long long* __restrict__ yset, uint64_t yset_mask,
                                                    int32_t bits_y, DevStatus* st) {
+  bool bad = false;  // a value is Inf or NaN
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
     if (b.check && !coords_ok(yidx, nnz, e, b)) record_error(st, kErrCoord);
     const uint64_t key = pack_key(yidx, nnz, e, kc);
@@ -92,6 +93,7 @@ __global__ __launch_bounds__(256) void k_y_scatter(const int32_t* __restrict__ y
     YEntry ent;
     ent.phi = pack_key(yidx, nnz, e, kf);
     ent.v = yval[e];
+    bad |= !isfinite(ent.v);
     yg[pos] = ent;
     if (yset) {  // a repeated full coordinate marks Y as having duplicates
       const unsigned long long full = full_y_key(key, ent.phi, bits_y);
@@ -107,6 +109,7 @@ __global__ __launch_bounds__(256) void k_y_scatter(const int32_t* __restrict__ y
       }
     }
   }
+  if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(&st->nonfinite, 1u);
 }
 
 __global__ void k_fill_keys(unsigned long long* __restrict__ keys, int64_t n) {
@@ -495,6 +498,7 @@ __global__ __launch_bounds__(kAggBlock) void k_y_scatter_agg(const int32_t* __re
                                                              unsigned long long* __restrict__ yset,
                                                              uint64_t yset_mask, uint64_t seed, int32_t bits_y,
                                                              DevStatus* st) {
+  bool bad = false;  // a value is Inf or NaN
   extern __shared__ unsigned s_agg[];
   place_chunk(yidx, nnz, kc, nslots, choff, s_agg, s_agg + nslots,
               [&](const int64_t* e, const uint64_t* keys, const unsigned* pos, const bool* ok) {
@@ -507,7 +511,10 @@ __global__ __launch_bounds__(kAggBlock) void k_y_scatter_agg(const int32_t* __re
                 if (b.check)
                   coords_ok_batch<kAggUnroll>(yidx, nnz, e, ok, b, inb);
 #pragma unroll
-                for (int u = 0; u < kAggUnroll; ++u) v[u] = ok[u] ? yval[e[u]] : 0.0;
+                for (int u = 0; u < kAggUnroll; ++u) {
+                  v[u] = ok[u] ? yval[e[u]] : 0.0;
+                  bad |= !isfinite(v[u]);
+                }
 #pragma unroll
                 for (int u = 0; u < kAggUnroll; ++u) {
                   good[u] = ok[u];
@@ -533,6 +540,7 @@ __global__ __launch_bounds__(kAggBlock) void k_y_scatter_agg(const int32_t* __re
                     if (seen[u]) st->ydup = 1u;
                 }
               });
+  if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(&st->nonfinite, 1u);
 }
 }  // namespace
 

@@ -305,6 +305,9 @@ struct sptc_plan_s : Workspace {
   uint16_t* cellof = nullptr;
   MfmaPlan mplan{};
   bool in_batch = false;      // the packed plan of a batch
+  bool block_surveyed = false;  // the block survey ran (dense Y free key, one contraction)
+  int32_t block_nonfinite = 0;  // an X or Y value is not finite (the matrix cores need finite values)
+  int64_t block_products = 0;   // survey: products of the block class
   unsigned long long* dpos = nullptr;
   uint16_t* ykey16 = nullptr;  // dense Y free keys: compact copy of grouped Y
   double* yval = nullptr;
@@ -563,19 +566,19 @@ double mfma_work(int64_t rows, int64_t cols, int64_t runs) {
   return up(rows, kMfmaRows) * up(cols, kMfmaCols) * up(runs, kMfmaK);
 }
 
-// Before any survey: a single contraction, not ruled out by the option, and
-// (under the cost rule) work within the ratio of what the plan already
-// knows -- the products outside the direct class bound the block class's.
+// From what is read back with the class counts: every X and Y value finite
+// (zero padding must add exact zeros), not ruled out by the option, and
+// under the cost rule dense work within the ratio of the block class's
+// products (block survey).
 bool mfma_candidate(const sptc_plan_s* P) {
-  if (P->in_batch || P->opt.block_mfma == 0 || P->ycols == 0) return false;
+  if (!P->block_surveyed || P->block_nonfinite || P->ycols == 0) return false;
   if (P->opt.block_mfma > 0) return true;
-  const double bound = (double)(P->products - P->direct_products);
-  return mfma_work(P->nb, P->ycols, P->y_groups) <= kMfmaWorkRatio * bound;
+  return mfma_work(P->nb, P->ycols, P->y_groups) <= kMfmaWorkRatio * (double)P->block_products;
 }
 
-// Dense block class on the matrix cores: the panels are built from what the
-// plan knows (rows, columns that occur, runs) while the class is surveyed,
-// and one read-back then decides.
+// Dense block class on the matrix cores (the survey already decided): the
+// panels are built from what the plan knows (rows, columns that occur, runs),
+// with no read-back.
 sptc_status plan_block_mfma(sptc_plan_s* P) {
   const hipStream_t s = P->stream;
   sptc_status st;
@@ -608,14 +611,6 @@ sptc_status plan_block_mfma(sptc_plan_s* P) {
   HIP_TRY(launch_mfma_panels(P->ycolbits, P->groups, P->blist, P->nb, P->eoff, P->xr, P->run_start, runid,
                              (unsigned)nruns, P->ykey16, P->yval, P->ny, P->colid, P->cellof, cells, (unsigned)nsteps,
                              P->ydup, pa, am, pb, bm, P->msv, P->st, P->num_cus, s));
-  MfmaSurvey hs{};
-  HIP_TRY(hipMemcpyAsync(&hs, P->msv, sizeof hs, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  if (hs.nruns != (unsigned)nruns) return fail(SPTC_ERR_INTERNAL, "%u Y runs in the table, %lld counted", hs.nruns,
-                                               (long long)nruns);
-  if (hs.nonfinite) return SPTC_OK;
-  if (P->opt.block_mfma < 0 && mfma_work(P->nb, cells, nruns) > kMfmaWorkRatio * (double)hs.block_products)
-    return SPTC_OK;
   P->mplan = MfmaPlan{pa, am, pb, bm, P->cellof, (unsigned)nsteps, cells, (unsigned)nct};
   P->block_mfma = 1;
   return SPTC_OK;
@@ -671,6 +666,11 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
   HIP_TRY(launch_classify(P->groups, P->nx, P->eoff, P->ycells, P->dense, P->dlist, P->wlist, P->blist, P->glist,
                           P->tile_sums, P->st, s));
   HIP_TRY(launch_scan_direct(P->groups, P->dlist, P->nx, P->eoff, P->dpos, P->tile_sums, P->st, s));
+  // the block class's products and finiteness, read back with the counts
+  // below, decide the matrix-core class with no read-back of its own
+  P->block_surveyed = P->dense && !P->in_batch && P->opt.block_mfma != 0;
+  if (P->block_surveyed)
+    HIP_TRY(launch_block_survey(P->groups, P->blist, P->eoff, P->st, P->num_cus, s));
   HIP_TRY(mark(P, s, SPTC_STAGE_P_SCAN, 1));
 
   DevStatus host{};
@@ -686,6 +686,8 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
   P->direct_products = (int64_t)host.direct_products;
   P->ydup = host.ydup ? 1 : 0;
   P->ycols = host.ycols;
+  P->block_products = (int64_t)host.block_products;
+  P->block_nonfinite = host.nonfinite ? 1 : 0;
   if (P->ngl < 0) return fail(SPTC_ERR_INTERNAL, "group classes do not add up");
   if (P->nd > 0 && P->direct_products > 0 &&
       (st = P->allocate_n(direct_tile_bound((uint64_t)P->direct_products), &P->dtfirst)))

@@ -137,10 +137,11 @@ struct alignas(16) DevStatus {
   unsigned long long global_entries;   // X entries of groups accumulated in the global hash
   unsigned long long global_products;  // their products
   unsigned long long out_base;         // output cursor: outputs placed so far
+  unsigned long long block_products;   // products of the block class (block survey)
   unsigned int err;                    // kErr* bits
   unsigned int ydup;                   // nonzero: Y holds a repeated coordinate
   unsigned int ycols;                  // dense Y free key: distinct Y free cells that occur
-  unsigned int pad;
+  unsigned int nonfinite;              // an X or Y value is Inf or NaN (set by the scatter kernels)
 };
 
 // Capacities of the LDS accumulators (distinct outputs per X group).
@@ -373,6 +374,12 @@ hipError_t launch_y_cells(const uint16_t* ykey16, int64_t ny, unsigned* colbits,
 // first (the Y blocks and their masks; the X panel is written whole), while
 // surveying the class into sv (zeroed first): its products and whether its X
 // values and the Y values are finite.
+// Block survey, before the class counts are read back: the block class's
+// products into st->block_products (zeroed first); the block list's length
+// is read on the device (st->class_hi).  The X and Y scatter kernels set
+// st->nonfinite when a value is Inf or NaN.
+hipError_t launch_block_survey(const GroupRec* groups, const uint32_t* blist, const unsigned long long* eoff,
+                               DevStatus* st, int num_cus, hipStream_t stream);
 hipError_t launch_mfma_runs(const YSlot* ytab, int64_t yslots, int64_t ny, unsigned* run_start, unsigned* runid,
                             MfmaSurvey* sv, void* tile_sums, hipStream_t stream);
 hipError_t launch_mfma_panels(const unsigned* colbits, const GroupRec* groups, const uint32_t* blist, int64_t nb,

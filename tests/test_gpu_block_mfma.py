@@ -89,6 +89,20 @@ def test_non_finite_value_falls_back():
     assert_parity(q, gidx, gval)
 
 
+def test_non_finite_x_value_falls_back():
+    """An Inf among the X values rules the class out as well; it sits on a
+    contracting key no Y entry has, so no product takes it and the outputs
+    stay finite and comparable."""
+    p = _dense_random(38, 400, 100, 400, 20_000, 20_000, name="xinf")
+    xi = np.concatenate([p.X.idx, np.array([[0], [0], [100]], np.int32)], axis=1)
+    X = Coo((p.X.dims[0], p.X.dims[1], 101), xi, np.concatenate([p.X.val, [np.inf]]))
+    Y = Coo((101,) + tuple(p.Y.dims[1:]), p.Y.idx, p.Y.val)
+    q = Problem("xinf", X, Y, (2,), (0,))
+    info, gidx, gval = run_gpu(q, options=_opts(1))
+    assert info["classes"]["block"] > 0 and not info["block_mfma"], info
+    assert_parity(q, gidx, gval)
+
+
 def test_long_y_runs_and_large_groups():
     """Runs and groups far longer than a step or a tile: a run of 3000 Y
     entries and a group of 6000 X entries spread over many steps."""
