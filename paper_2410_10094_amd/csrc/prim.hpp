@@ -316,20 +316,21 @@ __global__ __launch_bounds__(kScanBlock) void k_tile_scan(Op op, int64_t n, cons
   }
 }
 
-// A scan of at most one tile: the whole of it in one workgroup, fin(total)
-// on thread 0 at the end (one launch instead of three).
+// A scan of at most one tile: the whole of it in one 1024-thread
+// workgroup, fin(total) on thread 0 at the end (one launch instead of
+// three).
+constexpr int kSingleBlock = 1024;
+
 template <class Op, class Fin, class V>
-__global__ __launch_bounds__(kScanBlock) void k_scan_single(Op op, int64_t n, Fin fin) {
-  __shared__ V s_wave[kScanBlock / 64 + 1];
+__global__ __launch_bounds__(kSingleBlock) void k_scan_single(Op op, int64_t n, Fin fin) {
+  __shared__ V s_wave[kSingleBlock / 64 + 1];
   n = live_count(op, n);
   V carry{};
-  for (int k = 0; k < kScanItems; ++k) {
-    const int64_t chunk = (int64_t)k * kScanBlock;
-    if (chunk >= n) break;  // uniform across the block
+  for (int64_t chunk = 0; chunk < n; chunk += kSingleBlock) {  // uniform across the block
     const int64_t i = chunk + threadIdx.x;
     const V v = i < n ? op.get(i) : V{};
     V total;
-    const V excl = block_excl_scan_t<kScanBlock>(v, s_wave, &total);
+    const V excl = block_excl_scan_t<kSingleBlock>(v, s_wave, &total);
     if (i < n) op.put(i, carry + excl, v);
     carry = carry + total;
   }
@@ -349,7 +350,7 @@ hipError_t device_scan(Op op, int64_t n, void* tile_sums, Fin fin, hipStream_t s
   V* ts = static_cast<V*>(tile_sums);
   const int64_t tiles = scan_tiles(n);
   if (tiles <= 1) {
-    k_scan_single<Op, Fin, V><<<1, kScanBlock, 0, stream>>>(op, n, fin);
+    k_scan_single<Op, Fin, V><<<1, kSingleBlock, 0, stream>>>(op, n, fin);
     return hipGetLastError();
   }
   k_tile_reduce<Op, V><<<dim3((unsigned)tiles), dim3(kScanBlock), 0, stream>>>(op, n, ts);
