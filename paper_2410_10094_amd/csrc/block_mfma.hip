@@ -96,11 +96,12 @@ struct MfmaRunOp {
 };
 
 struct FinRuns {
-  MfmaSurvey* sv;
   unsigned* run_start;
   unsigned ny;
+  unsigned long long expected;  // runs the plan counted (the Y groups)
+  DevStatus* st;
   __device__ void operator()(unsigned long long total) const {
-    sv->nruns = (unsigned)total;
+    if (total != expected) record_error(st, kErrInternal);
     run_start[total] = ny;
   }
 };
@@ -130,8 +131,7 @@ __global__ __launch_bounds__(1024) void k_mfma_cols(const unsigned* __restrict__
 // nb): the row's entries are added into an LDS copy of a chunk of its panel
 // row (kXChunk runs; repeated X coordinates add up), with a bit per run in
 // the chunk's step masks, and the chunk is then written out whole (zeros
-// included), so the panel needs no clearing and no global atomics.  The
-// class's products and the finiteness of its values are surveyed on the way.
+// included), so the panel needs no clearing and no global atomics.
 constexpr unsigned kXChunk = 2560;  // runs per LDS chunk (80 steps)
 constexpr unsigned kXWaves = 1;  // one-wave workgroups: LDS is taken per wave, so more rows fit a CU
 constexpr unsigned kXUnroll = 4;  // entries per lane in flight
@@ -139,13 +139,12 @@ static_assert(kXChunk % kMfmaK == 0, "chunks of whole steps");
 
 __global__ __launch_bounds__(64 * kXWaves) void k_mfma_x_panel(const GroupRec* __restrict__ groups,
                                                                const uint32_t* __restrict__ blist, int64_t nb,
-                                                               const unsigned long long* __restrict__ eoff,
                                                                const XRec* __restrict__ xr,
                                                                const unsigned* __restrict__ runid,
                                                                const unsigned* __restrict__ run_start,
                                                                unsigned nruns, unsigned nsteps,
                                                                double* __restrict__ a, unsigned* __restrict__ am,
-                                                               MfmaSurvey* sv, DevStatus* st) {
+                                                               DevStatus* st) {
   __shared__ double s_v[kXWaves][kXChunk];
   __shared__ unsigned s_m[kXWaves][kXChunk / kMfmaK];
   const unsigned lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -156,12 +155,7 @@ __global__ __launch_bounds__(64 * kXWaves) void k_mfma_x_panel(const GroupRec* _
   const unsigned yend = run_start[nruns];
   const int64_t waves = (int64_t)gridDim.x * kXWaves;
   for (int64_t i = (int64_t)blockIdx.x * kXWaves + w; i < rows; i += waves) {
-    GroupRec G{0ull, 0u, 0u};
-    if (i < nb) {
-      G = groups[blist[i]];
-      if (lane == 0) atomicAdd(&sv->block_products, eoff[G.start + G.count] - eoff[G.start]);
-    }
-    bool bad = false;
+    const GroupRec G = i < nb ? groups[blist[i]] : GroupRec{0ull, 0u, 0u};
     for (size_t k0 = 0; k0 < K; k0 += kXChunk) {
       const unsigned nk = (unsigned)(K - k0 < kXChunk ? K - k0 : kXChunk);
       for (unsigned j = lane; j < nk; j += 64) v[j] = 0.0;
@@ -184,7 +178,6 @@ __global__ __launch_bounds__(64 * kXWaves) void k_mfma_x_panel(const GroupRec* _
         for (unsigned u = 0; u < kXUnroll; ++u) ks[u] = k[u] < nruns ? run_start[k[u]] : 0xffffffffu;
 #pragma unroll
         for (unsigned u = 0; u < kXUnroll; ++u) {
-          if (k0 == 0) bad |= !isfinite(r[u].v);
           if (!r[u].ycnt) continue;
           if (k[u] >= nruns || ks[u] != r[u].ystart) {
             if (k0 == 0) record_error(st, kErrInternal);
@@ -203,7 +196,6 @@ __global__ __launch_bounds__(64 * kXWaves) void k_mfma_x_panel(const GroupRec* _
       for (unsigned j = lane; j < nk / kMfmaK; j += 64) am[(size_t)i * nsteps + k0 / kMfmaK + j] = msk[j];
       wave_lds_fence();
     }
-    if (__ballot(bad) && lane == 0) atomicOr(&sv->nonfinite, 1u);
   }
 }
 
@@ -219,7 +211,7 @@ __global__ __launch_bounds__(kYBlock) void k_mfma_y_panel(const unsigned* __rest
                                                           const uint16_t* __restrict__ colid, unsigned nsteps,
                                                           unsigned split, unsigned ncols, unsigned nct, int ydup,
                                                           double* __restrict__ b, unsigned* __restrict__ bm,
-                                                          MfmaSurvey* sv, DevStatus* st) {
+                                                          DevStatus* st) {
   constexpr unsigned kCells = 1u << kDenseBits;
   __shared__ uint16_t s_col[kCells];
   __shared__ unsigned s_mask[kCells + kMfmaCols];  // nct * 64 <= kCells + 63
@@ -252,7 +244,6 @@ __global__ __launch_bounds__(kYBlock) void k_mfma_y_panel(const unsigned* __rest
         continue;
       }
       const double v = yval[j];
-      if (!isfinite(v)) atomicOr(&sv->nonfinite, 1u);
       double* dst = &b[(((size_t)(c / kMfmaCols) * nsteps + step) * kMfmaK + kk) * kMfmaCols + c % kMfmaCols];
       if (ydup)
         atomicAdd(dst, v);
@@ -482,9 +473,9 @@ hipError_t launch_block_survey(const GroupRec* groups, const uint32_t* blist, co
 }
 
 hipError_t launch_mfma_runs(const YSlot* ytab, int64_t yslots, int64_t ny, unsigned* run_start, unsigned* runid,
-                            MfmaSurvey* sv, void* tile_sums, hipStream_t stream) {
+                            int64_t nruns, DevStatus* st, void* tile_sums, hipStream_t stream) {
   return device_scan(MfmaRunOp{ytab, run_start, runid, (unsigned)ny}, yslots, tile_sums,
-                     FinRuns{sv, run_start, (unsigned)ny}, stream);
+                     FinRuns{run_start, (unsigned)ny, (unsigned long long)nruns, st}, stream);
 }
 
 hipError_t launch_y_cells(const uint16_t* ykey16, int64_t ny, unsigned* colbits, DevStatus* st, int num_cus,
@@ -496,15 +487,14 @@ hipError_t launch_y_cells(const uint16_t* ykey16, int64_t ny, unsigned* colbits,
 }
 
 hipError_t launch_mfma_panels(const unsigned* colbits, const GroupRec* groups, const uint32_t* blist, int64_t nb,
-                              const unsigned long long* eoff, const XRec* xr, const unsigned* run_start,
-                              const unsigned* runid, unsigned nruns, const uint16_t* ykey16, const double* yval,
-                              int64_t ny, uint16_t* colid, uint16_t* cellof, unsigned ncols, unsigned nsteps,
-                              int ydup, double* a, unsigned* am, double* b, unsigned* bm, MfmaSurvey* sv,
-                              DevStatus* st, int num_cus, hipStream_t stream) {
+                              const XRec* xr, const unsigned* run_start, const unsigned* runid, unsigned nruns,
+                              const uint16_t* ykey16, const double* yval, int64_t ny, uint16_t* colid,
+                              uint16_t* cellof, unsigned ncols, unsigned nsteps, int ydup, double* a, unsigned* am,
+                              double* b, unsigned* bm, DevStatus* st, int num_cus, hipStream_t stream) {
   k_mfma_cols<<<1, 1024, 0, stream>>>(colbits, colid, cellof);
   const int64_t xrows = (nb + kMfmaRows - 1) / kMfmaRows * kMfmaRows;
   k_mfma_x_panel<<<grid_for(xrows * 64, 64 * kXWaves, num_cus, 16), 64 * kXWaves, 0, stream>>>(
-      groups, blist, nb, eoff, xr, runid, run_start, nruns, nsteps, a, am, sv, st);
+      groups, blist, nb, xr, runid, run_start, nruns, nsteps, a, am, st);
   const unsigned nct = (ncols + kMfmaCols - 1) / kMfmaCols;
   if (nsteps == 0) return hipGetLastError();
   // about two workgroups per compute unit, each with at least a few
@@ -513,7 +503,7 @@ hipError_t launch_mfma_panels(const unsigned* colbits, const GroupRec* groups, c
   const int64_t room = ny / ((int64_t)nsteps * 4 * kYBlock);
   const unsigned split = (unsigned)std::max<int64_t>(1, std::min(want, room));
   k_mfma_y_panel<<<nsteps * split, kYBlock, 0, stream>>>(run_start, nruns, ny, ykey16, yval, colid, nsteps, split,
-                                                        ncols, nct, ydup, b, bm, sv, st);
+                                                        ncols, nct, ydup, b, bm, st);
   return hipGetLastError();
 }
 

@@ -299,7 +299,6 @@ struct sptc_plan_s : Workspace {
   int32_t block_mfma = 0;     // dense block class on the matrix cores
   unsigned* ycolbits = nullptr;  // dense Y free key: the cells that occur (bitmap)
   unsigned ycols = 0;            // and their number
-  MfmaSurvey* msv = nullptr;
   unsigned* run_start = nullptr;
   uint16_t* colid = nullptr;
   uint16_t* cellof = nullptr;
@@ -595,7 +594,6 @@ sptc_status plan_block_mfma(sptc_plan_s* P) {
   unsigned* runid = nullptr;
   double *pa = nullptr, *pb = nullptr;
   unsigned *am = nullptr, *bm = nullptr;
-  if ((st = P->allocate_n(1, &P->msv))) return st;
   if ((st = P->allocate_n(runs_cap, &P->run_start))) return st;
   if ((st = P->allocate_n(P->ny, &runid))) return st;
   if ((st = P->allocate_n((int64_t)1 << kDenseBits, &P->colid))) return st;
@@ -604,13 +602,12 @@ sptc_status plan_block_mfma(sptc_plan_s* P) {
   if ((st = P->allocate_n(ablocks * kMfmaRows, &am))) return st;
   if ((st = P->allocate_n(bblocks * kMfmaK * kMfmaCols, &pb))) return st;
   if ((st = P->allocate_n(bblocks * kMfmaCols, &bm))) return st;
-  HIP_TRY(hipMemsetAsync(P->msv, 0, sizeof(MfmaSurvey), s));
   HIP_TRY(hipMemsetAsync(pb, 0, sizeof(double) * bblocks * kMfmaK * kMfmaCols, s));
   HIP_TRY(hipMemsetAsync(bm, 0, sizeof(unsigned) * bblocks * kMfmaCols, s));
-  HIP_TRY(launch_mfma_runs(P->ytab, P->ytab_slots, P->ny, P->run_start, runid, P->msv, P->tile_sums, s));
-  HIP_TRY(launch_mfma_panels(P->ycolbits, P->groups, P->blist, P->nb, P->eoff, P->xr, P->run_start, runid,
-                             (unsigned)nruns, P->ykey16, P->yval, P->ny, P->colid, P->cellof, cells, (unsigned)nsteps,
-                             P->ydup, pa, am, pb, bm, P->msv, P->st, P->num_cus, s));
+  HIP_TRY(launch_mfma_runs(P->ytab, P->ytab_slots, P->ny, P->run_start, runid, nruns, P->st, P->tile_sums, s));
+  HIP_TRY(launch_mfma_panels(P->ycolbits, P->groups, P->blist, P->nb, P->xr, P->run_start, runid, (unsigned)nruns,
+                             P->ykey16, P->yval, P->ny, P->colid, P->cellof, cells, (unsigned)nsteps, P->ydup, pa, am,
+                             pb, bm, P->st, P->num_cus, s));
   P->mplan = MfmaPlan{pa, am, pb, bm, P->cellof, (unsigned)nsteps, cells, (unsigned)nct};
   P->block_mfma = 1;
   return SPTC_OK;

@@ -161,12 +161,6 @@ constexpr int kMfmaRows = 64;
 constexpr int kMfmaCols = 64;
 constexpr int kMfmaK = 32;
 
-// Plan-time survey, read back to decide whether the class may run there.
-struct alignas(16) MfmaSurvey {
-  unsigned long long block_products;  // products of the block-class groups
-  unsigned nonfinite;                 // a block-class X value or a Y value is Inf or NaN
-  unsigned nruns;                     // Y runs
-};
 constexpr int kCellWords = (1 << kDenseBits) / 32;  // bitmap of the dense Y free cells
 
 // What the matrix-core block kernel reads besides GroupArgs: X as a dense
@@ -367,27 +361,25 @@ hipError_t launch_sort_block_entries(const GroupRec* groups, const uint32_t* bli
 // zeroed first) and their number in st->ycols.
 hipError_t launch_y_cells(const uint16_t* ykey16, int64_t ny, unsigned* colbits, DevStatus* st, int num_cus,
                           hipStream_t stream);
-// Matrix-core block class, plan time.  runs: the run list
-// (run_start[0..nruns], the last entry ny; runid[ny] gets each run's index
-// at its start; sv->nruns).  panels: columns (colid [2^kDenseBits], cellof
-// [ncols], from colbits) and the panels of MfmaPlan, which must be zeroed
-// first (the Y blocks and their masks; the X panel is written whole), while
-// surveying the class into sv (zeroed first): its products and whether its X
-// values and the Y values are finite.
 // Block survey, before the class counts are read back: the block class's
 // products into st->block_products (zeroed first); the block list's length
 // is read on the device (st->class_hi).  The X and Y scatter kernels set
 // st->nonfinite when a value is Inf or NaN.
 hipError_t launch_block_survey(const GroupRec* groups, const uint32_t* blist, const unsigned long long* eoff,
                                DevStatus* st, int num_cus, hipStream_t stream);
+// Matrix-core block class, plan time.  runs: the run list
+// (run_start[0..nruns], the last entry ny; runid[ny] gets each run's index
+// at its start; a count other than nruns records an internal error).
+// panels: columns (colid [2^kDenseBits], cellof [ncols], from colbits) and
+// the panels of MfmaPlan, which must be zeroed first (the Y blocks and their
+// masks; the X panel is written whole).
 hipError_t launch_mfma_runs(const YSlot* ytab, int64_t yslots, int64_t ny, unsigned* run_start, unsigned* runid,
-                            MfmaSurvey* sv, void* tile_sums, hipStream_t stream);
+                            int64_t nruns, DevStatus* st, void* tile_sums, hipStream_t stream);
 hipError_t launch_mfma_panels(const unsigned* colbits, const GroupRec* groups, const uint32_t* blist, int64_t nb,
-                              const unsigned long long* eoff, const XRec* xr, const unsigned* run_start,
-                              const unsigned* runid, unsigned nruns, const uint16_t* ykey16, const double* yval,
-                              int64_t ny, uint16_t* colid, uint16_t* cellof, unsigned ncols, unsigned nsteps,
-                              int ydup, double* a, unsigned* am, double* b, unsigned* bm, MfmaSurvey* sv,
-                              DevStatus* st, int num_cus, hipStream_t stream);
+                              const XRec* xr, const unsigned* run_start, const unsigned* runid, unsigned nruns,
+                              const uint16_t* ykey16, const double* yval, int64_t ny, uint16_t* colid,
+                              uint16_t* cellof, unsigned ncols, unsigned nsteps, int ydup, double* a, unsigned* am,
+                              double* b, unsigned* bm, DevStatus* st, int num_cus, hipStream_t stream);
 // Execute: every block group's outputs (one atomic per tile on st->out_base).
 hipError_t launch_group_block_mfma(const GroupArgs& a, const uint32_t* blist, int64_t nb, const MfmaPlan& m,
                                    int num_cus, hipStream_t stream);
