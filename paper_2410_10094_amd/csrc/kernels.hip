@@ -35,6 +35,7 @@ __global__ __launch_bounds__(256) void k_key_count(const int32_t* __restrict__ i
                                                    YSlot* __restrict__ tab, TabGeom g, uint64_t seed,
                                                    int32_t max_probe, DevStatus* st,
                                                    unsigned long long* distinct) {
+  unsigned long long fresh = 0;  // keys this thread inserted (one atomic per wave at the end)
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * blockDim.x) {
     const uint64_t key = pack_key(idx, nnz, e, kc);
     ProbeSeq p = probe_seq(key, g, seed);
@@ -44,7 +45,7 @@ __global__ __launch_bounds__(256) void k_key_count(const int32_t* __restrict__ i
       const unsigned long long prev = atomicCAS(&tab[s].key, (unsigned long long)kEmpty, (unsigned long long)key);
       if (prev == kEmpty || prev == key) {
         atomicAdd(&tab[s].count, 1u);
-        if (prev == kEmpty && distinct) atomicAdd(distinct, 1ull);
+        fresh += prev == kEmpty;
         break;
       }
       if (++probe >= max_probe) {
@@ -53,6 +54,10 @@ __global__ __launch_bounds__(256) void k_key_count(const int32_t* __restrict__ i
       }
       p.next();
     }
+  }
+  if (distinct) {
+    for (int off = 32; off > 0; off >>= 1) fresh += __shfl_xor(fresh, off);
+    if ((threadIdx.x & 63) == 0 && fresh) atomicAdd(distinct, fresh);
   }
 }
 
