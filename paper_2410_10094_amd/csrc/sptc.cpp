@@ -451,9 +451,39 @@ sptc_status status_from_bits(uint32_t err) {
   return SPTC_OK;
 }
 
+// Pinned landing buffer for status read-backs, one per thread and device (a
+// read-back completes before its call returns), allocated on first use and
+// kept for the life of the process.  NULL if it cannot be allocated.
+DevStatus* pinned_status(int dev) {
+  thread_local DevStatus* buf[64] = {};
+  if (dev < 0 || dev >= 64) return nullptr;
+  if (!buf[dev]) {
+    void* p = nullptr;
+    if (hipHostMalloc(&p, sizeof(DevStatus), hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    buf[dev] = static_cast<DevStatus*>(p);
+  }
+  return buf[dev];
+}
+
+// The plan's counts: copied into pinned memory and waited for by polling the
+// stream (the plan needs them within microseconds of the last kernel; a
+// blocking wait would add its wake-up latency to every plan).
 sptc_status read_status(sptc_plan_s* P, DevStatus* host) {
-  HIP_TRY(hipMemcpyAsync(host, P->st, sizeof *host, hipMemcpyDeviceToHost, P->stream));
-  HIP_TRY(hipStreamSynchronize(P->stream));
+  DevStatus* pin = pinned_status(P->device);
+  if (!pin) {
+    HIP_TRY(hipMemcpyAsync(host, P->st, sizeof *host, hipMemcpyDeviceToHost, P->stream));
+    HIP_TRY(hipStreamSynchronize(P->stream));
+    return status_from_bits(host->err);
+  }
+  HIP_TRY(hipMemcpyAsync(pin, P->st, sizeof *pin, hipMemcpyDeviceToHost, P->stream));
+  hipError_t e;
+  while ((e = hipStreamQuery(P->stream)) == hipErrorNotReady) {
+  }
+  if (e != hipSuccess) return hip_fail(e, "hipStreamQuery");
+  *host = *pin;
   return status_from_bits(host->err);
 }
 
