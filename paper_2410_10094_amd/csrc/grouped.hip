@@ -309,6 +309,7 @@ struct ClassifyOp {
   uint32_t* wlist;
   uint32_t* blist;
   uint32_t* glist;
+  unsigned long long* dcnt;  // direct group k's products, at the k-th place (scanned in place into offsets)
   __device__ U128 code(int64_t g) const {
     const GroupRec G = groups[g];
     const unsigned long long b = eoff[G.start + G.count] - eoff[G.start];
@@ -323,9 +324,11 @@ struct ClassifyOp {
   __device__ void put(int64_t g, U128 excl, U128 v) const {
     if ((unsigned long long)g >= st->xgroups) return;
     const unsigned long long nd = excl.lo & 0xffffffffull, nw = excl.lo >> 32, nb = excl.hi;
-    if (v.lo == 1ull)
+    if (v.lo == 1ull) {
       dlist[nd] = (uint32_t)g;
-    else if (v.lo)
+      const GroupRec G = groups[g];  // read by code(g) just before: a cache hit
+      dcnt[nd] = eoff[G.start + G.count] - eoff[G.start];
+    } else if (v.lo)
       wlist[nw] = (uint32_t)g;
     else if (v.hi)
       blist[nb] = (uint32_t)g;
@@ -342,19 +345,15 @@ struct FinClassify {
   }
 };
 
+// In place over dpos: the products of each direct group (written by the
+// classification) become their offsets.  A thread reads element i before
+// it writes it, and no other thread touches it.
 struct DirectScanOp {
-  const GroupRec* groups;
-  const uint32_t* dlist;
-  const unsigned long long* eoff;
   unsigned long long* dpos;
   const DevStatus* st;
   __device__ bool valid(int64_t i) const { return (unsigned long long)i < (st->class_lo & 0xffffffffull); }
   __device__ int64_t live(int64_t) const { return (int64_t)(st->class_lo & 0xffffffffull); }
-  __device__ unsigned long long get(int64_t i) const {
-    if (!valid(i)) return 0ull;
-    const GroupRec G = groups[dlist[i]];
-    return eoff[G.start + G.count] - eoff[G.start];
-  }
+  __device__ unsigned long long get(int64_t i) const { return valid(i) ? dpos[i] : 0ull; }
   __device__ void put(int64_t i, unsigned long long excl, unsigned long long) const {
     if (valid(i)) dpos[i] = excl;
   }
@@ -1366,16 +1365,15 @@ hipError_t launch_scan_entries(const XRec* xr, int64_t n, unsigned long long* eo
 
 hipError_t launch_classify(const GroupRec* groups, int64_t max_groups, const unsigned long long* eoff,
                            uint64_t ycells, int32_t dense, uint32_t* dlist, uint32_t* wlist, uint32_t* blist,
-                           uint32_t* glist, void* tile_sums, DevStatus* st, hipStream_t stream) {
-  return device_scan(ClassifyOp{groups, eoff, st, ycells, dense, dlist, wlist, blist, glist}, max_groups, tile_sums,
-                     FinClassify{st}, stream);
+                           uint32_t* glist, unsigned long long* dpos, void* tile_sums, DevStatus* st,
+                           hipStream_t stream) {
+  return device_scan(ClassifyOp{groups, eoff, st, ycells, dense, dlist, wlist, blist, glist, dpos}, max_groups,
+                     tile_sums, FinClassify{st}, stream);
 }
 
-hipError_t launch_scan_direct(const GroupRec* groups, const uint32_t* dlist, int64_t max_groups,
-                              const unsigned long long* eoff, unsigned long long* dpos, void* tile_sums,
-                              DevStatus* st, hipStream_t stream) {
-  return device_scan(DirectScanOp{groups, dlist, eoff, dpos, st}, max_groups, tile_sums, FinDirect{dpos, st},
-                     stream);
+hipError_t launch_scan_direct(int64_t max_groups, unsigned long long* dpos, void* tile_sums, DevStatus* st,
+                              hipStream_t stream) {
+  return device_scan(DirectScanOp{dpos, st}, max_groups, tile_sums, FinDirect{dpos, st}, stream);
 }
 
 hipError_t launch_scan_global_entries(const GroupRec* groups, const uint32_t* glist, int64_t ngl,

@@ -691,8 +691,8 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
   HIP_TRY(mark(P, s, SPTC_STAGE_P_SCAN, 0));
   HIP_TRY(launch_scan_entries(P->xr, P->nx, P->eoff, P->tile_sums, P->st, s));
   HIP_TRY(launch_classify(P->groups, P->nx, P->eoff, P->ycells, P->dense, P->dlist, P->wlist, P->blist, P->glist,
-                          P->tile_sums, P->st, s));
-  HIP_TRY(launch_scan_direct(P->groups, P->dlist, P->nx, P->eoff, P->dpos, P->tile_sums, P->st, s));
+                          P->dpos, P->tile_sums, P->st, s));
+  HIP_TRY(launch_scan_direct(P->nx, P->dpos, P->tile_sums, P->st, s));
   // the block class's products and finiteness, read back with the counts
   // below, decide the matrix-core class with no read-back of its own
   P->block_surveyed = P->dense && !P->in_batch && P->opt.block_mfma != 0;

@@ -292,17 +292,18 @@ hipError_t launch_scan_entries(const XRec* xr, int64_t n, unsigned long long* eo
                                hipStream_t stream);
 
 // Sorts groups into direct / wave / block / global accumulation classes
-// (lists of group ids); counts land in st->class_lo / class_hi.
+// (lists of group ids); counts land in st->class_lo / class_hi, and each
+// direct group's products in dpos at its place in the direct list.
 hipError_t launch_classify(const GroupRec* groups, int64_t max_groups, const unsigned long long* eoff,
                            uint64_t ycells, int32_t dense, uint32_t* dlist, uint32_t* wlist, uint32_t* blist,
-                           uint32_t* glist, void* tile_sums, DevStatus* st, hipStream_t stream);
+                           uint32_t* glist, unsigned long long* dpos, void* tile_sums, DevStatus* st,
+                           hipStream_t stream);
 
-// dpos[i] = products of direct-class groups before list entry i; dpos[nd] and
-// st->direct_products = their total.  Scans max_groups entries, bounded on
-// the device by the direct count.
-hipError_t launch_scan_direct(const GroupRec* groups, const uint32_t* dlist, int64_t max_groups,
-                              const unsigned long long* eoff, unsigned long long* dpos, void* tile_sums,
-                              DevStatus* st, hipStream_t stream);
+// In place after launch_classify: dpos[i] = products of direct-class groups
+// before list entry i; dpos[nd] and st->direct_products = their total.
+// Scans max_groups entries, bounded on the device by the direct count.
+hipError_t launch_scan_direct(int64_t max_groups, unsigned long long* dpos, void* tile_sums, DevStatus* st,
+                              hipStream_t stream);
 
 // Entries of the global-class groups, gathered for the global hash; each
 // gathered record carries its group id in place of the packed X free key.
