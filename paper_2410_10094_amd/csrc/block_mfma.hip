@@ -358,6 +358,9 @@ __global__ __launch_bounds__(kMBlock, 3) void k_group_block_mfma(GroupArgs a, co
       store_step(r, s_at, s_b, s_amask, s_bmask);
       load_step(m, arow, arow0, K, min(step + 2, last), bblk0 + min(step + 2, last), r);
       __syncthreads();
+      // the multiply phase at raised wave priority: a wave that has its blocks
+      // issues its MFMAs ahead of waves still copying the next ones
+      __builtin_amdgcn_s_setprio(1);
       // D (16 x 16) += A (16 x 4) B (4 x 16): lane holds A[lane & 15][lane >> 4],
       // B[lane >> 4][lane & 15], and D rows (lane >> 4) + 4q of column lane & 15.
 #pragma unroll
@@ -370,6 +373,7 @@ __global__ __launch_bounds__(kMBlock, 3) void k_group_block_mfma(GroupArgs a, co
           acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[c], 0, 0, 0);
         }
       }
+      __builtin_amdgcn_s_setprio(0);
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const unsigned bmk = s_bmask[16 * c + (lane & 15)];
