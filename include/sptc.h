@@ -153,8 +153,8 @@ typedef struct sptc_options {
   int32_t block_mfma;        /* grouped mode, dense Y free key, sptc_plan only: run the block class
                                 as a dense product on the FP64 matrix cores.  -1 (default): when
                                 eligible and rows x columns x runs is at most 24x the class's
-                                products; 0: never; 1: whenever eligible.  Eligible: every value of
-                                the class and of Y finite, and dense X and Y panels of at most 8 GiB.
+                                products; 0: never; 1: whenever eligible.  Eligible: every X and Y
+                                value finite, and dense X and Y panels of at most 8 GiB.
                                 sptc_info.block_mfma reports the choice. */
 } sptc_options;
 
