@@ -45,7 +45,6 @@ constexpr int kBStride = kMfmaCols + 16;   // LDS row of the Y block, in doubles
 constexpr int kAPairs = kMfmaK * kMfmaRows / 2 / kMBlock;  // 16-byte loads per thread and step
 constexpr int kBPairs = kMfmaK * kMfmaCols / 2 / kMBlock;
 constexpr unsigned kXcdsM = 8;            // MI355X: 8 XCDs, each with its own L2
-constexpr int kMSurveyBlock = 256;
 static_assert(kMfmaRows == 64 && kMfmaCols == 64 && kMfmaK == 32, "tile shape is fixed by the lane layout below");
 
 typedef double v4d __attribute__((ext_vector_type(4)));
@@ -56,29 +55,6 @@ typedef double v2d __attribute__((ext_vector_type(2)));
 // ---------------------------------------------------------------------------
 
 // The Y free cells that occur (LDS bitmap per workgroup, ORed into colbits).
-__global__ __launch_bounds__(kMSurveyBlock) void k_y_cells(const uint16_t* __restrict__ ykey16, int64_t ny,
-                                                           unsigned* __restrict__ colbits) {
-  __shared__ unsigned s_bits[kCellWords];
-  for (unsigned w = threadIdx.x; w < (unsigned)kCellWords; w += kMSurveyBlock) s_bits[w] = 0u;
-  __syncthreads();
-  for (int64_t j = (int64_t)blockIdx.x * kMSurveyBlock + threadIdx.x; j < ny;
-       j += (int64_t)gridDim.x * kMSurveyBlock) {
-    const unsigned c = ykey16[j] & ((1u << kDenseBits) - 1u);
-    atomicOr(&s_bits[c >> 5], 1u << (c & 31));
-  }
-  __syncthreads();
-  for (unsigned w = threadIdx.x; w < (unsigned)kCellWords; w += kMSurveyBlock)
-    if (s_bits[w]) atomicOr(&colbits[w], s_bits[w]);
-}
-
-__global__ __launch_bounds__(kMSurveyBlock) void k_y_cell_count(const unsigned* __restrict__ colbits, DevStatus* st) {
-  __shared__ unsigned long long s_wave[kMSurveyBlock / 64 + 1];
-  unsigned long long n = 0;
-  for (unsigned w = threadIdx.x; w < (unsigned)kCellWords; w += kMSurveyBlock) n += (unsigned)__popc(colbits[w]);
-  n = block_sum<kMSurveyBlock>(n, s_wave);
-  if (threadIdx.x == 0) st->ycols = (unsigned)n;
-}
-
 // Runs: the non-empty Y table slots in slot order, which is the order of
 // their starts (the table scan placed the runs in slot order).
 struct MfmaRunOp {
@@ -454,10 +430,19 @@ __global__ __launch_bounds__(kMBlock, 3) void k_group_block_mfma(GroupArgs a, co
 }
 
 // Block survey: the block class's products, a thread per block group, one
-// atomic per wave.  (The scatter kernels flag non-finite values.)
+// atomic per wave, and (workgroup 0) the number of Y free cells that occur.
+// (The scatter kernels flag non-finite values.)
 __global__ __launch_bounds__(256) void k_block_survey(const GroupRec* __restrict__ groups,
                                                       const uint32_t* __restrict__ blist,
-                                                      const unsigned long long* __restrict__ eoff, DevStatus* st) {
+                                                      const unsigned long long* __restrict__ eoff,
+                                                      const unsigned* __restrict__ colbits, DevStatus* st) {
+  if (blockIdx.x == 0) {
+    __shared__ unsigned long long s_wave[256 / 64 + 1];
+    unsigned long long n = 0;
+    for (unsigned w = threadIdx.x; w < (unsigned)kCellWords; w += 256) n += (unsigned)__popc(colbits[w]);
+    n = block_sum<256>(n, s_wave);
+    if (threadIdx.x == 0) st->ycols = (unsigned)n;
+  }
   const int64_t nb = (int64_t)st->class_hi;
   unsigned long long prod = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += (int64_t)gridDim.x * blockDim.x) {
@@ -471,8 +456,8 @@ __global__ __launch_bounds__(256) void k_block_survey(const GroupRec* __restrict
 }  // namespace
 
 hipError_t launch_block_survey(const GroupRec* groups, const uint32_t* blist, const unsigned long long* eoff,
-                               DevStatus* st, int num_cus, hipStream_t stream) {
-  k_block_survey<<<(unsigned)(2 * num_cus), 256, 0, stream>>>(groups, blist, eoff, st);
+                               const unsigned* colbits, DevStatus* st, int num_cus, hipStream_t stream) {
+  k_block_survey<<<(unsigned)(2 * num_cus), 256, 0, stream>>>(groups, blist, eoff, colbits, st);
   return hipGetLastError();
 }
 
@@ -480,14 +465,6 @@ hipError_t launch_mfma_runs(const YSlot* ytab, int64_t yslots, int64_t ny, unsig
                             int64_t nruns, DevStatus* st, void* tile_sums, hipStream_t stream) {
   return device_scan(MfmaRunOp{ytab, run_start, runid, (unsigned)ny}, yslots, tile_sums,
                      FinRuns{run_start, (unsigned)ny, (unsigned long long)nruns, st}, stream);
-}
-
-hipError_t launch_y_cells(const uint16_t* ykey16, int64_t ny, unsigned* colbits, DevStatus* st, int num_cus,
-                          hipStream_t stream) {
-  if (ny > 0)
-    k_y_cells<<<grid_for(ny, kMSurveyBlock, num_cus, 1), kMSurveyBlock, 0, stream>>>(ykey16, ny, colbits);
-  k_y_cell_count<<<1, kMSurveyBlock, 0, stream>>>(colbits, st);
-  return hipGetLastError();
 }
 
 hipError_t launch_mfma_panels(const unsigned* colbits, const GroupRec* groups, const uint32_t* blist, int64_t nb,

@@ -1215,13 +1215,16 @@ template <bool SORT>
 __global__ __launch_bounds__(kBBlock) void k_sort_y_runs(const YSlot* __restrict__ ytab, int64_t nslots,
                                                          YEntry* __restrict__ yg, int64_t ny,
                                                          uint16_t* __restrict__ ykey16, double* __restrict__ yval,
-                                                         DevStatus* st) {
+                                                         unsigned* __restrict__ colbits, DevStatus* st) {
   __shared__ unsigned long long s_key[kBBlock];
   __shared__ YEntry s_ent[kBBlock];
-  __shared__ unsigned s_seen[(1u << kDenseBits) / 32];
   constexpr unsigned kSeenWords = (1u << kDenseBits) / 32;
+  __shared__ unsigned s_seen[kSeenWords];
+  __shared__ unsigned s_cells[kSeenWords];  // cells that occur in this workgroup's runs
+  for (unsigned w = threadIdx.x; w < kSeenWords; w += kBBlock) s_cells[w] = 0u;
   auto seen_before = [&](unsigned long long phi) {
     const unsigned c = (unsigned)phi & ((1u << kDenseBits) - 1u), bit = 1u << (c & 31);
+    if (colbits) atomicOr(&s_cells[c >> 5], bit);
     return (atomicOr(&s_seen[c >> 5], bit) & bit) != 0u;
   };
   for (int64_t slot = blockIdx.x; slot < nslots; slot += gridDim.x) {
@@ -1259,6 +1262,11 @@ __global__ __launch_bounds__(kBBlock) void k_sort_y_runs(const YSlot* __restrict
       yval[t.start + tid] = e.v;
     }
     __syncthreads();
+  }
+  if (colbits) {
+    __syncthreads();
+    for (unsigned w = threadIdx.x; w < kSeenWords; w += kBBlock)
+      if (s_cells[w]) atomicOr(&colbits[w], s_cells[w]);
   }
 }
 
@@ -1509,13 +1517,16 @@ hipError_t launch_scan_group_counts(const uint32_t* gn, const uint32_t* wlist, i
 }
 
 hipError_t launch_sort_y_runs(const YSlot* ytab, int64_t nslots, YEntry* yg, int64_t ny, uint16_t* ykey16,
-                              double* yval, DevStatus* st, bool sort, int num_cus, hipStream_t stream) {
+                              double* yval, unsigned* colbits, DevStatus* st, bool sort, int num_cus,
+                              hipStream_t stream) {
   if (nslots <= 0 || ny <= 0) return hipSuccess;
   int64_t grid = nslots < (int64_t)num_cus * 2 ? nslots : (int64_t)num_cus * 2;
   if (sort)
-    k_sort_y_runs<true><<<dim3((unsigned)grid), kBBlock, 0, stream>>>(ytab, nslots, yg, ny, ykey16, yval, st);
+    k_sort_y_runs<true><<<dim3((unsigned)grid), kBBlock, 0, stream>>>(ytab, nslots, yg, ny, ykey16, yval, colbits,
+                                                                       st);
   else
-    k_sort_y_runs<false><<<dim3((unsigned)grid), kBBlock, 0, stream>>>(ytab, nslots, yg, ny, ykey16, yval, st);
+    k_sort_y_runs<false><<<dim3((unsigned)grid), kBBlock, 0, stream>>>(ytab, nslots, yg, ny, ykey16, yval, colbits,
+                                                                        st);
   return hipGetLastError();
 }
 

@@ -543,8 +543,8 @@ sptc_status plan_group_y(sptc_plan_s* P, const sptc_coo* Y) {
                              P->yg, P->yset, (uint64_t)P->yset_slots - 1, yset_bits(P), P->st, P->num_cus, s));
   if (P->opt.mode == SPTC_MODE_GROUPED && P->dense) {
     // the runs are sorted later, for the block walk only (plan_grouped)
-    HIP_TRY(launch_sort_y_runs(P->ytab, P->ytab_slots, P->yg, P->ny, P->ykey16, P->yval, P->st, false, P->num_cus, s));
-    HIP_TRY(launch_y_cells(P->ykey16, P->ny, P->ycolbits, P->st, P->num_cus, s));
+    HIP_TRY(launch_sort_y_runs(P->ytab, P->ytab_slots, P->yg, P->ny, P->ykey16, P->yval, P->ycolbits, P->st, false,
+                               P->num_cus, s));
   }
   HIP_TRY(mark(P, s, SPTC_STAGE_Y_SCATTER, 1));
   return SPTC_OK;
@@ -697,7 +697,7 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
   // below, decide the matrix-core class with no read-back of its own
   P->block_surveyed = P->dense && !P->in_batch && P->opt.block_mfma != 0;
   if (P->block_surveyed)
-    HIP_TRY(launch_block_survey(P->groups, P->blist, P->eoff, P->st, P->num_cus, s));
+    HIP_TRY(launch_block_survey(P->groups, P->blist, P->eoff, P->ycolbits, P->st, P->num_cus, s));
   HIP_TRY(mark(P, s, SPTC_STAGE_P_SCAN, 1));
 
   DevStatus host{};
@@ -728,7 +728,7 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
       if (!P->block_mfma) {
         // the walk merges each group's entries in Y-run order, and walks
         // runs sorted by Y free key (consecutive accumulator cells)
-        HIP_TRY(launch_sort_y_runs(P->ytab, P->ytab_slots, P->yg, P->ny, P->ykey16, P->yval, P->st, true,
+        HIP_TRY(launch_sort_y_runs(P->ytab, P->ytab_slots, P->yg, P->ny, P->ykey16, P->yval, nullptr, P->st, true,
                                    P->num_cus, s));
         HIP_TRY(launch_sort_block_entries(P->groups, P->blist, P->nb, P->xr, P->bneff, P->num_cus, s));
       }

@@ -358,16 +358,13 @@ hipError_t launch_group_block(const GroupArgs& a, const uint32_t* blist, int64_t
 hipError_t launch_sort_block_entries(const GroupRec* groups, const uint32_t* blist, int64_t nb, XRec* xr,
                                      uint32_t* neff, int num_cus, hipStream_t stream);
 
-// Dense Y free keys: the cells that occur (colbits, kCellWords words,
-// zeroed first) and their number in st->ycols.
-hipError_t launch_y_cells(const uint16_t* ykey16, int64_t ny, unsigned* colbits, DevStatus* st, int num_cus,
-                          hipStream_t stream);
 // Block survey, before the class counts are read back: the block class's
-// products into st->block_products (zeroed first); the block list's length
-// is read on the device (st->class_hi).  The X and Y scatter kernels set
+// products into st->block_products (zeroed first; the block list's length
+// is read on the device, st->class_hi) and the number of occurring Y free
+// cells (bits of colbits) into st->ycols.  The X and Y scatter kernels set
 // st->nonfinite when a value is Inf or NaN.
 hipError_t launch_block_survey(const GroupRec* groups, const uint32_t* blist, const unsigned long long* eoff,
-                               DevStatus* st, int num_cus, hipStream_t stream);
+                               const unsigned* colbits, DevStatus* st, int num_cus, hipStream_t stream);
 // Matrix-core block class, plan time.  runs: the run list
 // (run_start[0..nruns], the last entry ny; runid[ny] gets each run's index
 // at its start; a count other than nruns records an internal error).
@@ -403,9 +400,12 @@ hipError_t launch_finalize(int64_t* out_nnz, int64_t out_cap, DevStatus* st, hip
 
 // Dense Y free keys: writes the compact copy of grouped Y (16-bit keys,
 // values) the dense accumulators read and flags repeated Y coordinates;
-// with sort, first sorts each run of 2..1024 entries by Y free key.
+// with sort, first sorts each run of 2..1024 entries by Y free key.  With
+// colbits (kCellWords words, zeroed first), also ORs in a bit for every
+// Y free cell that occurs.
 hipError_t launch_sort_y_runs(const YSlot* ytab, int64_t nslots, YEntry* yg, int64_t ny, uint16_t* ykey16,
-                              double* yval, DevStatus* st, bool sort, int num_cus, hipStream_t stream);
+                              double* yval, unsigned* colbits, DevStatus* st, bool sort, int num_cus,
+                              hipStream_t stream);
 
 // Clears st->err and st->out_base.
 hipError_t launch_reset_status(DevStatus* st, hipStream_t stream);
