@@ -690,9 +690,12 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
   HIP_TRY(mark(P, s, SPTC_STAGE_X_PROBE, 1));
   HIP_TRY(mark(P, s, SPTC_STAGE_P_SCAN, 0));
   HIP_TRY(launch_scan_entries(P->xr, P->nx, P->eoff, P->tile_sums, P->st, s));
-  HIP_TRY(launch_classify(P->groups, P->nx, P->eoff, P->ycells, P->dense, P->dlist, P->wlist, P->blist, P->glist,
-                          P->dpos, P->tile_sums, P->st, s));
-  HIP_TRY(launch_scan_direct(P->nx, P->dpos, P->tile_sums, P->st, s));
+  // at most one X group per occupied table slot: small tables make these
+  // scans a single tile
+  const int64_t max_groups = std::min<int64_t>(P->nx, P->xtab_slots);
+  HIP_TRY(launch_classify(P->groups, max_groups, P->eoff, P->ycells, P->dense, P->dlist, P->wlist, P->blist,
+                          P->glist, P->dpos, P->tile_sums, P->st, s));
+  HIP_TRY(launch_scan_direct(max_groups, P->dpos, P->tile_sums, P->st, s));
   // the block class's products and finiteness, read back with the counts
   // below, decide the matrix-core class with no read-back of its own
   P->block_surveyed = P->dense && !P->in_batch && P->opt.block_mfma != 0;
