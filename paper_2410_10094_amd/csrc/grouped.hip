@@ -238,16 +238,17 @@ __global__ __launch_bounds__(kAggBlock) void k_x_scatter_agg(const int32_t* __re
                                                              XRec* __restrict__ xr, DevStatus* st) {
   bool bad = false;  // a value is Inf or NaN
   extern __shared__ unsigned s_agg[];
-  place_chunk(xidx, nnz, kf, nslots, choff, s_agg, s_agg + nslots,
-              [&](const int64_t* e, const uint64_t*, const unsigned* pos, const bool* ok) {
+  const bool check = b.check != 0;
+  place_chunk(xidx, nnz, kf, check, b, nslots, choff, s_agg, s_agg + nslots,
+              [&](const int64_t* e, const uint64_t*, const unsigned* pos, const bool* ok, const bool* inbf) {
                 uint64_t ckey[kAggUnroll];
                 ProbeSeq ys[kAggUnroll];
                 YSlot slot[kAggUnroll];
                 double v[kAggUnroll];
-                bool inb[kAggUnroll];
-                pack_keys<kAggUnroll>(xidx, nnz, e, ok, kc, ckey);
-                if (b.check)
-                  coords_ok_batch<kAggUnroll>(xidx, nnz, e, ok, b, inb);
+                bool inb[kAggUnroll];  // the two packs read every mode once, and check it on the way
+#pragma unroll
+                for (int u = 0; u < kAggUnroll; ++u) inb[u] = inbf[u];
+                pack_keys<kAggUnroll>(xidx, nnz, e, ok, kc, ckey, check, b, inb);
 #pragma unroll
                 for (int u = 0; u < kAggUnroll; ++u) ys[u] = probe_seq(ckey[u], yg, seed);
 #pragma unroll
@@ -260,7 +261,7 @@ __global__ __launch_bounds__(kAggBlock) void k_x_scatter_agg(const int32_t* __re
 #pragma unroll
                 for (int u = 0; u < kAggUnroll; ++u) {
                   if (!ok[u]) continue;
-                  if (b.check && !inb[u]) record_error(st, kErrCoord);
+                  if (check && !inb[u]) record_error(st, kErrCoord);
                   if ((int64_t)pos[u] >= nnz) {
                     record_error(st, kErrInternal);
                     continue;

@@ -393,7 +393,8 @@ __global__ __launch_bounds__(kAggBlock) void k_key_count_agg(const int32_t* __re
   extern __shared__ unsigned s_cnt[];
   for (unsigned s = threadIdx.x; s < nslots; s += kAggBlock) s_cnt[s] = 0u;
   __syncthreads();
-  for_chunk_batches(idx, nnz, kc, [&](const int64_t*, const uint64_t* keys, const bool* ok) {
+  const Bounds none{};
+  for_chunk_batches(idx, nnz, kc, false, none, [&](const int64_t*, const uint64_t* keys, const bool* ok, const bool*) {
 #pragma unroll
     for (int u = 0; u < kAggUnroll; ++u)
       if (ok[u]) atomicAdd(&s_cnt[(unsigned)keys[u]], 1u);
@@ -505,16 +506,18 @@ __global__ __launch_bounds__(kAggBlock) void k_y_scatter_agg(const int32_t* __re
                                                              DevStatus* st) {
   bool bad = false;  // a value is Inf or NaN
   extern __shared__ unsigned s_agg[];
-  place_chunk(yidx, nnz, kc, nslots, choff, s_agg, s_agg + nslots,
-              [&](const int64_t* e, const uint64_t* keys, const unsigned* pos, const bool* ok) {
+  const bool check = b.check != 0;
+  place_chunk(yidx, nnz, kc, check, b, nslots, choff, s_agg, s_agg + nslots,
+              [&](const int64_t* e, const uint64_t* keys, const unsigned* pos, const bool* ok, const bool* inbc) {
                 bool good[kAggUnroll], inb[kAggUnroll];
                 unsigned long long full[kAggUnroll];
                 uint64_t fk[kAggUnroll];
                 double v[kAggUnroll];
-                // every load of the batch in flight before any store
-                pack_keys<kAggUnroll>(yidx, nnz, e, ok, kf, fk);
-                if (b.check)
-                  coords_ok_batch<kAggUnroll>(yidx, nnz, e, ok, b, inb);
+                // every load of the batch in flight before any store; the
+                // two packs read every mode once, and check it on the way
+#pragma unroll
+                for (int u = 0; u < kAggUnroll; ++u) inb[u] = inbc[u];
+                pack_keys<kAggUnroll>(yidx, nnz, e, ok, kf, fk, check, b, inb);
 #pragma unroll
                 for (int u = 0; u < kAggUnroll; ++u) {
                   v[u] = ok[u] ? yval[e[u]] : 0.0;
@@ -525,7 +528,7 @@ __global__ __launch_bounds__(kAggBlock) void k_y_scatter_agg(const int32_t* __re
                   good[u] = ok[u];
                   full[u] = 0ull;
                   if (!ok[u]) continue;
-                  if (b.check && !inb[u]) record_error(st, kErrCoord);
+                  if (check && !inb[u]) record_error(st, kErrCoord);
                   if ((int64_t)pos[u] >= nnz) {
                     record_error(st, kErrInternal);
                     good[u] = false;

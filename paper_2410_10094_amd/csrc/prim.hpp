@@ -52,10 +52,12 @@ __device__ __forceinline__ uint64_t pack_key(const int32_t* __restrict__ idx, in
 }
 
 // The keys of U entries at once (entry u is e[u], read only where ok[u]):
-// two modes of all U entries in flight together.
+// two modes of all U entries in flight together.  With check, also clears
+// inb[u] when a coordinate it reads is outside its mode length (b.dim).
 template <int U>
 __device__ __forceinline__ void pack_keys(const int32_t* __restrict__ idx, int64_t nnz, const int64_t* e,
-                                          const bool* ok, const KeyPack& kp, uint64_t* keys) {
+                                          const bool* ok, const KeyPack& kp, uint64_t* keys, bool check,
+                                          const Bounds& b, bool* inb) {
 #pragma unroll
   for (int u = 0; u < U; ++u) keys[u] = 0ull;
   const int n = kp.n;
@@ -76,32 +78,11 @@ __device__ __forceinline__ void pack_keys(const int32_t* __restrict__ idx, int64
       const unsigned sh = field_shift(f);
 #pragma unroll
       for (int u = 0; u < U; ++u) keys[u] |= (uint64_t)(c[j][u] & m) << sh;
-    }
-  }
-}
-
-// coords_ok for U entries at once (good[u]; entries with !ok[u] pass).
-template <int U>
-__device__ __forceinline__ void coords_ok_batch(const int32_t* __restrict__ idx, int64_t nnz, const int64_t* e,
-                                                const bool* ok, const Bounds& b, bool* good) {
+      if (check) {
+        const uint32_t d = b.dim[field_mode(f)];
 #pragma unroll
-  for (int u = 0; u < U; ++u) good[u] = true;
-  const int n = b.order;
-  for (int t0 = 0; t0 < n; t0 += 2) {
-    uint32_t c[2][U];
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int t = t0 + j < n ? t0 + j : n - 1;
-      const int32_t* col = idx + (int64_t)t * nnz;
-#pragma unroll
-      for (int u = 0; u < U; ++u) c[j][u] = ok[u] ? (uint32_t)col[e[u]] : 0u;
-    }
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      if (t0 + j >= n) continue;
-      const uint32_t d = b.dim[t0 + j];
-#pragma unroll
-      for (int u = 0; u < U; ++u) good[u] = good[u] && c[j][u] < d;
+        for (int u = 0; u < U; ++u) inb[u] = inb[u] && c[j][u] < d;
+      }
     }
   }
 }
@@ -456,34 +437,38 @@ constexpr int kAggBlock = 1024;
 constexpr int kAggUnroll = 4;    // entries a thread handles at once (independent memory ops in flight)
 
 // Walks this workgroup's chunk kAggUnroll entries per thread at a time: f
-// receives the entry indices, their packed keys and which are in range.
+// receives the entry indices, their packed keys, which are in range and
+// (with check) whether the coordinates packed so far are inside b.
 template <class F>
 __device__ __forceinline__ void for_chunk_batches(const int32_t* __restrict__ idx, int64_t nnz, const KeyPack& kp,
-                                                  F f) {
+                                                  bool check, const Bounds& b, F f) {
   const int64_t c0 = (int64_t)blockIdx.x * kAggChunk;
   const int64_t c1 = c0 + kAggChunk < nnz ? c0 + kAggChunk : nnz;
   for (int64_t base = c0 + threadIdx.x; base < c1; base += (int64_t)kAggBlock * kAggUnroll) {
     int64_t e[kAggUnroll];
     uint64_t keys[kAggUnroll];
-    bool ok[kAggUnroll];
+    bool ok[kAggUnroll], inb[kAggUnroll];
 #pragma unroll
     for (int u = 0; u < kAggUnroll; ++u) {
       e[u] = base + (int64_t)u * kAggBlock;
       ok[u] = e[u] < c1;
+      inb[u] = true;
     }
-    pack_keys<kAggUnroll>(idx, nnz, e, ok, kp, keys);
-    f(e, keys, ok);
+    pack_keys<kAggUnroll>(idx, nnz, e, ok, kp, keys, check, b, inb);
+    f(e, keys, ok, inb);
   }
 }
 
 // Places this workgroup's chunk: key s's entries of this chunk start at
 // choff[chunk][s] (the start of s's run plus s's entries in earlier chunks)
 // and follow in chunk order; hands every batch of entries with their
-// positions to place(e, key, pos, ok).  No global atomics.
+// positions to place(e, key, pos, ok, inb) (inb: kc's coordinates inside b,
+// with check).  No global atomics.
 template <class F>
 __device__ __forceinline__ void place_chunk(const int32_t* __restrict__ idx, int64_t nnz, const KeyPack& kc,
-                                            unsigned nslots, const unsigned* __restrict__ choff, unsigned* s_cnt,
-                                            unsigned* s_base, F place) {
+                                            bool check, const Bounds& b, unsigned nslots,
+                                            const unsigned* __restrict__ choff, unsigned* s_cnt, unsigned* s_base,
+                                            F place) {
   const unsigned* row = choff + (size_t)blockIdx.x * nslots;
   const unsigned* start = choff + (size_t)((nnz + kAggChunk - 1) / kAggChunk) * nslots;
   // nslots <= 2^kAggBits: all of a thread's loads in flight at once
@@ -504,12 +489,13 @@ __device__ __forceinline__ void place_chunk(const int32_t* __restrict__ idx, int
     }
   }
   __syncthreads();
-  for_chunk_batches(idx, nnz, kc, [&](const int64_t* e, const uint64_t* keys, const bool* ok) {
+  for_chunk_batches(idx, nnz, kc, check, b, [&](const int64_t* e, const uint64_t* keys, const bool* ok,
+                                                const bool* inb) {
     unsigned pos[kAggUnroll];
 #pragma unroll
     for (int u = 0; u < kAggUnroll; ++u)
       pos[u] = ok[u] ? s_base[(unsigned)keys[u]] + atomicAdd(&s_cnt[(unsigned)keys[u]], 1u) : 0u;
-    place(e, keys, pos, ok);
+    place(e, keys, pos, ok, inb);
   });
 }
 
