@@ -455,7 +455,8 @@ __global__ __launch_bounds__(kAggBlock) void k_agg_colscan(unsigned* __restrict_
 
 // k_agg_slotscan (one workgroup): an exclusive scan of the key totals in
 // row nchunks turns them into run starts in place; every occurring key gets
-// its table entry (count and run start), and *total the entry count.
+// its table entry (count and run start), every other slot is set empty, and
+// *total gets the entry count.
 constexpr unsigned kSlotsPerThread = 8;
 static_assert((1u << kAggBits) <= kAggBlock * kSlotsPerThread, "one workgroup scans every key");
 
@@ -480,13 +481,11 @@ __global__ __launch_bounds__(kAggBlock) void k_agg_slotscan(unsigned* __restrict
   for (unsigned k = 0; k < kSlotsPerThread; ++k) {
     if (s0 + k >= nslots) break;
     row[s0 + k] = (unsigned)run;
-    if (cnt[k]) {
-      YSlot t;
-      t.key = s0 + k;
-      t.count = cnt[k];
-      t.start = (unsigned)run;
-      tab[s0 + k] = t;
-    }
+    YSlot t;  // every slot is written: the table needs no fill beforehand
+    t.key = cnt[k] ? (unsigned long long)(s0 + k) : kEmpty;
+    t.count = cnt[k];
+    t.start = cnt[k] ? (unsigned)run : 0u;
+    tab[s0 + k] = t;
     run += cnt[k];
   }
   const unsigned long long nused = block_sum_t<kAggBlock>((unsigned long long)used, s_wave);
@@ -591,8 +590,9 @@ hipError_t launch_y_scatter(const int32_t* yidx, const double* yval, int64_t nnz
 hipError_t launch_key_count_agg(const int32_t* idx, int64_t nnz, KeyPack kc, YSlot* tab, unsigned nslots,
                                 unsigned* hist, unsigned long long* total, unsigned long long* distinct,
                                 hipStream_t stream) {
-  if (nnz <= 0) return hipSuccess;
   if (nslots > (1u << kAggBits)) return hipErrorInvalidValue;
+  // no entries: no slot scan runs, so the table is set empty here
+  if (nnz <= 0) return launch_fill_empty(tab, nslots, nullptr, stream);
   const unsigned chunks = (unsigned)agg_chunks(nnz);
   k_key_count_agg<<<chunks, kAggBlock, (size_t)nslots * 4, stream>>>(idx, nnz, kc, nslots, hist);
   hipError_t e = hipGetLastError();

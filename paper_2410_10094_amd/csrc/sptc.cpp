@@ -521,7 +521,7 @@ sptc_status plan_group_y(sptc_plan_s* P, const sptc_coo* Y) {
   sptc_status st;
   if (P->y_agg && (st = P->allocate_n((agg_chunks(P->ny) + 1) * P->ytab_slots, &P->yhist))) return st;
   HIP_TRY(mark(P, s, SPTC_STAGE_Y_COUNT, 0));
-  HIP_TRY(launch_fill_empty(P->ytab, P->ytab_slots, nullptr, s));
+  if (!P->y_agg) HIP_TRY(launch_fill_empty(P->ytab, P->ytab_slots, nullptr, s));  // the aggregated count writes every slot
   if (P->y_agg)
     HIP_TRY(launch_key_count_agg(Y->idx, P->ny, P->y_c, P->ytab, (unsigned)P->ytab_slots, P->yhist, P->agg_total,
                                  &P->st->groups, s));
@@ -672,7 +672,7 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
                              P->groups, P->ytab, P->ygeom, P->max_probe_y, seed, P->xr, P->tile_sums, P->st,
                              P->num_cus, s));
   } else {
-    HIP_TRY(launch_fill_empty(P->xtab, P->xtab_slots, nullptr, s));
+    if (!P->x_agg) HIP_TRY(launch_fill_empty(P->xtab, P->xtab_slots, nullptr, s));  // (as for Y)
     if (P->x_agg)
       HIP_TRY(launch_key_count_agg(X->idx, P->nx, P->x_f, P->xtab, (unsigned)P->xtab_slots, P->xhist, P->agg_total,
                                    nullptr, s));

@@ -194,8 +194,9 @@ hipError_t launch_key_count(const int32_t* idx, int64_t nnz, KeyPack kc, YSlot* 
 // each workgroup histograms a chunk of kAggChunk entries in LDS into row
 // `chunk` of hist [agg_chunks(nnz) + 1][nslots]; column scans turn row w
 // into the entries of each key in chunks before w, and the last row into
-// each key's run start; the table gets every key's count and run start (no
-// global atomics).  total: one device u64 (the entry count).
+// each key's run start; the table gets every key's count and run start and
+// every other slot is set empty (no fill needed first; no global
+// atomics).  total: one device u64 (the entry count).
 hipError_t launch_key_count_agg(const int32_t* idx, int64_t nnz, KeyPack kc, YSlot* tab, unsigned nslots,
                                 unsigned* hist, unsigned long long* total, unsigned long long* distinct,
                                 hipStream_t stream);
