@@ -63,6 +63,8 @@ def _load():
         lib.oracle_sample_outputs.restype = ctypes.c_int
         lib.oracle_values_at.argtypes = tens + tens + [i32, P, P, i64, P, P, P, P]
         lib.oracle_values_at.restype = ctypes.c_int
+        lib.oracle_count_outputs.argtypes = tens + tens + [i32, P, P, i32, P]
+        lib.oracle_count_outputs.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -182,3 +184,16 @@ def values_at(X, Y, cx, cy, coords: np.ndarray):
     _check(lib.oracle_values_at(*kx.args, *ky.args, len(cx), px, py, n, _ptr(coords) if coords.size else None,
                                 _ptr(val), _ptr(absval), _ptr(terms)))
     return val[:n], absval[:n], terms[:n]
+
+
+def count_outputs(X, Y, cx, cy, nthreads: int = 1) -> int:
+    """nnz of the contraction: the size of the output coordinate set of Eq. 2
+    (every coordinate reached by a matching pair, zero sums included),
+    counted without forming any value."""
+    lib = _load()
+    kx, ky = _Keep(X), _Keep(Y)
+    ax, px = _modes(cx)
+    ay, py = _modes(cy)
+    n = ctypes.c_int64()
+    _check(lib.oracle_count_outputs(*kx.args, *ky.args, len(cx), px, py, int(nthreads), ctypes.byref(n)))
+    return n.value

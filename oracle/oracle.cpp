@@ -38,6 +38,7 @@
 #include <map>
 #include <new>
 #include <random>
+#include <set>
 #include <thread>
 #include <vector>
 
@@ -390,6 +391,68 @@ int oracle_values_at(int32_t xo, const int64_t* xd, int64_t xn, const int32_t* x
         terms[s] += 1;
       }
     }
+  }
+  return ORACLE_OK;
+}
+
+
+// The number of distinct output coordinates, nnz(Z), by the definition of
+// the output coordinate set (section 2.2, Eq. 2; structural zeros kept):
+//
+//     S = { (x.c[fX], y.c[fY]) : x in X, y in Y, x.c[cx] = y.c[cy] }
+//
+// X entries are grouped by their free tuple; a group reaches the union, over
+// the contracting tuples its entries carry, of the Y free tuples that carry
+// the same contracting tuple.  |S| is the sum of the sizes of those unions.
+// No value is read.  `nthreads` >= 1 splits the X groups by leading free
+// coordinate (the count does not depend on it).
+int oracle_count_outputs(int32_t xo, const int64_t* xd, int64_t xn, const int32_t* xi, const double* xv, int32_t yo,
+                         const int64_t* yd, int64_t yn, const int32_t* yi, const double* yv, int32_t nc,
+                         const int32_t* cx, const int32_t* cy, int32_t nthreads, int64_t* count) {
+  if (!count) return ORACLE_BAD_ARG;
+  Problem p;
+  int rc = setup(p, xo, xd, xn, xi, xv, yo, yd, yn, yi, yv, nc, cx, cy);
+  if (rc != ORACLE_OK) return rc;
+  try {
+    // Y: contracting tuple -> its distinct free tuples
+    std::map<Tuple, std::set<Tuple>> yfree;
+    for (int64_t j = 0; j < yn; ++j) yfree[pick(p.Y, j, p.cy)].insert(pick(p.Y, j, p.fy));
+    // X: free tuple -> the distinct contracting tuples of its entries that Y has
+    int32_t parts = std::max<int32_t>(1, nthreads);
+    const int64_t lead_dim = p.fx.empty() ? 1 : xd[p.fx[0]];
+    parts = (int32_t)std::min<int64_t>(parts, lead_dim);
+    std::vector<int64_t> partial(parts, 0);
+    auto run = [&](int32_t k) {
+      std::map<Tuple, std::set<const std::set<Tuple>*>> groups;
+      for (int64_t i = 0; i < xn; ++i) {
+        if (parts > 1 && (int64_t)p.X.coord(p.fx[0], i) * parts / lead_dim != k) continue;
+        auto it = yfree.find(pick(p.X, i, p.cx));
+        if (it != yfree.end()) groups[pick(p.X, i, p.fx)].insert(&it->second);
+      }
+      int64_t n = 0;
+      for (const auto& g : groups) {
+        if (g.second.size() == 1) {
+          n += (int64_t)(*g.second.begin())->size();
+          continue;
+        }
+        std::set<Tuple> reach;
+        for (const std::set<Tuple>* s : g.second) reach.insert(s->begin(), s->end());
+        n += (int64_t)reach.size();
+      }
+      partial[k] = n;
+    };
+    if (parts == 1) {
+      run(0);
+    } else {
+      std::vector<std::thread> pool;
+      for (int32_t k = 0; k < parts; ++k) pool.emplace_back(run, k);
+      for (auto& t : pool) t.join();
+    }
+    int64_t total = 0;
+    for (int64_t n : partial) total += n;
+    *count = total;
+  } catch (const std::bad_alloc&) {
+    return ORACLE_NO_MEMORY;
   }
   return ORACLE_OK;
 }

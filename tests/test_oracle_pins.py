@@ -259,3 +259,36 @@ def test_sampled_values_match_full_result():
     # a coordinate no pair reaches has no terms
     v, a, t = oracle.values_at(p.X, p.Y, p.cx, p.cy, np.zeros((4, 1), np.int32) + 15)
     assert t[0] == 0 or (r.idx[:, -1] == 15).all()
+
+
+@pytest.mark.parametrize("p", H.tiny_problems(40, seed0=9300) + [W.plain(n=10, nnz=120)], ids=lambda p: p.name)
+def test_output_count_is_the_coordinate_set_size(p):
+    """nnz(Z) counted without values equals the size of the set of
+    free-coordinate pairs that share a contracting tuple (a Python set built
+    per key), and the number of cells einsum reaches with indicator
+    tensors."""
+    n = oracle.count_outputs(p.X, p.Y, p.cx, p.cy)
+    assert n == len(H.free_pair_set(p))
+    _, terms, _ = H.dense_reference(p)
+    assert n == int(np.count_nonzero(terms))
+    assert n == oracle.contract(p.X, p.Y, p.cx, p.cy).nnz
+
+
+def test_output_count_takes_the_union_over_keys():
+    """An X free tuple whose entries carry several contracting tuples reaches
+    the union of their Y free tuples: here 2 keys, each with Y free tuples
+    {0, 1} and {1, 2}, give 3 outputs, not 4.  Repeated entries count once."""
+    X = Coo((1, 2), np.array([[0, 0, 0], [0, 1, 1]], np.int32), np.array([1.0, 2.0, 3.0]))
+    Y = Coo((2, 3), np.array([[0, 0, 1, 1, 1], [0, 1, 1, 2, 2]], np.int32), np.ones(5))
+    assert oracle.count_outputs(X, Y, [1], [0]) == 3
+    assert oracle.contract(X, Y, [1], [0]).nnz == 3
+
+
+def test_output_count_threads_and_sizes():
+    p = W.random_problem(701, 3, 3, 1, 20, 40, 3000, 3000)
+    n = oracle.count_outputs(p.X, p.Y, p.cx, p.cy)
+    assert n == oracle.contract(p.X, p.Y, p.cx, p.cy).nnz
+    for t in (2, 7):
+        assert oracle.count_outputs(p.X, p.Y, p.cx, p.cy, nthreads=t) == n
+    q = W.block_sparse(n=16, block=4, p_block=0.3)
+    assert oracle.count_outputs(q.X, q.Y, q.cx, q.cy, nthreads=4) == oracle.contract(q.X, q.Y, q.cx, q.cy).nnz
