@@ -46,5 +46,9 @@ def assert_parity(p, gidx, gval, ref=None, nthreads=8):
     assert gval.shape[0] == ref.nnz, f"nnz {gval.shape[0]} != oracle {ref.nnz}"
     gi, gv = H.sort_coo(gidx, gval)
     np.testing.assert_array_equal(gi, ref.idx)
-    H.assert_values_close(gv, ref.val, ref.absval, ref.terms)
+    stats = H.assert_values_close(gv, ref.val, ref.absval, ref.terms)
+    if stats["multi_term_outputs"]:
+        log(f"[values] {getattr(p, 'name', '?')}: nnz {ref.nnz}, worst error "
+            f"{stats['worst_ratio_to_1e-12_sum_abs']:.3g} x 1e-12*sum|xy|, "
+            f"{stats['second_clause']} of {stats['multi_term_outputs']} multi-term outputs past 1e-12*|z|")
     return ref
