@@ -83,52 +83,66 @@ def algorithmic_bytes(stage, p, products, nnz_z, x_groups=0, mode="grouped", inf
 
 
 def survey_byte_model(p, products, nnz_z):
-    """Whole-step byte model of the survey's plan, which prices a
-    global-hash design: inputs once, grouped Y written and read, pass-1
-    records, 24 B of output-hash traffic per product, and the compaction.  The
-    grouped path keeps the per-product traffic in LDS, so its real HBM bytes
-    are far lower; this figure is kept for comparison only."""
+    """Whole-step algorithmic bytes of the method as a global-hash design
+    prices them: COO inputs read once, grouped Y written and read once (32 B
+    per Y entry), a pass-1 record per X entry (16 B), 24 B of output-hash
+    traffic per product (key read, value read, value written) and the
+    compaction (occupied slot read, COO written).  The global mode moves at
+    least this much.  The grouped path keeps the per-product traffic in LDS,
+    so its fraction of this model can exceed 1: the model then says how much
+    HBM traffic the per-group tables saved, not how close a kernel is to the
+    HBM peak."""
     nx, ny = p.X.nnz, p.Y.nnz
     nz_order = p.X.order + p.Y.order - 2 * len(p.cx)
     return (nx * (4 * p.X.order + 8) + ny * (4 * p.Y.order + 8) + 32 * ny + 16 * nx + 24 * products
             + nnz_z * (16 + 4 * nz_order + 8))
 
 
-def time_oracle(p, products_total, max_seconds=25.0):
-    """The CPU oracle on a bounded sample: a prefix of X against all of Y,
-    sized so one run takes about max_seconds at most.  Returns the record."""
-    import numpy as np
+def survey_roofline(p, products, nnz_z, sec):
+    b = survey_byte_model(p, products, nnz_z)
+    return {"bytes_per_step": b, "achieved_GBps": round(b / sec / 1e9, 1),
+            "frac_of_8TBps": round(b / sec / (HBM_PEAK_GBS * 1e9), 4)}
 
+
+def _oracle_sample(p, max_seconds, threads):
+    """The oracle on a prefix of X (against all of Y) sized so one run takes
+    about max_seconds at most.  Returns (products, outputs, seconds, n, nx)."""
     import oracle
     from paper_2410_10094_amd.workloads import Coo
-    threads = max(1, min(16, len(os.sched_getaffinity(0))))
     nx = p.X.nnz
-    frac = 1.0
-    # a small calibration run sets the sample size
-    probe_n = max(1, min(nx, 20_000))
+    probe_n = max(1, min(nx, 20_000 if threads > 1 else 4_000))
     Xs = Coo(p.X.dims, p.X.idx[:, :probe_n], p.X.val[:probe_n])
     _, pairs = oracle.match_counts(Xs, p.Y, p.cx, p.cy)
     t0 = time.perf_counter()
     oracle.contract(Xs, p.Y, p.cx, p.cy, nthreads=threads)
-    dt = max(time.perf_counter() - t0, 1e-6)
-    per_product = dt / max(pairs, 1)
-    budget_products = max_seconds / per_product
-    if products_total > budget_products:
-        frac = budget_products / products_total
-    n = max(1, min(nx, int(nx * frac)))
+    per_x = max(time.perf_counter() - t0, 1e-6) / probe_n
+    n = max(1, min(nx, int(max_seconds / per_x)))
     Xs = Coo(p.X.dims, p.X.idx[:, :n], p.X.val[:n])
     _, pairs = oracle.match_counts(Xs, p.Y, p.cx, p.cy)
     t0 = time.perf_counter()
     r = oracle.contract(Xs, p.Y, p.cx, p.cy, nthreads=threads)
-    dt = time.perf_counter() - t0
-    sample = "full workload" if n == nx else f"first {n} of {nx} X nonzeros against all of Y"
+    return pairs, r.nnz, time.perf_counter() - t0, n, nx
+
+
+def time_oracle(p, max_seconds=12.0):
+    """The CPU oracle as it stands, on bounded samples of the workload: on
+    the host cores this process may use (at most 16, the host share of one
+    GPU), and single-threaded.  Returns the cpu_baseline record."""
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    pairs, nnz, dt, n, nx = _oracle_sample(p, max_seconds, threads)
+    pairs1, nnz1, dt1, n1, _ = _oracle_sample(p, max_seconds, 1)
+    what = lambda k: "full workload" if k == nx else f"first {k} of {nx} X nonzeros against all of Y"
     return {"value": pairs / dt, "unit": "products/s", "cores": threads, "kind": "oracle",
-            "sample": f"{sample}: {pairs} products, {r.nnz} outputs, {dt:.2f} s, std::map join, "
+            "sample": f"{what(n)}: {pairs} products, {nnz} outputs, {dt:.2f} s, std::map join, "
                       f"{threads} threads partitioned by leading output coordinate",
-            "output_nnz_per_s": r.nnz / dt}
+            "output_nnz_per_s": nnz / dt,
+            "single_thread": {"value": pairs1 / dt1, "unit": "products/s", "cores": 1,
+                              "sample": f"{what(n1)}: {pairs1} products, {nnz1} outputs, {dt1:.2f} s",
+                              "output_nnz_per_s": nnz1 / dt1},
+            "host_cpus_visible": len(os.sched_getaffinity(0))}
 
 
-def run_workload(name, steps, warmup, with_events=True, mode="grouped", block_mfma=-1):
+def run_workload(name, steps, warmup, with_events=True, mode="grouped", block_mfma=0):
     import torch
 
     import paper_2410_10094_amd as sptc
@@ -251,10 +265,14 @@ def upload(draws):
     return dev
 
 
-def run_served(draws, dev, seconds, rate, budget_bytes, batch_products, max_batch, seed, load_factor=1 / 1.3):
+def run_served(draws, dev, seconds, rate, budget_bytes, batch_products, max_batch, seed, load_factor=1 / 1.3,
+               label="served"):
     """Poisson arrivals at `rate` per second for `seconds`; each request is a
     draw picked uniformly from the pool (inputs resident in HBM).  Served
-    with continuous batching under the memory budget."""
+    with continuous batching under the memory budget (max_batch 1: one
+    request per launch).  Every request is served to completion; the wall
+    time therefore exceeds the arrival window when the server falls
+    behind."""
     import numpy as np
 
     from paper_2410_10094_amd import sched, serve
@@ -267,19 +285,25 @@ def run_served(draws, dev, seconds, rate, budget_bytes, batch_products, max_batc
     import paper_2410_10094_amd as sptc
     backend = serve.TorchBackend(arena_bytes=budget_bytes, options=sptc.default_options(load_factor=load_factor))
     srv = serve.Server(backend, budget_bytes=budget_bytes, batch_products=batch_products, max_batch=max_batch)
+    progress(f"{label}: {len(reqs)} requests over {seconds:.0f} s")
     t0 = time.perf_counter()
-    done = srv.run(reqs)
+    done = srv.run(reqs, progress=lambda m: progress(f"{label}: {m}"))
     wall = time.perf_counter() - t0
     out = serve.latency_summary(done)
     products = sum(r.products for r in done)
+    in_window = [r for r in done if r.done <= seconds]
     out.update({"offered_requests_per_s": rate, "arrival_seconds": seconds, "wall_seconds": round(wall, 3),
                 "requests_per_s": len(done) / wall, "products": products, "products_per_s": products / wall,
+                "served_within_arrival_window": len(in_window),
                 "batches": srv.batches, "mean_batch": round(len(done) / max(srv.batches, 1), 2),
                 "peak_bytes": srv.peak_used, "budget_bytes": budget_bytes, "waits_for_memory": srv.waits_for_memory,
+                "deferred_requests": srv.deferred_requests, "admitted_requests": len(done),
                 "batch_products": batch_products, "max_batch": max_batch})
     for k in ("latency_ms_p50", "latency_ms_p99", "latency_ms_max", "latency_ms_mean"):
         if k in out:
             out[k] = round(out[k], 3)
+    progress(f"{label}: {len(done)} requests in {wall:.1f} s, p50 {out.get('latency_ms_p50')} ms, "
+             f"p99 {out.get('latency_ms_p99')} ms")
     return out
 
 
@@ -338,6 +362,10 @@ def run_batched(draws, dev, steps, warmup, budget, load_factor=1 / 1.3):
     bidx = torch.empty(max(need_i, 1), dtype=torch.int32, device="cuda")
     bval = torch.empty(max(need_v, 1), dtype=torch.float64, device="cuda")
     bnnz = torch.empty(len(draws), dtype=torch.int64, device="cuda")
+    # batch k's members' nnz land at bnnz[first[k] : first[k] + len(groups[k])]
+    first = [0]
+    for g in groups:
+        first.append(first[-1] + len(g))
 
     from paper_2410_10094_amd import binding as B
     nst = len(B.STAGES)
@@ -356,7 +384,7 @@ def run_batched(draws, dev, steps, warmup, budget, load_factor=1 / 1.3):
                 opt.stage_events = ctypes.cast(ev_arrays[k], ctypes.POINTER(ctypes.c_void_p))
             t0 = time.perf_counter()
             bt = sptc.batch([(dev[i][0], dev[i][1], draws[i].cx, draws[i].cy) for i in g], options=opt)
-            bt.execute_into(bidx, bval, bnnz[g[0]:g[0] + len(g)])
+            bt.execute_into(bidx, bval, bnnz[first[k]:first[k] + len(g)])
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             lat.extend([dt] * len(g))
@@ -392,16 +420,39 @@ def run_batched(draws, dev, steps, warmup, budget, load_factor=1 / 1.3):
     res["products"] = total_products
     res["nnz_x_total"] = sum(p.X.nnz for p in draws)
     res["nnz_y_total"] = sum(p.Y.nnz for p in draws)
+    # nnz(Z) of every draw, from the per-call leg, and the same total from the batched leg
+    per_nnz = onnz.cpu().tolist()
+    bat = bnnz.cpu().tolist()
+    batched_nnz = [0] * len(draws)
+    for k, g in enumerate(groups):
+        for j, i in enumerate(g):
+            batched_nnz[i] = bat[first[k] + j]
+    if batched_nnz != per_nnz:
+        raise RuntimeError("batched and per-call legs disagree on nnz(Z)")
+    res["nnz_z_total"] = sum(per_nnz)
+    b_alg = sum(survey_byte_model(p, P, n) for p, P, n in zip(draws, products, per_nnz))
+    res["survey_roofline"] = {"bytes_per_pass": b_alg}
+    for name in ("per_call", "batched"):
+        sec = res[name]["sec_per_step"]
+        res[name]["output_nnz_per_s"] = res["nnz_z_total"] / sec
+        res[name]["survey_frac_of_8TBps"] = round(b_alg / sec / (HBM_PEAK_GBS * 1e9), 4)
     res["steps"] = steps
     return res
 
 
 # HBM traffic of a dominant kernel, from two committed rocprofv3 --pmc runs
-# (FETCH_SIZE, then WRITE_SIZE), keyed by (workload, stage).  A figure only
+# (FETCH_SIZE, then WRITE_SIZE), keyed by (workload, kernel).  A figure only
 # holds while the kernel's sources are the ones profiled.
-TRAFFIC_PROFILES = {("block-sparse-1.5M", "block"): "block_mfma_block-sparse-1.5M_hbm_counters.md"}
+TRAFFIC_PROFILES = {
+    ("block-sparse-1.5M", "k_group_block_dense"): "block_walk_block-sparse-1.5M_counters.md",
+    ("block-sparse-1.5M", "k_group_block_mfma"): "block_mfma_block-sparse-1.5M_hbm_counters.md",
+    ("imbalanced", "k_group_direct"): "direct_imbalanced_counters.md",
+    ("block-sparse-1.5M", "k_expand_acc"): "expand_global_block-sparse-1.5M_counters.md",
+    ("imbalanced", "k_expand_acc"): "expand_global_imbalanced_counters.md",
+}
 KERNEL_SOURCES = ("paper_2410_10094_amd/csrc/grouped.hip", "paper_2410_10094_amd/csrc/block_mfma.hip",
-                  "paper_2410_10094_amd/csrc/prim.hpp", "paper_2410_10094_amd/csrc/sptc_internal.hpp")
+                  "paper_2410_10094_amd/csrc/kernels.hip", "paper_2410_10094_amd/csrc/prim.hpp",
+                  "paper_2410_10094_amd/csrc/sptc_internal.hpp")
 
 
 def kernel_source_hash():
@@ -413,10 +464,10 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(workload, stage):
+def measured_traffic(workload, kernel):
     """Bytes per launch from the committed counter summary, or None when
     there is none or the kernel changed since it was taken."""
-    name = TRAFFIC_PROFILES.get((workload, stage))
+    name = TRAFFIC_PROFILES.get((workload, kernel))
     path = os.path.join(ROOT, "profiles", name) if name else None
     if not path or not os.path.exists(path):
         return None
@@ -475,7 +526,7 @@ def run_sweep(steps):
                 p = W.paper_set(W.BASE_SEED + 10 * set_no + ox + oy, mode_len, nnz, ox, oy)
                 sec, P, n = time_problem(p, steps, 1)
                 row = {"set": set_no, "nnz": nnz, "orders": f"{ox}x{oy}", "products": P, "out_nnz": n,
-                       "ms": round(sec * 1e3, 4), "products_per_s": P / sec}
+                       "ms": round(sec * 1e3, 4)}
                 if ox != oy:  # operand swap: Y x X on the same data
                     from paper_2410_10094_amd.workloads import Problem
                     q = Problem(p.name + "-swap", p.Y, p.X, p.cy, p.cx)
@@ -486,34 +537,78 @@ def run_sweep(steps):
     return rows
 
 
+def kernel_of(stage, info):
+    """The kernel that does a stage's work (for the dominant stage)."""
+    if stage == "block":
+        if info.get("block_mfma"):
+            return "k_group_block_mfma"
+        return "k_group_block_dense" if info["key_bits"][2] <= 13 else "k_group_block"
+    return {"direct": "k_group_direct", "expand": "k_expand_acc", "group_count": "k_group_wave",
+            "group_fill": "k_group_wave", "compact": "occupancy scan", "x_probe": "X grouping",
+            "x_sort": "block entry sort"}.get(stage, stage)
+
+
 def roofline_of(r):
+    """Roofline of the dominant stage's kernel: its algorithmic bytes per
+    launch (bench.algorithmic_bytes: each datum it must move through HBM,
+    once; on the global path that includes 24 B of output-hash traffic per
+    product) over its event-measured time per launch, against 8 TB/s."""
     p = r["problem"]
     stage = max(r["stage_ms"], key=lambda s: r["stage_ms"][s])
     ms = r["stage_ms"][stage]
     bytes_alg = algorithmic_bytes(stage, p, r["products"], r["nnz_z"], r["info"]["x_groups"], r["mode"], r["info"])
     achieved = bytes_alg / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
-    out = {"kernel": stage, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(r["name"], stage),
-           "ms_per_launch": round(ms, 4), "algorithmic_bytes_per_launch": bytes_alg}
+    kernel = kernel_of(stage, r["info"])
+    out = {"kernel": kernel, "stage": stage, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+           "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(r["name"], kernel),
+           "ms_per_launch": round(ms, 4), "algorithmic_bytes_per_launch": bytes_alg,
+           "byte_model": "per-kernel" if stage != "expand" else "survey (24 B per product in the output hash)",
+           "products_per_s_in_kernel": round(r["products"] / (ms * 1e-3)) if ms > 0 else None}
     work = r["info"].get("block_mfma_work", 0)
     if stage == "block" and r["info"].get("block_mfma") and work and ms > 0:
-        # the block class ran as a dense FP64 product: its multiply-adds over
-        # the padded tiles against the matrix cores' FP64 peak
-        dense = 2.0 * work / (ms * 1e-3) / 1e12
+        # the block class ran as a dense FP64 product: the method's useful
+        # flops (one multiply and one add per product) against the matrix
+        # cores' FP64 peak; the padded dense work it spent them in is context
         useful = 2.0 * r["products"] / (ms * 1e-3) / 1e12
-        out["matrix_cores"] = {"kernel": "k_group_block_mfma", "dense_flops_per_launch": 2 * work,
-                               "achieved_tflops": round(dense, 2), "peak_tflops": FP64_MFMA_PEAK_TFLOPS,
-                               "frac": round(dense / FP64_MFMA_PEAK_TFLOPS, 4),
-                               "useful_flops_per_launch": 2 * r["products"], "useful_tflops": round(useful, 2)}
+        dense = 2.0 * work / (ms * 1e-3) / 1e12
+        out["matrix_cores"] = {"kernel": "k_group_block_mfma", "useful_flops_per_launch": 2 * r["products"],
+                               "achieved_tflops": round(useful, 2), "peak_tflops": FP64_MFMA_PEAK_TFLOPS,
+                               "frac": round(useful / FP64_MFMA_PEAK_TFLOPS, 4),
+                               "padded_flops_per_launch": 2 * work, "padded_tflops": round(dense, 2),
+                               "padding_ratio": round(work / max(r["products"], 1), 2)}
     return out
 
 
-def summary(name, r):
-    return {"workload": name, "products": r["products"], "out_nnz": r["nnz_z"],
-            "ms_per_step": round(r["sec"] * 1e3, 4), "products_per_s": r["products"] / r["sec"],
-            "output_nnz_per_s": r["nnz_z"] / r["sec"],
-            "stage_ms": {k: round(v, 4) for k, v in r["stage_ms"].items() if not k.startswith("batch_")},
-            "roofline": roofline_of(r)}
+def summary(name, r, variant=None):
+    out = {"workload": name, "mode": r["mode"], "products": r["products"], "out_nnz": r["nnz_z"],
+           "ms_per_step": round(r["sec"] * 1e3, 4), "products_per_s": r["products"] / r["sec"],
+           "output_nnz_per_s": r["nnz_z"] / r["sec"],
+           "stage_ms": {k: round(v, 4) for k, v in r["stage_ms"].items() if not k.startswith("batch_")},
+           "roofline": roofline_of(r),
+           "survey_roofline": survey_roofline(r["problem"], r["products"], r["nnz_z"], r["sec"])}
+    if variant:
+        out["variant"] = variant
+    return out
+
+
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def compact_batched(res):
+    if not res:
+        return res
+    keep = ("contractions", "products", "nnz_z_total", "load_factor", "speedup_batched_vs_per_call", "steps",
+            "survey_roofline")
+    out = {k: res[k] for k in keep if k in res}
+    for name in ("per_call", "batched"):
+        out[name] = {k: v for k, v in res[name].items() if k != "stage_ms_per_step"}
+    out["batched"]["top_stages_ms"] = dict(sorted(res["batched"].get("stage_ms_per_step", {}).items(),
+                                                  key=lambda kv: -kv[1])[:5])
+    if res.get("autotune"):
+        out["autotune"] = {k: res["autotune"][k] for k in ("load_factor", "batch_products", "tuning_seconds")
+                           if k in res["autotune"]}
+    return out
 
 
 def main():
@@ -524,13 +619,18 @@ def main():
     ap.add_argument("--workload", default="block-sparse-1.5M", choices=sorted(DESCRIPTIONS))
     ap.add_argument("--also", default="block-sparse,imbalanced,plain",
                     help="comma-separated extra workloads reported under 'also' ('' for none)")
+    ap.add_argument("--global-legs", default="block-sparse-1.5M,imbalanced",
+                    help="workloads also timed in the global mode (every product in the device output hash)")
+    ap.add_argument("--mfma-leg", type=int, default=1,
+                    help="1: also time the headline workload with the opt-in matrix-core block class")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (known bytes for scaling HBM counters) and exit")
     ap.add_argument("--mode", default="grouped", choices=["grouped", "global"],
                     help="accumulation strategy: per-X-group LDS tables (default) or one global hash")
-    ap.add_argument("--block-mfma", type=int, default=-1, choices=[-1, 0, 1],
-                    help="dense block class on the FP64 matrix cores: -1 the plan's cost rule, 0 never, 1 when eligible")
+    ap.add_argument("--block-mfma", type=int, default=0, choices=[-1, 0, 1],
+                    help="dense block class on the FP64 matrix cores: 0 never (default), 1 when eligible, "
+                         "-1 the plan's cost rule")
     ap.add_argument("--batched", type=int, default=512, metavar="COUNT",
                     help="draws of the batched workload timed per-call and batched (0: skip)")
     ap.add_argument("--batch-budget", type=float, default=1.0e9,
@@ -538,8 +638,8 @@ def main():
     ap.add_argument("--autotune", type=int, default=1,
                     help="1: tune load factor and batch budget on the first 128 draws before the batched legs")
     ap.add_argument("--sweep", type=int, default=1, help="1: time the paper's synthetic-set shapes (Table 1, sets 1-2)")
-    ap.add_argument("--serve", type=float, default=3.0, metavar="SECONDS",
-                    help="seconds of Poisson arrivals for the served leg (0: skip); the pool is the batched draws")
+    ap.add_argument("--serve", type=float, default=60.0, metavar="SECONDS",
+                    help="seconds of Poisson arrivals for the served legs (0: skip); the pool is the batched draws")
     ap.add_argument("--serve-rate", type=float, default=2000.0, help="arrivals per second of the served leg")
     ap.add_argument("--serve-budget-gb", type=float, default=64.0, help="device-memory budget of the served leg")
     ap.add_argument("--serve-batch-products", type=float, default=1e9,
@@ -571,12 +671,23 @@ def main():
         print(json.dumps({"calibrate_copy_bytes_read": n * 8, "calibrate_copy_bytes_written": n * 8, "launches": 3}))
         return
 
+    progress(f"headline: {args.workload}, {args.mode} mode, block_mfma={args.block_mfma}")
     r = run_workload(args.workload, args.steps, args.warmup, mode=args.mode, block_mfma=args.block_mfma)
     p = r["problem"]
+    progress(f"headline: {r['sec'] * 1e3:.3f} ms per step")
     also = []
     for name in [a for a in args.also.split(",") if a and a != args.workload]:
         also.append(summary(name, run_workload(name, max(3, args.steps // 2), max(1, args.warmup), mode=args.mode,
                                                block_mfma=args.block_mfma)))
+    if args.mfma_leg and args.mode == "grouped" and args.block_mfma != 1:
+        also.append(summary(args.workload, run_workload(args.workload, max(3, args.steps // 2), max(1, args.warmup),
+                                                        block_mfma=1),
+                            variant="opt-in matrix-core block class (dense FP64 product of padded panels)"))
+    glob = []
+    for name in [a for a in args.global_legs.split(",") if a]:
+        progress(f"global mode: {name}")
+        glob.append(summary(name, run_workload(name, 3, 1, mode="global")))
+    progress("single-workload legs done")
 
     batched = served = None
     if draws:
@@ -584,6 +695,7 @@ def main():
         tuned = autotune_batched(draws, dev, min(len(draws), 128)) if args.autotune else None
         budget = tuned["batch_products"] if tuned else args.batch_budget
         lf = tuned["load_factor"] if tuned else 1 / 1.3
+        progress("batched workload: per-call and batched legs")
         batched = run_batched(draws, dev, max(1, args.steps // 5), 1, budget, lf)
         batched["autotune"] = tuned
         release_cached_memory()
@@ -591,20 +703,27 @@ def main():
                                "1-2 contracted pairs, FP64 U[-1,1)")
         if args.serve > 0:
             budget = int(args.serve_budget_gb * (1 << 30))
-            served = {"workload": f"Poisson arrivals, each request one of the {len(draws)} batched draws "
-                                  "picked uniformly, inputs resident in HBM"}
+            served = {"workload": f"Poisson arrivals at {args.serve_rate:.0f}/s for {args.serve:.0f} s, each request "
+                                  f"one of the {len(draws)} batched draws picked uniformly, inputs resident in HBM; "
+                                  "both legs serve the same arrival trace to completion"}
             served["batched"] = run_served(draws, dev, args.serve, args.serve_rate, budget,
-                                           args.serve_batch_products, 4096, BASE_SEED + 5, lf)
-            # the same arrivals served one request per launch
-            served["per_call"] = run_served(draws, dev, min(args.serve, 1.0), args.serve_rate, budget,
-                                            args.serve_batch_products, 1, BASE_SEED + 5, lf)
+                                           args.serve_batch_products, 4096, BASE_SEED + 5, lf, label="served batched")
+            release_cached_memory()
+            served["per_call"] = run_served(draws, dev, args.serve, args.serve_rate, budget,
+                                            args.serve_batch_products, 1, BASE_SEED + 5, lf,
+                                            label="served per call")
 
-    sweep = run_sweep(2) if args.sweep else None
+    sweep = None
+    if args.sweep:
+        progress("paper-set sweep")
+        sweep = run_sweep(2)
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = time_oracle(p, r["products"])
+        progress("cpu baseline: the oracle on the host")
+        cpu = time_oracle(p)
 
+    # The driver keeps the tail of this line: the extras that matter most come last.
     line = {
         "metric": METRIC,
         "value": r["products"] / r["sec"],
@@ -620,21 +739,18 @@ def main():
         "data": "synthetic",
         "config": {"workload": DESCRIPTIONS[args.workload], "nnz_x": p.X.nnz, "nnz_y": p.Y.nnz,
                    "products": r["products"], "out_nnz": r["nnz_z"], "step": "plan + execute",
-                   "parallelism": "single GPU"},
-        "output_nnz_per_s": r["nnz_z"] / r["sec"],
-        "roofline": roofline_of(r),
-        "survey_byte_model": {"bytes_per_step": survey_byte_model(p, r["products"], r["nnz_z"]),
-                              "achieved_GBps": round(survey_byte_model(p, r["products"], r["nnz_z"]) / r["sec"] / 1e9,
-                                                     1),
-                              "frac_of_8TBps": round(survey_byte_model(p, r["products"], r["nnz_z"]) / r["sec"]
-                                                     / (HBM_PEAK_GBS * 1e9), 4)},
-        "cpu_baseline": cpu,
-        "stage_ms": {k: round(v, 4) for k, v in r["stage_ms"].items() if not k.startswith("batch_")},
-        "plan": r["info"],
-        "also": also,
-        "batched": batched,
-        "served": served,
+                   "mode": args.mode, "block_mfma": args.block_mfma, "parallelism": "single GPU"},
         "paper_set_sweep": sweep,
+        "also": also,
+        "batched": compact_batched(batched),
+        "served": served,
+        "global_mode": glob,
+        "plan": {k: v for k, v in r["info"].items() if k not in ("mode",)},
+        "stage_ms": {k: round(v, 4) for k, v in r["stage_ms"].items() if v >= 0.01 and not k.startswith("batch_")},
+        "output_nnz_per_s": r["nnz_z"] / r["sec"],
+        "cpu_baseline": cpu,
+        "survey_roofline": survey_roofline(p, r["products"], r["nnz_z"], r["sec"]),
+        "roofline": roofline_of(r),
     }
     print(json.dumps(line), flush=True)
 

@@ -27,9 +27,10 @@
  * every product as an output; small groups accumulate in a wave's LDS hash,
  * large ones in a workgroup's dense LDS array or LDS hash; groups too large
  * for LDS go to a device-memory hash (the footnote to section 4.4), compacted
- * by count, prefix sum and fill (writeback, section 2.5).  When X and Y are
- * dense enough, the large groups with a dense Y free key may instead run as
- * a dense FP64 product on the matrix cores (sptc_options.block_mfma).  The
+ * by count, prefix sum and fill (writeback, section 2.5).  On request
+ * (sptc_options.block_mfma, off by default), the large groups with a dense Y
+ * free key may instead run as a dense FP64 product on the matrix cores when
+ * X and Y are dense enough; the default path has no dense product.  The
  * GLOBAL mode sends every product to that device hash.
  *
  * Conventions
@@ -151,11 +152,11 @@ typedef struct sptc_options {
                                 the caller owns the events and keeps the array alive */
   int32_t mode;              /* sptc_mode; default SPTC_MODE_GROUPED */
   int32_t block_mfma;        /* grouped mode, dense Y free key, sptc_plan only: run the block class
-                                as a dense product on the FP64 matrix cores.  -1 (default): when
-                                eligible and rows x columns x runs is at most 24x the class's
-                                products; 0: never; 1: whenever eligible.  Eligible: every X and Y
-                                value finite, and dense X and Y panels of at most 8 GiB.
-                                sptc_info.block_mfma reports the choice. */
+                                as a dense product on the FP64 matrix cores instead of the LDS walk.
+                                0 (default): never; 1: whenever eligible; -1: when eligible and
+                                rows x columns x runs is at most 24x the class's products.
+                                Eligible: every X and Y value finite, and dense X and Y panels of at
+                                most 8 GiB.  sptc_info.block_mfma reports the choice. */
 } sptc_options;
 
 /* Sizes fixed by sptc_plan. */
@@ -183,27 +184,39 @@ typedef struct sptc_plan_s* sptc_plan_t;
 /* Fill *opt with the defaults. */
 SPTC_API void sptc_default_options(sptc_options* opt);
 
-/* Build a plan: group Y by contracting key, probe every X nonzero, count the
- * products and size the output hash.  Enqueues work on `stream` and
- * synchronises it once, to read the product count.  opt and alloc may be
- * NULL.  On success *plan owns all workspace (released by sptc_free).  On
- * failure *plan is NULL and nothing stays allocated. */
+/* Build a plan (sections 4.1-4.3): group Y by its contracting key (the
+ * counting sort of section 4.1.1 into the array form of Y with its probing
+ * table, section 4.2); in the grouped mode, group X by its free key the same
+ * way, look up every X entry's Y run, and take each X group's product count
+ * (the bound of section 4.3), which sums to P and picks the group's
+ * accumulation class; size the output hash (in the global mode, for all P
+ * products).  Enqueues work on `stream` and waits for it to read counts
+ * back: once in the global mode, and in the grouped mode once, or three
+ * times when some X group is too large for LDS (its entries and its
+ * products are counted before the device-memory hash is sized).  opt and
+ * alloc may be NULL.  On success *plan owns all workspace (released by
+ * sptc_free).  On failure *plan is NULL and nothing stays allocated. */
 SPTC_API sptc_status sptc_plan(sptc_plan_t* plan, const sptc_coo* X, const sptc_coo* Y, int32_t ncontract,
                       const int32_t* cx, const int32_t* cy, const sptc_options* opt,
                       const sptc_allocator* alloc, void* stream);
 
-/* Copy the plan's sizes into *info (host).  Does not synchronise. */
+/* Copy the plan's sizes into *info (host): P, the number of matching (x, y)
+ * pairs, which is the sum over X groups of the bound of section 4.3;
+ * out_nnz_bound = min(P, product of out_dims), enough out_cap for
+ * sptc_execute; class counts and workspace.  Does not synchronise. */
 SPTC_API sptc_status sptc_plan_info(sptc_plan_t plan, sptc_info* info);
 
-/* Expand all products, accumulate them in the output hash and write Z as
- * COO: out_idx device int32 [out_order][out_cap] (mode-major with row stride
- * out_cap; may be NULL when out_order is 0), out_val device double [out_cap],
- * out_nnz a device or pinned-host int64 that receives nnz(Z), or the negated
- * status when a kernel recorded an error (including nnz(Z) > out_cap, in
- * which case only the first out_cap entries are written).  Never
- * synchronises, allocates or copies to the host, so it can be captured into a
- * HIP graph; the plan may be executed any number of times.  Executions of one
- * plan must not overlap. */
+/* Contraction, accumulation and writeback (sections 2.4 and 2.5, with the
+ * per-group accumulation tables of section 4.3): expand every product,
+ * accumulate equal output coordinates (in the X group's LDS table, or in the
+ * output hash) and write Z as COO: out_idx device int32 [out_order][out_cap]
+ * (mode-major with row stride out_cap; may be NULL when out_order is 0),
+ * out_val device double [out_cap], out_nnz a device or pinned-host int64
+ * that receives nnz(Z), or the negated status when a kernel recorded an
+ * error (including nnz(Z) > out_cap, in which case only the first out_cap
+ * entries are written).  Never synchronises, allocates or copies to the
+ * host, so it can be captured into a HIP graph; the plan may be executed
+ * any number of times.  Executions of one plan must not overlap. */
 SPTC_API sptc_status sptc_execute(sptc_plan_t plan, int32_t* out_idx, double* out_val, int64_t out_cap,
                          int64_t* out_nnz, void* stream);
 

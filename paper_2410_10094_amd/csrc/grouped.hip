@@ -40,10 +40,15 @@ constexpr unsigned long long kWaveMaxProducts = 16384;  // beyond this a group g
 
 // X table -> dense group records, in table order (so group runs are in
 // increasing storage order).  Scans count << 32 | occupied in one pass.
+// Groups and their entries both fit `cap` (the number of X entries) unless
+// the table holds stale or corrupt counts: then the op records an internal
+// error and writes nothing out of bounds.
 struct XTableScanOp {
   YSlot* tab;
   GroupRec* groups;
   bool run_end;  // start = end of run (placement takes and decrements), else its beginning
+  unsigned long long cap;
+  DevStatus* st;
   __device__ unsigned long long get(int64_t i) const {
     const YSlot s = tab[i];
     return s.key != kEmpty ? (((unsigned long long)s.count << 32) | 1ull) : 0ull;
@@ -51,11 +56,16 @@ struct XTableScanOp {
   __device__ void put(int64_t i, unsigned long long excl, unsigned long long v) const {
     if (!v) return;
     const unsigned count = (unsigned)(v >> 32);
+    const unsigned long long gi = excl & 0xffffffffull, start = excl >> 32;
+    if (gi >= cap || start + count > cap) {
+      record_error(st, kErrInternal);
+      return;
+    }
     GroupRec g;
     g.phi = tab[i].key;
-    g.start = (unsigned)(excl >> 32);
+    g.start = (unsigned)start;
     g.count = count;
-    groups[(unsigned)(excl & 0xffffffffull)] = g;
+    groups[gi] = g;
     tab[i].start = run_end ? g.start + count : g.start;
   }
 };
@@ -125,6 +135,8 @@ __global__ __launch_bounds__(256) void k_key_count32(const int32_t* __restrict__
 struct XTable32ScanOp {
   unsigned long long* tab;
   GroupRec* groups;
+  unsigned long long cap;  // as in XTableScanOp
+  DevStatus* st;
   __device__ unsigned long long get(int64_t i) const {
     const unsigned long long w = tab[i];
     return w != kEmpty ? ((w & kLow32) << 32 | 1ull) : 0ull;
@@ -132,11 +144,16 @@ struct XTable32ScanOp {
   __device__ void put(int64_t i, unsigned long long excl, unsigned long long v) const {
     if (!v) return;
     const unsigned long long key = tab[i] >> 32;
+    const unsigned long long gi = excl & kLow32, start = excl >> 32;
+    if (gi >= cap || start + (v >> 32) > cap) {
+      record_error(st, kErrInternal);
+      return;
+    }
     GroupRec g;
     g.phi = key;
-    g.start = (unsigned)(excl >> 32);
+    g.start = (unsigned)start;
     g.count = (unsigned)(v >> 32);
-    groups[(unsigned)(excl & kLow32)] = g;
+    groups[gi] = g;
     tab[i] = key << 32 | (unsigned long long)(g.start + g.count) | (g.count == 1 ? kSingle : 0ull);
   }
 };
@@ -1322,9 +1339,10 @@ __global__ void k_x_groups(const GroupRec* __restrict__ groups, int64_t ng, cons
 // Launchers
 // ---------------------------------------------------------------------------
 
-hipError_t launch_scan_x_table(YSlot* tab, int64_t nslots, GroupRec* groups, bool run_end, void* tile_sums,
-                               DevStatus* st, hipStream_t stream) {
-  return device_scan(XTableScanOp{tab, groups, run_end}, nslots, tile_sums, FinXGroups{st}, stream);
+hipError_t launch_scan_x_table(YSlot* tab, int64_t nslots, GroupRec* groups, int64_t cap, bool run_end,
+                               void* tile_sums, DevStatus* st, hipStream_t stream) {
+  return device_scan(XTableScanOp{tab, groups, run_end, (unsigned long long)cap, st}, nslots, tile_sums,
+                     FinXGroups{st}, stream);
 }
 
 hipError_t launch_x_table32(const int32_t* xidx, const double* xval, int64_t nnz, KeyPack kf, KeyPack kc, Bounds b,
@@ -1339,7 +1357,8 @@ hipError_t launch_x_table32(const int32_t* xidx, const double* xval, int64_t nnz
   k_key_count32<<<grid_for(nnz, 256, num_cus), 256, 0, stream>>>(xidx, nnz, kf, xtab, xg, seed, max_probe_x, st);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  e = device_scan(XTable32ScanOp{xtab, groups}, nslots, tile_sums, FinXGroups{st}, stream);
+  e = device_scan(XTable32ScanOp{xtab, groups, (unsigned long long)nnz, st}, nslots, tile_sums, FinXGroups{st},
+                  stream);
   if (e != hipSuccess) return e;
   k_x_scatter32<<<grid_for(nnz, 256, num_cus), 256, 0, stream>>>(xidx, xval, nnz, kf, kc, b, xtab, xg, max_probe_x,
                                                                   ytab, yg, max_probe_y, seed, xr, st);

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstddef>
 #include <cmath>
 #include <cstdarg>
@@ -12,6 +13,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/sptc.h"
@@ -22,6 +24,9 @@ using namespace sptc;
 namespace {
 
 thread_local std::string g_last_error;
+// The last failed plan on this thread gave up on a stalled stream (its
+// callers then release memory in stream order without waiting).
+thread_local bool g_stalled = false;
 
 sptc_status fail(sptc_status s, const char* fmt, ...) {
   char buf[512];
@@ -304,6 +309,8 @@ struct sptc_plan_s : Workspace {
   uint16_t* cellof = nullptr;
   MfmaPlan mplan{};
   bool in_batch = false;      // the packed plan of a batch
+  bool stalled = false;       // a read-back timed out: the stream still holds the plan's work
+  bool pageable_readback = false;  // read counts back through pageable memory (no pinned buffer)
   bool block_surveyed = false;  // the block survey ran (dense Y free key, one contraction)
   int32_t block_nonfinite = 0;  // an X or Y value is not finite (the matrix cores need finite values)
   int64_t block_products = 0;   // survey: products of the block class
@@ -470,9 +477,15 @@ DevStatus* pinned_status(int dev) {
 
 // The plan's counts: copied into pinned memory and waited for by polling the
 // stream (the plan needs them within microseconds of the last kernel; a
-// blocking wait would add its wake-up latency to every plan).
+// blocking wait would add its wake-up latency to every plan).  The first
+// polls spin; later ones yield the core between queries, and after
+// kReadbackDeadline the plan gives up with SPTC_ERR_HIP (the work is still
+// queued: the plan's memory then goes back in stream order, without a wait).
+constexpr auto kReadbackDeadline = std::chrono::seconds(60);
+constexpr unsigned kReadbackSpins = 1024;
+
 sptc_status read_status(sptc_plan_s* P, DevStatus* host) {
-  DevStatus* pin = pinned_status(P->device);
+  DevStatus* pin = P->pageable_readback ? nullptr : pinned_status(P->device);
   if (!pin) {
     HIP_TRY(hipMemcpyAsync(host, P->st, sizeof *host, hipMemcpyDeviceToHost, P->stream));
     HIP_TRY(hipStreamSynchronize(P->stream));
@@ -480,7 +493,15 @@ sptc_status read_status(sptc_plan_s* P, DevStatus* host) {
   }
   HIP_TRY(hipMemcpyAsync(pin, P->st, sizeof *pin, hipMemcpyDeviceToHost, P->stream));
   hipError_t e;
-  while ((e = hipStreamQuery(P->stream)) == hipErrorNotReady) {
+  const auto t0 = std::chrono::steady_clock::now();
+  for (unsigned polls = 0; (e = hipStreamQuery(P->stream)) == hipErrorNotReady; ++polls) {
+    if (polls < kReadbackSpins) continue;
+    std::this_thread::yield();
+    if ((polls & 255) == 0 && std::chrono::steady_clock::now() - t0 > kReadbackDeadline) {
+      P->stalled = true;
+      return fail(SPTC_ERR_HIP, "plan read-back: the stream did not finish within %lld s",
+                  (long long)std::chrono::duration_cast<std::chrono::seconds>(kReadbackDeadline).count());
+    }
   }
   if (e != hipSuccess) return hip_fail(e, "hipStreamQuery");
   *host = *pin;
@@ -679,7 +700,7 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
     else
       HIP_TRY(launch_key_count(X->idx, P->nx, P->x_f, P->xtab, P->xgeom, seed, P->max_probe_x, P->st, nullptr,
                                P->num_cus, s));
-    HIP_TRY(launch_scan_x_table(P->xtab, P->xtab_slots, P->groups, !P->x_agg, P->tile_sums, P->st, s));
+    HIP_TRY(launch_scan_x_table(P->xtab, P->xtab_slots, P->groups, P->nx, !P->x_agg, P->tile_sums, P->st, s));
     if (P->x_agg)
       HIP_TRY(launch_x_scatter_agg(X->idx, X->val, P->nx, P->x_f, P->x_c, P->xb, P->xtab, (unsigned)P->xtab_slots,
                                    P->xhist, P->ytab, P->ygeom, P->max_probe_y, seed, P->xr, P->st, s));
@@ -890,7 +911,7 @@ sptc_status check_key_widths(const Layout& L, int32_t mode) {
 // key tables are cut into the batch's per-contraction regions.
 sptc_status plan_create(sptc_plan_t* plan, const sptc_coo* X, const sptc_coo* Y, int32_t ncontract, const int32_t* cx,
                         const int32_t* cy, const sptc_options* opt, const sptc_allocator* alloc, void* stream,
-                        const BatchRegions* br) {
+                        const BatchRegions* br, bool pageable_readback = false) {
   if (!plan) return fail(SPTC_ERR_INVALID_ARG, "plan is NULL");
   *plan = nullptr;
   sptc_status st;
@@ -913,6 +934,7 @@ sptc_status plan_create(sptc_plan_t* plan, const sptc_coo* X, const sptc_coo* Y,
   if (!P) return fail(SPTC_ERR_OUT_OF_MEMORY, "host allocation failed");
   P->opt = o;
   P->in_batch = br != nullptr;
+  P->pageable_readback = pageable_readback;
   P->stream = static_cast<hipStream_t>(stream);
   if (alloc) {
     P->has_alloc = true;
@@ -963,7 +985,8 @@ sptc_status plan_create(sptc_plan_t* plan, const sptc_coo* X, const sptc_coo* Y,
   st = plan_body(P, X, Y, cx, cy, br);
   if (st != SPTC_OK) {
     std::string msg = g_last_error;
-    (void)hipStreamSynchronize(P->stream);
+    g_stalled = P->stalled;
+    if (!P->stalled) (void)hipStreamSynchronize(P->stream);
     P->release_all();
     delete P;
     g_last_error = msg;
@@ -1249,7 +1272,7 @@ void sptc_default_options(sptc_options* opt) {
   opt->out_table_slots = 0;
   opt->stage_events = nullptr;
   opt->mode = SPTC_MODE_GROUPED;
-  opt->block_mfma = -1;
+  opt->block_mfma = 0;
 }
 
 sptc_status sptc_plan(sptc_plan_t* plan, const sptc_coo* X, const sptc_coo* Y, int32_t ncontract, const int32_t* cx,
@@ -1414,10 +1437,11 @@ sptc_status sptc_batch_plan(sptc_batch_t* batch, int32_t count, const sptc_coo* 
     B->has_alloc = true;
     B->alloc = *alloc;
   }
+  g_stalled = false;
   st = batch_body(B, X, Y, o);
   if (st != SPTC_OK) {
     std::string msg = g_last_error;
-    (void)hipStreamSynchronize(B->stream);
+    if (!g_stalled) (void)hipStreamSynchronize(B->stream);
     if (B->inner) sptc_free(B->inner);
     B->release_all();
     delete B;

@@ -264,7 +264,7 @@ hipError_t launch_compact_grouped(const ZSlot* tab, int64_t nslots, const GroupR
 
 // X table (keyed by X free key) -> dense group records; the table's start
 // field becomes each group's end (run_end) or start offset for the scatter.
-hipError_t launch_scan_x_table(YSlot* tab, int64_t nslots, GroupRec* groups, bool run_end, void* tile_sums,
+hipError_t launch_scan_x_table(YSlot* tab, int64_t nslots, GroupRec* groups, int64_t cap, bool run_end, void* tile_sums,
                                DevStatus* st, hipStream_t stream);
 
 // X scatter for a direct-addressed X table of nslots <= 2^kAggBits slots,

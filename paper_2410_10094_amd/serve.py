@@ -288,6 +288,7 @@ class Server:
         self.peak_used = 0
         self.batches = 0
         self.waits_for_memory = 0
+        self.deferred_requests = 0  # members of plans declined for lack of room, each time
 
     def _select(self, queue: Deque[Request]) -> List[int]:
         """Positions in the queue of the next batch: the head request's shape
@@ -313,9 +314,13 @@ class Server:
         queue.extend(rest)
         return members
 
-    def run(self, requests: Sequence[Request]) -> List[Request]:
-        """Serves requests (sorted by arrival) to completion; returns them."""
+    def run(self, requests: Sequence[Request], progress: Optional[Callable[[str], None]] = None,
+            progress_every: float = 10.0) -> List[Request]:
+        """Serves requests (sorted by arrival) to completion; returns them.
+        progress, if given, receives a status line every progress_every
+        seconds."""
         be = self.backend
+        next_report = progress_every
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
         queue: Deque[Request] = collections.deque()
         inflight: List[_Batch] = []
@@ -325,6 +330,10 @@ class Server:
         t0 = be.start()
         while pending or queue or inflight or staged:
             now = self.clock() - t0
+            if progress and now >= next_report:
+                progress(f"{now:.0f} s: {len(done)} served, {len(queue)} queued, {len(pending)} yet to arrive, "
+                         f"{self.batches} batches")
+                next_report += progress_every
             while pending and pending[0].arrival <= now:
                 queue.append(pending.popleft())
             progressed = False
@@ -354,6 +363,7 @@ class Server:
                         queue = collections.deque(sorted(queue, key=lambda r: (r.arrival, r.rid)))
                         plan_blocked = True
                         self.waits_for_memory += 1
+                        self.deferred_requests += len(members)
                     else:
                         handle, need = planned
                         if need > self.budget:

@@ -37,6 +37,7 @@ def test_default_options():
     o = B.default_options()
     assert abs(o.load_factor - 1 / 1.3) < 1e-15
     assert o.validate == 1 and o.max_probe == 0 and o.out_table_slots == 0
+    assert o.block_mfma == 0  # the matrix-core block class is opt-in
 
 
 def _plan(X, Y, cx, cy, opt=None):

@@ -63,8 +63,15 @@ def test_matrix_core_block_class_matches_oracle(p):
 
 def test_auto_takes_the_matrix_cores_when_dense():
     p = _dense_random(34, 1024, 256, 1024, 120_000, 120_000, name="dense-auto")
-    info, gidx, gval = run_gpu(p)  # block_mfma = -1: the cost rule decides
+    info, gidx, gval = run_gpu(p, options=_opts(-1))  # the cost rule decides
     assert info["classes"]["block"] > 500 and info["block_mfma"], info
+    assert_parity(p, gidx, gval)
+
+
+def test_default_is_the_sparse_walk():
+    p = _dense_random(36, 1024, 256, 1024, 120_000, 120_000, name="dense-default")
+    info, gidx, gval = run_gpu(p)  # default options: the matrix cores are opt-in
+    assert info["classes"]["block"] > 500 and not info["block_mfma"], info
     assert_parity(p, gidx, gval)
 
 

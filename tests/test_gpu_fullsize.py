@@ -1,12 +1,16 @@
-"""Parity at the full workload sizes, with the default launch configuration
-the benchmark times.
+"""Parity at the full workload sizes, in the launch configurations the
+benchmark times.
 
 * block-sparse 48^4 (literal parameters): complete element-wise parity.
-* block-sparse 48^4 at ~1.5M nnz and the imbalanced 1e7 x 1e6 workload:
-  outputs sampled by the oracle and evaluated one by one, plus properties
-  that hold at any size: P equals the oracle's pair count, coordinates are
-  distinct and inside the output shape, the sum of all outputs equals
-  sum_k (sum X_k)(sum Y_k), and nnz is bounded by P.
+* block-sparse 48^4 at ~1.5M nnz: complete element-wise parity of all
+  5,308,416 outputs against the oracle (16 threads), for the walk (the
+  default), the matrix-core block class and the global output hash.
+* imbalanced 1e7 x 1e6: nnz equal to the oracle's count of the output
+  coordinate set; outputs sampled by the oracle and evaluated one by one;
+  properties that hold at any size: P equals the oracle's pair count,
+  coordinates are distinct and inside the output shape, the sum of all
+  outputs equals sum_k (sum X_k)(sum Y_k), nnz is bounded by P.  Both
+  accumulation modes.
 """
 import math
 
@@ -16,7 +20,7 @@ import pytest
 import oracle
 from paper_2410_10094_amd import workloads as W
 from tests import helpers as H
-from tests.gpu_common import assert_parity, log, to_device
+from tests.gpu_common import MODES, assert_parity, log, to_device
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -71,16 +75,57 @@ def _check_output(p, idx, val, P, bound, dims, nsamples, seed=20241010):
     H.assert_values_close(got, ref_val, ref_abs, ref_terms)
 
 
-def _check_large(p, nsamples=3000):
+ORACLE_THREADS = 16
+
+
+def _run(p, mode="grouped", block_mfma=0):
     import paper_2410_10094_amd as sptc
     X, Y = to_device(p)
-    log(f"[full] {p.name}: planning")
-    with sptc.plan(X, Y, p.cx, p.cy) as pl:
+    opt = sptc.default_options(mode=MODES[mode], block_mfma=block_mfma)
+    log(f"[full] {p.name} {mode} block_mfma={block_mfma}: planning")
+    with sptc.plan(X, Y, p.cx, p.cy, options=opt) as pl:
         idx, val = pl.execute()
-        P, bound, dims = pl.products, pl.out_nnz_bound, pl.out_dims
-    log(f"[full] {p.name}: P={P} nnz={val.shape[0]}")
-    _check_output(p, idx, val, P, bound, dims, nsamples)
-    log(f"[full] {p.name}: ok")
+        info = dict(products=pl.products, bound=pl.out_nnz_bound, dims=pl.out_dims, block_mfma=pl.block_mfma)
+    log(f"[full] {p.name}: P={info['products']} nnz={val.shape[0]}")
+    return info, idx, val
+
+
+@pytest.fixture(scope="module")
+def c2_1p5m():
+    p = W.block_sparse(p_block=0.565)
+    log(f"[full] {p.name} nnz {p.X.nnz}x{p.Y.nnz}: oracle on {ORACLE_THREADS} threads")
+    ref = oracle.contract(p.X, p.Y, p.cx, p.cy, nthreads=ORACLE_THREADS)
+    log(f"[full] {p.name}: oracle nnz {ref.nnz}, P {int(ref.terms.sum())}")
+    return p, ref
+
+
+@pytest.mark.parametrize("mode,block_mfma", [("grouped", 0), ("grouped", 1), ("global", 0)])
+def test_block_sparse_1p5m_full_parity(c2_1p5m, mode, block_mfma):
+    p, ref = c2_1p5m
+    info, idx, val = _run(p, mode, block_mfma)
+    if mode == "grouped":
+        assert info["block_mfma"] == block_mfma
+    assert info["products"] == int(ref.terms.sum())
+    assert_parity(p, idx.cpu().numpy(), val.cpu().numpy(), ref)
+    log(f"[full] {p.name} {mode} block_mfma={block_mfma}: all {ref.nnz} outputs match")
+
+
+@pytest.fixture(scope="module")
+def c3():
+    p = W.imbalanced()
+    log(f"[full] {p.name} nnz {p.X.nnz}x{p.Y.nnz}: oracle output count on {ORACLE_THREADS} threads")
+    n = oracle.count_outputs(p.X, p.Y, p.cx, p.cy, nthreads=ORACLE_THREADS)
+    log(f"[full] {p.name}: oracle nnz {n}")
+    return p, n
+
+
+@pytest.mark.parametrize("mode", ["grouped", "global"])
+def test_imbalanced_full_size(c3, mode):
+    p, n = c3
+    info, idx, val = _run(p, mode)
+    assert val.shape[0] == n, f"nnz {val.shape[0]} != oracle {n}"
+    _check_output(p, idx, val, info["products"], info["bound"], info["dims"], 3000)
+    log(f"[full] {p.name} {mode}: ok")
 
 
 def test_block_sparse_full_parity():
@@ -91,14 +136,6 @@ def test_block_sparse_full_parity():
     ref = oracle.contract(p.X, p.Y, p.cx, p.cy, nthreads=16)
     assert info["products"] == int(ref.terms.sum())
     assert_parity(p, gidx, gval, ref)
-
-
-def test_block_sparse_1p5m_sampled():
-    _check_large(W.block_sparse(p_block=0.565))
-
-
-def test_imbalanced_full_size_sampled():
-    _check_large(W.imbalanced())
 
 
 def test_batched_workload_full_size_draws():
