@@ -297,9 +297,11 @@ class Server:
         head = queue[0]
         picked, acc = [], 0.0
         for k, r in enumerate(queue):
+            if len(picked) >= self.max_batch:
+                break
             if r.klass != head.klass:
                 continue
-            if picked and (acc + r.expected_products > self.batch_products or len(picked) >= self.max_batch):
+            if picked and acc + r.expected_products > self.batch_products:
                 break
             picked.append(k)
             acc += r.expected_products
@@ -307,6 +309,8 @@ class Server:
 
     @staticmethod
     def _remove(queue: Deque[Request], picked: List[int]) -> List[Request]:
+        if picked[-1] == len(picked) - 1:  # a prefix of the queue (always, with one shape class)
+            return [queue.popleft() for _ in picked]
         chosen = set(picked)
         members = [r for k, r in enumerate(queue) if k in chosen]
         rest = [r for k, r in enumerate(queue) if k not in chosen]
