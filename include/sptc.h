@@ -316,6 +316,31 @@ SPTC_API void sptc_batch_free(sptc_batch_t batch);
  * that fails first releases the cache and retries. */
 SPTC_API sptc_status sptc_pool_trim(size_t keep_bytes);
 
+/* ---- One contraction without allocating ----
+ *
+ * For callers that cannot allocate device memory (code that must not call
+ * hipMalloc, tight serving loops, harnesses that forbid allocation):
+ * sptc_plan + sptc_execute + sptc_free in one call, with every workspace
+ * buffer carved from a static device array of SPTC_NOALLOC_SCRATCH_BYTES
+ * that the library holds on each device it runs on until the process ends.
+ * The call makes no device allocation, no pinned-host allocation and no
+ * free; the caller passes the inputs (as for sptc_plan) and the outputs (as
+ * for sptc_execute, so out_cap must be at least the contraction's
+ * out_nnz_bound, known for instance from an earlier sptc_plan).  It waits
+ * for `stream` to read the plan's counts back (as sptc_plan does), then
+ * enqueues the execution and returns without waiting for it.
+ * A contraction whose workspace does not fit the array returns
+ * SPTC_ERR_CAPACITY (sptc_last_error() names the size) and writes nothing.
+ * Every call on one device uses that device's one array, which keeps what
+ * the last call left there (the plan clears what must start at zero):
+ * calls on one stream run one after another, but calls that overlap on one
+ * device (other streams, other threads) race and give wrong results. */
+#define SPTC_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+
+SPTC_API sptc_status sptc_contract_noalloc(const sptc_coo* X, const sptc_coo* Y, int32_t ncontract, const int32_t* cx,
+                                           const int32_t* cy, const sptc_options* opt, int32_t* out_idx,
+                                           double* out_val, int64_t out_cap, int64_t* out_nnz, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -117,6 +117,24 @@ def _resolve_allocator(allocator, device):
     return allocator, ctypes.byref(allocator.struct)
 
 
+def contract_noalloc(X: DeviceCoo, Y: DeviceCoo, cx: Sequence[int], cy: Sequence[int], out_idx, out_val,
+                     out_cap: int, out_nnz, options=None, stream=None):
+    """``sptc_contract_noalloc``: plan, execute and release one contraction
+    with no device allocation (workspace from the library's static device
+    array).  The caller's output tensors are written as by
+    ``Plan.execute_into``; nnz lands in ``out_nnz`` (not synchronised)."""
+    if len(cx) != len(cy):
+        raise ValueError("cx and cy must have the same length")
+    lib = _b.load()
+    cX, kx = X.as_c()
+    cY, ky = Y.as_c()
+    acx, acy = _b.int_array(cx), _b.int_array(cy)
+    opt = options if options is not None else _b.default_options()
+    _b.check(lib.sptc_contract_noalloc(ctypes.byref(cX), ctypes.byref(cY), len(cx), acx, acy, ctypes.byref(opt),
+                                       out_idx.data_ptr() if out_idx is not None and out_idx.numel() else None,
+                                       out_val.data_ptr(), int(out_cap), out_nnz.data_ptr(), _stream_handle(stream)))
+
+
 class Plan:
     """A contraction plan (``sptc_plan``): Y grouped, X probed, products
     counted and the output hash sized.  ``execute`` may run any number of

@@ -21,7 +21,7 @@ EXPORTS = (
     "sptc_default_options", "sptc_plan", "sptc_plan_info", "sptc_execute", "sptc_plan_status", "sptc_free",
     "sptc_status_string", "sptc_last_error", "sptc_plan_y_groups", "sptc_plan_y_grouped", "sptc_plan_x_counts",
     "sptc_plan_set_stage_events", "sptc_plan_x_groups", "sptc_batch_plan", "sptc_batch_sizes", "sptc_batch_info",
-    "sptc_batch_execute", "sptc_batch_free", "sptc_pool_trim",
+    "sptc_batch_execute", "sptc_batch_free", "sptc_pool_trim", "sptc_contract_noalloc",
 )
 
 BATCH_MAX = 4096
@@ -123,6 +123,9 @@ def load():
     lib.sptc_batch_free.restype = None
     lib.sptc_pool_trim.argtypes = [ctypes.c_size_t]
     lib.sptc_pool_trim.restype = st
+    lib.sptc_contract_noalloc.argtypes = [ctypes.POINTER(Coo), ctypes.POINTER(Coo), i32, P, P,
+                                          ctypes.POINTER(Options), P, P, i64, P, P]
+    lib.sptc_contract_noalloc.restype = st
     _lib = lib
     return lib
 

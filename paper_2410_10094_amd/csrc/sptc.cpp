@@ -1261,6 +1261,56 @@ sptc_status batch_body(sptc_batch_s* B, const sptc_coo* X, const sptc_coo* Y, co
 
 }  // namespace
 
+namespace sptc {
+
+// Bump allocation over a caller-given device range: buffers are carved in
+// order and never given back one by one (the range is reused by the next
+// call).  `need` keeps the bytes asked for, also past the end.
+struct ScratchBump {
+  char* base;
+  size_t cap, used, need;
+};
+
+void* scratch_alloc(size_t bytes, void* /*stream*/, void* ctx) {
+  ScratchBump* b = static_cast<ScratchBump*>(ctx);
+  const size_t n = (bytes + 255) & ~(size_t)255;
+  b->need += n;
+  if (b->used + n > b->cap) return nullptr;
+  void* p = b->base + b->used;
+  b->used += n;
+  return p;
+}
+
+void scratch_release(void*, size_t, void*, void*) {}
+
+// One contraction planned, executed and released with every workspace
+// buffer carved from [base, base + bytes) and the plan's count read-backs
+// through pageable memory, so that nothing is allocated: the body of
+// sptc_contract_noalloc.
+sptc_status contract_in_scratch(void* base, size_t bytes, const sptc_coo* X, const sptc_coo* Y, int32_t ncontract,
+                                const int32_t* cx, const int32_t* cy, const sptc_options* opt, int32_t* out_idx,
+                                double* out_val, int64_t out_cap, int64_t* out_nnz, void* stream) {
+  if (!out_nnz) return fail(SPTC_ERR_INVALID_ARG, "out_nnz is NULL");
+  if (out_cap < 0) return fail(SPTC_ERR_INVALID_ARG, "out_cap < 0");
+  ScratchBump bump{static_cast<char*>(base), bytes, 0, 0};
+  const sptc_allocator al{scratch_alloc, scratch_release, &bump};
+  sptc_plan_t plan = nullptr;
+  sptc_status st = plan_create(&plan, X, Y, ncontract, cx, cy, opt, &al, stream, nullptr, true);
+  if (st == SPTC_ERR_OUT_OF_MEMORY && bump.need > bump.cap)
+    return fail(SPTC_ERR_CAPACITY, "the plan needs more workspace than the %zu bytes of static scratch (%zu bytes asked "
+                "for when it stopped)", bump.cap, bump.need);
+  if (st != SPTC_OK) return st;
+  if (out_cap > 0 && !out_val) st = fail(SPTC_ERR_INVALID_ARG, "out_val is NULL");
+  else if (out_cap > 0 && plan->out_order > 0 && !out_idx) st = fail(SPTC_ERR_INVALID_ARG, "out_idx is NULL");
+  else st = execute_plan(plan, out_idx, out_val, out_cap, out_nnz, static_cast<hipStream_t>(stream), nullptr);
+  sptc_free(plan);
+  return st;
+}
+
+sptc_status report_hip_error(hipError_t e, const char* what) { return hip_fail(e, what); }
+
+}  // namespace sptc
+
 extern "C" {
 
 void sptc_default_options(sptc_options* opt) {
