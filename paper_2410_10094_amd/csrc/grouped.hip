@@ -29,9 +29,6 @@ constexpr int kGWaves = kGBlock / 64;
 constexpr int kBBlock = 1024;                           // block-class workgroup
 constexpr unsigned kXcds = 8;                          // MI355X: 8 XCDs, each with its own L2
 constexpr int kBChunk = 1024;
-constexpr int kCoWin = 1024;           // co-accumulation: X entries merged per window
-constexpr int kCoMaxGroups = 4;        // co-accumulation: groups per workgroup, at most
-constexpr size_t kCoLds = 135 * 1024;  // co-accumulation: dynamic LDS for the accumulators (+ ~24 KiB static <= 160 KiB)                           // X entries staged per chunk (product-parallel walk)
 constexpr unsigned long long kWaveMaxProducts = 16384;  // beyond this a group goes to a workgroup
 
 // ---------------------------------------------------------------------------
@@ -541,11 +538,6 @@ __global__ __launch_bounds__(kGBlock) void k_group_wave(GroupArgs a, const uint3
   }
 }
 
-// A dense accumulator cell was reached by some product (see k_group_block).
-__device__ __forceinline__ bool dense_reached(const double* acc, const unsigned char* flag, unsigned s) {
-  return __double_as_longlong(acc[s]) != (long long)0x8000000000000000ull || flag[s] != 0;
-}
-
 // Ascending bitonic sort of a[0, n) in LDS (n a power of two, n <= blockDim.x),
 // one element per thread; every thread of the block must call it.
 __device__ __forceinline__ void bitonic_sort_lds(unsigned long long* a, unsigned n) {
@@ -565,27 +557,20 @@ __device__ __forceinline__ void bitonic_sort_lds(unsigned long long* a, unsigned
   }
 }
 
-// Block class: one 1024-thread workgroup per group, accumulating in a dense
-// LDS array indexed by the Y free key or in an LDS hash of up to kBlockSlots
-// slots.  Dense cells start at -0.0: adding any nonzero product leaves a
-// value other than -0.0 (an exact cancellation rounds to +0.0), so a cell was
-// reached iff its bits changed; only a product that is itself zero (a zero
-// input value, or underflow) sets the cell's flag explicitly.  When the group's X entries average
-// many products, each wave walks whole Y runs (coalesced, no search);
-// otherwise the products are spread over all threads by a search over the
-// staged entry offsets.  Then the group's outputs are counted, reserved with
-// one atomic on the output cursor, and written.
-template <bool DENSE>
-__global__ __launch_bounds__(kBBlock) void k_group_block(GroupArgs a, const uint32_t* __restrict__ blist, int64_t nb,
-                                                         unsigned dense_cells) {
+// Block class with a Y free key too wide for a dense accumulator: one
+// 1024-thread workgroup per group, accumulating in an LDS hash of up to
+// kBlockSlots slots.  When the group's X entries average many products, each
+// wave walks whole Y runs (coalesced, no search); otherwise the products are
+// spread over all threads by a search over the staged entry offsets.  Then
+// the group's outputs are counted, reserved with one atomic on the output
+// cursor, and written.
+__global__ __launch_bounds__(kBBlock) void k_group_block(GroupArgs a, const uint32_t* __restrict__ blist, int64_t nb) {
   extern __shared__ __align__(16) unsigned char s_dyn[];
   __shared__ unsigned long long s_off[kBChunk];
   __shared__ unsigned s_ys[kBChunk];
   __shared__ double s_v[kBChunk];
   __shared__ unsigned long long s_wave[kBBlock / 64 + 1];
   __shared__ unsigned long long s_base;
-  double* acc = reinterpret_cast<double*>(s_dyn);
-  unsigned char* flag = s_dyn + (size_t)dense_cells * 8;
   ZSlot* tab = reinterpret_cast<ZSlot*>(s_dyn);
   const unsigned tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr unsigned kWaves = kBBlock / 64;
@@ -603,29 +588,17 @@ __global__ __launch_bounds__(kBBlock) void k_group_block(GroupArgs a, const uint
     const GroupRec G = a.groups[g];
     const unsigned long long b = a.eoff[G.start + G.count] - a.eoff[G.start];
     const unsigned long long d = b < a.ycells ? b : a.ycells;
-    const unsigned tsize = DENSE ? dense_cells : (table_size_for(d, kBlockSlots) < (unsigned)kBBlock
-                                                      ? (unsigned)kBBlock
-                                                      : table_size_for(d, kBlockSlots));
+    const unsigned tsize = table_size_for(d, kBlockSlots) < (unsigned)kBBlock ? (unsigned)kBBlock
+                                                                                : table_size_for(d, kBlockSlots);
     const unsigned tmask = tsize - 1;
     for (unsigned s = tid; s < tsize; s += kBBlock) {
-      if (DENSE) {
-        acc[s] = -0.0;
-        flag[s] = 0;
-      } else {
-        tab[s].key = kEmpty;
-        tab[s].val = 0.0;
-      }
+      tab[s].key = kEmpty;
+      tab[s].val = 0.0;
     }
     __syncthreads();
 
     auto accumulate = [&](unsigned long long key, double pv) {
-      if (DENSE) {
-        const unsigned cell = (unsigned)key & tmask;
-        atomicAdd(&acc[cell], pv);
-        if (pv == 0.0) flag[cell] = 1;
-      } else if (!lds_accumulate(tab, tmask, key, pv, a.seed)) {
-        record_error(a.st, kErrCapacity);
-      }
+      if (!lds_accumulate(tab, tmask, key, pv, a.seed)) record_error(a.st, kErrCapacity);
     };
 
     if (b >= 32ull * G.count) {
@@ -635,7 +608,7 @@ __global__ __launch_bounds__(kBBlock) void k_group_block(GroupArgs a, const uint
       // and share them through its L2.  Each wave takes kEU entries at a time
       // (kEU independent loads in flight per lane); the waves of a workgroup
       // stay within kWaves * kEU consecutive entries of the sorted order.
-      constexpr unsigned kEU = DENSE ? 8 : 4;
+      constexpr unsigned kEU = 4;
       for (unsigned base = 0; base < G.count; base += kBChunk) {
         const unsigned n = G.count - base < (unsigned)kBChunk ? G.count - base : (unsigned)kBChunk;
         unsigned long long key = ~0ull;
@@ -673,30 +646,14 @@ __global__ __launch_bounds__(kBBlock) void k_group_block(GroupArgs a, const uint
             }
             m = cnt[u] > m ? cnt[u] : m;
           }
-          if (DENSE) {  // compact copy of Y: 10 bytes per product
-            for (unsigned j = lane; j < m; j += 64) {
-              unsigned yk[kEU];
-              double yv[kEU];
+          for (unsigned j = lane; j < m; j += 64) {
+            YEntry ye[kEU];
 #pragma unroll
-              for (unsigned u = 0; u < kEU; ++u)
-                if (j < cnt[u]) {
-                  yk[u] = a.ykey16[ys[u] + j];
-                  yv[u] = a.yval[ys[u] + j];
-                }
+            for (unsigned u = 0; u < kEU; ++u)
+              if (j < cnt[u]) ye[u] = a.yg[ys[u] + j];
 #pragma unroll
-              for (unsigned u = 0; u < kEU; ++u)
-                if (j < cnt[u]) accumulate(yk[u], __dmul_rn(xv[u], yv[u]));
-            }
-          } else {
-            for (unsigned j = lane; j < m; j += 64) {
-              YEntry ye[kEU];
-#pragma unroll
-              for (unsigned u = 0; u < kEU; ++u)
-                if (j < cnt[u]) ye[u] = a.yg[ys[u] + j];
-#pragma unroll
-              for (unsigned u = 0; u < kEU; ++u)
-                if (j < cnt[u]) accumulate(ye[u].phi, __dmul_rn(xv[u], ye[u].v));
-            }
+            for (unsigned u = 0; u < kEU; ++u)
+              if (j < cnt[u]) accumulate(ye[u].phi, __dmul_rn(xv[u], ye[u].v));
           }
         }
         __syncthreads();
@@ -744,8 +701,7 @@ __global__ __launch_bounds__(kBBlock) void k_group_block(GroupArgs a, const uint
 
     // count, reserve, write
     unsigned long long n = 0;
-    for (unsigned s = tid; s < tsize; s += kBBlock)
-      n += DENSE ? (dense_reached(acc, flag, s) ? 1u : 0u) : (tab[s].key != kEmpty ? 1u : 0u);
+    for (unsigned s = tid; s < tsize; s += kBBlock) n += tab[s].key != kEmpty ? 1u : 0u;
     n = block_sum<kBBlock>(n, s_wave);
     if (tid == 0) s_base = atomicAdd(a.bout ? &a.bseg[G.phi >> a.bwx].cursor : &a.st->out_base, n);
     __syncthreads();
@@ -753,19 +709,10 @@ __global__ __launch_bounds__(kBBlock) void k_group_block(GroupArgs a, const uint
     unsigned long long run = 0;
     for (unsigned s0 = 0; s0 < tsize; s0 += kBBlock) {
       const unsigned s = s0 + tid;
-      bool occ;
-      unsigned long long key;
-      double val;
-      if (DENSE) {
-        occ = dense_reached(acc, flag, s);
-        key = s;
-        val = acc[s];
-      } else {
-        const ZSlot z = tab[s];
-        occ = z.key != kEmpty;
-        key = z.key;
-        val = z.val;
-      }
+      const ZSlot z = tab[s];
+      const bool occ = z.key != kEmpty;
+      const unsigned long long key = z.key;
+      const double val = z.val;
       unsigned long long tot;
       const unsigned long long r = block_excl_scan<kBBlock>(occ ? 1ull : 0ull, s_wave, &tot);
       if (occ) {
@@ -778,302 +725,6 @@ __global__ __launch_bounds__(kBBlock) void k_group_block(GroupArgs a, const uint
       run += tot;
     }
     __syncthreads();
-  }
-}
-
-// Ascending bitonic sort of a[0, n) in LDS, n a power of two of at most
-// 4 * blockDim.x; every thread of the block must call it.
-__device__ __forceinline__ void bitonic_sort_lds_n(unsigned long long* a, unsigned n) {
-  for (unsigned k = 2; k <= n; k <<= 1) {
-    for (unsigned j = k >> 1; j > 0; j >>= 1) {
-      for (unsigned i = threadIdx.x; i < n; i += blockDim.x) {
-        const unsigned ixj = i ^ j;
-        if (ixj > i) {
-          const unsigned long long x = a[i], y = a[ixj];
-          if ((x > y) == ((i & k) == 0)) {
-            a[i] = y;
-            a[ixj] = x;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
-}
-
-// Plan time, dense block class: sorts each group's X entries (of at most
-// kCoSortMax) by the start of their Y run, entries without a Y match last,
-// and records how many have one (neff).  Order within a group is free
-// (section 4.1.3); the sorted order lets co-accumulation below merge the
-// entries of several groups by Y run.
-// Two launches share the work: THREADS = 256 sorts the groups of at most
-// kSortSmall entries (small LDS, many workgroups per CU), THREADS = 1024 the
-// larger ones; each skips the other's groups.
-constexpr int kSortSmall = 1024;
-
-template <int THREADS, int MAXN>
-__global__ __launch_bounds__(THREADS) void k_sort_block_entries(const GroupRec* __restrict__ groups,
-                                                                const uint32_t* __restrict__ blist, int64_t nb,
-                                                                XRec* __restrict__ xr, uint32_t* __restrict__ neff) {
-  extern __shared__ __align__(16) unsigned char s_dyn[];
-  unsigned long long* s_key = reinterpret_cast<unsigned long long*>(s_dyn);  // [MAXN]
-  XRec* s_rec = reinterpret_cast<XRec*>(s_dyn + (size_t)MAXN * 8);           // [MAXN]
-  __shared__ unsigned s_n;
-  constexpr bool kSmall = MAXN <= kSortSmall;
-  for (int64_t i = blockIdx.x; i < nb; i += gridDim.x) {
-    const GroupRec G = groups[blist[i]];
-    if (kSmall ? G.count > (unsigned)MAXN : G.count <= (unsigned)kSortSmall) continue;  // the other launch's
-    if (G.count > (unsigned)kCoSortMax) {  // uniform: left unsorted, not co-accumulated
-      if (threadIdx.x == 0) neff[i] = G.count;
-      continue;
-    }
-    unsigned nsort = 2;
-    while (nsort < G.count) nsort <<= 1;
-    if (threadIdx.x == 0) s_n = 0u;
-    __syncthreads();
-    for (unsigned e = threadIdx.x; e < nsort; e += THREADS) {
-      unsigned long long key = ~0ull;
-      if (e < G.count) {
-        const XRec r = xr[G.start + e];
-        s_rec[e] = r;
-        key = ((unsigned long long)(r.ycnt ? r.ystart : 0xffffffffu) << 32) | e;
-        if (r.ycnt) atomicAdd(&s_n, 1u);
-      }
-      s_key[e] = key;
-    }
-    __syncthreads();
-    bitonic_sort_lds_n(s_key, nsort);
-    for (unsigned e = threadIdx.x; e < G.count; e += THREADS)
-      xr[G.start + e] = s_rec[(unsigned)(s_key[e] & 0xffffffffull)];
-    if (threadIdx.x == 0) neff[i] = s_n;
-    __syncthreads();
-  }
-}
-
-// Dense block class with co-accumulation.  A workgroup takes a set of up to
-// `ng_max` neighbouring groups of the list (neighbours share most of their
-// contracting keys, hence their Y runs), each with its own dense LDS
-// accumulator.  Their X entries, sorted by Y run at plan time, are merged in
-// windows of kCoWin entries; each distinct Y run in a window is read once
-// and every entry of the set that matches it takes its products from that
-// one read.  Y traffic, which bounds the one-group walk, drops by the number
-// of groups sharing a run.  Sets holding a group too large to have been
-// sorted fall back to a product-parallel walk per group.  Cells start at
-// -0.0 (see k_group_block); zero products set a bit in the group's bitmap.
-__device__ __forceinline__ bool co_reached(const double* acc, const unsigned* zbits, unsigned s) {
-  return __double_as_longlong(acc[s]) != (long long)0x8000000000000000ull || ((zbits[s >> 5] >> (s & 31)) & 1u);
-}
-
-__global__ __launch_bounds__(kBBlock) void k_group_block_dense(GroupArgs a, const uint32_t* __restrict__ blist,
-                                                               int64_t nb, const uint32_t* __restrict__ neff,
-                                                               unsigned cells, unsigned ng_max) {
-  extern __shared__ __align__(16) unsigned char s_dyn[];
-  __shared__ unsigned long long s_key[kCoWin];
-  __shared__ unsigned s_cnt[kCoWin];
-  __shared__ double s_v[kCoWin];
-  __shared__ unsigned s_unit[kCoWin + 1];
-  __shared__ unsigned long long s_wave[kBBlock / 64 + 1];
-  __shared__ GroupRec s_grp[kCoMaxGroups];
-  __shared__ unsigned s_neff[kCoMaxGroups], s_p[kCoMaxGroups], s_take[kCoMaxGroups], s_bnd[kCoMaxGroups];
-  __shared__ unsigned long long s_base;
-  __shared__ unsigned s_all;
-  double* acc = reinterpret_cast<double*>(s_dyn);                                    // [ng_max][cells]
-  unsigned* zbits = reinterpret_cast<unsigned*>(s_dyn + (size_t)ng_max * cells * 8);  // [ng_max][cells / 32]
-  const unsigned zwords = cells / 32;
-  const unsigned tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  constexpr unsigned kWaves = kBBlock / 64;
-  const unsigned win = kCoWin / ng_max;  // entries per group per window
-  const unsigned cmask = cells - 1;
-
-  auto add = [&](unsigned t, unsigned cell, double pv) {
-    atomicAdd(&acc[(size_t)t * cells + cell], pv);
-    if (pv == 0.0) atomicOr(&zbits[t * zwords + (cell >> 5)], 1u << (cell & 31));
-  };
-
-  const int64_t nsets = (nb + ng_max - 1) / ng_max;
-  const unsigned nxcd = gridDim.x % kXcds == 0 ? kXcds : 1u;  // XCD-aware order, as in k_group_block
-  const unsigned xcd = blockIdx.x % nxcd, per_xcd = gridDim.x / nxcd;
-  const int64_t lo = nsets * xcd / nxcd, hi = nsets * (xcd + 1) / nxcd;
-  for (int64_t set = lo + blockIdx.x / nxcd; set < hi; set += per_xcd) {
-    const int64_t g0 = set * ng_max;
-    const unsigned ng = (unsigned)(nb - g0 < (int64_t)ng_max ? nb - g0 : (int64_t)ng_max);
-    if (tid == 0) s_all = 1u;
-    __syncthreads();
-    if (tid < ng) {
-      const GroupRec G = a.groups[blist[g0 + tid]];
-      s_grp[tid] = G;
-      s_neff[tid] = neff[g0 + tid];
-      s_p[tid] = 0u;
-      s_take[tid] = 0u;
-      if (G.count > (unsigned)kCoSortMax) atomicAnd(&s_all, 0u);
-    }
-    for (unsigned c = tid; c < ng * cells; c += kBBlock) acc[c] = -0.0;
-    for (unsigned w = tid; w < ng * zwords; w += kBBlock) zbits[w] = 0u;
-    __syncthreads();
-
-    if (s_all) {
-      for (;;) {
-        // window bound: no group contributes more than `win` entries
-        if (tid < ng) {
-          const GroupRec G = s_grp[tid];
-          const unsigned rem = s_neff[tid] - s_p[tid];
-          s_bnd[tid] = rem > win ? a.xr[G.start + s_p[tid] + win - 1].ystart : 0xffffffffu;
-        }
-        __syncthreads();
-        unsigned bound = 0xffffffffu, left = 0;
-        for (unsigned t = 0; t < ng; ++t) {
-          bound = s_bnd[t] < bound ? s_bnd[t] : bound;
-          left += s_neff[t] - s_p[t];
-        }
-        if (left == 0) break;  // uniform
-        for (unsigned k = tid; k < kCoWin; k += kBBlock) {
-          const unsigned t = k / win;
-          unsigned long long key = ~0ull;
-          if (t < ng) {
-            const unsigned e = s_p[t] + (k - t * win);
-            if (e < s_neff[t]) {
-              XRec r = a.xr[s_grp[t].start + e];
-              if ((unsigned long long)r.ystart + r.ycnt > (unsigned long long)a.ny) {
-                record_error(a.st, kErrInternal);
-                r.ycnt = 0;
-              }
-              if (r.ystart <= bound) {  // key: Y start | group << 16 | window slot
-                key = ((unsigned long long)r.ystart << 32) | (t << 16) | k;
-                s_v[k] = r.v;
-                s_cnt[k] = r.ycnt;
-                atomicAdd(&s_take[t], 1u);
-              }
-            }
-          }
-          s_key[k] = key;
-        }
-        __syncthreads();
-        bitonic_sort_lds_n(s_key, kCoWin);
-        unsigned nwin = 0;
-        for (unsigned t = 0; t < ng; ++t) nwin += s_take[t];
-        // units: runs of equal Y start among the sorted window
-        bool first = false;
-        if (tid < nwin) first = tid == 0 || (s_key[tid] >> 32) != (s_key[tid - 1] >> 32);
-        unsigned long long nunits;
-        const unsigned long long uidx = block_excl_scan<kBBlock>(first ? 1ull : 0ull, s_wave, &nunits);
-        if (first) s_unit[uidx] = tid;
-        if (tid == 0) s_unit[nunits] = nwin;
-        __syncthreads();
-        constexpr unsigned kEU = 7;  // Y runs in flight per wave: memory-level parallelism bounds this walk
-        for (unsigned r0 = wave; r0 < (unsigned)nunits; r0 += kWaves * kEU) {
-          unsigned ys[kEU], cnt[kEU], span[kEU];  // span: first entry | end entry << 16
-          unsigned m = 0;
-#pragma unroll
-          for (unsigned u = 0; u < kEU; ++u) {
-            const unsigned unit = r0 + u * kWaves;
-            cnt[u] = 0;
-            ys[u] = 0;
-            span[u] = 0;
-            if (unit < (unsigned)nunits) {
-              const unsigned i0 = s_unit[unit];
-              span[u] = i0 | (s_unit[unit + 1] << 16);
-              const unsigned long long k = s_key[i0];
-              ys[u] = (unsigned)(k >> 32);
-              cnt[u] = s_cnt[(unsigned)(k & 0xffffu)];
-            }
-            m = cnt[u] > m ? cnt[u] : m;
-          }
-          for (unsigned j = lane; j < m; j += 64) {
-            unsigned yk[kEU];
-            double yv[kEU];
-#pragma unroll
-            for (unsigned u = 0; u < kEU; ++u)
-              if (j < cnt[u]) {
-                yk[u] = a.ykey16[ys[u] + j];
-                yv[u] = a.yval[ys[u] + j];
-              }
-#pragma unroll
-            for (unsigned u = 0; u < kEU; ++u)
-              if (j < cnt[u])
-                for (unsigned i = span[u] & 0xffffu; i < (span[u] >> 16); ++i) {
-                  const unsigned k = (unsigned)s_key[i];  // one LDS broadcast per wave
-                  add((k >> 16) & 0xffu, yk[u] & cmask, __dmul_rn(s_v[k & 0xffffu], yv[u]));
-                }
-          }
-        }
-        __syncthreads();
-        if (tid < ng) {
-          s_p[tid] += s_take[tid];
-          s_take[tid] = 0u;
-        }
-        __syncthreads();
-      }
-    } else {
-      // product-parallel per group over chunks of kCoWin entries
-      for (unsigned t = 0; t < ng; ++t) {
-        const GroupRec G = s_grp[t];
-        for (unsigned base = 0; base < G.count; base += kCoWin) {
-          const unsigned e = base + tid;
-          unsigned long long c = 0;
-          unsigned ys = 0;
-          double v = 0.0;
-          if (e < G.count) {
-            const XRec r = a.xr[G.start + e];
-            c = r.ycnt;
-            ys = r.ystart;
-            v = r.v;
-          }
-          unsigned long long tot;
-          const unsigned long long excl = block_excl_scan<kBBlock>(c, s_wave, &tot);
-          s_key[tid] = excl;
-          s_cnt[tid] = ys;
-          s_v[tid] = v;
-          __syncthreads();
-          for (unsigned long long q = tid; q < tot; q += kBBlock) {
-            int l = 0, h = kCoWin - 1;
-            while (l < h) {
-              const int mid = (l + h + 1) >> 1;
-              if (s_key[mid] <= q)
-                l = mid;
-              else
-                h = mid - 1;
-            }
-            const unsigned long long y = (unsigned long long)s_cnt[l] + (q - s_key[l]);
-            if (y >= (unsigned long long)a.ny) {
-              record_error(a.st, kErrInternal);
-              continue;
-            }
-            add(t, (unsigned)a.ykey16[y] & cmask, __dmul_rn(s_v[l], a.yval[y]));
-          }
-          __syncthreads();
-        }
-      }
-    }
-    __syncthreads();
-
-    // per group: count, reserve, write
-    for (unsigned t = 0; t < ng; ++t) {
-      const GroupRec G = s_grp[t];
-      const double* at = acc + (size_t)t * cells;
-      const unsigned* zt = zbits + t * zwords;
-      unsigned long long n = 0;
-      for (unsigned c = tid; c < cells; c += kBBlock) n += co_reached(at, zt, c) ? 1u : 0u;
-      n = block_sum<kBBlock>(n, s_wave);
-      if (tid == 0) s_base = atomicAdd(a.bout ? &a.bseg[G.phi >> a.bwx].cursor : &a.st->out_base, n);
-      __syncthreads();
-      const unsigned long long obase = s_base;
-      unsigned long long run = 0;
-      for (unsigned c0 = 0; c0 < cells; c0 += kBBlock) {
-        const unsigned c = c0 + tid;
-        const bool occ = c < cells && co_reached(at, zt, c);
-        unsigned long long tot;
-        const unsigned long long r = block_excl_scan<kBBlock>(occ ? 1ull : 0ull, s_wave, &tot);
-        if (occ) {
-          const unsigned long long pos = obase + run + r;
-          if (a.bout)
-            batch_store(a.bout, a.out_idx, a.out_val, a.bwx, (uint32_t)(G.phi >> a.bwx), pos, G.phi, c, at[c], a.st);
-          else if ((int64_t)pos < a.out_cap)
-            write_output(a, pos, G.phi, c, at[c]);
-        }
-        run += tot;
-      }
-      __syncthreads();
-    }
   }
 }
 
@@ -1229,35 +880,65 @@ __global__ __launch_bounds__(kDBlock) void k_group_direct(GroupArgs a, const uin
 // grouped Y and finds repeated Y coordinates (two entries of one run with
 // the same free key) with a per-run bitmap of the 2^kDenseBits keys, which
 // the direct class needs to know about.
+// With yso (SORT only), the compact copy of every run is also cut into
+// kSlices slices of the Y free key space (key >> slice_shift): a sorted run
+// is cut where the slice changes, a longer run is placed slice by slice (in
+// no order within a slice).  yso[slot * (kSlices + 1) + s] receives the
+// position where slice s of the slot's run begins (entry kSlices: the run's
+// end), and runslot[start of the run] the slot.
 template <bool SORT>
 __global__ __launch_bounds__(kBBlock) void k_sort_y_runs(const YSlot* __restrict__ ytab, int64_t nslots,
                                                          YEntry* __restrict__ yg, int64_t ny,
                                                          uint16_t* __restrict__ ykey16, double* __restrict__ yval,
-                                                         unsigned* __restrict__ colbits, DevStatus* st) {
+                                                         unsigned* __restrict__ colbits, uint32_t* __restrict__ yso,
+                                                         uint32_t* __restrict__ runslot, unsigned slice_shift,
+                                                         DevStatus* st) {
   __shared__ unsigned long long s_key[kBBlock];
   __shared__ YEntry s_ent[kBBlock];
   constexpr unsigned kSeenWords = (1u << kDenseBits) / 32;
   __shared__ unsigned s_seen[kSeenWords];
   __shared__ unsigned s_cells[kSeenWords];  // cells that occur in this workgroup's runs
+  __shared__ unsigned s_slice[kSlices];     // entries per slice, then the slices' placement cursors
   for (unsigned w = threadIdx.x; w < kSeenWords; w += kBBlock) s_cells[w] = 0u;
   auto seen_before = [&](unsigned long long phi) {
     const unsigned c = (unsigned)phi & ((1u << kDenseBits) - 1u), bit = 1u << (c & 31);
     if (colbits) atomicOr(&s_cells[c >> 5], bit);
     return (atomicOr(&s_seen[c >> 5], bit) & bit) != 0u;
   };
+  const unsigned smask = kSlices - 1u;
   for (int64_t slot = blockIdx.x; slot < nslots; slot += gridDim.x) {
     const YSlot t = ytab[slot];
     if (t.key == kEmpty || t.count == 0 || (unsigned long long)t.start + t.count > (unsigned long long)ny)
       continue;  // uniform across the block
     const unsigned n = t.count, tid = threadIdx.x;
+    uint32_t* so = yso ? yso + (size_t)slot * (kSlices + 1) : nullptr;
+    if (so && tid == 0) runslot[t.start] = (uint32_t)slot;
     for (unsigned w = tid; w < kSeenWords; w += kBBlock) s_seen[w] = 0u;
+    if (tid < kSlices) s_slice[tid] = 0u;
     __syncthreads();
-    if (!SORT || n > (unsigned)kBBlock) {  // copy as is (too long to sort here)
+    if (!SORT || n > (unsigned)kBBlock) {  // too long to sort here: copied as is, or slice by slice
+      if (so) {
+        for (unsigned j = tid; j < n; j += kBBlock)
+          atomicAdd(&s_slice[((unsigned)yg[t.start + j].phi >> slice_shift) & smask], 1u);
+        __syncthreads();
+        if (tid == 0) {
+          unsigned run = 0;
+          for (unsigned q = 0; q < kSlices; ++q) {
+            const unsigned c = s_slice[q];
+            so[q] = t.start + run;
+            s_slice[q] = run;
+            run += c;
+          }
+          so[kSlices] = t.start + n;
+        }
+        __syncthreads();
+      }
       for (unsigned j = tid; j < n; j += kBBlock) {
         const YEntry e = yg[t.start + j];
         if (seen_before(e.phi)) st->ydup = 1u;
-        ykey16[t.start + j] = (uint16_t)e.phi;
-        yval[t.start + j] = e.v;
+        const unsigned at = so ? atomicAdd(&s_slice[((unsigned)e.phi >> slice_shift) & smask], 1u) : j;
+        ykey16[t.start + at] = (uint16_t)e.phi;
+        yval[t.start + at] = e.v;
       }
       __syncthreads();
       continue;
@@ -1278,6 +959,13 @@ __global__ __launch_bounds__(kBBlock) void k_sort_y_runs(const YSlot* __restrict
       yg[t.start + tid] = e;
       ykey16[t.start + tid] = (uint16_t)e.phi;
       yval[t.start + tid] = e.v;
+      if (so) {  // slice boundaries: where the (sorted) slice index changes
+        const unsigned q = ((unsigned)e.phi >> slice_shift) & smask;
+        const unsigned qp = tid == 0 ? 0u : ((unsigned)(s_key[tid - 1] >> 11) >> slice_shift) & smask;
+        for (unsigned b = (tid == 0 ? 0u : qp + 1u); b <= q; ++b) so[b] = t.start + tid;
+        if (tid == n - 1)
+          for (unsigned b = q + 1u; b <= (unsigned)kSlices; ++b) so[b] = t.start + n;
+      }
     }
     __syncthreads();
   }
@@ -1432,81 +1120,18 @@ hipError_t launch_group_wave(const GroupArgs& a, const uint32_t* wlist, int64_t 
 
 // Dynamic LDS of the block class: a kBlockSlots-slot hash of 16-byte slots,
 // or (dense) up to kCoMaxGroups arrays of `cells` doubles plus bitmaps
-// within kCoLds; the plan-time sort stages kCoSortMax keys and records.
 constexpr size_t kBlockHashLds = (size_t)kBlockSlots * 16;
-constexpr size_t kSortLds = (size_t)kCoSortMax * (8 + sizeof(XRec));
-constexpr size_t kSortSmallLds = (size_t)kSortSmall * (8 + sizeof(XRec));
-
-// Groups a dense workgroup co-accumulates for `cells` accumulator cells.
-static unsigned co_groups(unsigned cells) {
-  const size_t per = (size_t)cells * 8 + cells / 8;
-  size_t g = kCoLds / per;
-  if (g > (size_t)kCoMaxGroups) g = kCoMaxGroups;
-  return g < 1 ? 1u : (unsigned)g;
-}
-
-// Groups per co-accumulating workgroup.  One workgroup runs per CU, so a
-// list of `sets` sets takes ceil(sets / CUs) rounds; sharing Y runs makes a
-// group about 8% cheaper per extra group of its set (measured on the 48^4
-// block-sparse workload).  Picks the count with the least estimated time:
-// large lists take the most groups LDS allows, short ones the count that
-// fills the last round.
-static unsigned pick_co_groups(int64_t nb, unsigned gmax, int num_cus) {
-  const int64_t cus = num_cus > 0 ? num_cus : 1;
-  double best = 0.0;
-  unsigned pick = 1;
-  for (unsigned g = 1; g <= gmax; ++g) {
-    const int64_t sets = (nb + g - 1) / g, rounds = (sets + cus - 1) / cus;
-    const double cost = (double)rounds * g * (1.0 - 0.08 * (g - 1));
-    if (g == 1 || cost < best) {
-      best = cost;
-      pick = g;
-    }
-  }
-  return pick;
-}
-
-static unsigned dense_cells_for(int32_t bits_y) {
-  unsigned cells = 1u << bits_y;
-  return cells < (unsigned)kBBlock ? (unsigned)kBBlock : cells;
-}
-
 hipError_t prepare_group_block() {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_group_block_dense),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kCoLds);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sort_block_entries<kBBlock, kCoSortMax>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSortLds);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_group_block<false>),
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_group_block),
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)kBlockHashLds);
 }
 
-hipError_t launch_sort_block_entries(const GroupRec* groups, const uint32_t* blist, int64_t nb, XRec* xr,
-                                     uint32_t* neff, int num_cus, hipStream_t stream) {
+hipError_t launch_group_block(const GroupArgs& a, const uint32_t* blist, int64_t nb, int num_cus,
+                              hipStream_t stream) {
   if (nb <= 0) return hipSuccess;
-  k_sort_block_entries<256, kSortSmall><<<grid_for(nb * 256, 256, num_cus, 8), 256, kSortSmallLds, stream>>>(
-      groups, blist, nb, xr, neff);
-  k_sort_block_entries<kBBlock, kCoSortMax><<<grid_for(nb * kBBlock, kBBlock, num_cus, 2), kBBlock, kSortLds,
-                                                stream>>>(groups, blist, nb, xr, neff);
-  return hipGetLastError();
-}
-
-hipError_t launch_group_block(const GroupArgs& a, const uint32_t* blist, int64_t nb, int dense, const uint32_t* neff,
-                              int num_cus, hipStream_t stream) {
-  if (nb <= 0) return hipSuccess;
-  if (dense) {
-    const unsigned cells = dense_cells_for(a.bits_y), ng = pick_co_groups(nb, co_groups(cells), num_cus);
-    const int64_t nsets = (nb + ng - 1) / ng;
-    unsigned grid = grid_for(nsets * kBBlock, kBBlock, num_cus, 2);
-    if (grid >= kXcds) grid -= grid % kXcds;  // whole rounds over the XCDs
-    const size_t lds = (size_t)ng * cells * 8 + (size_t)ng * (cells / 8);
-    k_group_block_dense<<<grid, kBBlock, lds, stream>>>(a, blist, nb, neff, cells, ng);
-  } else {
-    unsigned grid = grid_for(nb * kBBlock, kBBlock, num_cus, 2);
-    if (grid >= kXcds) grid -= grid % kXcds;
-    k_group_block<false><<<grid, kBBlock, kBlockHashLds, stream>>>(a, blist, nb, 0u);
-  }
+  unsigned grid = grid_for(nb * kBBlock, kBBlock, num_cus, 2);
+  if (grid >= kXcds) grid -= grid % kXcds;
+  k_group_block<<<grid, kBBlock, kBlockHashLds, stream>>>(a, blist, nb);
   return hipGetLastError();
 }
 
@@ -1538,15 +1163,16 @@ hipError_t launch_scan_group_counts(const uint32_t* gn, const uint32_t* wlist, i
 
 hipError_t launch_sort_y_runs(const YSlot* ytab, int64_t nslots, YEntry* yg, int64_t ny, uint16_t* ykey16,
                               double* yval, unsigned* colbits, DevStatus* st, bool sort, int num_cus,
-                              hipStream_t stream) {
+                              hipStream_t stream, uint32_t* yso, uint32_t* runslot, unsigned slice_shift) {
   if (nslots <= 0 || ny <= 0) return hipSuccess;
+  if (yso && !sort) return hipErrorInvalidValue;
   int64_t grid = nslots < (int64_t)num_cus * 2 ? nslots : (int64_t)num_cus * 2;
   if (sort)
     k_sort_y_runs<true><<<dim3((unsigned)grid), kBBlock, 0, stream>>>(ytab, nslots, yg, ny, ykey16, yval, colbits,
-                                                                       st);
+                                                                       yso, runslot, slice_shift, st);
   else
     k_sort_y_runs<false><<<dim3((unsigned)grid), kBBlock, 0, stream>>>(ytab, nslots, yg, ny, ykey16, yval, colbits,
-                                                                        st);
+                                                                        nullptr, nullptr, 0u, st);
   return hipGetLastError();
 }
 

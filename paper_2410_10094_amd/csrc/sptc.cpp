@@ -300,7 +300,7 @@ struct sptc_plan_s : Workspace {
   uint32_t* wlist = nullptr;
   uint32_t* blist = nullptr;
   uint32_t* glist = nullptr;
-  uint32_t* bneff = nullptr;  // dense block class: entries with a Y match, per listed group (sorted first)
+  uint32_t* yso = nullptr;    // dense block class: where each slice of each Y run begins, per Y table slot
   int32_t block_mfma = 0;     // dense block class on the matrix cores
   unsigned* ycolbits = nullptr;  // dense Y free key: the cells that occur (bitmap)
   unsigned ycols = 0;            // and their number
@@ -531,6 +531,9 @@ sptc_status size_out_table(sptc_plan_s* P, int64_t products) {
   return SPTC_OK;
 }
 
+// Cells of the dense LDS accumulator for a Y free key of bits_y bits.
+unsigned dense_cells(int32_t bits_y) { return std::max(1u << bits_y, 1024u); }
+
 // Shift of the Y free key in the repeated-coordinate check, or -1 when the
 // whole coordinate does not fit 63 bits and the check hashes it instead.
 int32_t yset_bits(const sptc_plan_s* P) { return P->bits_c + P->bits_fy <= 63 ? P->bits_fy : -1; }
@@ -746,15 +749,19 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
   if (P->nb > 0) {
     HIP_TRY(prepare_group_block());
     if (P->dense) {
-      if ((st = P->allocate_n(P->nb, &P->bneff))) return st;
       HIP_TRY(mark(P, s, SPTC_STAGE_X_SORT, 0));
       if (mfma_candidate(P) && (st = plan_block_mfma(P))) return st;
       if (!P->block_mfma) {
-        // the walk merges each group's entries in Y-run order, and walks
-        // runs sorted by Y free key (consecutive accumulator cells)
+        // the sliced walk: runs sorted by Y free key (consecutive
+        // accumulator cells) and cut into the slices of the Y free key
+        // space; block-class X records keyed by their run's table slot
+        uint32_t* runslot = nullptr;
+        if ((st = P->allocate_n(P->ytab_slots * (kSlices + 1), &P->yso))) return st;
+        if ((st = P->allocate_n(P->ny, &runslot))) return st;
+        const unsigned cells = dense_cells(P->bits_fy);
         HIP_TRY(launch_sort_y_runs(P->ytab, P->ytab_slots, P->yg, P->ny, P->ykey16, P->yval, nullptr, P->st, true,
-                                   P->num_cus, s));
-        HIP_TRY(launch_sort_block_entries(P->groups, P->blist, P->nb, P->xr, P->bneff, P->num_cus, s));
+                                   P->num_cus, s, P->yso, runslot, (unsigned)__builtin_ctz(cells / kSlices)));
+        HIP_TRY(launch_block_runslots(P->groups, P->blist, P->nb, P->xr, runslot, P->ny, P->st, P->num_cus, s));
       }
       HIP_TRY(mark(P, s, SPTC_STAGE_X_SORT, 1));
     }
@@ -1051,7 +1058,10 @@ sptc_status execute_plan(sptc_plan_s* P, int32_t* out_idx, double* out_val, int6
     if (P->block_mfma)
       HIP_TRY(launch_group_block_mfma(a, P->blist, P->nb, P->mplan, P->num_cus, s));
     else
-      HIP_TRY(launch_group_block(a, P->blist, P->nb, P->dense, P->bneff, P->num_cus, s));
+      HIP_TRY(P->dense ? launch_group_block_sliced(a, P->blist, P->nb, P->yso, P->ytab_slots, dense_cells(P->bits_fy),
+                                                    (double)P->ny / (double)std::max<int64_t>(P->y_groups, 1) / kSlices,
+                                                    P->num_cus, s)
+                       : launch_group_block(a, P->blist, P->nb, P->num_cus, s));
     HIP_TRY(mark(P, s, SPTC_STAGE_BLOCK, 1));
     if (P->ngl == 0) {
       HIP_TRY(mark(P, s, SPTC_STAGE_COMPACT, 0));

@@ -150,7 +150,6 @@ constexpr int kWaveCap = 358;      // largest distinct-output bound a wave takes
 constexpr int kBlockSlots = 4096;  // LDS hash slots per workgroup
 constexpr int kBlockCap = 2867;    // largest distinct-output bound a workgroup hash takes
 constexpr int kDenseBits = 13;     // dense LDS accumulator when the Y free key has <= 13 bits
-constexpr int kCoSortMax = 4096;   // block groups sorted at plan time (and co-accumulated): at most this many entries
 
 // Block class on the matrix cores (dense Y free keys, one contraction).
 // The block groups are the rows, the Y runs (distinct contracting keys) the
@@ -347,17 +346,11 @@ hipError_t launch_group_wave(const GroupArgs& a, const uint32_t* wlist, int64_t 
 
 // Block class, single pass: each workgroup accumulates a group, reserves its
 // outputs with one atomic on st->out_base and writes them.
-// Raises the block-class kernels' dynamic LDS limit on the current device;
-// called once per plan so that execute issues kernel launches only.
+// Raises the hashed block-class kernel's dynamic LDS limit on the current
+// device; called once per plan so that execute issues kernel launches only.
 hipError_t prepare_group_block();
-// Dense block class: neff[i] is filled by launch_sort_block_entries.
-hipError_t launch_group_block(const GroupArgs& a, const uint32_t* blist, int64_t nb, int dense, const uint32_t* neff,
-                              int num_cus, hipStream_t stream);
-
-// Plan time, dense block class: sorts each listed group's X entries by Y run
-// (groups of at most 4096 entries) and counts those with a Y match into neff.
-hipError_t launch_sort_block_entries(const GroupRec* groups, const uint32_t* blist, int64_t nb, XRec* xr,
-                                     uint32_t* neff, int num_cus, hipStream_t stream);
+// Hashed block class (Y free key wider than kDenseBits).
+hipError_t launch_group_block(const GroupArgs& a, const uint32_t* blist, int64_t nb, int num_cus, hipStream_t stream);
 
 // Block survey, before the class counts are read back: the block class's
 // products into st->block_products (zeroed first; the block list's length
@@ -403,10 +396,36 @@ hipError_t launch_finalize(int64_t* out_nnz, int64_t out_cap, DevStatus* st, hip
 // values) the dense accumulators read and flags repeated Y coordinates;
 // with sort, first sorts each run of 2..1024 entries by Y free key.  With
 // colbits (kCellWords words, zeroed first), also ORs in a bit for every
-// Y free cell that occurs.
+// Y free cell that occurs.  With yso (sort only; [nslots][kSlices + 1]
+// u32) and runslot ([ny] u32), also cuts every run into kSlices slices of
+// the Y free key (key >> slice_shift), slice by slice in the compact copy:
+// yso[slot][s] is where slice s of the slot's run begins (yso[slot][kSlices]
+// its end) and runslot[run start] = slot.
 hipError_t launch_sort_y_runs(const YSlot* ytab, int64_t nslots, YEntry* yg, int64_t ny, uint16_t* ykey16,
                               double* yval, unsigned* colbits, DevStatus* st, bool sort, int num_cus,
-                              hipStream_t stream);
+                              hipStream_t stream, uint32_t* yso = nullptr, uint32_t* runslot = nullptr,
+                              unsigned slice_shift = 0);
+
+// ---- dense block class, sliced (block_sliced.hip) ----
+// The dense Y free key space is cut into kSlices slices, one per XCD: a
+// tile is (block-class group, slice), accumulated by one wave in LDS.
+constexpr int kSlices = 8;
+
+// Plan time: block-class X records refer to their Y run by its table slot
+// (runslot of their run start) instead of the run start.
+hipError_t launch_block_runslots(const GroupRec* groups, const uint32_t* blist, int64_t nb, XRec* xr,
+                                 const uint32_t* runslot, int64_t ny, DevStatus* st, int num_cus,
+                                 hipStream_t stream);
+
+// Dense block class: every (group, slice) tile accumulates its group's
+// products whose Y free key falls in the slice (runs cut by yso), reserves
+// its outputs with one atomic and writes them.  cells: the dense
+// accumulator size (a power of two of at least 1024 and at least 2^bits_y);
+// mean_slice_run: average entries of a run per slice (picks the lanes per
+// X entry).
+hipError_t launch_group_block_sliced(const GroupArgs& a, const uint32_t* blist, int64_t nb, const uint32_t* yso,
+                                     int64_t yso_slots, unsigned cells, double mean_slice_run, int num_cus,
+                                     hipStream_t stream);
 
 // Clears st->err and st->out_base.
 hipError_t launch_reset_status(DevStatus* st, hipStream_t stream);

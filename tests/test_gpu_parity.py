@@ -358,10 +358,9 @@ def test_out_of_range_coordinate_is_rejected():
 
 
 def _co_problems():
-    """Dense block-class groups in numbers that make a workgroup accumulate
-    several groups at once (co-accumulation), with entries spread over
-    several merge windows, explicit zero values, repeated X coordinates, and
-    a group too large to be sorted at plan time (its set falls back)."""
+    """Many dense block-class groups of uneven sizes (many more tiles than
+    waves in flight), explicit zero values, repeated X coordinates, and one
+    group far larger than the rest."""
     rng = np.random.default_rng(71)
     out = []
 
@@ -370,7 +369,7 @@ def _co_problems():
         yi = np.stack([np.repeat(np.arange(C), per), rng.integers(0, 64, ny), rng.integers(0, 64, ny)])
         return Coo((C, 64, 64), yi.astype(np.int32), W.nonzero_uniform(rng, ny))
 
-    # ~2000 groups (four per workgroup), most with ~20 entries, every 50th with ~700
+    # ~2000 groups, most with ~20 entries, every 50th with ~700
     C = 1024
     cols = []
     for g in range(2000):
@@ -384,7 +383,7 @@ def _co_problems():
     xi = np.concatenate([xi, dup], axis=1)
     xv = np.concatenate([xv, W.nonzero_uniform(rng, dup.shape[1])])
     out.append(Problem("co-2000-groups", Coo((50, 40, C), xi, xv), y_dense(C, 30), (2,), (0,)))
-    # ~300 groups (two per workgroup)
+    # ~300 groups of 40-400 entries
     cols = []
     for g in range(300):
         n = int(rng.integers(40, 400))
@@ -392,7 +391,7 @@ def _co_problems():
     xi = np.concatenate(cols, axis=1).astype(np.int32)
     out.append(Problem("co-300-groups", Coo((15, 20, C), xi, W.nonzero_uniform(rng, xi.shape[1])),
                        y_dense(C, 20), (2,), (0,)))
-    # a group of 5000 entries among 2000 small ones: its set is walked per group
+    # a group of 5000 entries among 2000 small ones (13-bit Y free key)
     C2 = 8192
     cols = [np.stack([np.zeros(5000, int), np.zeros(5000, int), rng.choice(C2, 5000, replace=False)])]
     for g in range(1, 2000):
@@ -406,9 +405,8 @@ def _co_problems():
 
 @pytest.mark.parametrize("mfma", [0, 1], ids=["walk", "mfma"])
 @pytest.mark.parametrize("p", _co_problems(), ids=lambda p: p.name)
-def test_dense_block_co_accumulation(p, mfma):
-    """Both block-class kernels: the sparse walk (co-accumulation, with its
-    per-group fallback for the group too large to sort) and the matrix-core
+def test_dense_block_many_groups(p, mfma):
+    """Both dense block-class kernels: the sliced walk and the matrix-core
     product."""
     import paper_2410_10094_amd as sptc
     log(f"[co] {p.name} nnz {p.X.nnz}x{p.Y.nnz} block_mfma {mfma}")
