@@ -53,13 +53,6 @@ def algorithmic_bytes(stage, p, products, nnz_z, x_groups=0, mode="grouped", inf
     if stage == "block":
         # grouped X records and grouped-Y entries read once, COO written once
         return 16 * nx + 16 * ny + nnz_z * (4 * nz_order + 8)
-    if stage == "group_count":
-        # grouped X records (16 B) and the needed grouped-Y entries (16 B) read once;
-        # group records (16 B) and product offsets (2 x 8 B) read, one count (4 B) written per group
-        return 16 * nx + 16 * ny + x_groups * (16 + 16 + 4)
-    if stage == "group_fill":
-        # as the count pass, plus the output offsets (8 B per group) and the COO written once
-        return 16 * nx + 16 * ny + x_groups * (16 + 16 + 8 + 4) + nnz_z * (4 * nz_order + 8)
     if stage == "x_probe" and mode == "grouped":
         # X COO read once, grouped X records (16 B) written once
         return nx * (4 * ox + 8) + 16 * nx
@@ -314,11 +307,11 @@ def autotune_batched(draws, dev, sample):
     sub = draws[:sample]
     tuner = autotune.Autotuner()
     run = autotune.torch_batch_runner(sub, dev[:sample], klass)
-    run(1 / 1.3, 1e9)  # warm the pools before timing candidates
+    run(1 / 1.3, 1e9, 0)  # warm the pools before timing candidates
     return tuner.tune(autotune.signature(sub, klass), run)
 
 
-def run_batched(draws, dev, steps, warmup, budget, load_factor=1 / 1.3):
+def run_batched(draws, dev, steps, warmup, budget, load_factor=1 / 1.3, tile=0):
     """The batched workload two ways, each step covering every draw:
     per-call (sptc_plan + sptc_execute per contraction) and batched
     (sptc_batch_plan + sptc_batch_execute per sub-batch of at most `budget`
@@ -332,7 +325,7 @@ def run_batched(draws, dev, steps, warmup, budget, load_factor=1 / 1.3):
 
     # per-call: one output buffer sized for the largest bound
     bounds, orders, products = [], [], []
-    opts = lambda: sptc.default_options(load_factor=load_factor)
+    opts = lambda: sptc.default_options(load_factor=load_factor, tile=tile)
     for (X, Y), p in zip(dev, draws):
         with sptc.plan(X, Y, p.cx, p.cy, options=opts()) as pl:
             bounds.append(pl.out_nnz_bound)
@@ -444,14 +437,15 @@ def run_batched(draws, dev, steps, warmup, budget, load_factor=1 / 1.3):
 # (FETCH_SIZE, then WRITE_SIZE), keyed by (workload, kernel).  A figure only
 # holds while the kernel's sources are the ones profiled.
 TRAFFIC_PROFILES = {
-    ("block-sparse-1.5M", "k_group_block_dense"): "block_walk_block-sparse-1.5M_counters.md",
+    ("block-sparse-1.5M", "k_lds_queue"): "lds_queue_block-sparse-1.5M_counters.md",
     ("block-sparse-1.5M", "k_group_block_mfma"): "block_mfma_block-sparse-1.5M_hbm_counters.md",
     ("imbalanced", "k_group_direct"): "direct_imbalanced_counters.md",
     ("block-sparse-1.5M", "k_expand_acc"): "expand_global_block-sparse-1.5M_counters.md",
     ("imbalanced", "k_expand_acc"): "expand_global_imbalanced_counters.md",
 }
 KERNEL_SOURCES = ("paper_2410_10094_amd/csrc/grouped.hip", "paper_2410_10094_amd/csrc/block_mfma.hip",
-                  "paper_2410_10094_amd/csrc/kernels.hip", "paper_2410_10094_amd/csrc/prim.hpp",
+                  "paper_2410_10094_amd/csrc/kernels.hip", "paper_2410_10094_amd/csrc/queue.hip",
+                  "paper_2410_10094_amd/csrc/lds_items.hpp", "paper_2410_10094_amd/csrc/prim.hpp",
                   "paper_2410_10094_amd/csrc/sptc_internal.hpp")
 
 
@@ -542,9 +536,8 @@ def kernel_of(stage, info):
     if stage == "block":
         if info.get("block_mfma"):
             return "k_group_block_mfma"
-        return "k_group_block_dense" if info["key_bits"][2] <= 13 else "k_group_block"
-    return {"direct": "k_group_direct", "expand": "k_expand_acc", "group_count": "k_group_wave",
-            "group_fill": "k_group_wave", "compact": "occupancy scan", "x_probe": "X grouping",
+        return "k_lds_queue" if info["key_bits"][2] <= 13 else "k_group_block"
+    return {"direct": "k_group_direct", "expand": "k_expand_acc", "compact": "occupancy scan", "x_probe": "X grouping",
             "x_sort": "block entry sort"}.get(stage, stage)
 
 
@@ -606,7 +599,7 @@ def compact_batched(res):
     out["batched"]["top_stages_ms"] = dict(sorted(res["batched"].get("stage_ms_per_step", {}).items(),
                                                   key=lambda kv: -kv[1])[:5])
     if res.get("autotune"):
-        out["autotune"] = {k: res["autotune"][k] for k in ("load_factor", "batch_products", "tuning_seconds")
+        out["autotune"] = {k: res["autotune"][k] for k in ("load_factor", "batch_products", "tile", "tuning_seconds")
                            if k in res["autotune"]}
     return out
 
@@ -695,8 +688,9 @@ def main():
         tuned = autotune_batched(draws, dev, min(len(draws), 128)) if args.autotune else None
         budget = tuned["batch_products"] if tuned else args.batch_budget
         lf = tuned["load_factor"] if tuned else 1 / 1.3
+        tile = tuned["tile"] if tuned else 0
         progress("batched workload: per-call and batched legs")
-        batched = run_batched(draws, dev, max(1, args.steps // 5), 1, budget, lf)
+        batched = run_batched(draws, dev, max(1, args.steps // 5), 1, budget, lf, tile)
         batched["autotune"] = tuned
         release_cached_memory()
         batched["workload"] = (f"{len(draws)} draws: orders 3-5, dims U[32,4096], nnz log-U[1e3,1e6], "

@@ -121,10 +121,11 @@ typedef enum sptc_stage {
   SPTC_STAGE_OUT_CLEAR = 5,  /* output hash: mark every slot empty */
   SPTC_STAGE_EXPAND = 6,     /* expand products, accumulate in the output hash */
   SPTC_STAGE_COMPACT = 7,    /* output hash -> COO: count, prefix sum, fill */
-  SPTC_STAGE_GROUP_COUNT = 8, /* grouped path, small groups: accumulate in LDS, count outputs */
-  SPTC_STAGE_GROUP_FILL = 9,  /* grouped path, small groups: prefix sum of the counts, accumulate again, write */
+  SPTC_STAGE_GROUP_COUNT = 8, /* (no longer marked: small groups run in stage BLOCK's persistent launch) */
+  SPTC_STAGE_GROUP_FILL = 9,  /* (no longer marked, as GROUP_COUNT) */
   SPTC_STAGE_DIRECT = 10,     /* grouped path, single-entry groups: write every product as an output */
-  SPTC_STAGE_BLOCK = 11,      /* grouped path, large groups: accumulate in LDS, reserve and write */
+  SPTC_STAGE_BLOCK = 11,      /* grouped path, groups accumulated in LDS (small and large): one persistent
+                                 launch over a device work queue, then the hashed or matrix-core block class */
   SPTC_STAGE_BATCH_PACK = 12,   /* batch plan: key every contraction's entries with its index */
   SPTC_STAGE_BATCH_SEGMENTS = 13, /* batch plan: products and output segments per contraction */
   SPTC_STAGE_X_SORT = 14,       /* grouped plan: dense block groups' X entries sorted by Y run */
@@ -157,6 +158,19 @@ typedef struct sptc_options {
                                 rows x columns x runs is at most 24x the class's products.
                                 Eligible: every X and Y value finite, and dense X and Y panels of at
                                 most 8 GiB.  sptc_info.block_mfma reports the choice. */
+  int32_t tile;              /* products per workgroup tile of the single-entry (direct) class: 0 (default,
+                                2048), 1024 or 2048 */
+  int32_t lds_max_keys;      /* grouped mode: most distinct outputs a group with a hashed (wide) Y free key
+                                may accumulate in a workgroup's LDS table before it goes to the output hash in
+                                device memory: 0 (default, 2867) or 64..2867 */
+  int64_t capture_out_cap;   /* 0 (default): sptc_plan reads its counts back.  > 0: sptc_plan makes no
+                                read-back at all (so sptc_plan and sptc_execute can be captured together into
+                                one HIP graph): every buffer is sized from the nonzero counts and from this
+                                bound on nnz(Z), every launch reads its counts on the device, and the plan
+                                needs a caller allocator.  Counts the plan would read back are then unknown
+                                (sptc_plan_info reports products = -1 and out_nnz_bound = capture_out_cap);
+                                errors, including nnz(Z) > capture_out_cap, show in sptc_execute's out_nnz.
+                                The matrix-core block class is not used.  Not for batches. */
 } sptc_options;
 
 /* Sizes fixed by sptc_plan. */

@@ -41,7 +41,8 @@ class Options(ctypes.Structure):
     _fields_ = [("load_factor", ctypes.c_double), ("validate", ctypes.c_int32), ("max_probe", ctypes.c_int32),
                 ("hash_seed", ctypes.c_uint64), ("out_table_slots", ctypes.c_int64),
                 ("stage_events", ctypes.POINTER(ctypes.c_void_p)), ("mode", ctypes.c_int32),
-                ("block_mfma", ctypes.c_int32)]
+                ("block_mfma", ctypes.c_int32), ("tile", ctypes.c_int32), ("lds_max_keys", ctypes.c_int32),
+                ("capture_out_cap", ctypes.c_int64)]
 
 
 class Info(ctypes.Structure):

@@ -95,36 +95,22 @@ __device__ __forceinline__ int64_t first_of(const GroupRec* __restrict__ groups,
 }
 
 __global__ void k_batch_segments(const GroupRec* __restrict__ groups, const uint32_t* __restrict__ dlist, int64_t nd,
-                                 const unsigned long long* __restrict__ dpos, const uint32_t* __restrict__ wlist,
-                                 int64_t nw, int32_t wx, int32_t count, BatchSeg* __restrict__ seg) {
+                                 const unsigned long long* __restrict__ dpos, int32_t wx, int32_t count,
+                                 BatchSeg* __restrict__ seg) {
   for (int32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < count; b += gridDim.x * blockDim.x) {
     const int64_t dlo = first_of(groups, dlist, nd, wx, (uint64_t)b);
     const int64_t dhi = first_of(groups, dlist, nd, wx, (uint64_t)b + 1);
     BatchSeg s;
     s.dshift = dlo < dhi ? dpos[dlo] : 0ull;
     s.dcount = dlo < dhi ? dpos[dhi] - dpos[dlo] : 0ull;
-    s.wshift = 0ull;
-    s.cursor = 0ull;
-    s.wlo = (uint32_t)first_of(groups, wlist, nw, wx, (uint64_t)b);
-    s.whi = (uint32_t)first_of(groups, wlist, nw, wx, (uint64_t)b + 1);
+    s.cursor = s.dcount;
     seg[b] = s;
   }
 }
 
-__global__ void k_batch_bases(const uint32_t* __restrict__ wlist, const uint32_t* __restrict__ gn,
-                              const unsigned long long* __restrict__ goff, int32_t count, BatchSeg* __restrict__ seg) {
-  for (int32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < count; b += gridDim.x * blockDim.x) {
-    BatchSeg s = seg[b];
-    unsigned long long wstart = 0ull, wcount = 0ull;
-    if (s.whi > s.wlo) {
-      const uint32_t first = wlist[s.wlo], last = wlist[s.whi - 1];
-      wstart = goff[first];
-      wcount = goff[last] + gn[last] - wstart;
-    }
-    s.wshift = wstart - s.dcount;  // modulo 2^64: numbering - wshift = place in b's COO
-    s.cursor = s.dcount + wcount;
-    seg[b] = s;
-  }
+__global__ void k_batch_reset(int32_t count, BatchSeg* __restrict__ seg) {
+  for (int32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < count; b += gridDim.x * blockDim.x)
+    seg[b].cursor = seg[b].dcount;
 }
 
 __global__ void k_batch_finalize(const DevStatus* __restrict__ st, const BatchSeg* __restrict__ seg,
@@ -165,17 +151,16 @@ hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t stream)
 }
 
 hipError_t launch_batch_segments(const GroupRec* groups, const uint32_t* dlist, int64_t nd,
-                                 const unsigned long long* dpos, const uint32_t* wlist, int64_t nw, int32_t wx,
-                                 int32_t count, BatchSeg* seg, hipStream_t stream) {
+                                 const unsigned long long* dpos, int32_t wx, int32_t count, BatchSeg* seg,
+                                 hipStream_t stream) {
   const int32_t g = (count + 255) / 256;
-  k_batch_segments<<<g < 1 ? 1 : g, 256, 0, stream>>>(groups, dlist, nd, dpos, wlist, nw, wx, count, seg);
+  k_batch_segments<<<g < 1 ? 1 : g, 256, 0, stream>>>(groups, dlist, nd, dpos, wx, count, seg);
   return hipGetLastError();
 }
 
-hipError_t launch_batch_bases(const uint32_t* wlist, const uint32_t* gn, const unsigned long long* goff, int32_t count,
-                              BatchSeg* seg, hipStream_t stream) {
+hipError_t launch_batch_reset(int32_t count, BatchSeg* seg, hipStream_t stream) {
   const int32_t g = (count + 255) / 256;
-  k_batch_bases<<<g < 1 ? 1 : g, 256, 0, stream>>>(wlist, gn, goff, count, seg);
+  k_batch_reset<<<g < 1 ? 1 : g, 256, 0, stream>>>(count, seg);
   return hipGetLastError();
 }
 

@@ -10,22 +10,23 @@
 //   direct  one X entry and no repeated coordinate in Y: every product is its
 //           own output, written straight from a product-space gather;
 //   wave    d <= kWaveCap and few products: one wave, a private LDS hash;
-//           outputs found by a count pass, a prefix sum and a fill pass;
-//   block   dense Y free key (<= kDenseBits bits) or d <= kBlockCap: one
-//           1024-thread workgroup, a dense LDS accumulator or an LDS hash; a
-//           single pass that reserves the group's outputs with one atomic;
+//   block   dense Y free key (<= kDenseBits bits): (group, slice) tiles of a
+//           dense LDS accumulator, one wave each; or d <= kBlockCap: one
+//           1024-thread workgroup with an LDS hash;
+//           wave and dense block items run in one persistent launch over a
+//           device work queue (queue.hip); each reserves its outputs with
+//           one atomic;
 //   global  everything else: the products go to the device-memory hash.
 #include <hip/hip_runtime.h>
 
 #include "../../include/sptc.h"
+#include "lds_items.hpp"
 #include "prim.hpp"
 #include "sptc_internal.hpp"
 
 namespace sptc {
 namespace {
 
-constexpr int kGBlock = 256;
-constexpr int kGWaves = kGBlock / 64;
 constexpr int kBBlock = 1024;                           // block-class workgroup
 constexpr unsigned kXcds = 8;                          // MI355X: 8 XCDs, each with its own L2
 constexpr int kBChunk = 1024;
@@ -325,13 +326,14 @@ struct ClassifyOp {
   uint32_t* blist;
   uint32_t* glist;
   unsigned long long* dcnt;  // direct group k's products, at the k-th place (scanned in place into offsets)
+  unsigned long long block_cap;  // most distinct outputs of a group in a workgroup's LDS hash
   __device__ U128 code(int64_t g) const {
     const GroupRec G = groups[g];
     const unsigned long long b = eoff[G.start + G.count] - eoff[G.start];
     const unsigned long long d = b < ycells ? b : ycells;
     if (G.count == 1 && !st->ydup) return U128{1ull, 0ull};
     if (d <= (unsigned long long)kWaveCap && b <= kWaveMaxProducts) return U128{1ull << 32, 0ull};
-    if (dense || d <= (unsigned long long)kBlockCap) return U128{0ull, 1ull};
+    if (dense || d <= block_cap) return U128{0ull, 1ull};
     return U128{0ull, 0ull};
   }
   __device__ int64_t live(int64_t) const { return (int64_t)st->xgroups; }
@@ -357,6 +359,10 @@ struct FinClassify {
   __device__ void operator()(U128 total) const {
     st->class_lo = total.lo;
     st->class_hi = total.hi;
+    st->n_direct = total.lo & 0xffffffffull;
+    st->n_wave = total.lo >> 32;
+    st->n_block = total.hi;
+    st->n_global = st->xgroups - st->n_direct - st->n_wave - st->n_block;
   }
 };
 
@@ -387,6 +393,8 @@ struct GlobalEntryScanOp {
   const GroupRec* groups;
   const uint32_t* glist;
   unsigned long long* gl_eoff;
+  const DevStatus* st;
+  __device__ int64_t live(int64_t) const { return (int64_t)st->n_global; }
   __device__ unsigned long long get(int64_t i) const { return groups[glist[i]].count; }
   __device__ void put(int64_t i, unsigned long long excl, unsigned long long) const { gl_eoff[i] = excl; }
 };
@@ -400,8 +408,10 @@ __global__ __launch_bounds__(256) void k_gather_global(const GroupRec* __restric
                                                        const uint32_t* __restrict__ glist, int64_t ngl,
                                                        const unsigned long long* __restrict__ gl_eoff,
                                                        const XRec* __restrict__ xr, XEntry* __restrict__ xrec,
-                                                       uint32_t* __restrict__ xg, uint32_t* __restrict__ xcnt) {
+                                                       uint32_t* __restrict__ xg, uint32_t* __restrict__ xcnt,
+                                                       const DevStatus* dc) {
   const int lane = threadIdx.x & 63;
+  if (dc && (int64_t)dc->n_global < ngl) ngl = (int64_t)dc->n_global;  // read on the device
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   for (int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < ngl; i += nwaves) {
     const uint32_t g = glist[i];
@@ -422,121 +432,6 @@ __global__ __launch_bounds__(256) void k_gather_global(const GroupRec* __restric
 // ---------------------------------------------------------------------------
 // Execute: per-group accumulation in LDS
 // ---------------------------------------------------------------------------
-
-// Power-of-two table size holding d keys at load <= 0.7; at least 64 slots.
-__device__ __forceinline__ unsigned table_size_for(unsigned long long d, unsigned max_slots) {
-  const unsigned long long need = (d * 10 + 6) / 7;
-  unsigned t = 64;
-  while (t < need && t < max_slots) t <<= 1;
-  return t;
-}
-
-// Adds v at key in an LDS hash table (linear probing, 64-bit CAS).
-__device__ __forceinline__ bool lds_accumulate(ZSlot* tab, unsigned tmask, unsigned long long key, double v,
-                                               uint64_t seed) {
-  unsigned s = (unsigned)fmix64(key ^ seed) & tmask;
-  for (unsigned probe = 0; probe <= tmask; ++probe) {
-    const unsigned long long prev = atomicCAS(&tab[s].key, (unsigned long long)kEmpty, key);
-    if (prev == kEmpty || prev == key) {
-      atomicAdd(&tab[s].val, v);
-      return true;
-    }
-    s = (s + 1) & tmask;
-  }
-  return false;
-}
-
-
-struct WaveScratch {
-  unsigned long long off[64];
-  unsigned ys[64];
-  double v[64];
-};
-
-// One wave per group; each wave owns kWaveSlots LDS slots.
-template <bool FILL>
-__global__ __launch_bounds__(kGBlock) void k_group_wave(GroupArgs a, const uint32_t* __restrict__ wlist, int64_t nw) {
-  __shared__ ZSlot s_tab[kGWaves][kWaveSlots];
-  __shared__ WaveScratch s_sc[kGWaves];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  ZSlot* tab = s_tab[w];
-  WaveScratch& sc = s_sc[w];
-  for (int64_t i = (int64_t)blockIdx.x * kGWaves + w; i < nw; i += (int64_t)gridDim.x * kGWaves) {
-    const uint32_t g = wlist[i];
-    const GroupRec G = a.groups[g];
-    const unsigned long long p0 = a.eoff[G.start];
-    const unsigned long long b = a.eoff[G.start + G.count] - p0;
-    const unsigned long long d = b < a.ycells ? b : a.ycells;
-    const unsigned tsize = table_size_for(d, kWaveSlots);
-    const unsigned tmask = tsize - 1;
-    for (unsigned s = lane; s < tsize; s += 64) {
-      tab[s].key = kEmpty;
-      tab[s].val = 0.0;
-    }
-    wave_lds_fence();
-    for (unsigned base = 0; base < G.count; base += 64) {
-      const unsigned e = base + lane;
-      unsigned long long c = 0;
-      unsigned ys = 0;
-      double v = 0.0;
-      if (e < G.count) {
-        const XRec r = a.xr[G.start + e];
-        c = r.ycnt;
-        ys = r.ystart;
-        v = r.v;
-      }
-      const unsigned long long incl = wave_incl_scan(c);
-      const unsigned long long tot = __shfl(incl, 63, 64);
-      sc.off[lane] = incl - c;
-      sc.ys[lane] = ys;
-      sc.v[lane] = v;
-      wave_lds_fence();
-      for (unsigned long long q = lane; q < tot; q += 64) {
-        int lo = 0, hi = 63;  // the last entry whose run starts at or before q
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (sc.off[mid] <= q)
-            lo = mid;
-          else
-            hi = mid - 1;
-        }
-        const unsigned long long y = (unsigned long long)sc.ys[lo] + (q - sc.off[lo]);
-        if (y >= (unsigned long long)a.ny) {
-          record_error(a.st, kErrInternal);
-          continue;
-        }
-        const YEntry ye = a.yg[y];
-        if (!lds_accumulate(tab, tmask, ye.phi, __dmul_rn(sc.v[lo], ye.v), a.seed)) record_error(a.st, kErrCapacity);
-      }
-      wave_lds_fence();
-    }
-    if (!FILL) {
-      unsigned n = 0;
-      for (unsigned s = lane; s < tsize; s += 64) n += tab[s].key != kEmpty ? 1u : 0u;
-      n = (unsigned)wave_sum((unsigned long long)n);
-      if (lane == 0) a.gn[g] = n;
-    } else {
-      const unsigned long long base = a.goff[g];
-      const uint32_t bb = a.bout ? (uint32_t)(G.phi >> a.bwx) : 0u;
-      const unsigned long long shift = a.bout ? a.bseg[bb].wshift : 0ull;
-      unsigned long long run = 0;
-      for (unsigned s0 = 0; s0 < tsize; s0 += 64) {
-        const ZSlot z = tab[s0 + lane];
-        const bool occ = z.key != kEmpty;
-        const unsigned long long m = __ballot(occ);
-        if (occ) {
-          const unsigned long long pos = base + run + (unsigned long long)__popcll(m & lanemask_lt());
-          if (a.bout)
-            batch_store(a.bout, a.out_idx, a.out_val, a.bwx, bb, pos - shift, G.phi, z.key, z.val, a.st);
-          else if ((int64_t)pos < a.out_cap)
-            write_output(a, pos, G.phi, z.key, z.val);
-        }
-        run += (unsigned long long)__popcll(m);
-      }
-    }
-    wave_lds_fence();
-  }
-}
 
 // Ascending bitonic sort of a[0, n) in LDS (n a power of two, n <= blockDim.x),
 // one element per thread; every thread of the block must call it.
@@ -564,7 +459,9 @@ __device__ __forceinline__ void bitonic_sort_lds(unsigned long long* a, unsigned
 // spread over all threads by a search over the staged entry offsets.  Then
 // the group's outputs are counted, reserved with one atomic on the output
 // cursor, and written.
-__global__ __launch_bounds__(kBBlock) void k_group_block(GroupArgs a, const uint32_t* __restrict__ blist, int64_t nb) {
+__global__ __launch_bounds__(kBBlock) void k_group_block(GroupArgs a, const uint32_t* __restrict__ blist, int64_t nb,
+                                                         const DevStatus* dc) {
+  if (dc) nb = (int64_t)dc->n_block;  // the count read on the device
   extern __shared__ __align__(16) unsigned char s_dyn[];
   __shared__ unsigned long long s_off[kBChunk];
   __shared__ unsigned s_ys[kBChunk];
@@ -736,13 +633,25 @@ __global__ __launch_bounds__(kBBlock) void k_group_block(GroupArgs a, const uint
 constexpr int kDBlock = 256;
 constexpr int kDItemsOne = 8;    // products in flight per lane, one contraction
 constexpr int kDItemsBatch = 5;  // and in a batch (the per-contraction decode takes registers)
+constexpr int kDItemsSmall = 4;  // with the 1024-product tile option
 constexpr int kDGroups = 1024;  // groups staged per tile; more fall back to global loads
 
 // First direct group of every product-space tile: tile k's first product
 // (k * tile) lies in group tfirst[k], the nonempty group that holds it, and
 // tfirst[ntiles] = nd.  A thread per group writes the tiles starting in it.
+// With dc the group and product counts are read on the device, and tiles
+// past max_tiles (what tfirst holds) are an error.
 __global__ __launch_bounds__(256) void k_direct_tiles(const unsigned long long* __restrict__ dpos, int64_t nd,
-                                                      uint64_t tile, uint64_t ntiles, uint32_t* __restrict__ tfirst) {
+                                                      uint64_t tile, uint64_t ntiles, uint32_t* __restrict__ tfirst,
+                                                      DevStatus* dc, uint64_t max_tiles) {
+  if (dc) {
+    nd = (int64_t)dc->n_direct;
+    ntiles = (dc->direct_products + tile - 1) / tile;
+    if (ntiles > max_tiles) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) record_error(dc, kErrCapacity);
+      ntiles = max_tiles;
+    }
+  }
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nd; i += (int64_t)gridDim.x * blockDim.x) {
     const uint64_t lo = dpos[i], hi = dpos[i + 1];
     for (uint64_t k = (lo + tile - 1) / tile; k < ntiles && k * tile < hi; ++k) tfirst[k] = (uint32_t)i;
@@ -753,8 +662,15 @@ __global__ __launch_bounds__(256) void k_direct_tiles(const unsigned long long* 
 template <bool BATCH, int kDItems>
 __global__ __launch_bounds__(kDBlock) void k_group_direct(GroupArgs a, const uint32_t* __restrict__ dlist,
                                                           const unsigned long long* __restrict__ dpos, int64_t nd,
-                                                          uint64_t nprod, const uint32_t* __restrict__ tfirst) {
+                                                          uint64_t nprod, const uint32_t* __restrict__ tfirst,
+                                                          const DevStatus* dc, uint64_t max_tiles) {
   constexpr int kDTile = kDBlock * kDItems;
+  if (dc) {  // counts read on the device; tfirst holds max_tiles tiles
+    nd = (int64_t)dc->n_direct;
+    nprod = dc->direct_products;
+    if (nprod > max_tiles * (uint64_t)kDTile) nprod = max_tiles * (uint64_t)kDTile;
+  }
+  if (nd <= 0) return;
   __shared__ unsigned long long s_pos[kDGroups + 1];
   __shared__ unsigned long long s_phi[kDGroups];
   __shared__ double s_v[kDGroups];
@@ -976,20 +892,7 @@ __global__ __launch_bounds__(kBBlock) void k_sort_y_runs(const YSlot* __restrict
   }
 }
 
-struct ListScanOp {
-  const uint32_t* gn;
-  const uint32_t* wlist;
-  unsigned long long* goff;
-  uint64_t base;
-  __device__ unsigned long long get(int64_t i) const { return gn[wlist[i]]; }
-  __device__ void put(int64_t i, unsigned long long excl, unsigned long long) const { goff[wlist[i]] = base + excl; }
-};
 
-struct FinOutBase {
-  DevStatus* st;
-  uint64_t base;
-  __device__ void operator()(unsigned long long total) const { st->out_base = base + total; }
-};
 
 __global__ void k_finalize(int64_t* out_nnz, int64_t out_cap, DevStatus* st) {
   const unsigned long long total = st->out_base;
@@ -1001,9 +904,16 @@ __global__ void k_finalize(int64_t* out_nnz, int64_t out_cap, DevStatus* st) {
   *out_nnz = err ? -(int64_t)status_of(err) : (int64_t)total;
 }
 
-__global__ void k_reset_status(DevStatus* st) {
+// Start of an execution: no error yet; outputs placed by the output cursor
+// follow the direct class's (which take [0, direct products)); the work
+// queues start over.
+__global__ void k_reset_status(DevStatus* st, LdsQueue* q) {
   st->err = 0u;
-  st->out_base = 0ull;
+  st->out_base = st->direct_products;
+  if (q) {
+    for (int s = 0; s < kSlices; ++s) q->next_tile[s] = 0ull;
+    q->next_wave = 0ull;
+  }
 }
 
 // Inspection: X groups -> (free coordinates, entry count, product count).
@@ -1082,8 +992,9 @@ hipError_t launch_scan_entries(const XRec* xr, int64_t n, unsigned long long* eo
 hipError_t launch_classify(const GroupRec* groups, int64_t max_groups, const unsigned long long* eoff,
                            uint64_t ycells, int32_t dense, uint32_t* dlist, uint32_t* wlist, uint32_t* blist,
                            uint32_t* glist, unsigned long long* dpos, void* tile_sums, DevStatus* st,
-                           hipStream_t stream) {
-  return device_scan(ClassifyOp{groups, eoff, st, ycells, dense, dlist, wlist, blist, glist, dpos}, max_groups,
+                           hipStream_t stream, int32_t block_cap) {
+  const unsigned long long cap = block_cap > 0 && block_cap < kBlockCap ? (unsigned long long)block_cap : kBlockCap;
+  return device_scan(ClassifyOp{groups, eoff, st, ycells, dense, dlist, wlist, blist, glist, dpos, cap}, max_groups,
                      tile_sums, FinClassify{st}, stream);
 }
 
@@ -1095,28 +1006,18 @@ hipError_t launch_scan_direct(int64_t max_groups, unsigned long long* dpos, void
 hipError_t launch_scan_global_entries(const GroupRec* groups, const uint32_t* glist, int64_t ngl,
                                       unsigned long long* gl_eoff, void* tile_sums, DevStatus* st,
                                       hipStream_t stream) {
-  return device_scan(GlobalEntryScanOp{groups, glist, gl_eoff}, ngl, tile_sums, FinGlobalEntries{st}, stream);
+  return device_scan(GlobalEntryScanOp{groups, glist, gl_eoff, st}, ngl, tile_sums, FinGlobalEntries{st}, stream);
 }
 
 hipError_t launch_gather_global(const GroupRec* groups, const uint32_t* glist, int64_t ngl,
                                 const unsigned long long* gl_eoff, const XRec* xr, XEntry* xrec, uint32_t* xg,
-                                uint32_t* xcnt, int num_cus, hipStream_t stream) {
+                                uint32_t* xcnt, int num_cus, hipStream_t stream, const DevStatus* dc) {
   if (ngl <= 0) return hipSuccess;
   k_gather_global<<<grid_for(ngl * 64, 256, num_cus), 256, 0, stream>>>(groups, glist, ngl, gl_eoff, xr, xrec, xg,
-                                                                         xcnt);
+                                                                         xcnt, dc);
   return hipGetLastError();
 }
 
-hipError_t launch_group_wave(const GroupArgs& a, const uint32_t* wlist, int64_t nw, int fill, int num_cus,
-                             hipStream_t stream) {
-  if (nw <= 0) return hipSuccess;
-  const unsigned grid = grid_for(nw * 64, kGBlock, num_cus, 8);
-  if (fill)
-    k_group_wave<true><<<grid, kGBlock, 0, stream>>>(a, wlist, nw);
-  else
-    k_group_wave<false><<<grid, kGBlock, 0, stream>>>(a, wlist, nw);
-  return hipGetLastError();
-}
 
 // Dynamic LDS of the block class: a kBlockSlots-slot hash of 16-byte slots,
 // or (dense) up to kCoMaxGroups arrays of `cells` doubles plus bitmaps
@@ -1127,39 +1028,45 @@ hipError_t prepare_group_block() {
 }
 
 hipError_t launch_group_block(const GroupArgs& a, const uint32_t* blist, int64_t nb, int num_cus,
-                              hipStream_t stream) {
+                              hipStream_t stream, const DevStatus* dc) {
   if (nb <= 0) return hipSuccess;
   unsigned grid = grid_for(nb * kBBlock, kBBlock, num_cus, 2);
   if (grid >= kXcds) grid -= grid % kXcds;
-  k_group_block<<<grid, kBBlock, kBlockHashLds, stream>>>(a, blist, nb);
+  k_group_block<<<grid, kBBlock, kBlockHashLds, stream>>>(a, blist, nb, dc);
   return hipGetLastError();
 }
 
 int64_t direct_tile_bound(uint64_t nprod) {
-  const uint64_t tile = (uint64_t)kDBlock * (kDItemsBatch < kDItemsOne ? kDItemsBatch : kDItemsOne);
+  const uint64_t tile = (uint64_t)kDBlock * kDItemsSmall;  // the smallest tile
   return (int64_t)((nprod + tile - 1) / tile) + 1;
 }
 
 hipError_t launch_group_direct(const GroupArgs& a, const uint32_t* dlist, const unsigned long long* dpos, int64_t nd,
-                               uint64_t nprod, uint32_t* tfirst, int num_cus, hipStream_t stream) {
+                               uint64_t nprod, uint32_t* tfirst, int num_cus, hipStream_t stream, int tile_products,
+                               DevStatus* dc, int64_t tfirst_slots) {
   if (nd <= 0 || nprod == 0) return hipSuccess;
   if (nd >= (int64_t)UINT32_MAX) return hipErrorInvalidValue;
-  const int items = a.bout ? kDItemsBatch : kDItemsOne;
+  const bool small = tile_products == (int)(kDBlock * kDItemsSmall);
+  const int items = small ? kDItemsSmall : (a.bout ? kDItemsBatch : kDItemsOne);
   const uint64_t tile = (uint64_t)kDBlock * items, tiles = (nprod + tile - 1) / tile;
-  k_direct_tiles<<<grid_for(nd, 256, num_cus, 8), 256, 0, stream>>>(dpos, nd, tile, tiles, tfirst);
+  const uint64_t max_tiles = dc ? (uint64_t)(tfirst_slots > 1 ? tfirst_slots - 1 : 0) : tiles;
+  k_direct_tiles<<<grid_for(nd, 256, num_cus, 8), 256, 0, stream>>>(dpos, nd, tile, tiles, tfirst, dc, max_tiles);
   uint64_t g = (uint64_t)num_cus * 8;
   if (g > tiles) g = tiles;
-  if (a.bout)
-    k_group_direct<true, kDItemsBatch><<<dim3((unsigned)g), kDBlock, 0, stream>>>(a, dlist, dpos, nd, nprod, tfirst);
+#define D_LAUNCH(B, I) \
+  k_group_direct<B, I><<<dim3((unsigned)g), kDBlock, 0, stream>>>(a, dlist, dpos, nd, nprod, tfirst, dc, max_tiles)
+  if (a.bout && small)
+    D_LAUNCH(true, kDItemsSmall);
+  else if (a.bout)
+    D_LAUNCH(true, kDItemsBatch);
+  else if (small)
+    D_LAUNCH(false, kDItemsSmall);
   else
-    k_group_direct<false, kDItemsOne><<<dim3((unsigned)g), kDBlock, 0, stream>>>(a, dlist, dpos, nd, nprod, tfirst);
+    D_LAUNCH(false, kDItemsOne);
+#undef D_LAUNCH
   return hipGetLastError();
 }
 
-hipError_t launch_scan_group_counts(const uint32_t* gn, const uint32_t* wlist, int64_t nw, uint64_t base,
-                                    unsigned long long* goff, void* tile_sums, DevStatus* st, hipStream_t stream) {
-  return device_scan(ListScanOp{gn, wlist, goff, base}, nw, tile_sums, FinOutBase{st, base}, stream);
-}
 
 hipError_t launch_sort_y_runs(const YSlot* ytab, int64_t nslots, YEntry* yg, int64_t ny, uint16_t* ykey16,
                               double* yval, unsigned* colbits, DevStatus* st, bool sort, int num_cus,
@@ -1181,8 +1088,8 @@ hipError_t launch_finalize(int64_t* out_nnz, int64_t out_cap, DevStatus* st, hip
   return hipGetLastError();
 }
 
-hipError_t launch_reset_status(DevStatus* st, hipStream_t stream) {
-  k_reset_status<<<1, 1, 0, stream>>>(st);
+hipError_t launch_reset_status(DevStatus* st, LdsQueue* q, hipStream_t stream) {
+  k_reset_status<<<1, 1, 0, stream>>>(st, q);
   return hipGetLastError();
 }
 

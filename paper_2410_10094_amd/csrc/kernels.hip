@@ -153,18 +153,24 @@ __global__ __launch_bounds__(256) void k_x_probe(const int32_t* __restrict__ xid
   }
 }
 
+// live_n (when given): the number of entries in use, counted on the device.
 struct ProductScanOp {
   const uint32_t* xcnt;
   unsigned long long* poff;
+  const unsigned long long* live_n;
+  __device__ int64_t live(int64_t n) const { return live_n ? (int64_t)*live_n : n; }
   __device__ unsigned long long get(int64_t i) const { return xcnt[i]; }
   __device__ void put(int64_t i, unsigned long long excl, unsigned long long) const { poff[i] = excl; }
 };
 
 struct FinProducts {
-  unsigned long long* poff_end;
+  unsigned long long* poff;
+  int64_t n;
+  const unsigned long long* live_n;
   unsigned long long* total_out;
   __device__ void operator()(unsigned long long total) const {
-    *poff_end = total;
+    const int64_t m = live_n && (int64_t)*live_n < n ? (int64_t)*live_n : n;
+    poff[m] = total;
     *total_out = total;
   }
 };
@@ -203,9 +209,13 @@ __global__ __launch_bounds__(kExpBlock) void k_expand_acc(const unsigned long lo
                                                           const uint32_t* __restrict__ xg,
                                                           const YEntry* __restrict__ yg, int64_t ny, int32_t bits_y,
                                                           ZSlot* __restrict__ tab, uint64_t mask, uint64_t seed,
-                                                          int32_t max_probe, uint64_t products, DevStatus* st) {
+                                                          int32_t max_probe, uint64_t products, DevStatus* st,
+                                                          const unsigned long long* dnx,
+                                                          const unsigned long long* dprod) {
   __shared__ unsigned long long s_poff[kExpTile + 1];
   __shared__ int64_t s_range[2];
+  if (dnx && (int64_t)*dnx < nx) nx = (int64_t)*dnx;  // counts read on the device (bounded by the host's)
+  if (dprod) products = *dprod;
   const uint64_t ntiles = (products + kExpTile - 1) / kExpTile;
   for (uint64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const uint64_t p0 = t * kExpTile;
@@ -634,20 +644,23 @@ hipError_t launch_x_probe(const int32_t* xidx, const double* xval, int64_t nnz, 
 }
 
 hipError_t launch_scan_products(const uint32_t* xcnt, int64_t n, unsigned long long* poff,
-                                unsigned long long* tile_sums, unsigned long long* total, hipStream_t stream) {
-  return device_scan(ProductScanOp{xcnt, poff}, n, tile_sums, FinProducts{poff + n, total}, stream);
+                                unsigned long long* tile_sums, unsigned long long* total, hipStream_t stream,
+                                const unsigned long long* live_n) {
+  return device_scan(ProductScanOp{xcnt, poff, live_n}, n, tile_sums, FinProducts{poff, n, live_n, total}, stream);
 }
 
 hipError_t launch_expand_acc(const unsigned long long* poff, int64_t nx, const XEntry* xrec, const uint32_t* xg,
                              const YEntry* yg, int64_t ny, int32_t bits_y, ZSlot* tab, uint64_t mask, uint64_t seed,
                              int32_t max_probe, uint64_t products, DevStatus* st, int num_cus,
-                             hipStream_t stream) {
-  if (products == 0) return hipSuccess;
-  const uint64_t tiles = (products + kExpTile - 1) / kExpTile;
+                             hipStream_t stream, const unsigned long long* dnx, const unsigned long long* dprod) {
+  if (!dprod && products == 0) return hipSuccess;
+  // with device counts the grid is the persistent one; tiles past the
+  // device's product count are skipped
+  const uint64_t tiles = dprod ? ~0ull : (products + kExpTile - 1) / kExpTile;
   uint64_t g = (uint64_t)num_cus * 8;
   if (g > tiles) g = tiles;
   k_expand_acc<<<dim3((unsigned)g), dim3(kExpBlock), 0, stream>>>(poff, nx, xrec, xg, yg, ny, bits_y, tab, mask,
-                                                                   seed, max_probe, products, st);
+                                                                   seed, max_probe, products, st, dnx, dprod);
   return hipGetLastError();
 }
 

@@ -310,6 +310,8 @@ struct sptc_plan_s : Workspace {
   MfmaPlan mplan{};
   bool in_batch = false;      // the packed plan of a batch
   bool stalled = false;       // a read-back timed out: the stream still holds the plan's work
+  bool capture = false;       // no read-back (opt.capture_out_cap > 0): counts stay on the device
+  int64_t dtfirst_slots = 0;  // entries of the direct class's tile table
   bool pageable_readback = false;  // read counts back through pageable memory (no pinned buffer)
   bool block_surveyed = false;  // the block survey ran (dense Y free key, one contraction)
   int32_t block_nonfinite = 0;  // an X or Y value is not finite (the matrix cores need finite values)
@@ -319,10 +321,8 @@ struct sptc_plan_s : Workspace {
   double* yval = nullptr;
   unsigned long long* yset = nullptr;
   int64_t yset_slots = 0;
-  uint32_t* gn = nullptr;
-  unsigned long long* goff = nullptr;
+  LdsQueue* queue = nullptr;   // work queue counters of the persistent launch (grouped mode)
   unsigned long long* gl_eoff = nullptr;
-  unsigned long long* etile_sums = nullptr;
   int64_t x_groups = 0, nd = 0, nw = 0, nb = 0, ngl = 0;
   int64_t direct_products = 0;
   int32_t ydup = 0;
@@ -408,6 +408,11 @@ sptc_status check_options(const sptc_options& o) {
   if (o.out_table_slots != 0 && (o.out_table_slots < 2 || (o.out_table_slots & (o.out_table_slots - 1))))
     return fail(SPTC_ERR_INVALID_ARG, "out_table_slots %lld is not a power of two >= 2",
                 (long long)o.out_table_slots);
+  if (o.tile != 0 && o.tile != 1024 && o.tile != 2048)
+    return fail(SPTC_ERR_INVALID_ARG, "tile %d is not 0, 1024 or 2048", o.tile);
+  if (o.lds_max_keys != 0 && (o.lds_max_keys < 64 || o.lds_max_keys > kBlockCap))
+    return fail(SPTC_ERR_INVALID_ARG, "lds_max_keys %d outside 64..%d", o.lds_max_keys, kBlockCap);
+  if (o.capture_out_cap < 0) return fail(SPTC_ERR_INVALID_ARG, "capture_out_cap < 0");
   return SPTC_OK;
 }
 
@@ -588,12 +593,17 @@ sptc_status plan_global(sptc_plan_s* P, const sptc_coo* X) {
   HIP_TRY(mark(P, s, SPTC_STAGE_P_SCAN, 0));
   HIP_TRY(launch_scan_products(P->xcnt, P->nx, P->poff, P->tile_sums, &P->st->products, s));
   HIP_TRY(mark(P, s, SPTC_STAGE_P_SCAN, 1));
+  P->expand_nx = P->nx;
+  if (P->capture) {  // no read-back: the product count stays on the device
+    P->products = P->y_groups = P->expand_products = -1;
+    P->out_bound = std::min<int64_t>(P->opt.capture_out_cap, out_cells(P));
+    return size_out_table(P, P->out_bound);
+  }
   DevStatus host{};
   if ((st = read_status(P, &host))) return st;
   P->products = (int64_t)host.products;
   P->y_groups = (int64_t)host.groups;
   P->out_bound = std::min<int64_t>(P->products, out_cells(P));
-  P->expand_nx = P->nx;
   P->expand_products = P->products;
   return size_out_table(P, P->products);
 }
@@ -718,7 +728,7 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
   // scans a single tile
   const int64_t max_groups = std::min<int64_t>(P->nx, P->xtab_slots);
   HIP_TRY(launch_classify(P->groups, max_groups, P->eoff, P->ycells, P->dense, P->dlist, P->wlist, P->blist,
-                          P->glist, P->dpos, P->tile_sums, P->st, s));
+                          P->glist, P->dpos, P->tile_sums, P->st, s, P->opt.lds_max_keys));
   HIP_TRY(launch_scan_direct(max_groups, P->dpos, P->tile_sums, P->st, s));
   // the block class's products and finiteness, read back with the counts
   // below, decide the matrix-core class with no read-back of its own
@@ -728,24 +738,39 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
   HIP_TRY(mark(P, s, SPTC_STAGE_P_SCAN, 1));
 
   DevStatus host{};
-  if ((st = read_status(P, &host))) return st;
-  P->products = (int64_t)host.products;
-  P->y_groups = (int64_t)host.groups;
-  P->out_bound = std::min<int64_t>(P->products, out_cells(P));
-  P->x_groups = (int64_t)host.xgroups;
-  P->nd = (int64_t)(host.class_lo & 0xffffffffull);
-  P->nw = (int64_t)(host.class_lo >> 32);
-  P->nb = (int64_t)host.class_hi;
-  P->ngl = P->x_groups - P->nd - P->nw - P->nb;
-  P->direct_products = (int64_t)host.direct_products;
-  P->ydup = host.ydup ? 1 : 0;
-  P->ycols = host.ycols;
-  P->block_products = (int64_t)host.block_products;
-  P->block_nonfinite = host.nonfinite ? 1 : 0;
-  if (P->ngl < 0) return fail(SPTC_ERR_INTERNAL, "group classes do not add up");
-  if (P->nd > 0 && P->direct_products > 0 &&
-      (st = P->allocate_n(direct_tile_bound((uint64_t)P->direct_products), &P->dtfirst)))
-    return st;
+  if (P->capture) {
+    // no read-back: every count stays on the device and the host keeps
+    // upper bounds (each class at most every group, the direct class's
+    // products at most the outputs); the launches read the counts
+    P->products = P->y_groups = -1;
+    P->out_bound = std::min<int64_t>(P->opt.capture_out_cap, out_cells(P));
+    P->x_groups = P->nd = P->nw = P->nb = P->ngl = max_groups;
+    P->direct_products = P->out_bound;
+    P->ydup = 1;
+    P->ycols = 0;
+    P->block_products = 0;
+    P->block_nonfinite = 1;
+  } else {
+    if ((st = read_status(P, &host))) return st;
+    P->products = (int64_t)host.products;
+    P->y_groups = (int64_t)host.groups;
+    P->out_bound = std::min<int64_t>(P->products, out_cells(P));
+    P->x_groups = (int64_t)host.xgroups;
+    P->nd = (int64_t)(host.class_lo & 0xffffffffull);
+    P->nw = (int64_t)(host.class_lo >> 32);
+    P->nb = (int64_t)host.class_hi;
+    P->ngl = P->x_groups - P->nd - P->nw - P->nb;
+    P->direct_products = (int64_t)host.direct_products;
+    P->ydup = host.ydup ? 1 : 0;
+    P->ycols = host.ycols;
+    P->block_products = (int64_t)host.block_products;
+    P->block_nonfinite = host.nonfinite ? 1 : 0;
+    if (P->ngl < 0) return fail(SPTC_ERR_INTERNAL, "group classes do not add up");
+  }
+  if (P->nd > 0 && P->direct_products > 0) {
+    P->dtfirst_slots = direct_tile_bound((uint64_t)P->direct_products);
+    if ((st = P->allocate_n(P->dtfirst_slots, &P->dtfirst))) return st;
+  }
   if (P->nb > 0) {
     HIP_TRY(prepare_group_block());
     if (P->dense) {
@@ -761,14 +786,14 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
         const unsigned cells = dense_cells(P->bits_fy);
         HIP_TRY(launch_sort_y_runs(P->ytab, P->ytab_slots, P->yg, P->ny, P->ykey16, P->yval, nullptr, P->st, true,
                                    P->num_cus, s, P->yso, runslot, (unsigned)__builtin_ctz(cells / kSlices)));
-        HIP_TRY(launch_block_runslots(P->groups, P->blist, P->nb, P->xr, runslot, P->ny, P->st, P->num_cus, s));
+        HIP_TRY(launch_block_runslots(P->groups, P->blist, P->nb, P->xr, runslot, P->ny, P->st, P->num_cus, s,
+                                      P->capture ? P->st : nullptr));
       }
       HIP_TRY(mark(P, s, SPTC_STAGE_X_SORT, 1));
     }
   }
-  if ((st = P->allocate_n(P->x_groups, &P->gn))) return st;
-  if ((st = P->allocate_n(P->x_groups, &P->goff))) return st;
-  if ((st = P->allocate_n(scan_tiles(P->nw) + 1, &P->etile_sums))) return st;
+  if ((st = P->allocate_n(1, &P->queue))) return st;
+  HIP_TRY(prepare_lds_queue());
   if (P->ngl == 0) return SPTC_OK;
 
   // The global class keys its table by (place in glist << Y free bits) | Y free key.
@@ -777,15 +802,24 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
                 (long long)P->ngl, P->bits_fy);
   if ((st = P->allocate_n(P->ngl, &P->gl_eoff))) return st;
   HIP_TRY(launch_scan_global_entries(P->groups, P->glist, P->ngl, P->gl_eoff, P->tile_sums, P->st, s));
-  if ((st = read_status(P, &host))) return st;
-  P->expand_nx = (int64_t)host.global_entries;
+  if (P->capture) {
+    P->expand_nx = P->nx;  // the global class's entries, at most all of X
+  } else {
+    if ((st = read_status(P, &host))) return st;
+    P->expand_nx = (int64_t)host.global_entries;
+  }
   if ((st = P->allocate_n(P->expand_nx, &P->xrec))) return st;
   if ((st = P->allocate_n(P->expand_nx, &P->xg))) return st;
   if ((st = P->allocate_n(P->expand_nx, &P->xcnt))) return st;
   if ((st = P->allocate_n(P->expand_nx + 1, &P->poff))) return st;
   HIP_TRY(launch_gather_global(P->groups, P->glist, P->ngl, P->gl_eoff, P->xr, P->xrec, P->xg, P->xcnt, P->num_cus,
-                               s));
-  HIP_TRY(launch_scan_products(P->xcnt, P->expand_nx, P->poff, P->tile_sums, &P->st->global_products, s));
+                               s, P->capture ? P->st : nullptr));
+  HIP_TRY(launch_scan_products(P->xcnt, P->expand_nx, P->poff, P->tile_sums, &P->st->global_products, s,
+                               P->capture ? &P->st->global_entries : nullptr));
+  if (P->capture) {
+    P->expand_products = -1;
+    return size_out_table(P, P->out_bound);  // the class's distinct outputs are outputs
+  }
   if ((st = read_status(P, &host))) return st;
   P->expand_products = (int64_t)host.global_products;
   return size_out_table(P, P->expand_products);
@@ -830,7 +864,7 @@ sptc_status plan_body(sptc_plan_s* P, const sptc_coo* X, const sptc_coo* Y, cons
     if ((st = P->allocate_n(P->ny, &P->ykey16))) return st;
     if ((st = P->allocate_n(P->ny, &P->yval))) return st;
     if ((st = P->allocate_n(kCellWords, &P->ycolbits))) return st;
-    HIP_TRY(hipMemsetAsync(P->ycolbits, 0, sizeof(unsigned) * kCellWords, P->stream));
+    HIP_TRY(launch_zero_u64(reinterpret_cast<unsigned long long*>(P->ycolbits), kCellWords / 2, P->stream));
   }
   const int64_t tiles = std::max<int64_t>({scan_tiles(P->ytab_slots), scan_tiles(P->xtab_slots), scan_tiles(P->nx)});
   if ((st = P->allocate_n(2 * (tiles + 1), &P->tile_sums))) return st;  // room for pair-valued scans
@@ -845,7 +879,8 @@ sptc_status plan_body(sptc_plan_s* P, const sptc_coo* X, const sptc_coo* Y, cons
   if ((st = P->allocate_n(1, &P->st))) return st;
   if ((st = P->allocate_n(1, &P->agg_total))) return st;
   if ((st = P->allocate_n(2, &P->readback))) return st;
-  HIP_TRY(hipMemsetAsync(P->st, 0, sizeof(DevStatus), P->stream));
+  static_assert(sizeof(DevStatus) % 8 == 0, "DevStatus is cleared in 8-byte words");
+  HIP_TRY(launch_zero_u64(reinterpret_cast<unsigned long long*>(P->st), sizeof(DevStatus) / 8, P->stream));
   if ((st = plan_group_y(P, Y))) return st;
   return grouped ? plan_grouped(P, X) : plan_global(P, X);
 }
@@ -929,6 +964,10 @@ sptc_status plan_create(sptc_plan_t* plan, const sptc_coo* X, const sptc_coo* Y,
   if ((st = check_options(o))) return st;
   if (alloc && (!alloc->alloc || !alloc->release))
     return fail(SPTC_ERR_INVALID_ARG, "allocator must provide alloc and release");
+  if (o.capture_out_cap > 0 && !alloc)
+    return fail(SPTC_ERR_INVALID_ARG, "capture_out_cap needs a caller allocator (the plan must not allocate from "
+                                      "the stream's pool inside a graph capture)");
+  if (o.capture_out_cap > 0 && br) return fail(SPTC_ERR_INVALID_ARG, "capture_out_cap is not for batches");
   Layout L;
   make_layout(X, Y, ncontract, cx, cy, o.validate, &L);
   if ((st = check_key_widths(L, o.mode))) return st;
@@ -941,6 +980,8 @@ sptc_status plan_create(sptc_plan_t* plan, const sptc_coo* X, const sptc_coo* Y,
   if (!P) return fail(SPTC_ERR_OUT_OF_MEMORY, "host allocation failed");
   P->opt = o;
   P->in_batch = br != nullptr;
+  P->capture = o.capture_out_cap > 0;
+  if (P->capture) P->opt.block_mfma = 0;
   P->pageable_readback = pageable_readback;
   P->stream = static_cast<hipStream_t>(stream);
   if (alloc) {
@@ -1017,7 +1058,8 @@ sptc_status execute_plan(sptc_plan_s* P, int32_t* out_idx, double* out_val, int6
                          hipStream_t s, const BatchExec* bx) {
   if (bx) out_cap = INT64_MAX;  // capacity is checked per contraction
   if (P->opt.mode == SPTC_MODE_GROUPED) {
-    HIP_TRY(launch_reset_status(P->st, s));
+    HIP_TRY(launch_reset_status(P->st, P->queue, s));
+    if (bx) HIP_TRY(launch_batch_reset(bx->count, bx->bseg, s));
     GroupArgs a{};
     a.groups = P->groups;
     a.xr = P->xr;
@@ -1031,8 +1073,6 @@ sptc_status execute_plan(sptc_plan_s* P, int32_t* out_idx, double* out_val, int6
     a.bits_y = P->bits_fy;
     a.ux = P->ux;
     a.uy = P->uy;
-    a.gn = P->gn;
-    a.goff = P->goff;
     a.out_idx = out_idx;
     a.out_val = out_val;
     a.out_cap = out_cap;
@@ -1042,26 +1082,24 @@ sptc_status execute_plan(sptc_plan_s* P, int32_t* out_idx, double* out_val, int6
       a.bseg = bx->bseg;
       a.bwx = bx->bwx;
     }
-    HIP_TRY(mark(P, s, SPTC_STAGE_GROUP_COUNT, 0));
-    HIP_TRY(launch_group_wave(a, P->wlist, P->nw, 0, P->num_cus, s));
-    HIP_TRY(mark(P, s, SPTC_STAGE_GROUP_COUNT, 1));
-    HIP_TRY(mark(P, s, SPTC_STAGE_GROUP_FILL, 0));
-    HIP_TRY(launch_scan_group_counts(P->gn, P->wlist, P->nw, (uint64_t)P->direct_products, P->goff, P->etile_sums,
-                                     P->st, s));
-    if (bx) HIP_TRY(launch_batch_bases(P->wlist, P->gn, P->goff, bx->count, bx->bseg, s));
-    HIP_TRY(launch_group_wave(a, P->wlist, P->nw, 1, P->num_cus, s));
-    HIP_TRY(mark(P, s, SPTC_STAGE_GROUP_FILL, 1));
     HIP_TRY(mark(P, s, SPTC_STAGE_DIRECT, 0));
-    HIP_TRY(launch_group_direct(a, P->dlist, P->dpos, P->nd, (uint64_t)P->direct_products, P->dtfirst, P->num_cus, s));
+    HIP_TRY(launch_group_direct(a, P->dlist, P->dpos, P->nd, (uint64_t)P->direct_products, P->dtfirst, P->num_cus, s,
+                                P->opt.tile, P->capture ? P->st : nullptr, P->dtfirst_slots));
     HIP_TRY(mark(P, s, SPTC_STAGE_DIRECT, 1));
     HIP_TRY(mark(P, s, SPTC_STAGE_BLOCK, 0));
+    // the dense block class's tiles and the wave class's groups: one
+    // persistent launch over the device work queue
+    const int tiles = P->dense && !P->block_mfma && P->nb > 0;
+    // Y runs: read back, or (no read-back) what the Y table can hold at its load factor
+    const int64_t runs = P->y_groups > 0 ? P->y_groups
+                                         : std::max<int64_t>(1, std::min<int64_t>(P->ny, (int64_t)(P->ytab_slots *
+                                                                                                  P->opt.load_factor)));
+    HIP_TRY(launch_lds_queue(a, P->blist, P->wlist, P->yso, P->ytab_slots, dense_cells(P->bits_fy), tiles, P->nw > 0,
+                             (double)P->ny / (double)runs / kSlices, P->queue, P->num_cus, s));
     if (P->block_mfma)
       HIP_TRY(launch_group_block_mfma(a, P->blist, P->nb, P->mplan, P->num_cus, s));
-    else
-      HIP_TRY(P->dense ? launch_group_block_sliced(a, P->blist, P->nb, P->yso, P->ytab_slots, dense_cells(P->bits_fy),
-                                                    (double)P->ny / (double)std::max<int64_t>(P->y_groups, 1) / kSlices,
-                                                    P->num_cus, s)
-                       : launch_group_block(a, P->blist, P->nb, P->num_cus, s));
+    else if (!P->dense)
+      HIP_TRY(launch_group_block(a, P->blist, P->nb, P->num_cus, s, P->capture ? P->st : nullptr));
     HIP_TRY(mark(P, s, SPTC_STAGE_BLOCK, 1));
     if (P->ngl == 0) {
       HIP_TRY(mark(P, s, SPTC_STAGE_COMPACT, 0));
@@ -1079,8 +1117,13 @@ sptc_status execute_plan(sptc_plan_s* P, int32_t* out_idx, double* out_val, int6
   HIP_TRY(launch_fill_empty(P->ztab, P->ztab_slots, grouped ? nullptr : P->st, s));
   HIP_TRY(mark(P, s, SPTC_STAGE_OUT_CLEAR, 1));
   HIP_TRY(mark(P, s, SPTC_STAGE_EXPAND, 0));
+  // without read-backs the entry and product counts are read on the device
+  const unsigned long long* dnx = P->capture && grouped ? &P->st->global_entries : nullptr;
+  const unsigned long long* dprod =
+      P->capture ? (grouped ? &P->st->global_products : &P->st->products) : nullptr;
   HIP_TRY(launch_expand_acc(P->poff, P->expand_nx, P->xrec, P->xg, P->yg, P->ny, P->bits_fy, P->ztab, zmask,
-                            P->opt.hash_seed, P->max_probe_z, (uint64_t)P->expand_products, P->st, P->num_cus, s));
+                            P->opt.hash_seed, P->max_probe_z, (uint64_t)P->expand_products, P->st, P->num_cus, s,
+                            dnx, dprod));
   HIP_TRY(mark(P, s, SPTC_STAGE_EXPAND, 1));
   HIP_TRY(mark(P, s, SPTC_STAGE_COMPACT, 0));
   if (grouped) {
@@ -1262,8 +1305,7 @@ sptc_status batch_body(sptc_batch_s* B, const sptc_coo* X, const sptc_coo* Y, co
   if ((st = B->allocate_n(count, &B->seg))) return st;
   if ((st = B->allocate_n(1, &B->tnnz))) return st;
   HIP_TRY(hipMemcpyAsync(B->outs, outs.data(), sizeof(BatchOut) * count, hipMemcpyHostToDevice, s));
-  HIP_TRY(launch_batch_segments(inner->groups, inner->dlist, inner->nd, inner->dpos, inner->wlist, inner->nw, wx, count,
-                                B->seg, s));
+  HIP_TRY(launch_batch_segments(inner->groups, inner->dlist, inner->nd, inner->dpos, wx, count, B->seg, s));
   HIP_TRY(mark_events(o.stage_events, s, SPTC_STAGE_BATCH_SEGMENTS, 1));
   HIP_TRY(hipStreamSynchronize(s));  // host arrays above are copied before they go out of scope
   return SPTC_OK;
@@ -1333,6 +1375,9 @@ void sptc_default_options(sptc_options* opt) {
   opt->stage_events = nullptr;
   opt->mode = SPTC_MODE_GROUPED;
   opt->block_mfma = 0;
+  opt->tile = 0;
+  opt->lds_max_keys = 0;
+  opt->capture_out_cap = 0;
 }
 
 sptc_status sptc_plan(sptc_plan_t* plan, const sptc_coo* X, const sptc_coo* Y, int32_t ncontract, const int32_t* cx,

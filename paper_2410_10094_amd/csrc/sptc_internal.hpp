@@ -138,6 +138,7 @@ struct alignas(16) DevStatus {
   unsigned long long global_products;  // their products
   unsigned long long out_base;         // output cursor: outputs placed so far
   unsigned long long block_products;   // products of the block class (block survey)
+  unsigned long long n_direct, n_wave, n_block, n_global;  // groups per class (grouped path)
   unsigned int err;                    // kErr* bits
   unsigned int ydup;                   // nonzero: Y holds a repeated coordinate
   unsigned int ycols;                  // dense Y free key: distinct Y free cells that occur
@@ -236,13 +237,18 @@ hipError_t launch_x_probe(const int32_t* xidx, const double* xval, int64_t nnz, 
                           uint32_t* xg, uint32_t* xcnt, DevStatus* st, int num_cus, hipStream_t stream);
 
 // poff[i] = sum of xcnt[0..i), poff[n] = total, and the total also into *total.
+// live_n (device, optional): only the first *live_n <= n entries are in use.
 hipError_t launch_scan_products(const uint32_t* xcnt, int64_t n, unsigned long long* poff,
-                                unsigned long long* tile_sums, unsigned long long* total, hipStream_t stream);
+                                unsigned long long* tile_sums, unsigned long long* total, hipStream_t stream,
+                                const unsigned long long* live_n = nullptr);
 
+// dnx, dprod (device, optional): the X entry and product counts, read on
+// the device (nx then bounds the entries, the grid is sized without P).
 hipError_t launch_expand_acc(const unsigned long long* poff, int64_t nx, const XEntry* xrec, const uint32_t* xg,
                              const YEntry* yg, int64_t ny, int32_t bits_y, ZSlot* tab, uint64_t mask, uint64_t seed,
                              int32_t max_probe, uint64_t products, DevStatus* st, int num_cus,
-                             hipStream_t stream);
+                             hipStream_t stream, const unsigned long long* dnx = nullptr,
+                             const unsigned long long* dprod = nullptr);
 
 // Two-pass compaction of the output hash to COO, written from position
 // *base (0 when base is NULL); writes *base + nnz (or the negated status on
@@ -294,10 +300,12 @@ hipError_t launch_scan_entries(const XRec* xr, int64_t n, unsigned long long* eo
 // Sorts groups into direct / wave / block / global accumulation classes
 // (lists of group ids); counts land in st->class_lo / class_hi, and each
 // direct group's products in dpos at its place in the direct list.
+// block_cap: most distinct outputs of a group in a workgroup's LDS hash
+// (0: kBlockCap).
 hipError_t launch_classify(const GroupRec* groups, int64_t max_groups, const unsigned long long* eoff,
                            uint64_t ycells, int32_t dense, uint32_t* dlist, uint32_t* wlist, uint32_t* blist,
                            uint32_t* glist, unsigned long long* dpos, void* tile_sums, DevStatus* st,
-                           hipStream_t stream);
+                           hipStream_t stream, int32_t block_cap = 0);
 
 // In place after launch_classify: dpos[i] = products of direct-class groups
 // before list entry i; dpos[nd] and st->direct_products = their total.
@@ -310,9 +318,11 @@ hipError_t launch_scan_direct(int64_t max_groups, unsigned long long* dpos, void
 hipError_t launch_scan_global_entries(const GroupRec* groups, const uint32_t* glist, int64_t ngl,
                                       unsigned long long* gl_eoff, void* tile_sums, DevStatus* st,
                                       hipStream_t stream);
+// dc (optional): the global class's group count read on the device (ngl
+// then bounds it).
 hipError_t launch_gather_global(const GroupRec* groups, const uint32_t* glist, int64_t ngl,
                                 const unsigned long long* gl_eoff, const XRec* xr, XEntry* xrec, uint32_t* xg,
-                                uint32_t* xcnt, int num_cus, hipStream_t stream);
+                                uint32_t* xcnt, int num_cus, hipStream_t stream, const DevStatus* dc = nullptr);
 
 // Per-group accumulation in LDS.  fill = 0: count each group's outputs into
 // gn[g]; fill = 1: write them from goff[g].
@@ -329,8 +339,6 @@ struct GroupArgs {
   int32_t bits_y;
   KeyUnpack ux;  // X free key -> X free coordinates (output rows 0..)
   KeyUnpack uy;  // Y free key -> Y free coordinates (following rows)
-  uint32_t* gn;
-  const unsigned long long* goff;
   int32_t* out_idx;
   double* out_val;
   int64_t out_cap;
@@ -341,8 +349,6 @@ struct GroupArgs {
   BatchSeg* bseg;
   int32_t bwx;
 };
-hipError_t launch_group_wave(const GroupArgs& a, const uint32_t* wlist, int64_t nw, int fill, int num_cus,
-                             hipStream_t stream);
 
 // Block class, single pass: each workgroup accumulates a group, reserves its
 // outputs with one atomic on st->out_base and writes them.
@@ -350,7 +356,9 @@ hipError_t launch_group_wave(const GroupArgs& a, const uint32_t* wlist, int64_t 
 // device; called once per plan so that execute issues kernel launches only.
 hipError_t prepare_group_block();
 // Hashed block class (Y free key wider than kDenseBits).
-hipError_t launch_group_block(const GroupArgs& a, const uint32_t* blist, int64_t nb, int num_cus, hipStream_t stream);
+// dc (optional): the block-class count read on the device (nb sizes the grid).
+hipError_t launch_group_block(const GroupArgs& a, const uint32_t* blist, int64_t nb, int num_cus, hipStream_t stream,
+                              const DevStatus* dc = nullptr);
 
 // Block survey, before the class counts are read back: the block class's
 // products into st->block_products (zeroed first; the block list's length
@@ -381,13 +389,14 @@ hipError_t launch_group_block_mfma(const GroupArgs& a, const uint32_t* blist, in
 // tfirst: scratch of direct_tile_bound(nprod) u32 (each product tile's first
 // group, found first by a pass over the groups).
 int64_t direct_tile_bound(uint64_t nprod);
+// dc (optional): the direct class's group and product counts read on the
+// device (nd and nprod then size the grids; tfirst holds tfirst_slots
+// entries, and more tiles than that are a capacity error).
+// tile_products: 1024 for the small tile, else the default (2048, or 1280
+// in a batch).
 hipError_t launch_group_direct(const GroupArgs& a, const uint32_t* dlist, const unsigned long long* dpos, int64_t nd,
-                               uint64_t nprod, uint32_t* tfirst, int num_cus, hipStream_t stream);
-
-// goff[g] = base + outputs of wave-list groups before g; st->out_base = base
-// + their total.
-hipError_t launch_scan_group_counts(const uint32_t* gn, const uint32_t* wlist, int64_t nw, uint64_t base,
-                                    unsigned long long* goff, void* tile_sums, DevStatus* st, hipStream_t stream);
+                               uint64_t nprod, uint32_t* tfirst, int num_cus, hipStream_t stream,
+                               int tile_products = 0, DevStatus* dc = nullptr, int64_t tfirst_slots = 0);
 
 // *out_nnz = st->out_base, or the negated status.
 hipError_t launch_finalize(int64_t* out_nnz, int64_t out_cap, DevStatus* st, hipStream_t stream);
@@ -406,29 +415,41 @@ hipError_t launch_sort_y_runs(const YSlot* ytab, int64_t nslots, YEntry* yg, int
                               hipStream_t stream, uint32_t* yso = nullptr, uint32_t* runslot = nullptr,
                               unsigned slice_shift = 0);
 
-// ---- dense block class, sliced (block_sliced.hip) ----
+// ---- persistent LDS classes (queue.hip) ----
 // The dense Y free key space is cut into kSlices slices, one per XCD: a
-// tile is (block-class group, slice), accumulated by one wave in LDS.
+// tile of the dense block class is (block-class group, slice), accumulated
+// by one wave in LDS.
 constexpr int kSlices = 8;
+
+// Work queue counters of the persistent launch, zeroed by launch_reset_status.
+struct LdsQueue {
+  unsigned long long next_tile[kSlices];  // next block-class group of each slice's queue
+  unsigned long long next_wave;           // next wave-class group
+};
 
 // Plan time: block-class X records refer to their Y run by its table slot
 // (runslot of their run start) instead of the run start.
+// dc (optional): the block-class count read on the device (nb sizes the grid).
 hipError_t launch_block_runslots(const GroupRec* groups, const uint32_t* blist, int64_t nb, XRec* xr,
                                  const uint32_t* runslot, int64_t ny, DevStatus* st, int num_cus,
-                                 hipStream_t stream);
+                                 hipStream_t stream, const DevStatus* dc = nullptr);
 
-// Dense block class: every (group, slice) tile accumulates its group's
-// products whose Y free key falls in the slice (runs cut by yso), reserves
-// its outputs with one atomic and writes them.  cells: the dense
-// accumulator size (a power of two of at least 1024 and at least 2^bits_y);
-// mean_slice_run: average entries of a run per slice (picks the lanes per
-// X entry).
-hipError_t launch_group_block_sliced(const GroupArgs& a, const uint32_t* blist, int64_t nb, const uint32_t* yso,
-                                     int64_t yso_slots, unsigned cells, double mean_slice_run, int num_cus,
-                                     hipStream_t stream);
+// Raises the persistent kernel's dynamic LDS limit on the current device.
+hipError_t prepare_lds_queue();
+
+// One persistent launch over the dense block class's (group, slice) tiles
+// (when tiles: blist, runs cut by yso) and the wave class's groups (when
+// waves: wlist); the item counts are read on the device from the plan's
+// class counts.  cells: the dense accumulator size (a power of two of at
+// least 1024 and at least 2^bits_y); mean_slice_run: average entries of a
+// run per slice (picks the lanes per X entry).  Each item reserves its
+// outputs with one atomic on the output cursor.
+hipError_t launch_lds_queue(const GroupArgs& a, const uint32_t* blist, const uint32_t* wlist, const uint32_t* yso,
+                            int64_t yso_slots, unsigned cells, int tiles, int waves, double mean_slice_run,
+                            LdsQueue* q, int num_cus, hipStream_t stream);
 
 // Clears st->err and st->out_base.
-hipError_t launch_reset_status(DevStatus* st, hipStream_t stream);
+hipError_t launch_reset_status(DevStatus* st, LdsQueue* q, hipStream_t stream);
 
 // Inspection: group g's X free coordinates ([nfx][cap]), entry count and product count.
 hipError_t launch_x_groups(const GroupRec* groups, int64_t ng, const unsigned long long* eoff, KeyUnpack ku,
@@ -477,9 +498,7 @@ struct BatchOut {
 struct BatchSeg {
   unsigned long long dshift;  // numbering of b's first direct output
   unsigned long long dcount;  // b's direct outputs
-  unsigned long long wshift;  // numbering of b's first wave output, minus dcount
-  unsigned long long cursor;
-  uint32_t wlo, whi;          // b's wave groups: wlist[wlo, whi)
+  unsigned long long cursor;  // b's next output place after its direct outputs
 };
 
 // Packed key widths: a key of w bits is stored as (key >> lo, key & (2^lo - 1)).
@@ -500,16 +519,15 @@ hipError_t launch_batch_products(const GroupRec* groups, int64_t ngroups, const 
 // Zeroes n 8-byte words.
 hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t stream);
 
-// Plan time: each contraction's direct outputs and wave groups, from the
-// contraction-ordered direct and wave lists.
+// Plan time: each contraction's direct outputs, from the contraction-ordered
+// direct list.
 hipError_t launch_batch_segments(const GroupRec* groups, const uint32_t* dlist, int64_t nd,
-                                 const unsigned long long* dpos, const uint32_t* wlist, int64_t nw, int32_t wx,
-                                 int32_t count, BatchSeg* seg, hipStream_t stream);
+                                 const unsigned long long* dpos, int32_t wx, int32_t count, BatchSeg* seg,
+                                 hipStream_t stream);
 
-// Execute time, after the wave outputs are counted and numbered: each
-// contraction's wave shift and the start of its block/global outputs.
-hipError_t launch_batch_bases(const uint32_t* wlist, const uint32_t* gn, const unsigned long long* goff, int32_t count,
-                              BatchSeg* seg, hipStream_t stream);
+// Execute time, first: each contraction's output cursor starts after its
+// direct outputs.
+hipError_t launch_batch_reset(int32_t count, BatchSeg* seg, hipStream_t stream);
 
 // out_nnz[b] = b's nnz, or the negated status when the pipeline or b's
 // region reported an error.

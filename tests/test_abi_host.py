@@ -38,6 +38,7 @@ def test_default_options():
     assert abs(o.load_factor - 1 / 1.3) < 1e-15
     assert o.validate == 1 and o.max_probe == 0 and o.out_table_slots == 0
     assert o.block_mfma == 0  # the matrix-core block class is opt-in
+    assert o.tile == 0 and o.lds_max_keys == 0 and o.capture_out_cap == 0
 
 
 def _plan(X, Y, cx, cy, opt=None):
@@ -78,6 +79,10 @@ coo.keep = []
     ("bad_mode", B.ERR_INVALID_ARG),
     ("bad_load_factor", B.ERR_INVALID_ARG),
     ("bad_table_slots", B.ERR_INVALID_ARG),
+    ("bad_tile", B.ERR_INVALID_ARG),
+    ("bad_lds_max_keys", B.ERR_INVALID_ARG),
+    ("negative_capture_out_cap", B.ERR_INVALID_ARG),
+    ("capture_without_allocator", B.ERR_INVALID_ARG),
 ])
 def test_plan_validation(case, status):
     X, Y, cx, cy, opt = coo((8, 9, 10)), coo((10, 9, 7)), [2], [0], None
@@ -119,6 +124,18 @@ def test_plan_validation(case, status):
     elif case == "bad_table_slots":
         opt = B.default_options()
         opt.out_table_slots = 100
+    elif case == "bad_tile":
+        opt = B.default_options()
+        opt.tile = 512
+    elif case == "bad_lds_max_keys":
+        opt = B.default_options()
+        opt.lds_max_keys = 5000
+    elif case == "negative_capture_out_cap":
+        opt = B.default_options()
+        opt.capture_out_cap = -1
+    elif case == "capture_without_allocator":
+        opt = B.default_options()
+        opt.capture_out_cap = 1000  # a plan without read-backs must not allocate from the stream's pool
     st, h = _plan(X, Y, cx, cy, opt)
     assert st == status, (st, B.last_error())
     assert h is None  # *plan is reset to NULL on failure

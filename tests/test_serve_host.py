@@ -264,22 +264,24 @@ def test_autotuner_picks_fastest_and_caches(tmp_path):
     from paper_2410_10094_amd import autotune
     calls = []
 
-    def run(lf, bud):
-        calls.append((lf, bud))
-        return abs(lf - 0.625) + abs(bud - 5e8) / 1e9  # fastest at (0.625, 5e8)
+    def run(lf, bud, tile):
+        calls.append((lf, bud, tile))
+        return abs(lf - 0.625) + abs(bud - 5e8) / 1e9 + (tile == 2048) * 0.01  # fastest at (0.625, 5e8, 1024)
 
     path = str(tmp_path / "tune.json")
     t = autotune.Autotuner(path)
     rec = t.tune("k", run)
-    assert (rec["load_factor"], rec["batch_products"]) == (0.625, 5e8)
-    assert len(calls) == len(autotune.LOAD_FACTORS) * len(autotune.BATCH_BUDGETS)
+    assert (rec["load_factor"], rec["batch_products"], rec["tile"]) == (0.625, 5e8, 1024)
+    n = len(autotune.LOAD_FACTORS) * len(autotune.BATCH_BUDGETS) * len(autotune.TILES)
+    assert len(calls) == n
     again = autotune.Autotuner(path).tune("k", run)  # from the cache: no new timings
-    assert again["load_factor"] == 0.625 and len(calls) == 16
+    assert again["load_factor"] == 0.625 and again["tile"] == 1024 and len(calls) == n
 
 
 def test_autotuner_tie_prefers_larger_load_factor_and_batch():
     from paper_2410_10094_amd import autotune
-    assert autotune.choose({(0.5, 1e9): 1.0, (0.9, 1e9): 1.0, (0.9, 2e9): 1.0, (0.5, 2e8): 2.0}) == (0.9, 2e9)
+    assert autotune.choose({(0.5, 1e9, 1024): 1.0, (0.9, 1e9, 1024): 1.0, (0.9, 2e9, 1024): 1.0,
+                            (0.9, 2e9, 2048): 1.0, (0.5, 2e8, 2048): 2.0}) == (0.9, 2e9, 2048)
 
 
 def test_scheduler_cost_estimate_and_classes():
