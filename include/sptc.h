@@ -191,6 +191,8 @@ typedef struct sptc_info {
   int64_t direct_products;                 /* their products (= their outputs) */
   int32_t block_mfma;                      /* 1: the block class runs on the matrix cores */
   int64_t block_mfma_work;                 /* then: padded rows x columns x runs (multiply-adds) */
+  int32_t block_tiles_scanned;             /* 1: the dense block class's tiles are counted, then placed by a
+                                              scan (many small tiles); 0: each reserves its outputs */
 } sptc_info;
 
 typedef struct sptc_plan_s* sptc_plan_t;

@@ -177,6 +177,7 @@ class Plan:
         self.direct_products = info.direct_products
         self.block_mfma = bool(info.block_mfma)
         self.block_mfma_work = info.block_mfma_work
+        self.block_tiles_scanned = bool(info.block_tiles_scanned)
 
     def close(self):
         if getattr(self, "_h", None):

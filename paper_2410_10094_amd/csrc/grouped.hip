@@ -13,9 +13,10 @@
 //   block   dense Y free key (<= kDenseBits bits): (group, slice) tiles of a
 //           dense LDS accumulator, one wave each; or d <= kBlockCap: one
 //           1024-thread workgroup with an LDS hash;
-//           wave and dense block items run in one persistent launch over a
-//           device work queue (queue.hip); each reserves its outputs with
-//           one atomic;
+//           dense block tiles run in a persistent launch over per-XCD work
+//           queues and reserve their outputs with one atomic each; wave
+//           groups take their output positions from a count pass and a
+//           scan (queue.hip);
 //   global  everything else: the products go to the device-memory hash.
 #include <hip/hip_runtime.h>
 
@@ -911,8 +912,7 @@ __global__ void k_reset_status(DevStatus* st, LdsQueue* q) {
   st->err = 0u;
   st->out_base = st->direct_products;
   if (q) {
-    for (int s = 0; s < kSlices; ++s) q->next_tile[s] = 0ull;
-    q->next_wave = 0ull;
+    for (int s = 0; s < kSlices; ++s) q->next_tile[s].v = q->next_fill[s].v = 0ull;
   }
 }
 

@@ -3,14 +3,14 @@
 // group's bound), shared by the kernels that run them.
 //
 //   wave class   one group per wave, a private LDS hash of at most
-//                kWaveSlots slots;
+//                kWaveSlots slots; the outputs' positions come from a count
+//                pass and a scan (a batch: one atomic per group on its
+//                contraction's cursor);
 //   dense block  one (group, slice) tile per wave: the group's row of the
 //                dense Y free key space restricted to one of kSlices slices,
-//                a dense LDS array.
-//
-// Either way the wave counts the item's outputs, reserves them with one
-// atomic on the output cursor (the contraction's own cursor in a batch) and
-// writes them, so an item needs nothing from any other item.
+//                a dense LDS array; the wave counts the tile's outputs,
+//                reserves them with one atomic on the output cursor and
+//                writes them.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -74,21 +74,32 @@ struct WaveScratch {
 
 constexpr size_t kWaveItemLds = (size_t)kWaveSlots * sizeof(ZSlot) + sizeof(WaveScratch);
 
-// Group g in the wave's LDS hash (tab, kWaveSlots slots) and scratch: the
-// group's X entries 64 at a time, their products spread over the lanes by a
-// search over the entries' product offsets.
-__device__ __forceinline__ void wave_group_item(const GroupArgs& a, uint32_t g, ZSlot* tab, WaveScratch& sc) {
-  const unsigned lane = threadIdx.x & 63u;
-  const GroupRec G = a.groups[g];
-  const unsigned long long b = a.eoff[G.start + G.count] - a.eoff[G.start];
-  const unsigned long long d = b < a.ycells ? b : a.ycells;
-  const unsigned tsize = table_size_for(d, kWaveSlots);
-  const unsigned tmask = tsize - 1;
-  for (unsigned s = lane; s < tsize; s += 64) {
-    tab[s].key = kEmpty;
-    tab[s].val = 0.0;
+// Inserts key in an LDS key set (linear probing); false when the table is full.
+__device__ __forceinline__ bool lds_insert(unsigned long long* keys, unsigned tmask, unsigned long long key,
+                                           uint64_t seed) {
+  unsigned s = (unsigned)fmix64(key ^ seed) & tmask;
+  for (unsigned probe = 0; probe <= tmask; ++probe) {
+    const unsigned long long prev = atomicCAS(&keys[s], (unsigned long long)kEmpty, key);
+    if (prev == kEmpty || prev == key) return true;
+    s = (s + 1) & tmask;
   }
-  wave_lds_fence();
+  return false;
+}
+
+// Table size of group G in the wave class (from its bound).
+__device__ __forceinline__ unsigned wave_table_size(const GroupArgs& a, const GroupRec& G) {
+  const unsigned long long b = a.eoff[G.start + G.count] - a.eoff[G.start];
+  return table_size_for(b < a.ycells ? b : a.ycells, kWaveSlots);
+}
+
+// Group G's products spread over the wave's lanes, 64 X entries at a time
+// (a search over the entries' product offsets in the scratch): with VALUES
+// each product is added into the LDS hash tab (ZSlot), else only its Y free
+// key is inserted into the LDS key set keys.  The table must be cleared.
+template <bool VALUES>
+__device__ __forceinline__ void wave_group_walk(const GroupArgs& a, const GroupRec& G, unsigned tmask, ZSlot* tab,
+                                                unsigned long long* keys, WaveScratch& sc) {
+  const unsigned lane = threadIdx.x & 63u;
   for (unsigned base = 0; base < G.count; base += 64) {
     const unsigned e = base + lane;
     unsigned long long c = 0;
@@ -104,7 +115,7 @@ __device__ __forceinline__ void wave_group_item(const GroupArgs& a, uint32_t g, 
     const unsigned long long tot = __shfl(incl, 63, 64);
     sc.off[lane] = incl - c;
     sc.ys[lane] = ys;
-    sc.v[lane] = v;
+    if (VALUES) sc.v[lane] = v;
     wave_lds_fence();
     for (unsigned long long q = lane; q < tot; q += 64) {
       int lo = 0, hi = 63;  // the last entry whose run starts at or before q
@@ -120,25 +131,68 @@ __device__ __forceinline__ void wave_group_item(const GroupArgs& a, uint32_t g, 
         record_error(a.st, kErrInternal);
         continue;
       }
-      const YEntry ye = a.yg[y];
-      if (!lds_accumulate(tab, tmask, ye.phi, __dmul_rn(sc.v[lo], ye.v), a.seed)) record_error(a.st, kErrCapacity);
+      bool ok;
+      if (VALUES) {
+        const YEntry ye = a.yg[y];
+        ok = lds_accumulate(tab, tmask, ye.phi, __dmul_rn(sc.v[lo], ye.v), a.seed);
+      } else {
+        ok = lds_insert(keys, tmask, a.yg[y].phi, a.seed);
+      }
+      if (!ok) record_error(a.st, kErrCapacity);
     }
     wave_lds_fence();
   }
+}
+
+// Distinct outputs of group g (the count pass): the group's Y free keys in
+// the wave's LDS key set (kWaveSlots slots).  Wave-uniform result.
+__device__ __forceinline__ unsigned wave_group_count(const GroupArgs& a, uint32_t g, unsigned long long* keys,
+                                                     WaveScratch& sc) {
+  const unsigned lane = threadIdx.x & 63u;
+  const GroupRec G = a.groups[g];
+  const unsigned tsize = wave_table_size(a, G);
+  for (unsigned s = lane; s < tsize; s += 64) keys[s] = kEmpty;
+  wave_lds_fence();
+  wave_group_walk<false>(a, G, tsize - 1, nullptr, keys, sc);
   unsigned n = 0;
-  for (unsigned s = lane; s < tsize; s += 64) n += tab[s].key != kEmpty ? 1u : 0u;
+  for (unsigned s = lane; s < tsize; s += 64) n += keys[s] != kEmpty ? 1u : 0u;
   n = (unsigned)wave_sum((unsigned long long)n);
-  if (n) {
-    unsigned long long pos = 0;
+  wave_lds_fence();
+  return n;
+}
+
+// Group g accumulated in the wave's LDS hash (tab, kWaveSlots slots) and its
+// outputs written from position pos, in slot order; with RESERVE, pos is
+// taken instead by one atomic on the group's output cursor.
+template <bool RESERVE>
+__device__ __forceinline__ void wave_group_fill(const GroupArgs& a, uint32_t g, unsigned long long pos, ZSlot* tab,
+                                                WaveScratch& sc) {
+  const unsigned lane = threadIdx.x & 63u;
+  const GroupRec G = a.groups[g];
+  const unsigned tsize = wave_table_size(a, G);
+  for (unsigned s = lane; s < tsize; s += 64) {
+    tab[s].key = kEmpty;
+    tab[s].val = 0.0;
+  }
+  wave_lds_fence();
+  wave_group_walk<true>(a, G, tsize - 1, tab, nullptr, sc);
+  if (RESERVE) {
+    unsigned n = 0;
+    for (unsigned s = lane; s < tsize; s += 64) n += tab[s].key != kEmpty ? 1u : 0u;
+    n = (unsigned)wave_sum((unsigned long long)n);
+    if (!n) {
+      wave_lds_fence();
+      return;
+    }
     if (lane == 0) pos = atomicAdd(out_cursor(a, G.phi), (unsigned long long)n);
     pos = __shfl(pos, 0);
-    for (unsigned s0 = 0; s0 < tsize; s0 += 64) {
-      const ZSlot z = tab[s0 + lane];
-      const bool occ = z.key != kEmpty;
-      const unsigned long long m = __ballot(occ);
-      if (occ) put_output(a, pos + lanes_below(m), G.phi, z.key, z.val);
-      pos += (unsigned long long)__popcll(m);
-    }
+  }
+  for (unsigned s0 = 0; s0 < tsize; s0 += 64) {
+    const ZSlot z = tab[s0 + lane];
+    const bool occ = z.key != kEmpty;
+    const unsigned long long m = __ballot(occ);
+    if (occ) put_output(a, pos + lanes_below(m), G.phi, z.key, z.val);
+    pos += (unsigned long long)__popcll(m);
   }
   wave_lds_fence();
 }
@@ -215,24 +269,83 @@ struct YReader {
   }
 };
 
-// Tile (group G, slice) in the wave's dense accumulator acc[wcells]: the
-// wave takes G's X entries 64 at a time, one per lane, each lane loading its
-// entry's record and the bounds of the entry's slice of its Y run (two
-// dependent loads, in parallel across the lanes).  Teams of LPE lanes then
-// walk the staged entries, U per team at a time, loading F * LPE Y entries
-// of each of its U slices before any of their products is added, so that a
-// step's loads are all in flight together; longer slices take further steps.
-template <int LPE, int U, int F, bool BUF>
-__device__ __forceinline__ void sliced_tile_item(const GroupArgs& a, const GroupRec& G, unsigned slice,
-                                                 double* acc, unsigned wcells, const uint32_t* __restrict__ yso,
-                                                 int64_t yso_slots, const YReader<BUF>& yr) {
-  constexpr unsigned kTeams = 64 / LPE;
-  const unsigned lane = threadIdx.x & 63u, team = lane / LPE, tl = lane % LPE;
+// A tile's outputs: the reached cells of acc[wcells] (Y free keys c0 + c).
+__device__ __forceinline__ unsigned tile_count(const double* acc, unsigned wcells) {
+  const unsigned lane = threadIdx.x & 63u;
+  unsigned cnt = 0;
+  for (unsigned cw = 0; cw < wcells; cw += 64) cnt += (unsigned)__popcll(__ballot(cell_reached(acc, cw + lane)));
+  return cnt;
+}
+
+// Writes them in cell order from position pos.
+__device__ __forceinline__ void tile_write(const GroupArgs& a, const GroupRec& G, unsigned c0, const double* acc,
+                                           unsigned wcells, unsigned long long pos) {
+  const unsigned lane = threadIdx.x & 63u;
+  for (unsigned cw = 0; cw < wcells; cw += 64) {
+    const unsigned c = cw + lane;
+    const bool occ = cell_reached(acc, c);
+    const unsigned long long mask = __ballot(occ);
+    if (occ) put_output(a, pos + lanes_below(mask), G.phi, c0 + c, acc[c]);
+    pos += (unsigned long long)__popcll(mask);
+  }
+}
+
+// Counts them, reserves them with one atomic on the output cursor and
+// writes them.
+__device__ __forceinline__ void tile_outputs(const GroupArgs& a, const GroupRec& G, unsigned c0, const double* acc,
+                                             unsigned wcells) {
+  const unsigned cnt = tile_count(acc, wcells);
+  if (cnt) {
+    unsigned long long pos = 0;
+    if ((threadIdx.x & 63u) == 0) pos = atomicAdd(out_cursor(a, G.phi), (unsigned long long)cnt);
+    tile_write(a, G, c0, acc, wcells, __shfl(pos, 0));
+  }
+}
+
+// Tile (group G, slice) in the wave's dense accumulator: the group's X
+// entries are staged up to 64 at a time, one per lane (each lane loading its
+// entry's record and the bounds of the entry's slice of its Y run: two
+// dependent loads, in parallel across the lanes), and the products of a
+// stage are taken as one flat stream: each entry contributes its slice of
+// its Y run, and lane q of window w takes product 64 w + q of the stream, so
+// every lane has a product whatever the slices' lengths.
+//
+// A lane's entry is the number of entries whose last product comes before
+// its own (entries with no product are dropped from the stage).  At stage
+// time each entry sets the bit of its last product in its window's 64-bit
+// mask; window w's mask sits in lane w, so a window reads it with two
+// scalar lane reads, and a lane's entry is the running count of earlier
+// windows' bits plus the mask's bits below the lane (one mbcnt pair).  A
+// stage takes the longest prefix of its entries whose stream fits the 64
+// windows (4096 products), or, when the first entry alone is longer, that
+// entry on its own (all its products then belong to it).
+//
+// The tile is left accumulated in acc (its outputs are the reached cells).
+// Per wave LDS: acc[wcells + 2], then the stage: (stream start, first Y
+// entry) and x of each entry, and the window masks.  Cell wcells collects
+// the products of a bad cell (a corrupt plan: reported), cell wcells + 1
+// those of lanes past the stream's end; neither is an output.  K windows
+// are loaded before any of their products is added, with no branch between
+// the loads and the adds.
+constexpr unsigned kFlatStageBytes = 64 * 8 + 64 * 8 + 64 * 8;
+
+__host__ __device__ constexpr size_t flat_wave_lds(unsigned wcells) {
+  return (size_t)(wcells + 2) * 8 + kFlatStageBytes;
+}
+
+template <int K, bool BUF>
+__device__ __forceinline__ void flat_tile_accumulate(const GroupArgs& a, const GroupRec& G, unsigned slice, double* acc,
+                                               unsigned wcells, const uint32_t* __restrict__ yso, int64_t yso_slots,
+                                               const YReader<BUF>& yr) {
+  uint2* sse = reinterpret_cast<uint2*>(acc + wcells + 2);  // (stream start, first Y entry) per entry
+  double* sx = reinterpret_cast<double*>(sse + 64);
+  unsigned long long* smask = reinterpret_cast<unsigned long long*>(sx + 64);
+  const unsigned lane = threadIdx.x & 63u;
   const unsigned c0 = slice * wcells;  // first Y free key of the slice
-  for (unsigned c = lane; c < wcells; c += 64) acc[c] = -0.0;
-  wave_lds_fence();
-  for (unsigned e0 = 0; e0 < G.count; e0 += 64) {
-    // stage: lane l holds entry e0 + l's slice (start, length) and value
+  for (unsigned c = lane; c < wcells + 2; c += 64) acc[c] = -0.0;
+  bool bad = false;
+  for (unsigned e0 = 0, taken = 0; e0 < G.count; e0 += taken) {
+    // stage: lane l's entry e0 + l: its slice (start, length) and value
     unsigned my_lo = 0u, my_n = 0u;
     double my_x = 0.0;
     if (e0 + lane < G.count) {
@@ -245,83 +358,74 @@ __device__ __forceinline__ void sliced_tile_item(const GroupArgs& a, const Group
           my_n = h - l;
           my_x = r.v;
         } else {
-          record_error(a.st, kErrInternal);
+          bad = true;
         }
       } else if (r.ycnt) {
-        record_error(a.st, kErrInternal);
+        bad = true;
       }
     }
-    const unsigned staged = G.count - e0 < 64u ? G.count - e0 : 64u;
-    for (unsigned s0 = 0; s0 < staged; s0 += U * kTeams) {
-      unsigned lo[U], n[U];
-      double xv[U];
-      unsigned m = 0;
+    const unsigned long long incl64 = wave_incl_scan((unsigned long long)my_n);
+    const unsigned nfit = (unsigned)__popcll(__ballot(incl64 <= 64ull * 64ull));  // a prefix of the lanes
+    const bool single = nfit == 0;  // the first entry alone is longer than 64 windows
+    taken = single ? 1u : nfit;
+    const unsigned total = (unsigned)__builtin_amdgcn_readlane((unsigned)incl64, (int)taken - 1);
+    if (lane >= taken) my_n = 0u;  // staged again next time
+    const unsigned start = (unsigned)incl64 - my_n;
+    const unsigned rank = lanes_below(__ballot(my_n != 0u));
+    wave_lds_fence();  // the previous stage's readers are done
+    if (my_n) {
+      sse[rank] = make_uint2(start, my_lo);
+      sx[rank] = my_x;
+    }
+    smask[lane] = 0ull;
+    wave_lds_fence();
+    if (my_n && !single) {
+      const unsigned last = start + my_n - 1u;
+      atomicOr(&smask[last >> 6], 1ull << (last & 63u));
+    }
+    wave_lds_fence();
+    const unsigned long long vmask = smask[lane];  // window `lane`'s mask
+    const unsigned nwin = (unsigned)(((unsigned long long)total + 63ull) >> 6);
+    unsigned cnt = 0;  // uniform: entries whose last product lies in an earlier window
+    for (unsigned w0 = 0; w0 < nwin; w0 += K) {
+      unsigned idx[K], cell[K];
+      double xv[K], yv[K];
+      bool ok[K];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        // staged entry s0 + u * kTeams + team (past `staged`: a lane with n = 0)
-        if constexpr (LPE == 64) {
-          const int src = (int)(s0 + u) & 63;  // uniform: a scalar read of the lane
-          lo[u] = __builtin_amdgcn_readlane(my_lo, src);
-          n[u] = __builtin_amdgcn_readlane(my_n, src);
-          const unsigned long long xb = (unsigned long long)__double_as_longlong(my_x);
-          const unsigned xlo = __builtin_amdgcn_readlane((unsigned)xb, src);
-          const unsigned xhi = __builtin_amdgcn_readlane((unsigned)(xb >> 32), src);
-          xv[u] = __longlong_as_double((long long)(((unsigned long long)xhi << 32) | xlo));
-        } else {
-          const int src = (int)(s0 + u * kTeams + team) & 63;
-          lo[u] = __shfl(my_lo, src);
-          n[u] = __shfl(my_n, src);
-          xv[u] = __shfl(my_x, src);
-        }
-        m = n[u] > m ? n[u] : m;
+      for (int k = 0; k < K; ++k) {
+        const unsigned w = w0 + k, p = w * 64u + lane;
+        const int wl = (int)(w & 63u);  // (past the stage's windows: any lane; those lanes are past the end)
+        // (readlane returns int: each half goes through unsigned, so the low
+        // half is not sign-extended into the high one)
+        const unsigned mlo = (unsigned)__builtin_amdgcn_readlane((unsigned)vmask, wl);
+        const unsigned mhi = (unsigned)__builtin_amdgcn_readlane((unsigned)(vmask >> 32), wl);
+        const unsigned long long m = ((unsigned long long)mhi << 32) | mlo;
+        unsigned e = __builtin_amdgcn_mbcnt_hi(mhi, __builtin_amdgcn_mbcnt_lo(mlo, cnt));
+        e = e < 63u ? e : 63u;
+        cnt += (unsigned)__popcll(m);
+        ok[k] = p < total;
+        const uint2 se = sse[e];
+        // past the end: Y entry 0 (a mask, not a select, so that the compiler
+        // reads se for every lane instead of branching around the read)
+        idx[k] = (se.y + (p - se.x)) & (ok[k] ? ~0u : 0u);
+        xv[k] = sx[e];
       }
-      for (unsigned jb = 0; jb < m; jb += F * LPE) {
-        unsigned cell[U][F];
-        double yv[U][F];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+      for (int k = 0; k < K; ++k) {
+        cell[k] = yr.cell(idx[k]);
+        yv[k] = yr.value(idx[k]);
+      }
 #pragma unroll
-          for (int f = 0; f < F; ++f) {
-            const unsigned j = jb + f * LPE + tl;
-            if (j < n[u]) {
-              cell[u][f] = yr.cell(lo[u] + j);
-              yv[u][f] = yr.value(lo[u] + j);
-            }
-          }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-          for (int f = 0; f < F; ++f) {
-            const unsigned j = jb + f * LPE + tl;
-            if (j < n[u]) {
-              const unsigned c = cell[u][f] - c0;
-              if (c < wcells)
-                atomicAdd(&acc[c], __dmul_rn(xv[u], yv[u][f]) + 0.0);
-              else
-                record_error(a.st, kErrInternal);
-            }
-          }
+      for (int k = 0; k < K; ++k) {
+        const unsigned c = cell[k] - c0;
+        const unsigned t = c < wcells ? c : wcells;
+        atomicAdd(&acc[ok[k] ? t : wcells + 1u], __dmul_rn(xv[k], yv[k]) + 0.0);
       }
     }
   }
   wave_lds_fence();
-
-  // the tile's outputs: count, reserve with one atomic, write in cell order
-  unsigned cnt = 0;
-  for (unsigned cw = 0; cw < wcells; cw += 64) cnt += (unsigned)__popcll(__ballot(cell_reached(acc, cw + lane)));
-  if (cnt) {
-    unsigned long long pos = 0;
-    if (lane == 0) pos = atomicAdd(out_cursor(a, G.phi), (unsigned long long)cnt);
-    pos = __shfl(pos, 0);
-    for (unsigned cw = 0; cw < wcells; cw += 64) {
-      const unsigned c = cw + lane;
-      const bool occ = cell_reached(acc, c);
-      const unsigned long long mask = __ballot(occ);
-      if (occ) put_output(a, pos + lanes_below(mask), G.phi, c0 + c, acc[c]);
-      pos += (unsigned long long)__popcll(mask);
-    }
-  }
-  wave_lds_fence();
+  bad |= cell_reached(acc, wcells);
+  if (__ballot(bad) && lane == 0) record_error(a.st, kErrInternal);
 }
 
 }  // namespace

@@ -298,6 +298,11 @@ struct sptc_plan_s : Workspace {
   uint32_t* dlist = nullptr;
   uint32_t* dtfirst = nullptr;  // direct class: each product tile's first group
   uint32_t* wlist = nullptr;
+  uint32_t* wcnt = nullptr;            // wave class: each group's output count (by list place)
+  unsigned long long* woff = nullptr;  // and its first output's offset in the class
+  uint32_t* tcnt = nullptr;            // dense block tiles placed by a scan: each tile's output count
+  unsigned long long* toff = nullptr;  // and its offset
+  unsigned long long* tsums = nullptr;  // scan scratch for them
   uint32_t* blist = nullptr;
   uint32_t* glist = nullptr;
   uint32_t* yso = nullptr;    // dense block class: where each slice of each Y run begins, per Y table slot
@@ -536,6 +541,14 @@ sptc_status size_out_table(sptc_plan_s* P, int64_t products) {
   return SPTC_OK;
 }
 
+// Dense block tiles are placed by a count pass and a scan instead of an
+// atomic each when there are more than kTileScanTiles of them (the atomics
+// alone would take 1.6 ms) and they average fewer than kTileScanProducts
+// products (a second walk is cheap); with 20K tiles a second walk measured
+// costlier than the atomics it saves.
+constexpr int64_t kTileScanTiles = 131072;
+constexpr int64_t kTileScanProducts = 4096;
+
 // Cells of the dense LDS accumulator for a Y free key of bits_y bits.
 unsigned dense_cells(int32_t bits_y) { return std::max(1u << bits_y, 1024u); }
 
@@ -767,6 +780,10 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
     P->block_nonfinite = host.nonfinite ? 1 : 0;
     if (P->ngl < 0) return fail(SPTC_ERR_INTERNAL, "group classes do not add up");
   }
+  if (P->nw > 0 && !P->in_batch) {
+    if ((st = P->allocate_n(P->nw, &P->wcnt))) return st;
+    if ((st = P->allocate_n(P->nw, &P->woff))) return st;
+  }
   if (P->nd > 0 && P->direct_products > 0) {
     P->dtfirst_slots = direct_tile_bound((uint64_t)P->direct_products);
     if ((st = P->allocate_n(P->dtfirst_slots, &P->dtfirst))) return st;
@@ -794,6 +811,17 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
   }
   if ((st = P->allocate_n(1, &P->queue))) return st;
   HIP_TRY(prepare_lds_queue());
+  // Very many small dense tiles: each tile's atomic on the one output
+  // cursor (serialised, about 12 ns each) would cost more than accumulating
+  // the tiles twice, once to count their outputs and once to write them at
+  // offsets from a scan.  The read-back's products stand in for the class's.
+  if (P->dense && !P->block_mfma && P->nb > 0 && !P->capture && !P->in_batch && P->nb * kSlices > kTileScanTiles &&
+      P->nb * kSlices > P->products / kTileScanProducts) {
+    const int64_t nt = P->nb * kSlices;
+    if ((st = P->allocate_n(nt, &P->tcnt))) return st;
+    if ((st = P->allocate_n(nt, &P->toff))) return st;
+    if ((st = P->allocate_n(2 * (scan_tiles(nt) + 1), &P->tsums))) return st;
+  }
   if (P->ngl == 0) return SPTC_OK;
 
   // The global class keys its table by (place in glist << Y free bits) | Y free key.
@@ -1087,15 +1115,12 @@ sptc_status execute_plan(sptc_plan_s* P, int32_t* out_idx, double* out_val, int6
                                 P->opt.tile, P->capture ? P->st : nullptr, P->dtfirst_slots));
     HIP_TRY(mark(P, s, SPTC_STAGE_DIRECT, 1));
     HIP_TRY(mark(P, s, SPTC_STAGE_BLOCK, 0));
-    // the dense block class's tiles and the wave class's groups: one
-    // persistent launch over the device work queue
-    const int tiles = P->dense && !P->block_mfma && P->nb > 0;
-    // Y runs: read back, or (no read-back) what the Y table can hold at its load factor
-    const int64_t runs = P->y_groups > 0 ? P->y_groups
-                                         : std::max<int64_t>(1, std::min<int64_t>(P->ny, (int64_t)(P->ytab_slots *
-                                                                                                  P->opt.load_factor)));
-    HIP_TRY(launch_lds_queue(a, P->blist, P->wlist, P->yso, P->ytab_slots, dense_cells(P->bits_fy), tiles, P->nw > 0,
-                             (double)P->ny / (double)runs / kSlices, P->queue, P->num_cus, s));
+    // the wave class first: its outputs' positions come from a scan and
+    // follow the direct class's; the later classes reserve theirs by atomics
+    HIP_TRY(launch_wave_class(a, P->wlist, P->nw, P->wcnt, P->woff, P->tile_sums, P->num_cus, s));
+    if (P->dense && !P->block_mfma && P->nb > 0)
+      HIP_TRY(launch_lds_queue(a, P->blist, P->nb, P->yso, P->ytab_slots, dense_cells(P->bits_fy), P->queue, P->tcnt,
+                               P->toff, P->tsums, P->num_cus, s));
     if (P->block_mfma)
       HIP_TRY(launch_group_block_mfma(a, P->blist, P->nb, P->mplan, P->num_cus, s));
     else if (!P->dense)
@@ -1408,6 +1433,7 @@ sptc_status sptc_plan_info(sptc_plan_t P, sptc_info* info) {
   info->global_groups = P->ngl;
   info->block_mfma = P->block_mfma;
   info->block_mfma_work = P->block_mfma ? (int64_t)mfma_work(P->nb, P->mplan.ncols, P->y_groups) : 0;
+  info->block_tiles_scanned = P->tcnt != nullptr;
   return SPTC_OK;
 }
 

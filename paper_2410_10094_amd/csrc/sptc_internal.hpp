@@ -139,6 +139,7 @@ struct alignas(16) DevStatus {
   unsigned long long out_base;         // output cursor: outputs placed so far
   unsigned long long block_products;   // products of the block class (block survey)
   unsigned long long n_direct, n_wave, n_block, n_global;  // groups per class (grouped path)
+  unsigned long long tile_base;        // dense block tiles placed by a scan: their first output
   unsigned int err;                    // kErr* bits
   unsigned int ydup;                   // nonzero: Y holds a repeated coordinate
   unsigned int ycols;                  // dense Y free key: distinct Y free cells that occur
@@ -415,16 +416,23 @@ hipError_t launch_sort_y_runs(const YSlot* ytab, int64_t nslots, YEntry* yg, int
                               hipStream_t stream, uint32_t* yso = nullptr, uint32_t* runslot = nullptr,
                               unsigned slice_shift = 0);
 
-// ---- persistent LDS classes (queue.hip) ----
+// ---- LDS classes: dense block tiles and the wave class (queue.hip) ----
 // The dense Y free key space is cut into kSlices slices, one per XCD: a
 // tile of the dense block class is (block-class group, slice), accumulated
 // by one wave in LDS.
 constexpr int kSlices = 8;
 
 // Work queue counters of the persistent launch, zeroed by launch_reset_status.
+// A queue counter on a cache line of its own: device-scope atomics on one
+// line are serialised (about 12 ns each), so counters of different XCDs
+// sharing a line would serialise every XCD's pops together.
+struct alignas(128) QueueCounter {
+  unsigned long long v;
+};
+
 struct LdsQueue {
-  unsigned long long next_tile[kSlices];  // next block-class group of each slice's queue
-  unsigned long long next_wave;           // next wave-class group
+  QueueCounter next_tile[kSlices];  // next block-class tile of each slice's queue
+  QueueCounter next_fill[kSlices];  // the same for the fill pass of a two-pass launch
 };
 
 // Plan time: block-class X records refer to their Y run by its table slot
@@ -437,16 +445,27 @@ hipError_t launch_block_runslots(const GroupRec* groups, const uint32_t* blist, 
 // Raises the persistent kernel's dynamic LDS limit on the current device.
 hipError_t prepare_lds_queue();
 
-// One persistent launch over the dense block class's (group, slice) tiles
-// (when tiles: blist, runs cut by yso) and the wave class's groups (when
-// waves: wlist); the item counts are read on the device from the plan's
-// class counts.  cells: the dense accumulator size (a power of two of at
-// least 1024 and at least 2^bits_y); mean_slice_run: average entries of a
-// run per slice (picks the lanes per X entry).  Each item reserves its
-// outputs with one atomic on the output cursor.
-hipError_t launch_lds_queue(const GroupArgs& a, const uint32_t* blist, const uint32_t* wlist, const uint32_t* yso,
-                            int64_t yso_slots, unsigned cells, int tiles, int waves, double mean_slice_run,
-                            LdsQueue* q, int num_cus, hipStream_t stream);
+// The dense block class's (group, slice) tiles (blist, runs cut by yso),
+// persistent launches over per-XCD queues; the tile count is read on the
+// device from the plan's class counts.  cells: the dense accumulator size (a
+// power of two of at least 1024 and at least 2^bits_y).  With tcnt == NULL
+// each tile reserves its outputs with one atomic on the output cursor (one
+// launch).  Otherwise (tcnt, toff: 8 * nb elements; tile_sums: scan scratch
+// for them) a count launch writes each tile's outputs to tcnt, a scan turns
+// them into offsets after the outputs placed so far, and a fill launch
+// accumulates again and writes: no atomic per tile, for many small tiles.
+hipError_t launch_lds_queue(const GroupArgs& a, const uint32_t* blist, int64_t nb, const uint32_t* yso,
+                            int64_t yso_slots, unsigned cells, LdsQueue* q, uint32_t* tcnt, unsigned long long* toff,
+                            void* tile_sums, int num_cus, hipStream_t stream);
+
+// The wave class (wlist, at most nw groups; the count is read on the
+// device).  One contraction: a count pass into wcnt[nw], a scan into
+// woff[nw] (tile_sums: scan scratch for nw elements) and a fill pass; the
+// class's outputs take [direct products, + their count) and st->out_base
+// moves past them.  A batch (a.bout): one pass, one atomic per group on its
+// contraction's cursor (wcnt, woff unused).
+hipError_t launch_wave_class(const GroupArgs& a, const uint32_t* wlist, int64_t nw, uint32_t* wcnt,
+                             unsigned long long* woff, void* tile_sums, int num_cus, hipStream_t stream);
 
 // Clears st->err and st->out_base.
 hipError_t launch_reset_status(DevStatus* st, LdsQueue* q, hipStream_t stream);
@@ -495,7 +514,9 @@ struct BatchOut {
 // wave outputs are contiguous in that numbering.  b's COO takes its direct
 // outputs first, its wave outputs next, then block and global class outputs
 // from `cursor`, which ends as b's nnz.
-struct BatchSeg {
+// One cache line per contraction: device-scope atomics on one line are
+// serialised, so contractions must not share their cursors' line.
+struct alignas(128) BatchSeg {
   unsigned long long dshift;  // numbering of b's first direct output
   unsigned long long dcount;  // b's direct outputs
   unsigned long long cursor;  // b's next output place after its direct outputs

@@ -34,7 +34,8 @@ def run_gpu(p, options=None, allocator="pool", mode=None):
         idx, val = pl.execute()
         info = dict(products=pl.products, out_nnz_bound=pl.out_nnz_bound, y_groups=pl.y_groups,
                     out_order=pl.out_order, out_dims=pl.out_dims, out_table_slots=pl.out_table_slots,
-                    mode=pl.mode, x_groups=pl.x_groups, classes=pl.group_classes, block_mfma=pl.block_mfma)
+                    mode=pl.mode, x_groups=pl.x_groups, classes=pl.group_classes, block_mfma=pl.block_mfma,
+                    block_tiles_scanned=pl.block_tiles_scanned)
         return info, idx.cpu().numpy(), val.cpu().numpy()
 
 

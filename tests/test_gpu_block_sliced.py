@@ -2,7 +2,8 @@
 walked as (group, slice of the Y free key space) tiles: runs short enough
 to be sorted and runs cut slice by slice without sorting, every lanes-per-
 entry variant, the smallest and the largest accumulator, repeated Y
-coordinates and explicit zeros.  Against the oracle, element by element."""
+coordinates and explicit zeros, tiles placed by an atomic each or by a
+count pass and a scan.  Against the oracle, element by element."""
 import numpy as np
 import pytest
 
@@ -51,7 +52,13 @@ CASES = [
     ("thirteen-bit-cells", lambda: _matrix_like(6, 150, 100, 8192, 9_000, 150_000, "thirteen-bit-cells")),
     # explicit zero values: zero products still make structural outputs
     ("explicit-zeros", lambda: _matrix_like(7, 200, 150, 4096, 20_000, 60_000, "explicit-zeros", zeros=0.3)),
+    # few large tiles (about 24,000 products each)
+    ("few-large-tiles", lambda: _matrix_like(9, 16, 64, 4096, 1024, 192_000, "few-large-tiles")),
+    # over 131,072 tiles of about 60 products: counted, then placed by a
+    # scan (every case above reserves each tile's outputs with an atomic)
+    ("many-small-tiles", lambda: _matrix_like(10, 40_000, 2_000, 4096, 200_000, 200_000, "many-small-tiles")),
 ]
+SCANNED = {c[0]: c[0] == "many-small-tiles" for c in CASES}
 
 
 @pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
@@ -60,6 +67,7 @@ def test_sliced_block_class(name, make):
     log(f"[sliced] {p.name} nnz {p.X.nnz}x{p.Y.nnz}")
     info, gidx, gval = run_gpu(p)
     assert info["classes"]["block"] > 0 and not info["block_mfma"], info["classes"]
+    assert info["block_tiles_scanned"] == SCANNED[name], (info["products"], info["classes"])
     assert_parity(p, gidx, gval)
 
 
