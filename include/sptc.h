@@ -171,6 +171,13 @@ typedef struct sptc_options {
                                 (sptc_plan_info reports products = -1 and out_nnz_bound = capture_out_cap);
                                 errors, including nnz(Z) > capture_out_cap, show in sptc_execute's out_nnz.
                                 The matrix-core block class is not used.  Not for batches. */
+  int32_t operand_order;     /* grouped mode, sptc_plan only.  0 (default): group whichever operand's free
+                                key space is larger, so that the other's (the one the per-group tables
+                                are indexed by) is the smaller (section 5.4: the operand order matters);
+                                with Y's free key space the larger, the plan groups Y and accumulates
+                                over X's free keys.  Z is the same either way (its modes stay X's free
+                                modes, then Y's); sptc_info.operands_swapped reports the choice, and the
+                                inspection calls then describe the operands as swapped.  1: as given. */
 } sptc_options;
 
 /* Sizes fixed by sptc_plan. */
@@ -193,6 +200,8 @@ typedef struct sptc_info {
   int64_t block_mfma_work;                 /* then: padded rows x columns x runs (multiply-adds) */
   int32_t block_tiles_scanned;             /* 1: the dense block class's tiles are counted, then placed by a
                                               scan (many small tiles); 0: each reserves its outputs */
+  int32_t operands_swapped;                /* 1: the plan groups Y (sptc_options.operand_order); key widths,
+                                              group counts and classes then refer to the swapped operands */
 } sptc_info;
 
 typedef struct sptc_plan_s* sptc_plan_t;

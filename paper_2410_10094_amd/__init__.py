@@ -178,6 +178,7 @@ class Plan:
         self.block_mfma = bool(info.block_mfma)
         self.block_mfma_work = info.block_mfma_work
         self.block_tiles_scanned = bool(info.block_tiles_scanned)
+        self.operands_swapped = bool(info.operands_swapped)
 
     def close(self):
         if getattr(self, "_h", None):

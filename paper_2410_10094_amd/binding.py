@@ -42,7 +42,7 @@ class Options(ctypes.Structure):
                 ("hash_seed", ctypes.c_uint64), ("out_table_slots", ctypes.c_int64),
                 ("stage_events", ctypes.POINTER(ctypes.c_void_p)), ("mode", ctypes.c_int32),
                 ("block_mfma", ctypes.c_int32), ("tile", ctypes.c_int32), ("lds_max_keys", ctypes.c_int32),
-                ("capture_out_cap", ctypes.c_int64)]
+                ("capture_out_cap", ctypes.c_int64), ("operand_order", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -55,7 +55,7 @@ class Info(ctypes.Structure):
                 ("global_groups", ctypes.c_int64), ("direct_groups", ctypes.c_int64),
                 ("direct_products", ctypes.c_int64), ("block_mfma", ctypes.c_int32),
                 ("block_mfma_work", ctypes.c_int64),
-                ("block_tiles_scanned", ctypes.c_int32)]
+                ("block_tiles_scanned", ctypes.c_int32), ("operands_swapped", ctypes.c_int32)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)

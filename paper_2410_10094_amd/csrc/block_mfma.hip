@@ -403,7 +403,7 @@ __global__ __launch_bounds__(kMBlock, 3) void k_group_block_mfma(GroupArgs a, co
     const int nx = a.ux.n, ny = a.uy.n;
     for (int d = 0; d < nx; ++d) {
       const uint32_t fd = a.ux.field[d];
-      int32_t* dst = a.out_idx + (int64_t)d * a.out_cap + (int64_t)base;
+      int32_t* dst = a.out_idx + (int64_t)(a.ux.row0 + d) * a.out_cap + (int64_t)base;
 #pragma unroll
       for (int c = 0; c < 4; ++c)
 #pragma unroll
@@ -412,7 +412,7 @@ __global__ __launch_bounds__(kMBlock, 3) void k_group_block_mfma(GroupArgs a, co
     }
     for (int d = 0; d < ny; ++d) {
       const uint32_t fd = a.uy.field[d];
-      int32_t* dst = a.out_idx + (int64_t)(nx + d) * a.out_cap + (int64_t)base;
+      int32_t* dst = a.out_idx + (int64_t)(a.uy.row0 + d) * a.out_cap + (int64_t)base;
 #pragma unroll
       for (int c = 0; c < 4; ++c)
 #pragma unroll

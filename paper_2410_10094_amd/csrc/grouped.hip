@@ -30,7 +30,7 @@ namespace {
 
 constexpr int kBBlock = 1024;                           // block-class workgroup
 constexpr unsigned kXcds = 8;                          // MI355X: 8 XCDs, each with its own L2
-constexpr int kBChunk = 1024;
+constexpr int kBChunk = 512;  // X entries staged at a time (LDS: two workgroups fit a CU)
 constexpr unsigned long long kWaveMaxProducts = 16384;  // beyond this a group goes to a workgroup
 
 // ---------------------------------------------------------------------------
@@ -455,9 +455,10 @@ __device__ __forceinline__ void bitonic_sort_lds(unsigned long long* a, unsigned
 
 // Block class with a Y free key too wide for a dense accumulator: one
 // 1024-thread workgroup per group, accumulating in an LDS hash of up to
-// kBlockSlots slots.  When the group's X entries average many products, each
-// wave walks whole Y runs (coalesced, no search); otherwise the products are
-// spread over all threads by a search over the staged entry offsets.  Then
+// kBlockSlots slots.  When the group has enough X entries for every wave and
+// they average many products, each wave walks whole Y runs (coalesced, no
+// search); otherwise the products are spread over all threads by a search
+// over the staged entry offsets.  Then
 // the group's outputs are counted, reserved with one atomic on the output
 // cursor, and written.
 __global__ __launch_bounds__(kBBlock) void k_group_block(GroupArgs a, const uint32_t* __restrict__ blist, int64_t nb,
@@ -499,7 +500,7 @@ __global__ __launch_bounds__(kBBlock) void k_group_block(GroupArgs a, const uint
       if (!lds_accumulate(tab, tmask, key, pv, a.seed)) record_error(a.st, kErrCapacity);
     };
 
-    if (b >= 32ull * G.count) {
+    if (b >= 32ull * G.count && G.count >= 2u * kWaves) {
       // entry-parallel.  Entries come in chunks of kBChunk, sorted by the
       // start of their Y run: every workgroup walks Y in the same order, so
       // the groups running at once on an XCD read the same Y runs together
@@ -520,7 +521,7 @@ __global__ __launch_bounds__(kBBlock) void k_group_block(GroupArgs a, const uint
           s_v[tid] = r.v;
           key = ((unsigned long long)r.ystart << 32) | tid;
         }
-        s_off[tid] = key;
+        if (tid < (unsigned)kBChunk) s_off[tid] = key;
         __syncthreads();
         unsigned nsort = 2;
         while (nsort < n) nsort <<= 1;
@@ -563,7 +564,7 @@ __global__ __launch_bounds__(kBBlock) void k_group_block(GroupArgs a, const uint
         unsigned long long c = 0;
         unsigned ys = 0;
         double v = 0.0;
-        if (e < G.count) {
+        if (tid < (unsigned)kBChunk && e < G.count) {
           const XRec r = a.xr[G.start + e];
           c = r.ycnt;
           ys = r.ystart;
@@ -571,9 +572,11 @@ __global__ __launch_bounds__(kBBlock) void k_group_block(GroupArgs a, const uint
         }
         unsigned long long tot;
         const unsigned long long excl = block_excl_scan<kBBlock>(c, s_wave, &tot);
-        s_off[tid] = excl;
-        s_ys[tid] = ys;
-        s_v[tid] = v;
+        if (tid < (unsigned)kBChunk) {
+          s_off[tid] = excl;
+          s_ys[tid] = ys;
+          s_v[tid] = v;
+        }
         __syncthreads();
         for (unsigned long long q = tid; q < tot; q += kBBlock) {
           int lo = 0, hi = kBChunk - 1;
@@ -769,14 +772,14 @@ __global__ __launch_bounds__(kDBlock) void k_group_direct(GroupArgs a, const uin
       const int nx = a.ux.n, ny = a.uy.n;
       for (int d = 0; d < nx; ++d) {
         const uint32_t fd = a.ux.field[d];
-        int32_t* dst = a.out_idx + (int64_t)d * a.out_cap + (int64_t)q0;
+        int32_t* dst = a.out_idx + (int64_t)(a.ux.row0 + d) * a.out_cap + (int64_t)q0;
 #pragma unroll
         for (int it = 0; it < kDItems; ++it)
           if (put[it]) __builtin_nontemporal_store(key_field(phx[it], fd), dst + it * kDBlock);
       }
       for (int d = 0; d < ny; ++d) {
         const uint32_t fd = a.uy.field[d];
-        int32_t* dst = a.out_idx + (int64_t)(nx + d) * a.out_cap + (int64_t)q0;
+        int32_t* dst = a.out_idx + (int64_t)(a.uy.row0 + d) * a.out_cap + (int64_t)q0;
 #pragma unroll
         for (int it = 0; it < kDItems; ++it)
           if (put[it]) __builtin_nontemporal_store(key_field(ye[it].phi, fd), dst + it * kDBlock);

@@ -340,12 +340,12 @@ struct GroupedOccupancyOp {
     for (int m = 0; m < kMaxOrder; ++m)
       if (m < ux.n)
         __builtin_nontemporal_store(key_field(phix, ux.field[m]),
-                                    &out_idx[(int64_t)m * out_cap + (int64_t)pos]);
+                                    &out_idx[(int64_t)(ux.row0 + m) * out_cap + (int64_t)pos]);
 #pragma unroll
     for (int m = 0; m < kMaxOrder; ++m)
       if (m < uy.n)
         __builtin_nontemporal_store(key_field(phiy, uy.field[m]),
-                                    &out_idx[(int64_t)(ux.n + m) * out_cap + (int64_t)pos]);
+                                    &out_idx[(int64_t)(uy.row0 + m) * out_cap + (int64_t)pos]);
     __builtin_nontemporal_store(z.val, &out_val[pos]);
   }
 };

@@ -536,12 +536,12 @@ __device__ __forceinline__ void write_output(const GroupArgs& a, unsigned long l
   for (int m = 0; m < kMaxOrder; ++m)
     if (m < a.ux.n)
       __builtin_nontemporal_store(key_field(phix, a.ux.field[m]),
-                                  &a.out_idx[(int64_t)m * a.out_cap + (int64_t)pos]);
+                                  &a.out_idx[(int64_t)(a.ux.row0 + m) * a.out_cap + (int64_t)pos]);
 #pragma unroll
   for (int m = 0; m < kMaxOrder; ++m)
     if (m < a.uy.n)
       __builtin_nontemporal_store(key_field(phiy, a.uy.field[m]),
-                                  &a.out_idx[(int64_t)(a.ux.n + m) * a.out_cap + (int64_t)pos]);
+                                  &a.out_idx[(int64_t)(a.uy.row0 + m) * a.out_cap + (int64_t)pos]);
   __builtin_nontemporal_store(v, &a.out_val[pos]);
 }
 
@@ -563,11 +563,11 @@ __device__ __forceinline__ void batch_store_at(const BatchOut* __restrict__ bout
   int32_t* row = out_idx + d.idx_off + (int64_t)pos;
 #pragma unroll
   for (int m = 0; m < kMaxOrder; ++m)
-    if (m < nx) __builtin_nontemporal_store(key_field(fx, d.ux.field[m]), row + (int64_t)m * d.cap);
+    if (m < nx) __builtin_nontemporal_store(key_field(fx, d.ux.field[m]), row + (int64_t)(d.ux.row0 + m) * d.cap);
 #pragma unroll
   for (int m = 0; m < kMaxOrder; ++m)
     if (m < ny)
-      __builtin_nontemporal_store(key_field(phiy, d.uy.field[m]), row + (int64_t)(nx + m) * d.cap);
+      __builtin_nontemporal_store(key_field(phiy, d.uy.field[m]), row + (int64_t)(d.uy.row0 + m) * d.cap);
   __builtin_nontemporal_store(v, &out_val[d.val_off + (int64_t)pos]);
 }
 

@@ -316,6 +316,7 @@ struct sptc_plan_s : Workspace {
   bool in_batch = false;      // the packed plan of a batch
   bool stalled = false;       // a read-back timed out: the stream still holds the plan's work
   bool capture = false;       // no read-back (opt.capture_out_cap > 0): counts stay on the device
+  bool swapped = false;       // X and Y traded places (operand order): Z's rows are put back
   int64_t dtfirst_slots = 0;  // entries of the direct class's tile table
   bool pageable_readback = false;  // read counts back through pageable memory (no pinned buffer)
   bool block_surveyed = false;  // the block survey ran (dense Y free key, one contraction)
@@ -418,6 +419,8 @@ sptc_status check_options(const sptc_options& o) {
   if (o.lds_max_keys != 0 && (o.lds_max_keys < 64 || o.lds_max_keys > kBlockCap))
     return fail(SPTC_ERR_INVALID_ARG, "lds_max_keys %d outside 64..%d", o.lds_max_keys, kBlockCap);
   if (o.capture_out_cap < 0) return fail(SPTC_ERR_INVALID_ARG, "capture_out_cap < 0");
+  if (o.operand_order != 0 && o.operand_order != 1)
+    return fail(SPTC_ERR_INVALID_ARG, "operand_order %d is not 0 or 1", o.operand_order);
   return SPTC_OK;
 }
 
@@ -936,6 +939,15 @@ sptc_status check_problem(const sptc_coo* X, const sptc_coo* Y, int32_t ncontrac
   return SPTC_OK;
 }
 
+// Cells of a tensor's free key space (saturating): the product of its
+// uncontracted mode lengths.
+int64_t free_cells(const sptc_coo* T, int32_t ncontract, const int32_t* c) {
+  std::vector<int32_t> fm;
+  for (int32_t m = 0; m < T->order; ++m)
+    if (std::find(c, c + ncontract, m) == c + ncontract) fm.push_back(m);
+  return sat_prod(T->dims, fm);
+}
+
 void make_layout(const sptc_coo* X, const sptc_coo* Y, int32_t ncontract, const int32_t* cx, const int32_t* cy,
                  int32_t validate, Layout* L) {
   std::vector<int32_t> cxv(cx, cx + ncontract), cyv(cy, cy + ncontract), fx, fy;
@@ -960,6 +972,8 @@ void make_layout(const sptc_coo* X, const sptc_coo* Y, int32_t ncontract, const 
   for (int32_t m : fy) L->out_dims[k++] = Y->dims[m];
   add_unpack(L->ux, L->x_f, 0);
   add_unpack(L->uy, L->y_f, 0);
+  L->ux.row0 = 0;
+  L->uy.row0 = L->ux.n;  // Z's modes: X's free modes, then Y's
   L->ycells = (uint64_t)sat_prod(Y->dims, fy);
   L->c_cells = sat_prod(X->dims, cxv);
   L->fx_cells = sat_prod(X->dims, fx);
@@ -996,8 +1010,29 @@ sptc_status plan_create(sptc_plan_t* plan, const sptc_coo* X, const sptc_coo* Y,
     return fail(SPTC_ERR_INVALID_ARG, "capture_out_cap needs a caller allocator (the plan must not allocate from "
                                       "the stream's pool inside a graph capture)");
   if (o.capture_out_cap > 0 && br) return fail(SPTC_ERR_INVALID_ARG, "capture_out_cap is not for batches");
+  // Operand order (section 5.4): the grouped mode groups X by its free key
+  // and indexes each group's table by Y's free key, so it groups whichever
+  // operand has the larger free key space.  With Y's the larger, X and Y
+  // trade places here, and Z's rows are put back in X-then-Y order below.
+  const bool swap = !br && o.mode == SPTC_MODE_GROUPED && o.operand_order == 0 &&
+                    free_cells(Y, ncontract, cy) > free_cells(X, ncontract, cx);
+  if (swap) {
+    std::swap(X, Y);
+    std::swap(cx, cy);
+  }
   Layout L;
   make_layout(X, Y, ncontract, cx, cy, o.validate, &L);
+  if (swap) {
+    // Z's modes stay the caller's X free modes, then Y's: the grouped
+    // operand's free coordinates (the caller's Y) go after the others
+    int64_t dims[SPTC_MAX_OUT_ORDER];
+    const int32_t nfx = L.ux.n, nfy = L.uy.n;
+    for (int32_t m = 0; m < nfy; ++m) dims[m] = L.out_dims[nfx + m];
+    for (int32_t m = 0; m < nfx; ++m) dims[nfy + m] = L.out_dims[m];
+    for (int32_t m = 0; m < nfx + nfy; ++m) L.out_dims[m] = dims[m];
+    L.uy.row0 = 0;
+    L.ux.row0 = nfy;
+  }
   if ((st = check_key_widths(L, o.mode))) return st;
   if (br) {  // regions decide direct addressing of X free keys per contraction
     if (o.mode != SPTC_MODE_GROUPED) return fail(SPTC_ERR_INTERNAL, "table regions need the grouped mode");
@@ -1031,10 +1066,16 @@ sptc_status plan_create(sptc_plan_t* plan, const sptc_coo* X, const sptc_coo* Y,
   P->nfy = L.nfy;
   P->out_order = L.out_order;
   for (int32_t m = 0; m < L.out_order; ++m) P->out_dims[m] = L.out_dims[m];
-  if (L.bits_fx + L.bits_fy <= 63) {  // packed output key (global mode, global class)
-    add_unpack(P->out_unpack, P->x_f, P->bits_fy);
-    add_unpack(P->out_unpack, P->y_f, 0);
+  if (L.bits_fx + L.bits_fy <= 63) {  // packed output key (global mode, global class), fields in Z's row order
+    if (swap) {
+      add_unpack(P->out_unpack, P->y_f, 0);
+      add_unpack(P->out_unpack, P->x_f, P->bits_fy);
+    } else {
+      add_unpack(P->out_unpack, P->x_f, P->bits_fy);
+      add_unpack(P->out_unpack, P->y_f, 0);
+    }
   }
+  P->swapped = swap;
   add_unpack(P->ykey_unpack, P->y_c, 0);
   add_unpack(P->yfree_unpack, P->y_f, 0);
   P->y_agg = P->bits_c <= kAggBits ? 1 : 0;
@@ -1403,6 +1444,7 @@ void sptc_default_options(sptc_options* opt) {
   opt->tile = 0;
   opt->lds_max_keys = 0;
   opt->capture_out_cap = 0;
+  opt->operand_order = 0;
 }
 
 sptc_status sptc_plan(sptc_plan_t* plan, const sptc_coo* X, const sptc_coo* Y, int32_t ncontract, const int32_t* cx,
@@ -1434,6 +1476,7 @@ sptc_status sptc_plan_info(sptc_plan_t P, sptc_info* info) {
   info->block_mfma = P->block_mfma;
   info->block_mfma_work = P->block_mfma ? (int64_t)mfma_work(P->nb, P->mplan.ncols, P->y_groups) : 0;
   info->block_tiles_scanned = P->tcnt != nullptr;
+  info->operands_swapped = P->swapped ? 1 : 0;
   return SPTC_OK;
 }
 

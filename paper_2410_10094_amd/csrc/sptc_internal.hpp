@@ -83,6 +83,7 @@ struct TabGeom {
 // Decodes an output key into out_order coordinates.
 struct KeyUnpack {
   int32_t n;
+  int32_t row0;                  // output row (coordinate mode of Z) of field 0; field m goes to row0 + m
   uint32_t field[kMaxOutOrder];  // make_field(0, shift, width)
 };
 

@@ -23,19 +23,23 @@ def to_device(p):
 MODES = {"grouped": 0, "global": 1}
 
 
-def run_gpu(p, options=None, allocator="pool", mode=None):
-    """Plan + execute on cuda:0; returns (plan info dict, idx numpy, val numpy)."""
+def run_gpu(p, options=None, allocator="pool", mode=None, order=1):
+    """Plan + execute on cuda:0; returns (plan info dict, idx numpy, val numpy).
+    order: sptc_options.operand_order, pinned to 1 (X grouped, as given) by
+    default so that a test's class and kernel assertions hold for the
+    operands it built; 0 lets the plan pick the operand to group."""
     import paper_2410_10094_amd as sptc
     X, Y = to_device(p)
+    options = options or sptc.default_options()
+    options.operand_order = order
     if mode is not None:
-        options = options or sptc.default_options()
         options.mode = MODES[mode]
     with sptc.plan(X, Y, p.cx, p.cy, options=options, allocator=allocator) as pl:
         idx, val = pl.execute()
         info = dict(products=pl.products, out_nnz_bound=pl.out_nnz_bound, y_groups=pl.y_groups,
                     out_order=pl.out_order, out_dims=pl.out_dims, out_table_slots=pl.out_table_slots,
                     mode=pl.mode, x_groups=pl.x_groups, classes=pl.group_classes, block_mfma=pl.block_mfma,
-                    block_tiles_scanned=pl.block_tiles_scanned)
+                    block_tiles_scanned=pl.block_tiles_scanned, operands_swapped=pl.operands_swapped)
         return info, idx.cpu().numpy(), val.cpu().numpy()
 
 

@@ -39,6 +39,7 @@ def test_default_options():
     assert o.validate == 1 and o.max_probe == 0 and o.out_table_slots == 0
     assert o.block_mfma == 0  # the matrix-core block class is opt-in
     assert o.tile == 0 and o.lds_max_keys == 0 and o.capture_out_cap == 0
+    assert o.operand_order == 0  # the grouped mode picks the operand to group
 
 
 def _plan(X, Y, cx, cy, opt=None):
@@ -83,6 +84,7 @@ coo.keep = []
     ("bad_lds_max_keys", B.ERR_INVALID_ARG),
     ("negative_capture_out_cap", B.ERR_INVALID_ARG),
     ("capture_without_allocator", B.ERR_INVALID_ARG),
+    ("bad_operand_order", B.ERR_INVALID_ARG),
 ])
 def test_plan_validation(case, status):
     X, Y, cx, cy, opt = coo((8, 9, 10)), coo((10, 9, 7)), [2], [0], None
@@ -136,6 +138,9 @@ def test_plan_validation(case, status):
     elif case == "capture_without_allocator":
         opt = B.default_options()
         opt.capture_out_cap = 1000  # a plan without read-backs must not allocate from the stream's pool
+    elif case == "bad_operand_order":
+        opt = B.default_options()
+        opt.operand_order = 2
     st, h = _plan(X, Y, cx, cy, opt)
     assert st == status, (st, B.last_error())
     assert h is None  # *plan is reset to NULL on failure

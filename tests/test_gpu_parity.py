@@ -46,7 +46,7 @@ PROBLEMS = _problems()
 @pytest.mark.parametrize("p", PROBLEMS, ids=lambda p: p.name)
 def test_parity_against_oracle(p, mode):
     log(f"[parity] {p.name} {mode} nnz {p.X.nnz}x{p.Y.nnz} cx={p.cx} cy={p.cy}")
-    info, gidx, gval = run_gpu(p, mode=mode)
+    info, gidx, gval = run_gpu(p, mode=mode, order=0)  # the plan picks the operand to group
     per_x, total = oracle.match_counts(p.X, p.Y, p.cx, p.cy)
     assert info["products"] == total
     ref = assert_parity(p, gidx, gval)
@@ -62,7 +62,7 @@ def test_stage_y_groups_and_grouped_array():
               W.plain()]:
         log(f"[stage-A] {p.name}")
         X, Y = to_device(p)
-        with sptc.plan(X, Y, p.cx, p.cy) as pl:
+        with sptc.plan(X, Y, p.cx, p.cy, options=sptc.default_options(operand_order=1)) as pl:
             kc, counts, starts = (t.cpu().numpy() for t in pl.y_groups_table())
             free, vals = (t.cpu().numpy() for t in pl.y_grouped())
         tuples, ocounts = oracle.group_counts(p.Y, p.cy)
@@ -108,7 +108,7 @@ def test_stage_x_groups():
               W.random_problem(92, 4, 3, 1, 2, 7, 5000, 3000, duplicates=True)]:
         log(f"[stage-X] {p.name}")
         X, Y = to_device(p)
-        with sptc.plan(X, Y, p.cx, p.cy) as pl:
+        with sptc.plan(X, Y, p.cx, p.cy, options=sptc.default_options(operand_order=1)) as pl:
             coords, counts, prods = (t.cpu().numpy() for t in pl.x_groups_table())
             ng, P = pl.x_groups, pl.products
         fx = [m for m in range(p.X.order) if m not in p.cx]
