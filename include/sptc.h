@@ -202,6 +202,8 @@ typedef struct sptc_info {
                                               scan (many small tiles); 0: each reserves its outputs */
   int32_t operands_swapped;                /* 1: the plan groups Y (sptc_options.operand_order); key widths,
                                               group counts and classes then refer to the swapped operands */
+  int32_t block_dense_rows;                /* 1: the dense block class's groups are small, and each is
+                                              accumulated whole (its dense output row) by one workgroup */
 } sptc_info;
 
 typedef struct sptc_plan_s* sptc_plan_t;

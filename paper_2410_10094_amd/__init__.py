@@ -179,6 +179,7 @@ class Plan:
         self.block_mfma_work = info.block_mfma_work
         self.block_tiles_scanned = bool(info.block_tiles_scanned)
         self.operands_swapped = bool(info.operands_swapped)
+        self.block_dense_rows = bool(info.block_dense_rows)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -55,7 +55,8 @@ class Info(ctypes.Structure):
                 ("global_groups", ctypes.c_int64), ("direct_groups", ctypes.c_int64),
                 ("direct_products", ctypes.c_int64), ("block_mfma", ctypes.c_int32),
                 ("block_mfma_work", ctypes.c_int64),
-                ("block_tiles_scanned", ctypes.c_int32), ("operands_swapped", ctypes.c_int32)]
+                ("block_tiles_scanned", ctypes.c_int32), ("operands_swapped", ctypes.c_int32),
+                ("block_dense_rows", ctypes.c_int32)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)

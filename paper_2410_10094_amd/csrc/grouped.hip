@@ -28,9 +28,10 @@
 namespace sptc {
 namespace {
 
-constexpr int kBBlock = 1024;                           // block-class workgroup
+constexpr int kBBlock = 1024;                           // block-class workgroup (large tables)
+constexpr int kBSmallBlock = 256;                       // and for groups that fit the small table
+constexpr int kBlockSmallSlots = 2048;
 constexpr unsigned kXcds = 8;                          // MI355X: 8 XCDs, each with its own L2
-constexpr int kBChunk = 512;  // X entries staged at a time (LDS: two workgroups fit a CU)
 constexpr unsigned long long kWaveMaxProducts = 16384;  // beyond this a group goes to a workgroup
 
 // ---------------------------------------------------------------------------
@@ -453,26 +454,36 @@ __device__ __forceinline__ void bitonic_sort_lds(unsigned long long* a, unsigned
   }
 }
 
-// Block class with a Y free key too wide for a dense accumulator: one
-// 1024-thread workgroup per group, accumulating in an LDS hash of up to
-// kBlockSlots slots.  When the group has enough X entries for every wave and
-// they average many products, each wave walks whole Y runs (coalesced, no
-// search); otherwise the products are spread over all threads by a search
-// over the staged entry offsets.  Then
-// the group's outputs are counted, reserved with one atomic on the output
-// cursor, and written.
-__global__ __launch_bounds__(kBBlock) void k_group_block(GroupArgs a, const uint32_t* __restrict__ blist, int64_t nb,
-                                                         const DevStatus* dc) {
+// Block class, one workgroup of BLOCK threads per group.  KIND 0 and 1: a
+// Y free key too wide for a dense accumulator, an LDS hash of up to SLOTS
+// slots; a group is taken by the instance whose table its bound fits (0: at
+// most 70% of the small table's slots; 1: the rest), so that small groups
+// run four to a CU instead of two.  KIND 2: a dense Y free key and small
+// groups (a few (group, slice) tiles' worth of products): the group's whole
+// output row as a dense LDS array of `cells` doubles, cells starting at -0.0
+// and products added as x * y + 0.0, so a cell is an output exactly when it
+// is no longer -0.0 (see the sliced tiles).  When the group has enough X
+// entries for every wave and they average many products, each wave walks
+// whole Y runs (coalesced, no search); otherwise the products are spread
+// over all threads by a search over the staged entry offsets.  Then each
+// wave counts the outputs in its share of the table, one atomic on the
+// output cursor reserves the group's, and each wave writes its share.
+template <int BLOCK, int SLOTS, int KIND>
+__global__ __launch_bounds__(BLOCK) void k_group_block(GroupArgs a, const uint32_t* __restrict__ blist, int64_t nb,
+                                                       const DevStatus* dc, unsigned cells) {
+  constexpr int kBChunk = BLOCK / 2;  // X entries staged at a time (LDS: the table dominates)
+  constexpr unsigned long long kSmallCap = (unsigned long long)kBlockSmallSlots * 7 / 10;
   if (dc) nb = (int64_t)dc->n_block;  // the count read on the device
   extern __shared__ __align__(16) unsigned char s_dyn[];
   __shared__ unsigned long long s_off[kBChunk];
   __shared__ unsigned s_ys[kBChunk];
   __shared__ double s_v[kBChunk];
-  __shared__ unsigned long long s_wave[kBBlock / 64 + 1];
+  __shared__ unsigned long long s_wave[BLOCK / 64 + 1];
   __shared__ unsigned long long s_base;
   ZSlot* tab = reinterpret_cast<ZSlot*>(s_dyn);
+  double* acc = reinterpret_cast<double*>(s_dyn);
   const unsigned tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  constexpr unsigned kWaves = kBBlock / 64;
+  constexpr unsigned kWaves = BLOCK / 64;
 
   // XCD-aware order: workgroups go to the XCDs round-robin, so workgroup w
   // runs on XCD w % kXcds.  Each XCD takes one contiguous range of the list
@@ -487,17 +498,29 @@ __global__ __launch_bounds__(kBBlock) void k_group_block(GroupArgs a, const uint
     const GroupRec G = a.groups[g];
     const unsigned long long b = a.eoff[G.start + G.count] - a.eoff[G.start];
     const unsigned long long d = b < a.ycells ? b : a.ycells;
-    const unsigned tsize = table_size_for(d, kBlockSlots) < (unsigned)kBBlock ? (unsigned)kBBlock
-                                                                                : table_size_for(d, kBlockSlots);
+    if (KIND != 2 && (d <= kSmallCap) != (KIND == 0)) continue;  // the other instance's group (uniform)
+    const unsigned tsize =
+        KIND == 2 ? cells : (table_size_for(d, SLOTS) < (unsigned)BLOCK ? (unsigned)BLOCK : table_size_for(d, SLOTS));
     const unsigned tmask = tsize - 1;
-    for (unsigned s = tid; s < tsize; s += kBBlock) {
-      tab[s].key = kEmpty;
-      tab[s].val = 0.0;
+    for (unsigned s = tid; s < tsize; s += BLOCK) {
+      if constexpr (KIND == 2) {
+        acc[s] = -0.0;
+      } else {
+        tab[s].key = kEmpty;
+        tab[s].val = 0.0;
+      }
     }
     __syncthreads();
 
     auto accumulate = [&](unsigned long long key, double pv) {
-      if (!lds_accumulate(tab, tmask, key, pv, a.seed)) record_error(a.st, kErrCapacity);
+      if constexpr (KIND == 2) {
+        if (key < tsize)
+          atomicAdd(&acc[key], pv + 0.0);
+        else
+          record_error(a.st, kErrInternal);
+      } else {
+        if (!lds_accumulate(tab, tmask, key, pv, a.seed)) record_error(a.st, kErrCapacity);
+      }
     };
 
     if (b >= 32ull * G.count && G.count >= 2u * kWaves) {
@@ -571,14 +594,14 @@ __global__ __launch_bounds__(kBBlock) void k_group_block(GroupArgs a, const uint
           v = r.v;
         }
         unsigned long long tot;
-        const unsigned long long excl = block_excl_scan<kBBlock>(c, s_wave, &tot);
+        const unsigned long long excl = block_excl_scan<BLOCK>(c, s_wave, &tot);
         if (tid < (unsigned)kBChunk) {
           s_off[tid] = excl;
           s_ys[tid] = ys;
           s_v[tid] = v;
         }
         __syncthreads();
-        for (unsigned long long q = tid; q < tot; q += kBBlock) {
+        for (unsigned long long q = tid; q < tot; q += BLOCK) {
           int lo = 0, hi = kBChunk - 1;
           while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
@@ -600,30 +623,43 @@ __global__ __launch_bounds__(kBBlock) void k_group_block(GroupArgs a, const uint
     }
     __syncthreads();
 
-    // count, reserve, write
-    unsigned long long n = 0;
-    for (unsigned s = tid; s < tsize; s += kBBlock) n += tab[s].key != kEmpty ? 1u : 0u;
-    n = block_sum<kBBlock>(n, s_wave);
-    if (tid == 0) s_base = atomicAdd(a.bout ? &a.bseg[G.phi >> a.bwx].cursor : &a.st->out_base, n);
+    // count, reserve, write: wave w takes slots [w R, (w + 1) R)
+    const unsigned R = tsize / kWaves;  // tsize >= BLOCK: a multiple of 64
+    auto occupied = [&](unsigned s) {
+      if constexpr (KIND == 2)
+        return __double_as_longlong(acc[s]) != (long long)0x8000000000000000ull;
+      else
+        return tab[s].key != kEmpty;
+    };
+    unsigned n = 0;
+    for (unsigned s0 = wave * R; s0 < (wave + 1) * R; s0 += 64) n += (unsigned)__popcll(__ballot(occupied(s0 + lane)));
+    if (lane == 0) s_wave[wave] = n;
     __syncthreads();
-    const unsigned long long obase = s_base;
-    unsigned long long run = 0;
-    for (unsigned s0 = 0; s0 < tsize; s0 += kBBlock) {
-      const unsigned s = s0 + tid;
-      const ZSlot z = tab[s];
-      const bool occ = z.key != kEmpty;
-      const unsigned long long key = z.key;
-      const double val = z.val;
-      unsigned long long tot;
-      const unsigned long long r = block_excl_scan<kBBlock>(occ ? 1ull : 0ull, s_wave, &tot);
-      if (occ) {
-        const unsigned long long pos = obase + run + r;
-        if (a.bout)
-          batch_store(a.bout, a.out_idx, a.out_val, a.bwx, (uint32_t)(G.phi >> a.bwx), pos, G.phi, key, val, a.st);
-        else if ((int64_t)pos < a.out_cap)
-          write_output(a, pos, G.phi, key, val);
+    if (tid == 0) {
+      unsigned long long run = 0;
+      for (unsigned w = 0; w < kWaves; ++w) {
+        const unsigned long long t = s_wave[w];
+        s_wave[w] = run;
+        run += t;
       }
-      run += tot;
+      s_base = run ? atomicAdd(a.bout ? &a.bseg[G.phi >> a.bwx].cursor : &a.st->out_base, run) : 0ull;
+    }
+    __syncthreads();
+    unsigned long long pos = s_base + s_wave[wave];
+    for (unsigned s0 = wave * R; s0 < (wave + 1) * R; s0 += 64) {
+      const unsigned s = s0 + lane;
+      const bool occ = occupied(s);
+      const unsigned long long m = __ballot(occ);
+      if (occ) {
+        const unsigned long long key = KIND == 2 ? (unsigned long long)s : tab[s].key;
+        const double val = KIND == 2 ? acc[s] : tab[s].val;
+        const unsigned long long at = pos + lanes_below(m);
+        if (a.bout)
+          batch_store(a.bout, a.out_idx, a.out_val, a.bwx, (uint32_t)(G.phi >> a.bwx), at, G.phi, key, val, a.st);
+        else if ((int64_t)at < a.out_cap)
+          write_output(a, at, G.phi, key, val);
+      }
+      pos += (unsigned long long)__popcll(m);
     }
     __syncthreads();
   }
@@ -1022,20 +1058,41 @@ hipError_t launch_gather_global(const GroupRec* groups, const uint32_t* glist, i
 }
 
 
-// Dynamic LDS of the block class: a kBlockSlots-slot hash of 16-byte slots,
-// or (dense) up to kCoMaxGroups arrays of `cells` doubles plus bitmaps
-constexpr size_t kBlockHashLds = (size_t)kBlockSlots * 16;
+// Dynamic LDS of the block class: a hash of 16-byte slots, or a dense row.
 hipError_t prepare_group_block() {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_group_block),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kBlockHashLds);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_group_block<kBBlock, kBlockSlots, 1>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, kBlockSlots * 16);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_group_block<kBSmallBlock, kBlockSmallSlots, 0>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kBlockSmallSlots * 16);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_group_block<kBSmallBlock, 0, 2>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (1 << kDenseBits) * 8);
+  return e;
 }
 
+// Hashed: both instances walk the whole list, each taking the groups its
+// table fits: four small-table workgroups of 256 threads per CU, two of
+// 1024.  Dense (cells > 0): 256-thread workgroups with a row of cells.
 hipError_t launch_group_block(const GroupArgs& a, const uint32_t* blist, int64_t nb, int num_cus,
-                              hipStream_t stream, const DevStatus* dc) {
+                              hipStream_t stream, const DevStatus* dc, unsigned cells) {
   if (nb <= 0) return hipSuccess;
-  unsigned grid = grid_for(nb * kBBlock, kBBlock, num_cus, 2);
+  if (cells) {
+    if (cells < 64u || (cells & (cells - 1u)) || cells > (1u << kDenseBits)) return hipErrorInvalidValue;
+    unsigned grid = grid_for(nb, 1, num_cus, std::min(8, std::max(1, (160 << 10) / (int)(cells * 8 + (8 << 10)))));
+    if (grid >= kXcds) grid -= grid % kXcds;
+    k_group_block<kBSmallBlock, 0, 2><<<grid, kBSmallBlock, cells * 8, stream>>>(a, blist, nb, dc, cells);
+    return hipGetLastError();
+  }
+  unsigned grid = grid_for(nb, 1, num_cus, 4);
   if (grid >= kXcds) grid -= grid % kXcds;
-  k_group_block<<<grid, kBBlock, kBlockHashLds, stream>>>(a, blist, nb, dc);
+  k_group_block<kBSmallBlock, kBlockSmallSlots, 0><<<grid, kBSmallBlock, kBlockSmallSlots * 16, stream>>>(a, blist,
+                                                                                                      nb, dc, 0u);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  grid = grid_for(nb, 1, num_cus, 2);
+  if (grid >= kXcds) grid -= grid % kXcds;
+  k_group_block<kBBlock, kBlockSlots, 1><<<grid, kBBlock, kBlockSlots * 16, stream>>>(a, blist, nb, dc, 0u);
   return hipGetLastError();
 }
 

@@ -317,6 +317,7 @@ struct sptc_plan_s : Workspace {
   bool stalled = false;       // a read-back timed out: the stream still holds the plan's work
   bool capture = false;       // no read-back (opt.capture_out_cap > 0): counts stay on the device
   bool swapped = false;       // X and Y traded places (operand order): Z's rows are put back
+  bool dense_rows = false;    // dense block class of small groups: a whole dense row per workgroup
   int64_t dtfirst_slots = 0;  // entries of the direct class's tile table
   bool pageable_readback = false;  // read counts back through pageable memory (no pinned buffer)
   bool block_surveyed = false;  // the block survey ran (dense Y free key, one contraction)
@@ -551,6 +552,10 @@ sptc_status size_out_table(sptc_plan_s* P, int64_t products) {
 // costlier than the atomics it saves.
 constexpr int64_t kTileScanTiles = 131072;
 constexpr int64_t kTileScanProducts = 4096;
+
+// Dense block groups averaging fewer products than this run one workgroup
+// per group with the whole dense row instead of (group, slice) tiles.
+constexpr int64_t kDenseRowProducts = 8192;
 
 // Cells of the dense LDS accumulator for a Y free key of bits_y bits.
 unsigned dense_cells(int32_t bits_y) { return std::max(1u << bits_y, 1024u); }
@@ -796,7 +801,10 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
     if (P->dense) {
       HIP_TRY(mark(P, s, SPTC_STAGE_X_SORT, 0));
       if (mfma_candidate(P) && (st = plan_block_mfma(P))) return st;
-      if (!P->block_mfma) {
+      // small groups (a few tiles' worth of products each): a workgroup per
+      // group with its whole dense row beats eight thin slice tiles
+      P->dense_rows = !P->block_mfma && !P->capture && P->products < P->nb * kDenseRowProducts;
+      if (!P->block_mfma && !P->dense_rows) {
         // the sliced walk: runs sorted by Y free key (consecutive
         // accumulator cells) and cut into the slices of the Y free key
         // space; block-class X records keyed by their run's table slot
@@ -818,7 +826,8 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
   // cursor (serialised, about 12 ns each) would cost more than accumulating
   // the tiles twice, once to count their outputs and once to write them at
   // offsets from a scan.  The read-back's products stand in for the class's.
-  if (P->dense && !P->block_mfma && P->nb > 0 && !P->capture && !P->in_batch && P->nb * kSlices > kTileScanTiles &&
+  if (P->dense && !P->block_mfma && !P->dense_rows && P->nb > 0 && !P->capture && !P->in_batch &&
+      P->nb * kSlices > kTileScanTiles &&
       P->nb * kSlices > P->products / kTileScanProducts) {
     const int64_t nt = P->nb * kSlices;
     if ((st = P->allocate_n(nt, &P->tcnt))) return st;
@@ -1159,7 +1168,9 @@ sptc_status execute_plan(sptc_plan_s* P, int32_t* out_idx, double* out_val, int6
     // the wave class first: its outputs' positions come from a scan and
     // follow the direct class's; the later classes reserve theirs by atomics
     HIP_TRY(launch_wave_class(a, P->wlist, P->nw, P->wcnt, P->woff, P->tile_sums, P->num_cus, s));
-    if (P->dense && !P->block_mfma && P->nb > 0)
+    if (P->dense_rows)
+      HIP_TRY(launch_group_block(a, P->blist, P->nb, P->num_cus, s, nullptr, dense_cells(P->bits_fy)));
+    else if (P->dense && !P->block_mfma && P->nb > 0)
       HIP_TRY(launch_lds_queue(a, P->blist, P->nb, P->yso, P->ytab_slots, dense_cells(P->bits_fy), P->queue, P->tcnt,
                                P->toff, P->tsums, P->num_cus, s));
     if (P->block_mfma)
@@ -1477,6 +1488,7 @@ sptc_status sptc_plan_info(sptc_plan_t P, sptc_info* info) {
   info->block_mfma_work = P->block_mfma ? (int64_t)mfma_work(P->nb, P->mplan.ncols, P->y_groups) : 0;
   info->block_tiles_scanned = P->tcnt != nullptr;
   info->operands_swapped = P->swapped ? 1 : 0;
+  info->block_dense_rows = P->dense_rows ? 1 : 0;
   return SPTC_OK;
 }
 

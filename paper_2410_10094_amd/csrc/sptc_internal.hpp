@@ -359,8 +359,11 @@ struct GroupArgs {
 hipError_t prepare_group_block();
 // Hashed block class (Y free key wider than kDenseBits).
 // dc (optional): the block-class count read on the device (nb sizes the grid).
+// cells > 0: a dense Y free key and small groups, each accumulated in a
+// dense LDS row of `cells` doubles (a power of two, 64..2^kDenseBits) by one
+// workgroup, in place of the (group, slice) tiles.
 hipError_t launch_group_block(const GroupArgs& a, const uint32_t* blist, int64_t nb, int num_cus, hipStream_t stream,
-                              const DevStatus* dc = nullptr);
+                              const DevStatus* dc = nullptr, unsigned cells = 0);
 
 // Block survey, before the class counts are read back: the block class's
 // products into st->block_products (zeroed first; the block list's length

@@ -39,7 +39,8 @@ def run_gpu(p, options=None, allocator="pool", mode=None, order=1):
         info = dict(products=pl.products, out_nnz_bound=pl.out_nnz_bound, y_groups=pl.y_groups,
                     out_order=pl.out_order, out_dims=pl.out_dims, out_table_slots=pl.out_table_slots,
                     mode=pl.mode, x_groups=pl.x_groups, classes=pl.group_classes, block_mfma=pl.block_mfma,
-                    block_tiles_scanned=pl.block_tiles_scanned, operands_swapped=pl.operands_swapped)
+                    block_tiles_scanned=pl.block_tiles_scanned, operands_swapped=pl.operands_swapped,
+                    block_dense_rows=pl.block_dense_rows)
         return info, idx.cpu().numpy(), val.cpu().numpy()
 
 

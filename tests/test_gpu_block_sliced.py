@@ -3,7 +3,8 @@ walked as (group, slice of the Y free key space) tiles: runs short enough
 to be sorted and runs cut slice by slice without sorting, every lanes-per-
 entry variant, the smallest and the largest accumulator, repeated Y
 coordinates and explicit zeros, tiles placed by an atomic each or by a
-count pass and a scan.  Against the oracle, element by element."""
+count pass and a scan, and small groups accumulated whole in a dense row.
+Against the oracle, element by element."""
 import numpy as np
 import pytest
 
@@ -54,11 +55,12 @@ CASES = [
     ("explicit-zeros", lambda: _matrix_like(7, 200, 150, 4096, 20_000, 60_000, "explicit-zeros", zeros=0.3)),
     # few large tiles (about 24,000 products each)
     ("few-large-tiles", lambda: _matrix_like(9, 16, 64, 4096, 1024, 192_000, "few-large-tiles")),
-    # over 131,072 tiles of about 60 products: counted, then placed by a
-    # scan (every case above reserves each tile's outputs with an atomic)
-    ("many-small-tiles", lambda: _matrix_like(10, 40_000, 2_000, 4096, 200_000, 200_000, "many-small-tiles")),
+    # groups of about 680 products: each accumulated whole, its dense row in
+    # one workgroup, instead of eight thin tiles
+    ("small-groups-dense-rows", lambda: _matrix_like(10, 40_000, 2_000, 4096, 200_000, 200_000,
+                                                     "small-groups-dense-rows")),
 ]
-SCANNED = {c[0]: c[0] == "many-small-tiles" for c in CASES}
+DENSE_ROWS = {c[0]: c[0] == "small-groups-dense-rows" for c in CASES}
 
 
 @pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
@@ -67,8 +69,21 @@ def test_sliced_block_class(name, make):
     log(f"[sliced] {p.name} nnz {p.X.nnz}x{p.Y.nnz}")
     info, gidx, gval = run_gpu(p)
     assert info["classes"]["block"] > 0 and not info["block_mfma"], info["classes"]
-    assert info["block_tiles_scanned"] == SCANNED[name], (info["products"], info["classes"])
+    assert info["block_dense_rows"] == DENSE_ROWS[name], (info["products"], info["classes"])
+    assert not info["block_tiles_scanned"]
     assert_parity(p, gidx, gval)
+
+
+def test_many_tiles_counted_then_placed_by_a_scan():
+    """Over 131,072 tiles (16,400 groups x 8 slices) of 1,024 products:
+    each tile's outputs are counted, a scan places them, and a second walk
+    writes them (no atomic per tile).  134M products, against the oracle."""
+    import oracle
+    p = _matrix_like(11, 16_400, 64, 4096, 16_400 * 64, 64 * 128, "many-tiles")
+    log(f"[sliced] {p.name} nnz {p.X.nnz}x{p.Y.nnz}")
+    info, gidx, gval = run_gpu(p)
+    assert info["block_tiles_scanned"] and not info["block_dense_rows"], (info["products"], info["classes"])
+    assert_parity(p, gidx, gval, oracle.contract(p.X, p.Y, p.cx, p.cy, nthreads=16))
 
 
 def test_sliced_block_class_order4():

@@ -143,6 +143,12 @@ def _class_problems():
     Y = Coo((40, 1 << 16), np.stack([rng.integers(0, 40, 2000), rng.integers(0, 1 << 16, 2000)]).astype(np.int32),
             W.nonzero_uniform(rng, 2000))
     out.append(("block", Problem("block-hash", X, Y, (1,), (0,))))
+    # block, hash, both table sizes: rows 0-49 with ~15 entries (bounds below
+    # 1,433: the 2,048-slot table), rows 50-99 with 40 (bounds ~2,000: 4,096)
+    xs = np.concatenate([np.stack([rng.integers(0, 50, 750), rng.integers(0, 40, 750)]),
+                         np.stack([np.repeat(np.arange(50, 100), 40), np.tile(np.arange(40), 50)])], axis=1)
+    X = Coo((100, 40), xs.astype(np.int32), W.nonzero_uniform(rng, xs.shape[1]))
+    out.append(("block", Problem("block-hash-two-sizes", X, Y, (1,), (0,))))
     # global: groups with more distinct outputs than a workgroup's LDS holds
     X = Coo((3, 8), np.stack([rng.integers(0, 3, 200), rng.integers(0, 8, 200)]).astype(np.int32),
             W.nonzero_uniform(rng, 200))
