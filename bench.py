@@ -33,6 +33,8 @@ DESCRIPTIONS = {
                          "X modes (2,3) with Y modes (0,1)",
     "imbalanced": "imbalanced order-3 SpTC: X 1e7 nnz on 2^17x2^14x2^15 (contracting mode Zipf 1.2), "
                   "Y 1e6 nnz on 2^15x2^12x2^10, X mode 2 with Y mode 0",
+    "paper-set-50-5x5-500K": "synthetic set 1 (Table 1): order-5 x order-5, all modes 50, 500K random nnz each, "
+                             "modes (1,2) contracted",
 }
 
 
@@ -157,7 +159,8 @@ def run_workload(name, steps, warmup, with_events=True, mode="grouped", block_mf
                     workspace_bytes=pl0.workspace_bytes, key_bits=pl0.key_bits, x_groups=pl0.x_groups,
                     group_classes=pl0.group_classes, direct_groups=pl0.group_classes["direct"],
                     direct_products=pl0.direct_products, block_mfma=pl0.block_mfma,
-                    block_mfma_work=pl0.block_mfma_work)
+                    block_mfma_work=pl0.block_mfma_work, block_dense_rows=pl0.block_dense_rows,
+                    block_tiles_scanned=pl0.block_tiles_scanned, operands_swapped=pl0.operands_swapped)
 
     nst = len(B.STAGES)
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2 * nst)] for _ in range(steps)]
@@ -438,21 +441,28 @@ def run_batched(draws, dev, steps, warmup, budget, load_factor=1 / 1.3, tile=0):
 # holds while the kernel's sources are the ones profiled.
 TRAFFIC_PROFILES = {
     ("block-sparse-1.5M", "k_lds_queue"): "lds_queue_block-sparse-1.5M_counters.md",
-    ("block-sparse-1.5M", "k_group_block_mfma"): "block_mfma_block-sparse-1.5M_hbm_counters.md",
+    ("block-sparse-1.5M", "k_group_block_mfma"): "block_mfma_block-sparse-1.5M_counters.md",
     ("imbalanced", "k_group_direct"): "direct_imbalanced_counters.md",
     ("block-sparse-1.5M", "k_expand_acc"): "expand_global_block-sparse-1.5M_counters.md",
     ("imbalanced", "k_expand_acc"): "expand_global_imbalanced_counters.md",
+    ("paper-set-50-5x5-500K", "k_group_block"): "group_block_paper-set-50-5x5-500K_counters.md",
 }
-KERNEL_SOURCES = ("paper_2410_10094_amd/csrc/grouped.hip", "paper_2410_10094_amd/csrc/block_mfma.hip",
-                  "paper_2410_10094_amd/csrc/kernels.hip", "paper_2410_10094_amd/csrc/queue.hip",
-                  "paper_2410_10094_amd/csrc/lds_items.hpp", "paper_2410_10094_amd/csrc/prim.hpp",
-                  "paper_2410_10094_amd/csrc/sptc_internal.hpp")
+_CSRC = "paper_2410_10094_amd/csrc/"
+_COMMON = (_CSRC + "prim.hpp", _CSRC + "sptc_internal.hpp")
+# the sources each kernel is compiled from
+KERNEL_SOURCES = {
+    "k_lds_queue": (_CSRC + "queue.hip", _CSRC + "lds_items.hpp") + _COMMON,
+    "k_group_block": (_CSRC + "grouped.hip", _CSRC + "lds_items.hpp") + _COMMON,
+    "k_group_direct": (_CSRC + "grouped.hip", _CSRC + "lds_items.hpp") + _COMMON,
+    "k_expand_acc": (_CSRC + "kernels.hip",) + _COMMON,
+    "k_group_block_mfma": (_CSRC + "block_mfma.hip",) + _COMMON,
+}
 
 
-def kernel_source_hash():
+def kernel_source_hash(kernel):
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in KERNEL_SOURCES[kernel]:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -471,7 +481,7 @@ def measured_traffic(workload, kernel):
             if ":" in line and line.startswith("- "):
                 k, v = line[2:].split(":", 1)
                 fields[k.strip()] = v.strip().strip("`")
-    if fields.get("source_sha256") != kernel_source_hash():
+    if kernel not in KERNEL_SOURCES or fields.get("source_sha256") != kernel_source_hash(kernel):
         return None
     try:
         return int(fields["traffic_bytes_per_launch"])
@@ -536,6 +546,8 @@ def kernel_of(stage, info):
     if stage == "block":
         if info.get("block_mfma"):
             return "k_group_block_mfma"
+        if info.get("block_dense_rows"):
+            return "k_group_block"
         return "k_lds_queue" if info["key_bits"][2] <= 13 else "k_group_block"
     return {"direct": "k_group_direct", "expand": "k_expand_acc", "compact": "occupancy scan", "x_probe": "X grouping",
             "x_sort": "block entry sort"}.get(stage, stage)

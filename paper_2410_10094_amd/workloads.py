@@ -280,4 +280,6 @@ WORKLOADS = {
     "block-sparse": lambda: block_sparse(),
     "block-sparse-1.5M": lambda: block_sparse(p_block=0.565),
     "imbalanced": lambda: imbalanced(),
+    # the largest shape of the synthetic sets' sweep (set 1, order 5 x 5)
+    "paper-set-50-5x5-500K": lambda: paper_set(BASE_SEED + 10 + 5 + 5, 50, 500_000, 5, 5),
 }

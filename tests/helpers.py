@@ -84,24 +84,27 @@ def sort_coo(idx: np.ndarray, *vals):
 
 def value_tolerance(ref_val, absval, terms, rel=1e-12):
     """Allowed |gpu - oracle| per output: the larger of rel*|z| and
-    min(2*(k-1)*u*S, rel*S), where k is the output's number of terms and S
+    min(2.0002*k*u*S, rel*S), where k is the output's number of terms and S
     their sum of |x*y|; a single-term output must match bit for bit.
 
     Where a sum cancels, rel*|z| alone would ask for more than either side's
     rounding can give, so the bar falls back to rel*S (1e-12 of the summation
     error scale).  Below about 4,500 terms the rounding-error bound is the
-    tighter of the two: both sides round each product once (the oracle) or
-    never (a fused multiply-add) and add the terms in different orders, and
-    recursive summation of k terms in any order stays within (k-1)*u*S of
-    the exact sum, so two orders differ by at most 2*(k-1)*u*S.  Above it
-    the bar stays at rel*S: a statistical bar there, not a worst case (the
-    worst case grows with k; rounding errors of many terms behave like a
-    random walk, of order sqrt(k)*u*S).  A repeated X coordinate summed before
-    its multiply adds one more rounding of its terms, within the same
-    bound."""
+    tighter of the two.  With fl(a op b) = (a op b)(1 + d), |d| <= u, and
+    gamma_n = n*u/(1 - n*u): a sum of the k rounded products in any order
+    (the oracle, the LDS classes) is within u*S + gamma_(k-1)*(1+u)*S <=
+    gamma_k*S of the exact sum; a chain of k fused multiply-adds from zero
+    (the matrix cores: each exact product added with one rounding) is within
+    gamma_k*S too, and so is that chain when r repeated X coordinates are
+    summed before their multiply (r - 1 more roundings on those terms, r - 1
+    fewer steps in the chain: no term is rounded more than k times).  Two
+    results within gamma_k*S of the same exact sum differ by at most
+    2*gamma_k*S <= 2.0002*k*u*S (k*u <= 1e-4).  Above about 4,500 terms the
+    bar stays at rel*S: a statistical bar there, not a worst case (rounding
+    errors of many terms behave like a random walk, of order sqrt(k)*u*S)."""
     k = np.asarray(terms, dtype=np.float64)
     S = np.asarray(absval)
-    bound = np.minimum(2.0 * np.maximum(k - 1.0, 0.0) * U * 1.0001 * S, rel * S)
+    bound = np.minimum(2.0002 * k * U * S, rel * S)
     return np.maximum(rel * np.abs(ref_val), bound) * (k > 1)
 
 
