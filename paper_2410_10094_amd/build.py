@@ -14,8 +14,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB_PATH = os.path.join(HERE, "libsptc.so")
 SOURCES = [os.path.join(CSRC, "kernels.hip"), os.path.join(CSRC, "grouped.hip"), os.path.join(CSRC, "batch.hip"),
-           os.path.join(CSRC, "block_mfma.hip"), os.path.join(CSRC, "queue.hip"), os.path.join(CSRC, "noalloc.hip"), os.path.join(CSRC, "sptc.cpp")]
-HEADERS = [os.path.join(CSRC, "sptc_internal.hpp"), os.path.join(CSRC, "prim.hpp"), os.path.join(ROOT, "include", "sptc.h")]
+           os.path.join(CSRC, "block_mfma.hip"), os.path.join(CSRC, "queue.hip"), os.path.join(CSRC, "xpart.hip"), os.path.join(CSRC, "noalloc.hip"), os.path.join(CSRC, "sptc.cpp")]
+HEADERS = [os.path.join(CSRC, "sptc_internal.hpp"), os.path.join(CSRC, "prim.hpp"), os.path.join(CSRC, "xpart.hpp"), os.path.join(ROOT, "include", "sptc.h")]
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [

@@ -18,6 +18,7 @@
 
 #include "../../include/sptc.h"
 #include "sptc_internal.hpp"
+#include "xpart.hpp"
 
 using namespace sptc;
 
@@ -704,8 +705,19 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
   sptc_status st;
   // hashed X free keys of at most 31 bits: the compact table
   const bool x32 = !P->x_agg && !P->xgeom.reg && !P->xgeom.ident && P->bits_fx <= 31 && P->nx < ((int64_t)1 << 31);
+  // ... grouped by partition (no device atomic per entry) up to kPartMaxEntries
+  const bool xpart = x32 && P->nx <= kPartMaxEntries;
   unsigned long long* xtab32 = nullptr;
-  if (x32) {
+  XPartBuffers xw{};
+  if (xpart) {
+    const int64_t nbk = (int64_t)1 << part_bits(P->nx), nh = nbk * part_tiles(P->nx);
+    unsigned long long* scan = nullptr;
+    if ((st = P->allocate_n(P->nx, &xw.pkey)) || (st = P->allocate_n(P->nx, &xw.prec)) ||
+        (st = P->allocate_n(nh, &xw.hist)) || (st = P->allocate_n(nbk, &xw.bdist)) ||
+        (st = P->allocate_n(nbk, &xw.gbase)) || (st = P->allocate_n(scan_tiles(std::max(nh, nbk)) + 1, &scan)))
+      return st;
+    xw.scan = scan;
+  } else if (x32) {
     if ((st = P->allocate_n(P->xtab_slots, &xtab32))) return st;
   } else if ((st = P->allocate_n(P->xtab_slots, &P->xtab))) {
     return st;
@@ -722,7 +734,11 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
   if (P->x_agg && (st = P->allocate_n((agg_chunks(P->nx) + 1) * P->xtab_slots, &P->xhist))) return st;
 
   HIP_TRY(mark(P, s, SPTC_STAGE_X_PROBE, 0));
-  if (x32) {
+  if (xpart) {
+    HIP_TRY(prepare_x_partition());
+    HIP_TRY(launch_x_partition(X->idx, X->val, P->nx, P->x_f, P->x_c, P->xb, P->ytab, P->ygeom, P->max_probe_y, seed,
+                               xw, P->groups, P->xr, P->st, P->num_cus, s));
+  } else if (x32) {
     HIP_TRY(launch_x_table32(X->idx, X->val, P->nx, P->x_f, P->x_c, P->xb, xtab32, P->xgeom, P->max_probe_x,
                              P->groups, P->ytab, P->ygeom, P->max_probe_y, seed, P->xr, P->tile_sums, P->st,
                              P->num_cus, s));

@@ -105,7 +105,12 @@ def test_stage_x_groups():
     product counts (the bound of section 4.3), all exact."""
     import paper_2410_10094_amd as sptc
     for p in [W.block_sparse(n=24, block=4), W.plain(),
-              W.random_problem(92, 4, 3, 1, 2, 7, 5000, 3000, duplicates=True)]:
+              W.random_problem(92, 4, 3, 1, 2, 7, 5000, 3000, duplicates=True),
+              # X free keys of 22 and 24 bits, hashed: grouped by partition
+              # into 16 and 8 buckets (the second with repeated coordinates)
+              W.imbalanced(nnz_x=50_000, nnz_y=20_000, xdims=(1 << 12, 1 << 10, 1 << 10),
+                           ydims=(1 << 10, 1 << 8, 1 << 6)),
+              W.random_problem(93, 3, 3, 1, 2000, 3000, 30_000, 5_000, duplicates=True)]:
         log(f"[stage-X] {p.name}")
         X, Y = to_device(p)
         with sptc.plan(X, Y, p.cx, p.cy, options=sptc.default_options(operand_order=1)) as pl:
