@@ -456,32 +456,44 @@ __device__ __forceinline__ void bitonic_sort_lds(unsigned long long* a, unsigned
 
 // Block class, one workgroup of BLOCK threads per group.  KIND 0 and 1: a
 // Y free key too wide for a dense accumulator, an LDS hash of up to SLOTS
-// slots; a group is taken by the instance whose table its bound fits (0: at
-// most 70% of the small table's slots; 1: the rest), so that small groups
-// run four to a CU instead of two.  KIND 2: a dense Y free key and small
-// groups (a few (group, slice) tiles' worth of products): the group's whole
-// output row as a dense LDS array of `cells` doubles, cells starting at -0.0
-// and products added as x * y + 0.0, so a cell is an output exactly when it
-// is no longer -0.0 (see the sliced tiles).  When the group has enough X
-// entries for every wave and they average many products, each wave walks
-// whole Y runs (coalesced, no search); otherwise the products are spread
-// over all threads by a search over the staged entry offsets.  Then each
-// wave counts the outputs in its share of the table, one atomic on the
-// output cursor reserves the group's, and each wave writes its share.
+// slots (keys, then values: 8-byte words at random slots spread over twice
+// the LDS banks that 16-byte {key, value} slots would use).  KIND 0 walks
+// the class list and takes the groups whose bound fits its table (at most
+// 70% of its slots), four workgroups to a CU; it appends the others to
+// `defer` (count in ndefer), which KIND 1, with the large table, walks
+// afterwards, so that neither walks the other's groups.  KIND 2: a dense Y
+// free key and small groups (a few (group, slice) tiles' worth of
+// products): the group's whole output row as a dense LDS array of `cells`
+// doubles, cells starting at -0.0 and products added as x * y + 0.0, so a
+// cell is an output exactly when it is no longer -0.0 (see the sliced
+// tiles).  When the group has enough X entries for every wave and they
+// average many products, each wave walks whole Y runs (coalesced, no
+// search); otherwise the products are spread over all threads by a search
+// over the staged entry offsets.  Then each wave counts the outputs in its
+// share of the table, one atomic on the output cursor reserves the group's,
+// and each wave writes its share.  The next group's list entry, record and
+// product count are loaded one step per phase of the current group, so
+// that their chain of dependent loads is not on the critical path.
 template <int BLOCK, int SLOTS, int KIND>
 __global__ __launch_bounds__(BLOCK) void k_group_block(GroupArgs a, const uint32_t* __restrict__ blist, int64_t nb,
-                                                       const DevStatus* dc, unsigned cells) {
+                                                       const DevStatus* dc, unsigned cells, uint32_t* defer,
+                                                       QueueCounter* ndefer) {
   constexpr int kBChunk = BLOCK / 2;  // X entries staged at a time (LDS: the table dominates)
   constexpr unsigned long long kSmallCap = (unsigned long long)kBlockSmallSlots * 7 / 10;
-  if (dc) nb = (int64_t)dc->n_block;  // the count read on the device
+  if (KIND == 1 && defer)
+    nb = (int64_t)ndefer->v;  // the groups KIND 0 passed on
+  else if (dc)
+    nb = (int64_t)dc->n_block;  // the count read on the device
+  const uint32_t* __restrict__ list = KIND == 1 && defer ? defer : blist;
   extern __shared__ __align__(16) unsigned char s_dyn[];
   __shared__ unsigned long long s_off[kBChunk];
   __shared__ unsigned s_ys[kBChunk];
   __shared__ double s_v[kBChunk];
   __shared__ unsigned long long s_wave[BLOCK / 64 + 1];
   __shared__ unsigned long long s_base;
-  ZSlot* tab = reinterpret_cast<ZSlot*>(s_dyn);
-  double* acc = reinterpret_cast<double*>(s_dyn);
+  unsigned long long* tkey = reinterpret_cast<unsigned long long*>(s_dyn);  // KIND 0, 1: SLOTS keys
+  double* tval = reinterpret_cast<double*>(s_dyn + (size_t)SLOTS * 8);       // then SLOTS values
+  double* acc = reinterpret_cast<double*>(s_dyn);                            // KIND 2: the dense row
   const unsigned tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr unsigned kWaves = BLOCK / 64;
 
@@ -493,12 +505,33 @@ __global__ __launch_bounds__(BLOCK) void k_group_block(GroupArgs a, const uint32
   const unsigned nxcd = gridDim.x % kXcds == 0 ? kXcds : 1u;
   const unsigned xcd = blockIdx.x % nxcd, per_xcd = gridDim.x / nxcd;
   const int64_t lo = nb * xcd / nxcd, hi = nb * (xcd + 1) / nxcd;
-  for (int64_t i = lo + blockIdx.x / nxcd; i < hi; i += per_xcd) {
-    const uint32_t g = blist[i];
-    const GroupRec G = a.groups[g];
-    const unsigned long long b = a.eoff[G.start + G.count] - a.eoff[G.start];
+  int64_t i = lo + blockIdx.x / nxcd;
+  uint32_t gn = 0;
+  GroupRec Gn{};
+  unsigned long long bn = 0;
+  if (i < hi) {
+    gn = list[i];
+    Gn = a.groups[gn];
+    bn = a.eoff[Gn.start + Gn.count] - a.eoff[Gn.start];
+  }
+  for (; i < hi; i += per_xcd) {
+    const uint32_t g = gn;
+    const GroupRec G = Gn;
+    const unsigned long long b = bn;
+    const int64_t inext = i + per_xcd;
+    const bool more = inext < hi;
+    uint32_t gq = 0;
+    if (more) gq = list[inext];  // the next group: its list entry now
     const unsigned long long d = b < a.ycells ? b : a.ycells;
-    if (KIND != 2 && (d <= kSmallCap) != (KIND == 0)) continue;  // the other instance's group (uniform)
+    if (KIND != 2 && (d <= kSmallCap) != (KIND == 0)) {  // the other instance's group (uniform)
+      if (KIND == 0 && defer && tid == 0) defer[atomicAdd(&ndefer->v, 1ull)] = g;
+      if (more) {
+        gn = gq;
+        Gn = a.groups[gq];
+        bn = a.eoff[Gn.start + Gn.count] - a.eoff[Gn.start];
+      }
+      continue;
+    }
     const unsigned tsize =
         KIND == 2 ? cells : (table_size_for(d, SLOTS) < (unsigned)BLOCK ? (unsigned)BLOCK : table_size_for(d, SLOTS));
     const unsigned tmask = tsize - 1;
@@ -506,11 +539,13 @@ __global__ __launch_bounds__(BLOCK) void k_group_block(GroupArgs a, const uint32
       if constexpr (KIND == 2) {
         acc[s] = -0.0;
       } else {
-        tab[s].key = kEmpty;
-        tab[s].val = 0.0;
+        tkey[s] = kEmpty;
+        tval[s] = 0.0;
       }
     }
     __syncthreads();
+    GroupRec Gq{};
+    if (more) Gq = a.groups[gq];  // the next group: its record
 
     auto accumulate = [&](unsigned long long key, double pv) {
       if constexpr (KIND == 2) {
@@ -519,7 +554,16 @@ __global__ __launch_bounds__(BLOCK) void k_group_block(GroupArgs a, const uint32
         else
           record_error(a.st, kErrInternal);
       } else {
-        if (!lds_accumulate(tab, tmask, key, pv, a.seed)) record_error(a.st, kErrCapacity);
+        unsigned s = (unsigned)fmix64(key ^ a.seed) & tmask;
+        for (unsigned probe = 0; probe <= tmask; ++probe) {
+          const unsigned long long prev = atomicCAS(&tkey[s], (unsigned long long)kEmpty, key);
+          if (prev == kEmpty || prev == key) {
+            atomicAdd(&tval[s], pv);
+            return;
+          }
+          s = (s + 1) & tmask;
+        }
+        record_error(a.st, kErrCapacity);
       }
     };
 
@@ -581,9 +625,12 @@ __global__ __launch_bounds__(BLOCK) void k_group_block(GroupArgs a, const uint32
         __syncthreads();
       }
     } else {
-      // product-parallel over chunks of kBChunk entries
+      // product-parallel over chunks of kBChunk entries: product q of the
+      // chunk belongs to the last staged entry whose offset is <= q, found
+      // by a branch-free search over the chunk's n entries
       for (unsigned base = 0; base < G.count; base += kBChunk) {
         const unsigned e = base + tid;
+        const unsigned n = G.count - base < (unsigned)kBChunk ? G.count - base : (unsigned)kBChunk;
         unsigned long long c = 0;
         unsigned ys = 0;
         double v = 0.0;
@@ -601,14 +648,12 @@ __global__ __launch_bounds__(BLOCK) void k_group_block(GroupArgs a, const uint32
           s_v[tid] = v;
         }
         __syncthreads();
+        const int top = n > 1 ? 1 << (31 - __clz((int)n - 1)) : 0;  // the largest power of two below n
         for (unsigned long long q = tid; q < tot; q += BLOCK) {
-          int lo = 0, hi = kBChunk - 1;
-          while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_off[mid] <= q)
-              lo = mid;
-            else
-              hi = mid - 1;
+          int lo = 0;
+          for (int step = top; step > 0; step >>= 1) {
+            const int c2 = lo + step;
+            if (c2 < (int)n && s_off[c2] <= q) lo = c2;
           }
           const unsigned long long y = (unsigned long long)s_ys[lo] + (q - s_off[lo]);
           if (y >= (unsigned long long)a.ny) {
@@ -622,6 +667,8 @@ __global__ __launch_bounds__(BLOCK) void k_group_block(GroupArgs a, const uint32
       }
     }
     __syncthreads();
+    unsigned long long bq = 0;
+    if (more) bq = a.eoff[Gq.start + Gq.count] - a.eoff[Gq.start];  // the next group: its product count
 
     // count, reserve, write: wave w takes slots [w R, (w + 1) R)
     const unsigned R = tsize / kWaves;  // tsize >= BLOCK: a multiple of 64
@@ -629,7 +676,7 @@ __global__ __launch_bounds__(BLOCK) void k_group_block(GroupArgs a, const uint32
       if constexpr (KIND == 2)
         return __double_as_longlong(acc[s]) != (long long)0x8000000000000000ull;
       else
-        return tab[s].key != kEmpty;
+        return tkey[s] != kEmpty;
     };
     unsigned n = 0;
     for (unsigned s0 = wave * R; s0 < (wave + 1) * R; s0 += 64) n += (unsigned)__popcll(__ballot(occupied(s0 + lane)));
@@ -651,8 +698,8 @@ __global__ __launch_bounds__(BLOCK) void k_group_block(GroupArgs a, const uint32
       const bool occ = occupied(s);
       const unsigned long long m = __ballot(occ);
       if (occ) {
-        const unsigned long long key = KIND == 2 ? (unsigned long long)s : tab[s].key;
-        const double val = KIND == 2 ? acc[s] : tab[s].val;
+        const unsigned long long key = KIND == 2 ? (unsigned long long)s : tkey[s];
+        const double val = KIND == 2 ? acc[s] : tval[s];
         const unsigned long long at = pos + lanes_below(m);
         if (a.bout)
           batch_store(a.bout, a.out_idx, a.out_val, a.bwx, (uint32_t)(G.phi >> a.bwx), at, G.phi, key, val, a.st);
@@ -662,6 +709,9 @@ __global__ __launch_bounds__(BLOCK) void k_group_block(GroupArgs a, const uint32
       pos += (unsigned long long)__popcll(m);
     }
     __syncthreads();
+    gn = gq;
+    Gn = Gq;
+    bn = bq;
   }
 }
 
@@ -952,6 +1002,7 @@ __global__ void k_reset_status(DevStatus* st, LdsQueue* q) {
   st->out_base = st->direct_products;
   if (q) {
     for (int s = 0; s < kSlices; ++s) q->next_tile[s].v = q->next_fill[s].v = 0ull;
+    q->n_defer.v = 0ull;
   }
 }
 
@@ -1071,28 +1122,33 @@ hipError_t prepare_group_block() {
   return e;
 }
 
-// Hashed: both instances walk the whole list, each taking the groups its
-// table fits: four small-table workgroups of 256 threads per CU, two of
-// 1024.  Dense (cells > 0): 256-thread workgroups with a row of cells.
+// Hashed: the small-table instance walks the list, four workgroups of 256
+// threads per CU, and passes the groups its table cannot hold to the
+// large-table instance, two workgroups of 1024 per CU, which reads their
+// count on the device.  Dense (cells > 0): 256-thread workgroups with a row
+// of cells.
 hipError_t launch_group_block(const GroupArgs& a, const uint32_t* blist, int64_t nb, int num_cus,
-                              hipStream_t stream, const DevStatus* dc, unsigned cells) {
+                              hipStream_t stream, const DevStatus* dc, unsigned cells, uint32_t* defer, LdsQueue* q) {
   if (nb <= 0) return hipSuccess;
   if (cells) {
     if (cells < 64u || (cells & (cells - 1u)) || cells > (1u << kDenseBits)) return hipErrorInvalidValue;
     unsigned grid = grid_for(nb, 1, num_cus, std::min(8, std::max(1, (160 << 10) / (int)(cells * 8 + (8 << 10)))));
     if (grid >= kXcds) grid -= grid % kXcds;
-    k_group_block<kBSmallBlock, 0, 2><<<grid, kBSmallBlock, cells * 8, stream>>>(a, blist, nb, dc, cells);
+    k_group_block<kBSmallBlock, 0, 2><<<grid, kBSmallBlock, cells * 8, stream>>>(a, blist, nb, dc, cells, nullptr,
+                                                                                 nullptr);
     return hipGetLastError();
   }
+  if (!defer || !q) return hipErrorInvalidValue;
   unsigned grid = grid_for(nb, 1, num_cus, 4);
   if (grid >= kXcds) grid -= grid % kXcds;
-  k_group_block<kBSmallBlock, kBlockSmallSlots, 0><<<grid, kBSmallBlock, kBlockSmallSlots * 16, stream>>>(a, blist,
-                                                                                                      nb, dc, 0u);
+  k_group_block<kBSmallBlock, kBlockSmallSlots, 0><<<grid, kBSmallBlock, kBlockSmallSlots * 16, stream>>>(
+      a, blist, nb, dc, 0u, defer, &q->n_defer);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   grid = grid_for(nb, 1, num_cus, 2);
   if (grid >= kXcds) grid -= grid % kXcds;
-  k_group_block<kBBlock, kBlockSlots, 1><<<grid, kBBlock, kBlockSlots * 16, stream>>>(a, blist, nb, dc, 0u);
+  k_group_block<kBBlock, kBlockSlots, 1><<<grid, kBBlock, kBlockSlots * 16, stream>>>(a, blist, nb, dc, 0u, defer,
+                                                                                       &q->n_defer);
   return hipGetLastError();
 }
 

@@ -305,6 +305,7 @@ struct sptc_plan_s : Workspace {
   unsigned long long* toff = nullptr;  // and its offset
   unsigned long long* tsums = nullptr;  // scan scratch for them
   uint32_t* blist = nullptr;
+  uint32_t* bdefer = nullptr;          // hashed block class: groups passed to the large-table launch
   uint32_t* glist = nullptr;
   uint32_t* yso = nullptr;    // dense block class: where each slice of each Y run begins, per Y table slot
   int32_t block_mfma = 0;     // dense block class on the matrix cores
@@ -838,6 +839,7 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
   }
   if ((st = P->allocate_n(1, &P->queue))) return st;
   HIP_TRY(prepare_lds_queue());
+  if (P->nb > 0 && !P->dense && (st = P->allocate_n(P->nb, &P->bdefer))) return st;
   // Very many small dense tiles: each tile's atomic on the one output
   // cursor (serialised, about 12 ns each) would cost more than accumulating
   // the tiles twice, once to count their outputs and once to write them at
@@ -1192,7 +1194,8 @@ sptc_status execute_plan(sptc_plan_s* P, int32_t* out_idx, double* out_val, int6
     if (P->block_mfma)
       HIP_TRY(launch_group_block_mfma(a, P->blist, P->nb, P->mplan, P->num_cus, s));
     else if (!P->dense)
-      HIP_TRY(launch_group_block(a, P->blist, P->nb, P->num_cus, s, P->capture ? P->st : nullptr));
+      HIP_TRY(launch_group_block(a, P->blist, P->nb, P->num_cus, s, P->capture ? P->st : nullptr, 0u, P->bdefer,
+                                 P->queue));
     HIP_TRY(mark(P, s, SPTC_STAGE_BLOCK, 1));
     if (P->ngl == 0) {
       HIP_TRY(mark(P, s, SPTC_STAGE_COMPACT, 0));

@@ -362,8 +362,14 @@ hipError_t prepare_group_block();
 // cells > 0: a dense Y free key and small groups, each accumulated in a
 // dense LDS row of `cells` doubles (a power of two, 64..2^kDenseBits) by one
 // workgroup, in place of the (group, slice) tiles.
+// Hashed (cells == 0): defer (nb elements) and q are required; the
+// small-table launch passes the groups its table cannot hold on to the
+// large-table launch through defer and q->n_defer (zeroed by
+// launch_reset_status).
+struct LdsQueue;
 hipError_t launch_group_block(const GroupArgs& a, const uint32_t* blist, int64_t nb, int num_cus, hipStream_t stream,
-                              const DevStatus* dc = nullptr, unsigned cells = 0);
+                              const DevStatus* dc = nullptr, unsigned cells = 0, uint32_t* defer = nullptr,
+                              LdsQueue* q = nullptr);
 
 // Block survey, before the class counts are read back: the block class's
 // products into st->block_products (zeroed first; the block list's length
@@ -437,6 +443,7 @@ struct alignas(128) QueueCounter {
 struct LdsQueue {
   QueueCounter next_tile[kSlices];  // next block-class tile of each slice's queue
   QueueCounter next_fill[kSlices];  // the same for the fill pass of a two-pass launch
+  QueueCounter n_defer;             // hashed block groups passed to the large-table launch
 };
 
 // Plan time: block-class X records refer to their Y run by its table slot
