@@ -116,19 +116,21 @@ typedef enum sptc_stage {
   SPTC_STAGE_Y_COUNT = 0,    /* Y key table: clear, then count entries per contracting key */
   SPTC_STAGE_Y_SCAN = 1,     /* prefix sum of the counts: group boundaries */
   SPTC_STAGE_Y_SCATTER = 2,  /* grouped Y array */
-  SPTC_STAGE_X_PROBE = 3,    /* per X nonzero: its Y group */
+  SPTC_STAGE_X_PROBE = 3,    /* per X nonzero: its Y group (grouped mode: with X grouped by its free key) */
   SPTC_STAGE_P_SCAN = 4,     /* prefix sum of products per X nonzero; P */
   SPTC_STAGE_OUT_CLEAR = 5,  /* output hash: mark every slot empty */
   SPTC_STAGE_EXPAND = 6,     /* expand products, accumulate in the output hash */
   SPTC_STAGE_COMPACT = 7,    /* output hash -> COO: count, prefix sum, fill */
-  SPTC_STAGE_GROUP_COUNT = 8, /* (no longer marked: small groups run in stage BLOCK's persistent launch) */
-  SPTC_STAGE_GROUP_FILL = 9,  /* (no longer marked, as GROUP_COUNT) */
+  SPTC_STAGE_GROUP_COUNT = 8, /* (not marked: the wave class runs in stage BLOCK) */
+  SPTC_STAGE_GROUP_FILL = 9,  /* (not marked, as GROUP_COUNT) */
   SPTC_STAGE_DIRECT = 10,     /* grouped path, single-entry groups: write every product as an output */
-  SPTC_STAGE_BLOCK = 11,      /* grouped path, groups accumulated in LDS (small and large): one persistent
-                                 launch over a device work queue, then the hashed or matrix-core block class */
+  SPTC_STAGE_BLOCK = 11,      /* grouped path, groups accumulated in LDS: the wave class (count, scan,
+                                 fill), then the block class (dense (group, slice) tiles over per-XCD work
+                                 queues, dense rows, hashed tables, or the matrix cores) */
   SPTC_STAGE_BATCH_PACK = 12,   /* batch plan: key every contraction's entries with its index */
   SPTC_STAGE_BATCH_SEGMENTS = 13, /* batch plan: products and output segments per contraction */
-  SPTC_STAGE_X_SORT = 14,       /* grouped plan: dense block groups' X entries sorted by Y run */
+  SPTC_STAGE_X_SORT = 14,       /* grouped plan, dense block class: Y runs sorted and cut into slices for
+                                   the tiles (or the matrix-core panels built) */
   SPTC_NUM_STAGES = 15
 } sptc_stage;
 
@@ -162,7 +164,7 @@ typedef struct sptc_options {
                                 2048), 1024 or 2048 */
   int32_t lds_max_keys;      /* grouped mode: most distinct outputs a group with a hashed (wide) Y free key
                                 may accumulate in a workgroup's LDS table before it goes to the output hash in
-                                device memory: 0 (default, 2867) or 64..2867 */
+                                device memory: 0 (default, 5734) or 64..5734 */
   int64_t capture_out_cap;   /* 0 (default): sptc_plan reads its counts back.  > 0: sptc_plan makes no
                                 read-back at all (so sptc_plan and sptc_execute can be captured together into
                                 one HIP graph): every buffer is sized from the nonzero counts and from this

@@ -457,11 +457,12 @@ __device__ __forceinline__ void bitonic_sort_lds(unsigned long long* a, unsigned
 // Block class, one workgroup of BLOCK threads per group.  KIND 0 and 1: a
 // Y free key too wide for a dense accumulator, an LDS hash of up to SLOTS
 // slots (keys, then values: 8-byte words at random slots spread over twice
-// the LDS banks that 16-byte {key, value} slots would use).  KIND 0 walks
-// the class list and takes the groups whose bound fits its table (at most
-// 70% of its slots), four workgroups to a CU; it appends the others to
-// `defer` (count in ndefer), which KIND 1, with the large table, walks
-// afterwards, so that neither walks the other's groups.  KIND 2: a dense Y
+// the LDS banks that 16-byte {key, value} slots would use).  KIND 0 (2,048
+// slots, four workgroups to a CU) walks the class list; KIND 1 (4,096 or
+// 8,192 slots, two or one to a CU) walks in_list, *in_count entries.  Each
+// takes the groups whose bound fits its table (at most 70% of its slots)
+// and appends the others to out_list (count in *out_count) for the next
+// table size, so that no instance walks another's groups.  KIND 2: a dense Y
 // free key and small groups (a few (group, slice) tiles' worth of
 // products): the group's whole output row as a dense LDS array of `cells`
 // doubles, cells starting at -0.0 and products added as x * y + 0.0, so a
@@ -476,15 +477,17 @@ __device__ __forceinline__ void bitonic_sort_lds(unsigned long long* a, unsigned
 // that their chain of dependent loads is not on the critical path.
 template <int BLOCK, int SLOTS, int KIND>
 __global__ __launch_bounds__(BLOCK) void k_group_block(GroupArgs a, const uint32_t* __restrict__ blist, int64_t nb,
-                                                       const DevStatus* dc, unsigned cells, uint32_t* defer,
-                                                       QueueCounter* ndefer) {
+                                                       const DevStatus* dc, unsigned cells,
+                                                       const uint32_t* __restrict__ in_list,
+                                                       const QueueCounter* in_count, uint32_t* out_list,
+                                                       QueueCounter* out_count) {
   constexpr int kBChunk = BLOCK / 2;  // X entries staged at a time (LDS: the table dominates)
-  constexpr unsigned long long kSmallCap = (unsigned long long)kBlockSmallSlots * 7 / 10;
-  if (KIND == 1 && defer)
-    nb = (int64_t)ndefer->v;  // the groups KIND 0 passed on
+  constexpr unsigned long long kCap = (unsigned long long)SLOTS * 7 / 10;  // KIND 0, 1: the bound it takes
+  if (in_list)
+    nb = (int64_t)in_count->v;  // the groups the smaller table passed on
   else if (dc)
     nb = (int64_t)dc->n_block;  // the count read on the device
-  const uint32_t* __restrict__ list = KIND == 1 && defer ? defer : blist;
+  const uint32_t* __restrict__ list = in_list ? in_list : blist;
   extern __shared__ __align__(16) unsigned char s_dyn[];
   __shared__ unsigned long long s_off[kBChunk];
   __shared__ unsigned s_ys[kBChunk];
@@ -523,8 +526,13 @@ __global__ __launch_bounds__(BLOCK) void k_group_block(GroupArgs a, const uint32
     uint32_t gq = 0;
     if (more) gq = list[inext];  // the next group: its list entry now
     const unsigned long long d = b < a.ycells ? b : a.ycells;
-    if (KIND != 2 && (d <= kSmallCap) != (KIND == 0)) {  // the other instance's group (uniform)
-      if (KIND == 0 && defer && tid == 0) defer[atomicAdd(&ndefer->v, 1ull)] = g;
+    if (KIND != 2 && d > kCap) {  // for a larger table (uniform)
+      if (tid == 0) {
+        if (out_list)
+          out_list[atomicAdd(&out_count->v, 1ull)] = g;
+        else
+          record_error(a.st, kErrInternal);  // past the class's cap
+      }
       if (more) {
         gn = gq;
         Gn = a.groups[gq];
@@ -1002,7 +1010,7 @@ __global__ void k_reset_status(DevStatus* st, LdsQueue* q) {
   st->out_base = st->direct_products;
   if (q) {
     for (int s = 0; s < kSlices; ++s) q->next_tile[s].v = q->next_fill[s].v = 0ull;
-    q->n_defer.v = 0ull;
+    q->n_defer.v = q->n_defer2.v = 0ull;
   }
 }
 
@@ -1114,6 +1122,9 @@ hipError_t prepare_group_block() {
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_group_block<kBBlock, kBlockSlots, 1>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, kBlockSlots * 16);
   if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_group_block<kBBlock, kBlockXlSlots, 1>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kBlockXlSlots * 16);
+  if (e == hipSuccess)
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_group_block<kBSmallBlock, kBlockSmallSlots, 0>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, kBlockSmallSlots * 16);
   if (e == hipSuccess)
@@ -1124,9 +1135,10 @@ hipError_t prepare_group_block() {
 
 // Hashed: the small-table instance walks the list, four workgroups of 256
 // threads per CU, and passes the groups its table cannot hold to the
-// large-table instance, two workgroups of 1024 per CU, which reads their
-// count on the device.  Dense (cells > 0): 256-thread workgroups with a row
-// of cells.
+// large-table instance, two workgroups of 1024 per CU, which passes its
+// own misfits to the largest table, one workgroup of 1024 per CU; each
+// reads its count on the device.  Dense (cells > 0): 256-thread workgroups
+// with a row of cells.
 hipError_t launch_group_block(const GroupArgs& a, const uint32_t* blist, int64_t nb, int num_cus,
                               hipStream_t stream, const DevStatus* dc, unsigned cells, uint32_t* defer, LdsQueue* q) {
   if (nb <= 0) return hipSuccess;
@@ -1135,20 +1147,27 @@ hipError_t launch_group_block(const GroupArgs& a, const uint32_t* blist, int64_t
     unsigned grid = grid_for(nb, 1, num_cus, std::min(8, std::max(1, (160 << 10) / (int)(cells * 8 + (8 << 10)))));
     if (grid >= kXcds) grid -= grid % kXcds;
     k_group_block<kBSmallBlock, 0, 2><<<grid, kBSmallBlock, cells * 8, stream>>>(a, blist, nb, dc, cells, nullptr,
-                                                                                 nullptr);
+                                                                                 nullptr, nullptr, nullptr);
     return hipGetLastError();
   }
   if (!defer || !q) return hipErrorInvalidValue;
+  uint32_t* defer2 = defer + nb;
   unsigned grid = grid_for(nb, 1, num_cus, 4);
   if (grid >= kXcds) grid -= grid % kXcds;
   k_group_block<kBSmallBlock, kBlockSmallSlots, 0><<<grid, kBSmallBlock, kBlockSmallSlots * 16, stream>>>(
-      a, blist, nb, dc, 0u, defer, &q->n_defer);
+      a, blist, nb, dc, 0u, nullptr, nullptr, defer, &q->n_defer);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   grid = grid_for(nb, 1, num_cus, 2);
   if (grid >= kXcds) grid -= grid % kXcds;
-  k_group_block<kBBlock, kBlockSlots, 1><<<grid, kBBlock, kBlockSlots * 16, stream>>>(a, blist, nb, dc, 0u, defer,
-                                                                                       &q->n_defer);
+  k_group_block<kBBlock, kBlockSlots, 1><<<grid, kBBlock, kBlockSlots * 16, stream>>>(
+      a, blist, nb, dc, 0u, defer, &q->n_defer, defer2, &q->n_defer2);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  grid = grid_for(nb, 1, num_cus, 1);
+  if (grid >= kXcds) grid -= grid % kXcds;
+  k_group_block<kBBlock, kBlockXlSlots, 1><<<grid, kBBlock, kBlockXlSlots * 16, stream>>>(
+      a, blist, nb, dc, 0u, defer2, &q->n_defer2, nullptr, nullptr);
   return hipGetLastError();
 }
 

@@ -839,7 +839,7 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
   }
   if ((st = P->allocate_n(1, &P->queue))) return st;
   HIP_TRY(prepare_lds_queue());
-  if (P->nb > 0 && !P->dense && (st = P->allocate_n(P->nb, &P->bdefer))) return st;
+  if (P->nb > 0 && !P->dense && (st = P->allocate_n(2 * P->nb, &P->bdefer))) return st;
   // Very many small dense tiles: each tile's atomic on the one output
   // cursor (serialised, about 12 ns each) would cost more than accumulating
   // the tiles twice, once to count their outputs and once to write them at

@@ -150,8 +150,9 @@ struct alignas(16) DevStatus {
 // Capacities of the LDS accumulators (distinct outputs per X group).
 constexpr int kWaveSlots = 512;    // LDS hash slots per wave
 constexpr int kWaveCap = 358;      // largest distinct-output bound a wave takes (load <= 0.7)
-constexpr int kBlockSlots = 4096;  // LDS hash slots per workgroup
-constexpr int kBlockCap = 2867;    // largest distinct-output bound a workgroup hash takes
+constexpr int kBlockSlots = 4096;    // LDS hash slots per workgroup (large table)
+constexpr int kBlockXlSlots = 8192;  // and the largest table (128 KB: one workgroup per CU)
+constexpr int kBlockCap = 5734;      // largest distinct-output bound a workgroup hash takes (70% of 8192)
 constexpr int kDenseBits = 13;     // dense LDS accumulator when the Y free key has <= 13 bits
 
 // Block class on the matrix cores (dense Y free keys, one contraction).
@@ -362,9 +363,9 @@ hipError_t prepare_group_block();
 // cells > 0: a dense Y free key and small groups, each accumulated in a
 // dense LDS row of `cells` doubles (a power of two, 64..2^kDenseBits) by one
 // workgroup, in place of the (group, slice) tiles.
-// Hashed (cells == 0): defer (nb elements) and q are required; the
-// small-table launch passes the groups its table cannot hold on to the
-// large-table launch through defer and q->n_defer (zeroed by
+// Hashed (cells == 0): defer (2 nb elements) and q are required; each of
+// the three table sizes' launches passes the groups its table cannot hold
+// on to the next through defer (counts q->n_defer, q->n_defer2, zeroed by
 // launch_reset_status).
 struct LdsQueue;
 hipError_t launch_group_block(const GroupArgs& a, const uint32_t* blist, int64_t nb, int num_cus, hipStream_t stream,
@@ -444,6 +445,7 @@ struct LdsQueue {
   QueueCounter next_tile[kSlices];  // next block-class tile of each slice's queue
   QueueCounter next_fill[kSlices];  // the same for the fill pass of a two-pass launch
   QueueCounter n_defer;             // hashed block groups passed to the large-table launch
+  QueueCounter n_defer2;            // and from it to the largest-table launch
 };
 
 // Plan time: block-class X records refer to their Y run by its table slot

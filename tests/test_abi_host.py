@@ -131,7 +131,7 @@ def test_plan_validation(case, status):
         opt.tile = 512
     elif case == "bad_lds_max_keys":
         opt = B.default_options()
-        opt.lds_max_keys = 5000
+        opt.lds_max_keys = 6000
     elif case == "negative_capture_out_cap":
         opt = B.default_options()
         opt.capture_out_cap = -1

@@ -142,18 +142,22 @@ def _class_problems():
     out[-1] = ("wave", Problem("wave-groups", X, Y, (2,), (0,)))
     # block, dense: Y free key of 12 bits, large groups
     out.append(("block", W.block_sparse(n=16, block=4, p_block=0.6, p_fill=0.8)))
-    # block, hash: Y free key wider than 13 bits, <= 2867 distinct outputs per group
+    # block, hash: Y free key wider than 13 bits, <= 5734 distinct outputs per group
     X = Coo((200, 40), np.stack([rng.integers(0, 200, 3000), rng.integers(0, 40, 3000)]).astype(np.int32),
             W.nonzero_uniform(rng, 3000))
     Y = Coo((40, 1 << 16), np.stack([rng.integers(0, 40, 2000), rng.integers(0, 1 << 16, 2000)]).astype(np.int32),
             W.nonzero_uniform(rng, 2000))
     out.append(("block", Problem("block-hash", X, Y, (1,), (0,))))
-    # block, hash, both table sizes: rows 0-49 with ~15 entries (bounds below
-    # 1,433: the 2,048-slot table), rows 50-99 with 40 (bounds ~2,000: 4,096)
+    # block, hash, all three table sizes: rows 0-49 with ~15 entries (bounds
+    # below 1,433: the 2,048-slot table), rows 50-99 with 40 (bounds ~2,000:
+    # 4,096), rows 100-119 with every contracting key twice or three times
+    # (repeated X coordinates; bounds ~5,000: 8,192)
+    xl = np.concatenate([np.tile(np.arange(40), 2), rng.integers(0, 40, 20)])
     xs = np.concatenate([np.stack([rng.integers(0, 50, 750), rng.integers(0, 40, 750)]),
-                         np.stack([np.repeat(np.arange(50, 100), 40), np.tile(np.arange(40), 50)])], axis=1)
-    X = Coo((100, 40), xs.astype(np.int32), W.nonzero_uniform(rng, xs.shape[1]))
-    out.append(("block", Problem("block-hash-two-sizes", X, Y, (1,), (0,))))
+                         np.stack([np.repeat(np.arange(50, 100), 40), np.tile(np.arange(40), 50)]),
+                         np.stack([np.repeat(np.arange(100, 120), xl.size), np.tile(xl, 20)])], axis=1)
+    X = Coo((120, 40), xs.astype(np.int32), W.nonzero_uniform(rng, xs.shape[1]))
+    out.append(("block", Problem("block-hash-three-sizes", X, Y, (1,), (0,))))
     # global: groups with more distinct outputs than a workgroup's LDS holds
     X = Coo((3, 8), np.stack([rng.integers(0, 3, 200), rng.integers(0, 8, 200)]).astype(np.int32),
             W.nonzero_uniform(rng, 200))
@@ -202,7 +206,7 @@ def _wide_key_problems():
     X = Coo((1 << 12, 1 << 12, 8), np.stack([lin >> 12, lin & 4095, rng.integers(4, 8, nx)]).astype(np.int32),
             W.nonzero_uniform(rng, nx))
     X.idx[:, :4] = np.array([[lin[0] >> 12] * 4, [lin[0] & 4095] * 4, [0, 1, 2, 3]], np.int32)
-    ny = 3200
+    ny = 6400  # the one group's 6,400 products: more than the largest LDS table takes (5,734)
     Y = Coo((8,) + (1 << 12,) * 4, np.stack([np.arange(ny) % 4] + [rng.integers(0, 1 << 12, ny) for _ in range(4)])
             .astype(np.int32), W.nonzero_uniform(rng, ny))
     out.append(Problem("wide-global-class-many-groups", X, Y, (2,), (0,)))
