@@ -28,7 +28,8 @@
 namespace sptc {
 namespace {
 
-constexpr int kBBlock = 1024;                           // block-class workgroup (large tables)
+constexpr int kBBlock = 1024;                           // block-class workgroup (largest table), Y run sort
+constexpr int kBMidBlock = 512;                         // block-class workgroup (4,096-slot table): two per CU
 constexpr int kBSmallBlock = 256;                       // and for groups that fit the small table
 constexpr int kBlockSmallSlots = 2048;
 constexpr unsigned kXcds = 8;                          // MI355X: 8 XCDs, each with its own L2
@@ -458,8 +459,9 @@ __device__ __forceinline__ void bitonic_sort_lds(unsigned long long* a, unsigned
 // Y free key too wide for a dense accumulator, an LDS hash of up to SLOTS
 // slots (keys, then values: 8-byte words at random slots spread over twice
 // the LDS banks that 16-byte {key, value} slots would use).  KIND 0 (2,048
-// slots, four workgroups to a CU) walks the class list; KIND 1 (4,096 or
-// 8,192 slots, two or one to a CU) walks in_list, *in_count entries.  Each
+// slots, four workgroups to a CU) walks the class list; KIND 1 (4,096
+// slots and 512 threads, two to a CU, or 8,192 and 1,024, one) walks
+// in_list, *in_count entries.  Each
 // takes the groups whose bound fits its table (at most 70% of its slots)
 // and appends the others to out_list (count in *out_count) for the next
 // table size, so that no instance walks another's groups.  KIND 2: a dense Y
@@ -1119,7 +1121,7 @@ hipError_t launch_gather_global(const GroupRec* groups, const uint32_t* glist, i
 
 // Dynamic LDS of the block class: a hash of 16-byte slots, or a dense row.
 hipError_t prepare_group_block() {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_group_block<kBBlock, kBlockSlots, 1>),
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_group_block<kBMidBlock, kBlockSlots, 1>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, kBlockSlots * 16);
   if (e == hipSuccess)
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_group_block<kBBlock, kBlockXlSlots, 1>),
@@ -1135,9 +1137,9 @@ hipError_t prepare_group_block() {
 
 // Hashed: the small-table instance walks the list, four workgroups of 256
 // threads per CU, and passes the groups its table cannot hold to the
-// large-table instance, two workgroups of 1024 per CU, which passes its
-// own misfits to the largest table, one workgroup of 1024 per CU; each
-// reads its count on the device.  Dense (cells > 0): 256-thread workgroups
+// large-table instance, two workgroups of 512 per CU (LDS and registers
+// both allow two), which passes its own misfits to the largest table, one
+// workgroup of 1024 per CU; each reads its count on the device.  Dense (cells > 0): 256-thread workgroups
 // with a row of cells.
 hipError_t launch_group_block(const GroupArgs& a, const uint32_t* blist, int64_t nb, int num_cus,
                               hipStream_t stream, const DevStatus* dc, unsigned cells, uint32_t* defer, LdsQueue* q) {
@@ -1160,7 +1162,7 @@ hipError_t launch_group_block(const GroupArgs& a, const uint32_t* blist, int64_t
   if (e != hipSuccess) return e;
   grid = grid_for(nb, 1, num_cus, 2);
   if (grid >= kXcds) grid -= grid % kXcds;
-  k_group_block<kBBlock, kBlockSlots, 1><<<grid, kBBlock, kBlockSlots * 16, stream>>>(
+  k_group_block<kBMidBlock, kBlockSlots, 1><<<grid, kBMidBlock, kBlockSlots * 16, stream>>>(
       a, blist, nb, dc, 0u, defer, &q->n_defer, defer2, &q->n_defer2);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
