@@ -895,8 +895,10 @@ __global__ __launch_bounds__(kDBlock) void k_group_direct(GroupArgs a, const uin
 // banks.  Either way (dense Y free keys only) it writes the compact copy of
 // grouped Y and finds repeated Y coordinates (two entries of one run with
 // the same free key) with a per-run bitmap of the 2^kDenseBits keys, which
-// the direct class needs to know about.
-// With yso (SORT only), the compact copy of every run is also cut into
+// the direct class needs to know about.  Without SORT it serves small
+// tables only (a few slots per workgroup); larger ones take k_y_compact and
+// k_y_repeats.
+// With yso, the compact copy of every run is also cut into
 // kSlices slices of the Y free key space (key >> slice_shift): a sorted run
 // is cut where the slice changes, a longer run is placed slice by slice (in
 // no order within a slice).  yso[slot * (kSlices + 1) + s] receives the
@@ -993,6 +995,111 @@ __global__ __launch_bounds__(kBBlock) void k_sort_y_runs(const YSlot* __restrict
 }
 
 
+
+// Dense Y free keys, at plan time: the compact copy of grouped Y (16-bit
+// free key, value), entry by entry, and the cells that occur (colbits,
+// optional; each workgroup gathers its entries' cells in LDS first).
+__global__ __launch_bounds__(256) void k_y_compact(const YEntry* __restrict__ yg, int64_t ny,
+                                                   uint16_t* __restrict__ ykey16, double* __restrict__ yval,
+                                                   unsigned* __restrict__ colbits, unsigned* __restrict__ nlong) {
+  constexpr unsigned kWords = (1u << kDenseBits) / 32;
+  __shared__ unsigned s_cells[kWords];
+  if (blockIdx.x == 0 && threadIdx.x == 0) *nlong = 0u;  // the long-run list of the repeat check
+  for (unsigned w = threadIdx.x; w < kWords; w += blockDim.x) s_cells[w] = 0u;
+  __syncthreads();
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < ny; p += (int64_t)gridDim.x * blockDim.x) {
+    const YEntry e = yg[p];
+    ykey16[p] = (uint16_t)e.phi;
+    yval[p] = e.v;
+    if (colbits) {
+      const unsigned c = (unsigned)e.phi & ((1u << kDenseBits) - 1u);
+      atomicOr(&s_cells[c >> 5], 1u << (c & 31));
+    }
+  }
+  __syncthreads();
+  if (colbits)
+    for (unsigned w = threadIdx.x; w < kWords; w += blockDim.x)
+      if (s_cells[w]) atomicOr(&colbits[w], s_cells[w]);
+}
+
+// Dense Y free keys: repeated Y coordinates, i.e. two entries of one run (Y
+// group) with the same free key, which the direct class must know about.
+// Each wave reads 64 Y table slots at a time and checks their runs of two
+// to kLongRun entries one after another against a bitmap of the
+// 2^kDenseBits keys in its own LDS (cleared per run; one wave's LDS
+// operations complete in order).  Runs of one entry cannot repeat and cost
+// nothing but their slot's read; longer runs go to the list `lng` (count
+// *nlong, room for cap) for k_y_repeats_long, a workgroup per run, so that
+// a few long runs do not hold a few waves for long.
+constexpr unsigned kLongRun = 512;
+
+__global__ __launch_bounds__(256) void k_y_repeats(const YSlot* __restrict__ ytab, int64_t nslots,
+                                                   const YEntry* __restrict__ yg, int64_t ny, DevStatus* st,
+                                                   uint32_t* __restrict__ lng, unsigned cap,
+                                                   unsigned* __restrict__ nlong) {
+  constexpr unsigned kWords = (1u << kDenseBits) / 32;
+  __shared__ unsigned s_seen[4][kWords];
+  const unsigned lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  unsigned* seen = s_seen[wave];
+  const int64_t nwaves = (int64_t)gridDim.x * 4;
+  bool dup = false;
+  for (int64_t base = ((int64_t)blockIdx.x * 4 + wave) * 64; base < nslots; base += nwaves * 64) {
+    const int64_t slot = base + lane;
+    unsigned start = 0u, n = 0u;
+    if (slot < nslots) {
+      const YSlot t = ytab[slot];
+      if (t.key != kEmpty && t.count >= 2u && (unsigned long long)t.start + t.count <= (unsigned long long)ny) {
+        start = t.start;
+        n = t.count;
+      }
+    }
+    for (unsigned long long m = __ballot(n != 0u); m; m &= m - 1ull) {
+      const int r = __ffsll((long long)m) - 1;
+      const unsigned rs = (unsigned)__builtin_amdgcn_readlane((int)start, r);
+      const unsigned rn = (unsigned)__builtin_amdgcn_readlane((int)n, r);
+      if (rn > kLongRun) {
+        if (lane == 0) {
+          const unsigned k = atomicAdd(nlong, 1u);
+          if (k < cap)
+            lng[k] = (uint32_t)(base + r);
+          else
+            record_error(st, kErrInternal);  // more long runs than entries allow
+        }
+        continue;
+      }
+      for (unsigned w = lane; w < kWords; w += 64) seen[w] = 0u;
+      wave_lds_fence();
+      for (unsigned j = lane; j < rn; j += 64) {
+        const unsigned c = (unsigned)yg[rs + j].phi & ((1u << kDenseBits) - 1u), bit = 1u << (c & 31);
+        if (atomicOr(&seen[c >> 5], bit) & bit) dup = true;
+      }
+      wave_lds_fence();
+    }
+  }
+  if (__ballot(dup) && lane == 0) st->ydup = 1u;
+}
+
+// The long runs of k_y_repeats, one workgroup per run, with the bitmap in
+// the workgroup's LDS.
+__global__ __launch_bounds__(256) void k_y_repeats_long(const YSlot* __restrict__ ytab, const YEntry* __restrict__ yg,
+                                                        DevStatus* st, const uint32_t* __restrict__ lng,
+                                                        const unsigned* __restrict__ nlong) {
+  constexpr unsigned kWords = (1u << kDenseBits) / 32;
+  __shared__ unsigned s_seen[kWords];
+  const unsigned nl = *nlong;
+  bool dup = false;
+  for (unsigned i = blockIdx.x; i < nl; i += gridDim.x) {
+    const YSlot t = ytab[lng[i]];  // a run k_y_repeats checked: start + count <= ny
+    for (unsigned w = threadIdx.x; w < kWords; w += blockDim.x) s_seen[w] = 0u;
+    __syncthreads();
+    for (unsigned j = threadIdx.x; j < t.count; j += blockDim.x) {
+      const unsigned c = (unsigned)yg[t.start + j].phi & ((1u << kDenseBits) - 1u), bit = 1u << (c & 31);
+      if (atomicOr(&s_seen[c >> 5], bit) & bit) dup = true;
+    }
+    __syncthreads();
+  }
+  if (__ballot(dup) && (threadIdx.x & 63u) == 0) st->ydup = 1u;
+}
 
 __global__ void k_finalize(int64_t* out_nnz, int64_t out_cap, DevStatus* st) {
   const unsigned long long total = st->out_base;
@@ -1205,18 +1312,43 @@ hipError_t launch_group_direct(const GroupArgs& a, const uint32_t* dlist, const 
 }
 
 
+int64_t y_long_run_slots(int64_t ny) { return ny / kLongRun + 2; }
+
+// Y tables of at most this many slots take the one-launch copy without
+// sorting: with a workgroup per slot each workgroup visits a few slots,
+// where the three launches of the larger tables' path would cost more.
+constexpr int64_t kSmallYTable = 8192;
+
 hipError_t launch_sort_y_runs(const YSlot* ytab, int64_t nslots, YEntry* yg, int64_t ny, uint16_t* ykey16,
                               double* yval, unsigned* colbits, DevStatus* st, bool sort, int num_cus,
-                              hipStream_t stream, uint32_t* yso, uint32_t* runslot, unsigned slice_shift) {
+                              hipStream_t stream, uint32_t* yso, uint32_t* runslot, unsigned slice_shift,
+                              uint32_t* ylong) {
   if (nslots <= 0 || ny <= 0) return hipSuccess;
   if (yso && !sort) return hipErrorInvalidValue;
-  int64_t grid = nslots < (int64_t)num_cus * 2 ? nslots : (int64_t)num_cus * 2;
-  if (sort)
+  const int64_t grid = nslots < (int64_t)num_cus * 2 ? nslots : (int64_t)num_cus * 2;
+  if (sort) {
     k_sort_y_runs<true><<<dim3((unsigned)grid), kBBlock, 0, stream>>>(ytab, nslots, yg, ny, ykey16, yval, colbits,
                                                                        yso, runslot, slice_shift, st);
-  else
+    return hipGetLastError();
+  }
+  if (nslots <= kSmallYTable) {  // a few slots per workgroup: one launch
     k_sort_y_runs<false><<<dim3((unsigned)grid), kBBlock, 0, stream>>>(ytab, nslots, yg, ny, ykey16, yval, colbits,
                                                                         nullptr, nullptr, 0u, st);
+    return hipGetLastError();
+  }
+  // a larger table, mostly short runs or empty slots: an elementwise copy,
+  // and the repeat check by waves over the slots, long runs by workgroups
+  if (!ylong) return hipErrorInvalidValue;
+  const unsigned cap = (unsigned)(ny / kLongRun + 1);
+  unsigned* nlong = ylong + cap;
+  k_y_compact<<<grid_for(ny, 256, num_cus, 8), 256, 0, stream>>>(yg, ny, ykey16, yval, colbits, nlong);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_y_repeats<<<grid_for((nslots + 255) / 256, 1, num_cus, 8), 256, 0, stream>>>(ytab, nslots, yg, ny, st, ylong, cap,
+                                                                                 nlong);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_y_repeats_long<<<grid_for(ny / kLongRun + 1, 1, num_cus, 4), 256, 0, stream>>>(ytab, yg, st, ylong, nlong);
   return hipGetLastError();
 }
 

@@ -327,6 +327,7 @@ struct sptc_plan_s : Workspace {
   int64_t block_products = 0;   // survey: products of the block class
   unsigned long long* dpos = nullptr;
   uint16_t* ykey16 = nullptr;  // dense Y free keys: compact copy of grouped Y
+  uint32_t* ylong = nullptr;    // and the long runs of the repeat check (with their count)
   double* yval = nullptr;
   unsigned long long* yset = nullptr;
   int64_t yset_slots = 0;
@@ -596,7 +597,7 @@ sptc_status plan_group_y(sptc_plan_s* P, const sptc_coo* Y) {
   if (P->opt.mode == SPTC_MODE_GROUPED && P->dense) {
     // the runs are sorted later, for the block walk only (plan_grouped)
     HIP_TRY(launch_sort_y_runs(P->ytab, P->ytab_slots, P->yg, P->ny, P->ykey16, P->yval, P->ycolbits, P->st, false,
-                               P->num_cus, s));
+                               P->num_cus, s, nullptr, nullptr, 0u, P->ylong));
   }
   HIP_TRY(mark(P, s, SPTC_STAGE_Y_SCATTER, 1));
   return SPTC_OK;
@@ -921,6 +922,7 @@ sptc_status plan_body(sptc_plan_s* P, const sptc_coo* X, const sptc_coo* Y, cons
   if (grouped && P->dense) {
     if ((st = P->allocate_n(P->ny, &P->ykey16))) return st;
     if ((st = P->allocate_n(P->ny, &P->yval))) return st;
+    if ((st = P->allocate_n(y_long_run_slots(P->ny), &P->ylong))) return st;
     if ((st = P->allocate_n(kCellWords, &P->ycolbits))) return st;
     HIP_TRY(launch_zero_u64(reinterpret_cast<unsigned long long*>(P->ycolbits), kCellWords / 2, P->stream));
   }

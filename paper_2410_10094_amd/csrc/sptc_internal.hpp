@@ -421,11 +421,14 @@ hipError_t launch_finalize(int64_t* out_nnz, int64_t out_cap, DevStatus* st, hip
 // u32) and runslot ([ny] u32), also cuts every run into kSlices slices of
 // the Y free key (key >> slice_shift), slice by slice in the compact copy:
 // yso[slot][s] is where slice s of the slot's run begins (yso[slot][kSlices]
-// its end) and runslot[run start] = slot.
+// its end) and runslot[run start] = slot.  Without sort, ylong
+// (y_long_run_slots(ny) u32) is required: the list of long runs whose
+// repeats a workgroup each checks.
 hipError_t launch_sort_y_runs(const YSlot* ytab, int64_t nslots, YEntry* yg, int64_t ny, uint16_t* ykey16,
                               double* yval, unsigned* colbits, DevStatus* st, bool sort, int num_cus,
                               hipStream_t stream, uint32_t* yso = nullptr, uint32_t* runslot = nullptr,
-                              unsigned slice_shift = 0);
+                              unsigned slice_shift = 0, uint32_t* ylong = nullptr);
+int64_t y_long_run_slots(int64_t ny);
 
 // ---- LDS classes: dense block tiles and the wave class (queue.hip) ----
 // The dense Y free key space is cut into kSlices slices, one per XCD: a

@@ -248,6 +248,34 @@ def test_repeated_y_coordinates_disable_direct_class(kind):
     assert_parity(q, gidx, gval)
 
 
+@pytest.mark.parametrize("where", ["short-run", "long-run"])
+def test_repeated_y_coordinates_in_a_large_y_table(where):
+    """A dense Y free key with 20,000 contracting keys: a Y table of more than
+    8,192 slots, whose repeat check reads the slots by waves and hands runs
+    of more than 512 entries to a workgroup each.  One repeated coordinate,
+    in a run of two entries or in a run of 700, disables the direct class;
+    without it the class is used; both match the oracle."""
+    rng = np.random.default_rng(37)
+    nc, nf = 20_000, 4096
+    xc = W.unique_coords(rng, (1000, nc), 2000)
+    xc[1, :50] = 7  # X entries that meet the long run
+    xc = np.unique(xc, axis=1).astype(np.int32)
+    X = Coo((1000, nc), xc, W.nonzero_uniform(rng, xc.shape[1]))
+    base = W.unique_coords(rng, (nc, nf), 30_000)
+    base = base[:, base[0] != 7]
+    long_run = np.stack([np.full(700, 7), np.arange(700)]).astype(np.int32)
+    yc = np.concatenate([base, long_run], axis=1)
+    rep = yc[:, :1] if where == "short-run" else long_run[:, 3:4]
+    for name, coords, want_direct in ((f"y-repeat-{where}", np.concatenate([yc, rep], axis=1), False),
+                                      (f"y-unique-{where}", yc, True)):
+        Y = Coo((nc, nf), coords, W.nonzero_uniform(rng, coords.shape[1]))
+        p = Problem(name, X, Y, (1,), (0,))
+        log(f"[ydup-large] {name}")
+        info, gidx, gval = run_gpu(p, mode="grouped")
+        assert (info["classes"]["direct"] > 0) == want_direct, info["classes"]
+        assert_parity(p, gidx, gval)
+
+
 @pytest.mark.parametrize("cls,p", _class_problems(), ids=lambda v: v if isinstance(v, str) else v.name)
 def test_grouped_accumulation_classes(cls, p):
     log(f"[class] {cls} {p.name}")
