@@ -330,6 +330,8 @@ struct ClassifyOp {
   uint32_t* glist;
   unsigned long long* dcnt;  // direct group k's products, at the k-th place (scanned in place into offsets)
   unsigned long long block_cap;  // most distinct outputs of a group in a workgroup's LDS hash
+  const XRec* xr;                // grouped X records
+  DRec* drec;                    // direct group k's staging record, at the k-th place
   __device__ U128 code(int64_t g) const {
     const GroupRec G = groups[g];
     const unsigned long long b = eoff[G.start + G.count] - eoff[G.start];
@@ -348,6 +350,8 @@ struct ClassifyOp {
       dlist[nd] = (uint32_t)g;
       const GroupRec G = groups[g];  // read by code(g) just before: a cache hit
       dcnt[nd] = eoff[G.start + G.count] - eoff[G.start];
+      const XRec r = xr[G.start];
+      drec[nd] = DRec{G.phi, r.v, r.ystart, 0u};
     } else if (v.lo)
       wlist[nw] = (uint32_t)g;
     else if (v.hi)
@@ -760,7 +764,7 @@ __global__ __launch_bounds__(256) void k_direct_tiles(const unsigned long long* 
 }
 
 template <bool BATCH, int kDItems>
-__global__ __launch_bounds__(kDBlock) void k_group_direct(GroupArgs a, const uint32_t* __restrict__ dlist,
+__global__ __launch_bounds__(kDBlock) void k_group_direct(GroupArgs a, const DRec* __restrict__ drec,
                                                           const unsigned long long* __restrict__ dpos, int64_t nd,
                                                           uint64_t nprod, const uint32_t* __restrict__ tfirst,
                                                           const DevStatus* dc, uint64_t max_tiles) {
@@ -790,13 +794,12 @@ __global__ __launch_bounds__(kDBlock) void k_group_direct(GroupArgs a, const uin
     const bool staged = nloc <= kDGroups;
     if (staged) {
       for (int64_t k = threadIdx.x; k < nloc; k += kDBlock) {
-        const GroupRec G = a.groups[dlist[ilo + k]];
-        const XRec r = a.xr[G.start];
+        const DRec d = drec[ilo + k];
         s_pos[k] = dpos[ilo + k];
-        s_phi[k] = G.phi;
-        s_v[k] = r.v;
-        s_ys[k] = r.ystart;
-        if constexpr (BATCH) s_sh[k] = a.bseg[G.phi >> a.bwx].dshift;
+        s_phi[k] = d.phi;
+        s_v[k] = d.v;
+        s_ys[k] = d.ystart;
+        if constexpr (BATCH) s_sh[k] = a.bseg[d.phi >> a.bwx].dshift;
       }
       if (threadIdx.x == 0) s_pos[nloc] = dpos[ihi + 1];
     }
@@ -834,12 +837,11 @@ __global__ __launch_bounds__(kDBlock) void k_group_direct(GroupArgs a, const uin
         if constexpr (BATCH) dsh[it] = s_sh[lo];
       } else {
         const int64_t li = upper_bound_idx(dpos, ilo, ihi + 1, q) - 1;
-        const GroupRec G = a.groups[dlist[li]];
-        const XRec r = a.xr[G.start];
-        ys[it] = (unsigned long long)r.ystart + (q - dpos[li]);
-        phx[it] = G.phi;
-        xv[it] = r.v;
-        if constexpr (BATCH) dsh[it] = a.bseg[G.phi >> a.bwx].dshift;
+        const DRec d = drec[li];
+        ys[it] = (unsigned long long)d.ystart + (q - dpos[li]);
+        phx[it] = d.phi;
+        xv[it] = d.v;
+        if constexpr (BATCH) dsh[it] = a.bseg[d.phi >> a.bwx].dshift;
       }
       if (ys[it] >= (unsigned long long)a.ny) {
         record_error(a.st, kErrInternal);
@@ -1199,10 +1201,11 @@ hipError_t launch_scan_entries(const XRec* xr, int64_t n, unsigned long long* eo
 hipError_t launch_classify(const GroupRec* groups, int64_t max_groups, const unsigned long long* eoff,
                            uint64_t ycells, int32_t dense, uint32_t* dlist, uint32_t* wlist, uint32_t* blist,
                            uint32_t* glist, unsigned long long* dpos, void* tile_sums, DevStatus* st,
-                           hipStream_t stream, int32_t block_cap) {
+                           hipStream_t stream, int32_t block_cap, const XRec* xr, DRec* drec) {
+  if (!xr || !drec) return hipErrorInvalidValue;
   const unsigned long long cap = block_cap > 0 && block_cap < kBlockCap ? (unsigned long long)block_cap : kBlockCap;
-  return device_scan(ClassifyOp{groups, eoff, st, ycells, dense, dlist, wlist, blist, glist, dpos, cap}, max_groups,
-                     tile_sums, FinClassify{st}, stream);
+  return device_scan(ClassifyOp{groups, eoff, st, ycells, dense, dlist, wlist, blist, glist, dpos, cap, xr, drec},
+                     max_groups, tile_sums, FinClassify{st}, stream);
 }
 
 hipError_t launch_scan_direct(int64_t max_groups, unsigned long long* dpos, void* tile_sums, DevStatus* st,
@@ -1285,7 +1288,7 @@ int64_t direct_tile_bound(uint64_t nprod) {
   return (int64_t)((nprod + tile - 1) / tile) + 1;
 }
 
-hipError_t launch_group_direct(const GroupArgs& a, const uint32_t* dlist, const unsigned long long* dpos, int64_t nd,
+hipError_t launch_group_direct(const GroupArgs& a, const DRec* drec, const unsigned long long* dpos, int64_t nd,
                                uint64_t nprod, uint32_t* tfirst, int num_cus, hipStream_t stream, int tile_products,
                                DevStatus* dc, int64_t tfirst_slots) {
   if (nd <= 0 || nprod == 0) return hipSuccess;
@@ -1298,7 +1301,7 @@ hipError_t launch_group_direct(const GroupArgs& a, const uint32_t* dlist, const 
   uint64_t g = (uint64_t)num_cus * 8;
   if (g > tiles) g = tiles;
 #define D_LAUNCH(B, I) \
-  k_group_direct<B, I><<<dim3((unsigned)g), kDBlock, 0, stream>>>(a, dlist, dpos, nd, nprod, tfirst, dc, max_tiles)
+  k_group_direct<B, I><<<dim3((unsigned)g), kDBlock, 0, stream>>>(a, drec, dpos, nd, nprod, tfirst, dc, max_tiles)
   if (a.bout && small)
     D_LAUNCH(true, kDItemsSmall);
   else if (a.bout)

@@ -297,6 +297,7 @@ struct sptc_plan_s : Workspace {
   XRec* xr = nullptr;
   unsigned long long* eoff = nullptr;
   uint32_t* dlist = nullptr;
+  DRec* drec = nullptr;  // the direct groups' staging records, by list place
   uint32_t* dtfirst = nullptr;  // direct class: each product tile's first group
   uint32_t* wlist = nullptr;
   uint32_t* wcnt = nullptr;            // wave class: each group's output count (by list place)
@@ -728,6 +729,7 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
   if ((st = P->allocate_n(P->nx, &P->xr))) return st;
   if ((st = P->allocate_n(P->nx + 1, &P->eoff))) return st;
   if ((st = P->allocate_n(P->nx, &P->dlist))) return st;
+  if ((st = P->allocate_n(P->nx, &P->drec))) return st;
   if ((st = P->allocate_n(P->nx, &P->wlist))) return st;
   if ((st = P->allocate_n(P->nx, &P->blist))) return st;
   if ((st = P->allocate_n(P->nx, &P->glist))) return st;
@@ -767,7 +769,7 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
   // scans a single tile
   const int64_t max_groups = std::min<int64_t>(P->nx, P->xtab_slots);
   HIP_TRY(launch_classify(P->groups, max_groups, P->eoff, P->ycells, P->dense, P->dlist, P->wlist, P->blist,
-                          P->glist, P->dpos, P->tile_sums, P->st, s, P->opt.lds_max_keys));
+                          P->glist, P->dpos, P->tile_sums, P->st, s, P->opt.lds_max_keys, P->xr, P->drec));
   HIP_TRY(launch_scan_direct(max_groups, P->dpos, P->tile_sums, P->st, s));
   // the block class's products and finiteness, read back with the counts
   // below, decide the matrix-core class with no read-back of its own
@@ -1181,7 +1183,7 @@ sptc_status execute_plan(sptc_plan_s* P, int32_t* out_idx, double* out_val, int6
       a.bwx = bx->bwx;
     }
     HIP_TRY(mark(P, s, SPTC_STAGE_DIRECT, 0));
-    HIP_TRY(launch_group_direct(a, P->dlist, P->dpos, P->nd, (uint64_t)P->direct_products, P->dtfirst, P->num_cus, s,
+    HIP_TRY(launch_group_direct(a, P->drec, P->dpos, P->nd, (uint64_t)P->direct_products, P->dtfirst, P->num_cus, s,
                                 P->opt.tile, P->capture ? P->st : nullptr, P->dtfirst_slots));
     HIP_TRY(mark(P, s, SPTC_STAGE_DIRECT, 1));
     HIP_TRY(mark(P, s, SPTC_STAGE_BLOCK, 0));

@@ -120,6 +120,16 @@ struct alignas(16) XRec {
   double v;
 };
 
+// A direct-class group as the direct kernel stages it, written at its
+// place in the direct list when the groups are classified: its X free key,
+// its one X entry's value and the start of that entry's Y run.
+struct DRec {
+  unsigned long long phi;
+  double v;
+  uint32_t ystart;
+  uint32_t pad;
+};
+
 // An X group: packed X free key, and its run [start, start + count) of XRec.
 struct alignas(16) GroupRec {
   unsigned long long phi;
@@ -302,13 +312,14 @@ hipError_t launch_scan_entries(const XRec* xr, int64_t n, unsigned long long* eo
 
 // Sorts groups into direct / wave / block / global accumulation classes
 // (lists of group ids); counts land in st->class_lo / class_hi, and each
-// direct group's products in dpos at its place in the direct list.
+// direct group's products in dpos at its place in the direct list, and its
+// staging record (from the grouped X records xr) in drec at the same place.
 // block_cap: most distinct outputs of a group in a workgroup's LDS hash
 // (0: kBlockCap).
 hipError_t launch_classify(const GroupRec* groups, int64_t max_groups, const unsigned long long* eoff,
                            uint64_t ycells, int32_t dense, uint32_t* dlist, uint32_t* wlist, uint32_t* blist,
                            uint32_t* glist, unsigned long long* dpos, void* tile_sums, DevStatus* st,
-                           hipStream_t stream, int32_t block_cap = 0);
+                           hipStream_t stream, int32_t block_cap, const XRec* xr, DRec* drec);
 
 // In place after launch_classify: dpos[i] = products of direct-class groups
 // before list entry i; dpos[nd] and st->direct_products = their total.
@@ -406,7 +417,7 @@ int64_t direct_tile_bound(uint64_t nprod);
 // entries, and more tiles than that are a capacity error).
 // tile_products: 1024 for the small tile, else the default (2048, or 1280
 // in a batch).
-hipError_t launch_group_direct(const GroupArgs& a, const uint32_t* dlist, const unsigned long long* dpos, int64_t nd,
+hipError_t launch_group_direct(const GroupArgs& a, const DRec* drec, const unsigned long long* dpos, int64_t nd,
                                uint64_t nprod, uint32_t* tfirst, int num_cus, hipStream_t stream,
                                int tile_products = 0, DevStatus* dc = nullptr, int64_t tfirst_slots = 0);
 
