@@ -110,7 +110,10 @@ def test_stage_x_groups():
               # into 16 and 8 buckets (the second with repeated coordinates)
               W.imbalanced(nnz_x=50_000, nnz_y=20_000, xdims=(1 << 12, 1 << 10, 1 << 10),
                            ydims=(1 << 10, 1 << 8, 1 << 6)),
-              W.random_problem(93, 3, 3, 1, 2000, 3000, 30_000, 5_000, duplicates=True)]:
+              W.random_problem(93, 3, 3, 1, 2000, 3000, 30_000, 5_000, duplicates=True),
+              # 1.2M X entries: 512 buckets of the partition
+              W.imbalanced(nnz_x=1_200_000, nnz_y=20_000, xdims=(1 << 12, 1 << 10, 1 << 10),
+                           ydims=(1 << 10, 1 << 8, 1 << 6))]:
         log(f"[stage-X] {p.name}")
         X, Y = to_device(p)
         with sptc.plan(X, Y, p.cx, p.cy, options=sptc.default_options(operand_order=1)) as pl:
