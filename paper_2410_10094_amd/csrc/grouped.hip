@@ -852,12 +852,60 @@ __global__ __launch_bounds__(kDBlock) void k_group_direct(GroupArgs a, const DRe
     for (int it = 0; it < kDItems; ++it)
       if (ys[it] != ~0ull) ye[it] = a.yg[ys[it]];
     if constexpr (BATCH) {
+      // Usually every item of the wave belongs to one contraction (the list
+      // is ordered by contraction): its output layout is then read once and
+      // each output row stored for all items, as for one contraction;
+      // otherwise each item is stored on its own.
+      uint32_t bi = ~0u;
+      bool one = true;
 #pragma unroll
       for (int it = 0; it < kDItems; ++it) {
-        const uint64_t q = p0 + (uint64_t)it * kDBlock + threadIdx.x;
         if (ys[it] == ~0ull) continue;
-        batch_store(a.bout, a.out_idx, a.out_val, a.bwx, (uint32_t)(phx[it] >> a.bwx), q - dsh[it], phx[it],
-                    ye[it].phi, __dmul_rn(xv[it], ye[it].v), a.st);
+        const uint32_t b = (uint32_t)(phx[it] >> a.bwx);
+        if (bi == ~0u) bi = b;
+        one &= b == bi;
+      }
+      const uint32_t b0 = __builtin_amdgcn_readfirstlane(bi);
+      if (b0 != ~0u && __ballot(!one || (bi != ~0u && bi != b0)) == 0ull) {
+        const BatchOut& d = a.bout[b0];
+        const uint64_t xmask = low_mask(a.bwx);
+        bool put[kDItems];
+        unsigned long long pos[kDItems];
+#pragma unroll
+        for (int it = 0; it < kDItems; ++it) {
+          pos[it] = p0 + (uint64_t)it * kDBlock + threadIdx.x - dsh[it];
+          put[it] = ys[it] != ~0ull;
+          if (put[it] && (int64_t)pos[it] >= d.cap) {
+            record_error(a.st, kErrCapacity);
+            put[it] = false;
+          }
+        }
+        int32_t* rows = a.out_idx + d.idx_off;
+        for (int m = 0; m < d.ux.n; ++m) {
+          const uint32_t fd = d.ux.field[m];
+          int32_t* dst = rows + (int64_t)(d.ux.row0 + m) * d.cap;
+#pragma unroll
+          for (int it = 0; it < kDItems; ++it)
+            if (put[it]) __builtin_nontemporal_store(key_field(phx[it] & xmask, fd), dst + pos[it]);
+        }
+        for (int m = 0; m < d.uy.n; ++m) {
+          const uint32_t fd = d.uy.field[m];
+          int32_t* dst = rows + (int64_t)(d.uy.row0 + m) * d.cap;
+#pragma unroll
+          for (int it = 0; it < kDItems; ++it)
+            if (put[it]) __builtin_nontemporal_store(key_field(ye[it].phi, fd), dst + pos[it]);
+        }
+#pragma unroll
+        for (int it = 0; it < kDItems; ++it)
+          if (put[it]) __builtin_nontemporal_store(__dmul_rn(xv[it], ye[it].v), a.out_val + d.val_off + pos[it]);
+      } else {
+#pragma unroll
+        for (int it = 0; it < kDItems; ++it) {
+          const uint64_t q = p0 + (uint64_t)it * kDBlock + threadIdx.x;
+          if (ys[it] == ~0ull) continue;
+          batch_store(a.bout, a.out_idx, a.out_val, a.bwx, (uint32_t)(phx[it] >> a.bwx), q - dsh[it], phx[it],
+                      ye[it].phi, __dmul_rn(xv[it], ye[it].v), a.st);
+        }
       }
     } else {
       // one output row (coordinate mode) at a time over all items: the
