@@ -559,7 +559,7 @@ constexpr int64_t kTileScanProducts = 4096;
 
 // Dense block groups averaging fewer products than this run one workgroup
 // per group with the whole dense row instead of (group, slice) tiles.
-constexpr int64_t kDenseRowProducts = 8192;
+constexpr int64_t kDenseRowProducts = 16384;
 
 // Cells of the dense LDS accumulator for a Y free key of bits_y bits.
 unsigned dense_cells(int32_t bits_y) { return std::max(1u << bits_y, 1024u); }

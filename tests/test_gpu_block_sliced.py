@@ -75,11 +75,12 @@ def test_sliced_block_class(name, make):
 
 
 def test_many_tiles_counted_then_placed_by_a_scan():
-    """Over 131,072 tiles (16,400 groups x 8 slices) of 1,024 products:
-    each tile's outputs are counted, a scan places them, and a second walk
-    writes them (no atomic per tile).  134M products, against the oracle."""
+    """Over 131,072 tiles (16,400 groups x 8 slices) of 2,560 products
+    (groups of 20,480: above the dense rows' 16,384): each tile's outputs are
+    counted, a scan places them, and a second walk writes them (no atomic
+    per tile).  336M products, against the oracle."""
     import oracle
-    p = _matrix_like(11, 16_400, 64, 4096, 16_400 * 64, 64 * 128, "many-tiles")
+    p = _matrix_like(11, 16_400, 64, 4096, 16_400 * 64, 64 * 320, "many-tiles")
     log(f"[sliced] {p.name} nnz {p.X.nnz}x{p.Y.nnz}")
     info, gidx, gval = run_gpu(p)
     assert info["block_tiles_scanned"] and not info["block_dense_rows"], (info["products"], info["classes"])
