@@ -42,7 +42,11 @@ __global__ __launch_bounds__(256) void k_key_count(const int32_t* __restrict__ i
     int32_t probe = 0;
     for (;;) {
       const uint64_t s = p.slot();
-      const unsigned long long prev = atomicCAS(&tab[s].key, (unsigned long long)kEmpty, (unsigned long long)key);
+      // a slot's key changes once, from empty: a key seen here is final, and
+      // only an empty slot needs the compare-and-swap
+      const unsigned long long seen = __atomic_load_n(&tab[s].key, __ATOMIC_RELAXED);
+      const unsigned long long prev =
+          seen == kEmpty ? atomicCAS(&tab[s].key, (unsigned long long)kEmpty, (unsigned long long)key) : seen;
       if (prev == kEmpty || prev == key) {
         atomicAdd(&tab[s].count, 1u);
         fresh += prev == kEmpty;
