@@ -195,7 +195,12 @@ __device__ __forceinline__ void hash_accumulate(ZSlot* __restrict__ tab, uint64_
   uint64_t s = fmix64(key ^ seed) & mask;
   int32_t probe = 0;
   for (;;) {
-    const unsigned long long prev = atomicCAS(&tab[s].key, (unsigned long long)kEmpty, (unsigned long long)key);
+    // a slot's key changes once, from empty: a key read here is final, and
+    // only an empty slot needs the compare-and-swap (most products meet
+    // their output's key already in place)
+    const unsigned long long seen = __atomic_load_n(&tab[s].key, __ATOMIC_RELAXED);
+    const unsigned long long prev =
+        seen == kEmpty ? atomicCAS(&tab[s].key, (unsigned long long)kEmpty, (unsigned long long)key) : seen;
     if (prev == kEmpty || prev == key) {
       unsafeAtomicAdd(&tab[s].val, v);
       return;
