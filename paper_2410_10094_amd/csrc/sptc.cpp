@@ -716,8 +716,7 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
     const int64_t nbk = (int64_t)1 << part_bits(P->nx), nh = nbk * part_tiles(P->nx);
     unsigned long long* scan = nullptr;
     if ((st = P->allocate_n(P->nx, &xw.pkey)) || (st = P->allocate_n(P->nx, &xw.prec)) ||
-        (st = P->allocate_n(nh, &xw.hist)) || (st = P->allocate_n(nbk, &xw.bdist)) ||
-        (st = P->allocate_n(nbk, &xw.gbase)) || (st = P->allocate_n(scan_tiles(std::max(nh, nbk)) + 1, &scan)))
+        (st = P->allocate_n(nh, &xw.hist)) || (st = P->allocate_n(scan_tiles(nh) + 1, &scan)))
       return st;
     xw.scan = scan;
   } else if (x32) {

@@ -6,8 +6,9 @@
 // key's hash into 2^bbits buckets of about 4,096 entries (per-tile LDS
 // histograms, a scan of them bucket-major, a scatter with LDS cursors);
 // then one workgroup per bucket groups its entries with an LDS table of
-// keys and counts, numbers the bucket's groups in slot order after those of
-// earlier buckets, and places each entry in its group's run.  Each entry's
+// keys and counts, numbers the bucket's groups in slot order from a base
+// reserved with one atomic per bucket, and places each entry in its group's
+// run.  Each entry's
 // X record (its Y run and value) is formed in the scatter, while X streams
 // in order.  The groups and records come out as the hashed X table's path
 // makes them (groups in some order, each group's entries contiguous).
@@ -177,46 +178,13 @@ __device__ __forceinline__ void part_table(unsigned long long* tab, unsigned tsi
   __syncthreads();
 }
 
-// Distinct keys of each bucket.
-__global__ __launch_bounds__(kPGBlock) void k_xpart_count(const unsigned* __restrict__ pkey,
-                                                          const unsigned* __restrict__ hist, int bbits,
-                                                          int64_t ntiles, int64_t nnz, uint64_t seed, unsigned tmax,
-                                                          unsigned* __restrict__ bdist, DevStatus* st) {
-  extern __shared__ unsigned long long s_tab[];
-  __shared__ unsigned long long s_wave[kPGBlock / 64 + 1];
-  const unsigned nbk = 1u << bbits;
-  for (unsigned b = blockIdx.x; b < nbk; b += gridDim.x) {
-    unsigned lo, hi;
-    part_range(hist, b, nbk, ntiles, nnz, &lo, &hi);
-    const unsigned tsize = part_slots(hi - lo, tmax);
-    part_table(s_tab, tsize, pkey, lo, hi, seed, st);
-    unsigned long long n = 0;
-    for (unsigned s = threadIdx.x; s < tsize; s += kPGBlock) n += s_tab[s] != kEmpty ? 1u : 0u;
-    n = block_sum<kPGBlock>(n, s_wave);
-    if (threadIdx.x == 0) bdist[b] = (unsigned)n;
-    __syncthreads();
-  }
-}
-
-struct FinPartGroups {
-  DevStatus* st;
-  __device__ void operator()(unsigned long long total) const { st->xgroups = total & 0xffffffffull; }
-};
-
-struct BucketScanOp {
-  const unsigned* bdist;
-  unsigned* gbase;
-  __device__ unsigned long long get(int64_t i) const { return bdist[i]; }
-  __device__ void put(int64_t i, unsigned long long excl, unsigned long long) const { gbase[i] = (unsigned)excl; }
-};
-
-// Each bucket's groups, in slot order after earlier buckets' groups, and its
-// entries placed in their groups' runs.
+// Each bucket's groups, numbered in slot order from a base that one atomic
+// on the group count reserves (so buckets' groups come in no fixed order),
+// and its entries placed in their groups' runs.
 __global__ __launch_bounds__(kPGBlock) void k_xpart_place(const unsigned* __restrict__ pkey,
                                                           const XRec* __restrict__ prec,
                                                           const unsigned* __restrict__ hist, int bbits,
                                                           int64_t ntiles, int64_t nnz, uint64_t seed, unsigned tmax,
-                                                          const unsigned* __restrict__ gbase,
                                                           GroupRec* __restrict__ groups, XRec* __restrict__ xr,
                                                           DevStatus* st) {
   extern __shared__ unsigned long long s_tab[];
@@ -237,10 +205,16 @@ __global__ __launch_bounds__(kPGBlock) void k_xpart_place(const unsigned* __rest
     }
     unsigned long long tot;
     unsigned long long run = block_excl_scan<kPGBlock>(mine, s_wave, &tot);
+    // st->xgroups starts at zero (the plan clears the status) and ends as
+    // the number of groups
+    __shared__ unsigned long long s_gb;
+    if (threadIdx.x == 0) s_gb = (tot & 0xffffffffull) ? atomicAdd(&st->xgroups, tot & 0xffffffffull) : 0ull;
+    __syncthreads();
+    const unsigned long long gb = s_gb;
     for (unsigned k = 0; k < kPer; ++k) {
       const unsigned long long w = s_tab[s0 + k];
       if (w == kEmpty) continue;
-      const unsigned long long gi = (unsigned long long)gbase[b] + (run & 0xffffffffull);
+      const unsigned long long gi = gb + (run & 0xffffffffull);
       const unsigned long long start = (unsigned long long)lo + (run >> 32), count = w & 0xffffffffull;
       if ((int64_t)gi >= nnz || (int64_t)(start + count) > nnz) {
         record_error(st, kErrInternal);
@@ -289,9 +263,9 @@ int part_bits(int64_t nnz) {
 int64_t part_tiles(int64_t nnz) { return (nnz + kPTile - 1) / kPTile; }
 
 hipError_t prepare_x_partition() {
-  const void* big[] = {reinterpret_cast<const void*>(&k_xpart_count), reinterpret_cast<const void*>(&k_xpart_place)};
-  for (const void* k : big) {
-    const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kPSlots * 8));
+  {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_xpart_place),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kPSlots * 8));
     if (e != hipSuccess) return e;
   }
   const void* hist[] = {reinterpret_cast<const void*>(&k_xpart_hist), reinterpret_cast<const void*>(&k_xpart_scatter)};
@@ -325,13 +299,8 @@ hipError_t launch_x_partition(const int32_t* xidx, const double* xval, int64_t n
   while ((int64_t)tmax < 2 * ((nnz + nbk - 1) / nbk) && tmax < kPSlots) tmax <<= 1;
   const unsigned per_cu = tmax * 8 <= (64u << 10) ? 2u : 1u;  // 1,024-thread workgroups: two fill a CU
   const unsigned bgrid = nbk < per_cu * (unsigned)num_cus ? nbk : per_cu * (unsigned)num_cus;
-  k_xpart_count<<<bgrid, kPGBlock, tmax * 8, stream>>>(w.pkey, w.hist, bbits, ntiles, nnz, seed, tmax, w.bdist, st);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  e = device_scan(BucketScanOp{w.bdist, w.gbase}, nbk, w.scan, FinPartGroups{st}, stream);
-  if (e != hipSuccess) return e;
   k_xpart_place<<<bgrid, kPGBlock, tmax * 8, stream>>>(w.pkey, w.prec, w.hist, bbits, ntiles, nnz, seed, tmax,
-                                                       w.gbase, groups, xr, st);
+                                                       groups, xr, st);
   return hipGetLastError();
 }
 

@@ -15,15 +15,12 @@ constexpr int64_t kPartMaxEntries = (int64_t)150 << 20;  // beyond: buckets coul
 
 // Workspace of launch_x_partition for nnz X entries (device, caller-owned):
 // pkey[nnz] and prec[nnz] (the partitioned keys and X records),
-// hist[2^part_bits(nnz) * part_tiles(nnz)], bdist and gbase [2^part_bits],
-// and scan scratch for the larger of the two scans (scan_tiles(n) + 1
-// 64-bit values).
+// hist[2^part_bits(nnz) * part_tiles(nnz)], and scan scratch for the
+// histogram's scan (scan_tiles(n) + 1 64-bit values).
 struct XPartBuffers {
   unsigned* pkey;
   XRec* prec;
   unsigned* hist;
-  unsigned* bdist;
-  unsigned* gbase;
   void* scan;
 };
 
@@ -35,8 +32,8 @@ hipError_t prepare_x_partition();
 
 // X grouped by its free key (at most 31 bits, hashed, one contraction, nnz
 // <= kPartMaxEntries): groups[0, xgroups) and the grouped X records xr[nnz],
-// st->xgroups, and st->nonfinite when an X value is not finite; with b.check,
-// coordinates out of range are recorded.
+// st->xgroups (counted up: zero on entry), and st->nonfinite when an X value
+// is not finite; with b.check, coordinates out of range are recorded.
 hipError_t launch_x_partition(const int32_t* xidx, const double* xval, int64_t nnz, KeyPack kf, KeyPack kc, Bounds b,
                               const YSlot* ytab, TabGeom yg, int32_t max_probe_y, uint64_t seed, const XPartBuffers& w,
                               GroupRec* groups, XRec* xr, DevStatus* st, int num_cus, hipStream_t stream);
