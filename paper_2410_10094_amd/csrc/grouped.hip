@@ -949,7 +949,8 @@ __global__ __launch_bounds__(kDBlock) void k_group_direct(GroupArgs a, const DRe
 // tables only (a few slots per workgroup); larger ones take k_y_compact and
 // k_y_repeats.
 // With yso, the compact copy of every run is also cut into
-// kSlices slices of the Y free key space (key >> slice_shift): a sorted run
+// kSlices slices of the Y free key space (key / slice_cells, the last
+// slice taking every larger key): a sorted run
 // is cut where the slice changes, a longer run is placed slice by slice (in
 // no order within a slice).  yso[slot * (kSlices + 1) + s] receives the
 // position where slice s of the slot's run begins (entry kSlices: the run's
@@ -959,7 +960,7 @@ __global__ __launch_bounds__(kBBlock) void k_sort_y_runs(const YSlot* __restrict
                                                          YEntry* __restrict__ yg, int64_t ny,
                                                          uint16_t* __restrict__ ykey16, double* __restrict__ yval,
                                                          unsigned* __restrict__ colbits, uint32_t* __restrict__ yso,
-                                                         uint32_t* __restrict__ runslot, unsigned slice_shift,
+                                                         uint32_t* __restrict__ runslot, unsigned slice_cells,
                                                          DevStatus* st) {
   __shared__ unsigned long long s_key[kBBlock];
   __shared__ YEntry s_ent[kBBlock];
@@ -973,7 +974,10 @@ __global__ __launch_bounds__(kBBlock) void k_sort_y_runs(const YSlot* __restrict
     if (colbits) atomicOr(&s_cells[c >> 5], bit);
     return (atomicOr(&s_seen[c >> 5], bit) & bit) != 0u;
   };
-  const unsigned smask = kSlices - 1u;
+  auto slice_of = [&](unsigned long long phi) {
+    const unsigned q = (unsigned)phi / slice_cells;
+    return q < (unsigned)kSlices - 1u ? q : (unsigned)kSlices - 1u;
+  };
   for (int64_t slot = blockIdx.x; slot < nslots; slot += gridDim.x) {
     const YSlot t = ytab[slot];
     if (t.key == kEmpty || t.count == 0 || (unsigned long long)t.start + t.count > (unsigned long long)ny)
@@ -987,7 +991,7 @@ __global__ __launch_bounds__(kBBlock) void k_sort_y_runs(const YSlot* __restrict
     if (!SORT || n > (unsigned)kBBlock) {  // too long to sort here: copied as is, or slice by slice
       if (so) {
         for (unsigned j = tid; j < n; j += kBBlock)
-          atomicAdd(&s_slice[((unsigned)yg[t.start + j].phi >> slice_shift) & smask], 1u);
+          atomicAdd(&s_slice[slice_of(yg[t.start + j].phi)], 1u);
         __syncthreads();
         if (tid == 0) {
           unsigned run = 0;
@@ -1004,7 +1008,7 @@ __global__ __launch_bounds__(kBBlock) void k_sort_y_runs(const YSlot* __restrict
       for (unsigned j = tid; j < n; j += kBBlock) {
         const YEntry e = yg[t.start + j];
         if (seen_before(e.phi)) st->ydup = 1u;
-        const unsigned at = so ? atomicAdd(&s_slice[((unsigned)e.phi >> slice_shift) & smask], 1u) : j;
+        const unsigned at = so ? atomicAdd(&s_slice[slice_of(e.phi)], 1u) : j;
         ykey16[t.start + at] = (uint16_t)e.phi;
         yval[t.start + at] = e.v;
       }
@@ -1028,8 +1032,8 @@ __global__ __launch_bounds__(kBBlock) void k_sort_y_runs(const YSlot* __restrict
       ykey16[t.start + tid] = (uint16_t)e.phi;
       yval[t.start + tid] = e.v;
       if (so) {  // slice boundaries: where the (sorted) slice index changes
-        const unsigned q = ((unsigned)e.phi >> slice_shift) & smask;
-        const unsigned qp = tid == 0 ? 0u : ((unsigned)(s_key[tid - 1] >> 11) >> slice_shift) & smask;
+        const unsigned q = slice_of(e.phi);
+        const unsigned qp = tid == 0 ? 0u : slice_of(s_key[tid - 1] >> 11);
         for (unsigned b = (tid == 0 ? 0u : qp + 1u); b <= q; ++b) so[b] = t.start + tid;
         if (tid == n - 1)
           for (unsigned b = q + 1u; b <= (unsigned)kSlices; ++b) so[b] = t.start + n;
@@ -1372,19 +1376,20 @@ constexpr int64_t kSmallYTable = 8192;
 
 hipError_t launch_sort_y_runs(const YSlot* ytab, int64_t nslots, YEntry* yg, int64_t ny, uint16_t* ykey16,
                               double* yval, unsigned* colbits, DevStatus* st, bool sort, int num_cus,
-                              hipStream_t stream, uint32_t* yso, uint32_t* runslot, unsigned slice_shift,
+                              hipStream_t stream, uint32_t* yso, uint32_t* runslot, unsigned slice_cells,
                               uint32_t* ylong) {
   if (nslots <= 0 || ny <= 0) return hipSuccess;
   if (yso && !sort) return hipErrorInvalidValue;
+  if (yso && (slice_cells == 0u || slice_cells % 64u)) return hipErrorInvalidValue;
   const int64_t grid = nslots < (int64_t)num_cus * 2 ? nslots : (int64_t)num_cus * 2;
   if (sort) {
     k_sort_y_runs<true><<<dim3((unsigned)grid), kBBlock, 0, stream>>>(ytab, nslots, yg, ny, ykey16, yval, colbits,
-                                                                       yso, runslot, slice_shift, st);
+                                                                       yso, runslot, yso ? slice_cells : 1u, st);
     return hipGetLastError();
   }
   if (nslots <= kSmallYTable) {  // a few slots per workgroup: one launch
     k_sort_y_runs<false><<<dim3((unsigned)grid), kBBlock, 0, stream>>>(ytab, nslots, yg, ny, ykey16, yval, colbits,
-                                                                        nullptr, nullptr, 0u, st);
+                                                                        nullptr, nullptr, 1u, st);
     return hipGetLastError();
   }
   // a larger table, mostly short runs or empty slots: an elementwise copy,

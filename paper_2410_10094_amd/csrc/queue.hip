@@ -217,12 +217,13 @@ unsigned queue_grid(size_t lds, int num_cus) {
 }  // namespace
 
 hipError_t launch_lds_queue(const GroupArgs& a, const uint32_t* blist, int64_t nb, const uint32_t* yso,
-                            int64_t yso_slots, unsigned cells, LdsQueue* q, uint32_t* tcnt, unsigned long long* toff,
-                            void* tile_sums, int num_cus, hipStream_t stream) {
+                            int64_t yso_slots, unsigned cells, unsigned slice_cells, LdsQueue* q, uint32_t* tcnt,
+                            unsigned long long* toff, void* tile_sums, int num_cus, hipStream_t stream) {
   if (cells < 1024u || (cells & (cells - 1u)) || cells > (1u << kDenseBits)) return hipErrorInvalidValue;
+  if (slice_cells == 0u || slice_cells % 64u || slice_cells > cells / kSlices) return hipErrorInvalidValue;
   if (a.ny <= 0 || nb <= 0) return hipSuccess;  // no products: no tile has an output
   if ((tcnt == nullptr) != (toff == nullptr)) return hipErrorInvalidValue;
-  const unsigned wcells = cells / kSlices;
+  const unsigned wcells = slice_cells;
   const unsigned wave_lds = (unsigned)flat_wave_lds(wcells);
   const size_t lds = (size_t)kQWaves * wave_lds;
   const unsigned grid = queue_grid(lds, num_cus);

@@ -309,6 +309,7 @@ struct sptc_plan_s : Workspace {
   uint32_t* bdefer = nullptr;          // hashed block class: groups passed to the large-table launch
   uint32_t* glist = nullptr;
   uint32_t* yso = nullptr;    // dense block class: where each slice of each Y run begins, per Y table slot
+  unsigned slice_cells = 0;   // and the width of a slice of the Y free key space
   int32_t block_mfma = 0;     // dense block class on the matrix cores
   unsigned* ycolbits = nullptr;  // dense Y free key: the cells that occur (bitmap)
   unsigned ycols = 0;            // and their number
@@ -563,6 +564,27 @@ constexpr int64_t kDenseRowProducts = 16384;
 
 // Cells of the dense LDS accumulator for a Y free key of bits_y bits.
 unsigned dense_cells(int32_t bits_y) { return std::max(1u << bits_y, 1024u); }
+
+// Width of one slice of the dense Y free key space for the sliced walk:
+// the keys that Y's mode lengths allow, 0 to pack(dims - 1), cut into
+// kSlices equal parts of whole 64-cell chunks.  Cutting the packed key
+// space itself would leave the keys past the largest (a mode length that is
+// not a power of two leaves the top of its field unused) whole slices with
+// nothing in them, and their XCDs idle.  A batch's packed plan cuts the
+// whole space.
+unsigned slice_width(const sptc_plan_s* P, unsigned cells) {
+  const unsigned full = cells / kSlices;
+  if (P->in_batch) return full;
+  uint64_t kmax = 0;
+  for (int32_t k = 0; k < P->y_f.n; ++k) {
+    const uint32_t f = P->y_f.field[k];
+    const uint64_t d = P->yb.dim[field_mode(f)];
+    if (d > 1) kmax |= (d - 1) << field_shift(f);
+  }
+  uint64_t w = (kmax + kSlices) / kSlices;  // ceil((kmax + 1) / kSlices)
+  w = (w + 63) / 64 * 64;
+  return (unsigned)std::min<uint64_t>(w, full);
+}
 
 // Shift of the Y free key in the repeated-coordinate check, or -1 when the
 // whole coordinate does not fit 63 bits and the check hashes it instead.
@@ -830,9 +852,9 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
         uint32_t* runslot = nullptr;
         if ((st = P->allocate_n(P->ytab_slots * (kSlices + 1), &P->yso))) return st;
         if ((st = P->allocate_n(P->ny, &runslot))) return st;
-        const unsigned cells = dense_cells(P->bits_fy);
+        P->slice_cells = slice_width(P, dense_cells(P->bits_fy));
         HIP_TRY(launch_sort_y_runs(P->ytab, P->ytab_slots, P->yg, P->ny, P->ykey16, P->yval, nullptr, P->st, true,
-                                   P->num_cus, s, P->yso, runslot, (unsigned)__builtin_ctz(cells / kSlices)));
+                                   P->num_cus, s, P->yso, runslot, P->slice_cells));
         HIP_TRY(launch_block_runslots(P->groups, P->blist, P->nb, P->xr, runslot, P->ny, P->st, P->num_cus, s,
                                       P->capture ? P->st : nullptr));
       }
@@ -1192,8 +1214,8 @@ sptc_status execute_plan(sptc_plan_s* P, int32_t* out_idx, double* out_val, int6
     if (P->dense_rows)
       HIP_TRY(launch_group_block(a, P->blist, P->nb, P->num_cus, s, nullptr, dense_cells(P->bits_fy)));
     else if (P->dense && !P->block_mfma && P->nb > 0)
-      HIP_TRY(launch_lds_queue(a, P->blist, P->nb, P->yso, P->ytab_slots, dense_cells(P->bits_fy), P->queue, P->tcnt,
-                               P->toff, P->tsums, P->num_cus, s));
+      HIP_TRY(launch_lds_queue(a, P->blist, P->nb, P->yso, P->ytab_slots, dense_cells(P->bits_fy), P->slice_cells,
+                               P->queue, P->tcnt, P->toff, P->tsums, P->num_cus, s));
     if (P->block_mfma)
       HIP_TRY(launch_group_block_mfma(a, P->blist, P->nb, P->mplan, P->num_cus, s));
     else if (!P->dense)

@@ -430,7 +430,8 @@ hipError_t launch_finalize(int64_t* out_nnz, int64_t out_cap, DevStatus* st, hip
 // colbits (kCellWords words, zeroed first), also ORs in a bit for every
 // Y free cell that occurs.  With yso (sort only; [nslots][kSlices + 1]
 // u32) and runslot ([ny] u32), also cuts every run into kSlices slices of
-// the Y free key (key >> slice_shift), slice by slice in the compact copy:
+// the Y free key (key / slice_cells, a positive multiple of 64; the last
+// slice also takes every larger key), slice by slice in the compact copy:
 // yso[slot][s] is where slice s of the slot's run begins (yso[slot][kSlices]
 // its end) and runslot[run start] = slot.  Without sort, ylong
 // (y_long_run_slots(ny) u32) is required: the list of long runs whose
@@ -438,7 +439,7 @@ hipError_t launch_finalize(int64_t* out_nnz, int64_t out_cap, DevStatus* st, hip
 hipError_t launch_sort_y_runs(const YSlot* ytab, int64_t nslots, YEntry* yg, int64_t ny, uint16_t* ykey16,
                               double* yval, unsigned* colbits, DevStatus* st, bool sort, int num_cus,
                               hipStream_t stream, uint32_t* yso = nullptr, uint32_t* runslot = nullptr,
-                              unsigned slice_shift = 0, uint32_t* ylong = nullptr);
+                              unsigned slice_cells = 0, uint32_t* ylong = nullptr);
 int64_t y_long_run_slots(int64_t ny);
 
 // ---- LDS classes: dense block tiles and the wave class (queue.hip) ----
@@ -475,15 +476,17 @@ hipError_t prepare_lds_queue();
 // The dense block class's (group, slice) tiles (blist, runs cut by yso),
 // persistent launches over per-XCD queues; the tile count is read on the
 // device from the plan's class counts.  cells: the dense accumulator size (a
-// power of two of at least 1024 and at least 2^bits_y).  With tcnt == NULL
+// power of two of at least 1024 and at least 2^bits_y); slice_cells: the
+// width of one slice, as the runs were cut (a positive multiple of 64, at
+// most cells / kSlices).  With tcnt == NULL
 // each tile reserves its outputs with one atomic on the output cursor (one
 // launch).  Otherwise (tcnt, toff: 8 * nb elements; tile_sums: scan scratch
 // for them) a count launch writes each tile's outputs to tcnt, a scan turns
 // them into offsets after the outputs placed so far, and a fill launch
 // accumulates again and writes: no atomic per tile, for many small tiles.
 hipError_t launch_lds_queue(const GroupArgs& a, const uint32_t* blist, int64_t nb, const uint32_t* yso,
-                            int64_t yso_slots, unsigned cells, LdsQueue* q, uint32_t* tcnt, unsigned long long* toff,
-                            void* tile_sums, int num_cus, hipStream_t stream);
+                            int64_t yso_slots, unsigned cells, unsigned slice_cells, LdsQueue* q, uint32_t* tcnt,
+                            unsigned long long* toff, void* tile_sums, int num_cus, hipStream_t stream);
 
 // The wave class (wlist, at most nw groups; the count is read on the
 // device).  One contraction: a count pass into wcnt[nw], a scan into

@@ -53,6 +53,9 @@ CASES = [
     ("thirteen-bit-cells", lambda: _matrix_like(6, 150, 100, 8192, 9_000, 150_000, "thirteen-bit-cells")),
     # explicit zero values: zero products still make structural outputs
     ("explicit-zeros", lambda: _matrix_like(7, 200, 150, 4096, 20_000, 60_000, "explicit-zeros", zeros=0.3)),
+    # 3,000 columns (a 12-bit key, 4,096 cells): the slices cut 0..2,999,
+    # 384 cells each, not the packed key space's 512
+    ("uneven-key-range", lambda: _matrix_like(12, 200, 150, 3000, 20_000, 60_000, "uneven-key-range")),
     # few large tiles (about 24,000 products each)
     ("few-large-tiles", lambda: _matrix_like(9, 16, 64, 4096, 1024, 192_000, "few-large-tiles")),
     # groups of about 680 products: each accumulated whole, its dense row in
@@ -98,3 +101,20 @@ def test_sliced_block_class_order4():
     info, gidx, gval = run_gpu(p)
     assert info["classes"]["block"] > 0, info["classes"]
     assert_parity(p, gidx, gval)
+
+
+def test_sliced_block_class_two_uneven_free_modes():
+    """A Y free key of two modes of 37 and 50 (6 bits each): the keys in use
+    end at 36 * 64 + 49, so the slices are 320 cells wide, and the last
+    slice holds the largest coordinates (every (y1, y2) pair occurs)."""
+    rng = np.random.default_rng(13)
+    X = _tensor(rng, (200, 40), 8_000)
+    Y = _tensor(rng, (40, 37, 50), 37_000)
+    assert Y.idx[1].max() == 36 and Y.idx[2].max() == 49
+    p = Problem("two-uneven-free-modes", X, Y, (1,), (0,))
+    log(f"[sliced] {p.name} nnz {p.X.nnz}x{p.Y.nnz}")
+    info, gidx, gval = run_gpu(p)
+    assert info["classes"]["block"] > 0 and not info["block_mfma"], info["classes"]
+    assert not info["block_dense_rows"], (info["products"], info["classes"])
+    assert_parity(p, gidx, gval)
+
