@@ -177,7 +177,78 @@ __global__ __launch_bounds__(256) void k_block_runslots(const GroupRec* __restri
   }
 }
 
+// Longest first: the dense block class's list reordered by decreasing
+// product count, so that each XCD's queue hands out its largest tiles first
+// and the smallest ones fill in at the end.  The order is by 1,024 bins of
+// the count (bin width: the largest count / 1,024), enough for the balance:
+// one workgroup holds every group's count in registers, bins them in LDS,
+// scans the bins and places each group at its bin's cursor.
+constexpr unsigned kOrderBlock = 1024;
+constexpr unsigned kOrderBins = 1024;
+constexpr unsigned kOrderPer = kOrderMax / kOrderBlock;
+
+__global__ __launch_bounds__(kOrderBlock) void k_order_blist(const GroupRec* __restrict__ groups,
+                                                             const unsigned long long* __restrict__ eoff,
+                                                             uint32_t* __restrict__ blist, unsigned nb) {
+  __shared__ unsigned s_bin[kOrderBins];
+  __shared__ unsigned long long s_wave[kOrderBlock / 64 + 1];
+  if (nb < 2u || nb > kOrderMax) return;  // uniform across the block
+  uint32_t g[kOrderPer];
+  unsigned long long p[kOrderPer];
+  unsigned long long pmax = 0;
+#pragma unroll
+  for (unsigned k = 0; k < kOrderPer; ++k) {
+    const unsigned i = k * kOrderBlock + threadIdx.x;
+    g[k] = 0u;
+    p[k] = 0ull;
+    if (i < nb) {
+      g[k] = blist[i];
+      const GroupRec G = groups[g[k]];
+      p[k] = eoff[G.start + G.count] - eoff[G.start];
+      pmax = p[k] > pmax ? p[k] : pmax;
+    }
+  }
+  s_bin[threadIdx.x] = 0u;
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long t = __shfl_xor(pmax, o);
+    pmax = t > pmax ? t : pmax;
+  }
+  if ((threadIdx.x & 63u) == 0) s_wave[threadIdx.x >> 6] = pmax;
+  __syncthreads();
+  pmax = 0;
+  for (unsigned w = 0; w < kOrderBlock / 64; ++w) pmax = s_wave[w] > pmax ? s_wave[w] : pmax;
+  // bin kOrderBins - 1 - floor(p * kOrderBins / (pmax + 1)): the largest counts first
+  unsigned bin[kOrderPer];
+#pragma unroll
+  for (unsigned k = 0; k < kOrderPer; ++k) {
+    const unsigned i = k * kOrderBlock + threadIdx.x;
+    const double scaled = (double)p[k] * (double)kOrderBins / ((double)pmax + 1.0);  // in [0, kOrderBins)
+    bin[k] = kOrderBins - 1u - (scaled < (double)(kOrderBins - 1u) ? (unsigned)scaled : kOrderBins - 1u);
+    if (i < nb) atomicAdd(&s_bin[bin[k]], 1u);
+  }
+  __syncthreads();
+  unsigned long long tot;
+  const unsigned long long start = block_excl_scan<kOrderBlock>(s_bin[threadIdx.x], s_wave, &tot);
+  s_bin[threadIdx.x] = (unsigned)start;  // the bin's cursor
+  __syncthreads();
+#pragma unroll
+  for (unsigned k = 0; k < kOrderPer; ++k) {
+    const unsigned i = k * kOrderBlock + threadIdx.x;
+    if (i < nb) {
+      const unsigned at = atomicAdd(&s_bin[bin[k]], 1u);
+      if (at < nb) blist[at] = g[k];
+    }
+  }
+}
+
 }  // namespace
+
+hipError_t launch_order_blist(const GroupRec* groups, const unsigned long long* eoff, uint32_t* blist, int64_t nb,
+                              hipStream_t stream) {
+  if (nb < 2 || nb > (int64_t)kOrderMax) return hipSuccess;
+  k_order_blist<<<1, kOrderBlock, 0, stream>>>(groups, eoff, blist, (unsigned)nb);
+  return hipGetLastError();
+}
 
 hipError_t launch_block_runslots(const GroupRec* groups, const uint32_t* blist, int64_t nb, XRec* xr,
                                  const uint32_t* runslot, int64_t ny, DevStatus* st, int num_cus,

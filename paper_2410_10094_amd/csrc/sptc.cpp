@@ -857,6 +857,8 @@ sptc_status plan_grouped(sptc_plan_s* P, const sptc_coo* X) {
                                    P->num_cus, s, P->yso, runslot, P->slice_cells));
         HIP_TRY(launch_block_runslots(P->groups, P->blist, P->nb, P->xr, runslot, P->ny, P->st, P->num_cus, s,
                                       P->capture ? P->st : nullptr));
+        // (the list's length is known here unless the plan is captured)
+        if (!P->capture && !P->in_batch) HIP_TRY(launch_order_blist(P->groups, P->eoff, P->blist, P->nb, s));
       }
       HIP_TRY(mark(P, s, SPTC_STAGE_X_SORT, 1));
     }

@@ -470,6 +470,13 @@ hipError_t launch_block_runslots(const GroupRec* groups, const uint32_t* blist, 
                                  const uint32_t* runslot, int64_t ny, DevStatus* st, int num_cus,
                                  hipStream_t stream, const DevStatus* dc = nullptr);
 
+// The dense block class's list (blist, nb groups; groups and eoff as the
+// classification read them) reordered by decreasing product count, when
+// 2 <= nb <= kOrderMax; otherwise left as it is.
+constexpr unsigned kOrderMax = 8192;
+hipError_t launch_order_blist(const GroupRec* groups, const unsigned long long* eoff, uint32_t* blist, int64_t nb,
+                              hipStream_t stream);
+
 // Raises the persistent kernel's dynamic LDS limit on the current device.
 hipError_t prepare_lds_queue();
 
