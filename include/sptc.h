@@ -130,7 +130,8 @@ typedef enum sptc_stage {
   SPTC_STAGE_BATCH_PACK = 12,   /* batch plan: key every contraction's entries with its index */
   SPTC_STAGE_BATCH_SEGMENTS = 13, /* batch plan: products and output segments per contraction */
   SPTC_STAGE_X_SORT = 14,       /* grouped plan, dense block class: Y runs sorted and cut into slices for
-                                   the tiles (or the matrix-core panels built) */
+                                   the tiles and the class list ordered largest group first (or the
+                                   matrix-core panels built) */
   SPTC_NUM_STAGES = 15
 } sptc_stage;
 
