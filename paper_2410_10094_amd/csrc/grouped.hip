@@ -948,7 +948,9 @@ __global__ __launch_bounds__(kDBlock) void k_group_direct(GroupArgs a, const DRe
 // the direct class needs to know about.  Without SORT it serves small
 // tables only (a few slots per workgroup); larger ones take k_y_compact and
 // k_y_repeats.
-// With yso, the compact copy of every run is also cut into
+// With yso, runs are sorted by counting over the keys 0 ..
+// slice_cells * kSlices - 1 (those the slices cover), else by a bitonic
+// sort.  With yso, the compact copy of every run is also cut into
 // kSlices slices of the Y free key space (key / slice_cells, the last
 // slice taking every larger key): a sorted run
 // is cut where the slice changes, a longer run is placed slice by slice (in
@@ -961,7 +963,7 @@ __global__ __launch_bounds__(kBBlock) void k_sort_y_runs(const YSlot* __restrict
                                                          uint16_t* __restrict__ ykey16, double* __restrict__ yval,
                                                          unsigned* __restrict__ colbits, uint32_t* __restrict__ yso,
                                                          uint32_t* __restrict__ runslot, unsigned slice_cells,
-                                                         DevStatus* st) {
+                                                         unsigned key_cells, DevStatus* st) {
   __shared__ unsigned long long s_key[kBBlock];
   __shared__ YEntry s_ent[kBBlock];
   constexpr unsigned kSeenWords = (1u << kDenseBits) / 32;
@@ -1015,17 +1017,53 @@ __global__ __launch_bounds__(kBBlock) void k_sort_y_runs(const YSlot* __restrict
       __syncthreads();
       continue;
     }
-    unsigned long long key = ~0ull;
-    if (tid < n) {
-      s_ent[tid] = yg[t.start + tid];
-      if (seen_before(s_ent[tid].phi)) st->ydup = 1u;
-      key = (s_ent[tid].phi << 11) | tid;  // phi has <= kDenseBits bits here; tid < 2048
+    if (key_cells) {
+      // a counting sort over the keys 0..key_cells - 1 (a larger key, from
+      // a coordinate past its mode's length, goes in the last bin): a
+      // histogram, its scan, and each entry placed at its bin's cursor;
+      // s_key[place] = (key << 11) | entry, as the bitonic sort leaves it
+      __shared__ unsigned s_cnt[1u << kDenseBits];
+      __shared__ unsigned long long s_wave[kBBlock / 64 + 1];
+      for (unsigned c = tid; c < key_cells; c += kBBlock) s_cnt[c] = 0u;
+      __syncthreads();
+      unsigned bin = 0;
+      if (tid < n) {
+        s_ent[tid] = yg[t.start + tid];
+        if (seen_before(s_ent[tid].phi)) st->ydup = 1u;
+        bin = s_ent[tid].phi < key_cells ? (unsigned)s_ent[tid].phi : key_cells - 1u;
+        atomicAdd(&s_cnt[bin], 1u);
+      }
+      __syncthreads();
+      const unsigned per = (key_cells + kBBlock - 1u) / kBBlock, c0 = tid * per;
+      const unsigned c1 = c0 + per < key_cells ? c0 + per : key_cells;
+      unsigned long long mine = 0;
+      for (unsigned c = c0; c < c1; ++c) mine += s_cnt[c];
+      unsigned long long tot;
+      unsigned long long run = block_excl_scan<kBBlock>(mine, s_wave, &tot);
+      for (unsigned c = c0; c < c1; ++c) {
+        const unsigned v = s_cnt[c];
+        s_cnt[c] = (unsigned)run;
+        run += v;
+      }
+      __syncthreads();
+      if (tid < n) {
+        const unsigned at = atomicAdd(&s_cnt[bin], 1u);
+        if (at < n) s_key[at] = (s_ent[tid].phi << 11) | tid;
+      }
+      __syncthreads();
+    } else {
+      unsigned long long key = ~0ull;
+      if (tid < n) {
+        s_ent[tid] = yg[t.start + tid];
+        if (seen_before(s_ent[tid].phi)) st->ydup = 1u;
+        key = (s_ent[tid].phi << 11) | tid;  // phi has <= kDenseBits bits here; tid < 2048
+      }
+      s_key[tid] = key;
+      __syncthreads();
+      unsigned nsort = 2;
+      while (nsort < n) nsort <<= 1;
+      bitonic_sort_lds(s_key, nsort);
     }
-    s_key[tid] = key;
-    __syncthreads();
-    unsigned nsort = 2;
-    while (nsort < n) nsort <<= 1;
-    bitonic_sort_lds(s_key, nsort);
     if (tid < n) {
       const YEntry e = s_ent[(unsigned)(s_key[tid] & 2047ull)];
       yg[t.start + tid] = e;
@@ -1380,16 +1418,18 @@ hipError_t launch_sort_y_runs(const YSlot* ytab, int64_t nslots, YEntry* yg, int
                               uint32_t* ylong) {
   if (nslots <= 0 || ny <= 0) return hipSuccess;
   if (yso && !sort) return hipErrorInvalidValue;
-  if (yso && (slice_cells == 0u || slice_cells % 64u)) return hipErrorInvalidValue;
+  if (yso && (slice_cells == 0u || slice_cells % 64u || slice_cells * kSlices > (1u << kDenseBits)))
+    return hipErrorInvalidValue;
   const int64_t grid = nslots < (int64_t)num_cus * 2 ? nslots : (int64_t)num_cus * 2;
   if (sort) {
     k_sort_y_runs<true><<<dim3((unsigned)grid), kBBlock, 0, stream>>>(ytab, nslots, yg, ny, ykey16, yval, colbits,
-                                                                       yso, runslot, yso ? slice_cells : 1u, st);
+                                                                       yso, runslot, yso ? slice_cells : 1u,
+                                                                       yso ? slice_cells * kSlices : 0u, st);
     return hipGetLastError();
   }
   if (nslots <= kSmallYTable) {  // a few slots per workgroup: one launch
     k_sort_y_runs<false><<<dim3((unsigned)grid), kBBlock, 0, stream>>>(ytab, nslots, yg, ny, ykey16, yval, colbits,
-                                                                        nullptr, nullptr, 1u, st);
+                                                                        nullptr, nullptr, 1u, 0u, st);
     return hipGetLastError();
   }
   // a larger table, mostly short runs or empty slots: an elementwise copy,
