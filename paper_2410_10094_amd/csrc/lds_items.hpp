@@ -203,10 +203,10 @@ __device__ __forceinline__ void wave_group_fill(const GroupArgs& a, uint32_t g, 
 //
 // With a dense Y free key (at most kDenseBits bits) a group accumulates in a
 // dense array indexed by the Y free key, which is exactly the group's output
-// row.  The Y free key space is cut into kSlices equal slices, and every Y
-// run (the Y entries of one contracting key, section 4.2) is laid out slice
-// by slice at plan time, with yso giving where each slice of each run
-// begins.  A tile is (group, slice): one wave walks the group's X entries
+// row.  The Y free keys that the mode lengths allow are cut into kSlices
+// equal slices of wcells cells (a multiple of 64), and every Y run (the Y
+// entries of one contracting key, section 4.2) is laid out slice by slice
+// at plan time, with yso giving where each slice of each run begins.  A tile is (group, slice): one wave walks the group's X entries
 // and, for each, the slice of its Y run, adding x * y into the slice's cells
 // of the group's row in LDS.
 //
